@@ -1,0 +1,9 @@
+"""MI355X-native Deep Potential (se_e2_a) energy, force and virial.
+
+Submodules:
+  synth    seeded synthetic frames and random-initialised parameters (no method arithmetic)
+  dpk      ctypes binding of the HIP library libdpk.so (C ABI declared in include/dpk.h)
+  torch_op torch.autograd.Function over the device entry point
+  serving  continuous-batching request loop over the device entry points
+"""
+__all__ = ["synth"]

@@ -1,0 +1,462 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU).
+
+Each test names the passage it follows. None of them re-types the oracle's formulas: they use
+closed forms at special points, finite differences, invariances of the model, brute force on small
+inputs, and the interpolation conditions that define the quintic table.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2304_09409_amd import synth
+
+RNG = np.random.default_rng(12345)
+
+
+# ---------------------------------------------------------------------------------------------
+# Switching function, Sec. II.A.1 (eq. switch)
+# ---------------------------------------------------------------------------------------------
+
+def test_switch_special_values(water_oracle):
+    o = water_oracle
+    rs, rc = o.model["rcut_smth"], o.model["rcut"]
+    # below r_s the function is exactly 1/r
+    for r in (0.1, 0.3, 0.49):
+        s, ds = o.switch(r)
+        assert s == pytest.approx(1.0 / r, rel=1e-15)
+        assert ds == pytest.approx(-1.0 / r ** 2, rel=1e-15)
+    # x = 1/2: the quintic is 1/8 (-6/4 + 15/2 - 10) + 1 = 1/2
+    r = rs + 0.5 * (rc - rs)
+    assert o.switch(r)[0] == pytest.approx(0.5 / r, rel=1e-14)
+    # x = 0 and x = 1 end values, and zero at and beyond r_c
+    assert o.switch(rs)[0] == pytest.approx(1.0 / rs, rel=1e-15)
+    assert o.switch(rc) == (0.0, 0.0)
+    assert o.switch(rc + 1.0) == (0.0, 0.0)
+
+
+def test_switch_derivative_matches_fd(water_oracle):
+    o = water_oracle
+    for r in np.linspace(0.2, 5.9, 23):
+        h = 1e-5
+        fd = (o.switch(r + h)[0] - o.switch(r - h)[0]) / (2 * h)
+        assert o.switch(r)[1] == pytest.approx(fd, rel=1e-7, abs=1e-9)
+
+
+@pytest.mark.parametrize("where", ["rs", "rc"])
+def test_switch_is_c2_but_not_c3(water_oracle, where):
+    """The paper states s has a continuous second derivative: jumps of s, s', s'' across r_s and
+    r_c vanish with the probe distance, while s''' jumps by u'''/((r_c - r_s)^3 r) != 0."""
+    o = water_oracle
+    rs, rc = o.model["rcut_smth"], o.model["rcut"]
+    r0 = rs if where == "rs" else rc
+
+    def d2(r, h=1e-4):
+        return (o.switch(r + h)[1] - o.switch(r - h)[1]) / (2 * h)
+
+    jumps = []
+    for eps in (1e-2, 5e-3, 2.5e-3):
+        lo, hi = r0 - eps, r0 + eps
+        jumps.append((abs(o.switch(hi)[0] - o.switch(lo)[0]),
+                      abs(o.switch(hi)[1] - o.switch(lo)[1]),
+                      abs(d2(hi, eps / 10) - d2(lo, eps / 10))))
+    jumps = np.array(jumps)
+    # every jump shrinks at least linearly with eps (it would stay O(1) for a discontinuity)
+    assert (jumps[1:] < 0.6 * jumps[:-1] + 1e-12).all()
+    # the third derivative does jump: |u'''| = 60 at both ends of the band. One-sided estimates
+    # sample one side only and extrapolate linearly to r0.
+    def d3(r, h=5e-4):
+        return (d2(r + h, 1e-4) - d2(r - h, 1e-4)) / (2 * h)
+
+    dl = 2e-3
+    right = 2 * d3(r0 + dl) - d3(r0 + 2 * dl)
+    left = 2 * d3(r0 - dl) - d3(r0 - 2 * dl)
+    jump3 = abs(right - left)
+    expected = 60.0 / ((rc - rs) ** 3 * r0)
+    assert jump3 == pytest.approx(expected, rel=0.1)
+
+
+# ---------------------------------------------------------------------------------------------
+# Layers (eq. NN), embedding (eq. G2) and fitting (eq. fitting_energy)
+# ---------------------------------------------------------------------------------------------
+
+def test_embedding_derivatives_match_fd(water_oracle):
+    o = water_oracle
+    for net in range(4):
+        for x in (0.05, 0.4, 1.1, 1.9):
+            y, dy, d2y = o.embed(net, x)
+            h = 1e-5
+            yp, dyp, _ = o.embed(net, x + h)
+            ym, dym, _ = o.embed(net, x - h)
+            np.testing.assert_allclose(dy, (yp - ym) / (2 * h), rtol=1e-6, atol=1e-8)
+            np.testing.assert_allclose(d2y, (dyp - dym) / (2 * h), rtol=1e-5, atol=1e-7)
+
+
+def _embedding_only(model, params, net_keep):
+    """Copy of params whose embedding net `net_keep` has W2 = W3 = 0 and b2 = b3 = 0."""
+    p = params.copy()
+    off = 0
+    emb = [1] + model["emb"]
+    for net in range(model["ntypes"] ** 2):
+        for k in range(3):
+            nin, nout = emb[k], emb[k + 1]
+            if net == net_keep and k > 0:
+                p[off:off + nin * nout + nout] = 0.0   # W and b of layers 2, 3
+            off += nin * nout + 2 * nout
+    return p
+
+
+def test_embedding_skip_is_concatenation(water_oracle):
+    """With the two wider layers switched off (W = b = 0, so tanh(0) = 0), each ResNet layer that
+    doubles the width must pass {x, x} through: G repeats the 25 first-layer outputs 4 times."""
+    m = synth.WATER_MODEL
+    p = _embedding_only(m, synth.water_params(), 1)
+    o = Oracle(m, p)
+    y, dy, _ = o.embed(1, 0.7)
+    first = y[:25]
+    np.testing.assert_array_equal(y, np.tile(first, 4))
+    np.testing.assert_array_equal(dy, np.tile(dy[:25], 4))
+    # the first layer has no skip (1 -> 25): values are bounded by |w_hat| = 1
+    assert np.all(np.abs(first) <= 1.0)
+
+
+def test_fitting_gradient_matches_fd(water_oracle):
+    o = water_oracle
+    d = RNG.normal(0.0, 1e-3, 1600)
+    for t in (0, 1):
+        e, g = o.fit(t, d)
+        idx = RNG.choice(1600, 12, replace=False)
+        h = 1e-7
+        for k in idx:
+            dp, dm = d.copy(), d.copy()
+            dp[k] += h
+            dm[k] -= h
+            fd = (o.fit(t, dp)[0] - o.fit(t, dm)[0]) / (2 * h)
+            assert g[k] == pytest.approx(fd, rel=1e-5, abs=1e-6)
+
+
+# ---------------------------------------------------------------------------------------------
+# The dimer: the descriptor of a two-atom cluster has a closed form (Sec. II.A.1)
+# ---------------------------------------------------------------------------------------------
+
+def _dimer(r):
+    c = np.array([[0.0, 0.0, 0.0], [r * 0.6, r * 0.48, r * 0.64]])
+    return c, np.array([0, 1], dtype=np.int32)
+
+
+def test_dimer_descriptor_closed_form(water_oracle):
+    """Each atom has one neighbour, so T = N_c^-1 G^T R_j and, because |R_j|^2 = 2 s^2,
+    D = (2 s^2 / N_c^2) G G_<^T. E_i must equal F_0 of exactly that D (row-major, m*M_< + n)."""
+    o = water_oracle
+    nc = o.nc
+    for r in (0.4, 1.3, 3.0, 5.5):
+        c, t = _dimer(r)
+        out = o.compute(c, t, None, dumps=True)
+        s = o.switch(r)[0]
+        for i, (ti, tj) in enumerate([(0, 1), (1, 0)]):
+            G = o.embed(ti * 2 + tj, s)[0]
+            D = 2.0 * s * s / nc ** 2 * np.outer(G, G[:16])
+            e_ref = o.fit(ti, D.ravel())[0]
+            assert out["atom_energy"][i] == pytest.approx(e_ref, rel=1e-13, abs=1e-13)
+
+
+def test_dimer_force_is_central_and_matches_fd(water_oracle):
+    o = water_oracle
+    for r in (0.45, 0.9, 2.5, 5.2):
+        c, t = _dimer(r)
+        out = o.compute(c, t, None)
+        f = out["force"]
+        u = c[1] / np.linalg.norm(c[1])
+        np.testing.assert_allclose(f[0], -f[1], atol=1e-14)            # Newton's third law
+        np.testing.assert_allclose(np.cross(f[1], u), 0.0, atol=1e-14)  # along the bond
+        h = 1e-4
+        e = lambda rr: o.energy(*_dimer(rr), None)  # noqa: E731
+        de = (8 * (e(r + h) - e(r - h)) - (e(r + 2 * h) - e(r - 2 * h))) / (12 * h)
+        assert f[1] @ u == pytest.approx(-de, rel=1e-8, abs=1e-10)
+
+
+def test_dimer_force_vanishes_smoothly_at_cutoff(water_oracle):
+    """s, s', s'' vanish at r_c and s ~ (r_c - r)^3 there. The dimer descriptor is quadratic in s,
+    so its energy varies like (r_c - r)^6 and the force decays like (r_c - r)^5."""
+    o = water_oracle
+    rc = o.model["rcut"]
+    mags = []
+    for eps in (4e-2, 2e-2, 1e-2):
+        c, t = _dimer(rc - eps)
+        mags.append(np.linalg.norm(o.compute(c, t, None)["force"][1]))
+    assert mags[1] / mags[0] == pytest.approx(1 / 32, rel=0.1)
+    assert mags[2] / mags[1] == pytest.approx(1 / 32, rel=0.1)
+    c, t = _dimer(rc + 1e-9)
+    out = o.compute(c, t, None)
+    assert np.all(out["force"] == 0.0)
+
+
+# ---------------------------------------------------------------------------------------------
+# F = -dE/dr and the virial (Sec. II.A.2)
+# ---------------------------------------------------------------------------------------------
+
+def _fd_force(o, c, t, box, atom, comp, h=1e-4, **kw):
+    def e(delta):
+        cc = c.copy()
+        cc[atom, comp] += delta
+        return o.energy(cc, t, box, **kw)
+    return -(8 * (e(h) - e(-h)) - (e(2 * h) - e(-2 * h))) / (12 * h)
+
+
+@pytest.mark.parametrize("case", ["water192", "serve50_3type", "serve180_2type"])
+def test_force_matches_fd(case, water_oracle, serve_oracle):
+    if case == "water192":
+        o, (c, t, b) = water_oracle, synth.water_192()
+    elif case == "serve50_3type":   # L = 7.94 A < 2 r_c: several images of one atom
+        o, (c, t, b) = serve_oracle, synth.serving_frame(50, 7, 3)
+    else:
+        o, (c, t, b) = serve_oracle, synth.serving_frame(180, 8, 2)
+    f = o.compute(c, t, b)["force"]
+    for atom in RNG.choice(len(t), 4, replace=False):
+        for comp in range(3):
+            assert f[atom, comp] == pytest.approx(_fd_force(o, c, t, b, atom, comp), abs=2e-7)
+
+
+def test_virial_matches_cell_derivative(water_oracle):
+    """Xi_ab = -sum_g dE/dh_ga h_gb, differentiating with fractional coordinates held fixed.
+    The cell is made triclinic first so every entry of h matters."""
+    o = water_oracle
+    c, t, b = synth.water_192()
+    b = b + np.array([[0.0, 0.0, 0.0], [0.9, 0.0, 0.0], [-0.6, 0.7, 0.0]])
+    frac = c @ np.linalg.inv(synth.water_192()[2])
+    c = frac @ b
+    xi = o.compute(c, t, b)["virial"]
+
+    def e(hh):
+        return o.energy(frac @ hh, t, hh)
+
+    dEdh = np.zeros((3, 3))
+    step = 1e-5
+    for g in range(3):
+        for a in range(3):
+            hp, hm = b.copy(), b.copy()
+            hp[g, a] += step
+            hm[g, a] -= step
+            dEdh[g, a] = (e(hp) - e(hm)) / (2 * step)
+    ref = -dEdh.T @ b      # ref[a, b'] = -sum_g dE/dh_ga h_gb'
+    np.testing.assert_allclose(xi, ref, atol=5e-6)
+    np.testing.assert_allclose(xi, xi.T, atol=1e-10)
+
+
+def _cluster(n=60, seed=3):
+    c, t, _ = synth.serving_frame(n, seed, 2)
+    return c, t
+
+
+def test_open_cluster_virial_torque_and_momentum(water_oracle):
+    o = water_oracle
+    c, t = _cluster()
+    out = o.compute(c, t, None)
+    f, xi = out["force"], out["virial"]
+    np.testing.assert_allclose(f.sum(0), 0.0, atol=1e-12)
+    np.testing.assert_allclose(np.cross(c, f).sum(0), 0.0, atol=1e-11)
+    # for an open cluster the pair virial is sum_k F_k (x) r_k
+    np.testing.assert_allclose(xi, np.einsum("ka,kb->ab", f, c), atol=1e-11)
+
+
+def test_periodic_momentum_and_symmetric_virial(water_oracle):
+    out = water_oracle.compute(*synth.water_192())
+    np.testing.assert_allclose(out["force"].sum(0), 0.0, atol=1e-12)
+    np.testing.assert_allclose(out["virial"], out["virial"].T, atol=1e-11)
+
+
+# ---------------------------------------------------------------------------------------------
+# Invariances of the construction (relative coordinates, R R^T Gram form, sum over neighbours)
+# ---------------------------------------------------------------------------------------------
+
+def _rot(seed):
+    q = np.random.default_rng(seed).standard_normal(4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def test_translation_invariance(water_oracle):
+    c, t, b = synth.water_192()
+    a = water_oracle.compute(c, t, b)
+    z = water_oracle.compute(c + np.array([3.7, -11.2, 40.1]), t, b)
+    assert z["energy"] == pytest.approx(a["energy"], rel=1e-12)
+    np.testing.assert_allclose(z["force"], a["force"], atol=1e-10)
+    np.testing.assert_allclose(z["virial"], a["virial"], atol=1e-10)
+
+
+def test_rotation_invariance_periodic_and_open(water_oracle):
+    Q = _rot(9)
+    c, t, b = synth.water_192()
+    a = water_oracle.compute(c, t, b)
+    z = water_oracle.compute(c @ Q.T, t, b @ Q.T)      # rotate atoms and lattice vectors
+    assert z["energy"] == pytest.approx(a["energy"], rel=1e-12)
+    np.testing.assert_allclose(z["force"], a["force"] @ Q.T, atol=1e-10)
+    np.testing.assert_allclose(z["virial"], Q @ a["virial"] @ Q.T, atol=1e-10)
+    c, t = _cluster()
+    a = water_oracle.compute(c, t, None)
+    z = water_oracle.compute(c @ Q.T, t, None)
+    assert z["energy"] == pytest.approx(a["energy"], rel=1e-12)
+    np.testing.assert_allclose(z["force"], a["force"] @ Q.T, atol=1e-11)
+
+
+def test_permutation_invariance(serve_oracle):
+    c, t, b = synth.serving_frame(300, 11, 3)
+    a = serve_oracle.compute(c, t, b)
+    perm = RNG.permutation(len(t))
+    z = serve_oracle.compute(c[perm], t[perm], b)
+    assert z["energy"] == pytest.approx(a["energy"], rel=1e-12)
+    np.testing.assert_allclose(z["force"], a["force"][perm], atol=1e-11)
+    np.testing.assert_allclose(z["virial"], a["virial"], atol=1e-10)
+
+
+def test_tiling_small_cell_vs_replica(serve_oracle):
+    """A 50-atom cell with L = 7.94 A < 2 r_c (several images of one atom within r_c) and its
+    2x2x2 replica (L >= 2 r_c) describe the same infinite crystal: equal forces per image, 8x the
+    energy and virial, as long as no neighbour is cut by sel."""
+    c, t, b = synth.serving_frame(50, 21, 2)
+    a = serve_oracle.compute(c, t, b)
+    L = b[0, 0]
+    shifts = np.array([[i, j, k] for i in range(2) for j in range(2) for k in range(2)]) * L
+    c8 = (c[None] + shifts[:, None]).reshape(-1, 3)
+    t8 = np.tile(t, 8)
+    z = serve_oracle.compute(c8, t8, 2 * b)
+    assert a["ndrop"] == 0 and z["ndrop"] == 0
+    assert z["energy"] == pytest.approx(8 * a["energy"], rel=1e-12)
+    np.testing.assert_allclose(z["force"].reshape(8, -1, 3), np.broadcast_to(a["force"], (8, 50, 3)),
+                               atol=1e-11)
+    np.testing.assert_allclose(z["virial"], 8 * a["virial"], atol=1e-9)
+
+
+# ---------------------------------------------------------------------------------------------
+# Neighbour list (Sec. II.A padding, Sec. II.A.1 type blocks, Sec. III.B.1 ordering)
+# ---------------------------------------------------------------------------------------------
+
+def _brute_neighbours(c, t, box, rc):
+    """Independent enumeration with numpy: every (j, image) with |r_j + n h - r_i| < r_c."""
+    frac = c @ np.linalg.inv(box)
+    frac -= np.floor(frac)
+    pos = frac @ box
+    width = np.linalg.det(box) / np.linalg.norm(np.cross(np.roll(box, -1, 0), np.roll(box, -2, 0)), axis=1)
+    K = np.ceil(rc / width).astype(int)
+    shifts = np.array([[a, b, cc] for a in range(-K[0], K[0] + 1) for b in range(-K[1], K[1] + 1)
+                       for cc in range(-K[2], K[2] + 1)], dtype=float) @ box
+    out = []
+    for i in range(len(t)):
+        d = pos[None, :, :] + shifts[:, None, :] - pos[i]
+        r = np.linalg.norm(d, axis=2)
+        ok = r < rc
+        zero = np.all(shifts == 0, axis=1)
+        ok[zero, i] = False
+        out.append(sorted(zip(t[np.nonzero(ok)[1]], r[ok], np.nonzero(ok)[1])))
+    return out
+
+
+@pytest.mark.parametrize("case", ["water192", "serve50", "fcc_trunc", "triclinic"])
+def test_nlist_brute_force_and_cell_list_agree(case, water_oracle, serve_oracle, fcc_oracle):
+    if case == "water192":
+        o, (c, t, b) = water_oracle, synth.water_192()
+    elif case == "serve50":
+        o, (c, t, b) = serve_oracle, synth.serving_frame(50, 4, 3)
+    elif case == "fcc_trunc":
+        o, (c, t, b) = fcc_oracle, synth.fcc_box(5, 3.6, 1)
+    else:
+        o = serve_oracle
+        c, t, b0 = synth.serving_frame(400, 2, 3)
+        b = b0 + np.array([[0, 0, 0], [4.0, 0, 0], [-3.0, 5.0, 0]])
+        c = (c @ np.linalg.inv(b0)) @ b
+    nl0, r0, d0 = o.nlist(c, t, b, method=0)
+    nl1, r1, d1 = o.nlist(c, t, b, method=1)
+    np.testing.assert_array_equal(nl0, nl1)
+    np.testing.assert_array_equal(r0, r1)
+    assert d0 == d1
+
+
+@pytest.mark.parametrize("case", ["serve50", "fcc_trunc"])
+def test_nlist_is_sorted_per_type_and_keeps_nearest(case, serve_oracle, fcc_oracle):
+    if case == "serve50":
+        o, (c, t, b) = serve_oracle, synth.serving_frame(50, 4, 3)
+    else:
+        o, (c, t, b) = fcc_oracle, synth.fcc_box(5, 3.6, 1)
+    nl, rij, ndrop = o.nlist(c, t, b)
+    ref = _brute_neighbours(c, t, b, o.model["rcut"])
+    sel = o.model["sel"]
+    off = np.concatenate([[0], np.cumsum(sel)])
+    total_drop = 0
+    for i in range(len(t)):
+        for a in range(len(sel)):
+            want = [x for x in ref[i] if x[0] == a]
+            keep = want[:sel[a]]
+            total_drop += len(want) - len(keep)
+            block = nl[i, off[a]:off[a + 1]]
+            got = block[block >= 0]
+            assert list(got) == [x[2] for x in keep]
+            assert np.all(block[len(keep):] == -1)                  # padding after the real rows
+            r = np.linalg.norm(rij[i, off[a]:off[a] + len(keep)], axis=1)
+            np.testing.assert_allclose(r, [x[1] for x in keep], rtol=1e-13)
+            assert np.all(np.diff(r) >= 0)                            # ascending distance
+            assert np.all(t[got] == a)
+    assert ndrop == total_drop
+    if case == "fcc_trunc":
+        assert ndrop > 0
+
+
+# ---------------------------------------------------------------------------------------------
+# Tabulated embedding (Sec. II.A.6, eq. compress and its coefficients)
+# ---------------------------------------------------------------------------------------------
+
+def test_table_pieces_interpolate_value_slope_curvature(fcc_oracle):
+    """The printed coefficients must make each quintic match y, y', y'' of the net at both ends
+    of its interval (the conditions that define the quintic Hermite interpolant)."""
+    o = fcc_oracle
+    dx, nint = 0.01, 50
+    coef = o.table(dx, nint)
+    for l in (0, 7, 23, 49):
+        for side, x in ((0, l * dx), (1, (l + 1) * dx)):
+            y, dy, d2y = o.embed(0, x)
+            a, b, c, d, e, f = coef[0, l].T
+            tt = x - l * dx
+            val = ((((a * tt + b) * tt + c) * tt + d) * tt + e) * tt + f
+            der = (((5 * a * tt + 4 * b) * tt + 3 * c) * tt + 2 * d) * tt + e
+            cur = ((20 * a * tt + 12 * b) * tt + 6 * c) * tt + 2 * d
+            np.testing.assert_allclose(val, y, rtol=1e-11, atol=1e-12)
+            np.testing.assert_allclose(der, dy, rtol=1e-9, atol=1e-10)
+            np.testing.assert_allclose(cur, d2y, rtol=1e-7, atol=1e-8)
+
+
+def test_table_error_is_sixth_order(water_oracle):
+    """The quintic Hermite remainder is t^3 (t - dx)^3 y^(6) / 6!, so halving the stride divides
+    the error by about 2^6 = 64 (coarse strides keep it above rounding)."""
+    o = water_oracle
+    errs = []
+    xs = np.linspace(0.003, 1.997, 101)
+    for dx, nint in ((0.4, 5), (0.2, 10), (0.1, 20)):
+        coef = o.table(dx, nint)
+        errs.append(max(np.abs(o.table_eval(coef, dx, 1, x)[0] - o.embed(1, x)[0]).max() for x in xs))
+    assert 40.0 < errs[0] / errs[1] < 100.0
+    assert 40.0 < errs[1] / errs[2] < 100.0
+
+
+def test_tabulated_model_force_matches_fd(fcc_oracle):
+    o = fcc_oracle
+    c, t, b = synth.fcc_box(4, 3.6, 5)
+    coef = o.table(0.01, 50)
+    out = o.compute(c, t, b, table=coef, dx=0.01)
+    assert out["table_oor"] == 0
+    for atom in (0, 17, 200):
+        for comp in range(3):
+            fd = _fd_force(o, c, t, b, atom, comp, table=coef, dx=0.01)
+            assert out["force"][atom, comp] == pytest.approx(fd, abs=5e-7)
+
+
+def test_tabulated_model_close_to_network(fcc_oracle):
+    o = fcc_oracle
+    c, t, b = synth.fcc_box(4, 3.6, 5)
+    coef = o.table(0.01, 50)
+    tab = o.compute(c, t, b, table=coef, dx=0.01)
+    net = o.compute(c, t, b)
+    assert abs(tab["energy"] - net["energy"]) / len(t) < 1e-8
+    assert np.abs(tab["force"] - net["force"]).max() < 1e-6
