@@ -1,0 +1,155 @@
+/*
+ * dpk.h -- C ABI of libdpk.so: MI355X (gfx950) evaluation of the smooth two-body-embedding
+ * Deep Potential (se_e2_a): energy, forces and virial of one frame.
+ *
+ * The operation follows DeePMD-kit v2 (arXiv 2304.09409):
+ *   Sec. II.A        E = sum_i E_i with E_i = F_0(D^i); neighbour lists padded to N_c.
+ *   Sec. II.A.1      D^i = N_c^-2 (G^i)^T R^i (R^i)^T G^i_<, environment rows
+ *                    (s, s x/r, s y/r, s z/r) with r_ij = r_j - r_i and the C^2 switching function
+ *                    s(r) (eq. switch); G_j = N^{a_i,a_j}(s(r_ij)) (eq. G2); per-species nets.
+ *   Sec. II.A.2      E_i = F_0(D^i) (eq. fitting_energy); F_i = -dE/dr_i;
+ *                    Xi_ab = -sum_g dE/dh_ga h_gb.
+ *   Sec. II.A.6      layers y = w_hat * tanh(x W + b) (+ x or + {x,x}) (eq. NN); tabulated
+ *                    embedding by quintic pieces (eq. compress).
+ *   Sec. III.B.1     neighbour formatting by (type, distance, index).
+ *
+ * Conventions shared by every entry point:
+ *   - Units: Angstrom and eV; the virial is in eV with Xi_ab stored at [3a + b].
+ *   - coord is [natoms][3] row-major; atype is [natoms] with values in [0, ntypes);
+ *     box is the 3x3 cell h row-major, rows are the lattice vectors (h_ab = component b of
+ *     lattice vector a), or NULL for an open (non-periodic) cluster.
+ *   - Outputs are in the caller's atom order.
+ *   - Every function returns DPK_OK (0) or a negative code; dpk_last_error() returns a
+ *     thread-local description of the last failure on the calling thread.
+ *   - No function keeps a caller pointer after it returns, except as stated for the device
+ *     entry point's stream-ordered completion.
+ *
+ * Model parameter blob (FP64, flat, owned by the caller during dpk_model_create only):
+ *   embedding nets first, net index e = a_i * ntypes + a_j (or e = a_j when type_one_side),
+ *   each with layers 1 -> emb[0] -> emb[1] -> emb[2]; then one fitting net per type a_i with
+ *   layers (emb[2] * axis) -> fit[0] -> fit[1] -> fit[2] -> 1. Every layer stores
+ *   W [n_in][n_out] row-major, then b [n_out], then w_hat [n_out]. Hidden layers use tanh with a
+ *   skip connection +x when n_out == n_in and +{x,x} when n_out == 2 n_in; the fitting output
+ *   layer is linear without skip.
+ */
+#ifndef DPK_H
+#define DPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DPK_OK = 0,
+    DPK_E_INVALID_ARG = -1,   /* NULL pointer, natoms < 1, bad model description            */
+    DPK_E_TYPE_RANGE = -2,    /* an atom type outside [0, ntypes)                            */
+    DPK_E_BOX = -3,           /* det(h) <= 0                                                  */
+    DPK_E_NBR_OVERFLOW = -4,  /* more candidates within r_c than the selection buffer holds,
+                                 or (strict mode) a neighbour cut by sel                      */
+    DPK_E_BUDGET = -5,        /* the frame's device workspace exceeds the context's budget    */
+    DPK_E_OOM = -6,           /* device allocation failed                                     */
+    DPK_E_DEVICE = -7,        /* a HIP call failed                                            */
+    DPK_E_UNIMPLEMENTED = -8  /* combination not supported (e.g. table in FP64 with ntypes>4) */
+};
+
+enum {
+    DPK_FP64 = 0,   /* every GEMM and activation in FP64 (FP64 MFMA)                          */
+    DPK_MIXED = 1,  /* embedding and fitting GEMMs as three BF16 MFMA products (hi*hi + hi*lo +
+                       lo*hi) with FP32 accumulation; FP32 activations; FP64 geometry, switching
+                       function, force chain rule, force and virial accumulation, energy sum  */
+    DPK_BF16 = 2    /* as DPK_MIXED with one BF16 product per GEMM (fast, about 1e-2 relative) */
+};
+
+#define DPK_MAX_TYPES 8
+
+/* Model description. sel[] are the per-type neighbour capacities (N_c = sum of sel);
+ * emb[] the embedding widths, axis = M_<, fit[] the fitting hidden widths. This build's
+ * kernels require emb = {25, 50, 100}, axis = 16, fit = {240, 240, 240}. */
+typedef struct {
+    int32_t ntypes;
+    int32_t sel[DPK_MAX_TYPES];
+    double rcut;
+    double rcut_smth;
+    int32_t emb[3];
+    int32_t axis;
+    int32_t fit[3];
+    int32_t type_one_side;
+} dpk_model_desc;
+
+typedef struct dpk_model dpk_model;   /* immutable after creation; shareable across contexts  */
+typedef struct dpk_ctx dpk_ctx;       /* one device + workspace; not thread-safe             */
+
+typedef struct {
+    int64_t nbr_dropped;          /* neighbours cut by sel in the last computed frame          */
+    int64_t table_out_of_range;   /* tabulated inputs outside [0, table range] (last frame)    */
+    int64_t max_candidates;       /* largest number of atoms within r_c of one atom            */
+    int64_t workspace_bytes;      /* device bytes held by the context                          */
+} dpk_stats;
+
+/* Last error message of the calling thread ("" if none). */
+const char *dpk_last_error(void);
+
+/* Create a model from a description and its FP64 parameter blob (nparams values, layout
+ * above). The blob is copied; the caller keeps ownership of params. */
+int dpk_model_create(const dpk_model_desc *desc, const double *params, int64_t nparams,
+                     dpk_model **out);
+
+/* Number of FP64 values the blob of desc must hold. */
+int64_t dpk_model_param_count(const dpk_model_desc *desc);
+
+/* Replace the embedding nets by quintic tables (Sec. II.A.6, eq. compress): nodes at
+ * x_l = l * stride, l = 0..L_c with L_c = ceil(x_max / stride), values and first and second
+ * derivatives of each net at the nodes, and the paper's coefficient formulas. The table
+ * variable is the net input x = s(r). Contexts created afterwards use the table. */
+int dpk_model_tabulate(dpk_model *m, double stride, double x_max);
+
+void dpk_model_free(dpk_model *m);
+
+/* Create a context on HIP device `device` with precision DPK_FP64, DPK_MIXED or DPK_BF16.
+ * hbm_budget_bytes bounds the context's workspace (0 = no bound). strict_sel != 0 makes a
+ * neighbour cut by sel an error (DPK_E_NBR_OVERFLOW) instead of a counted truncation. */
+int dpk_ctx_create(const dpk_model *m, int device, int precision, size_t hbm_budget_bytes,
+                   int strict_sel, dpk_ctx **out);
+
+void dpk_ctx_free(dpk_ctx *c);
+
+/* Device bytes a frame of natoms atoms needs in this context (workspace only). */
+int64_t dpk_ctx_workspace_bytes(const dpk_ctx *c, int64_t natoms);
+
+/* Host-pointer entry point: copies the frame to the device, evaluates it and copies the results
+ * back; returns after the results are in the caller's buffers. energy: 1 double; force:
+ * natoms*3; virial: 9; atom_energy: natoms or NULL. */
+int dpk_compute(dpk_ctx *c, int64_t natoms, const double *coord, const int32_t *atype,
+                const double *box, double *energy, double *force, double *virial,
+                double *atom_energy);
+
+/* Device-pointer entry point: d_coord, d_atype and the outputs are device pointers; box is a
+ * HOST pointer (9 doubles) or NULL. All work is enqueued on hip_stream (a hipStream_t, NULL for
+ * the default stream) and the call returns without waiting, except with box == NULL, where it
+ * waits once for the cluster's bounding box. The outputs are valid once the stream reaches this
+ * point. Type-range and overflow errors found on the device are reported by the next
+ * dpk_ctx_check() (or the next call of a synchronising entry point). */
+int dpk_compute_device(dpk_ctx *c, int64_t natoms, const double *d_coord,
+                       const int32_t *d_atype, const double *box, double *d_energy,
+                       double *d_force, double *d_virial, double *d_atom_energy,
+                       void *hip_stream);
+
+/* Wait for the context's last stream and report device-side errors of the last frame. */
+int dpk_ctx_check(dpk_ctx *c);
+
+int dpk_ctx_stats(dpk_ctx *c, dpk_stats *out);
+
+/* Stage dumps of the last computed frame (host buffers, caller order), for parity tests.
+ * nlist: natoms * N_c neighbour indices (caller numbering, -1 padding), in the per-type block
+ * order of Sec. II.A.1 sorted by (distance, index, image). */
+int dpk_debug_nlist(dpk_ctx *c, int32_t *nlist);
+/* T = N_c^-1 G^T R (natoms * M * 4) and dE/dT (natoms * M * 4), as FP64. */
+int dpk_debug_descriptor(dpk_ctx *c, double *T, double *dT);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPK_H */

@@ -1,0 +1,756 @@
+// api.cpp -- host side of libdpk: the C ABI declared in include/dpk.h.
+//
+// Model packing (per precision), the quintic table build (Sec. II.A.6, eq. compress), device
+// workspace management, frame geometry set-up and the launch sequence of one evaluation:
+//   types -> cell list -> neighbour list -> embedding + contraction (T) -> fitting (E_i, dE/dT)
+//   -> adjoint (F, virial) -> reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dpk.h"
+#include "dpk_internal.h"
+#include "dpk_launch.h"
+
+using namespace dpk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return fail(DPK_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+uint16_t bf16_bits(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+float bf16_float(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+int64_t count_params(const dpk_model_desc* d)
+{
+    int e[4] = {1, d->emb[0], d->emb[1], d->emb[2]};
+    int f[5] = {d->emb[2] * d->axis, d->fit[0], d->fit[1], d->fit[2], 1};
+    int64_t nets = d->type_one_side ? d->ntypes : (int64_t)d->ntypes * d->ntypes;
+    int64_t c = 0;
+    for (int k = 0; k < 3; ++k) c += nets * ((int64_t)e[k] * e[k + 1] + 2 * e[k + 1]);
+    for (int k = 0; k < 4; ++k) c += (int64_t)d->ntypes * ((int64_t)f[k] * f[k + 1] + 2 * f[k + 1]);
+    return c;
+}
+
+struct Layer {
+    int nin, nout;
+    const double *W, *b, *wh;
+};
+
+}  // namespace
+
+struct dpk_model {
+    dpk_model_desc desc;
+    std::vector<double> params;
+    int nets = 0, nc = 0;
+    std::vector<Layer> emb;   // [nets][3]
+    std::vector<Layer> fit;   // [ntypes][4]
+    bool tabulated = false;
+    double tab_dx = 0.0;
+    int tab_nint = 0;
+    std::vector<double> table;   // [nets][nint][100][6]
+};
+
+namespace {
+
+void index_layers(dpk_model* m)
+{
+    const dpk_model_desc& d = m->desc;
+    int e[4] = {1, d.emb[0], d.emb[1], d.emb[2]};
+    int f[5] = {d.emb[2] * d.axis, d.fit[0], d.fit[1], d.fit[2], 1};
+    const double* p = m->params.data();
+    auto take = [&](int nin, int nout) {
+        Layer L{nin, nout, p, p + (int64_t)nin * nout, p + (int64_t)nin * nout + nout};
+        p += (int64_t)nin * nout + 2 * nout;
+        return L;
+    };
+    m->emb.clear();
+    m->fit.clear();
+    for (int n = 0; n < m->nets; ++n)
+        for (int k = 0; k < 3; ++k) m->emb.push_back(take(e[k], e[k + 1]));
+    for (int t = 0; t < d.ntypes; ++t)
+        for (int k = 0; k < 4; ++k) m->fit.push_back(take(f[k], f[k + 1]));
+}
+
+// Value and first two derivatives (d/dx) of embedding net `net` at x, carried forward through
+// the layers of eq. NN (tanh, skip by size).
+void embed_derivs(const dpk_model* m, int net, double x, double* y, double* y1, double* y2)
+{
+    std::vector<double> z{x}, z1{1.0}, z2{0.0};
+    for (int k = 0; k < 3; ++k) {
+        const Layer& L = m->emb[(size_t)net * 3 + k];
+        std::vector<double> a(L.nout), n0(L.nout), n1(L.nout), n2(L.nout);
+        for (int o = 0; o < L.nout; ++o) {
+            double v = L.b[o], v1 = 0.0, v2 = 0.0;
+            for (int i = 0; i < L.nin; ++i) {
+                const double w = L.W[(int64_t)i * L.nout + o];
+                v += z[i] * w;
+                v1 += z1[i] * w;
+                v2 += z2[i] * w;
+            }
+            const double t = std::tanh(v), gp = 1.0 - t * t;
+            const double t1 = gp * v1, t2 = gp * v2 - 2.0 * t * gp * v1 * v1;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            if (L.nout == L.nin) { s0 = z[o]; s1 = z1[o]; s2 = z2[o]; }
+            else if (L.nout == 2 * L.nin) { s0 = z[o % L.nin]; s1 = z1[o % L.nin]; s2 = z2[o % L.nin]; }
+            n0[o] = L.wh[o] * t + s0;
+            n1[o] = L.wh[o] * t1 + s1;
+            n2[o] = L.wh[o] * t2 + s2;
+        }
+        z.swap(n0);
+        z1.swap(n1);
+        z2.swap(n2);
+    }
+    for (int o = 0; o < E2; ++o) { y[o] = z[o]; y1[o] = z1[o]; y2[o] = z2[o]; }
+}
+
+// Physical position of logical K index k within 16-wide K-chunks. FP64 MFMA lanes of group g
+// supply k = 16c + g + 4v (v = 0..3); storing them contiguously lets each lane load its four
+// operands at once. The BF16 instructions take k = 16c + 4g + v, which is already contiguous.
+inline int kphys(int precision, int k)
+{
+    if (precision != DPK_FP64) return k;
+    const int c = k >> 4, r = k & 15;
+    return 16 * c + 4 * (r & 3) + (r >> 2);
+}
+
+// Dense matrix (row-major, `rows` x `cols`) in each plane's element type.
+struct Planes {
+    int precision;
+    std::vector<double> d;     // FP64
+    std::vector<uint16_t> h, l;
+    void init(int prec, size_t n) {
+        precision = prec;
+        if (prec == DPK_FP64) d.assign(n, 0.0);
+        else { h.assign(n, 0); if (prec == DPK_MIXED) l.assign(n, 0); }
+    }
+    void set(size_t i, double v) {
+        if (precision == DPK_FP64) { d[i] = v; return; }
+        const uint16_t hb = bf16_bits((float)v);
+        h[i] = hb;
+        if (precision == DPK_MIXED) l[i] = bf16_bits((float)(v - (double)bf16_float(hb)));
+    }
+};
+
+}  // namespace
+
+struct dpk_ctx {
+    const dpk_model* model = nullptr;
+    int device = 0, precision = 0, strict = 0;
+    size_t budget = 0;
+    hipStream_t stream = nullptr;        // own stream for the host entry point
+    hipStream_t last_stream = nullptr;   // stream of the last frame
+    size_t acc_size = 8;
+    // device model
+    void* evec = nullptr;
+    void* emat = nullptr;
+    void* fvec = nullptr;
+    void* fmat = nullptr;
+    void* table = nullptr;
+    size_t model_bytes = 0;
+    // workspace
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t cap_atoms = 0;
+    int64_t cap_cells = 0;
+    // views of the workspace (valid for the capacity)
+    int *perm, *inv_perm, *itype, *tcount, *toff, *cell_of, *cell_atoms, *cell_count, *cell_start, *cursor;
+    int *nl_j, *nnei, *h_atype;
+    double *pos, *nl_r, *Ei, *F, *vir_part, *bbox, *h_coord, *h_out;
+    void *T, *dT;
+    DevStats* stats;
+    int64_t vir_blocks = 0;
+    // last frame
+    int64_t last_n = 0;
+    int64_t last_nvp = 0;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Byte layout of the workspace for n atoms and ncell bins; if base != nullptr, assign views.
+size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
+{
+    const dpk_model* m = c->model;
+    const int nt = m->desc.ntypes, nc = m->nc;
+    const int64_t nvb = (n + embed_atoms_per_block(c->precision) - 1) / embed_atoms_per_block(c->precision);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    char* p;
+    p = take(sizeof(int) * n); if (base) c->perm = (int*)p;
+    p = take(sizeof(int) * n); if (base) c->inv_perm = (int*)p;
+    p = take(sizeof(int) * n); if (base) c->itype = (int*)p;
+    p = take(sizeof(int) * MAXT); if (base) c->tcount = (int*)p;
+    p = take(sizeof(int) * (MAXT + 1)); if (base) c->toff = (int*)p;
+    p = take(sizeof(DevStats)); if (base) c->stats = (DevStats*)p;
+    p = take(sizeof(double) * 3 * n); if (base) c->pos = (double*)p;
+    p = take(sizeof(int) * n); if (base) c->cell_of = (int*)p;
+    p = take(sizeof(int) * n); if (base) c->cell_atoms = (int*)p;
+    p = take(sizeof(int) * ncell); if (base) c->cell_count = (int*)p;
+    p = take(sizeof(int) * (ncell + 1)); if (base) c->cell_start = (int*)p;
+    p = take(sizeof(int) * ncell); if (base) c->cursor = (int*)p;
+    p = take(sizeof(int) * n * nc); if (base) c->nl_j = (int*)p;
+    p = take(sizeof(int) * n * nt); if (base) c->nnei = (int*)p;
+    p = take(sizeof(double) * 3 * n * nc); if (base) c->nl_r = (double*)p;
+    p = take(c->acc_size * n * E2 * 4); if (base) c->T = p;
+    p = take(c->acc_size * n * E2 * 4); if (base) c->dT = p;
+    p = take(sizeof(double) * n); if (base) c->Ei = (double*)p;
+    p = take(sizeof(double) * 3 * n); if (base) c->F = (double*)p;
+    p = take(sizeof(double) * 9 * nvb); if (base) { c->vir_part = (double*)p; c->vir_blocks = nvb; }
+    p = take(sizeof(double) * 8); if (base) c->bbox = (double*)p;
+    p = take(sizeof(double) * 3 * n); if (base) c->h_coord = (double*)p;
+    p = take(sizeof(int) * n); if (base) c->h_atype = (int*)p;
+    p = take(sizeof(double) * (10 + 4 * n)); if (base) c->h_out = (double*)p;
+    return off;
+}
+
+int ensure_ws(dpk_ctx* c, int64_t n, int64_t ncell)
+{
+    if (n <= c->cap_atoms && ncell <= c->cap_cells && c->ws) return DPK_OK;
+    int64_t nn = std::max<int64_t>(n, c->cap_atoms), ncl = std::max<int64_t>(ncell, c->cap_cells);
+    size_t bytes = layout_ws(c, nn, ncl, nullptr);
+    if (c->budget && bytes + c->model_bytes > c->budget)
+        return fail(DPK_E_BUDGET, "frame of %lld atoms needs %zu workspace bytes + %zu model bytes, budget %zu",
+                    (long long)n, bytes, c->model_bytes, c->budget);
+    if (c->ws) {
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipFree(c->ws));
+        c->ws = nullptr;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        hipGetLastError();
+        return fail(DPK_E_OOM, "hipMalloc of %zu workspace bytes failed", bytes);
+    }
+    c->ws = p;
+    c->ws_bytes = bytes;
+    c->cap_atoms = nn;
+    c->cap_cells = ncl;
+    layout_ws(c, nn, ncl, (char*)p);
+    return DPK_OK;
+}
+
+// Cell geometry (Sec. II.A: coordinates under PBC or in vacuum). Rows of h are the lattice
+// vectors; fractional s = r h^-1; perpendicular width d_k = det h / |a_l x a_m|.
+int setup_geometry(dpk_ctx* c, const double* box, const double* bbox, GeomParams& gp)
+{
+    const dpk_model* m = c->model;
+    const double rc = m->desc.rcut;
+    std::memset(&gp, 0, sizeof(gp));
+    gp.rc2 = rc * rc;
+    gp.ntypes = m->desc.ntypes;
+    gp.nc = m->nc;
+    int acc = 0;
+    for (int t = 0; t < m->desc.ntypes; ++t) {
+        gp.sel[t] = m->desc.sel[t];
+        gp.off[t] = acc;
+        acc += m->desc.sel[t];
+    }
+    if (box) {
+        const double* h = box;
+        const double det = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) +
+                           h[2] * (h[3] * h[7] - h[4] * h[6]);
+        if (!(det > 0.0)) return fail(DPK_E_BOX, "det(box) = %g is not positive", det);
+        gp.periodic = 1;
+        for (int k = 0; k < 9; ++k) gp.h[k] = h[k];
+        gp.hinv[0] = (h[4] * h[8] - h[5] * h[7]) / det;
+        gp.hinv[1] = (h[2] * h[7] - h[1] * h[8]) / det;
+        gp.hinv[2] = (h[1] * h[5] - h[2] * h[4]) / det;
+        gp.hinv[3] = (h[5] * h[6] - h[3] * h[8]) / det;
+        gp.hinv[4] = (h[0] * h[8] - h[2] * h[6]) / det;
+        gp.hinv[5] = (h[2] * h[3] - h[0] * h[5]) / det;
+        gp.hinv[6] = (h[3] * h[7] - h[4] * h[6]) / det;
+        gp.hinv[7] = (h[1] * h[6] - h[0] * h[7]) / det;
+        gp.hinv[8] = (h[0] * h[4] - h[1] * h[3]) / det;
+        for (int k = 0; k < 3; ++k) {
+            const double* a = h + 3 * ((k + 1) % 3);
+            const double* b = h + 3 * ((k + 2) % 3);
+            const double cx = a[1] * b[2] - a[2] * b[1], cy = a[2] * b[0] - a[0] * b[2], cz = a[0] * b[1] - a[1] * b[0];
+            const double width = det / std::sqrt(cx * cx + cy * cy + cz * cz);
+            int nb = (int)std::floor(width / rc);
+            if (nb < 1) nb = 1;
+            if (nb > 256) nb = 256;
+            gp.nb[k] = nb;
+            gp.K[k] = (int)std::ceil(rc / (width / nb));
+            if (gp.K[k] > 60) return fail(DPK_E_BOX, "cell too thin for r_c (%d image shells)", gp.K[k]);
+        }
+    } else {
+        gp.periodic = 0;
+        for (int k = 0; k < 3; ++k) {
+            const double lo = bbox[k], hi = bbox[3 + k];
+            double ext = hi - lo;
+            int nb = (int)std::floor(ext / rc);
+            if (nb < 1) nb = 1;
+            if (nb > 256) nb = 256;
+            gp.nb[k] = nb;
+            gp.origin[k] = lo;
+            gp.binw[k] = (ext > 0.0 ? ext : 1.0) / nb;
+            if (nb * gp.binw[k] < ext) gp.binw[k] = std::nextafter(gp.binw[k], 1e300);
+            gp.K[k] = (int)std::ceil(rc / gp.binw[k]);
+            if (gp.K[k] > nb) gp.K[k] = nb;
+        }
+    }
+    return DPK_OK;
+}
+
+template <class T>
+int upload(void** dst, const T* src, size_t n)
+{
+    HIPCHK(hipMalloc(dst, sizeof(T) * n));
+    HIPCHK(hipMemcpy(*dst, src, sizeof(T) * n, hipMemcpyHostToDevice));
+    return DPK_OK;
+}
+
+int upload_planes(void** dst, const Planes& P)
+{
+    if (P.precision == DPK_FP64) return upload(dst, P.d.data(), P.d.size());
+    std::vector<uint16_t> all(P.h);
+    all.insert(all.end(), P.l.begin(), P.l.end());
+    return upload(dst, all.data(), all.size());
+}
+
+// Pack and upload the model for one precision.
+int upload_model(dpk_ctx* c)
+{
+    const dpk_model* m = c->model;
+    const int prec = c->precision, nets = m->nets, nt = m->desc.ntypes;
+    const bool f64 = prec == DPK_FP64;
+    std::vector<double> ev((size_t)nets * EVEC, 0.0), fv((size_t)nt * FVEC, 0.0);
+    Planes em, fm;
+    em.init(prec, (size_t)nets * EM_SIZE);
+    fm.init(prec, (size_t)nt * FM_SIZE);
+    for (int n = 0; n < nets; ++n) {
+        const Layer* L = &m->emb[(size_t)n * 3];
+        double* v = &ev[(size_t)n * EVEC];
+        for (int k = 0; k < E0; ++k) {
+            v[EV_W1 + k] = L[0].W[k];
+            v[EV_B1 + k] = L[0].b[k];
+            v[EV_WH1 + k] = L[0].wh[k];
+        }
+        for (int k = 0; k < E1; ++k) { v[EV_B2 + k] = L[1].b[k]; v[EV_WH2 + k] = L[1].wh[k]; }
+        for (int k = 0; k < E2; ++k) { v[EV_B3 + k] = L[2].b[k]; v[EV_WH3 + k] = L[2].wh[k]; }
+        const size_t base = (size_t)n * EM_SIZE;
+        for (int k = 0; k < E0; ++k)
+            for (int o = 0; o < E1; ++o) em.set(base + EM_W2T + (size_t)o * K2P + kphys(prec, k), L[1].W[k * E1 + o]);
+        for (int k = 0; k < E1; ++k)
+            for (int o = 0; o < E2; ++o) em.set(base + EM_W3T + (size_t)o * N2P + kphys(prec, k), L[2].W[k * E2 + o]);
+    }
+    for (int t = 0; t < nt; ++t) {
+        const Layer* L = &m->fit[(size_t)t * 4];
+        double* v = &fv[(size_t)t * FVEC];
+        for (int k = 0; k < FW; ++k) {
+            v[FV_B1 + k] = L[0].b[k]; v[FV_WH1 + k] = L[0].wh[k];
+            v[FV_B2 + k] = L[1].b[k]; v[FV_WH2 + k] = L[1].wh[k];
+            v[FV_B3 + k] = L[2].b[k]; v[FV_WH3 + k] = L[2].wh[k];
+            v[FV_W4 + k] = L[3].W[k];
+        }
+        v[FV_B4] = L[3].b[0];
+        v[FV_WH4] = L[3].wh[0];
+        const size_t base = (size_t)t * FM_SIZE;
+        for (int f = 0; f < DD; ++f)
+            for (int o = 0; o < FW; ++o) {
+                const double w = L[0].W[(int64_t)f * FW + o];
+                fm.set(base + FM_W1T + (size_t)o * DD + kphys(prec, f), w);
+                fm.set(base + FM_W1 + (size_t)f * FW + kphys(prec, o), w);
+            }
+        for (int li = 1; li <= 2; ++li) {
+            const int64_t mt = li == 1 ? FM_W2T : FM_W3T, mw = li == 1 ? FM_W2 : FM_W3;
+            for (int i = 0; i < FW; ++i)
+                for (int o = 0; o < FW; ++o) {
+                    const double w = L[li].W[(int64_t)i * FW + o];
+                    fm.set(base + mt + (size_t)o * FW + kphys(prec, i), w);
+                    fm.set(base + mw + (size_t)i * FW + kphys(prec, o), w);
+                }
+        }
+    }
+    int rc;
+    if (f64) {
+        if ((rc = upload(&c->evec, ev.data(), ev.size()))) return rc;
+        if ((rc = upload(&c->fvec, fv.data(), fv.size()))) return rc;
+    } else {
+        std::vector<float> evf(ev.begin(), ev.end()), fvf(fv.begin(), fv.end());
+        if ((rc = upload(&c->evec, evf.data(), evf.size()))) return rc;
+        if ((rc = upload(&c->fvec, fvf.data(), fvf.size()))) return rc;
+    }
+    if ((rc = upload_planes(&c->emat, em))) return rc;
+    if ((rc = upload_planes(&c->fmat, fm))) return rc;
+    c->model_bytes = ev.size() * c->acc_size + fv.size() * c->acc_size +
+                     (f64 ? em.d.size() * 8 + fm.d.size() * 8 : (em.h.size() + em.l.size() + fm.h.size() + fm.l.size()) * 2);
+    if (m->tabulated) {
+        if (f64) {
+            if ((rc = upload(&c->table, m->table.data(), m->table.size()))) return rc;
+        } else {
+            std::vector<float> tf(m->table.begin(), m->table.end());
+            if ((rc = upload(&c->table, tf.data(), tf.size()))) return rc;
+        }
+        c->model_bytes += m->table.size() * c->acc_size;
+    }
+    return DPK_OK;
+}
+
+}  // namespace
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+const char* dpk_last_error(void) { return g_err.c_str(); }
+
+int64_t dpk_model_param_count(const dpk_model_desc* desc)
+{
+    if (!desc || desc->ntypes < 1 || desc->ntypes > DPK_MAX_TYPES) return -1;
+    return count_params(desc);
+}
+
+int dpk_model_create(const dpk_model_desc* desc, const double* params, int64_t nparams, dpk_model** out)
+{
+    if (!desc || !params || !out) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (desc->ntypes < 1 || desc->ntypes > DPK_MAX_TYPES) return fail(DPK_E_INVALID_ARG, "ntypes must be in 1..8");
+    if (desc->emb[0] != E0 || desc->emb[1] != E1 || desc->emb[2] != E2 || desc->axis != AX ||
+        desc->fit[0] != FW || desc->fit[1] != FW || desc->fit[2] != FW)
+        return fail(DPK_E_UNIMPLEMENTED, "kernels are built for emb (25,50,100), axis 16, fit (240,240,240)");
+    if (!(desc->rcut > desc->rcut_smth) || !(desc->rcut_smth > 0.0))
+        return fail(DPK_E_INVALID_ARG, "need 0 < rcut_smth < rcut");
+    int nc = 0;
+    for (int t = 0; t < desc->ntypes; ++t) {
+        if (desc->sel[t] < 0) return fail(DPK_E_INVALID_ARG, "negative sel");
+        nc += desc->sel[t];
+    }
+    if (nc < 1 || nc > 4096) return fail(DPK_E_INVALID_ARG, "sum of sel must be in 1..4096");
+    const int64_t need = count_params(desc);
+    if (nparams != need) return fail(DPK_E_INVALID_ARG, "parameter blob has %lld values, model needs %lld",
+                                     (long long)nparams, (long long)need);
+    dpk_model* m = new dpk_model;
+    m->desc = *desc;
+    m->params.assign(params, params + nparams);
+    m->nets = desc->type_one_side ? desc->ntypes : desc->ntypes * desc->ntypes;
+    m->nc = nc;
+    index_layers(m);
+    *out = m;
+    return DPK_OK;
+}
+
+int dpk_model_tabulate(dpk_model* m, double stride, double x_max)
+{
+    if (!m || !(stride > 0.0) || !(x_max > 0.0)) return fail(DPK_E_INVALID_ARG, "bad table range");
+    const int nint = (int)std::ceil(x_max / stride - 1e-9);
+    if (nint < 1 || nint > 100000) return fail(DPK_E_INVALID_ARG, "table would have %d intervals", nint);
+    const double dx = stride;
+    m->table.assign((size_t)m->nets * nint * E2 * 6, 0.0);
+    std::vector<double> y((size_t)(nint + 1) * E2), y1(y.size()), y2(y.size());
+    for (int net = 0; net < m->nets; ++net) {
+        for (int l = 0; l <= nint; ++l)
+            embed_derivs(m, net, l * dx, &y[(size_t)l * E2], &y1[(size_t)l * E2], &y2[(size_t)l * E2]);
+        for (int l = 0; l < nint; ++l)
+            for (int o = 0; o < E2; ++o) {
+                const double f0 = y[(size_t)l * E2 + o], f1 = y[(size_t)(l + 1) * E2 + o];
+                const double d0 = y1[(size_t)l * E2 + o], d1 = y1[(size_t)(l + 1) * E2 + o];
+                const double s0 = y2[(size_t)l * E2 + o], s1 = y2[(size_t)(l + 1) * E2 + o];
+                const double h = f1 - f0, dx2 = dx * dx, dx3 = dx2 * dx;
+                double* cf = &m->table[(((size_t)net * nint + l) * E2 + o) * 6];
+                cf[0] = (12.0 * h - 6.0 * (d1 + d0) * dx + (s1 - s0) * dx2) / (2.0 * dx3 * dx2);
+                cf[1] = (-30.0 * h + (14.0 * d1 + 16.0 * d0) * dx + (-2.0 * s1 + 3.0 * s0) * dx2) / (2.0 * dx2 * dx2);
+                cf[2] = (20.0 * h - (8.0 * d1 + 12.0 * d0) * dx + (s1 - 3.0 * s0) * dx2) / (2.0 * dx3);
+                cf[3] = 0.5 * s0;
+                cf[4] = d0;
+                cf[5] = f0;
+            }
+    }
+    m->tabulated = true;
+    m->tab_dx = dx;
+    m->tab_nint = nint;
+    return DPK_OK;
+}
+
+void dpk_model_free(dpk_model* m) { delete m; }
+
+int dpk_ctx_create(const dpk_model* m, int device, int precision, size_t hbm_budget_bytes, int strict_sel,
+                   dpk_ctx** out)
+{
+    if (!m || !out) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (precision < DPK_FP64 || precision > DPK_BF16) return fail(DPK_E_INVALID_ARG, "unknown precision %d", precision);
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(DPK_E_INVALID_ARG, "device %d not present (%d devices)", device, ndev);
+    HIPCHK(hipSetDevice(device));
+    dpk_ctx* c = new dpk_ctx;
+    c->model = m;
+    c->device = device;
+    c->precision = precision;
+    c->budget = hbm_budget_bytes;
+    c->strict = strict_sel;
+    c->acc_size = precision == DPK_FP64 ? 8 : 4;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(DPK_E_DEVICE, "hipStreamCreate failed");
+    }
+    int rc = upload_model(c);
+    if (rc) { dpk_ctx_free(c); return rc; }
+    if (c->budget && c->model_bytes > c->budget) {
+        dpk_ctx_free(c);
+        return fail(DPK_E_BUDGET, "model needs %zu device bytes, budget %zu", c->model_bytes, hbm_budget_bytes);
+    }
+    *out = c;
+    return DPK_OK;
+}
+
+void dpk_ctx_free(dpk_ctx* c)
+{
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    hipFree(c->evec); hipFree(c->emat); hipFree(c->fvec); hipFree(c->fmat); hipFree(c->table); hipFree(c->ws);
+    if (c->stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int64_t dpk_ctx_workspace_bytes(const dpk_ctx* c, int64_t natoms)
+{
+    if (!c || natoms < 1) return -1;
+    dpk_ctx tmp = *c;
+    return (int64_t)layout_ws(&tmp, natoms, 256 * 256 * 4, nullptr) + (int64_t)c->model_bytes;
+}
+
+int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const int32_t* d_atype, const double* box,
+                       double* d_energy, double* d_force, double* d_virial, double* d_atom_energy, void* hip_stream)
+{
+    if (!c || !d_coord || !d_atype || !d_energy || !d_force || !d_virial) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    if (natoms < 1 || natoms > (1LL << 30)) return fail(DPK_E_INVALID_ARG, "natoms = %lld", (long long)natoms);
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const dpk_model* m = c->model;
+    const int n = (int)natoms;
+    int rc;
+    GeomParams gp;
+    if (box) {
+        if ((rc = setup_geometry(c, box, nullptr, gp))) return rc;
+    } else {
+        // open boundary: bounding box of the cluster (one wait on the stream)
+        if ((rc = ensure_ws(c, n, 1))) return rc;
+        launch_bbox(n, d_coord, c->bbox, s);
+        double bb[6];
+        HIPCHK(hipMemcpyAsync(bb, c->bbox, sizeof(bb), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if ((rc = setup_geometry(c, nullptr, bb, gp))) return rc;
+    }
+    const int64_t ncell = (int64_t)gp.nb[0] * gp.nb[1] * gp.nb[2];
+    if ((rc = ensure_ws(c, n, ncell))) return rc;
+    const int nt = m->desc.ntypes;
+
+    launch_zero(c->tcount, sizeof(int) * MAXT, s);
+    launch_zero(c->stats, sizeof(DevStats), s);
+    launch_zero(c->cell_count, sizeof(int) * ncell, s);
+    launch_zero(c->F, sizeof(double) * 3 * n, s);
+    launch_types(n, d_atype, nt, c->tcount, c->toff, c->perm, c->inv_perm, c->itype, c->stats, s);
+    launch_cells(n, d_coord, c->perm, gp, c->pos, c->cell_of, c->cell_count, c->cell_start, c->cursor, c->cell_atoms, s);
+    launch_nlist(n, c->pos, c->itype, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cell_atoms, gp, c->nl_j,
+                 c->nl_r, c->nnei, c->stats, s);
+
+    EmbArgs ea;
+    std::memset(&ea, 0, sizeof(ea));
+    ea.natoms = n;
+    ea.ntypes = nt;
+    ea.nc = m->nc;
+    ea.type_one_side = m->desc.type_one_side;
+    for (int t = 0; t < nt; ++t) ea.off[t] = gp.off[t];
+    ea.itype = c->itype;
+    ea.nnei = c->nnei;
+    ea.nl_j = c->nl_j;
+    ea.nl_r = c->nl_r;
+    ea.rs = m->desc.rcut_smth;
+    ea.rc = m->desc.rcut;
+    ea.inv_nc = 1.0 / m->nc;
+    ea.evec = c->evec;
+    ea.emat = c->emat;
+    ea.table = c->table;
+    ea.tab_dx = m->tab_dx;
+    ea.tab_nint = m->tab_nint;
+    ea.T = c->T;
+    ea.dT = c->dT;
+    ea.F = c->F;
+    ea.vir_part = c->vir_part;
+    ea.stats = c->stats;
+    const bool tab = m->tabulated;
+    launch_embed_fwd(c->precision, tab, ea, s);
+
+    FitArgs fa;
+    fa.natoms = n;
+    fa.ntypes = nt;
+    fa.itype = c->itype;
+    fa.toff = c->toff;
+    fa.fvec = c->fvec;
+    fa.fmat = c->fmat;
+    fa.T = c->T;
+    fa.dT = c->dT;
+    fa.Ei = c->Ei;
+    launch_fit(c->precision, fa, s);
+
+    launch_embed_bwd(c->precision, tab, ea, s);
+    const int nvp = (n + embed_atoms_per_block(c->precision) - 1) / embed_atoms_per_block(c->precision);
+    launch_finalize(n, c->Ei, nvp, c->vir_part, d_energy, d_virial, c->perm, c->F, d_force, d_atom_energy, s);
+    HIPCHK(hipGetLastError());
+    c->last_stream = s;
+    c->last_n = n;
+    c->last_nvp = nvp;
+    return DPK_OK;
+}
+
+int dpk_ctx_check(dpk_ctx* c)
+{
+    if (!c) return fail(DPK_E_INVALID_ARG, "NULL context");
+    if (!c->last_n) return DPK_OK;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->last_stream));
+    DevStats st;
+    HIPCHK(hipMemcpy(&st, c->stats, sizeof(st), hipMemcpyDeviceToHost));
+    if (st.err_type) return fail(DPK_E_TYPE_RANGE, "an atom type is outside [0, %d)", c->model->desc.ntypes);
+    if (st.err_overflow)
+        return fail(DPK_E_NBR_OVERFLOW, "%d atoms within r_c of one atom exceed the selection buffer (%d)", st.max_cand,
+                    NL_CAP);
+    if (c->strict && st.nbr_dropped)
+        return fail(DPK_E_NBR_OVERFLOW, "%llu neighbours cut by sel (strict mode)", (unsigned long long)st.nbr_dropped);
+    return DPK_OK;
+}
+
+int dpk_compute(dpk_ctx* c, int64_t natoms, const double* coord, const int32_t* atype, const double* box, double* energy,
+                double* force, double* virial, double* atom_energy)
+{
+    if (!c || !coord || !atype || !energy || !force || !virial) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    if (natoms < 1 || natoms > (1LL << 30)) return fail(DPK_E_INVALID_ARG, "natoms = %lld", (long long)natoms);
+    HIPCHK(hipSetDevice(c->device));
+    // Size the workspace first (geometry from the host copy of the frame), so that the device
+    // entry point below never reallocates the buffers the frame is staged in.
+    GeomParams gp;
+    int rc;
+    if (box) {
+        if ((rc = setup_geometry(c, box, nullptr, gp))) return rc;
+    } else {
+        double bb[6] = {1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+        for (int64_t i = 0; i < natoms; ++i)
+            for (int k = 0; k < 3; ++k) {
+                bb[k] = std::min(bb[k], coord[3 * i + k]);
+                bb[3 + k] = std::max(bb[3 + k], coord[3 * i + k]);
+            }
+        if ((rc = setup_geometry(c, nullptr, bb, gp))) return rc;
+    }
+    if ((rc = ensure_ws(c, natoms, (int64_t)gp.nb[0] * gp.nb[1] * gp.nb[2]))) return rc;
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemcpyAsync(c->h_coord, coord, sizeof(double) * 3 * natoms, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->h_atype, atype, sizeof(int) * natoms, hipMemcpyHostToDevice, s));
+    double* o = c->h_out;
+    rc = dpk_compute_device(c, natoms, c->h_coord, c->h_atype, box, o, o + 10, o + 1, o + 10 + 3 * natoms, s);
+    if (rc) return rc;
+    if ((rc = dpk_ctx_check(c))) return rc;
+    std::vector<double> host(10 + 4 * natoms);
+    HIPCHK(hipMemcpy(host.data(), o, sizeof(double) * host.size(), hipMemcpyDeviceToHost));
+    *energy = host[0];
+    std::memcpy(virial, &host[1], sizeof(double) * 9);
+    std::memcpy(force, &host[10], sizeof(double) * 3 * natoms);
+    if (atom_energy) std::memcpy(atom_energy, &host[10 + 3 * natoms], sizeof(double) * natoms);
+    return DPK_OK;
+}
+
+int dpk_ctx_stats(dpk_ctx* c, dpk_stats* out)
+{
+    if (!c || !out) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    out->workspace_bytes = (int64_t)(c->ws_bytes + c->model_bytes);
+    if (!c->last_n) return DPK_OK;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->last_stream));
+    DevStats st;
+    HIPCHK(hipMemcpy(&st, c->stats, sizeof(st), hipMemcpyDeviceToHost));
+    out->nbr_dropped = (int64_t)st.nbr_dropped;
+    out->table_out_of_range = (int64_t)st.table_oor;
+    out->max_candidates = st.max_cand;
+    return DPK_OK;
+}
+
+int dpk_debug_nlist(dpk_ctx* c, int32_t* nlist)
+{
+    if (!c || !nlist) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    if (!c->last_n) return fail(DPK_E_INVALID_ARG, "no frame computed yet");
+    HIPCHK(hipSetDevice(c->device));
+    const int n = (int)c->last_n, nc = c->model->nc;
+    int* d = nullptr;
+    HIPCHK(hipMalloc(&d, sizeof(int) * (size_t)n * nc));
+    launch_debug_nlist(n, nc, c->perm, c->nl_j, d, c->last_stream);
+    hipError_t e = hipStreamSynchronize(c->last_stream);
+    if (e == hipSuccess) e = hipMemcpy(nlist, d, sizeof(int) * (size_t)n * nc, hipMemcpyDeviceToHost);
+    hipFree(d);
+    if (e != hipSuccess) return fail(DPK_E_DEVICE, "debug nlist: %s", hipGetErrorString(e));
+    return DPK_OK;
+}
+
+int dpk_debug_descriptor(dpk_ctx* c, double* T, double* dT)
+{
+    if (!c || !T || !dT) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    if (!c->last_n) return fail(DPK_E_INVALID_ARG, "no frame computed yet");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->last_stream));
+    const int64_t n = c->last_n, per = E2 * 4;
+    std::vector<int> perm(n);
+    HIPCHK(hipMemcpy(perm.data(), c->perm, sizeof(int) * n, hipMemcpyDeviceToHost));
+    std::vector<char> bt(c->acc_size * n * per), bd(bt.size());
+    HIPCHK(hipMemcpy(bt.data(), c->T, bt.size(), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(bd.data(), c->dT, bd.size(), hipMemcpyDeviceToHost));
+    for (int64_t a = 0; a < n; ++a)
+        for (int64_t k = 0; k < per; ++k) {
+            const int64_t src = a * per + k, dst = (int64_t)perm[a] * per + k;
+            if (c->acc_size == 8) {
+                T[dst] = ((const double*)bt.data())[src];
+                dT[dst] = ((const double*)bd.data())[src];
+            } else {
+                T[dst] = ((const float*)bt.data())[src];
+                dT[dst] = ((const float*)bd.data())[src];
+            }
+        }
+    return DPK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// dpk_internal.h -- shared host/device definitions of libdpk (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpk {
+
+// Network sizes this build's kernels are written for (Sec. IV model sizes: embedding (25,50,100),
+// M_< = 16, fitting (240,240,240,1)).
+constexpr int E0 = 25, E1 = 50, E2 = 100, AX = 16, FW = 240, DD = E2 * AX;
+constexpr int K2P = 32;    // layer-2 input width padded to whole 16-wide K-chunks
+constexpr int N2P = 64;    // layer-2 output (= layer-3 input) width padded
+constexpr int N3P = 112;   // layer-3 output width padded to 7 tiles of 16
+constexpr int EVEC = 3 * K2P + 2 * N2P + 2 * N3P;   // W1, b1, wh1 | b2, wh2 | b3, wh3
+constexpr int FVEC = 7 * FW + 8;                    // b1,wh1,b2,wh2,b3,wh3,w4 | b4, wh4, pad
+constexpr int MAXT = 8;
+constexpr int NL_CAP = 1024;   // candidate buffer of the neighbour-list kernel (per atom)
+
+// Offsets inside one packed embedding vector block.
+constexpr int EV_W1 = 0, EV_B1 = K2P, EV_WH1 = 2 * K2P, EV_B2 = 3 * K2P, EV_WH2 = 3 * K2P + N2P,
+              EV_B3 = 3 * K2P + 2 * N2P, EV_WH3 = 3 * K2P + 2 * N2P + N3P;
+// Offsets inside one packed fitting vector block.
+constexpr int FV_B1 = 0, FV_WH1 = FW, FV_B2 = 2 * FW, FV_WH2 = 3 * FW, FV_B3 = 4 * FW,
+              FV_WH3 = 5 * FW, FV_W4 = 6 * FW, FV_B4 = 7 * FW, FV_WH4 = 7 * FW + 1;
+// Matrices of one fitting net, each [rows][cols] row-major, in this order.
+constexpr int64_t FM_W1T = 0;                          // [240][1600]
+constexpr int64_t FM_W1 = FM_W1T + (int64_t)FW * DD;   // [1600][240]
+constexpr int64_t FM_W2T = FM_W1 + (int64_t)DD * FW;   // [240][240]
+constexpr int64_t FM_W2 = FM_W2T + FW * FW;
+constexpr int64_t FM_W3T = FM_W2 + FW * FW;
+constexpr int64_t FM_W3 = FM_W3T + FW * FW;
+constexpr int64_t FM_SIZE = FM_W3 + FW * FW;
+constexpr int64_t EM_W2T = 0;                          // [64][32]
+constexpr int64_t EM_W3T = N2P * K2P;                  // [112][64]
+constexpr int64_t EM_SIZE = EM_W3T + N3P * N2P;
+
+// Geometry of the frame for neighbour search.
+struct GeomParams {
+    int periodic;
+    int nb[3];          // bins per axis
+    int K[3];           // stencil half-width per axis (bins)
+    double h[9];        // cell rows (periodic)
+    double hinv[9];
+    double origin[3];   // open boundary: lower corner of the bin grid
+    double binw[3];     // open boundary: bin widths
+    double rc2;
+    int ntypes, nc;
+    int sel[MAXT], off[MAXT];
+};
+
+// Device-side error / statistics block of one frame.
+struct DevStats {
+    unsigned long long nbr_dropped;
+    unsigned long long table_oor;
+    int max_cand;
+    int err_type;       // atom type out of range
+    int err_overflow;   // candidate buffer overflow
+    int pad;
+};
+
+// Arguments of the embedding kernels.
+struct EmbArgs {
+    int natoms, ntypes, nc, type_one_side;
+    int off[MAXT];
+    const int* itype;        // [N] type of internal atom
+    const int* nnei;         // [N][ntypes] kept neighbours per type block
+    const int* nl_j;         // [N][nc]
+    const double* nl_r;      // [N][nc][3]
+    double rs, rc, inv_nc;
+    // network (packed per policy) or table
+    const void* evec;        // [nets][EVEC] of acc type
+    const void* emat;        // [planes][nets][EM_SIZE] of weight type
+    const void* table;       // [nets][nint][100][6] of acc type
+    double tab_dx; int tab_nint;
+    void* T;                 // [N][100][4] of acc type (forward output)
+    const void* dT;          // [N][100][4] (backward input)
+    double* F;               // [N][3] internal order (backward output, atomics)
+    double* vir_part;        // [gridDim][9]
+    DevStats* stats;
+};
+
+struct FitArgs {
+    int natoms, ntypes;
+    const int* itype;
+    const int* toff;        // [ntypes+1] internal type offsets (device)
+    const void* fvec;       // [ntypes][FVEC] acc type
+    const void* fmat;       // [planes][ntypes][FM_SIZE] weight type
+    const void* T;          // [N][100][4]
+    void* dT;               // [N][100][4]
+    double* Ei;             // [N]
+};
+
+}  // namespace dpk

@@ -1,0 +1,28 @@
+// dpk_launch.h -- host-side launchers of the libdpk kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "dpk_internal.h"
+
+namespace dpk {
+
+void launch_zero(void* p, size_t bytes, hipStream_t s);
+void launch_types(int n, const int* atype, int ntypes, int* tcount, int* toff, int* perm, int* inv_perm,
+                  int* itype, DevStats* st, hipStream_t s);
+void launch_bbox(int n, const double* coord, double* out, hipStream_t s);
+void launch_cells(int n, const double* coord, const int* perm, const GeomParams& gp, double* pos, int* cell_of,
+                  int* cell_count, int* cell_start, int* cursor, int* cell_atoms, hipStream_t s);
+void launch_nlist(int n, const double* pos, const int* itype, const int* perm, const int* inv_perm,
+                  const int* cell_of, const int* cell_start, const int* cell_atoms, const GeomParams& gp, int* nl_j,
+                  double* nl_r, int* nnei, DevStats* st, hipStream_t s);
+void launch_finalize(int n, const double* ei, int nvp, const double* vir_part, double* energy, double* virial,
+                     const int* perm, const double* f_int, double* force, double* atom_energy, hipStream_t s);
+void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s);
+
+// precision: 0 = FP64, 1 = split-BF16 (three products), 2 = BF16 (one product)
+int embed_atoms_per_block(int precision);
+int fit_atoms_per_block(int precision);
+void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s);
+void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s);
+void launch_fit(int precision, const FitArgs& a, hipStream_t s);
+
+}  // namespace dpk

@@ -1,0 +1,849 @@
+// kernels_nn.hip -- embedding net with the descriptor contraction, fitting net, and the
+// hand-written adjoint (prod_force / prod_virial) of the se_e2_a Deep Potential.
+//
+// Paper: Sec. II.A.1 (environment rows, switching function eq. switch, embedding eq. G2,
+// D = N_c^-2 G^T R R^T G_<), Sec. II.A.2 (E_i = F_0(D), F = -dE/dr, virial), Sec. II.A.6 (layers
+// eq. NN; tabulated embedding eq. compress; operator merging: G never leaves registers; precise
+// neighbour indexing: only kept neighbours are evaluated).
+//
+// Matrix-core mapping (16x16 output tiles, one 64-lane wave):
+//   * An MFMA computes D[i][j] += sum_k A[i][k] B[k][j] over a 16-wide K-chunk. Lane l supplies row
+//     i = l%16 of A and column j = l%16 of B, with the lane group g = l/16 holding the K values
+//     kidx(c, g, v), v = 0..3; the output holds D[orow(g, r)][l%16] in register r. The two maps
+//     depend on the instruction (see the policies); with them, the output of one tile is the
+//     B operand of the next K-chunk without any data movement.
+//   * Embedding, per chunk of 16 neighbours of one centre atom: layer 1 (1 -> 25) on the VALU
+//     straight into B-operand layout; layer 2 (25 -> 50) transposed (W^T as A, activations as B);
+//     forward pass: layer 3 (50 -> 100) untransposed (activations as A), which puts 4 neighbours
+//     in each lane's registers for the contraction T += G^T R done on the VALU; backward pass:
+//     layer 3 transposed, which keeps one neighbour per lane column so the reductions over the
+//     100 channels (dE/dR_j and dE/ds_j) are lane-local plus two cross-group shuffles.
+//   * The backward pass re-evaluates the net with its forward-mode derivative d/ds (the input is
+//     a scalar), rather than storing G: G would cost 400 B per neighbour in HBM.
+//   * Fitting: per block 16 or 32 atoms of one type; every layer transposed (W^T as A), the
+//     descriptor D = T T_<^T is formed on the fly in B-operand layout from T in LDS; the input
+//     gradient uses the untransposed weights (W as A).
+#include <hip/hip_runtime.h>
+#include "dpk_internal.h"
+#include "dpk_launch.h"
+
+namespace dpk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------------------------
+// Precision policies
+// ---------------------------------------------------------------------------------------------
+
+// FP64: v_mfma_f64_16x16x4f64, four instructions per 16-wide K-chunk. Output register r of lane
+// group g holds row g + 4r. Weight matrices are stored with each 16-wide K-chunk permuted so that
+// the four K values a lane needs (g, g+4, g+8, g+12) are contiguous.
+struct PF64 {
+    typedef double acc;
+    typedef double wt;
+    typedef d4 accv;
+    static constexpr int NPL = 1;
+    struct frag { d4 v; };
+    __device__ static int orow(int g, int r) { return g + 4 * r; }
+    __device__ static int kidx(int c, int g, int v) { return 16 * c + g + 4 * v; }
+    __device__ static frag make(acc x0, acc x1, acc x2, acc x3) { frag f; f.v = d4{x0, x1, x2, x3}; return f; }
+    __device__ static frag load(const wt* p, int64_t) {
+        frag f;
+        f.v = *reinterpret_cast<const d4*>(p);
+        return f;
+    }
+    __device__ static void mma(accv& d, const frag& a, const frag& b) {
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[0], b.v[0], d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[1], b.v[1], d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[2], b.v[2], d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[3], b.v[3], d, 0, 0, 0);
+    }
+    __device__ static acc act(acc x) { return tanh(x); }
+};
+
+// FP32 hyperbolic tangent: 1 - 2 / (exp(2x) + 1), with exp(2x) = 2^(2x log2 e) on the hardware
+// exp2 and the hardware reciprocal. Saturates to +-1 without overflow trouble (2^inf = inf,
+// 1/inf = 0). Absolute error about 1e-7.
+__device__ __forceinline__ float tanh_fast(float x)
+{
+    float e = __builtin_amdgcn_exp2f(x * 2.885390081777927f);
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo)
+{
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+
+// Split BF16: each FP32 operand is hi + lo with both parts BF16; the product is formed as
+// lo*hi + hi*lo + hi*hi with FP32 accumulation (v_mfma_f32_16x16x16_bf16), about 16 significant
+// bits per operand. Output register r of lane group g holds row 4g + r.
+struct PMIX {
+    typedef float acc;
+    typedef __bf16 wt;
+    typedef f4 accv;
+    static constexpr int NPL = 2;
+    struct frag { bf4 h, l; };
+    __device__ static int orow(int g, int r) { return 4 * g + r; }
+    __device__ static int kidx(int c, int g, int v) { return 16 * c + 4 * g + v; }
+    __device__ static frag make(acc x0, acc x1, acc x2, acc x3) {
+        frag f;
+        __bf16 h, l;
+        split_bf16(x0, h, l); f.h[0] = h; f.l[0] = l;
+        split_bf16(x1, h, l); f.h[1] = h; f.l[1] = l;
+        split_bf16(x2, h, l); f.h[2] = h; f.l[2] = l;
+        split_bf16(x3, h, l); f.h[3] = h; f.l[3] = l;
+        return f;
+    }
+    __device__ static frag load(const wt* p, int64_t plane) {
+        frag f;
+        f.h = *reinterpret_cast<const bf4*>(p);
+        f.l = *reinterpret_cast<const bf4*>(p + plane);
+        return f;
+    }
+    __device__ static void mma(accv& d, const frag& a, const frag& b) {
+        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.l, b.h, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h, b.l, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h, b.h, d, 0, 0, 0);
+    }
+    __device__ static acc act(acc x) { return tanh_fast(x); }
+};
+
+// Plain BF16 operands, one product (fast, about 1e-2 relative force error).
+struct PBF16 {
+    typedef float acc;
+    typedef __bf16 wt;
+    typedef f4 accv;
+    static constexpr int NPL = 1;
+    struct frag { bf4 h; };
+    __device__ static int orow(int g, int r) { return 4 * g + r; }
+    __device__ static int kidx(int c, int g, int v) { return 16 * c + 4 * g + v; }
+    __device__ static frag make(acc x0, acc x1, acc x2, acc x3) {
+        frag f;
+        f.h[0] = (__bf16)x0; f.h[1] = (__bf16)x1; f.h[2] = (__bf16)x2; f.h[3] = (__bf16)x3;
+        return f;
+    }
+    __device__ static frag load(const wt* p, int64_t) {
+        frag f;
+        f.h = *reinterpret_cast<const bf4*>(p);
+        return f;
+    }
+    __device__ static void mma(accv& d, const frag& a, const frag& b) {
+        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h, b.h, d, 0, 0, 0);
+    }
+    __device__ static acc act(acc x) { return tanh_fast(x); }
+};
+
+template <class V> __device__ __forceinline__ void zero4(V& v) { v[0] = 0; v[1] = 0; v[2] = 0; v[3] = 0; }
+
+// Wave-scope ordering of LDS traffic between lanes of one wave.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Switching function of Sec. II.A.1 (eq. switch) and its derivative, FP64.
+__device__ __forceinline__ void switch_fn(double r, double rs, double rc, double& s, double& ds)
+{
+    if (r < rs) {
+        s = 1.0 / r;
+        ds = -1.0 / (r * r);
+    } else if (r < rc) {
+        double x = (r - rs) / (rc - rs);
+        double x2 = x * x;
+        double u = x2 * x * (x * (15.0 - 6.0 * x) - 10.0) + 1.0;
+        double du = -30.0 * x2 * (x - 1.0) * (x - 1.0);
+        double ir = 1.0 / r;
+        s = u * ir;
+        ds = du * ir / (rc - rs) - u * ir * ir;
+    } else {
+        s = 0.0;
+        ds = 0.0;
+    }
+}
+
+// Row strides of the weight tiles staged in LDS (elements; multiples of 4, padded against bank
+// conflicts between the 16 rows a wave reads at once).
+constexpr int LD2 = K2P + 4;
+constexpr int LD3 = N2P + 4;
+
+// Stage one embedding net into LDS: vector block and the W2^T / W3^T planes.
+template <class P, bool W3LDS>
+__device__ void stage_net(const EmbArgs& A, int net, typename P::acc* s_vec, typename P::wt* s_w2,
+                          typename P::wt* s_w3)
+{
+    typedef typename P::acc acc;
+    typedef typename P::wt wt;
+    const acc* ev = reinterpret_cast<const acc*>(A.evec) + (size_t)net * EVEC;
+    for (int i = threadIdx.x; i < EVEC; i += blockDim.x) s_vec[i] = ev[i];
+    const int nets = A.type_one_side ? A.ntypes : A.ntypes * A.ntypes;
+    const wt* em = reinterpret_cast<const wt*>(A.emat);
+    for (int pl = 0; pl < P::NPL; ++pl) {
+        const wt* src = em + ((size_t)pl * nets + net) * EM_SIZE;
+        for (int i = threadIdx.x; i < N2P * K2P; i += blockDim.x)
+            s_w2[pl * N2P * LD2 + (i / K2P) * LD2 + (i % K2P)] = src[EM_W2T + i];
+        if (W3LDS)
+            for (int i = threadIdx.x; i < N3P * N2P; i += blockDim.x)
+                s_w3[pl * N3P * LD3 + (i / N2P) * LD3 + (i % N2P)] = src[EM_W3T + i];
+    }
+}
+
+template <class P> struct EmbCfg {
+    // FP64 keeps W3^T in global memory (L1/L2) to leave LDS for the activation buffers.
+    static constexpr bool W3LDS = sizeof(typename P::acc) == 4;
+};
+
+// ---------------------------------------------------------------------------------------------
+// Forward: T_a = N_c^-1 sum_j G_j^T R_j for every atom a (G evaluated and contracted in
+// registers, never stored).
+// ---------------------------------------------------------------------------------------------
+template <class P, int APB, bool TAB>
+__global__ void __launch_bounds__(256) k_embed_fwd(EmbArgs A)
+{
+    typedef typename P::acc acc;
+    typedef typename P::wt wt;
+    typedef typename P::accv accv;
+    typedef typename P::frag frag;
+    constexpr bool W3LDS = EmbCfg<P>::W3LDS;
+    __shared__ acc s_vec[EVEC];
+    __shared__ __attribute__((aligned(32))) wt s_w2[P::NPL * N2P * LD2];
+    __shared__ __attribute__((aligned(32))) wt s_w3[W3LDS ? P::NPL * N3P * LD3 : 1];
+    __shared__ acc s_z1[4][16][E0 + 1];
+    __shared__ acc s_z2[4][16][E1 + 2];
+    __shared__ acc s_R[4][16][4];
+    __shared__ double s_x[4][16];
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int a0 = blockIdx.x * APB;
+    const int a1 = min(a0 + APB, A.natoms);
+    if (a0 >= a1) return;
+    const int t_lo = A.itype[a0], t_hi = A.itype[a1 - 1];
+    const int nets = A.type_one_side ? A.ntypes : A.ntypes * A.ntypes;
+    const wt* gw3 = reinterpret_cast<const wt*>(A.emat);
+    acc* Tout = reinterpret_cast<acc*>(A.T);
+
+    for (int ti = t_lo; ti <= t_hi; ++ti) {
+        for (int tj = 0; tj < A.ntypes; ++tj) {
+            const int net = A.type_one_side ? tj : ti * A.ntypes + tj;
+            __syncthreads();
+            if (!TAB) stage_net<P, W3LDS>(A, net, s_vec, s_w2, s_w3);
+            __syncthreads();
+            const wt* w3base = W3LDS ? s_w3 : gw3 + (size_t)net * EM_SIZE + EM_W3T;
+            const int w3ld = W3LDS ? LD3 : N2P;
+            const int64_t w3pl = W3LDS ? (int64_t)N3P * LD3 : (int64_t)nets * EM_SIZE;
+            const acc* tab = reinterpret_cast<const acc*>(A.table) + (size_t)net * A.tab_nint * E2 * 6;
+
+            for (int a = a0 + wave; a < a1; a += 4) {
+                if (A.itype[a] != ti) continue;
+                acc Tacc[7][4];
+                for (int i = 0; i < 7; ++i) zero4(Tacc[i]);
+                const int np = A.nnei[(size_t)a * A.ntypes + tj];
+                const size_t slot0 = (size_t)a * A.nc + A.off[tj];
+                for (int c0 = 0; c0 < np; c0 += 16) {
+                    const int p = c16;
+                    const bool valid = c0 + p < np;
+                    double s = 0.0, R[4] = {0.0, 0.0, 0.0, 0.0};
+                    if (valid) {
+                        const double* v = A.nl_r + 3 * (slot0 + c0 + p);
+                        double x = v[0], y = v[1], z = v[2];
+                        double r = sqrt(x * x + y * y + z * z);
+                        double ds;
+                        switch_fn(r, A.rs, A.rc, s, ds);
+                        double sr = s / r;
+                        R[0] = s; R[1] = sr * x; R[2] = sr * y; R[3] = sr * z;
+                    }
+                    wave_sync();
+                    if (g == 0) {
+                        for (int k = 0; k < 4; ++k) s_R[wave][p][k] = (acc)R[k];
+                        s_x[wave][p] = s;
+                    }
+                    if (TAB) {
+                        wave_sync();
+                        for (int tm = 0; tm < 7; ++tm) {
+                            const int m = 16 * tm + c16;
+                            if (m >= E2) continue;
+                            for (int r = 0; r < 4; ++r) {
+                                const int q = P::orow(g, r);
+                                double xs = s_x[wave][q];
+                                int li = (int)floor(xs / A.tab_dx);
+                                li = li < 0 ? 0 : (li >= A.tab_nint ? A.tab_nint - 1 : li);
+                                acc t = (acc)(xs - li * A.tab_dx);
+                                const acc* cf = tab + ((size_t)li * E2 + m) * 6;
+                                acc G = ((((cf[0] * t + cf[1]) * t + cf[2]) * t + cf[3]) * t + cf[4]) * t + cf[5];
+                                for (int k = 0; k < 4; ++k) Tacc[tm][k] += G * s_R[wave][q][k];
+                            }
+                        }
+                        if (g == 0 && valid && (s < 0.0 || s > A.tab_nint * A.tab_dx))
+                            atomicAdd(&A.stats->table_oor, 1ull);
+                        continue;
+                    }
+                    // layer 1 (1 -> 25) straight into the B operand of layer 2
+                    frag B1[2];
+                    for (int c = 0; c < 2; ++c) {
+                        acc z[4];
+                        for (int v = 0; v < 4; ++v) {
+                            const int k = P::kidx(c, g, v);
+                            z[v] = 0;
+                            if (k < E0) {
+                                z[v] = s_vec[EV_WH1 + k] * P::act((acc)s * s_vec[EV_W1 + k] + s_vec[EV_B1 + k]);
+                                s_z1[wave][p][k] = z[v];
+                            }
+                        }
+                        B1[c] = P::make(z[0], z[1], z[2], z[3]);
+                    }
+                    // layer 2 (25 -> 50), transposed: pre2^T = W2^T z1^T
+                    accv acc2[4];
+                    for (int t = 0; t < 4; ++t) {
+                        zero4(acc2[t]);
+                        for (int c = 0; c < 2; ++c)
+                            P::mma(acc2[t], P::load(&s_w2[(16 * t + c16) * LD2 + 16 * c + 4 * g], N2P * LD2), B1[c]);
+                    }
+                    wave_sync();
+                    frag A3[4];
+                    for (int t = 0; t < 4; ++t) {
+                        acc z[4];
+                        for (int r = 0; r < 4; ++r) {
+                            const int n = 16 * t + P::orow(g, r);
+                            z[r] = 0;
+                            if (n < E1) {
+                                z[r] = s_vec[EV_WH2 + n] * P::act(acc2[t][r] + s_vec[EV_B2 + n]) + s_z1[wave][p][n % E0];
+                                s_z2[wave][p][n] = z[r];
+                            }
+                        }
+                        A3[t] = P::make(z[0], z[1], z[2], z[3]);
+                    }
+                    // layer 3 (50 -> 100), untransposed: pre3 = z2 W3
+                    accv acc3[7];
+                    for (int tm = 0; tm < 7; ++tm) {
+                        zero4(acc3[tm]);
+                        for (int c = 0; c < 4; ++c)
+                            P::mma(acc3[tm], A3[c], P::load(&w3base[(16 * tm + c16) * w3ld + 16 * c + 4 * g], w3pl));
+                    }
+                    wave_sync();
+                    // G = w_hat tanh(pre3 + b) + {z2, z2}; contraction T += G^T R
+                    for (int tm = 0; tm < 7; ++tm) {
+                        const int m = 16 * tm + c16;
+                        if (m >= E2) continue;
+                        const acc wh = s_vec[EV_WH3 + m], bb = s_vec[EV_B3 + m];
+                        for (int r = 0; r < 4; ++r) {
+                            const int q = P::orow(g, r);
+                            acc G = wh * P::act(acc3[tm][r] + bb) + s_z2[wave][q][m % E1];
+                            for (int k = 0; k < 4; ++k) Tacc[tm][k] += G * s_R[wave][q][k];
+                        }
+                    }
+                }
+                // sum the four lane groups (they hold different neighbours) and store T
+                for (int tm = 0; tm < 7; ++tm)
+                    for (int k = 0; k < 4; ++k) {
+                        acc v = Tacc[tm][k];
+                        v += __shfl_xor(v, 16);
+                        v += __shfl_xor(v, 32);
+                        Tacc[tm][k] = v;
+                    }
+                if (g == 0) {
+                    for (int tm = 0; tm < 7; ++tm) {
+                        const int m = 16 * tm + c16;
+                        if (m >= E2) continue;
+                        acc* dst = Tout + ((size_t)a * E2 + m) * 4;
+                        for (int k = 0; k < 4; ++k) {
+                            acc v = Tacc[tm][k] * (acc)A.inv_nc;
+                            dst[k] = (tj == 0) ? v : dst[k] + v;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Backward (input gradient only): re-evaluate G_j and dG_j/ds, then
+//   dE/dR_j = N_c^-1 G_j dT,  dE/ds_j|_G = N_c^-1 sum_m dG_jm/ds (dT R_j)_m,
+//   g_ij = dE/dr_ij = [(dR_0 + dE/ds) s' + q (s' - s/r)] r^ + (s/r) dR_{1:3},  q = dR_{1:3} . r^,
+//   F_i += g_ij, F_j -= g_ij (FP64 atomics), Xi_ab -= g_ij,a r_ij,b (FP64, per-block partials).
+// ---------------------------------------------------------------------------------------------
+template <class P, int APB, bool TAB>
+__global__ void __launch_bounds__(256) k_embed_bwd(EmbArgs A)
+{
+    typedef typename P::acc acc;
+    typedef typename P::wt wt;
+    typedef typename P::accv accv;
+    typedef typename P::frag frag;
+    constexpr bool W3LDS = EmbCfg<P>::W3LDS;
+    __shared__ acc s_vec[EVEC];
+    __shared__ __attribute__((aligned(32))) wt s_w2[P::NPL * N2P * LD2];
+    __shared__ __attribute__((aligned(32))) wt s_w3[W3LDS ? P::NPL * N3P * LD3 : 1];
+    __shared__ acc s_z1[4][16][E0 + 1];
+    __shared__ acc s_z1d[4][16][E0 + 1];
+    __shared__ acc s_z2[4][16][E1 + 2];
+    __shared__ acc s_z2d[4][16][E1 + 2];
+    __shared__ acc s_dT[4][E2][4];
+    __shared__ double s_vir[4][9];
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int a0 = blockIdx.x * APB;
+    const int a1 = min(a0 + APB, A.natoms);
+    double vir[9];
+    for (int k = 0; k < 9; ++k) vir[k] = 0.0;
+    const int nets = A.type_one_side ? A.ntypes : A.ntypes * A.ntypes;
+    const wt* gw3 = reinterpret_cast<const wt*>(A.emat);
+    const acc* dTin = reinterpret_cast<const acc*>(A.dT);
+    const int t_lo = a0 < a1 ? A.itype[a0] : 0, t_hi = a0 < a1 ? A.itype[a1 - 1] : -1;
+
+    for (int ti = t_lo; ti <= t_hi; ++ti) {
+        for (int tj = 0; tj < A.ntypes; ++tj) {
+            const int net = A.type_one_side ? tj : ti * A.ntypes + tj;
+            __syncthreads();
+            if (!TAB) stage_net<P, W3LDS>(A, net, s_vec, s_w2, s_w3);
+            __syncthreads();
+            const wt* w3base = W3LDS ? s_w3 : gw3 + (size_t)net * EM_SIZE + EM_W3T;
+            const int w3ld = W3LDS ? LD3 : N2P;
+            const int64_t w3pl = W3LDS ? (int64_t)N3P * LD3 : (int64_t)nets * EM_SIZE;
+            const acc* tab = reinterpret_cast<const acc*>(A.table) + (size_t)net * A.tab_nint * E2 * 6;
+
+            for (int a = a0 + wave; a < a1; a += 4) {
+                if (A.itype[a] != ti) continue;
+                const int np = A.nnei[(size_t)a * A.ntypes + tj];
+                if (np == 0) continue;
+                wave_sync();
+                for (int i = lane; i < E2 * 4; i += 64) s_dT[wave][i >> 2][i & 3] = dTin[(size_t)a * E2 * 4 + i];
+                wave_sync();
+                const size_t slot0 = (size_t)a * A.nc + A.off[tj];
+                double Fi[3] = {0.0, 0.0, 0.0};
+                for (int c0 = 0; c0 < np; c0 += 16) {
+                    const int p = c16;
+                    const bool valid = c0 + p < np;
+                    double x = 0.0, y = 0.0, z = 0.0, r = 1.0, s = 0.0, ds = 0.0;
+                    if (valid) {
+                        const double* v = A.nl_r + 3 * (slot0 + c0 + p);
+                        x = v[0]; y = v[1]; z = v[2];
+                        r = sqrt(x * x + y * y + z * z);
+                        switch_fn(r, A.rs, A.rc, s, ds);
+                    }
+                    const double ir = 1.0 / r;
+                    const double ux = x * ir, uy = y * ir, uz = z * ir, sr = s * ir;
+                    const acc Ra[4] = {(acc)s, (acc)(sr * x), (acc)(sr * y), (acc)(sr * z)};
+                    acc dR[4] = {0, 0, 0, 0}, H[4] = {0, 0, 0, 0};
+                    if (TAB) {
+                        int li = (int)floor(s / A.tab_dx);
+                        li = li < 0 ? 0 : (li >= A.tab_nint ? A.tab_nint - 1 : li);
+                        const acc t = (acc)(s - li * A.tab_dx);
+                        for (int tm = 0; tm < 7; ++tm)
+                            for (int rr = 0; rr < 4; ++rr) {
+                                const int m = 16 * tm + P::orow(g, rr);
+                                if (m >= E2) continue;
+                                const acc* cf = tab + ((size_t)li * E2 + m) * 6;
+                                acc G = ((((cf[0] * t + cf[1]) * t + cf[2]) * t + cf[3]) * t + cf[4]) * t + cf[5];
+                                acc Gd = (((5 * cf[0] * t + 4 * cf[1]) * t + 3 * cf[2]) * t + 2 * cf[3]) * t + cf[4];
+                                for (int k = 0; k < 4; ++k) {
+                                    acc dt = s_dT[wave][m][k];
+                                    dR[k] += G * dt;
+                                    H[k] += Gd * dt;
+                                }
+                            }
+                    } else {
+                        wave_sync();
+                        // layer 1 and its derivative d/ds
+                        frag B1[2], B1d[2];
+                        for (int c = 0; c < 2; ++c) {
+                            acc zz[4], zd[4];
+                            for (int v = 0; v < 4; ++v) {
+                                const int k = P::kidx(c, g, v);
+                                zz[v] = 0;
+                                zd[v] = 0;
+                                if (k < E0) {
+                                    const acc w1 = s_vec[EV_W1 + k], wh = s_vec[EV_WH1 + k];
+                                    const acc t1 = P::act((acc)s * w1 + s_vec[EV_B1 + k]);
+                                    zz[v] = wh * t1;
+                                    zd[v] = wh * (1 - t1 * t1) * w1;
+                                    s_z1[wave][p][k] = zz[v];
+                                    s_z1d[wave][p][k] = zd[v];
+                                }
+                            }
+                            B1[c] = P::make(zz[0], zz[1], zz[2], zz[3]);
+                            B1d[c] = P::make(zd[0], zd[1], zd[2], zd[3]);
+                        }
+                        accv acc2[4], acc2d[4];
+                        for (int t = 0; t < 4; ++t) {
+                            zero4(acc2[t]);
+                            zero4(acc2d[t]);
+                            for (int c = 0; c < 2; ++c) {
+                                frag W = P::load(&s_w2[(16 * t + c16) * LD2 + 16 * c + 4 * g], N2P * LD2);
+                                P::mma(acc2[t], W, B1[c]);
+                                P::mma(acc2d[t], W, B1d[c]);
+                            }
+                        }
+                        wave_sync();
+                        frag B3[4], B3d[4];
+                        for (int t = 0; t < 4; ++t) {
+                            acc zz[4], zd[4];
+                            for (int rr = 0; rr < 4; ++rr) {
+                                const int n = 16 * t + P::orow(g, rr);
+                                zz[rr] = 0;
+                                zd[rr] = 0;
+                                if (n < E1) {
+                                    const acc t2 = P::act(acc2[t][rr] + s_vec[EV_B2 + n]);
+                                    const acc wh = s_vec[EV_WH2 + n];
+                                    zz[rr] = wh * t2 + s_z1[wave][p][n % E0];
+                                    zd[rr] = wh * (1 - t2 * t2) * acc2d[t][rr] + s_z1d[wave][p][n % E0];
+                                    s_z2[wave][p][n] = zz[rr];
+                                    s_z2d[wave][p][n] = zd[rr];
+                                }
+                            }
+                            B3[t] = P::make(zz[0], zz[1], zz[2], zz[3]);
+                            B3d[t] = P::make(zd[0], zd[1], zd[2], zd[3]);
+                        }
+                        // layer 3 transposed: one neighbour per lane column
+                        accv acc3[7], acc3d[7];
+                        for (int tm = 0; tm < 7; ++tm) {
+                            zero4(acc3[tm]);
+                            zero4(acc3d[tm]);
+                            for (int c = 0; c < 4; ++c) {
+                                frag W = P::load(&w3base[(16 * tm + c16) * w3ld + 16 * c + 4 * g], w3pl);
+                                P::mma(acc3[tm], W, B3[c]);
+                                P::mma(acc3d[tm], W, B3d[c]);
+                            }
+                        }
+                        wave_sync();
+                        for (int tm = 0; tm < 7; ++tm)
+                            for (int rr = 0; rr < 4; ++rr) {
+                                const int m = 16 * tm + P::orow(g, rr);
+                                if (m >= E2) continue;
+                                const acc t3 = P::act(acc3[tm][rr] + s_vec[EV_B3 + m]);
+                                const acc wh = s_vec[EV_WH3 + m];
+                                const acc G = wh * t3 + s_z2[wave][p][m % E1];
+                                const acc Gd = wh * (1 - t3 * t3) * acc3d[tm][rr] + s_z2d[wave][p][m % E1];
+                                for (int k = 0; k < 4; ++k) {
+                                    const acc dt = s_dT[wave][m][k];
+                                    dR[k] += G * dt;
+                                    H[k] += Gd * dt;
+                                }
+                            }
+                    }
+                    for (int k = 0; k < 4; ++k) {
+                        dR[k] += __shfl_xor(dR[k], 16);
+                        dR[k] += __shfl_xor(dR[k], 32);
+                        H[k] += __shfl_xor(H[k], 16);
+                        H[k] += __shfl_xor(H[k], 32);
+                    }
+                    if (valid && g == 0) {
+                        const double inc = A.inv_nc;
+                        const double d0 = inc * (double)dR[0], d1 = inc * (double)dR[1];
+                        const double d2 = inc * (double)dR[2], d3 = inc * (double)dR[3];
+                        const double dEds = inc * ((double)H[0] * (double)Ra[0] + (double)H[1] * (double)Ra[1] +
+                                                   (double)H[2] * (double)Ra[2] + (double)H[3] * (double)Ra[3]);
+                        const double q = d1 * ux + d2 * uy + d3 * uz;
+                        const double rad = (d0 + dEds) * ds + q * (ds - sr);
+                        const double gx = rad * ux + sr * d1, gy = rad * uy + sr * d2, gz = rad * uz + sr * d3;
+                        const int j = A.nl_j[slot0 + c0 + p];
+                        unsafeAtomicAdd(&A.F[3 * (size_t)j], -gx);
+                        unsafeAtomicAdd(&A.F[3 * (size_t)j + 1], -gy);
+                        unsafeAtomicAdd(&A.F[3 * (size_t)j + 2], -gz);
+                        Fi[0] += gx; Fi[1] += gy; Fi[2] += gz;
+                        vir[0] -= gx * x; vir[1] -= gx * y; vir[2] -= gx * z;
+                        vir[3] -= gy * x; vir[4] -= gy * y; vir[5] -= gy * z;
+                        vir[6] -= gz * x; vir[7] -= gz * y; vir[8] -= gz * z;
+                    }
+                }
+                for (int k = 0; k < 3; ++k) {
+                    double v = Fi[k];
+                    v += __shfl_xor(v, 1);
+                    v += __shfl_xor(v, 2);
+                    v += __shfl_xor(v, 4);
+                    v += __shfl_xor(v, 8);
+                    Fi[k] = v;
+                }
+                if (lane == 0)
+                    for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&A.F[3 * (size_t)a + k], Fi[k]);
+            }
+        }
+    }
+    for (int k = 0; k < 9; ++k) {
+        double v = vir[k];
+        for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
+        vir[k] = v;
+    }
+    if (lane == 0)
+        for (int k = 0; k < 9; ++k) s_vir[wave][k] = vir[k];
+    __syncthreads();
+    if (threadIdx.x < 9)
+        A.vir_part[9 * (size_t)blockIdx.x + threadIdx.x] =
+            s_vir[0][threadIdx.x] + s_vir[1][threadIdx.x] + s_vir[2][threadIdx.x] + s_vir[3][threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fitting net F_0 (Sec. II.A.2, eq. fitting_energy) over 16*NSUB atoms of one type:
+// forward E_i and the input gradient dE_i/dT through D = T T_<^T.
+// ---------------------------------------------------------------------------------------------
+template <class P, int NSUB>
+__global__ void __launch_bounds__(256) k_fit(FitArgs A)
+{
+    typedef typename P::acc acc;
+    typedef typename P::wt wt;
+    typedef typename P::accv accv;
+    typedef typename P::frag frag;
+    constexpr int AF = 16 * NSUB;
+    constexpr int LDH = FW + 4;
+    __shared__ __attribute__((aligned(32))) acc s_T[AF * E2 * 4];
+    __shared__ __attribute__((aligned(32))) acc s_h[AF * LDH];
+    __shared__ acc s_e[4][AF];
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int a0 = blockIdx.x * AF;
+    const int a1 = min(a0 + AF, A.natoms);
+    if (a0 >= a1) return;
+    const int t_lo = A.itype[a0], t_hi = A.itype[a1 - 1];
+    const acc* Tin = reinterpret_cast<const acc*>(A.T);
+    acc* dTout = reinterpret_cast<acc*>(A.dT);
+    const int ntile = (wave < 3) ? 4 : 3;   // output tiles t = wave + 4 i of the 15 (240 / 16)
+
+    for (int ti = t_lo; ti <= t_hi; ++ti) {
+        const acc* fv = reinterpret_cast<const acc*>(A.fvec) + (size_t)ti * FVEC;
+        const wt* fm = reinterpret_cast<const wt*>(A.fmat) + (size_t)ti * FM_SIZE;
+        const int64_t plane = (int64_t)A.ntypes * FM_SIZE;
+        __syncthreads();
+        for (int i = threadIdx.x; i < AF * E2 * 4; i += 256) {
+            const int at = a0 + i / (E2 * 4);
+            s_T[i] = at < A.natoms ? Tin[(size_t)a0 * E2 * 4 + i] : (acc)0;
+        }
+        __syncthreads();
+        // T rows n < 16 of this lane's atoms, at the K positions this lane supplies
+        acc Tn[NSUB][4][4];
+        for (int sb = 0; sb < NSUB; ++sb)
+            for (int v = 0; v < 4; ++v)
+                for (int k = 0; k < 4; ++k) Tn[sb][v][k] = s_T[((c16 + 16 * sb) * E2 + P::kidx(0, g, v)) * 4 + k];
+
+        acc act1[NSUB][4][4], act2[NSUB][4][4], act3[NSUB][4][4], hcur[NSUB][4][4];
+        accv accs[NSUB][4];
+        // ---- layer 1: 1600 -> 240, input d = vec(T T_<^T) formed per K-chunk (m = c)
+        for (int sb = 0; sb < NSUB; ++sb)
+            for (int i = 0; i < 4; ++i) zero4(accs[sb][i]);
+        for (int c = 0; c < E2; ++c) {
+            frag B[NSUB];
+            for (int sb = 0; sb < NSUB; ++sb) {
+                const acc* Tm = &s_T[((c16 + 16 * sb) * E2 + c) * 4];
+                acc d[4];
+                for (int v = 0; v < 4; ++v)
+                    d[v] = Tm[0] * Tn[sb][v][0] + Tm[1] * Tn[sb][v][1] + Tm[2] * Tn[sb][v][2] + Tm[3] * Tn[sb][v][3];
+                B[sb] = P::make(d[0], d[1], d[2], d[3]);
+            }
+            for (int i = 0; i < ntile; ++i) {
+                const int t = wave + 4 * i;
+                frag W = P::load(fm + FM_W1T + (size_t)(16 * t + c16) * DD + 16 * c + 4 * g, plane);
+                for (int sb = 0; sb < NSUB; ++sb) P::mma(accs[sb][i], W, B[sb]);
+            }
+        }
+        for (int sb = 0; sb < NSUB; ++sb)
+            for (int i = 0; i < ntile; ++i)
+                for (int r = 0; r < 4; ++r) {
+                    const int n = 16 * (wave + 4 * i) + P::orow(g, r);
+                    act1[sb][i][r] = P::act(accs[sb][i][r] + fv[FV_B1 + n]);
+                    hcur[sb][i][r] = fv[FV_WH1 + n] * act1[sb][i][r];
+                    s_h[(c16 + 16 * sb) * LDH + n] = hcur[sb][i][r];
+                }
+        __syncthreads();
+        // ---- layers 2 and 3: 240 -> 240 with skip
+        for (int layer = 2; layer <= 3; ++layer) {
+            const int64_t mo = layer == 2 ? FM_W2T : FM_W3T;
+            const int ob = layer == 2 ? FV_B2 : FV_B3, ow = layer == 2 ? FV_WH2 : FV_WH3;
+            for (int sb = 0; sb < NSUB; ++sb)
+                for (int i = 0; i < 4; ++i) zero4(accs[sb][i]);
+            for (int c = 0; c < FW / 16; ++c) {
+                frag B[NSUB];
+                for (int sb = 0; sb < NSUB; ++sb) {
+                    const acc* hr = &s_h[(c16 + 16 * sb) * LDH];
+                    B[sb] = P::make(hr[P::kidx(c, g, 0)], hr[P::kidx(c, g, 1)], hr[P::kidx(c, g, 2)], hr[P::kidx(c, g, 3)]);
+                }
+                for (int i = 0; i < ntile; ++i) {
+                    const int t = wave + 4 * i;
+                    frag W = P::load(fm + mo + (size_t)(16 * t + c16) * FW + 16 * c + 4 * g, plane);
+                    for (int sb = 0; sb < NSUB; ++sb) P::mma(accs[sb][i], W, B[sb]);
+                }
+            }
+            __syncthreads();
+            for (int sb = 0; sb < NSUB; ++sb)
+                for (int i = 0; i < ntile; ++i)
+                    for (int r = 0; r < 4; ++r) {
+                        const int n = 16 * (wave + 4 * i) + P::orow(g, r);
+                        const acc av = P::act(accs[sb][i][r] + fv[ob + n]);
+                        if (layer == 2) act2[sb][i][r] = av; else act3[sb][i][r] = av;
+                        hcur[sb][i][r] = fv[ow + n] * av + hcur[sb][i][r];
+                        s_h[(c16 + 16 * sb) * LDH + n] = hcur[sb][i][r];
+                    }
+            __syncthreads();
+        }
+        // ---- output layer (linear): E_i = wh4 (h3 . w4 + b4)
+        for (int sb = 0; sb < NSUB; ++sb) {
+            acc e = 0;
+            for (int i = 0; i < ntile; ++i)
+                for (int r = 0; r < 4; ++r) e += hcur[sb][i][r] * fv[FV_W4 + 16 * (wave + 4 * i) + P::orow(g, r)];
+            e += __shfl_xor(e, 16);
+            e += __shfl_xor(e, 32);
+            if (g == 0) s_e[wave][c16 + 16 * sb] = e;
+        }
+        __syncthreads();
+        if (threadIdx.x < AF) {
+            const int at = a0 + threadIdx.x;
+            if (at < A.natoms && A.itype[at] == ti) {
+                double e = (double)s_e[0][threadIdx.x] + (double)s_e[1][threadIdx.x] + (double)s_e[2][threadIdx.x] +
+                           (double)s_e[3][threadIdx.x];
+                A.Ei[at] = (double)fv[FV_WH4] * (e + (double)fv[FV_B4]);
+            }
+        }
+        // ---- backward through layers 3, 2, 1 (dh = dE/dh, ga = dE/d(pre-activation))
+        acc gh[NSUB][4][4];
+        for (int sb = 0; sb < NSUB; ++sb)
+            for (int i = 0; i < ntile; ++i)
+                for (int r = 0; r < 4; ++r) {
+                    const int n = 16 * (wave + 4 * i) + P::orow(g, r);
+                    gh[sb][i][r] = fv[FV_WH4] * fv[FV_W4 + n];
+                }
+        for (int layer = 3; layer >= 1; --layer) {
+            const int ow = layer == 3 ? FV_WH3 : (layer == 2 ? FV_WH2 : FV_WH1);
+            for (int sb = 0; sb < NSUB; ++sb)
+                for (int i = 0; i < ntile; ++i)
+                    for (int r = 0; r < 4; ++r) {
+                        const int n = 16 * (wave + 4 * i) + P::orow(g, r);
+                        const acc av = layer == 3 ? act3[sb][i][r] : (layer == 2 ? act2[sb][i][r] : act1[sb][i][r]);
+                        s_h[(c16 + 16 * sb) * LDH + n] = gh[sb][i][r] * fv[ow + n] * (1 - av * av);
+                    }
+            __syncthreads();
+            if (layer == 1) break;
+            // gh_{l-1} = W_l ga_l + gh_l (skip)
+            const int64_t mo = layer == 3 ? FM_W3 : FM_W2;
+            for (int sb = 0; sb < NSUB; ++sb)
+                for (int i = 0; i < 4; ++i) zero4(accs[sb][i]);
+            for (int c = 0; c < FW / 16; ++c) {
+                frag B[NSUB];
+                for (int sb = 0; sb < NSUB; ++sb) {
+                    const acc* hr = &s_h[(c16 + 16 * sb) * LDH];
+                    B[sb] = P::make(hr[P::kidx(c, g, 0)], hr[P::kidx(c, g, 1)], hr[P::kidx(c, g, 2)], hr[P::kidx(c, g, 3)]);
+                }
+                for (int i = 0; i < ntile; ++i) {
+                    const int t = wave + 4 * i;
+                    frag W = P::load(fm + mo + (size_t)(16 * t + c16) * FW + 16 * c + 4 * g, plane);
+                    for (int sb = 0; sb < NSUB; ++sb) P::mma(accs[sb][i], W, B[sb]);
+                }
+            }
+            __syncthreads();
+            for (int sb = 0; sb < NSUB; ++sb)
+                for (int i = 0; i < ntile; ++i)
+                    for (int r = 0; r < 4; ++r) gh[sb][i][r] = accs[sb][i][r] + gh[sb][i][r];
+        }
+        // ---- dD^T = W1 ga1 (1600 x atoms), tiles m = wave + 4 i (25 per wave); dT from dD and T
+        acc p1[NSUB][4][4];                 // part (1) for the wave's rows m < 16
+        acc q2[NSUB][4][4];                 // part (2) contributions to rows n = orow(g, r) < 16
+        for (int sb = 0; sb < NSUB; ++sb)
+            for (int r = 0; r < 4; ++r)
+                for (int k = 0; k < 4; ++k) { q2[sb][r][k] = 0; p1[sb][r][k] = 0; }
+        for (int i = 0; i < 25; ++i) {
+            const int m = wave + 4 * i;
+            accv dd[NSUB];
+            for (int sb = 0; sb < NSUB; ++sb) zero4(dd[sb]);
+            for (int c = 0; c < FW / 16; ++c) {
+                frag W = P::load(fm + FM_W1 + (size_t)(16 * m + c16) * FW + 16 * c + 4 * g, plane);
+                for (int sb = 0; sb < NSUB; ++sb) {
+                    const acc* hr = &s_h[(c16 + 16 * sb) * LDH];
+                    frag B = P::make(hr[P::kidx(c, g, 0)], hr[P::kidx(c, g, 1)], hr[P::kidx(c, g, 2)], hr[P::kidx(c, g, 3)]);
+                    P::mma(dd[sb], W, B);
+                }
+            }
+            // lane holds dD[m][n = orow(g, r)] of atom c16 + 16 sb
+            for (int sb = 0; sb < NSUB; ++sb) {
+                const acc* Tm = &s_T[((c16 + 16 * sb) * E2 + m) * 4];
+                acc part[4];
+                for (int k = 0; k < 4; ++k) {
+                    acc sacc = 0;
+                    for (int r = 0; r < 4; ++r) {
+                        sacc += dd[sb][r] * Tn[sb][r][k];
+                        q2[sb][r][k] += dd[sb][r] * Tm[k];
+                    }
+                    sacc += __shfl_xor(sacc, 16);
+                    sacc += __shfl_xor(sacc, 32);
+                    part[k] = sacc;
+                }
+                const int at = a0 + c16 + 16 * sb;
+                if (i < 4) {
+                    for (int k = 0; k < 4; ++k) p1[sb][i][k] = part[k];
+                } else if (g == 0 && at < A.natoms && A.itype[at] == ti) {
+                    for (int k = 0; k < 4; ++k) dTout[((size_t)at * E2 + m) * 4 + k] = part[k];
+                }
+            }
+        }
+        __syncthreads();
+        acc* red = s_T;   // reuse: [wave][atom][16][4]
+        for (int sb = 0; sb < NSUB; ++sb)
+            for (int r = 0; r < 4; ++r)
+                for (int k = 0; k < 4; ++k)
+                    red[((wave * AF + c16 + 16 * sb) * 16 + P::orow(g, r)) * 4 + k] = q2[sb][r][k];
+        __syncthreads();
+        if (g == 0) {
+            for (int sb = 0; sb < NSUB; ++sb) {
+                const int atl = c16 + 16 * sb, at = a0 + atl;
+                if (at >= A.natoms || A.itype[at] != ti) continue;
+                for (int i = 0; i < 4; ++i) {
+                    const int m = wave + 4 * i;
+                    for (int k = 0; k < 4; ++k) {
+                        acc v = p1[sb][i][k];
+                        for (int w = 0; w < 4; ++w) v += red[((w * AF + atl) * 16 + m) * 4 + k];
+                        dTout[((size_t)at * E2 + m) * 4 + k] = v;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------------
+constexpr int APB_EMB = 16;
+
+int embed_atoms_per_block(int) { return APB_EMB; }
+int fit_atoms_per_block(int precision) { return precision == 0 ? 16 : 32; }
+
+void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s)
+{
+    dim3 grid((a.natoms + APB_EMB - 1) / APB_EMB), block(256);
+    if (precision == 0) {
+        if (table) hipLaunchKernelGGL((k_embed_fwd<PF64, APB_EMB, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_embed_fwd<PF64, APB_EMB, false>), grid, block, 0, s, a);
+    } else if (precision == 1) {
+        if (table) hipLaunchKernelGGL((k_embed_fwd<PMIX, APB_EMB, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_embed_fwd<PMIX, APB_EMB, false>), grid, block, 0, s, a);
+    } else {
+        if (table) hipLaunchKernelGGL((k_embed_fwd<PBF16, APB_EMB, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_embed_fwd<PBF16, APB_EMB, false>), grid, block, 0, s, a);
+    }
+}
+
+void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s)
+{
+    dim3 grid((a.natoms + APB_EMB - 1) / APB_EMB), block(256);
+    if (precision == 0) {
+        if (table) hipLaunchKernelGGL((k_embed_bwd<PF64, APB_EMB, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_embed_bwd<PF64, APB_EMB, false>), grid, block, 0, s, a);
+    } else if (precision == 1) {
+        if (table) hipLaunchKernelGGL((k_embed_bwd<PMIX, APB_EMB, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_embed_bwd<PMIX, APB_EMB, false>), grid, block, 0, s, a);
+    } else {
+        if (table) hipLaunchKernelGGL((k_embed_bwd<PBF16, APB_EMB, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_embed_bwd<PBF16, APB_EMB, false>), grid, block, 0, s, a);
+    }
+}
+
+void launch_fit(int precision, const FitArgs& a, hipStream_t s)
+{
+    const int af = fit_atoms_per_block(precision);
+    dim3 grid((a.natoms + af - 1) / af), block(256);
+    if (precision == 0) hipLaunchKernelGGL((k_fit<PF64, 1>), grid, block, 0, s, a);
+    else if (precision == 1) hipLaunchKernelGGL((k_fit<PMIX, 2>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_fit<PBF16, 2>), grid, block, 0, s, a);
+}
+
+}  // namespace dpk

@@ -1,0 +1,203 @@
+"""ctypes binding of libdpk.so (C ABI in include/dpk.h): argument marshalling only.
+
+Every step of the evaluation runs in the HIP library; there is no Python or CPU fallback. Loading
+fails loudly when the library has not been built (``python -m paper_2304_09409_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpk.so")
+
+DPK_OK, DPK_E_INVALID_ARG, DPK_E_TYPE_RANGE, DPK_E_BOX = 0, -1, -2, -3
+DPK_E_NBR_OVERFLOW, DPK_E_BUDGET, DPK_E_OOM, DPK_E_DEVICE, DPK_E_UNIMPLEMENTED = -4, -5, -6, -7, -8
+PRECISIONS = {"fp64": 0, "mixed": 1, "bf16": 2}
+MAX_TYPES = 8
+
+
+class DpkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"dpk error {code}: {msg}")
+        self.code = code
+
+
+class _Desc(C.Structure):
+    _fields_ = [("ntypes", C.c_int32), ("sel", C.c_int32 * MAX_TYPES), ("rcut", C.c_double),
+                ("rcut_smth", C.c_double), ("emb", C.c_int32 * 3), ("axis", C.c_int32),
+                ("fit", C.c_int32 * 3), ("type_one_side", C.c_int32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("nbr_dropped", C.c_int64), ("table_out_of_range", C.c_int64),
+                ("max_candidates", C.c_int64), ("workspace_bytes", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdpk.so (once)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2304_09409_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+        L.dpk_last_error.restype = C.c_char_p
+        L.dpk_model_param_count.argtypes = [C.POINTER(_Desc)]
+        L.dpk_model_param_count.restype = C.c_int64
+        L.dpk_model_create.argtypes = [C.POINTER(_Desc), dp, C.c_int64, C.POINTER(vp)]
+        L.dpk_model_tabulate.argtypes = [vp, C.c_double, C.c_double]
+        L.dpk_model_free.argtypes = [vp]
+        L.dpk_model_free.restype = None
+        L.dpk_ctx_create.argtypes = [vp, C.c_int, C.c_int, C.c_size_t, C.c_int, C.POINTER(vp)]
+        L.dpk_ctx_free.argtypes = [vp]
+        L.dpk_ctx_free.restype = None
+        L.dpk_ctx_workspace_bytes.argtypes = [vp, C.c_int64]
+        L.dpk_ctx_workspace_bytes.restype = C.c_int64
+        L.dpk_compute.argtypes = [vp, C.c_int64, dp, ip, dp, dp, dp, dp, dp]
+        L.dpk_compute_device.argtypes = [vp, C.c_int64, vp, vp, dp, vp, vp, vp, vp, vp]
+        L.dpk_ctx_check.argtypes = [vp]
+        L.dpk_ctx_stats.argtypes = [vp, C.POINTER(_Stats)]
+        L.dpk_debug_nlist.argtypes = [vp, ip]
+        L.dpk_debug_descriptor.argtypes = [vp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != DPK_OK:
+        raise DpkError(rc, lib().dpk_last_error().decode())
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def make_desc(model: dict) -> _Desc:
+    d = _Desc()
+    d.ntypes = model["ntypes"]
+    for t, s in enumerate(model["sel"]):
+        d.sel[t] = s
+    d.rcut, d.rcut_smth = model["rcut"], model["rcut_smth"]
+    for k in range(3):
+        d.emb[k] = model["emb"][k]
+        d.fit[k] = model["fit"][k]
+    d.axis = model["axis"]
+    d.type_one_side = int(model["type_one_side"])
+    return d
+
+
+def param_count(model: dict) -> int:
+    d = make_desc(model)
+    return int(lib().dpk_model_param_count(C.byref(d)))
+
+
+class Model:
+    """An immutable se_e2_a model (description + FP64 parameter blob)."""
+
+    def __init__(self, model: dict, params: np.ndarray):
+        self.desc_dict = dict(model)
+        self._desc = make_desc(model)
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib().dpk_model_create(C.byref(self._desc), _dp(p), p.size, C.byref(h)))
+        self.handle = h
+        self.nc = int(sum(model["sel"]))
+        self.ntypes = int(model["ntypes"])
+
+    def tabulate(self, stride: float, x_max: float):
+        _check(lib().dpk_model_tabulate(self.handle, stride, x_max))
+        return self
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.dpk_model_free(self.handle)
+            self.handle = None
+
+
+class Context:
+    """Device context: one GPU, one precision, a workspace."""
+
+    def __init__(self, model: Model, device: int = 0, precision: str = "fp64", budget_bytes: int = 0,
+                 strict_sel: bool = False):
+        self.model = model
+        self.precision = precision
+        h = C.c_void_p()
+        _check(lib().dpk_ctx_create(model.handle, device, PRECISIONS[precision], budget_bytes,
+                                    int(strict_sel), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.dpk_ctx_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    def workspace_bytes(self, natoms: int) -> int:
+        return int(lib().dpk_ctx_workspace_bytes(self.handle, natoms))
+
+    def compute(self, coord, atype, box=None, atom_energy: bool = False) -> dict:
+        """Host arrays in, host arrays out (synchronous)."""
+        coord = np.ascontiguousarray(coord, dtype=np.float64)
+        atype = np.ascontiguousarray(atype, dtype=np.int32)
+        n = coord.shape[0]
+        box = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(9)
+        e = C.c_double()
+        f = np.empty((n, 3))
+        v = np.empty(9)
+        ae = np.empty(n) if atom_energy else None
+        _check(lib().dpk_compute(self.handle, n, _dp(coord), _ip(atype), _dp(box), C.byref(e), _dp(f), _dp(v),
+                                 _dp(ae)))
+        out = dict(energy=e.value, force=f, virial=v.reshape(3, 3))
+        if atom_energy:
+            out["atom_energy"] = ae
+        return out
+
+    def compute_device(self, coord, atype, box, energy, force, virial, atom_energy=None, stream=None):
+        """torch tensors on the GPU (float64 coord [N,3], int32 atype [N]; outputs float64 energy [1],
+        force [N,3], virial [9] or [3,3]); box a host array or None. Asynchronous on `stream`
+        (default: torch's current stream)."""
+        import torch
+        n = coord.shape[0]
+        for t, dt in ((coord, torch.float64), (atype, torch.int32), (energy, torch.float64),
+                      (force, torch.float64), (virial, torch.float64)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("compute_device needs contiguous GPU tensors of the documented dtypes")
+        if stream is None:
+            stream = torch.cuda.current_stream(coord.device)
+        hbox = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(9)
+        _check(lib().dpk_compute_device(self.handle, n, coord.data_ptr(), atype.data_ptr(), _dp(hbox),
+                                        energy.data_ptr(), force.data_ptr(), virial.data_ptr(),
+                                        None if atom_energy is None else atom_energy.data_ptr(),
+                                        stream.cuda_stream))
+
+    def check(self):
+        _check(lib().dpk_ctx_check(self.handle))
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check(lib().dpk_ctx_stats(self.handle, C.byref(s)))
+        return dict(nbr_dropped=s.nbr_dropped, table_out_of_range=s.table_out_of_range,
+                    max_candidates=s.max_candidates, workspace_bytes=s.workspace_bytes)
+
+    def debug_nlist(self, natoms: int) -> np.ndarray:
+        out = np.empty((natoms, self.model.nc), dtype=np.int32)
+        _check(lib().dpk_debug_nlist(self.handle, _ip(out)))
+        return out
+
+    def debug_descriptor(self, natoms: int):
+        T = np.empty((natoms, 100, 4))
+        dT = np.empty((natoms, 100, 4))
+        _check(lib().dpk_debug_descriptor(self.handle, _dp(T), _dp(dT)))
+        return T, dT
