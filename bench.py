@@ -1,0 +1,177 @@
+#!/usr/bin/env python
+"""Benchmark: se_e2_a energy + forces + virial on the 12,288-atom water box, one MI355X.
+
+One step = one full evaluation (neighbour list, embedding + contraction, fitting, adjoint, force
+and virial reductions) of the whole frame, inputs resident in HBM. The FP64 path and the mixed
+path (split-BF16 MFMA GEMMs, FP32 activations, FP64 geometry and sums) are timed back to back;
+the JSON line's value is the mixed path's atom-steps/s, with the FP64 figures, the speedup and each
+path's force error against the FP64 CPU oracle beside it.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Published MI355X peaks (dense) and derived per-unit ceilings used for the roofline fields.
+PEAK = {
+    "hbm": 8000.0,          # GB/s
+    "fp64_mfma": 78.6,      # TFLOP/s
+    "bf16_mfma": 2500.0,    # TFLOP/s
+    "fp32_valu": 78.6,      # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (packed FP32 off)
+}
+
+
+def work_per_launch(stage: str, precision: str, natoms: int, npairs: int, nc: int):
+    """Algorithmic work of one launch of a stage: (bound, amount, peak, unit).
+
+    Per real neighbour pair: embedding layers 2 + 3 = 2 (25*50 + 50*100) = 12,500 flop, layer 1
+    50 flop, contraction G^T R 800 flop. The forward kernel computes G once (13,350 flop per
+    pair); the adjoint re-evaluates G and dG/ds (25,100), then dE/dR = G dT and (dG/ds) dT
+    (1,600) and the chain rule (~50): 26,750 flop per pair. Fitting per atom: D = T T_<^T 12,800,
+    forward 2 (1600*240 + 2*240^2 + 240) = 998,880, input gradient 2 (1600*240 + 2*240^2) =
+    998,400, dT 25,600: 2,035,680 flop. The neighbour list moves, per atom, the coordinates of the
+    candidates it reads once (24 B x 27 bins' atoms is served from cache) and writes its list:
+    N_c (4 B index + 24 B vector) + the per-type counts."""
+    if stage == "embed_fwd":
+        flops = 13350.0 * npairs
+    elif stage == "embed_bwd":
+        flops = 26750.0 * npairs
+    elif stage == "fit":
+        flops = 2035680.0 * natoms
+    else:
+        bytes_ = natoms * (nc * 28 + 8 + 24 + 4)
+        return "hbm", bytes_ / 1e9, PEAK["hbm"], "GB/s"
+    if precision == "fp64":
+        return "mfma", flops / 1e12, PEAK["fp64_mfma"], "TFLOP/s"
+    # mixed: the GEMMs run as three BF16 products each on the matrix cores; the kernel's binding
+    # unit is the vector ALU (activations, splits, epilogues), so it is measured against the
+    # FP32 vector peak.
+    return "alu", flops / 1e12, PEAK["fp32_valu"], "TFLOP/s"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2304_09409_amd import dpk, synth
+
+    c, t, b = synth.water_12288()
+    n = len(t)
+    model = dpk.Model(synth.WATER_MODEL, synth.water_params())
+    dev = torch.device("cuda:0")
+    coord = torch.tensor(c, dtype=torch.float64, device=dev)
+    atype = torch.tensor(t, dtype=torch.int32, device=dev)
+    energy = torch.zeros(1, dtype=torch.float64, device=dev)
+    force = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+    virial = torch.zeros(9, dtype=torch.float64, device=dev)
+    runs = {}
+    npairs = None
+    for prec in ("fp64", "mixed"):
+        ctx = dpk.Context(model, precision=prec)
+        for _ in range(args.warmup):
+            ctx.compute_device(coord, atype, b, energy, force, virial)
+        ctx.check()
+        if npairs is None:
+            npairs = int((ctx.debug_nlist(n) >= 0).sum())
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.compute_device(coord, atype, b, energy, force, virial)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stage_ms, nframes = ctx.profile_read()
+        ctx.profile(False)
+        ctx.check()
+        st = ctx.stats()
+        ms = (t1 - t0) * 1e3 / args.steps
+        runs[prec] = dict(ms_per_step=ms, value=n / (ms * 1e-3),
+                          stage_ms={k: v / nframes for k, v in stage_ms.items()},
+                          force=force.cpu().numpy().copy(), energy=float(energy.item()),
+                          virial=virial.cpu().numpy().reshape(3, 3).copy(), stats=st)
+        print(f"# {prec}: {ms:.3f} ms/step, {n / (ms * 1e-3):.4g} atom-steps/s, stages (ms) "
+              + ", ".join(f"{k} {v:.3f}" for k, v in runs[prec]["stage_ms"].items()), file=sys.stderr, flush=True)
+        ctx.close()
+
+    cpu = None
+    errs = {}
+    if not args.no_cpu:
+        from oracle import Oracle
+        o = Oracle(synth.WATER_MODEL, synth.water_params())
+        reps, elapsed, ref = 0, 0.0, None
+        while reps < 3 and (reps == 0 or elapsed < 10.0):
+            ts = time.perf_counter()
+            ref = o.compute(c, t, b)
+            elapsed += time.perf_counter() - ts
+            reps += 1
+        cpu = {"value": n * reps / elapsed, "unit": "atom-steps/s", "cores": o.threads(), "kind": "oracle",
+               "sample": f"the full 12,288-atom frame (E+F+virial), {reps} evaluation(s), {elapsed:.1f} s"}
+        for prec, r in runs.items():
+            d = r["force"] - ref["force"]
+            errs[prec] = {"max_abs_force_err": float(np.abs(d).max()),
+                          "rms_force_err": float(np.sqrt((d ** 2).mean())),
+                          "energy_err_per_atom": abs(r["energy"] - ref["energy"]) / n,
+                          "max_virial_err_per_atom": float(np.abs(r["virial"] - ref["virial"]).max()) / n}
+        errs["rms_force"] = float(np.sqrt((ref["force"] ** 2).mean()))
+
+    head = runs["mixed"]
+    dom = max(head["stage_ms"], key=head["stage_ms"].get)
+    bound, amount, peak, unit = work_per_launch(dom, "mixed", n, npairs, model.nc)
+    achieved = amount / (head["stage_ms"][dom] * 1e-3)
+    roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": None}
+    fp64_dom = max(runs["fp64"]["stage_ms"], key=runs["fp64"]["stage_ms"].get)
+    b2, a2, p2, u2 = work_per_launch(fp64_dom, "fp64", n, npairs, model.nc)
+    ach2 = a2 / (runs["fp64"]["stage_ms"][fp64_dom] * 1e-3)
+
+    line = {
+        "metric": "atom-steps/s (E+F+virial) mixed vs FP64 at stated force error; p50/p99 latency",
+        "value": head["value"],
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3-mfma/f32/f64",
+        "data": "synthetic",
+        "config": {"workload": "water-like box, 12,288 atoms (4,096 molecules), cubic 49.7 A periodic; "
+                               "se_e2_a rc 6.0 A, rc_smth 0.5 A, sel [46,92], embedding (25,50,100), "
+                               "M_< 16, fitting (240,240,240,1), 2 types",
+                   "atoms": n, "neighbour_pairs": npairs, "mode": "mixed"},
+        "fp64": {"value": runs["fp64"]["value"], "ms_per_step": runs["fp64"]["ms_per_step"],
+                 "stage_ms": runs["fp64"]["stage_ms"],
+                 "roofline": {"kernel": fp64_dom, "bound": b2, "achieved": ach2, "peak": p2, "unit": u2,
+                              "frac": ach2 / p2}},
+        "mixed_stage_ms": head["stage_ms"],
+        "speedup_mixed_vs_fp64": head["value"] / runs["fp64"]["value"],
+        "force_error_vs_oracle": errs or None,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -142,6 +142,22 @@ int dpk_ctx_check(dpk_ctx *c);
 
 int dpk_ctx_stats(dpk_ctx *c, dpk_stats *out);
 
+/* Stage profiler. While enabled, every frame records HIP events on its stream around each stage
+ * below; dpk_ctx_profile_read waits for the context's last stream and returns the summed stage
+ * durations (milliseconds, one per stage) and the number of frames since profiling was enabled.
+ * Enabling resets the sums. For timing tools (no effect on results). */
+enum {
+    DPK_STAGE_PREP = 0,      /* type partition, wrap into the cell, bin counting            */
+    DPK_STAGE_NLIST = 1,     /* candidate search, sorted per-type selection                 */
+    DPK_STAGE_EMBED_FWD = 2, /* environment rows, embedding net, contraction T              */
+    DPK_STAGE_FIT = 3,       /* descriptor, fitting net forward and input gradient           */
+    DPK_STAGE_EMBED_BWD = 4, /* embedding re-evaluation, adjoint, force and virial scatter   */
+    DPK_STAGE_FINAL = 5,     /* energy and virial sums, output permutation                   */
+    DPK_NSTAGES = 6
+};
+int dpk_ctx_profile(dpk_ctx *c, int enable);
+int dpk_ctx_profile_read(dpk_ctx *c, double *stage_ms, int64_t *frames);
+
 /* Stage dumps of the last computed frame (host buffers, caller order), for parity tests.
  * nlist: natoms * N_c neighbour indices (caller numbering, -1 padding), in the per-type block
  * order of Sec. II.A.1 sorted by (distance, index, image). */

@@ -200,6 +200,10 @@ struct dpk_ctx {
     // last frame
     int64_t last_n = 0;
     int64_t last_nvp = 0;
+    // stage profiler: one set of DPK_NSTAGES + 1 events per profiled frame
+    bool profiling = false;
+    std::vector<std::vector<hipEvent_t>> prof_events;
+    size_t prof_used = 0;
 };
 
 namespace {
@@ -244,6 +248,24 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
     p = take(sizeof(int) * n); if (base) c->h_atype = (int*)p;
     p = take(sizeof(double) * (10 + 4 * n)); if (base) c->h_out = (double*)p;
     return off;
+}
+
+// Returns the event set of this frame (nullptr when not profiling).
+std::vector<hipEvent_t>* prof_frame(dpk_ctx* c)
+{
+    if (!c->profiling) return nullptr;
+    if (c->prof_used == c->prof_events.size()) {
+        std::vector<hipEvent_t> ev(DPK_NSTAGES + 1);
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->prof_events.push_back(ev);
+    }
+    return &c->prof_events[c->prof_used++];
+}
+
+inline void prof_mark(std::vector<hipEvent_t>* ev, int k, hipStream_t s)
+{
+    if (ev) hipEventRecord((*ev)[k], s);
 }
 
 int ensure_ws(dpk_ctx* c, int64_t n, int64_t ncell)
@@ -545,6 +567,8 @@ void dpk_ctx_free(dpk_ctx* c)
     hipSetDevice(c->device);
     hipDeviceSynchronize();
     hipFree(c->evec); hipFree(c->emat); hipFree(c->fvec); hipFree(c->fmat); hipFree(c->table); hipFree(c->ws);
+    for (auto& set : c->prof_events)
+        for (auto e : set) hipEventDestroy(e);
     if (c->stream) hipStreamDestroy(c->stream);
     delete c;
 }
@@ -582,12 +606,15 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     if ((rc = ensure_ws(c, n, ncell))) return rc;
     const int nt = m->desc.ntypes;
 
+    std::vector<hipEvent_t>* ev = prof_frame(c);
+    prof_mark(ev, DPK_STAGE_PREP, s);
     launch_zero(c->tcount, sizeof(int) * MAXT, s);
     launch_zero(c->stats, sizeof(DevStats), s);
     launch_zero(c->cell_count, sizeof(int) * ncell, s);
     launch_zero(c->F, sizeof(double) * 3 * n, s);
     launch_types(n, d_atype, nt, c->tcount, c->toff, c->perm, c->inv_perm, c->itype, c->stats, s);
     launch_cells(n, d_coord, c->perm, gp, c->pos, c->cell_of, c->cell_count, c->cell_start, c->cursor, c->cell_atoms, s);
+    prof_mark(ev, DPK_STAGE_NLIST, s);
     launch_nlist(n, c->pos, c->itype, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cell_atoms, gp, c->nl_j,
                  c->nl_r, c->nnei, c->stats, s);
 
@@ -616,6 +643,7 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     ea.vir_part = c->vir_part;
     ea.stats = c->stats;
     const bool tab = m->tabulated;
+    prof_mark(ev, DPK_STAGE_EMBED_FWD, s);
     launch_embed_fwd(c->precision, tab, ea, s);
 
     FitArgs fa;
@@ -628,11 +656,15 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     fa.T = c->T;
     fa.dT = c->dT;
     fa.Ei = c->Ei;
+    prof_mark(ev, DPK_STAGE_FIT, s);
     launch_fit(c->precision, fa, s);
 
+    prof_mark(ev, DPK_STAGE_EMBED_BWD, s);
     launch_embed_bwd(c->precision, tab, ea, s);
+    prof_mark(ev, DPK_STAGE_FINAL, s);
     const int nvp = (n + embed_atoms_per_block(c->precision) - 1) / embed_atoms_per_block(c->precision);
     launch_finalize(n, c->Ei, nvp, c->vir_part, d_energy, d_virial, c->perm, c->F, d_force, d_atom_energy, s);
+    prof_mark(ev, DPK_NSTAGES, s);
     HIPCHK(hipGetLastError());
     c->last_stream = s;
     c->last_n = n;
@@ -708,6 +740,32 @@ int dpk_ctx_stats(dpk_ctx* c, dpk_stats* out)
     out->nbr_dropped = (int64_t)st.nbr_dropped;
     out->table_out_of_range = (int64_t)st.table_oor;
     out->max_candidates = st.max_cand;
+    return DPK_OK;
+}
+
+int dpk_ctx_profile(dpk_ctx* c, int enable)
+{
+    if (!c) return fail(DPK_E_INVALID_ARG, "NULL context");
+    HIPCHK(hipSetDevice(c->device));
+    if (c->last_stream) HIPCHK(hipStreamSynchronize(c->last_stream));
+    c->profiling = enable != 0;
+    c->prof_used = 0;
+    return DPK_OK;
+}
+
+int dpk_ctx_profile_read(dpk_ctx* c, double* stage_ms, int64_t* frames)
+{
+    if (!c || !stage_ms) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    HIPCHK(hipSetDevice(c->device));
+    if (c->last_stream) HIPCHK(hipStreamSynchronize(c->last_stream));
+    for (int k = 0; k < DPK_NSTAGES; ++k) stage_ms[k] = 0.0;
+    for (size_t f = 0; f < c->prof_used; ++f)
+        for (int k = 0; k < DPK_NSTAGES; ++k) {
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, c->prof_events[f][k], c->prof_events[f][k + 1]));
+            stage_ms[k] += ms;
+        }
+    if (frames) *frames = (int64_t)c->prof_used;
     return DPK_OK;
 }
 

@@ -63,6 +63,8 @@ def lib():
         L.dpk_compute_device.argtypes = [vp, C.c_int64, vp, vp, dp, vp, vp, vp, vp, vp]
         L.dpk_ctx_check.argtypes = [vp]
         L.dpk_ctx_stats.argtypes = [vp, C.POINTER(_Stats)]
+        L.dpk_ctx_profile.argtypes = [vp, C.c_int]
+        L.dpk_ctx_profile_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
         L.dpk_debug_nlist.argtypes = [vp, ip]
         L.dpk_debug_descriptor.argtypes = [vp, dp, dp]
         _lib = L
@@ -190,6 +192,17 @@ class Context:
         _check(lib().dpk_ctx_stats(self.handle, C.byref(s)))
         return dict(nbr_dropped=s.nbr_dropped, table_out_of_range=s.table_out_of_range,
                     max_candidates=s.max_candidates, workspace_bytes=s.workspace_bytes)
+
+    STAGES = ("prep", "nlist", "embed_fwd", "fit", "embed_bwd", "final")
+
+    def profile(self, enable: bool = True):
+        _check(lib().dpk_ctx_profile(self.handle, int(enable)))
+
+    def profile_read(self) -> tuple[dict, int]:
+        ms = np.zeros(len(self.STAGES))
+        nf = C.c_int64()
+        _check(lib().dpk_ctx_profile_read(self.handle, _dp(ms), C.byref(nf)))
+        return dict(zip(self.STAGES, ms.tolist())), nf.value
 
     def debug_nlist(self, natoms: int) -> np.ndarray:
         out = np.empty((natoms, self.model.nc), dtype=np.int32)
