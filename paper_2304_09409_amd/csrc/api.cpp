@@ -194,7 +194,7 @@ struct dpk_ctx {
     int *perm, *inv_perm, *itype, *tcount, *toff, *cell_of, *cell_atoms, *cell_count, *cell_start, *cursor;
     int *nl_j, *nnei, *h_atype;
     double *pos, *nl_r, *Ei, *F, *vir_part, *bbox, *h_coord, *h_out;
-    void *T, *dT;
+    void *T, *dT, *act;
     DevStats* stats;
     int64_t vir_blocks = 0;
     // last frame
@@ -240,6 +240,7 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
     p = take(sizeof(double) * 3 * n * nc); if (base) c->nl_r = (double*)p;
     p = take(c->acc_size * n * E2 * 4); if (base) c->T = p;
     p = take(c->acc_size * n * E2 * 4); if (base) c->dT = p;
+    p = take(c->acc_size * n * 3 * FW); if (base) c->act = p;
     p = take(sizeof(double) * n); if (base) c->Ei = (double*)p;
     p = take(sizeof(double) * 3 * n); if (base) c->F = (double*)p;
     p = take(sizeof(double) * 9 * nvb); if (base) { c->vir_part = (double*)p; c->vir_blocks = nvb; }
@@ -655,6 +656,7 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     fa.fmat = c->fmat;
     fa.T = c->T;
     fa.dT = c->dT;
+    fa.act = c->act;
     fa.Ei = c->Ei;
     prof_mark(ev, DPK_STAGE_FIT, s);
     launch_fit(c->precision, fa, s);

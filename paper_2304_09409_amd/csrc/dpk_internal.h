@@ -87,6 +87,7 @@ struct FitArgs {
     const void* fmat;       // [planes][ntypes][FM_SIZE] weight type
     const void* T;          // [N][100][4]
     void* dT;               // [N][100][4]
+    void* act;              // [N][3][240] forward activations (scratch)
     double* Ei;             // [N]
 };
 

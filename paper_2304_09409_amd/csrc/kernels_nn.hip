@@ -577,223 +577,309 @@ __global__ void __launch_bounds__(256) k_embed_bwd(EmbArgs A)
 }
 
 // ---------------------------------------------------------------------------------------------
-// Fitting net F_0 (Sec. II.A.2, eq. fitting_energy) over 16*NSUB atoms of one type:
-// forward E_i and the input gradient dE_i/dT through D = T T_<^T.
+// Fitting net F_0 (Sec. II.A.2, eq. fitting_energy): forward E_i and the input gradient dE_i/dT
+// through D = T T_<^T. Each wave owns 16 atoms and computes all 240 features of every layer, so
+// a layer's output tiles are the next layer's B operand in registers (no exchange between
+// waves). The four waves of a block share the weight K-chunks, staged through LDS with
+// register double buffering. Forward activations go to a per-atom scratch row (L2-resident) for
+// the backward pass.
 // ---------------------------------------------------------------------------------------------
-template <class P, int NSUB>
+constexpr int FIT_AF = 64;        // atoms per block (16 per wave)
+
+// Weight staging for the fitting kernel. A stage is ROWS rows x KC columns (K) of a row-major
+// matrix in global memory, stored per plane (BF16 hi, BF16 lo) or once (FP64). In LDS each row
+// holds KC/4 groups of four K values; a group is [hi0..3 lo0..3] (16 B) or [four doubles] (32 B),
+// exactly one lane's A fragment, and rows are padded by 16 B so the 16 rows a wave reads at once
+// fall in distinct banks. Global reads are 16-B pieces, issued into registers by load() one stage
+// ahead and written to LDS by store() after the MFMAs of the current stage.
+template <class P, int ROWS, int KC>
+struct FitStage {
+    typedef typename P::wt wt;
+    static constexpr int GB = 4 * sizeof(wt) * P::NPL;       // bytes per group in LDS
+    static constexpr int ROWB = (KC / 4) * GB + 16;           // bytes per LDS row
+    static constexpr int BYTES = ROWS * ROWB;
+    static constexpr int EPP = 16 / sizeof(wt);               // elements per 16-B piece
+    static constexpr int PPR = KC / EPP;                      // pieces per row and plane
+    static constexpr int TOTAL = ROWS * PPR * P::NPL;
+    static constexpr int NP = (TOTAL + 255) / 256;
+    uint4 r[NP];
+
+    __device__ __forceinline__ void load(const wt* src, int64_t ld, int64_t plane, int k0) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int q = threadIdx.x + 256 * p;
+            if (q < TOTAL) {
+                const int pl = q / (ROWS * PPR), rem = q - pl * ROWS * PPR;
+                const int row = rem / PPR, pc = rem - row * PPR;
+                r[p] = *reinterpret_cast<const uint4*>(src + pl * plane + (int64_t)row * ld + k0 + pc * EPP);
+            }
+        }
+    }
+    __device__ __forceinline__ void store(char* dst) const {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int q = threadIdx.x + 256 * p;
+            if (q < TOTAL) {
+                const int pl = q / (ROWS * PPR), rem = q - pl * ROWS * PPR;
+                const int row = rem / PPR, pc = rem - row * PPR;
+                char* rowp = dst + row * ROWB;
+                if (sizeof(wt) == 8) {
+                    // two doubles: half of group pc/2
+                    *reinterpret_cast<uint4*>(rowp + (pc >> 1) * GB + (pc & 1) * 16) = r[p];
+                } else {
+                    // eight BF16 of one plane: the plane's half of groups 2pc and 2pc+1
+                    *reinterpret_cast<uint2*>(rowp + (2 * pc) * GB + pl * 8) = make_uint2(r[p].x, r[p].y);
+                    *reinterpret_cast<uint2*>(rowp + (2 * pc + 1) * GB + pl * 8) = make_uint2(r[p].z, r[p].w);
+                }
+            }
+        }
+    }
+};
+
+// A fragment of row `row`, group `grp` of a staged block.
+template <class P, int ROWB>
+__device__ __forceinline__ typename P::frag fit_afrag(const char* base, int row, int grp)
+{
+    typename P::frag f;
+    const char* p = base + row * ROWB + grp * (4 * sizeof(typename P::wt) * P::NPL);
+    if constexpr (P::NPL == 2) {
+        f.h = *reinterpret_cast<const bf4*>(p);
+        f.l = *reinterpret_cast<const bf4*>(p + 8);
+    } else {
+        f = *reinterpret_cast<const typename P::frag*>(p);
+    }
+    return f;
+}
+
+template <class P> struct FitCfg {
+    static constexpr int KC1 = sizeof(typename P::wt) == 8 ? 16 : 32;   // layer-1 stage width
+};
+
+template <class P>
 __global__ void __launch_bounds__(256) k_fit(FitArgs A)
 {
     typedef typename P::acc acc;
     typedef typename P::wt wt;
     typedef typename P::accv accv;
     typedef typename P::frag frag;
-    constexpr int AF = 16 * NSUB;
-    constexpr int LDH = FW + 4;
-    __shared__ __attribute__((aligned(32))) acc s_T[AF * E2 * 4];
-    __shared__ __attribute__((aligned(32))) acc s_h[AF * LDH];
-    __shared__ acc s_e[4][AF];
+    constexpr int KC1 = FitCfg<P>::KC1;
+    typedef FitStage<P, FW, KC1> S1;     // layer 1: W1^T rows (240) x KC1
+    typedef FitStage<P, FW, 16> S2;      // 240 x 240 layers: 240 rows x 16
+    typedef FitStage<P, 16, FW> SD;      // dD: W1 rows 16m..16m+15 x 240
+    constexpr int BUFB = (S1::BYTES > S2::BYTES ? (S1::BYTES > SD::BYTES ? S1::BYTES : SD::BYTES)
+                                                : (S2::BYTES > SD::BYTES ? S2::BYTES : SD::BYTES));
+    __shared__ __attribute__((aligned(32))) char s_w[2][BUFB];
+    __shared__ acc s_p1[4][16][16][4];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
-    const int a0 = blockIdx.x * AF;
-    const int a1 = min(a0 + AF, A.natoms);
+    const int a0 = blockIdx.x * FIT_AF;
+    const int a1 = min(a0 + FIT_AF, A.natoms);
     if (a0 >= a1) return;
     const int t_lo = A.itype[a0], t_hi = A.itype[a1 - 1];
     const acc* Tin = reinterpret_cast<const acc*>(A.T);
     acc* dTout = reinterpret_cast<acc*>(A.dT);
-    const int ntile = (wave < 3) ? 4 : 3;   // output tiles t = wave + 4 i of the 15 (240 / 16)
+    acc* act = reinterpret_cast<acc*>(A.act);
+    const int atom = a0 + 16 * wave + c16;
+    const bool real = atom < A.natoms;
+    const int arow = real ? atom : a0;              // rows past the end read a valid row
+    const acc* Ta = Tin + (size_t)arow * E2 * 4;
+    acc* actrow = act + (size_t)arow * 3 * FW;
 
     for (int ti = t_lo; ti <= t_hi; ++ti) {
+        const bool mine = real && A.itype[atom] == ti;
         const acc* fv = reinterpret_cast<const acc*>(A.fvec) + (size_t)ti * FVEC;
         const wt* fm = reinterpret_cast<const wt*>(A.fmat) + (size_t)ti * FM_SIZE;
         const int64_t plane = (int64_t)A.ntypes * FM_SIZE;
-        __syncthreads();
-        for (int i = threadIdx.x; i < AF * E2 * 4; i += 256) {
-            const int at = a0 + i / (E2 * 4);
-            s_T[i] = at < A.natoms ? Tin[(size_t)a0 * E2 * 4 + i] : (acc)0;
-        }
-        __syncthreads();
-        // T rows n < 16 of this lane's atoms, at the K positions this lane supplies
-        acc Tn[NSUB][4][4];
-        for (int sb = 0; sb < NSUB; ++sb)
-            for (int v = 0; v < 4; ++v)
-                for (int k = 0; k < 4; ++k) Tn[sb][v][k] = s_T[((c16 + 16 * sb) * E2 + P::kidx(0, g, v)) * 4 + k];
 
-        acc act1[NSUB][4][4], act2[NSUB][4][4], act3[NSUB][4][4], hcur[NSUB][4][4];
-        accv accs[NSUB][4];
-        // ---- layer 1: 1600 -> 240, input d = vec(T T_<^T) formed per K-chunk (m = c)
-        for (int sb = 0; sb < NSUB; ++sb)
-            for (int i = 0; i < 4; ++i) zero4(accs[sb][i]);
-        for (int c = 0; c < E2; ++c) {
-            frag B[NSUB];
-            for (int sb = 0; sb < NSUB; ++sb) {
-                const acc* Tm = &s_T[((c16 + 16 * sb) * E2 + c) * 4];
-                acc d[4];
-                for (int v = 0; v < 4; ++v)
-                    d[v] = Tm[0] * Tn[sb][v][0] + Tm[1] * Tn[sb][v][1] + Tm[2] * Tn[sb][v][2] + Tm[3] * Tn[sb][v][3];
-                B[sb] = P::make(d[0], d[1], d[2], d[3]);
+        acc Tn[4][4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Tn[v][k] = Ta[P::kidx(0, g, v) * 4 + k];
+
+        acc h[15][4];
+        accv accs[15];
+        // ---------------------------------------------------------- layer 1: 1600 -> 240
+        {
+#pragma unroll
+            for (int t = 0; t < 15; ++t) zero4(accs[t]);
+            S1 st;
+            __syncthreads();
+            st.load(fm + FM_W1T, DD, plane, 0);
+            st.store(s_w[0]);
+            __syncthreads();
+            constexpr int NCH = DD / KC1;
+#pragma unroll 1
+            for (int c = 0; c < NCH; ++c) {
+                if (c + 1 < NCH) st.load(fm + FM_W1T, DD, plane, KC1 * (c + 1));
+                const char* buf = s_w[c & 1];
+#pragma unroll
+                for (int sub = 0; sub < KC1 / 16; ++sub) {
+                    const int m = c * (KC1 / 16) + sub;      // K-chunk of 16 = row m of D
+                    const acc T0 = Ta[m * 4 + 0], T1 = Ta[m * 4 + 1], T2 = Ta[m * 4 + 2], T3 = Ta[m * 4 + 3];
+                    acc d[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) d[v] = T0 * Tn[v][0] + T1 * Tn[v][1] + T2 * Tn[v][2] + T3 * Tn[v][3];
+                    const frag B = P::make(d[0], d[1], d[2], d[3]);
+#pragma unroll
+                    for (int t = 0; t < 15; ++t) P::mma(accs[t], fit_afrag<P, S1::ROWB>(buf, 16 * t + c16, 4 * sub + g), B);
+                }
+                if (c + 1 < NCH) st.store(s_w[(c + 1) & 1]);
+                __syncthreads();
             }
-            for (int i = 0; i < ntile; ++i) {
-                const int t = wave + 4 * i;
-                frag W = P::load(fm + FM_W1T + (size_t)(16 * t + c16) * DD + 16 * c + 4 * g, plane);
-                for (int sb = 0; sb < NSUB; ++sb) P::mma(accs[sb][i], W, B[sb]);
-            }
-        }
-        for (int sb = 0; sb < NSUB; ++sb)
-            for (int i = 0; i < ntile; ++i)
+#pragma unroll
+            for (int t = 0; t < 15; ++t)
+#pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int n = 16 * (wave + 4 * i) + P::orow(g, r);
-                    act1[sb][i][r] = P::act(accs[sb][i][r] + fv[FV_B1 + n]);
-                    hcur[sb][i][r] = fv[FV_WH1 + n] * act1[sb][i][r];
-                    s_h[(c16 + 16 * sb) * LDH + n] = hcur[sb][i][r];
+                    const int n = 16 * t + P::orow(g, r);
+                    const acc av = P::act(accs[t][r] + fv[FV_B1 + n]);
+                    actrow[n] = av;
+                    h[t][r] = fv[FV_WH1 + n] * av;
                 }
-        __syncthreads();
-        // ---- layers 2 and 3: 240 -> 240 with skip
-        for (int layer = 2; layer <= 3; ++layer) {
-            const int64_t mo = layer == 2 ? FM_W2T : FM_W3T;
-            const int ob = layer == 2 ? FV_B2 : FV_B3, ow = layer == 2 ? FV_WH2 : FV_WH3;
-            for (int sb = 0; sb < NSUB; ++sb)
-                for (int i = 0; i < 4; ++i) zero4(accs[sb][i]);
-            for (int c = 0; c < FW / 16; ++c) {
-                frag B[NSUB];
-                for (int sb = 0; sb < NSUB; ++sb) {
-                    const acc* hr = &s_h[(c16 + 16 * sb) * LDH];
-                    B[sb] = P::make(hr[P::kidx(c, g, 0)], hr[P::kidx(c, g, 1)], hr[P::kidx(c, g, 2)], hr[P::kidx(c, g, 3)]);
-                }
-                for (int i = 0; i < ntile; ++i) {
-                    const int t = wave + 4 * i;
-                    frag W = P::load(fm + mo + (size_t)(16 * t + c16) * FW + 16 * c + 4 * g, plane);
-                    for (int sb = 0; sb < NSUB; ++sb) P::mma(accs[sb][i], W, B[sb]);
-                }
-            }
-            __syncthreads();
-            for (int sb = 0; sb < NSUB; ++sb)
-                for (int i = 0; i < ntile; ++i)
-                    for (int r = 0; r < 4; ++r) {
-                        const int n = 16 * (wave + 4 * i) + P::orow(g, r);
-                        const acc av = P::act(accs[sb][i][r] + fv[ob + n]);
-                        if (layer == 2) act2[sb][i][r] = av; else act3[sb][i][r] = av;
-                        hcur[sb][i][r] = fv[ow + n] * av + hcur[sb][i][r];
-                        s_h[(c16 + 16 * sb) * LDH + n] = hcur[sb][i][r];
-                    }
-            __syncthreads();
         }
-        // ---- output layer (linear): E_i = wh4 (h3 . w4 + b4)
-        for (int sb = 0; sb < NSUB; ++sb) {
+        // ---------------------------------------------------------- 240 x 240 products
+        // y = W^T x (forward, weights FM_W2T / FM_W3T) or W x (backward, FM_W2 / FM_W3), with the
+        // B operand of K-chunk c taken from output tile c of the previous step (x[c][]).
+        auto gemm240 = [&](int64_t mo, acc (&x)[15][4]) {
+#pragma unroll
+            for (int t = 0; t < 15; ++t) zero4(accs[t]);
+            S2 st;
+            __syncthreads();
+            st.load(fm + mo, FW, plane, 0);
+            st.store(s_w[0]);
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < 15; ++c) {
+                if (c + 1 < 15) st.load(fm + mo, FW, plane, 16 * (c + 1));
+                const char* buf = s_w[c & 1];
+                const frag B = P::make(x[c][0], x[c][1], x[c][2], x[c][3]);
+#pragma unroll
+                for (int t = 0; t < 15; ++t) P::mma(accs[t], fit_afrag<P, S2::ROWB>(buf, 16 * t + c16, g), B);
+                if (c + 1 < 15) st.store(s_w[(c + 1) & 1]);
+                __syncthreads();
+            }
+        };
+#pragma unroll 1
+        for (int layer = 2; layer <= 3; ++layer) {
+            gemm240(layer == 2 ? FM_W2T : FM_W3T, h);
+            const int ob = layer == 2 ? FV_B2 : FV_B3, ow = layer == 2 ? FV_WH2 : FV_WH3;
+#pragma unroll
+            for (int t = 0; t < 15; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int n = 16 * t + P::orow(g, r);
+                    const acc av = P::act(accs[t][r] + fv[ob + n]);
+                    actrow[(layer - 1) * FW + n] = av;
+                    h[t][r] = fv[ow + n] * av + h[t][r];
+                }
+        }
+        // ---------------------------------------------------------- energy
+        {
             acc e = 0;
-            for (int i = 0; i < ntile; ++i)
-                for (int r = 0; r < 4; ++r) e += hcur[sb][i][r] * fv[FV_W4 + 16 * (wave + 4 * i) + P::orow(g, r)];
+#pragma unroll
+            for (int t = 0; t < 15; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) e += h[t][r] * fv[FV_W4 + 16 * t + P::orow(g, r)];
             e += __shfl_xor(e, 16);
             e += __shfl_xor(e, 32);
-            if (g == 0) s_e[wave][c16 + 16 * sb] = e;
+            if (g == 0 && mine) A.Ei[atom] = (double)fv[FV_WH4] * ((double)e + (double)fv[FV_B4]);
         }
-        __syncthreads();
-        if (threadIdx.x < AF) {
-            const int at = a0 + threadIdx.x;
-            if (at < A.natoms && A.itype[at] == ti) {
-                double e = (double)s_e[0][threadIdx.x] + (double)s_e[1][threadIdx.x] + (double)s_e[2][threadIdx.x] +
-                           (double)s_e[3][threadIdx.x];
-                A.Ei[at] = (double)fv[FV_WH4] * (e + (double)fv[FV_B4]);
-            }
-        }
-        // ---- backward through layers 3, 2, 1 (dh = dE/dh, ga = dE/d(pre-activation))
-        acc gh[NSUB][4][4];
-        for (int sb = 0; sb < NSUB; ++sb)
-            for (int i = 0; i < ntile; ++i)
+        // ---------------------------------------------------------- backward through layers 3, 2
+        // h[][] now holds gh = dE/dh of the current layer's output
+#pragma unroll
+        for (int t = 0; t < 15; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h[t][r] = fv[FV_WH4] * fv[FV_W4 + 16 * t + P::orow(g, r)];
+#pragma unroll 1
+        for (int layer = 3; layer >= 2; --layer) {
+            const int ow = layer == 3 ? FV_WH3 : FV_WH2;
+            acc ga[15][4];
+#pragma unroll
+            for (int t = 0; t < 15; ++t)
+#pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int n = 16 * (wave + 4 * i) + P::orow(g, r);
-                    gh[sb][i][r] = fv[FV_WH4] * fv[FV_W4 + n];
+                    const int n = 16 * t + P::orow(g, r);
+                    const acc av = actrow[(layer - 1) * FW + n];
+                    ga[t][r] = h[t][r] * fv[ow + n] * (1 - av * av);
                 }
-        for (int layer = 3; layer >= 1; --layer) {
-            const int ow = layer == 3 ? FV_WH3 : (layer == 2 ? FV_WH2 : FV_WH1);
-            for (int sb = 0; sb < NSUB; ++sb)
-                for (int i = 0; i < ntile; ++i)
-                    for (int r = 0; r < 4; ++r) {
-                        const int n = 16 * (wave + 4 * i) + P::orow(g, r);
-                        const acc av = layer == 3 ? act3[sb][i][r] : (layer == 2 ? act2[sb][i][r] : act1[sb][i][r]);
-                        s_h[(c16 + 16 * sb) * LDH + n] = gh[sb][i][r] * fv[ow + n] * (1 - av * av);
-                    }
-            __syncthreads();
-            if (layer == 1) break;
-            // gh_{l-1} = W_l ga_l + gh_l (skip)
-            const int64_t mo = layer == 3 ? FM_W3 : FM_W2;
-            for (int sb = 0; sb < NSUB; ++sb)
-                for (int i = 0; i < 4; ++i) zero4(accs[sb][i]);
-            for (int c = 0; c < FW / 16; ++c) {
-                frag B[NSUB];
-                for (int sb = 0; sb < NSUB; ++sb) {
-                    const acc* hr = &s_h[(c16 + 16 * sb) * LDH];
-                    B[sb] = P::make(hr[P::kidx(c, g, 0)], hr[P::kidx(c, g, 1)], hr[P::kidx(c, g, 2)], hr[P::kidx(c, g, 3)]);
-                }
-                for (int i = 0; i < ntile; ++i) {
-                    const int t = wave + 4 * i;
-                    frag W = P::load(fm + mo + (size_t)(16 * t + c16) * FW + 16 * c + 4 * g, plane);
-                    for (int sb = 0; sb < NSUB; ++sb) P::mma(accs[sb][i], W, B[sb]);
-                }
-            }
-            __syncthreads();
-            for (int sb = 0; sb < NSUB; ++sb)
-                for (int i = 0; i < ntile; ++i)
-                    for (int r = 0; r < 4; ++r) gh[sb][i][r] = accs[sb][i][r] + gh[sb][i][r];
+            gemm240(layer == 3 ? FM_W3 : FM_W2, ga);
+#pragma unroll
+            for (int t = 0; t < 15; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h[t][r] = accs[t][r] + h[t][r];   // skip connection
         }
-        // ---- dD^T = W1 ga1 (1600 x atoms), tiles m = wave + 4 i (25 per wave); dT from dD and T
-        acc p1[NSUB][4][4];                 // part (1) for the wave's rows m < 16
-        acc q2[NSUB][4][4];                 // part (2) contributions to rows n = orow(g, r) < 16
-        for (int sb = 0; sb < NSUB; ++sb)
-            for (int r = 0; r < 4; ++r)
-                for (int k = 0; k < 4; ++k) { q2[sb][r][k] = 0; p1[sb][r][k] = 0; }
-        for (int i = 0; i < 25; ++i) {
-            const int m = wave + 4 * i;
-            accv dd[NSUB];
-            for (int sb = 0; sb < NSUB; ++sb) zero4(dd[sb]);
-            for (int c = 0; c < FW / 16; ++c) {
-                frag W = P::load(fm + FM_W1 + (size_t)(16 * m + c16) * FW + 16 * c + 4 * g, plane);
-                for (int sb = 0; sb < NSUB; ++sb) {
-                    const acc* hr = &s_h[(c16 + 16 * sb) * LDH];
-                    frag B = P::make(hr[P::kidx(c, g, 0)], hr[P::kidx(c, g, 1)], hr[P::kidx(c, g, 2)], hr[P::kidx(c, g, 3)]);
-                    P::mma(dd[sb], W, B);
-                }
+        frag G1[15];
+#pragma unroll
+        for (int t = 0; t < 15; ++t) {
+            acc x[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * t + P::orow(g, r);
+                const acc av = actrow[n];
+                x[r] = h[t][r] * fv[FV_WH1 + n] * (1 - av * av);
             }
-            // lane holds dD[m][n = orow(g, r)] of atom c16 + 16 sb
-            for (int sb = 0; sb < NSUB; ++sb) {
-                const acc* Tm = &s_T[((c16 + 16 * sb) * E2 + m) * 4];
-                acc part[4];
+            G1[t] = P::make(x[0], x[1], x[2], x[3]);
+        }
+        // ---------------------------------------------------------- dD = W1 ga1 and dT
+        // Tile m holds dD[m][n = orow(g, r)] of this lane's atom. dT_mk collects
+        // sum_n dD_mn T_nk (part 1) and, for m < 16, sum_p dD_pm T_pk (part 2, in q2).
+        acc q2[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q2[r][k] = 0;
+        {
+            SD st;
+            __syncthreads();
+            st.load(fm + FM_W1, FW, plane, 0);
+            st.store(s_w[0]);
+            __syncthreads();
+#pragma unroll 1
+            for (int m = 0; m < E2; ++m) {
+                if (m + 1 < E2) st.load(fm + FM_W1 + (int64_t)(m + 1) * 16 * FW, FW, plane, 0);
+                const char* buf = s_w[m & 1];
+                accv dd;
+                zero4(dd);
+#pragma unroll
+                for (int c = 0; c < 15; ++c) P::mma(dd, fit_afrag<P, SD::ROWB>(buf, c16, 4 * c + g), G1[c]);
+                const acc T0 = Ta[m * 4 + 0], T1 = Ta[m * 4 + 1], T2 = Ta[m * 4 + 2], T3 = Ta[m * 4 + 3];
+                acc part[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    part[0] += dd[r] * Tn[r][0];
+                    part[1] += dd[r] * Tn[r][1];
+                    part[2] += dd[r] * Tn[r][2];
+                    part[3] += dd[r] * Tn[r][3];
+                    q2[r][0] += dd[r] * T0;
+                    q2[r][1] += dd[r] * T1;
+                    q2[r][2] += dd[r] * T2;
+                    q2[r][3] += dd[r] * T3;
+                }
+#pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    acc sacc = 0;
-                    for (int r = 0; r < 4; ++r) {
-                        sacc += dd[sb][r] * Tn[sb][r][k];
-                        q2[sb][r][k] += dd[sb][r] * Tm[k];
+                    part[k] += __shfl_xor(part[k], 16);
+                    part[k] += __shfl_xor(part[k], 32);
+                }
+                if (g == 0) {
+                    if (m < 16) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) s_p1[wave][c16][m][k] = part[k];
+                    } else if (mine) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) dTout[((size_t)atom * E2 + m) * 4 + k] = part[k];
                     }
-                    sacc += __shfl_xor(sacc, 16);
-                    sacc += __shfl_xor(sacc, 32);
-                    part[k] = sacc;
                 }
-                const int at = a0 + c16 + 16 * sb;
-                if (i < 4) {
-                    for (int k = 0; k < 4; ++k) p1[sb][i][k] = part[k];
-                } else if (g == 0 && at < A.natoms && A.itype[at] == ti) {
-                    for (int k = 0; k < 4; ++k) dTout[((size_t)at * E2 + m) * 4 + k] = part[k];
-                }
+                if (m + 1 < E2) st.store(s_w[(m + 1) & 1]);
+                __syncthreads();
             }
         }
-        __syncthreads();
-        acc* red = s_T;   // reuse: [wave][atom][16][4]
-        for (int sb = 0; sb < NSUB; ++sb)
-            for (int r = 0; r < 4; ++r)
-                for (int k = 0; k < 4; ++k)
-                    red[((wave * AF + c16 + 16 * sb) * 16 + P::orow(g, r)) * 4 + k] = q2[sb][r][k];
-        __syncthreads();
-        if (g == 0) {
-            for (int sb = 0; sb < NSUB; ++sb) {
-                const int atl = c16 + 16 * sb, at = a0 + atl;
-                if (at >= A.natoms || A.itype[at] != ti) continue;
-                for (int i = 0; i < 4; ++i) {
-                    const int m = wave + 4 * i;
-                    for (int k = 0; k < 4; ++k) {
-                        acc v = p1[sb][i][k];
-                        for (int w = 0; w < 4; ++w) v += red[((w * AF + atl) * 16 + m) * 4 + k];
-                        dTout[((size_t)at * E2 + m) * 4 + k] = v;
-                    }
-                }
+        // rows n < 16: part 1 (LDS) + part 2 (this lane's q2)
+        if (mine) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = P::orow(g, r);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dTout[((size_t)atom * E2 + n) * 4 + k] = s_p1[wave][c16][n][k] + q2[r][k];
             }
         }
     }
@@ -805,7 +891,7 @@ __global__ void __launch_bounds__(256) k_fit(FitArgs A)
 constexpr int APB_EMB = 16;
 
 int embed_atoms_per_block(int) { return APB_EMB; }
-int fit_atoms_per_block(int precision) { return precision == 0 ? 16 : 32; }
+int fit_atoms_per_block(int) { return FIT_AF; }
 
 void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s)
 {
@@ -839,11 +925,10 @@ void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s
 
 void launch_fit(int precision, const FitArgs& a, hipStream_t s)
 {
-    const int af = fit_atoms_per_block(precision);
-    dim3 grid((a.natoms + af - 1) / af), block(256);
-    if (precision == 0) hipLaunchKernelGGL((k_fit<PF64, 1>), grid, block, 0, s, a);
-    else if (precision == 1) hipLaunchKernelGGL((k_fit<PMIX, 2>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_fit<PBF16, 2>), grid, block, 0, s, a);
+    dim3 grid((a.natoms + FIT_AF - 1) / FIT_AF), block(256);
+    if (precision == 0) hipLaunchKernelGGL((k_fit<PF64>), grid, block, 0, s, a);
+    else if (precision == 1) hipLaunchKernelGGL((k_fit<PMIX>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_fit<PBF16>), grid, block, 0, s, a);
 }
 
 }  // namespace dpk
