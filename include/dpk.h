@@ -116,7 +116,8 @@ int dpk_ctx_create(const dpk_model *m, int device, int precision, size_t hbm_bud
 
 void dpk_ctx_free(dpk_ctx *c);
 
-/* Device bytes a frame of natoms atoms needs in this context (workspace only). */
+/* Device bytes of the model plus the workspace of a frame of natoms atoms (cell grid counted at
+ * one bin per atom, an upper bound at liquid densities). */
 int64_t dpk_ctx_workspace_bytes(const dpk_ctx *c, int64_t natoms);
 
 /* Host-pointer entry point: copies the frame to the device, evaluates it and copies the results
@@ -164,6 +165,64 @@ int dpk_ctx_profile_read(dpk_ctx *c, double *stage_ms, int64_t *frames);
 int dpk_debug_nlist(dpk_ctx *c, int32_t *nlist);
 /* T = N_c^-1 G^T R (natoms * M * 4) and dE/dT (natoms * M * 4), as FP64. */
 int dpk_debug_descriptor(dpk_ctx *c, double *T, double *dT);
+
+/* ---------------------------------------------------------------------------------------------
+ * Serving: continuous admission of frames of uneven size from many concurrent simulations.
+ * A server owns nslots device slots on one GPU (each a context with its own stream and workspace,
+ * sharing one copy of the model). A scheduler thread admits queued frames in arrival order as
+ * soon as a slot is idle and the HBM budget (model + every slot's workspace) allows, freeing idle
+ * slots' workspaces when that makes room; admitted frames run concurrently on their slots'
+ * streams. Frames that name the same simulation go back to the slot that ran its previous frame
+ * when it is idle, reusing that slot's device buffers (cell list, neighbour list, descriptor).
+ * -------------------------------------------------------------------------------------------- */
+typedef struct dpk_server dpk_server;
+
+typedef struct {
+    int64_t natoms;
+    const double *coord;      /* host, [natoms][3]; caller keeps it alive until the frame is done */
+    const int32_t *atype;     /* host, [natoms]                                                     */
+    const double *box;        /* host, 9 doubles, or NULL                                           */
+    double *energy;           /* host outputs, written when the frame completes                     */
+    double *force;            /* [natoms][3]                                                        */
+    double *virial;           /* [9]                                                                */
+    double *atom_energy;      /* [natoms] or NULL                                                   */
+    int64_t simulation;       /* id of the simulation the frame belongs to, or -1                   */
+} dpk_frame;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t peak_bytes;        /* largest device footprint (model + slot workspaces) reached     */
+    int64_t budget_waits;      /* admissions delayed because the budget was full                  */
+    int64_t slot_reuse;        /* frames that ran on the slot of their simulation's previous frame */
+} dpk_server_counters;
+
+/* hbm_budget_bytes = 0: no bound. nslots in 1..64. */
+int dpk_server_create(const dpk_model *m, int device, int precision, int nslots,
+                      size_t hbm_budget_bytes, dpk_server **out);
+/* Queue a frame; returns at once with a ticket. DPK_E_BUDGET if the frame alone exceeds the
+ * budget. The frame's buffers must stay valid until dpk_server_poll reports it done. */
+int dpk_server_submit(dpk_server *s, const dpk_frame *f, uint64_t *ticket);
+/* *done = 0 while queued or running, 1 when finished successfully, or the frame's (negative)
+ * error code. Never blocks. */
+int dpk_server_poll(dpk_server *s, uint64_t ticket, int *done);
+/* Block until the frame finishes; returns its result code (error text via dpk_last_error). */
+int dpk_server_wait(dpk_server *s, uint64_t ticket);
+/* Host steady-clock nanoseconds of the frame's submission, start on the device and completion
+ * (times[3]); valid once the frame is done. */
+int dpk_server_times(dpk_server *s, uint64_t ticket, int64_t *times);
+int dpk_server_stats(dpk_server *s, dpk_server_counters *out);
+/* Waits for every queued frame, then frees the server and its slots. */
+void dpk_server_free(dpk_server *s);
+
+/* The server's admission rule as a pure function (no device work): choose a slot for a frame
+ * needing need_bytes of workspace, given each slot's busy flag, workspace bytes and last
+ * simulation id. Returns 1 (admit into *slot; if *release_idle, the other idle slots' workspaces
+ * are freed and the chosen one resized to need_bytes first), 0 (wait), or DPK_E_BUDGET (the frame
+ * cannot fit even on an empty device). budget_bytes = 0 means unbounded. */
+int dpk_admit_plan(int nslots, const int32_t *busy, const int64_t *slot_bytes,
+                   const int64_t *slot_sim, int64_t need_bytes, int64_t simulation,
+                   int64_t budget_bytes, int64_t model_bytes, int32_t *slot,
+                   int32_t *release_idle);
 
 #ifdef __cplusplus
 }

@@ -7,6 +7,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -185,6 +193,7 @@ struct dpk_ctx {
     void* fmat = nullptr;
     void* table = nullptr;
     size_t model_bytes = 0;
+    bool owns_model = true;              // false for server slots sharing the first slot's copy
     // workspace
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -278,7 +287,9 @@ int ensure_ws(dpk_ctx* c, int64_t n, int64_t ncell)
         return fail(DPK_E_BUDGET, "frame of %lld atoms needs %zu workspace bytes + %zu model bytes, budget %zu",
                     (long long)n, bytes, c->model_bytes, c->budget);
     if (c->ws) {
-        HIPCHK(hipDeviceSynchronize());
+        // the old buffers may still be used by work queued on this context's streams
+        if (c->last_stream) HIPCHK(hipStreamSynchronize(c->last_stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
         HIPCHK(hipFree(c->ws));
         c->ws = nullptr;
     }
@@ -566,8 +577,12 @@ void dpk_ctx_free(dpk_ctx* c)
 {
     if (!c) return;
     hipSetDevice(c->device);
-    hipDeviceSynchronize();
-    hipFree(c->evec); hipFree(c->emat); hipFree(c->fvec); hipFree(c->fmat); hipFree(c->table); hipFree(c->ws);
+    if (c->last_stream) hipStreamSynchronize(c->last_stream);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->owns_model) {
+        hipFree(c->evec); hipFree(c->emat); hipFree(c->fvec); hipFree(c->fmat); hipFree(c->table);
+    }
+    hipFree(c->ws);
     for (auto& set : c->prof_events)
         for (auto e : set) hipEventDestroy(e);
     if (c->stream) hipStreamDestroy(c->stream);
@@ -577,8 +592,8 @@ void dpk_ctx_free(dpk_ctx* c)
 int64_t dpk_ctx_workspace_bytes(const dpk_ctx* c, int64_t natoms)
 {
     if (!c || natoms < 1) return -1;
-    dpk_ctx tmp = *c;
-    return (int64_t)layout_ws(&tmp, natoms, 256 * 256 * 4, nullptr) + (int64_t)c->model_bytes;
+    // bins are at least r_c wide, so a frame has at most about one bin per atom at liquid density
+    return (int64_t)layout_ws(const_cast<dpk_ctx*>(c), natoms, natoms + 1, nullptr) + (int64_t)c->model_bytes;
 }
 
 int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const int32_t* d_atype, const double* box,
@@ -796,21 +811,426 @@ int dpk_debug_descriptor(dpk_ctx* c, double* T, double* dT)
     const int64_t n = c->last_n, per = E2 * 4;
     std::vector<int> perm(n);
     HIPCHK(hipMemcpy(perm.data(), c->perm, sizeof(int) * n, hipMemcpyDeviceToHost));
-    std::vector<char> bt(c->acc_size * n * per), bd(bt.size());
+    std::vector<char> bt(c->acc_size * n * per), bd(c->acc_size * n * per);
     HIPCHK(hipMemcpy(bt.data(), c->T, bt.size(), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(bd.data(), c->dT, bd.size(), hipMemcpyDeviceToHost));
+    auto val = [&](const std::vector<char>& b, int64_t i) {
+        return c->acc_size == 8 ? ((const double*)b.data())[i] : (double)((const float*)b.data())[i];
+    };
     for (int64_t a = 0; a < n; ++a)
         for (int64_t k = 0; k < per; ++k) {
             const int64_t src = a * per + k, dst = (int64_t)perm[a] * per + k;
-            if (c->acc_size == 8) {
-                T[dst] = ((const double*)bt.data())[src];
-                dT[dst] = ((const double*)bd.data())[src];
-            } else {
-                T[dst] = ((const float*)bt.data())[src];
-                dT[dst] = ((const float*)bd.data())[src];
-            }
+            T[dst] = val(bt, src);
+            dT[dst] = val(bd, src);
         }
     return DPK_OK;
+}
+
+}  // extern "C"
+
+// =============================================================================================
+// Serving
+// =============================================================================================
+namespace {
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Request {
+    uint64_t ticket = 0;
+    dpk_frame f{};
+    int64_t need = 0;          // workspace bytes
+    int state = 0;             // 0 queued, 1 running, 2 done
+    int result = 0;
+    std::string err;
+    int64_t t_submit = 0, t_start = 0, t_done = 0;
+};
+
+struct Slot {
+    dpk_ctx* ctx = nullptr;
+    hipEvent_t done = nullptr;
+    Request* req = nullptr;
+    int64_t sim = -1;
+    double* pin_coord = nullptr;
+    int* pin_type = nullptr;
+    double* pin_out = nullptr;
+    int64_t pin_cap = 0;
+};
+
+void release_ws(dpk_ctx* c)
+{
+    if (!c->ws) return;
+    if (c->last_stream) hipStreamSynchronize(c->last_stream);
+    hipStreamSynchronize(c->stream);
+    hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    c->cap_atoms = 0;
+    c->cap_cells = 0;
+}
+
+// Workspace bytes of a frame (cell grid from the host copy of the frame).
+int frame_need(dpk_ctx* c, const dpk_frame& f, int64_t* need, int64_t* ncell)
+{
+    GeomParams gp;
+    int rc;
+    if (f.box) {
+        rc = setup_geometry(c, f.box, nullptr, gp);
+    } else {
+        double bb[6] = {1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+        for (int64_t i = 0; i < f.natoms; ++i)
+            for (int k = 0; k < 3; ++k) {
+                bb[k] = std::min(bb[k], f.coord[3 * i + k]);
+                bb[3 + k] = std::max(bb[3 + k], f.coord[3 * i + k]);
+            }
+        rc = setup_geometry(c, nullptr, bb, gp);
+    }
+    if (rc) return rc;
+    *ncell = (int64_t)gp.nb[0] * gp.nb[1] * gp.nb[2];
+    *need = (int64_t)layout_ws(c, f.natoms, *ncell, nullptr);
+    return DPK_OK;
+}
+
+}  // namespace
+
+struct dpk_server {
+    const dpk_model* model = nullptr;
+    int device = 0;
+    int64_t budget = 0;
+    std::vector<Slot> slots;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request*> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+    uint64_t next_ticket = 1;
+    std::thread th;
+    std::atomic<bool> stop{false};
+    dpk_server_counters st{};
+    int64_t model_bytes = 0;
+};
+
+namespace {
+
+int64_t resident_bytes(dpk_server* s)
+{
+    int64_t b = s->model_bytes;
+    for (auto& sl : s->slots) b += (int64_t)sl.ctx->ws_bytes;
+    return b;
+}
+
+void finish(dpk_server* s, Slot& sl, int rc, const std::string& msg)
+{
+    Request* r = sl.req;
+    r->result = rc;
+    r->err = msg;
+    if (rc == DPK_OK) {
+        const int64_t n = r->f.natoms;
+        const double* o = sl.pin_out;
+        *r->f.energy = o[0];
+        std::memcpy(r->f.virial, o + 1, sizeof(double) * 9);
+        std::memcpy(r->f.force, o + 10, sizeof(double) * 3 * n);
+        if (r->f.atom_energy) std::memcpy(r->f.atom_energy, o + 10 + 3 * n, sizeof(double) * n);
+        s->st.completed++;
+    } else {
+        s->st.failed++;
+    }
+    r->t_done = now_ns();
+    r->state = 2;
+    sl.req = nullptr;
+}
+
+int launch(dpk_server* s, Slot& sl, Request* r)
+{
+    dpk_ctx* c = sl.ctx;
+    const int64_t n = r->f.natoms;
+    int64_t need, ncell;
+    int rc = frame_need(c, r->f, &need, &ncell);
+    if (rc) return rc;
+    if ((rc = ensure_ws(c, n, ncell))) return rc;
+    if (sl.pin_cap < n) {
+        hipHostFree(sl.pin_coord);
+        hipHostFree(sl.pin_type);
+        hipHostFree(sl.pin_out);
+        sl.pin_coord = nullptr; sl.pin_type = nullptr; sl.pin_out = nullptr; sl.pin_cap = 0;
+        const int64_t cap = std::max<int64_t>(n, 1024);
+        if (hipHostMalloc((void**)&sl.pin_coord, sizeof(double) * 3 * cap) != hipSuccess ||
+            hipHostMalloc((void**)&sl.pin_type, sizeof(int) * cap) != hipSuccess ||
+            hipHostMalloc((void**)&sl.pin_out, sizeof(double) * (10 + 4 * cap)) != hipSuccess)
+            return fail(DPK_E_OOM, "pinned host staging of %lld atoms failed", (long long)cap);
+        sl.pin_cap = cap;
+    }
+    std::memcpy(sl.pin_coord, r->f.coord, sizeof(double) * 3 * n);
+    std::memcpy(sl.pin_type, r->f.atype, sizeof(int) * n);
+    hipStream_t st = c->stream;
+    HIPCHK(hipMemcpyAsync(c->h_coord, sl.pin_coord, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->h_atype, sl.pin_type, sizeof(int) * n, hipMemcpyHostToDevice, st));
+    double* o = c->h_out;
+    rc = dpk_compute_device(c, n, c->h_coord, c->h_atype, r->f.box, o, o + 10, o + 1,
+                            r->f.atom_energy ? o + 10 + 3 * n : nullptr, st);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(sl.pin_out, o, sizeof(double) * (10 + (r->f.atom_energy ? 4 : 3) * n),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(sl.done, st));
+    if (sl.sim >= 0 && sl.sim == r->f.simulation) s->st.slot_reuse++;
+    sl.sim = r->f.simulation;
+    sl.req = r;
+    r->state = 1;
+    r->t_start = now_ns();
+    return DPK_OK;
+}
+
+void scheduler(dpk_server* s)
+{
+    hipSetDevice(s->device);
+    const int ns = (int)s->slots.size();
+    std::vector<int32_t> busy(ns);
+    std::vector<int64_t> bytes(ns), sims(ns);
+    while (true) {
+        bool progressed = false;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            for (auto& sl : s->slots) {
+                if (!sl.req) continue;
+                hipError_t q = hipEventQuery(sl.done);
+                if (q == hipErrorNotReady) continue;
+                int rc = DPK_OK;
+                std::string msg;
+                if (q != hipSuccess) {
+                    rc = DPK_E_DEVICE;
+                    msg = hipGetErrorString(q);
+                } else {
+                    rc = dpk_ctx_check(sl.ctx);
+                    if (rc) msg = g_err;
+                }
+                finish(s, sl, rc, msg);
+                progressed = true;
+            }
+            while (!s->queue.empty()) {
+                Request* r = s->queue.front();
+                for (int k = 0; k < ns; ++k) {
+                    busy[k] = s->slots[k].req != nullptr;
+                    bytes[k] = (int64_t)s->slots[k].ctx->ws_bytes;
+                    sims[k] = s->slots[k].sim;
+                }
+                int32_t slot = -1, rel = 0;
+                int plan = dpk_admit_plan(ns, busy.data(), bytes.data(), sims.data(), r->need, r->f.simulation,
+                                          s->budget, s->model_bytes, &slot, &rel);
+                if (plan == 0) {
+                    bool any_idle = false;
+                    for (int k = 0; k < ns; ++k) any_idle |= !busy[k];
+                    if (any_idle) s->st.budget_waits++;
+                    break;
+                }
+                s->queue.pop_front();
+                int rc = DPK_OK;
+                if (plan < 0) {
+                    rc = plan;
+                    g_err = "frame does not fit the server's HBM budget";
+                } else {
+                    if (rel) {
+                        for (int k = 0; k < ns; ++k)
+                            if (!busy[k] && k != slot) release_ws(s->slots[k].ctx);
+                        if ((int64_t)s->slots[slot].ctx->ws_bytes > r->need) release_ws(s->slots[slot].ctx);
+                    }
+                    rc = launch(s, s->slots[slot], r);
+                    s->st.peak_bytes = std::max(s->st.peak_bytes, resident_bytes(s));
+                }
+                if (rc) {
+                    Slot tmp;
+                    tmp.req = r;
+                    r->state = 1;
+                    finish(s, tmp, rc, g_err);
+                    if (s->slots[slot >= 0 ? slot : 0].req == r) s->slots[slot].req = nullptr;
+                }
+                progressed = true;
+            }
+            if (progressed) s->cv.notify_all();
+            bool idle = s->queue.empty();
+            for (auto& sl : s->slots) idle &= sl.req == nullptr;
+            if (s->stop && idle) break;
+        }
+        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpk_admit_plan(int nslots, const int32_t* busy, const int64_t* slot_bytes, const int64_t* slot_sim,
+                   int64_t need_bytes, int64_t simulation, int64_t budget_bytes, int64_t model_bytes, int32_t* slot,
+                   int32_t* release_idle)
+{
+    if (nslots < 1 || !busy || !slot_bytes || !slot_sim || !slot || !release_idle || need_bytes < 0)
+        return fail(DPK_E_INVALID_ARG, "bad admission query");
+    *slot = -1;
+    *release_idle = 0;
+    if (budget_bytes > 0 && need_bytes + model_bytes > budget_bytes) return DPK_E_BUDGET;
+    int pick = -1;
+    // 1. the idle slot that ran this simulation's previous frame
+    if (simulation >= 0)
+        for (int k = 0; k < nslots; ++k)
+            if (!busy[k] && slot_sim[k] == simulation) { pick = k; break; }
+    // 2. the smallest idle slot that already holds enough workspace
+    if (pick < 0)
+        for (int k = 0; k < nslots; ++k)
+            if (!busy[k] && slot_bytes[k] >= need_bytes && (pick < 0 || slot_bytes[k] < slot_bytes[pick])) pick = k;
+    // 3. the idle slot with the most workspace (least growth)
+    if (pick < 0)
+        for (int k = 0; k < nslots; ++k)
+            if (!busy[k] && (pick < 0 || slot_bytes[k] > slot_bytes[pick])) pick = k;
+    if (pick < 0) return 0;
+    *slot = pick;
+    if (budget_bytes <= 0) return 1;
+    int64_t busy_b = 0, idle_b = 0;
+    for (int k = 0; k < nslots; ++k) {
+        if (busy[k]) busy_b += slot_bytes[k];
+        else if (k != pick) idle_b += slot_bytes[k];
+    }
+    const int64_t mine = std::max(slot_bytes[pick], need_bytes);
+    if (model_bytes + busy_b + idle_b + mine <= budget_bytes) return 1;
+    if (model_bytes + busy_b + need_bytes <= budget_bytes) {
+        *release_idle = 1;
+        return 1;
+    }
+    *slot = -1;
+    return 0;
+}
+
+int dpk_server_create(const dpk_model* m, int device, int precision, int nslots, size_t hbm_budget_bytes,
+                      dpk_server** out)
+{
+    if (!m || !out || nslots < 1 || nslots > 64) return fail(DPK_E_INVALID_ARG, "bad server arguments");
+    *out = nullptr;
+    auto* s = new dpk_server;
+    s->model = m;
+    s->device = device;
+    s->budget = (int64_t)hbm_budget_bytes;
+    s->slots.resize(nslots);
+    for (int k = 0; k < nslots; ++k) {
+        int rc;
+        if (k == 0) {
+            rc = dpk_ctx_create(m, device, precision, 0, 0, &s->slots[0].ctx);
+        } else {
+            // further slots share the first slot's device copy of the model
+            dpk_ctx* c = new dpk_ctx;
+            const dpk_ctx* c0 = s->slots[0].ctx;
+            c->model = m;
+            c->device = device;
+            c->precision = precision;
+            c->acc_size = c0->acc_size;
+            c->evec = c0->evec; c->emat = c0->emat; c->fvec = c0->fvec; c->fmat = c0->fmat; c->table = c0->table;
+            c->model_bytes = c0->model_bytes;
+            c->owns_model = false;
+            rc = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess ? DPK_OK : DPK_E_DEVICE;
+            s->slots[k].ctx = c;
+            if (rc) g_err = "hipStreamCreate failed";
+        }
+        if (!rc && hipEventCreateWithFlags(&s->slots[k].done, hipEventDisableTiming) != hipSuccess) rc = DPK_E_DEVICE;
+        if (rc) {
+            for (int q = k; q >= 0; --q) {
+                if (s->slots[q].done) hipEventDestroy(s->slots[q].done);
+                if (s->slots[q].ctx) dpk_ctx_free(s->slots[q].ctx);
+            }
+            delete s;
+            return rc;
+        }
+    }
+    s->model_bytes = (int64_t)s->slots[0].ctx->model_bytes;
+    if (s->budget && s->model_bytes > s->budget) {
+        dpk_server_free(s);
+        return fail(DPK_E_BUDGET, "model alone exceeds the server budget");
+    }
+    s->th = std::thread(scheduler, s);
+    *out = s;
+    return DPK_OK;
+}
+
+int dpk_server_submit(dpk_server* s, const dpk_frame* f, uint64_t* ticket)
+{
+    if (!s || !f || !ticket || !f->coord || !f->atype || !f->energy || !f->force || !f->virial || f->natoms < 1)
+        return fail(DPK_E_INVALID_ARG, "bad frame");
+    auto r = std::make_unique<Request>();
+    r->f = *f;
+    int64_t ncell;
+    int rc = frame_need(s->slots[0].ctx, *f, &r->need, &ncell);
+    if (rc) return rc;
+    if (s->budget && r->need + s->model_bytes > s->budget)
+        return fail(DPK_E_BUDGET, "frame of %lld atoms needs %lld workspace bytes; budget %lld with model %lld",
+                    (long long)f->natoms, (long long)r->need, (long long)s->budget, (long long)s->model_bytes);
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->ticket = s->next_ticket++;
+    r->t_submit = now_ns();
+    *ticket = r->ticket;
+    s->queue.push_back(r.get());
+    s->reqs[r->ticket] = std::move(r);
+    s->st.submitted++;
+    return DPK_OK;
+}
+
+int dpk_server_poll(dpk_server* s, uint64_t ticket, int* done)
+{
+    if (!s || !done) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(DPK_E_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    const Request* r = it->second.get();
+    *done = r->state == 2 ? (r->result == DPK_OK ? 1 : r->result) : 0;
+    return DPK_OK;
+}
+
+int dpk_server_wait(dpk_server* s, uint64_t ticket)
+{
+    if (!s) return fail(DPK_E_INVALID_ARG, "NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(DPK_E_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    Request* r = it->second.get();
+    s->cv.wait(lk, [&] { return r->state == 2; });
+    if (r->result) g_err = r->err;
+    return r->result;
+}
+
+int dpk_server_times(dpk_server* s, uint64_t ticket, int64_t* times)
+{
+    if (!s || !times) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(DPK_E_INVALID_ARG, "unknown ticket");
+    times[0] = it->second->t_submit;
+    times[1] = it->second->t_start;
+    times[2] = it->second->t_done;
+    return DPK_OK;
+}
+
+int dpk_server_stats(dpk_server* s, dpk_server_counters* out)
+{
+    if (!s || !out) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    return DPK_OK;
+}
+
+void dpk_server_free(dpk_server* s)
+{
+    if (!s) return;
+    if (s->th.joinable()) {
+        s->stop = true;
+        s->th.join();
+    }
+    for (auto& sl : s->slots) {
+        if (sl.done) hipEventDestroy(sl.done);
+        hipHostFree(sl.pin_coord);
+        hipHostFree(sl.pin_type);
+        hipHostFree(sl.pin_out);
+    }
+    // slots past the first share its model buffers: free them first
+    for (size_t k = s->slots.size(); k-- > 0;)
+        if (s->slots[k].ctx) dpk_ctx_free(s->slots[k].ctx);
+    delete s;
 }
 
 }  // extern "C"

@@ -20,9 +20,9 @@
 //     100 channels (dE/dR_j and dE/ds_j) are lane-local plus two cross-group shuffles.
 //   * The backward pass re-evaluates the net with its forward-mode derivative d/ds (the input is
 //     a scalar), rather than storing G: G would cost 400 B per neighbour in HBM.
-//   * Fitting: per block 16 or 32 atoms of one type; every layer transposed (W^T as A), the
-//     descriptor D = T T_<^T is formed on the fly in B-operand layout from T in LDS; the input
-//     gradient uses the untransposed weights (W as A).
+//   * Fitting: 16 atoms per wave, all 240 features per wave; every layer transposed (W^T as A)
+//     so each layer's output tiles are the next layer's B operand; the descriptor D = T T_<^T
+//     is formed on the fly in B-operand layout; the input gradient uses W as A.
 #include <hip/hip_runtime.h>
 #include "dpk_internal.h"
 #include "dpk_launch.h"
@@ -167,56 +167,127 @@ __device__ __forceinline__ void switch_fn(double r, double rs, double rc, double
     }
 }
 
-// Row strides of the weight tiles staged in LDS (elements; multiples of 4, padded against bank
-// conflicts between the 16 rows a wave reads at once).
-constexpr int LD2 = K2P + 4;
-constexpr int LD3 = N2P + 4;
-
-// Stage one embedding net into LDS: vector block and the W2^T / W3^T planes.
-template <class P, bool W3LDS>
-__device__ void stage_net(const EmbArgs& A, int net, typename P::acc* s_vec, typename P::wt* s_w2,
-                          typename P::wt* s_w3)
-{
-    typedef typename P::acc acc;
+// Launch shape of the embedding kernels: NW waves per block, APW atoms per wave. Split-BF16 runs
+// 8 waves (two per SIMD) sharing one staged net; FP64 runs 4 and keeps W3^T in global memory
+// (L1/L2) to leave LDS for the wider activation buffers.
+template <class P> struct EmbCfg {
     typedef typename P::wt wt;
-    const acc* ev = reinterpret_cast<const acc*>(A.evec) + (size_t)net * EVEC;
-    for (int i = threadIdx.x; i < EVEC; i += blockDim.x) s_vec[i] = ev[i];
-    const int nets = A.type_one_side ? A.ntypes : A.ntypes * A.ntypes;
-    const wt* em = reinterpret_cast<const wt*>(A.emat);
-    for (int pl = 0; pl < P::NPL; ++pl) {
-        const wt* src = em + ((size_t)pl * nets + net) * EM_SIZE;
-        for (int i = threadIdx.x; i < N2P * K2P; i += blockDim.x)
-            s_w2[pl * N2P * LD2 + (i / K2P) * LD2 + (i % K2P)] = src[EM_W2T + i];
-        if (W3LDS)
-            for (int i = threadIdx.x; i < N3P * N2P; i += blockDim.x)
-                s_w3[pl * N3P * LD3 + (i / N2P) * LD3 + (i % N2P)] = src[EM_W3T + i];
+    static constexpr bool F64 = sizeof(typename P::acc) == 8;
+    static constexpr int NW = F64 ? 4 : 8;
+    static constexpr int APW = 3;
+    static constexpr int APB = NW * APW;
+    static constexpr bool W3LDS = !F64;
+    // LDS rows of staged weights: groups of four K values, [hi0..3 lo0..3] for split BF16 (one
+    // lane's A or B fragment), padded by 16 B so 16 consecutive rows fall in distinct banks.
+    static constexpr int GB = 4 * sizeof(wt) * P::NPL;
+    static constexpr int ROW2 = (K2P / 4) * GB + 16;
+    static constexpr int ROW3 = (N2P / 4) * GB + 16;
+};
+
+// Fragment of row `row`, K-group `grp` from a staged block with `rowb` bytes per row.
+template <class P>
+__device__ __forceinline__ typename P::frag lds_frag(const char* base, int rowb, int row, int grp)
+{
+    const char* p = base + row * rowb + grp * (4 * sizeof(typename P::wt) * P::NPL);
+    typename P::frag f;
+    if constexpr (P::NPL == 2) {
+        f.h = *reinterpret_cast<const bf4*>(p);
+        f.l = *reinterpret_cast<const bf4*>(p + 8);
+    } else {
+        f = *reinterpret_cast<const typename P::frag*>(p);
+    }
+    return f;
+}
+
+// Stage rows x K of a per-plane row-major matrix into interleaved LDS rows.
+template <class P>
+__device__ void stage_rows(char* dst, int rowb, const typename P::wt* src, int64_t plane, int rows, int K)
+{
+    typedef typename P::wt wt;
+    constexpr int GB = 4 * sizeof(wt) * P::NPL;
+    const int G = K / 4;
+    for (int i = threadIdx.x; i < rows * G; i += blockDim.x) {
+        const int row = i / G, grp = i - row * G;
+        const wt* sp = src + (int64_t)row * K + 4 * grp;
+        char* d = dst + row * rowb + grp * GB;
+        if constexpr (sizeof(wt) == 8) {
+            *reinterpret_cast<d4*>(d) = *reinterpret_cast<const d4*>(sp);
+        } else {
+            *reinterpret_cast<uint2*>(d) = *reinterpret_cast<const uint2*>(sp);
+            if constexpr (P::NPL == 2) *reinterpret_cast<uint2*>(d + 8) = *reinterpret_cast<const uint2*>(sp + plane);
+        }
     }
 }
 
-template <class P> struct EmbCfg {
-    // FP64 keeps W3^T in global memory (L1/L2) to leave LDS for the activation buffers.
-    static constexpr bool W3LDS = sizeof(typename P::acc) == 4;
+// Stage one embedding net: vector block, W2^T and (split BF16) W3^T.
+template <class P>
+__device__ void stage_net(const EmbArgs& A, int net, typename P::acc* s_vec, char* s_w2, char* s_w3)
+{
+    typedef typename P::acc acc;
+    typedef typename P::wt wt;
+    typedef EmbCfg<P> Cfg;
+    const acc* ev = reinterpret_cast<const acc*>(A.evec) + (size_t)net * EVEC;
+    for (int i = threadIdx.x; i < EVEC; i += blockDim.x) s_vec[i] = ev[i];
+    const int nets = A.type_one_side ? A.ntypes : A.ntypes * A.ntypes;
+    const wt* src = reinterpret_cast<const wt*>(A.emat) + (size_t)net * EM_SIZE;
+    const int64_t plane = (int64_t)nets * EM_SIZE;
+    stage_rows<P>(s_w2, Cfg::ROW2, src + EM_W2T, plane, N2P, K2P);
+    if (Cfg::W3LDS) stage_rows<P>(s_w3, Cfg::ROW3, src + EM_W3T, plane, N3P, N2P);
+}
+
+// Per-wave walk over (atom, 16-neighbour chunk) work items of one (type_i, type_j) pass, with the
+// next item's neighbour vector and index loaded one item ahead.
+struct ChunkWalk {
+    int i, a, np, c0;
+    bool have;
+    double px, py, pz;
+    int pj;
+    __device__ __forceinline__ bool find_atom(const EmbArgs& A, int a0, int a1, int wave, int nw, int apw, int ti,
+                                              int tj, bool skip_empty) {
+        for (; i < apw; ++i) {
+            a = a0 + wave + nw * i;
+            if (a >= a1) return false;
+            if (A.itype[a] != ti) continue;
+            np = A.nnei[(size_t)a * A.ntypes + tj];
+            if (skip_empty && np == 0) continue;
+            return true;
+        }
+        return false;
+    }
+    __device__ __forceinline__ void fetch(const EmbArgs& A, int tj, int c16) {
+        px = py = pz = 0.0;
+        pj = 0;
+        if (have && c0 + c16 < np) {
+            const size_t slot = (size_t)a * A.nc + A.off[tj] + c0 + c16;
+            const double* v = A.nl_r + 3 * slot;
+            px = v[0]; py = v[1]; pz = v[2];
+            pj = A.nl_j[slot];
+        }
+    }
 };
 
 // ---------------------------------------------------------------------------------------------
 // Forward: T_a = N_c^-1 sum_j G_j^T R_j for every atom a (G evaluated and contracted in
-// registers, never stored).
+// registers, never stored). The neighbour-type blocks of atom a are separate passes (one staged
+// net each) that add into T[a]; the same lane owns T[a][m][k] in every pass.
 // ---------------------------------------------------------------------------------------------
-template <class P, int APB, bool TAB>
-__global__ void __launch_bounds__(256) k_embed_fwd(EmbArgs A)
+template <class P, bool TAB>
+__global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
 {
     typedef typename P::acc acc;
     typedef typename P::wt wt;
     typedef typename P::accv accv;
     typedef typename P::frag frag;
-    constexpr bool W3LDS = EmbCfg<P>::W3LDS;
+    typedef EmbCfg<P> Cfg;
+    constexpr int NW = Cfg::NW, APW = Cfg::APW, APB = Cfg::APB;
+    constexpr bool W3LDS = Cfg::W3LDS;
     __shared__ acc s_vec[EVEC];
-    __shared__ __attribute__((aligned(32))) wt s_w2[P::NPL * N2P * LD2];
-    __shared__ __attribute__((aligned(32))) wt s_w3[W3LDS ? P::NPL * N3P * LD3 : 1];
-    __shared__ acc s_z1[4][16][E0 + 1];
-    __shared__ acc s_z2[4][16][E1 + 2];
-    __shared__ acc s_R[4][16][4];
-    __shared__ double s_x[4][16];
+    __shared__ __attribute__((aligned(16))) char s_w2[TAB ? 16 : N2P * Cfg::ROW2];
+    __shared__ __attribute__((aligned(16))) char s_w3[(TAB || !W3LDS) ? 16 : N3P * Cfg::ROW3];
+    __shared__ acc s_z1[TAB ? 1 : NW][16][E0 + 1];
+    __shared__ acc s_z2[TAB ? 1 : NW][16][E1 + 2];
+    __shared__ acc s_R[NW][16][4];
+    __shared__ double s_x[NW][16];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     const int a0 = blockIdx.x * APB;
@@ -224,105 +295,125 @@ __global__ void __launch_bounds__(256) k_embed_fwd(EmbArgs A)
     if (a0 >= a1) return;
     const int t_lo = A.itype[a0], t_hi = A.itype[a1 - 1];
     const int nets = A.type_one_side ? A.ntypes : A.ntypes * A.ntypes;
-    const wt* gw3 = reinterpret_cast<const wt*>(A.emat);
-    acc* Tout = reinterpret_cast<acc*>(A.T);
 
     for (int ti = t_lo; ti <= t_hi; ++ti) {
         for (int tj = 0; tj < A.ntypes; ++tj) {
             const int net = A.type_one_side ? tj : ti * A.ntypes + tj;
             __syncthreads();
-            if (!TAB) stage_net<P, W3LDS>(A, net, s_vec, s_w2, s_w3);
+            if (!TAB) stage_net<P>(A, net, s_vec, s_w2, s_w3);
             __syncthreads();
-            const wt* w3base = W3LDS ? s_w3 : gw3 + (size_t)net * EM_SIZE + EM_W3T;
-            const int w3ld = W3LDS ? LD3 : N2P;
-            const int64_t w3pl = W3LDS ? (int64_t)N3P * LD3 : (int64_t)nets * EM_SIZE;
+            const wt* gw3 = reinterpret_cast<const wt*>(A.emat) + (size_t)net * EM_SIZE + EM_W3T;
+            const int64_t gpl = (int64_t)nets * EM_SIZE;
             const acc* tab = reinterpret_cast<const acc*>(A.table) + (size_t)net * A.tab_nint * E2 * 6;
+            acc* Tout = reinterpret_cast<acc*>(A.T);
 
-            for (int a = a0 + wave; a < a1; a += 4) {
-                if (A.itype[a] != ti) continue;
-                acc Tacc[7][4];
-                for (int i = 0; i < 7; ++i) zero4(Tacc[i]);
-                const int np = A.nnei[(size_t)a * A.ntypes + tj];
-                const size_t slot0 = (size_t)a * A.nc + A.off[tj];
-                for (int c0 = 0; c0 < np; c0 += 16) {
-                    const int p = c16;
-                    const bool valid = c0 + p < np;
-                    double s = 0.0, R[4] = {0.0, 0.0, 0.0, 0.0};
-                    if (valid) {
-                        const double* v = A.nl_r + 3 * (slot0 + c0 + p);
-                        double x = v[0], y = v[1], z = v[2];
-                        double r = sqrt(x * x + y * y + z * z);
-                        double ds;
-                        switch_fn(r, A.rs, A.rc, s, ds);
-                        double sr = s / r;
-                        R[0] = s; R[1] = sr * x; R[2] = sr * y; R[3] = sr * z;
+            ChunkWalk w;
+            w.i = 0;
+            w.c0 = 0;
+            w.have = w.find_atom(A, a0, a1, wave, NW, APW, ti, tj, false);
+            w.fetch(A, tj, c16);
+            acc Tacc[7][4];
+            while (w.have) {
+                const double x = w.px, y = w.py, z = w.pz;
+                const int ca = w.a, cc0 = w.c0, cnp = w.np;
+                bool last = false;
+                w.c0 += 16;
+                if (w.c0 >= w.np) {
+                    ++w.i;
+                    w.c0 = 0;
+                    w.have = w.find_atom(A, a0, a1, wave, NW, APW, ti, tj, false);
+                    last = true;
+                }
+                w.fetch(A, tj, c16);
+                if (cc0 == 0)
+                    for (int t = 0; t < 7; ++t) zero4(Tacc[t]);
+                // T accumulates over the neighbour-type passes; read the earlier passes' sum now
+                acc Tprev[7][4];
+                if (last && tj > 0 && g == 0) {
+                    for (int tm = 0; tm < 7; ++tm) {
+                        const int m = 16 * tm + c16;
+                        for (int k = 0; k < 4; ++k) Tprev[tm][k] = m < E2 ? Tout[((size_t)ca * E2 + m) * 4 + k] : (acc)0;
                     }
+                }
+
+                const int p = c16;
+                const bool valid = cc0 + p < cnp;
+                double s = 0.0, R[4] = {0.0, 0.0, 0.0, 0.0};
+                if (valid) {
+                    double r = sqrt(x * x + y * y + z * z);
+                    double ds;
+                    switch_fn(r, A.rs, A.rc, s, ds);
+                    double sr = s / r;
+                    R[0] = s; R[1] = sr * x; R[2] = sr * y; R[3] = sr * z;
+                }
+                wave_sync();
+                if (g == 0) {
+                    for (int k = 0; k < 4; ++k) s_R[wave][p][k] = (acc)R[k];
+                    s_x[wave][p] = s;
+                }
+                if (TAB) {
                     wave_sync();
-                    if (g == 0) {
-                        for (int k = 0; k < 4; ++k) s_R[wave][p][k] = (acc)R[k];
-                        s_x[wave][p] = s;
-                    }
-                    if (TAB) {
-                        wave_sync();
-                        for (int tm = 0; tm < 7; ++tm) {
-                            const int m = 16 * tm + c16;
-                            if (m >= E2) continue;
-                            for (int r = 0; r < 4; ++r) {
-                                const int q = P::orow(g, r);
-                                double xs = s_x[wave][q];
-                                int li = (int)floor(xs / A.tab_dx);
-                                li = li < 0 ? 0 : (li >= A.tab_nint ? A.tab_nint - 1 : li);
-                                acc t = (acc)(xs - li * A.tab_dx);
-                                const acc* cf = tab + ((size_t)li * E2 + m) * 6;
-                                acc G = ((((cf[0] * t + cf[1]) * t + cf[2]) * t + cf[3]) * t + cf[4]) * t + cf[5];
-                                for (int k = 0; k < 4; ++k) Tacc[tm][k] += G * s_R[wave][q][k];
-                            }
+                    for (int tm = 0; tm < 7; ++tm) {
+                        const int m = 16 * tm + c16;
+                        if (m >= E2) continue;
+                        for (int r = 0; r < 4; ++r) {
+                            const int q = P::orow(g, r);
+                            const double xs = s_x[wave][q];
+                            int li = (int)floor(xs / A.tab_dx);
+                            li = li < 0 ? 0 : (li >= A.tab_nint ? A.tab_nint - 1 : li);
+                            const acc t = (acc)(xs - li * A.tab_dx);
+                            const acc* cf = tab + ((size_t)li * E2 + m) * 6;
+                            const acc G = ((((cf[0] * t + cf[1]) * t + cf[2]) * t + cf[3]) * t + cf[4]) * t + cf[5];
+                            for (int k = 0; k < 4; ++k) Tacc[tm][k] += G * s_R[wave][q][k];
                         }
-                        if (g == 0 && valid && (s < 0.0 || s > A.tab_nint * A.tab_dx))
-                            atomicAdd(&A.stats->table_oor, 1ull);
-                        continue;
                     }
+                    if (g == 0 && valid && (s < 0.0 || s > A.tab_nint * A.tab_dx))
+                        atomicAdd(&A.stats->table_oor, 1ull);
+                } else {
                     // layer 1 (1 -> 25) straight into the B operand of layer 2
                     frag B1[2];
                     for (int c = 0; c < 2; ++c) {
-                        acc z[4];
+                        acc zz[4];
                         for (int v = 0; v < 4; ++v) {
                             const int k = P::kidx(c, g, v);
-                            z[v] = 0;
+                            zz[v] = 0;
                             if (k < E0) {
-                                z[v] = s_vec[EV_WH1 + k] * P::act((acc)s * s_vec[EV_W1 + k] + s_vec[EV_B1 + k]);
-                                s_z1[wave][p][k] = z[v];
+                                zz[v] = s_vec[EV_WH1 + k] * P::act((acc)s * s_vec[EV_W1 + k] + s_vec[EV_B1 + k]);
+                                s_z1[wave][p][k] = zz[v];
                             }
                         }
-                        B1[c] = P::make(z[0], z[1], z[2], z[3]);
+                        B1[c] = P::make(zz[0], zz[1], zz[2], zz[3]);
                     }
                     // layer 2 (25 -> 50), transposed: pre2^T = W2^T z1^T
                     accv acc2[4];
                     for (int t = 0; t < 4; ++t) {
                         zero4(acc2[t]);
                         for (int c = 0; c < 2; ++c)
-                            P::mma(acc2[t], P::load(&s_w2[(16 * t + c16) * LD2 + 16 * c + 4 * g], N2P * LD2), B1[c]);
+                            P::mma(acc2[t], lds_frag<P>(s_w2, Cfg::ROW2, 16 * t + c16, 4 * c + g), B1[c]);
                     }
                     wave_sync();
                     frag A3[4];
                     for (int t = 0; t < 4; ++t) {
-                        acc z[4];
+                        acc zz[4];
                         for (int r = 0; r < 4; ++r) {
                             const int n = 16 * t + P::orow(g, r);
-                            z[r] = 0;
+                            zz[r] = 0;
                             if (n < E1) {
-                                z[r] = s_vec[EV_WH2 + n] * P::act(acc2[t][r] + s_vec[EV_B2 + n]) + s_z1[wave][p][n % E0];
-                                s_z2[wave][p][n] = z[r];
+                                zz[r] = s_vec[EV_WH2 + n] * P::act(acc2[t][r] + s_vec[EV_B2 + n]) + s_z1[wave][p][n % E0];
+                                s_z2[wave][p][n] = zz[r];
                             }
                         }
-                        A3[t] = P::make(z[0], z[1], z[2], z[3]);
+                        A3[t] = P::make(zz[0], zz[1], zz[2], zz[3]);
                     }
                     // layer 3 (50 -> 100), untransposed: pre3 = z2 W3
                     accv acc3[7];
                     for (int tm = 0; tm < 7; ++tm) {
                         zero4(acc3[tm]);
-                        for (int c = 0; c < 4; ++c)
-                            P::mma(acc3[tm], A3[c], P::load(&w3base[(16 * tm + c16) * w3ld + 16 * c + 4 * g], w3pl));
+                        for (int c = 0; c < 4; ++c) {
+                            const frag Bw = W3LDS ? lds_frag<P>(s_w3, Cfg::ROW3, 16 * tm + c16, 4 * c + g)
+                                                  : P::load(gw3 + (16 * tm + c16) * N2P + 16 * c + 4 * g, gpl);
+                            P::mma(acc3[tm], A3[c], Bw);
+                        }
                     }
                     wave_sync();
                     // G = w_hat tanh(pre3 + b) + {z2, z2}; contraction T += G^T R
@@ -332,27 +423,27 @@ __global__ void __launch_bounds__(256) k_embed_fwd(EmbArgs A)
                         const acc wh = s_vec[EV_WH3 + m], bb = s_vec[EV_B3 + m];
                         for (int r = 0; r < 4; ++r) {
                             const int q = P::orow(g, r);
-                            acc G = wh * P::act(acc3[tm][r] + bb) + s_z2[wave][q][m % E1];
+                            const acc G = wh * P::act(acc3[tm][r] + bb) + s_z2[wave][q][m % E1];
                             for (int k = 0; k < 4; ++k) Tacc[tm][k] += G * s_R[wave][q][k];
                         }
                     }
                 }
-                // sum the four lane groups (they hold different neighbours) and store T
-                for (int tm = 0; tm < 7; ++tm)
-                    for (int k = 0; k < 4; ++k) {
-                        acc v = Tacc[tm][k];
-                        v += __shfl_xor(v, 16);
-                        v += __shfl_xor(v, 32);
-                        Tacc[tm][k] = v;
-                    }
-                if (g == 0) {
-                    for (int tm = 0; tm < 7; ++tm) {
-                        const int m = 16 * tm + c16;
-                        if (m >= E2) continue;
-                        acc* dst = Tout + ((size_t)a * E2 + m) * 4;
+                if (last) {
+                    // sum the four lane groups (they hold different neighbours) and store T
+                    for (int tm = 0; tm < 7; ++tm)
                         for (int k = 0; k < 4; ++k) {
-                            acc v = Tacc[tm][k] * (acc)A.inv_nc;
-                            dst[k] = (tj == 0) ? v : dst[k] + v;
+                            acc v = Tacc[tm][k];
+                            v += __shfl_xor(v, 16);
+                            v += __shfl_xor(v, 32);
+                            Tacc[tm][k] = v;
+                        }
+                    if (g == 0) {
+                        for (int tm = 0; tm < 7; ++tm) {
+                            const int m = 16 * tm + c16;
+                            if (m >= E2) continue;
+                            acc* dst = Tout + ((size_t)ca * E2 + m) * 4;
+                            for (int k = 0; k < 4; ++k)
+                                dst[k] = Tacc[tm][k] * (acc)A.inv_nc + (tj > 0 ? Tprev[tm][k] : (acc)0);
                         }
                     }
                 }
@@ -367,23 +458,26 @@ __global__ void __launch_bounds__(256) k_embed_fwd(EmbArgs A)
 //   g_ij = dE/dr_ij = [(dR_0 + dE/ds) s' + q (s' - s/r)] r^ + (s/r) dR_{1:3},  q = dR_{1:3} . r^,
 //   F_i += g_ij, F_j -= g_ij (FP64 atomics), Xi_ab -= g_ij,a r_ij,b (FP64, per-block partials).
 // ---------------------------------------------------------------------------------------------
-template <class P, int APB, bool TAB>
-__global__ void __launch_bounds__(256) k_embed_bwd(EmbArgs A)
+template <class P, bool TAB>
+__global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
 {
     typedef typename P::acc acc;
     typedef typename P::wt wt;
     typedef typename P::accv accv;
     typedef typename P::frag frag;
-    constexpr bool W3LDS = EmbCfg<P>::W3LDS;
+    typedef EmbCfg<P> Cfg;
+    constexpr int NW = Cfg::NW, APW = Cfg::APW, APB = Cfg::APB;
+    constexpr bool W3LDS = Cfg::W3LDS;
+    constexpr int DTL = (E2 * 4 + 63) / 64;     // dT values per lane
     __shared__ acc s_vec[EVEC];
-    __shared__ __attribute__((aligned(32))) wt s_w2[P::NPL * N2P * LD2];
-    __shared__ __attribute__((aligned(32))) wt s_w3[W3LDS ? P::NPL * N3P * LD3 : 1];
-    __shared__ acc s_z1[4][16][E0 + 1];
-    __shared__ acc s_z1d[4][16][E0 + 1];
-    __shared__ acc s_z2[4][16][E1 + 2];
-    __shared__ acc s_z2d[4][16][E1 + 2];
-    __shared__ acc s_dT[4][E2][4];
-    __shared__ double s_vir[4][9];
+    __shared__ __attribute__((aligned(16))) char s_w2[TAB ? 16 : N2P * Cfg::ROW2];
+    __shared__ __attribute__((aligned(16))) char s_w3[(TAB || !W3LDS) ? 16 : N3P * Cfg::ROW3];
+    __shared__ acc s_z1[TAB ? 1 : NW][16][E0 + 1];
+    __shared__ acc s_z1d[TAB ? 1 : NW][16][E0 + 1];
+    __shared__ acc s_z2[TAB ? 1 : NW][16][E1 + 2];
+    __shared__ acc s_z2d[TAB ? 1 : NW][16][E1 + 2];
+    __shared__ __attribute__((aligned(16))) acc s_dT[NW][E2][4];
+    __shared__ double s_vir[NW][9];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     const int a0 = blockIdx.x * APB;
@@ -391,7 +485,6 @@ __global__ void __launch_bounds__(256) k_embed_bwd(EmbArgs A)
     double vir[9];
     for (int k = 0; k < 9; ++k) vir[k] = 0.0;
     const int nets = A.type_one_side ? A.ntypes : A.ntypes * A.ntypes;
-    const wt* gw3 = reinterpret_cast<const wt*>(A.emat);
     const acc* dTin = reinterpret_cast<const acc*>(A.dT);
     const int t_lo = a0 < a1 ? A.itype[a0] : 0, t_hi = a0 < a1 ? A.itype[a1 - 1] : -1;
 
@@ -399,167 +492,194 @@ __global__ void __launch_bounds__(256) k_embed_bwd(EmbArgs A)
         for (int tj = 0; tj < A.ntypes; ++tj) {
             const int net = A.type_one_side ? tj : ti * A.ntypes + tj;
             __syncthreads();
-            if (!TAB) stage_net<P, W3LDS>(A, net, s_vec, s_w2, s_w3);
+            if (!TAB) stage_net<P>(A, net, s_vec, s_w2, s_w3);
             __syncthreads();
-            const wt* w3base = W3LDS ? s_w3 : gw3 + (size_t)net * EM_SIZE + EM_W3T;
-            const int w3ld = W3LDS ? LD3 : N2P;
-            const int64_t w3pl = W3LDS ? (int64_t)N3P * LD3 : (int64_t)nets * EM_SIZE;
+            const wt* gw3 = reinterpret_cast<const wt*>(A.emat) + (size_t)net * EM_SIZE + EM_W3T;
+            const int64_t gpl = (int64_t)nets * EM_SIZE;
             const acc* tab = reinterpret_cast<const acc*>(A.table) + (size_t)net * A.tab_nint * E2 * 6;
 
-            for (int a = a0 + wave; a < a1; a += 4) {
-                if (A.itype[a] != ti) continue;
-                const int np = A.nnei[(size_t)a * A.ntypes + tj];
-                if (np == 0) continue;
-                wave_sync();
-                for (int i = lane; i < E2 * 4; i += 64) s_dT[wave][i >> 2][i & 3] = dTin[(size_t)a * E2 * 4 + i];
-                wave_sync();
-                const size_t slot0 = (size_t)a * A.nc + A.off[tj];
-                double Fi[3] = {0.0, 0.0, 0.0};
-                for (int c0 = 0; c0 < np; c0 += 16) {
-                    const int p = c16;
-                    const bool valid = c0 + p < np;
-                    double x = 0.0, y = 0.0, z = 0.0, r = 1.0, s = 0.0, ds = 0.0;
-                    if (valid) {
-                        const double* v = A.nl_r + 3 * (slot0 + c0 + p);
-                        x = v[0]; y = v[1]; z = v[2];
-                        r = sqrt(x * x + y * y + z * z);
-                        switch_fn(r, A.rs, A.rc, s, ds);
+            ChunkWalk w;
+            w.i = 0;
+            w.c0 = 0;
+            w.have = w.find_atom(A, a0, a1, wave, NW, APW, ti, tj, true);
+            w.fetch(A, tj, c16);
+            acc pdT[DTL];
+            for (int q = 0; q < DTL; ++q) {
+                const int e = lane + 64 * q;
+                pdT[q] = (w.have && e < E2 * 4) ? dTin[(size_t)w.a * E2 * 4 + e] : (acc)0;
+            }
+            double Fi[3] = {0.0, 0.0, 0.0};
+            while (w.have) {
+                const double x = w.px, y = w.py, z = w.pz;
+                const int jn = w.pj;
+                const int ca = w.a, cc0 = w.c0, cnp = w.np;
+                bool last = false;
+                w.c0 += 16;
+                if (w.c0 >= w.np) {
+                    ++w.i;
+                    w.c0 = 0;
+                    w.have = w.find_atom(A, a0, a1, wave, NW, APW, ti, tj, true);
+                    last = true;
+                }
+                w.fetch(A, tj, c16);
+                if (cc0 == 0) {
+                    // the prefetched dT of this atom goes to LDS; the next atom's is requested
+                    wave_sync();
+                    for (int q = 0; q < DTL; ++q) {
+                        const int e = lane + 64 * q;
+                        if (e < E2 * 4) s_dT[wave][e >> 2][e & 3] = pdT[q];
                     }
-                    const double ir = 1.0 / r;
-                    const double ux = x * ir, uy = y * ir, uz = z * ir, sr = s * ir;
-                    const acc Ra[4] = {(acc)s, (acc)(sr * x), (acc)(sr * y), (acc)(sr * z)};
-                    acc dR[4] = {0, 0, 0, 0}, H[4] = {0, 0, 0, 0};
-                    if (TAB) {
-                        int li = (int)floor(s / A.tab_dx);
-                        li = li < 0 ? 0 : (li >= A.tab_nint ? A.tab_nint - 1 : li);
-                        const acc t = (acc)(s - li * A.tab_dx);
-                        for (int tm = 0; tm < 7; ++tm)
-                            for (int rr = 0; rr < 4; ++rr) {
-                                const int m = 16 * tm + P::orow(g, rr);
-                                if (m >= E2) continue;
-                                const acc* cf = tab + ((size_t)li * E2 + m) * 6;
-                                acc G = ((((cf[0] * t + cf[1]) * t + cf[2]) * t + cf[3]) * t + cf[4]) * t + cf[5];
-                                acc Gd = (((5 * cf[0] * t + 4 * cf[1]) * t + 3 * cf[2]) * t + 2 * cf[3]) * t + cf[4];
-                                for (int k = 0; k < 4; ++k) {
-                                    acc dt = s_dT[wave][m][k];
-                                    dR[k] += G * dt;
-                                    H[k] += Gd * dt;
-                                }
+                    wave_sync();
+                }
+                if (last) {
+                    for (int q = 0; q < DTL; ++q) {
+                        const int e = lane + 64 * q;
+                        pdT[q] = (w.have && e < E2 * 4) ? dTin[(size_t)w.a * E2 * 4 + e] : (acc)0;
+                    }
+                }
+
+                const int p = c16;
+                const bool valid = cc0 + p < cnp;
+                double r = 1.0, s = 0.0, ds = 0.0;
+                if (valid) {
+                    r = sqrt(x * x + y * y + z * z);
+                    switch_fn(r, A.rs, A.rc, s, ds);
+                }
+                const double ir = 1.0 / r;
+                const double ux = x * ir, uy = y * ir, uz = z * ir, sr = s * ir;
+                const acc Ra[4] = {(acc)s, (acc)(sr * x), (acc)(sr * y), (acc)(sr * z)};
+                acc dR[4] = {0, 0, 0, 0}, H[4] = {0, 0, 0, 0};
+                if (TAB) {
+                    int li = (int)floor(s / A.tab_dx);
+                    li = li < 0 ? 0 : (li >= A.tab_nint ? A.tab_nint - 1 : li);
+                    const acc t = (acc)(s - li * A.tab_dx);
+                    for (int tm = 0; tm < 7; ++tm)
+                        for (int rr = 0; rr < 4; ++rr) {
+                            const int m = 16 * tm + P::orow(g, rr);
+                            if (m >= E2) continue;
+                            const acc* cf = tab + ((size_t)li * E2 + m) * 6;
+                            const acc G = ((((cf[0] * t + cf[1]) * t + cf[2]) * t + cf[3]) * t + cf[4]) * t + cf[5];
+                            const acc Gd = (((5 * cf[0] * t + 4 * cf[1]) * t + 3 * cf[2]) * t + 2 * cf[3]) * t + cf[4];
+                            for (int k = 0; k < 4; ++k) {
+                                const acc dt = s_dT[wave][m][k];
+                                dR[k] += G * dt;
+                                H[k] += Gd * dt;
                             }
-                    } else {
-                        wave_sync();
-                        // layer 1 and its derivative d/ds
-                        frag B1[2], B1d[2];
+                        }
+                } else {
+                    wave_sync();
+                    // layer 1 and its derivative d/ds
+                    frag B1[2], B1d[2];
+                    for (int c = 0; c < 2; ++c) {
+                        acc zz[4], zd[4];
+                        for (int v = 0; v < 4; ++v) {
+                            const int k = P::kidx(c, g, v);
+                            zz[v] = 0;
+                            zd[v] = 0;
+                            if (k < E0) {
+                                const acc w1 = s_vec[EV_W1 + k], wh = s_vec[EV_WH1 + k];
+                                const acc t1 = P::act((acc)s * w1 + s_vec[EV_B1 + k]);
+                                zz[v] = wh * t1;
+                                zd[v] = wh * (1 - t1 * t1) * w1;
+                                s_z1[wave][p][k] = zz[v];
+                                s_z1d[wave][p][k] = zd[v];
+                            }
+                        }
+                        B1[c] = P::make(zz[0], zz[1], zz[2], zz[3]);
+                        B1d[c] = P::make(zd[0], zd[1], zd[2], zd[3]);
+                    }
+                    accv acc2[4], acc2d[4];
+                    for (int t = 0; t < 4; ++t) {
+                        zero4(acc2[t]);
+                        zero4(acc2d[t]);
                         for (int c = 0; c < 2; ++c) {
-                            acc zz[4], zd[4];
-                            for (int v = 0; v < 4; ++v) {
-                                const int k = P::kidx(c, g, v);
-                                zz[v] = 0;
-                                zd[v] = 0;
-                                if (k < E0) {
-                                    const acc w1 = s_vec[EV_W1 + k], wh = s_vec[EV_WH1 + k];
-                                    const acc t1 = P::act((acc)s * w1 + s_vec[EV_B1 + k]);
-                                    zz[v] = wh * t1;
-                                    zd[v] = wh * (1 - t1 * t1) * w1;
-                                    s_z1[wave][p][k] = zz[v];
-                                    s_z1d[wave][p][k] = zd[v];
-                                }
-                            }
-                            B1[c] = P::make(zz[0], zz[1], zz[2], zz[3]);
-                            B1d[c] = P::make(zd[0], zd[1], zd[2], zd[3]);
+                            const frag W = lds_frag<P>(s_w2, Cfg::ROW2, 16 * t + c16, 4 * c + g);
+                            P::mma(acc2[t], W, B1[c]);
+                            P::mma(acc2d[t], W, B1d[c]);
                         }
-                        accv acc2[4], acc2d[4];
-                        for (int t = 0; t < 4; ++t) {
-                            zero4(acc2[t]);
-                            zero4(acc2d[t]);
-                            for (int c = 0; c < 2; ++c) {
-                                frag W = P::load(&s_w2[(16 * t + c16) * LD2 + 16 * c + 4 * g], N2P * LD2);
-                                P::mma(acc2[t], W, B1[c]);
-                                P::mma(acc2d[t], W, B1d[c]);
-                            }
-                        }
-                        wave_sync();
-                        frag B3[4], B3d[4];
-                        for (int t = 0; t < 4; ++t) {
-                            acc zz[4], zd[4];
-                            for (int rr = 0; rr < 4; ++rr) {
-                                const int n = 16 * t + P::orow(g, rr);
-                                zz[rr] = 0;
-                                zd[rr] = 0;
-                                if (n < E1) {
-                                    const acc t2 = P::act(acc2[t][rr] + s_vec[EV_B2 + n]);
-                                    const acc wh = s_vec[EV_WH2 + n];
-                                    zz[rr] = wh * t2 + s_z1[wave][p][n % E0];
-                                    zd[rr] = wh * (1 - t2 * t2) * acc2d[t][rr] + s_z1d[wave][p][n % E0];
-                                    s_z2[wave][p][n] = zz[rr];
-                                    s_z2d[wave][p][n] = zd[rr];
-                                }
-                            }
-                            B3[t] = P::make(zz[0], zz[1], zz[2], zz[3]);
-                            B3d[t] = P::make(zd[0], zd[1], zd[2], zd[3]);
-                        }
-                        // layer 3 transposed: one neighbour per lane column
-                        accv acc3[7], acc3d[7];
-                        for (int tm = 0; tm < 7; ++tm) {
-                            zero4(acc3[tm]);
-                            zero4(acc3d[tm]);
-                            for (int c = 0; c < 4; ++c) {
-                                frag W = P::load(&w3base[(16 * tm + c16) * w3ld + 16 * c + 4 * g], w3pl);
-                                P::mma(acc3[tm], W, B3[c]);
-                                P::mma(acc3d[tm], W, B3d[c]);
-                            }
-                        }
-                        wave_sync();
-                        for (int tm = 0; tm < 7; ++tm)
-                            for (int rr = 0; rr < 4; ++rr) {
-                                const int m = 16 * tm + P::orow(g, rr);
-                                if (m >= E2) continue;
-                                const acc t3 = P::act(acc3[tm][rr] + s_vec[EV_B3 + m]);
-                                const acc wh = s_vec[EV_WH3 + m];
-                                const acc G = wh * t3 + s_z2[wave][p][m % E1];
-                                const acc Gd = wh * (1 - t3 * t3) * acc3d[tm][rr] + s_z2d[wave][p][m % E1];
-                                for (int k = 0; k < 4; ++k) {
-                                    const acc dt = s_dT[wave][m][k];
-                                    dR[k] += G * dt;
-                                    H[k] += Gd * dt;
-                                }
-                            }
                     }
-                    for (int k = 0; k < 4; ++k) {
-                        dR[k] += __shfl_xor(dR[k], 16);
-                        dR[k] += __shfl_xor(dR[k], 32);
-                        H[k] += __shfl_xor(H[k], 16);
-                        H[k] += __shfl_xor(H[k], 32);
+                    wave_sync();
+                    frag B3[4], B3d[4];
+                    for (int t = 0; t < 4; ++t) {
+                        acc zz[4], zd[4];
+                        for (int rr = 0; rr < 4; ++rr) {
+                            const int n = 16 * t + P::orow(g, rr);
+                            zz[rr] = 0;
+                            zd[rr] = 0;
+                            if (n < E1) {
+                                const acc t2 = P::act(acc2[t][rr] + s_vec[EV_B2 + n]);
+                                const acc wh = s_vec[EV_WH2 + n];
+                                zz[rr] = wh * t2 + s_z1[wave][p][n % E0];
+                                zd[rr] = wh * (1 - t2 * t2) * acc2d[t][rr] + s_z1d[wave][p][n % E0];
+                                s_z2[wave][p][n] = zz[rr];
+                                s_z2d[wave][p][n] = zd[rr];
+                            }
+                        }
+                        B3[t] = P::make(zz[0], zz[1], zz[2], zz[3]);
+                        B3d[t] = P::make(zd[0], zd[1], zd[2], zd[3]);
                     }
-                    if (valid && g == 0) {
-                        const double inc = A.inv_nc;
-                        const double d0 = inc * (double)dR[0], d1 = inc * (double)dR[1];
-                        const double d2 = inc * (double)dR[2], d3 = inc * (double)dR[3];
-                        const double dEds = inc * ((double)H[0] * (double)Ra[0] + (double)H[1] * (double)Ra[1] +
-                                                   (double)H[2] * (double)Ra[2] + (double)H[3] * (double)Ra[3]);
-                        const double q = d1 * ux + d2 * uy + d3 * uz;
-                        const double rad = (d0 + dEds) * ds + q * (ds - sr);
-                        const double gx = rad * ux + sr * d1, gy = rad * uy + sr * d2, gz = rad * uz + sr * d3;
-                        const int j = A.nl_j[slot0 + c0 + p];
-                        unsafeAtomicAdd(&A.F[3 * (size_t)j], -gx);
-                        unsafeAtomicAdd(&A.F[3 * (size_t)j + 1], -gy);
-                        unsafeAtomicAdd(&A.F[3 * (size_t)j + 2], -gz);
-                        Fi[0] += gx; Fi[1] += gy; Fi[2] += gz;
-                        vir[0] -= gx * x; vir[1] -= gx * y; vir[2] -= gx * z;
-                        vir[3] -= gy * x; vir[4] -= gy * y; vir[5] -= gy * z;
-                        vir[6] -= gz * x; vir[7] -= gz * y; vir[8] -= gz * z;
+                    // layer 3 transposed: one neighbour per lane column
+                    accv acc3[7], acc3d[7];
+                    for (int tm = 0; tm < 7; ++tm) {
+                        zero4(acc3[tm]);
+                        zero4(acc3d[tm]);
+                        for (int c = 0; c < 4; ++c) {
+                            const frag W = W3LDS ? lds_frag<P>(s_w3, Cfg::ROW3, 16 * tm + c16, 4 * c + g)
+                                                 : P::load(gw3 + (16 * tm + c16) * N2P + 16 * c + 4 * g, gpl);
+                            P::mma(acc3[tm], W, B3[c]);
+                            P::mma(acc3d[tm], W, B3d[c]);
+                        }
                     }
+                    wave_sync();
+                    for (int tm = 0; tm < 7; ++tm)
+                        for (int rr = 0; rr < 4; ++rr) {
+                            const int m = 16 * tm + P::orow(g, rr);
+                            if (m >= E2) continue;
+                            const acc t3 = P::act(acc3[tm][rr] + s_vec[EV_B3 + m]);
+                            const acc wh = s_vec[EV_WH3 + m];
+                            const acc G = wh * t3 + s_z2[wave][p][m % E1];
+                            const acc Gd = wh * (1 - t3 * t3) * acc3d[tm][rr] + s_z2d[wave][p][m % E1];
+                            const acc* dt = s_dT[wave][m];
+                            dR[0] += G * dt[0]; dR[1] += G * dt[1]; dR[2] += G * dt[2]; dR[3] += G * dt[3];
+                            H[0] += Gd * dt[0]; H[1] += Gd * dt[1]; H[2] += Gd * dt[2]; H[3] += Gd * dt[3];
+                        }
                 }
-                for (int k = 0; k < 3; ++k) {
-                    double v = Fi[k];
-                    v += __shfl_xor(v, 1);
-                    v += __shfl_xor(v, 2);
-                    v += __shfl_xor(v, 4);
-                    v += __shfl_xor(v, 8);
-                    Fi[k] = v;
+                for (int k = 0; k < 4; ++k) {
+                    dR[k] += __shfl_xor(dR[k], 16);
+                    dR[k] += __shfl_xor(dR[k], 32);
+                    H[k] += __shfl_xor(H[k], 16);
+                    H[k] += __shfl_xor(H[k], 32);
                 }
-                if (lane == 0)
-                    for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&A.F[3 * (size_t)a + k], Fi[k]);
+                if (valid && g == 0) {
+                    const double inc = A.inv_nc;
+                    const double d0 = inc * (double)dR[0], d1 = inc * (double)dR[1];
+                    const double d2 = inc * (double)dR[2], d3 = inc * (double)dR[3];
+                    const double dEds = inc * ((double)H[0] * (double)Ra[0] + (double)H[1] * (double)Ra[1] +
+                                               (double)H[2] * (double)Ra[2] + (double)H[3] * (double)Ra[3]);
+                    const double q = d1 * ux + d2 * uy + d3 * uz;
+                    const double rad = (d0 + dEds) * ds + q * (ds - sr);
+                    const double gx = rad * ux + sr * d1, gy = rad * uy + sr * d2, gz = rad * uz + sr * d3;
+                    unsafeAtomicAdd(&A.F[3 * (size_t)jn], -gx);
+                    unsafeAtomicAdd(&A.F[3 * (size_t)jn + 1], -gy);
+                    unsafeAtomicAdd(&A.F[3 * (size_t)jn + 2], -gz);
+                    Fi[0] += gx; Fi[1] += gy; Fi[2] += gz;
+                    vir[0] -= gx * x; vir[1] -= gx * y; vir[2] -= gx * z;
+                    vir[3] -= gy * x; vir[4] -= gy * y; vir[5] -= gy * z;
+                    vir[6] -= gz * x; vir[7] -= gz * y; vir[8] -= gz * z;
+                }
+                if (last) {
+                    for (int k = 0; k < 3; ++k) {
+                        double v = Fi[k];
+                        v += __shfl_xor(v, 1);
+                        v += __shfl_xor(v, 2);
+                        v += __shfl_xor(v, 4);
+                        v += __shfl_xor(v, 8);
+                        Fi[k] = v;
+                    }
+                    if (lane == 0)
+                        for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&A.F[3 * (size_t)ca + k], Fi[k]);
+                    Fi[0] = Fi[1] = Fi[2] = 0.0;
+                }
             }
         }
     }
@@ -571,9 +691,11 @@ __global__ void __launch_bounds__(256) k_embed_bwd(EmbArgs A)
     if (lane == 0)
         for (int k = 0; k < 9; ++k) s_vir[wave][k] = vir[k];
     __syncthreads();
-    if (threadIdx.x < 9)
-        A.vir_part[9 * (size_t)blockIdx.x + threadIdx.x] =
-            s_vir[0][threadIdx.x] + s_vir[1][threadIdx.x] + s_vir[2][threadIdx.x] + s_vir[3][threadIdx.x];
+    if (threadIdx.x < 9) {
+        double v = 0.0;
+        for (int q = 0; q < NW; ++q) v += s_vir[q][threadIdx.x];
+        A.vir_part[9 * (size_t)blockIdx.x + threadIdx.x] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -683,6 +805,7 @@ __global__ void __launch_bounds__(256) k_fit(FitArgs A)
     const bool real = atom < A.natoms;
     const int arow = real ? atom : a0;              // rows past the end read a valid row
     const acc* Ta = Tin + (size_t)arow * E2 * 4;
+    auto T_at = [&](int idx) { return Ta[idx]; };
     acc* actrow = act + (size_t)arow * 3 * FW;
 
     for (int ti = t_lo; ti <= t_hi; ++ti) {
@@ -695,7 +818,7 @@ __global__ void __launch_bounds__(256) k_fit(FitArgs A)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) Tn[v][k] = Ta[P::kidx(0, g, v) * 4 + k];
+            for (int k = 0; k < 4; ++k) Tn[v][k] = T_at(P::kidx(0, g, v) * 4 + k);
 
         acc h[15][4];
         accv accs[15];
@@ -716,7 +839,7 @@ __global__ void __launch_bounds__(256) k_fit(FitArgs A)
 #pragma unroll
                 for (int sub = 0; sub < KC1 / 16; ++sub) {
                     const int m = c * (KC1 / 16) + sub;      // K-chunk of 16 = row m of D
-                    const acc T0 = Ta[m * 4 + 0], T1 = Ta[m * 4 + 1], T2 = Ta[m * 4 + 2], T3 = Ta[m * 4 + 3];
+                    const acc T0 = T_at(m * 4 + 0), T1 = T_at(m * 4 + 1), T2 = T_at(m * 4 + 2), T3 = T_at(m * 4 + 3);
                     acc d[4];
 #pragma unroll
                     for (int v = 0; v < 4; ++v) d[v] = T0 * Tn[v][0] + T1 * Tn[v][1] + T2 * Tn[v][2] + T3 * Tn[v][3];
@@ -842,7 +965,7 @@ __global__ void __launch_bounds__(256) k_fit(FitArgs A)
                 zero4(dd);
 #pragma unroll
                 for (int c = 0; c < 15; ++c) P::mma(dd, fit_afrag<P, SD::ROWB>(buf, c16, 4 * c + g), G1[c]);
-                const acc T0 = Ta[m * 4 + 0], T1 = Ta[m * 4 + 1], T2 = Ta[m * 4 + 2], T3 = Ta[m * 4 + 3];
+                const acc T0 = T_at(m * 4 + 0), T1 = T_at(m * 4 + 1), T2 = T_at(m * 4 + 2), T3 = T_at(m * 4 + 3);
                 acc part[4] = {0, 0, 0, 0};
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -888,39 +1011,38 @@ __global__ void __launch_bounds__(256) k_fit(FitArgs A)
 // ---------------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------------
-constexpr int APB_EMB = 16;
-
-int embed_atoms_per_block(int) { return APB_EMB; }
+int embed_atoms_per_block(int precision)
+{
+    return precision == 0 ? EmbCfg<PF64>::APB : EmbCfg<PMIX>::APB;
+}
 int fit_atoms_per_block(int) { return FIT_AF; }
+
+template <class P>
+static void launch_embed(bool fwd, bool table, const EmbArgs& a, hipStream_t s)
+{
+    typedef EmbCfg<P> Cfg;
+    dim3 grid((a.natoms + Cfg::APB - 1) / Cfg::APB), block(Cfg::NW * 64);
+    if (fwd) {
+        if (table) hipLaunchKernelGGL((k_embed_fwd<P, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_embed_fwd<P, false>), grid, block, 0, s, a);
+    } else {
+        if (table) hipLaunchKernelGGL((k_embed_bwd<P, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_embed_bwd<P, false>), grid, block, 0, s, a);
+    }
+}
 
 void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s)
 {
-    dim3 grid((a.natoms + APB_EMB - 1) / APB_EMB), block(256);
-    if (precision == 0) {
-        if (table) hipLaunchKernelGGL((k_embed_fwd<PF64, APB_EMB, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_embed_fwd<PF64, APB_EMB, false>), grid, block, 0, s, a);
-    } else if (precision == 1) {
-        if (table) hipLaunchKernelGGL((k_embed_fwd<PMIX, APB_EMB, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_embed_fwd<PMIX, APB_EMB, false>), grid, block, 0, s, a);
-    } else {
-        if (table) hipLaunchKernelGGL((k_embed_fwd<PBF16, APB_EMB, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_embed_fwd<PBF16, APB_EMB, false>), grid, block, 0, s, a);
-    }
+    if (precision == 0) launch_embed<PF64>(true, table, a, s);
+    else if (precision == 1) launch_embed<PMIX>(true, table, a, s);
+    else launch_embed<PBF16>(true, table, a, s);
 }
 
 void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s)
 {
-    dim3 grid((a.natoms + APB_EMB - 1) / APB_EMB), block(256);
-    if (precision == 0) {
-        if (table) hipLaunchKernelGGL((k_embed_bwd<PF64, APB_EMB, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_embed_bwd<PF64, APB_EMB, false>), grid, block, 0, s, a);
-    } else if (precision == 1) {
-        if (table) hipLaunchKernelGGL((k_embed_bwd<PMIX, APB_EMB, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_embed_bwd<PMIX, APB_EMB, false>), grid, block, 0, s, a);
-    } else {
-        if (table) hipLaunchKernelGGL((k_embed_bwd<PBF16, APB_EMB, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_embed_bwd<PBF16, APB_EMB, false>), grid, block, 0, s, a);
-    }
+    if (precision == 0) launch_embed<PF64>(false, table, a, s);
+    else if (precision == 1) launch_embed<PMIX>(false, table, a, s);
+    else launch_embed<PBF16>(false, table, a, s);
 }
 
 void launch_fit(int precision, const FitArgs& a, hipStream_t s)

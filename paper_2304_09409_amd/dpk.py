@@ -43,6 +43,13 @@ def lib():
     """Load libdpk.so (once)."""
     global _lib
     if _lib is None:
+        # PyTorch ships its own HIP runtime and links it by an unversioned name; load it first so
+        # that libdpk.so binds to the same runtime (one HIP runtime per process: torch's device
+        # pointers and streams are then valid for the library, and torch can still initialise).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2304_09409_amd.build`")
         L = C.CDLL(LIB_PATH)
@@ -214,3 +221,120 @@ class Context:
         dT = np.empty((natoms, 100, 4))
         _check(lib().dpk_debug_descriptor(self.handle, _dp(T), _dp(dT)))
         return T, dT
+
+
+# ------------------------------------------------------------------------------------------
+# Serving
+# ------------------------------------------------------------------------------------------
+class _Frame(C.Structure):
+    _fields_ = [("natoms", C.c_int64), ("coord", C.POINTER(C.c_double)), ("atype", C.POINTER(C.c_int32)),
+                ("box", C.POINTER(C.c_double)), ("energy", C.POINTER(C.c_double)),
+                ("force", C.POINTER(C.c_double)), ("virial", C.POINTER(C.c_double)),
+                ("atom_energy", C.POINTER(C.c_double)), ("simulation", C.c_int64)]
+
+
+class _Counters(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("peak_bytes", C.c_int64), ("budget_waits", C.c_int64), ("slot_reuse", C.c_int64)]
+
+
+def _server_sigs(L):
+    if getattr(L, "_server_sigs", False):
+        return
+    vp, dp = C.c_void_p, C.POINTER(C.c_double)
+    i32p, i64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    L.dpk_server_create.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_size_t, C.POINTER(vp)]
+    L.dpk_server_submit.argtypes = [vp, C.POINTER(_Frame), C.POINTER(C.c_uint64)]
+    L.dpk_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int)]
+    L.dpk_server_wait.argtypes = [vp, C.c_uint64]
+    L.dpk_server_times.argtypes = [vp, C.c_uint64, i64p]
+    L.dpk_server_stats.argtypes = [vp, C.POINTER(_Counters)]
+    L.dpk_server_free.argtypes = [vp]
+    L.dpk_server_free.restype = None
+    L.dpk_admit_plan.argtypes = [C.c_int, i32p, i64p, i64p, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L._server_sigs = True
+
+
+def admit_plan(busy, slot_bytes, slot_sim, need, simulation=-1, budget=0, model_bytes=0):
+    """The server's admission rule (pure host function): returns (code, slot, release_idle)."""
+    L = lib()
+    _server_sigs(L)
+    b = np.ascontiguousarray(busy, dtype=np.int32)
+    sb = np.ascontiguousarray(slot_bytes, dtype=np.int64)
+    ss = np.ascontiguousarray(slot_sim, dtype=np.int64)
+    slot, rel = C.c_int32(), C.c_int32()
+    rc = L.dpk_admit_plan(len(b), b.ctypes.data_as(C.POINTER(C.c_int32)), sb.ctypes.data_as(C.POINTER(C.c_int64)),
+                          ss.ctypes.data_as(C.POINTER(C.c_int64)), need, simulation, budget, model_bytes,
+                          C.byref(slot), C.byref(rel))
+    return rc, slot.value, bool(rel.value)
+
+
+class Ticket:
+    """A submitted frame: keeps its host buffers alive until the result is read."""
+
+    def __init__(self, server, tid, keep, out):
+        self.server, self.id, self._keep, self.out = server, tid, keep, out
+
+    def done(self) -> int:
+        return self.server.poll(self)
+
+    def result(self) -> dict:
+        self.server.wait(self)
+        return self.out
+
+
+class Server:
+    """Continuous-batching server over nslots device slots (see dpk_server_* in include/dpk.h)."""
+
+    def __init__(self, model: Model, device: int = 0, precision: str = "mixed", nslots: int = 4,
+                 budget_bytes: int = 0):
+        L = lib()
+        _server_sigs(L)
+        self.model = model
+        h = C.c_void_p()
+        _check(L.dpk_server_create(model.handle, device, PRECISIONS[precision], nslots, budget_bytes, C.byref(h)))
+        self.handle = h
+
+    def submit(self, coord, atype, box=None, simulation: int = -1, atom_energy: bool = False) -> Ticket:
+        coord = np.ascontiguousarray(coord, dtype=np.float64)
+        atype = np.ascontiguousarray(atype, dtype=np.int32)
+        n = coord.shape[0]
+        box = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(9)
+        e, f, v = np.zeros(1), np.zeros((n, 3)), np.zeros(9)
+        ae = np.zeros(n) if atom_energy else None
+        fr = _Frame(n, _dp(coord), _ip(atype), _dp(box), _dp(e), _dp(f), _dp(v), _dp(ae), simulation)
+        t = C.c_uint64()
+        _check(lib().dpk_server_submit(self.handle, C.byref(fr), C.byref(t)))
+        out = {"energy_buf": e, "force": f, "virial_buf": v, "atom_energy": ae}
+        return Ticket(self, t.value, (coord, atype, box), out)
+
+    def poll(self, ticket: Ticket) -> int:
+        d = C.c_int()
+        _check(lib().dpk_server_poll(self.handle, ticket.id, C.byref(d)))
+        return d.value
+
+    def wait(self, ticket: Ticket):
+        _check(lib().dpk_server_wait(self.handle, ticket.id))
+        o = ticket.out
+        o["energy"] = float(o["energy_buf"][0])
+        o["virial"] = o["virial_buf"].reshape(3, 3)
+        return o
+
+    def times(self, ticket: Ticket):
+        t = np.zeros(3, dtype=np.int64)
+        _check(lib().dpk_server_times(self.handle, ticket.id, t.ctypes.data_as(C.POINTER(C.c_int64))))
+        return t
+
+    def stats(self) -> dict:
+        c = _Counters()
+        _check(lib().dpk_server_stats(self.handle, C.byref(c)))
+        return {k: getattr(c, k) for k, _ in _Counters._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.dpk_server_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()

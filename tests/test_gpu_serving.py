@@ -1,0 +1,126 @@
+"""Serving: frames of uneven size from several simulations admitted into device slots.
+
+* every frame's result in the mix equals the same frame computed alone (same precision), to the
+  reordering of FP64 force atomics (1e-12 eV/A absolute, 1e-12 relative energy);
+* FP64 server results match the CPU oracle within 1e-10 eV/A;
+* under an HBM budget that holds about two frames, admission waits, the device footprint never
+  exceeds the budget, and every frame completes with the same result;
+* a bad frame fails alone (its error code), and a frame larger than the budget is refused.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2304_09409_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dpk():
+    from paper_2304_09409_amd import dpk as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def model(dpk):
+    return dpk.Model(synth.SERVE_MODEL, synth.serve_params())
+
+
+def _frames(nreq, seed):
+    sizes, ntypes, seeds = synth.serving_stream(nreq, seed)
+    return [synth.serving_frame(int(n), int(s), int(nt)) for n, nt, s in zip(sizes, ntypes, seeds)]
+
+
+def _compare(a, b, n):
+    df = np.abs(a["force"] - b["force"]).max()
+    de = abs(a["energy"] - b["energy"])
+    assert df <= 1e-12, df
+    assert de <= 1e-12 * max(1.0, abs(b["energy"])), de
+    assert np.abs(a["virial"] - b["virial"]).max() <= 1e-10 * max(1.0, n / 100)
+
+
+def test_mix_equals_alone(dpk, model):
+    say("serving mixed: 24 frames, 4 slots, results equal alone")
+    fr = _frames(24, 11)
+    ctx = dpk.Context(model, precision="mixed")
+    alone = [ctx.compute(c, t, b) for c, t, b in fr]
+    ctx.close()
+    srv = dpk.Server(model, precision="mixed", nslots=4)
+    tickets = [srv.submit(c, t, b, simulation=k % 6) for k, (c, t, b) in enumerate(fr)]
+    outs = [tk.result() for tk in tickets]
+    for (c, t, b), a, o in zip(fr, alone, outs):
+        _compare(o, a, len(t))
+    st = srv.stats()
+    print(f"  stats {st}", flush=True)
+    assert st["completed"] == 24 and st["failed"] == 0
+    srv.close()
+
+
+def test_fp64_server_matches_oracle(dpk, model):
+    from oracle import Oracle
+    say("serving fp64 vs oracle")
+    o = Oracle(synth.SERVE_MODEL, synth.serve_params())
+    fr = _frames(5, 3)
+    srv = dpk.Server(model, precision="fp64", nslots=3)
+    tickets = [srv.submit(c, t, b) for c, t, b in fr]
+    for (c, t, b), tk in zip(fr, tickets):
+        ref = o.compute(c, t, b)
+        got = tk.result()
+        assert np.abs(got["force"] - ref["force"]).max() <= 1e-10
+        assert abs(got["energy"] - ref["energy"]) <= 1e-9
+    srv.close()
+
+
+def test_tight_budget_admission(dpk, model):
+    say("serving mixed under a tight HBM budget")
+    fr = _frames(16, 5)
+    ctx = dpk.Context(model, precision="mixed")
+    model_bytes = ctx.stats()["workspace_bytes"]
+    need = max(ctx.workspace_bytes(len(t)) for c, t, b in fr) - model_bytes
+    alone = [ctx.compute(c, t, b) for c, t, b in fr]
+    ctx.close()
+    budget = int(model_bytes + 2.5 * need)
+    srv = dpk.Server(model, precision="mixed", nslots=4, budget_bytes=budget)
+    tickets = [srv.submit(c, t, b, simulation=k) for k, (c, t, b) in enumerate(fr)]
+    outs = [tk.result() for tk in tickets]
+    for (c, t, b), a, o in zip(fr, alone, outs):
+        _compare(o, a, len(t))
+    st = srv.stats()
+    print(f"  budget {budget} peak {st['peak_bytes']} waits {st['budget_waits']}", flush=True)
+    assert st["completed"] == 16
+    assert st["peak_bytes"] <= budget
+    srv.close()
+
+
+def test_errors_are_isolated(dpk, model):
+    say("serving error isolation")
+    fr = _frames(3, 8)
+    srv = dpk.Server(model, precision="mixed", nslots=2)
+    c, t, b = fr[1]
+    bad = t.copy()
+    bad[0] = 9
+    tk = [srv.submit(*fr[0]), srv.submit(c, bad, b), srv.submit(*fr[2])]
+    tk[0].result()
+    with pytest.raises(dpk.DpkError) as e:
+        tk[1].result()
+    assert e.value.code == dpk.DPK_E_TYPE_RANGE
+    tk[2].result()
+    st = srv.stats()
+    assert st["completed"] == 2 and st["failed"] == 1
+    srv.close()
+    ctx = dpk.Context(model, precision="mixed")
+    model_bytes = ctx.stats()["workspace_bytes"]
+    ctx.close()
+    small = dpk.Server(model, precision="mixed", nslots=1, budget_bytes=model_bytes + (1 << 20))
+    big = synth.serving_frame(3000, 1, 3)
+    with pytest.raises(dpk.DpkError) as e:
+        small.submit(*big)
+    assert e.value.code == dpk.DPK_E_BUDGET
+    small.close()
