@@ -59,12 +59,75 @@ def work_per_launch(stage: str, precision: str, natoms: int, npairs: int, nc: in
     return "alu", flops / 1e12, PEAK["fp32_valu"], "TFLOP/s"
 
 
+def serving_bench(dpk, synth, n_sims=16, steps=16, slots=4, load=0.7, seed=2023):
+    """Requests from n_sims concurrent simulations (sizes log-uniform in [50, 3000], 2-type 1:2 or
+    3-type 2:1:1 frames at 0.1 atoms/A^3; consecutive frames of a simulation are small random
+    displacements), round-robin over the simulations. First all requests at once (saturated
+    throughput X), then Poisson arrivals at load * X / mean size; latency = completion - arrival."""
+    import math
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(math.log(50), math.log(3000), n_sims)).astype(int)
+    kinds = rng.choice([2, 3], size=n_sims)
+    sims = [synth.serving_frame(int(n), int(rng.integers(1 << 30)), int(k)) for n, k in zip(sizes, kinds)]
+    reqs = []
+    for step in range(steps):
+        for sid, (c, t, b) in enumerate(sims):
+            reqs.append((c + rng.normal(0.0, 0.01 * (step + 1) ** 0.5, c.shape), t, b, sid))
+    model = dpk.Model(synth.SERVE_MODEL, synth.serve_params())
+    probe = dpk.Context(model, precision="mixed")
+    model_bytes = probe.stats()["workspace_bytes"]
+    big = max(probe.workspace_bytes(len(t)) for _, t, _ in sims) - model_bytes
+    probe.close()
+    budget = int(model_bytes + 2.5 * big)
+    total_atoms = sum(len(r[1]) for r in reqs)
+    srv = dpk.Server(model, precision="mixed", nslots=slots, budget_bytes=budget)
+    # warm-up: one frame per simulation
+    for tk in [srv.submit(c, t, b, simulation=sid) for sid, (c, t, b) in enumerate(sims)]:
+        tk.result()
+    t0 = time.monotonic_ns()
+    tickets = [srv.submit(c, t, b, simulation=sid) for c, t, b, sid in reqs]
+    for tk in tickets:
+        tk.result()
+    t1 = time.monotonic_ns()
+    x_sat = total_atoms / ((t1 - t0) * 1e-9)
+    mean_n = total_atoms / len(reqs)
+    lam = load * x_sat / mean_n
+    gaps = rng.exponential(1.0 / lam, len(reqs))
+    arrivals = np.cumsum(gaps)
+    start = time.monotonic_ns() + 2_000_000
+    tickets, when = [], []
+    for (c, t, b, sid), a in zip(reqs, arrivals):
+        due = start + int(a * 1e9)
+        while time.monotonic_ns() < due:
+            pass
+        tickets.append(srv.submit(c, t, b, simulation=sid))
+        when.append(due)
+    lat = []
+    last = 0
+    for tk, due in zip(tickets, when):
+        tk.result()
+        done = int(srv.times(tk)[2])
+        lat.append((done - due) * 1e-6)
+        last = max(last, done)
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    return {"requests": len(reqs), "simulations": n_sims, "slots": slots, "budget_bytes": budget,
+            "mean_atoms": mean_n, "saturated_atom_steps_per_s": x_sat, "load": load,
+            "arrival_rate_req_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
+            "throughput_atom_steps_per_s": total_atoms / ((last - start) * 1e-9),
+            "peak_bytes": st["peak_bytes"], "budget_waits": st["budget_waits"],
+            "slot_reuse": st["slot_reuse"], "precision": "mixed"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving (latency) section")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
@@ -111,6 +174,12 @@ def main():
         print(f"# {prec}: {ms:.3f} ms/step, {n / (ms * 1e-3):.4g} atom-steps/s, stages (ms) "
               + ", ".join(f"{k} {v:.3f}" for k, v in runs[prec]["stage_ms"].items()), file=sys.stderr, flush=True)
         ctx.close()
+
+    serving = None if args.no_serving else serving_bench(dpk, synth)
+    if serving:
+        print(f"# serving: p50 {serving['p50_ms']:.3f} ms, p99 {serving['p99_ms']:.3f} ms at "
+              f"{serving['arrival_rate_req_per_s']:.0f} req/s; saturated {serving['saturated_atom_steps_per_s']:.4g} "
+              f"atom-steps/s", file=sys.stderr, flush=True)
 
     cpu = None
     errs = {}
@@ -168,6 +237,7 @@ def main():
         "speedup_mixed_vs_fp64": head["value"] / runs["fp64"]["value"],
         "force_error_vs_oracle": errs or None,
         "roofline": roof,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
