@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (latency) section")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 256 MiB device-to-device (the reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
@@ -136,6 +138,13 @@ def main():
 
     import torch
     from paper_2304_09409_amd import dpk, synth
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     c, t, b = synth.water_12288()
     n = len(t)

@@ -132,7 +132,10 @@ int dpk_compute(dpk_ctx *c, int64_t natoms, const double *coord, const int32_t *
  * the default stream) and the call returns without waiting, except with box == NULL, where it
  * waits once for the cluster's bounding box. The outputs are valid once the stream reaches this
  * point. Type-range and overflow errors found on the device are reported by the next
- * dpk_ctx_check() (or the next call of a synchronising entry point). */
+ * dpk_ctx_check() (or the next call of a synchronising entry point). The per-atom candidate
+ * buffer of the neighbour search is sized from the frame's mean density (twice the expected count
+ * within r_c, at least 256, at most 1024); a frame with a locally denser spot can report
+ * DPK_E_NBR_OVERFLOW here, where dpk_compute reruns it with the 1024-entry buffer. */
 int dpk_compute_device(dpk_ctx *c, int64_t natoms, const double *d_coord,
                        const int32_t *d_atype, const double *box, double *d_energy,
                        double *d_force, double *d_virial, double *d_atom_energy,

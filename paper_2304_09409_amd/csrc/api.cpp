@@ -201,11 +201,15 @@ struct dpk_ctx {
     int64_t cap_cells = 0;
     // views of the workspace (valid for the capacity)
     int *perm, *inv_perm, *itype, *tcount, *toff, *cell_of, *cell_atoms, *cell_count, *cell_start, *cursor;
-    int *nl_j, *nnei, *h_atype;
+    int *nl_j, *nnei, *h_atype, *bcount, *boff;
     double *pos, *nl_r, *Ei, *F, *vir_part, *bbox, *h_coord, *h_out;
+    double4* cand;
     void *T, *dT, *act;
     DevStats* stats;
     int64_t vir_blocks = 0;
+    // frame being set up (for the candidate-buffer estimate) and the overflow retry switch
+    int64_t cur_natoms = 0;
+    bool force_big_cap = false;
     // last frame
     int64_t last_n = 0;
     int64_t last_nvp = 0;
@@ -237,10 +241,13 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
     p = take(sizeof(int) * n); if (base) c->itype = (int*)p;
     p = take(sizeof(int) * MAXT); if (base) c->tcount = (int*)p;
     p = take(sizeof(int) * (MAXT + 1)); if (base) c->toff = (int*)p;
+    p = take(sizeof(int) * MAXT * ((n + 1023) / 1024)); if (base) c->bcount = (int*)p;
+    p = take(sizeof(int) * MAXT * ((n + 1023) / 1024)); if (base) c->boff = (int*)p;
     p = take(sizeof(DevStats)); if (base) c->stats = (DevStats*)p;
     p = take(sizeof(double) * 3 * n); if (base) c->pos = (double*)p;
     p = take(sizeof(int) * n); if (base) c->cell_of = (int*)p;
     p = take(sizeof(int) * n); if (base) c->cell_atoms = (int*)p;
+    p = take(sizeof(double4) * n); if (base) c->cand = (double4*)p;
     p = take(sizeof(int) * ncell); if (base) c->cell_count = (int*)p;
     p = take(sizeof(int) * (ncell + 1)); if (base) c->cell_start = (int*)p;
     p = take(sizeof(int) * ncell); if (base) c->cursor = (int*)p;
@@ -348,8 +355,13 @@ int setup_geometry(dpk_ctx* c, const double* box, const double* bbox, GeomParams
             if (nb > 256) nb = 256;
             gp.nb[k] = nb;
             gp.K[k] = (int)std::ceil(rc / (width / nb));
-            if (gp.K[k] > 60) return fail(DPK_E_BOX, "cell too thin for r_c (%d image shells)", gp.K[k]);
         }
+        // expected atoms within r_c at the frame's mean density, doubled plus a margin
+        const double expect = (double)c->cur_natoms / det * 4.18879020478639 * rc * rc * rc;
+        const double want = 2.0 * expect + 64.0;
+        gp.cap = c->force_big_cap ? NL_CAP : (want <= 256.0 ? 256 : (want <= 512.0 ? 512 : NL_CAP));
+        if ((2 * gp.K[0] + 1) * (2 * gp.K[1] + 1) * (2 * gp.K[2] + 1) > NL_STENCIL)
+            return fail(DPK_E_BOX, "cell too thin for r_c: a width below r_c/3 needs more than %d image bins", NL_STENCIL);
     } else {
         gp.periodic = 0;
         for (int k = 0; k < 3; ++k) {
@@ -365,6 +377,7 @@ int setup_geometry(dpk_ctx* c, const double* box, const double* bbox, GeomParams
             gp.K[k] = (int)std::ceil(rc / gp.binw[k]);
             if (gp.K[k] > nb) gp.K[k] = nb;
         }
+        gp.cap = NL_CAP;   // clusters can be locally dense: largest buffer
     }
     return DPK_OK;
 }
@@ -607,6 +620,7 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     const int n = (int)natoms;
     int rc;
     GeomParams gp;
+    c->cur_natoms = natoms;
     if (box) {
         if ((rc = setup_geometry(c, box, nullptr, gp))) return rc;
     } else {
@@ -624,15 +638,13 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
 
     std::vector<hipEvent_t>* ev = prof_frame(c);
     prof_mark(ev, DPK_STAGE_PREP, s);
-    launch_zero(c->tcount, sizeof(int) * MAXT, s);
-    launch_zero(c->stats, sizeof(DevStats), s);
-    launch_zero(c->cell_count, sizeof(int) * ncell, s);
-    launch_zero(c->F, sizeof(double) * 3 * n, s);
-    launch_types(n, d_atype, nt, c->tcount, c->toff, c->perm, c->inv_perm, c->itype, c->stats, s);
-    launch_cells(n, d_coord, c->perm, gp, c->pos, c->cell_of, c->cell_count, c->cell_start, c->cursor, c->cell_atoms, s);
+    launch_types(n, d_atype, nt, c->tcount, c->toff, c->bcount, c->boff, c->perm, c->inv_perm, c->itype,
+                 c->cell_count, (int)ncell, c->stats, s);
+    launch_cells(n, d_coord, c->perm, c->itype, gp, c->pos, c->cell_of, c->cell_count, c->cell_start, c->cursor,
+                 c->cell_atoms, c->cand, c->F, s);
     prof_mark(ev, DPK_STAGE_NLIST, s);
-    launch_nlist(n, c->pos, c->itype, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cell_atoms, gp, c->nl_j,
-                 c->nl_r, c->nnei, c->stats, s);
+    launch_nlist(n, c->pos, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cand, gp, c->nl_j, c->nl_r, c->nnei,
+                 c->stats, s);
 
     EmbArgs ea;
     std::memset(&ea, 0, sizeof(ea));
@@ -716,6 +728,7 @@ int dpk_compute(dpk_ctx* c, int64_t natoms, const double* coord, const int32_t* 
     // entry point below never reallocates the buffers the frame is staged in.
     GeomParams gp;
     int rc;
+    c->cur_natoms = natoms;
     if (box) {
         if ((rc = setup_geometry(c, box, nullptr, gp))) return rc;
     } else {
@@ -734,7 +747,15 @@ int dpk_compute(dpk_ctx* c, int64_t natoms, const double* coord, const int32_t* 
     double* o = c->h_out;
     rc = dpk_compute_device(c, natoms, c->h_coord, c->h_atype, box, o, o + 10, o + 1, o + 10 + 3 * natoms, s);
     if (rc) return rc;
-    if ((rc = dpk_ctx_check(c))) return rc;
+    rc = dpk_ctx_check(c);
+    if (rc == DPK_E_NBR_OVERFLOW && !c->force_big_cap && !c->strict) {
+        // a locally dense frame overflowed the estimated candidate buffer: rerun with the largest
+        c->force_big_cap = true;
+        rc = dpk_compute_device(c, natoms, c->h_coord, c->h_atype, box, o, o + 10, o + 1, o + 10 + 3 * natoms, s);
+        if (rc == DPK_OK) rc = dpk_ctx_check(c);
+        c->force_big_cap = false;
+    }
+    if (rc) return rc;
     std::vector<double> host(10 + 4 * natoms);
     HIPCHK(hipMemcpy(host.data(), o, sizeof(double) * host.size(), hipMemcpyDeviceToHost));
     *energy = host[0];
@@ -877,6 +898,7 @@ int frame_need(dpk_ctx* c, const dpk_frame& f, int64_t* need, int64_t* ncell)
 {
     GeomParams gp;
     int rc;
+    c->cur_natoms = f.natoms;
     if (f.box) {
         rc = setup_geometry(c, f.box, nullptr, gp);
     } else {

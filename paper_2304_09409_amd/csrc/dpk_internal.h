@@ -14,7 +14,8 @@ constexpr int N3P = 112;   // layer-3 output width padded to 7 tiles of 16
 constexpr int EVEC = 3 * K2P + 2 * N2P + 2 * N3P;   // W1, b1, wh1 | b2, wh2 | b3, wh3
 constexpr int FVEC = 7 * FW + 8;                    // b1,wh1,b2,wh2,b3,wh3,w4 | b4, wh4, pad
 constexpr int MAXT = 8;
-constexpr int NL_CAP = 1024;   // candidate buffer of the neighbour-list kernel (per atom)
+constexpr int NL_CAP = 1024;      // candidate buffer of the neighbour-list kernel (per atom)
+constexpr int NL_STENCIL = 343;   // bins visited per atom at most: (2K+1)^3 with K <= 3
 
 // Offsets inside one packed embedding vector block.
 constexpr int EV_W1 = 0, EV_B1 = K2P, EV_WH1 = 2 * K2P, EV_B2 = 3 * K2P, EV_WH2 = 3 * K2P + N2P,
@@ -46,6 +47,7 @@ struct GeomParams {
     double rc2;
     int ntypes, nc;
     int sel[MAXT], off[MAXT];
+    int cap;            // candidate buffer entries per atom (256, 512 or NL_CAP)
 };
 
 // Device-side error / statistics block of one frame.

@@ -6,14 +6,15 @@
 namespace dpk {
 
 void launch_zero(void* p, size_t bytes, hipStream_t s);
-void launch_types(int n, const int* atype, int ntypes, int* tcount, int* toff, int* perm, int* inv_perm,
-                  int* itype, DevStats* st, hipStream_t s);
+void launch_types(int n, const int* atype, int ntypes, int* tcount, int* toff, int* bcount, int* boff, int* perm,
+                  int* inv_perm, int* itype, int* cell_count, int ncell, DevStats* st, hipStream_t s);
 void launch_bbox(int n, const double* coord, double* out, hipStream_t s);
-void launch_cells(int n, const double* coord, const int* perm, const GeomParams& gp, double* pos, int* cell_of,
-                  int* cell_count, int* cell_start, int* cursor, int* cell_atoms, hipStream_t s);
-void launch_nlist(int n, const double* pos, const int* itype, const int* perm, const int* inv_perm,
-                  const int* cell_of, const int* cell_start, const int* cell_atoms, const GeomParams& gp, int* nl_j,
-                  double* nl_r, int* nnei, DevStats* st, hipStream_t s);
+void launch_cells(int n, const double* coord, const int* perm, const int* itype, const GeomParams& gp, double* pos,
+                  int* cell_of, int* cell_count, int* cell_start, int* cursor, int* cell_atoms, double4* cand,
+                  double* f_int, hipStream_t s);
+void launch_nlist(int n, const double* pos, const int* perm, const int* inv_perm, const int* cell_of,
+                  const int* cell_start, const double4* cand, const GeomParams& gp, int* nl_j, double* nl_r,
+                  int* nnei, DevStats* st, hipStream_t s);
 void launch_finalize(int n, const double* ei, int nvp, const double* vir_part, double* energy, double* virial,
                      const int* perm, const double* f_int, double* force, double* atom_energy, hipStream_t s);
 void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s);

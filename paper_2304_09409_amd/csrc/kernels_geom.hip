@@ -28,65 +28,80 @@ void launch_zero(void* p, size_t bytes, hipStream_t s)
 
 // ---- atom types: validation, counts, stable partition by type (atoms are kept sorted by
 // species so that each fitting GEMM and each embedding net runs over contiguous atoms) ----
+// Three passes over blocks of 1024 atoms: per-block type counts (k_type_count), a scan of the
+// counts over blocks (k_type_scan), and a scatter in which every block ranks its atoms of each
+// type with ballots (k_type_scatter). The order within a type is the caller order (stable).
+constexpr int TP_BLOCK = 1024;
 
-__global__ void k_type_count(int n, const int* atype, int ntypes, int* tcount, DevStats* st)
+// Zero the per-frame counters and the bin counts.
+__global__ void k_frame_init(int* tcount, DevStats* st, int* cell_count, int ncell)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < MAXT) tcount[i] = 0;
+    if (i < (int)(sizeof(DevStats) / 4)) reinterpret_cast<int*>(st)[i] = 0;
+    for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_count[c] = 0;
+}
+
+__device__ __forceinline__ int clamp_type(int t, int ntypes) { return t < 0 ? 0 : (t >= ntypes ? ntypes - 1 : t); }
+
+__global__ void __launch_bounds__(TP_BLOCK) k_type_count(int n, const int* atype, int ntypes, int* bcount, DevStats* st)
 {
     __shared__ int h[MAXT];
     if (threadIdx.x < MAXT) h[threadIdx.x] = 0;
     __syncthreads();
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * TP_BLOCK + threadIdx.x;
     if (i < n) {
         // Out-of-range types raise the error flag and are counted as the nearest valid type,
-        // the same clamp the partition below applies, so the permutation stays complete.
-        int t = atype[i];
-        if (t < 0 || t >= ntypes) atomicExch(&st->err_type, 1);
-        t = t < 0 ? 0 : (t >= ntypes ? ntypes - 1 : t);
-        atomicAdd(&h[t], 1);
+        // the same clamp the scatter applies, so the permutation stays complete.
+        const int t0 = atype[i];
+        if (t0 < 0 || t0 >= ntypes) atomicExch(&st->err_type, 1);
+        atomicAdd(&h[clamp_type(t0, ntypes)], 1);
     }
     __syncthreads();
-    if (threadIdx.x < ntypes && h[threadIdx.x]) atomicAdd(&tcount[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < MAXT) bcount[blockIdx.x * MAXT + threadIdx.x] = h[threadIdx.x];
 }
 
-// One block of 1024 threads: stable counting-sort scatter. perm[a] = caller index of internal
-// atom a; inv_perm is its inverse; itype[a] the type.
-__global__ void __launch_bounds__(1024) k_type_perm(int n, const int* atype, int ntypes, const int* tcount,
-                                                     int* toff, int* perm, int* inv_perm, int* itype)
+// bcount[b][t] -> exclusive offsets boff[b][t] = toff[t] + sum over earlier blocks; toff[ntypes+1].
+__global__ void __launch_bounds__(64) k_type_scan(int nblocks, int ntypes, const int* bcount, int* boff, int* toff,
+                                                  int* tcount)
 {
-    __shared__ int cursor[MAXT];
-    __shared__ int wsum[16];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (tid == 0) {
-        int acc = 0;
-        for (int t = 0; t < ntypes; ++t) { cursor[t] = acc; toff[t] = acc; acc += tcount[t]; }
-        toff[ntypes] = acc;
+    if (threadIdx.x != 0) return;
+    int acc = 0;
+    for (int t = 0; t < ntypes; ++t) {
+        toff[t] = acc;
+        int c = 0;
+        for (int b = 0; b < nblocks; ++b) {
+            boff[b * MAXT + t] = acc + c;
+            c += bcount[b * MAXT + t];
+        }
+        tcount[t] = c;
+        acc += c;
     }
-    __syncthreads();
+    toff[ntypes] = acc;
+}
+
+__global__ void __launch_bounds__(TP_BLOCK) k_type_scatter(int n, const int* atype, int ntypes, const int* boff,
+                                                           int* perm, int* inv_perm, int* itype)
+{
+    __shared__ int wsum[TP_BLOCK / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int i = blockIdx.x * TP_BLOCK + tid;
+    const int t = i < n ? clamp_type(atype[i], ntypes) : -1;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int base = 0; base < n; base += 1024) {
-        int i = base + tid;
-        int t = -1;
-        if (i < n) {
-            t = atype[i];
-            if (t < 0) t = 0;
-            if (t >= ntypes) t = ntypes - 1;
+    for (int k = 0; k < ntypes; ++k) {
+        const bool f = (t == k);
+        const unsigned long long m = __ballot(f);
+        if (lane == 0) wsum[wid] = __popcll(m);
+        __syncthreads();
+        int before = 0;
+        for (int w = 0; w < wid; ++w) before += wsum[w];
+        if (f) {
+            const int pos = boff[blockIdx.x * MAXT + k] + before + __popcll(m & lt);
+            perm[pos] = i;
+            inv_perm[i] = pos;
+            itype[pos] = k;
         }
-        for (int k = 0; k < ntypes; ++k) {
-            bool f = (t == k);
-            unsigned long long m = __ballot(f);
-            if (lane == 0) wsum[wid] = __popcll(m);
-            __syncthreads();
-            int before = 0, total = 0;
-            for (int w = 0; w < 16; ++w) { if (w < wid) before += wsum[w]; total += wsum[w]; }
-            if (f) {
-                int pos = cursor[k] + before + __popcll(m & lt);
-                perm[pos] = i;
-                inv_perm[i] = pos;
-                itype[pos] = k;
-            }
-            __syncthreads();
-            if (tid == 0) cursor[k] += total;
-            __syncthreads();
-        }
+        __syncthreads();
     }
 }
 
@@ -117,10 +132,13 @@ __global__ void __launch_bounds__(1024) k_bbox(int n, const double* coord, doubl
 // Wrap into the cell (periodic) and assign bins. Fractional s = r h^-1 (row vector), wrapped to
 // [0,1), and the wrapped position s h, each component summed in the fixed order 0, 1, 2.
 __global__ void k_wrap_bin(int n, const double* coord, const int* perm, GeomParams gp, double* pos,
-                           int* cell_of, int* cell_count)
+                           int* cell_of, int* cell_count, double* f_int)
 {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n) return;
+    f_int[3 * (size_t)a] = 0.0;   // the force accumulator of this frame (filled by atomics later)
+    f_int[3 * (size_t)a + 1] = 0.0;
+    f_int[3 * (size_t)a + 2] = 0.0;
     int i = perm[a];
     double x[3] = {coord[3 * (size_t)i], coord[3 * (size_t)i + 1], coord[3 * (size_t)i + 2]};
     int b[3];
@@ -185,13 +203,29 @@ __global__ void k_cell_fill(int n, const int* cell_of, int* cursor, int* cell_at
 }
 
 // ---- neighbour list: one wave per centre atom --------------------------------------------
-// Candidates (every atom image within r_c found through the bin stencil) are compacted into
-// LDS as 128-bit keys that compare like (type, r^2, caller index j, image n0, n1, n2):
+// Candidate records are stored in bin order (k_cell_pack): position and a tag holding the
+// internal index, the caller index and the type (30 + 30 + 4 bits), so one 32-B load gives
+// everything the candidate test and the output need.
+// The wave first loads the ranges of all stencil bins at once (one lane per bin) and scans their
+// sizes; it then sweeps the flat candidate range, several candidates per lane in flight.
+// Candidates within r_c are compacted into LDS as 128-bit keys that compare like
+// (type, r^2, caller index j, image n0, n1, n2):
 //   hi = type << 59 | bits(r^2) >> 5
 //   lo = (bits(r^2) & 31) << 59 | j << 21 | code(n)
 // (r^2 is a non-negative double, whose bit pattern orders like its value). A bitonic sort in LDS
 // orders them; the first sel[t] of each type fill that type's block of slots, the rest are
 // counted as dropped; unfilled slots get index -1.
+
+__global__ void k_cell_pack(int n, const int* cell_atoms, const double* pos, const int* perm, const int* itype,
+                            double4* cand)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int a = cell_atoms[q];
+    const long long tag = (long long)a | ((long long)perm[a] << 30) | ((long long)itype[a] << 60);
+    cand[q] = make_double4(pos[3 * (size_t)a], pos[3 * (size_t)a + 1], pos[3 * (size_t)a + 2],
+                           __longlong_as_double(tag));
+}
 
 __device__ __forceinline__ bool key_less(unsigned long long ah, unsigned long long al,
                                          unsigned long long bh, unsigned long long bl)
@@ -209,94 +243,148 @@ __device__ __forceinline__ void image_shift(const GeomParams& gp, int n0, int n1
     }
 }
 
-__global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const int* itype, const int* perm,
-                                              const int* inv_perm, const int* cell_of, const int* cell_start,
-                                              const int* cell_atoms, GeomParams gp, int* nl_j, double* nl_r,
-                                              int* nnei, DevStats* st)
+constexpr int NL_UNROLL = 4;
+
+template <int CAP>
+__global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const int* perm, const int* inv_perm,
+                                              const int* cell_of, const int* cell_start, const double4* cand,
+                                              GeomParams gp, int* nl_j, double* nl_r, int* nnei, DevStats* st)
 {
-    __shared__ unsigned long long khi[NL_CAP], klo[NL_CAP];
+    __shared__ unsigned long long khi[CAP], klo[CAP];
+    __shared__ int kq[CAP];          // flat candidate index, moved with its key
+    __shared__ int s_base[NL_STENCIL + 1], s_start[NL_STENCIL], s_code[NL_STENCIL];
     __shared__ int tcnt[MAXT];
     const int a = blockIdx.x, lane = threadIdx.x;
     if (lane < MAXT) tcnt[lane] = 0;
     const double pi[3] = {pos[3 * (size_t)a], pos[3 * (size_t)a + 1], pos[3 * (size_t)a + 2]};
+    const long long self_tag = (long long)a;
     const int ci = cell_of[a];
     const int bi[3] = {ci % gp.nb[0], (ci / gp.nb[0]) % gp.nb[1], ci / (gp.nb[0] * gp.nb[1])};
+    const int w0 = 2 * gp.K[0] + 1, w1 = 2 * gp.K[1] + 1, w2 = 2 * gp.K[2] + 1;
+    const int S = w0 * w1 * w2;
+    const int self_code = (64 << 14) | (64 << 7) | 64;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    __syncthreads();
-    int count = 0;   // wave-uniform
-    for (int o0 = -gp.K[0]; o0 <= gp.K[0]; ++o0)
-        for (int o1 = -gp.K[1]; o1 <= gp.K[1]; ++o1)
-            for (int o2 = -gp.K[2]; o2 <= gp.K[2]; ++o2) {
-                int tg[3] = {bi[0] + o0, bi[1] + o1, bi[2] + o2}, nn[3], bb[3];
-                bool skip = false;
-                for (int c = 0; c < 3; ++c) {
-                    if (gp.periodic) {
-                        int q = tg[c] / gp.nb[c];
-                        if ((tg[c] % gp.nb[c] != 0) && (tg[c] < 0)) --q;
-                        nn[c] = q;
-                        bb[c] = tg[c] - q * gp.nb[c];
-                    } else {
-                        nn[c] = 0;
-                        bb[c] = tg[c];
-                        if (tg[c] < 0 || tg[c] >= gp.nb[c]) skip = true;
-                    }
-                }
-                if (skip) continue;
-                double sh[3];
-                image_shift(gp, nn[0], nn[1], nn[2], sh);
-                const bool self_image = (nn[0] == 0 && nn[1] == 0 && nn[2] == 0);
-                const unsigned long long code =
-                    ((unsigned long long)(nn[0] + 64) << 14) | ((unsigned long long)(nn[1] + 64) << 7) |
-                    (unsigned long long)(nn[2] + 64);
-                const int cell = (bb[2] * gp.nb[1] + bb[1]) * gp.nb[0] + bb[0];
-                const int qs = cell_start[cell], qe = cell_start[cell + 1];
-                for (int q0 = qs; q0 < qe; q0 += 64) {
-                    int q = q0 + lane;
-                    bool pass = false;
-                    int j = 0;
-                    double r2 = 0.0;
-                    if (q < qe) {
-                        j = cell_atoms[q];
-                        if (!(j == a && self_image)) {
-                            double d0 = (pos[3 * (size_t)j] + sh[0]) - pi[0];
-                            double d1 = (pos[3 * (size_t)j + 1] + sh[1]) - pi[1];
-                            double d2 = (pos[3 * (size_t)j + 2] + sh[2]) - pi[2];
-                            r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                            pass = r2 < gp.rc2;
-                        }
-                    }
-                    unsigned long long m = __ballot(pass);
-                    if (pass) {
-                        int idx = count + __popcll(m & lt);
-                        if (idx < NL_CAP) {
-                            int tj = itype[j];
-                            unsigned long long rb = (unsigned long long)__double_as_longlong(r2);
-                            khi[idx] = ((unsigned long long)tj << 59) | (rb >> 5);
-                            klo[idx] = ((rb & 31ull) << 59) | ((unsigned long long)perm[j] << 21) | code;
-                            atomicAdd(&tcnt[tj], 1);
-                        }
-                    }
-                    count += __popcll(m);
+
+    // ranges of every stencil bin, scanned across the wave
+    int total = 0;   // wave-uniform
+    for (int sb = 0; sb < S; sb += 64) {
+        const int sidx = sb + lane;
+        int cnt = 0, start = 0, code = 0;
+        if (sidx < S) {
+            const int o0 = sidx / (w1 * w2) - gp.K[0];
+            const int o1 = (sidx / w2) % w1 - gp.K[1];
+            const int o2 = sidx % w2 - gp.K[2];
+            const int tg[3] = {bi[0] + o0, bi[1] + o1, bi[2] + o2};
+            int nn[3], bb[3];
+            bool skip = false;
+            for (int c = 0; c < 3; ++c) {
+                if (gp.periodic) {
+                    int q = tg[c] / gp.nb[c];
+                    if ((tg[c] % gp.nb[c] != 0) && (tg[c] < 0)) --q;
+                    nn[c] = q;
+                    bb[c] = tg[c] - q * gp.nb[c];
+                } else {
+                    nn[c] = 0;
+                    bb[c] = tg[c];
+                    if (tg[c] < 0 || tg[c] >= gp.nb[c]) skip = true;
                 }
             }
-    if (lane == 0) {
-        atomicMax(&st->max_cand, count);
-        if (count > NL_CAP) atomicExch(&st->err_overflow, 1);
+            code = ((nn[0] + 64) << 14) | ((nn[1] + 64) << 7) | (nn[2] + 64);
+            if (!skip) {
+                const int cell = (bb[2] * gp.nb[1] + bb[1]) * gp.nb[0] + bb[0];
+                start = cell_start[cell];
+                cnt = cell_start[cell + 1] - start;
+            }
+        }
+        int incl = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        if (sidx < S) {
+            s_base[sidx] = total + incl - cnt;
+            s_start[sidx] = start;
+            s_code[sidx] = code;
+        }
+        total += __shfl(incl, 63);
     }
-    if (count > NL_CAP) count = NL_CAP;
-    int S = 64;
-    while (S < count) S <<= 1;
-    for (int q = count + lane; q < S; q += 64) { khi[q] = ~0ull; klo[q] = ~0ull; }
+    if (lane == 0) s_base[S] = total;
     __syncthreads();
-    for (int k = 2; k <= S; k <<= 1) {
+
+    int count = 0;   // wave-uniform
+    int b = 0;       // this lane's current stencil bin
+    for (int q0 = 0; q0 < total; q0 += 64 * NL_UNROLL) {
+        double4 c4[NL_UNROLL];
+        int bin[NL_UNROLL], cq[NL_UNROLL];
+#pragma unroll
+        for (int u = 0; u < NL_UNROLL; ++u) {
+            const int q = q0 + 64 * u + lane;
+            bin[u] = -1;
+            if (q < total) {
+                while (s_base[b + 1] <= q) ++b;
+                bin[u] = b;
+                cq[u] = s_start[b] + (q - s_base[b]);
+                c4[u] = cand[cq[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NL_UNROLL; ++u) {
+            bool pass = false;
+            double r2 = 0.0;
+            long long tag = 0;
+            int code = 0;
+            if (bin[u] >= 0) {
+                code = s_code[bin[u]];
+                tag = __double_as_longlong(c4[u].w);
+                const int nn0 = (code >> 14) - 64, nn1 = ((code >> 7) & 127) - 64, nn2 = (code & 127) - 64;
+                double sh[3];
+                image_shift(gp, nn0, nn1, nn2, sh);
+                if (!((tag & 0x3fffffffll) == self_tag && code == self_code)) {
+                    const double d0 = (c4[u].x + sh[0]) - pi[0];
+                    const double d1 = (c4[u].y + sh[1]) - pi[1];
+                    const double d2 = (c4[u].z + sh[2]) - pi[2];
+                    r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                    pass = r2 < gp.rc2;
+                }
+            }
+            const unsigned long long m = __ballot(pass);
+            if (pass) {
+                const int idx = count + __popcll(m & lt);
+                if (idx < CAP) {
+                    const int tj = (int)((unsigned long long)tag >> 60);
+                    const unsigned long long jo = ((unsigned long long)tag >> 30) & 0x3fffffffull;
+                    const unsigned long long rb = (unsigned long long)__double_as_longlong(r2);
+                    khi[idx] = ((unsigned long long)tj << 59) | (rb >> 5);
+                    klo[idx] = ((rb & 31ull) << 59) | (jo << 21) | (unsigned long long)code;
+                    kq[idx] = cq[u];
+                    atomicAdd(&tcnt[tj], 1);
+                }
+            }
+            count += __popcll(m);
+        }
+    }
+    // one word shared by every atom: only the few atoms that raise the maximum touch it atomically
+    if (lane == 0 && count > __atomic_load_n(&st->max_cand, __ATOMIC_RELAXED)) {
+        atomicMax(&st->max_cand, count);
+        if (count > CAP) atomicExch(&st->err_overflow, 1);
+    }
+    if (count > CAP) count = CAP;
+    int S2 = 64;
+    while (S2 < count) S2 <<= 1;
+    for (int q = count + lane; q < S2; q += 64) { khi[q] = ~0ull; klo[q] = ~0ull; kq[q] = 0; }
+    __syncthreads();
+    for (int k = 2; k <= S2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = lane; i < S; i += 64) {
-                int ixj = i ^ j;
+            for (int i = lane; i < S2; i += 64) {
+                const int ixj = i ^ j;
                 if (ixj > i) {
-                    unsigned long long ah = khi[i], al = klo[i], bh = khi[ixj], bl = klo[ixj];
-                    bool up = (i & k) == 0;
+                    const unsigned long long ah = khi[i], al = klo[i], bh = khi[ixj], bl = klo[ixj];
+                    const bool up = (i & k) == 0;
                     if (key_less(bh, bl, ah, al) == up) {
                         khi[i] = bh; klo[i] = bl; khi[ixj] = ah; klo[ixj] = al;
+                        const int t = kq[i];
+                        kq[i] = kq[ixj];
+                        kq[ixj] = t;
                     }
                 }
             }
@@ -313,27 +401,28 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
     }
     const size_t rowj = (size_t)a * gp.nc;
     for (int q = lane; q < count; q += 64) {
-        int t = (int)(khi[q] >> 59);
-        int rank = q - tstart[t];
+        const int t = (int)(khi[q] >> 59);
+        const int rank = q - tstart[t];
         if (rank < gp.sel[t]) {
-            unsigned long long lo = klo[q];
-            int jo = (int)((lo >> 21) & ((1ull << 38) - 1));
-            int code = (int)(lo & ((1ull << 21) - 1));
-            int n0 = (code >> 14) - 64, n1 = ((code >> 7) & 127) - 64, n2 = (code & 127) - 64;
-            int j = inv_perm[jo];
+            const int code = (int)(klo[q] & ((1ull << 21) - 1));
+            const int n0 = (code >> 14) - 64, n1 = ((code >> 7) & 127) - 64, n2 = (code & 127) - 64;
+            const double4 c4 = cand[kq[q]];
+            const int j = (int)(__double_as_longlong(c4.w) & 0x3fffffffll);
             double sh[3];
             image_shift(gp, n0, n1, n2, sh);
-            size_t slot = rowj + gp.off[t] + rank;
+            const size_t slot = rowj + gp.off[t] + rank;
             nl_j[slot] = j;
-            for (int c = 0; c < 3; ++c) nl_r[3 * slot + c] = (pos[3 * (size_t)j + c] + sh[c]) - pi[c];
+            nl_r[3 * slot + 0] = (c4.x + sh[0]) - pi[0];
+            nl_r[3 * slot + 1] = (c4.y + sh[1]) - pi[1];
+            nl_r[3 * slot + 2] = (c4.z + sh[2]) - pi[2];
         }
     }
-    for (int s = lane; s < gp.nc; s += 64) {
+    for (int s2 = lane; s2 < gp.nc; s2 += 64) {
         int t = 0;
-        while (t + 1 < gp.ntypes && s >= gp.off[t + 1]) ++t;
-        if (s - gp.off[t] >= kept[t]) {
-            nl_j[rowj + s] = -1;
-            for (int c = 0; c < 3; ++c) nl_r[3 * (rowj + s) + c] = 0.0;
+        while (t + 1 < gp.ntypes && s2 >= gp.off[t + 1]) ++t;
+        if (s2 - gp.off[t] >= kept[t]) {
+            nl_j[rowj + s2] = -1;
+            for (int c = 0; c < 3; ++c) nl_r[3 * (rowj + s2) + c] = 0.0;
         }
     }
     if (lane < gp.ntypes) nnei[(size_t)a * gp.ntypes + lane] = kept[lane];
@@ -342,29 +431,37 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
 
 // ---- reductions and output ----------------------------------------------------------------
 
-// E = sum_i E_i and Xi = sum of per-block partials, in a fixed order (one block).
+// E = sum_i E_i and Xi = sum of per-block partials, in a fixed order (one block of 1008 threads).
+// Energy: strided partial sums, then a tree. Virial: thread t sums component t % 9 of the
+// partials t, t + 1008, ... (1008 = 112 * 9 keeps the component fixed and the reads coalesced),
+// then 9 threads add their component's 112 partial sums in order.
+constexpr int FIN_T = 1008;
+
 __global__ void __launch_bounds__(1024) k_finalize(int n, const double* ei, int nvp, const double* vir_part,
                                                     double* energy, double* virial)
 {
     __shared__ double red[1024];
-    for (int c = -1; c < 9; ++c) {
+    const int t = threadIdx.x;
+    double e = 0.0;
+    for (int i = t; i < n; i += FIN_T) e += ei[i];
+    red[t] = e;
+    if (t < 1024 - FIN_T) red[FIN_T + t] = 0.0;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) *energy = red[0];
+    __syncthreads();
+    double v = 0.0;
+    const size_t total = 9 * (size_t)nvp;
+    for (size_t i = t; i < total; i += FIN_T) v += vir_part[i];
+    red[t] = v;
+    __syncthreads();
+    if (t < 9) {
         double s = 0.0;
-        if (c < 0) {
-            for (int i = threadIdx.x; i < n; i += 1024) s += ei[i];
-        } else {
-            for (int i = threadIdx.x; i < nvp; i += 1024) s += vir_part[9 * (size_t)i + c];
-        }
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 512; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            if (c < 0) *energy = red[0];
-            else virial[c] = red[0];
-        }
-        __syncthreads();
+        for (int k = t; k < FIN_T; k += 9) s += red[k];
+        virial[t] = s;
     }
 }
 
@@ -391,12 +488,17 @@ __global__ void k_debug_nlist(int n, int nc, const int* perm, const int* nl_j, i
 
 // ---- launchers --------------------------------------------------------------------------
 
-void launch_types(int n, const int* atype, int ntypes, int* tcount, int* toff, int* perm, int* inv_perm,
-                  int* itype, DevStats* st, hipStream_t s)
+void launch_types(int n, const int* atype, int ntypes, int* tcount, int* toff, int* bcount, int* boff, int* perm,
+                  int* inv_perm, int* itype, int* cell_count, int ncell, DevStats* st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_type_count, dim3((n + 255) / 256), dim3(256), 0, s, n, atype, ntypes, tcount, st);
-    hipLaunchKernelGGL(k_type_perm, dim3(1), dim3(1024), 0, s, n, atype, ntypes, tcount, toff, perm, inv_perm,
-                       itype);
+    const int nb = (n + TP_BLOCK - 1) / TP_BLOCK;
+    int ib = (ncell + 255) / 256;
+    if (ib < 1) ib = 1;
+    if (ib > 1024) ib = 1024;
+    hipLaunchKernelGGL(k_frame_init, dim3(ib), dim3(256), 0, s, tcount, st, cell_count, ncell);
+    hipLaunchKernelGGL(k_type_count, dim3(nb), dim3(TP_BLOCK), 0, s, n, atype, ntypes, bcount, st);
+    hipLaunchKernelGGL(k_type_scan, dim3(1), dim3(64), 0, s, nb, ntypes, bcount, boff, toff, tcount);
+    hipLaunchKernelGGL(k_type_scatter, dim3(nb), dim3(TP_BLOCK), 0, s, n, atype, ntypes, boff, perm, inv_perm, itype);
 }
 
 void launch_bbox(int n, const double* coord, double* out, hipStream_t s)
@@ -404,28 +506,39 @@ void launch_bbox(int n, const double* coord, double* out, hipStream_t s)
     hipLaunchKernelGGL(k_bbox, dim3(1), dim3(1024), 0, s, n, coord, out);
 }
 
-void launch_cells(int n, const double* coord, const int* perm, const GeomParams& gp, double* pos, int* cell_of,
-                  int* cell_count, int* cell_start, int* cursor, int* cell_atoms, hipStream_t s)
+void launch_cells(int n, const double* coord, const int* perm, const int* itype, const GeomParams& gp, double* pos,
+                  int* cell_of, int* cell_count, int* cell_start, int* cursor, int* cell_atoms, double4* cand,
+                  double* f_int, hipStream_t s)
 {
     int ncell = gp.nb[0] * gp.nb[1] * gp.nb[2];
     hipLaunchKernelGGL(k_wrap_bin, dim3((n + 255) / 256), dim3(256), 0, s, n, coord, perm, gp, pos, cell_of,
-                       cell_count);
+                       cell_count, f_int);
     hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, ncell, cell_count, cell_start, cursor);
     hipLaunchKernelGGL(k_cell_fill, dim3((n + 255) / 256), dim3(256), 0, s, n, cell_of, cursor, cell_atoms);
+    hipLaunchKernelGGL(k_cell_pack, dim3((n + 255) / 256), dim3(256), 0, s, n, cell_atoms, pos, perm, itype, cand);
 }
 
-void launch_nlist(int n, const double* pos, const int* itype, const int* perm, const int* inv_perm,
-                  const int* cell_of, const int* cell_start, const int* cell_atoms, const GeomParams& gp, int* nl_j,
-                  double* nl_r, int* nnei, DevStats* st, hipStream_t s)
+void launch_nlist(int n, const double* pos, const int* perm, const int* inv_perm, const int* cell_of,
+                  const int* cell_start, const double4* cand, const GeomParams& gp, int* nl_j, double* nl_r,
+                  int* nnei, DevStats* st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_nlist, dim3(n), dim3(64), 0, s, n, pos, itype, perm, inv_perm, cell_of, cell_start,
-                       cell_atoms, gp, nl_j, nl_r, nnei, st);
+    // candidate buffer sized from the expected count within r_c (the synchronous entry point reruns
+    // a frame that overflowed with the largest buffer)
+    if (gp.cap <= 256)
+        hipLaunchKernelGGL((k_nlist<256>), dim3(n), dim3(64), 0, s, n, pos, perm, inv_perm, cell_of, cell_start, cand,
+                           gp, nl_j, nl_r, nnei, st);
+    else if (gp.cap <= 512)
+        hipLaunchKernelGGL((k_nlist<512>), dim3(n), dim3(64), 0, s, n, pos, perm, inv_perm, cell_of, cell_start, cand,
+                           gp, nl_j, nl_r, nnei, st);
+    else
+        hipLaunchKernelGGL((k_nlist<NL_CAP>), dim3(n), dim3(64), 0, s, n, pos, perm, inv_perm, cell_of, cell_start,
+                           cand, gp, nl_j, nl_r, nnei, st);
 }
 
 void launch_finalize(int n, const double* ei, int nvp, const double* vir_part, double* energy, double* virial,
                      const int* perm, const double* f_int, double* force, double* atom_energy, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, n, ei, nvp, vir_part, energy, virial);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_T), 0, s, n, ei, nvp, vir_part, energy, virial);
     hipLaunchKernelGGL(k_output, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, f_int, ei, force, atom_energy);
 }
 
