@@ -256,7 +256,9 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
     p = take(sizeof(double) * 3 * n * nc); if (base) c->nl_r = (double*)p;
     p = take(c->acc_size * n * E2 * 4); if (base) c->T = p;
     p = take(c->acc_size * n * E2 * 4); if (base) c->dT = p;
-    p = take(c->acc_size * n * 3 * FW); if (base) c->act = p;
+    // fitting scratch: one row per atom slot of the fitting grid (padding lanes get their own rows)
+    const int64_t nfit = (n + FIT_AF - 1) / FIT_AF * FIT_AF;
+    p = take(c->acc_size * nfit * (c->acc_size == 8 ? 6 : 3) * FW); if (base) c->act = p;
     p = take(sizeof(double) * n); if (base) c->Ei = (double*)p;
     p = take(sizeof(double) * 3 * n); if (base) c->F = (double*)p;
     p = take(sizeof(double) * 9 * nvb); if (base) { c->vir_part = (double*)p; c->vir_blocks = nvb; }

@@ -32,6 +32,7 @@ namespace dpk {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------------------------
 // Precision policies
@@ -706,7 +707,6 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
 // register double buffering. Forward activations go to a per-atom scratch row (L2-resident) for
 // the backward pass.
 // ---------------------------------------------------------------------------------------------
-constexpr int FIT_AF = 64;        // atoms per block (16 per wave)
 
 // Weight staging for the fitting kernel. A stage is ROWS rows x KC columns (K) of a row-major
 // matrix in global memory, stored per plane (BF16 hi, BF16 lo) or once (FP64). In LDS each row
@@ -724,16 +724,18 @@ struct FitStage {
     static constexpr int PPR = KC / EPP;                      // pieces per row and plane
     static constexpr int TOTAL = ROWS * PPR * P::NPL;
     static constexpr int NP = (TOTAL + 255) / 256;
-    uint4 r[NP];
+    u32x4 r[NP];
 
-    __device__ __forceinline__ void load(const wt* src, int64_t ld, int64_t plane, int k0) {
+    // Only the first nrows <= ROWS source rows are read; staged rows past them repeat the last one.
+    __device__ __forceinline__ void load(const wt* src, int64_t ld, int64_t plane, int k0, int nrows = ROWS) {
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int q = threadIdx.x + 256 * p;
             if (q < TOTAL) {
                 const int pl = q / (ROWS * PPR), rem = q - pl * ROWS * PPR;
                 const int row = rem / PPR, pc = rem - row * PPR;
-                r[p] = *reinterpret_cast<const uint4*>(src + pl * plane + (int64_t)row * ld + k0 + pc * EPP);
+                const int rs = row < nrows ? row : nrows - 1;
+                r[p] = *reinterpret_cast<const u32x4*>(src + pl * plane + (int64_t)rs * ld + k0 + pc * EPP);
             }
         }
     }
@@ -747,7 +749,7 @@ struct FitStage {
                 char* rowp = dst + row * ROWB;
                 if (sizeof(wt) == 8) {
                     // two doubles: half of group pc/2
-                    *reinterpret_cast<uint4*>(rowp + (pc >> 1) * GB + (pc & 1) * 16) = r[p];
+                    *reinterpret_cast<u32x4*>(rowp + (pc >> 1) * GB + (pc & 1) * 16) = r[p];
                 } else {
                     // eight BF16 of one plane: the plane's half of groups 2pc and 2pc+1
                     *reinterpret_cast<uint2*>(rowp + (2 * pc) * GB + pl * 8) = make_uint2(r[p].x, r[p].y);
@@ -806,7 +808,7 @@ __global__ void __launch_bounds__(256) k_fit(FitArgs A)
     const int arow = real ? atom : a0;              // rows past the end read a valid row
     const acc* Ta = Tin + (size_t)arow * E2 * 4;
     auto T_at = [&](int idx) { return Ta[idx]; };
-    acc* actrow = act + (size_t)arow * 3 * FW;
+    acc* actrow = act + (size_t)atom * 3 * FW;   // the scratch has a row for every lane of the grid
 
     for (int ti = t_lo; ti <= t_hi; ++ti) {
         const bool mine = real && A.itype[atom] == ti;
@@ -1009,6 +1011,235 @@ __global__ void __launch_bounds__(256) k_fit(FitArgs A)
 }
 
 // ---------------------------------------------------------------------------------------------
+// FP64 fitting net: the same computation as k_fit with FP64 MFMA. FP64 accumulators take twice the
+// registers, so every product runs in passes of eight 16-row output tiles and the layer outputs go
+// to a per-atom scratch row instead of registers. Values are stored in the K order the FP64 MFMA
+// lanes read (position 16c + 4g + v holds logical index 16c + g + 4v): the four outputs a lane
+// produces and the four B-operand values it later reads are the same 32 bytes, written and read by
+// the same lane, so the scratch row needs no synchronisation.
+// Scratch row per atom: a1, a2, a3 (tanh outputs), ga (two ping-pong buffers), gh.
+// ---------------------------------------------------------------------------------------------
+constexpr int F64_TP = 8;
+constexpr int FS_A1 = 0, FS_A2 = FW, FS_A3 = 2 * FW, FS_GA = 3 * FW, FS_GB = 4 * FW, FS_GH = 5 * FW, FS_ROW = 6 * FW;
+
+__global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
+{
+    typedef PF64 P;
+    typedef double acc;
+    typedef d4 accv;
+    typedef P::frag frag;
+    typedef FitStage<P, 16 * F64_TP, 16> SW;
+    __shared__ __attribute__((aligned(32))) char s_w[2][SW::BYTES];
+    __shared__ acc s_p1[4][16][16][4];
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int a0 = blockIdx.x * FIT_AF;
+    const int a1 = min(a0 + FIT_AF, A.natoms);
+    if (a0 >= a1) return;
+    const int t_lo = A.itype[a0], t_hi = A.itype[a1 - 1];
+    const acc* Tin = reinterpret_cast<const acc*>(A.T);
+    acc* dTout = reinterpret_cast<acc*>(A.dT);
+    const int atom = a0 + 16 * wave + c16;
+    const bool real = atom < A.natoms;
+    const int arow = real ? atom : a0;
+    const acc* Ta = Tin + (size_t)arow * E2 * 4;
+    acc* row = reinterpret_cast<acc*>(A.act) + (size_t)atom * FS_ROW;   // a row for every lane of the grid
+    auto rd4 = [&](int off) { return *reinterpret_cast<const d4*>(row + off); };
+    auto wr4 = [&](int off, const acc* x) { *reinterpret_cast<d4*>(row + off) = d4{x[0], x[1], x[2], x[3]}; };
+
+#pragma unroll 1
+    for (int ti = t_lo; ti <= t_hi; ++ti) {
+        const bool mine = real && A.itype[atom] == ti;
+        const acc* fv = reinterpret_cast<const acc*>(A.fvec) + (size_t)ti * FVEC;
+        const double* fm = reinterpret_cast<const double*>(A.fmat) + (size_t)ti * FM_SIZE;
+        acc Tn[4][4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Tn[v][k] = Ta[P::kidx(0, g, v) * 4 + k];
+
+        // y = W x for ntiles 16-row output tiles of the row-major matrix at fm + mo (K columns,
+        // stored in the MFMA K order); x for K-chunk c comes from bsrc(c); epi(t, out) receives
+        // output tile t (rows 16t + orow(g, r)).
+        auto gemm = [&](int64_t mo, int K, int ntiles, auto&& bsrc, auto&& epi) {
+            const int nchunk = K / 16;
+#pragma unroll 1
+            for (int t0 = 0; t0 < ntiles; t0 += F64_TP) {
+                const int nt = min(F64_TP, ntiles - t0);
+                accv accs[F64_TP];
+#pragma unroll
+                for (int t = 0; t < F64_TP; ++t) zero4(accs[t]);
+                SW st;
+                const double* src = fm + mo + (int64_t)16 * t0 * K;
+                __syncthreads();
+                st.load(src, K, 0, 0, 16 * nt);
+                st.store(s_w[0]);
+                __syncthreads();
+                frag Bn = bsrc(0);
+#pragma unroll 1
+                for (int c = 0; c < nchunk; ++c) {
+                    if (c + 1 < nchunk) st.load(src, K, 0, 16 * (c + 1), 16 * nt);
+                    const frag B = Bn;
+                    if (c + 1 < nchunk) Bn = bsrc(c + 1);
+                    const char* buf = s_w[c & 1];
+#pragma unroll
+                    for (int t = 0; t < F64_TP; ++t)
+                        if (t < nt) P::mma(accs[t], fit_afrag<P, SW::ROWB>(buf, 16 * t + c16, g), B);
+                    if (c + 1 < nchunk) st.store(s_w[(c + 1) & 1]);
+                    __syncthreads();
+                }
+#pragma unroll
+                for (int t = 0; t < F64_TP; ++t)
+                    if (t < nt) {
+                        const acc o[4] = {accs[t][0], accs[t][1], accs[t][2], accs[t][3]};
+                        epi(t0 + t, o);
+                    }
+            }
+        };
+        auto vec = [&](int off, int t, int r) { return fv[off + 16 * t + P::orow(g, r)]; };
+        auto kv = [&](int off, int c, int v) { return fv[off + P::kidx(c, g, v)]; };
+        auto rdfrag = [&](int off, int c) {
+            const d4 x = rd4(off + 16 * c + 4 * g);
+            return P::make(x[0], x[1], x[2], x[3]);
+        };
+
+        // a = tanh(y + b) in place over the 15 tiles of a layer output (a loop, so that the
+        // long FP64 tanh is not inlined once per tile)
+        auto activate = [&](int off, int boff) {
+#pragma unroll 1
+            for (int t = 0; t < 15; ++t) {
+                const d4 y = rd4(off + 16 * t + 4 * g);
+                acc a[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) a[r] = P::act(y[r] + vec(boff, t, r));
+                wr4(off + 16 * t + 4 * g, a);
+            }
+        };
+
+        // ---------------------------------------------------------- forward
+        // layer 1: a1 = tanh(W1 D + b1), D formed on the fly from T (Eq. 7)
+        gemm(FM_W1T, DD, 15,
+             [&](int c) {
+                 const acc T0 = Ta[c * 4 + 0], T1 = Ta[c * 4 + 1], T2 = Ta[c * 4 + 2], T3 = Ta[c * 4 + 3];
+                 acc d[4];
+#pragma unroll
+                 for (int v = 0; v < 4; ++v) d[v] = T0 * Tn[v][0] + T1 * Tn[v][1] + T2 * Tn[v][2] + T3 * Tn[v][3];
+                 return P::make(d[0], d[1], d[2], d[3]);
+             },
+             [&](int t, const acc* o) { wr4(FS_A1 + 16 * t + 4 * g, o); });
+        activate(FS_A1, FV_B1);
+        // layer 2 input h1 = wh1 a1; layer 3 input h2 = wh2 a2 + h1
+        gemm(FM_W2T, FW, 15,
+             [&](int c) {
+                 const d4 x1 = rd4(FS_A1 + 16 * c + 4 * g);
+                 return P::make(kv(FV_WH1, c, 0) * x1[0], kv(FV_WH1, c, 1) * x1[1], kv(FV_WH1, c, 2) * x1[2],
+                                kv(FV_WH1, c, 3) * x1[3]);
+             },
+             [&](int t, const acc* o) { wr4(FS_A2 + 16 * t + 4 * g, o); });
+        activate(FS_A2, FV_B2);
+        gemm(FM_W3T, FW, 15,
+             [&](int c) {
+                 const d4 x1 = rd4(FS_A1 + 16 * c + 4 * g), x2 = rd4(FS_A2 + 16 * c + 4 * g);
+                 acc h[4];
+#pragma unroll
+                 for (int v = 0; v < 4; ++v) h[v] = kv(FV_WH2, c, v) * x2[v] + kv(FV_WH1, c, v) * x1[v];
+                 return P::make(h[0], h[1], h[2], h[3]);
+             },
+             [&](int t, const acc* o) { wr4(FS_A3 + 16 * t + 4 * g, o); });
+        activate(FS_A3, FV_B3);
+        // ---------------------------------------------------------- energy (Eq. 9) and ga3
+        {
+            acc e = 0;
+#pragma unroll 1
+            for (int t = 0; t < 15; ++t) {
+                const d4 x1 = rd4(FS_A1 + 16 * t + 4 * g), x2 = rd4(FS_A2 + 16 * t + 4 * g),
+                         x3 = rd4(FS_A3 + 16 * t + 4 * g);
+                acc ga[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const acc h3 = vec(FV_WH3, t, r) * x3[r] + vec(FV_WH2, t, r) * x2[r] + vec(FV_WH1, t, r) * x1[r];
+                    e += h3 * vec(FV_W4, t, r);
+                    ga[r] = fv[FV_WH4] * vec(FV_W4, t, r) * vec(FV_WH3, t, r) * (1 - x3[r] * x3[r]);
+                }
+                wr4(FS_GA + 16 * t + 4 * g, ga);
+            }
+            e += __shfl_xor(e, 16);
+            e += __shfl_xor(e, 32);
+            if (g == 0 && mine) A.Ei[atom] = fv[FV_WH4] * (e + fv[FV_B4]);
+        }
+        // ---------------------------------------------------------- backward through layers 3, 2
+        // gh2 = W3^T ga3 + gh3 with gh3 = wh4 w4; ga2 = gh2 wh2 (1 - a2^2)
+        gemm(FM_W3, FW, 15, [&](int c) { return rdfrag(FS_GA, c); },
+             [&](int t, const acc* o) {
+                 const d4 x2 = rd4(FS_A2 + 16 * t + 4 * g);
+                 acc gh[4], ga[4];
+#pragma unroll
+                 for (int r = 0; r < 4; ++r) {
+                     gh[r] = o[r] + fv[FV_WH4] * vec(FV_W4, t, r);
+                     ga[r] = gh[r] * vec(FV_WH2, t, r) * (1 - x2[r] * x2[r]);
+                 }
+                 wr4(FS_GH + 16 * t + 4 * g, gh);
+                 wr4(FS_GB + 16 * t + 4 * g, ga);
+             });
+        // gh1 = W2^T ga2 + gh2; ga1 = gh1 wh1 (1 - a1^2)
+        gemm(FM_W2, FW, 15, [&](int c) { return rdfrag(FS_GB, c); },
+             [&](int t, const acc* o) {
+                 const d4 x1 = rd4(FS_A1 + 16 * t + 4 * g), gh2 = rd4(FS_GH + 16 * t + 4 * g);
+                 acc ga[4];
+#pragma unroll
+                 for (int r = 0; r < 4; ++r) ga[r] = (o[r] + gh2[r]) * vec(FV_WH1, t, r) * (1 - x1[r] * x1[r]);
+                 wr4(FS_GA + 16 * t + 4 * g, ga);
+             });
+        // ---------------------------------------------------------- dD = W1^T ga1 and dT (Eq. 7)
+        // Tile m of dD holds dD[m][n], n < 16: dT[m] += sum_n dD[m][n] T[n] (reduced over the lane
+        // groups, tiles m < 16 parked in LDS) and dT[n] += sum_m dD[m][n] T[m] (kept per lane).
+        acc q2[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q2[r][k] = 0;
+        gemm(FM_W1, FW, E2, [&](int c) { return rdfrag(FS_GA, c); },
+             [&](int m, const acc* dd) {
+                 const acc T0 = Ta[m * 4 + 0], T1 = Ta[m * 4 + 1], T2 = Ta[m * 4 + 2], T3 = Ta[m * 4 + 3];
+                 acc part[4] = {0, 0, 0, 0};
+#pragma unroll
+                 for (int r = 0; r < 4; ++r) {
+#pragma unroll
+                     for (int k = 0; k < 4; ++k) part[k] += dd[r] * Tn[r][k];
+                     q2[r][0] += dd[r] * T0;
+                     q2[r][1] += dd[r] * T1;
+                     q2[r][2] += dd[r] * T2;
+                     q2[r][3] += dd[r] * T3;
+                 }
+#pragma unroll
+                 for (int k = 0; k < 4; ++k) {
+                     part[k] += __shfl_xor(part[k], 16);
+                     part[k] += __shfl_xor(part[k], 32);
+                 }
+                 if (g == 0) {
+                     if (m < 16) {
+#pragma unroll
+                         for (int k = 0; k < 4; ++k) s_p1[wave][c16][m][k] = part[k];
+                     } else if (mine) {
+                         *reinterpret_cast<d4*>(dTout + ((size_t)atom * E2 + m) * 4) = d4{part[0], part[1], part[2], part[3]};
+                     }
+                 }
+             });
+        __syncthreads();
+        if (mine) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = P::orow(g, r);
+                d4 o;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) o[k] = s_p1[wave][c16][n][k] + q2[r][k];
+                *reinterpret_cast<d4*>(dTout + ((size_t)atom * E2 + n) * 4) = o;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------------
 int embed_atoms_per_block(int precision)
@@ -1048,7 +1279,7 @@ void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s
 void launch_fit(int precision, const FitArgs& a, hipStream_t s)
 {
     dim3 grid((a.natoms + FIT_AF - 1) / FIT_AF), block(256);
-    if (precision == 0) hipLaunchKernelGGL((k_fit<PF64>), grid, block, 0, s, a);
+    if (precision == 0) hipLaunchKernelGGL(k_fit_f64, grid, block, 0, s, a);
     else if (precision == 1) hipLaunchKernelGGL((k_fit<PMIX>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_fit<PBF16>), grid, block, 0, s, a);
 }
