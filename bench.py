@@ -60,7 +60,7 @@ def work_per_launch(stage: str, precision: str, natoms: int, npairs: int, nc: in
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_water12288.txt")
 KERNEL_SOURCES = ("paper_2304_09409_amd/csrc/kernels_nn.hip", "paper_2304_09409_amd/csrc/kernels_geom.hip",
-                  "paper_2304_09409_amd/csrc/dpk_internal.h")
+                  "paper_2304_09409_amd/csrc/dpk_internal.h", "paper_2304_09409_amd/csrc/kernels_fit.hip")
 
 
 def kernel_source_digest() -> str:

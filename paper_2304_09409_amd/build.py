@@ -24,6 +24,7 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-a
 SOURCES = {
     "kernels_geom.hip": ["-ffp-contract=off"],
     "kernels_nn.hip": [],
+    "kernels_fit.hip": [],
     "api.cpp": ["-ffp-contract=off"],
 }
 

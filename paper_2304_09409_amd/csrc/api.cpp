@@ -159,6 +159,30 @@ inline int kphys(int precision, int k)
     return 16 * c + 4 * (r & 3) + (r >> 2);
 }
 
+// K index held by value j (0..7) of lane group g in K-chunk c of a fragment-major BF16 matrix:
+// the 16x16x32 BF16 MFMA reads k = 8g + j of the chunk; values 0..3 are rows 4g..4g+3 of the
+// previous layer's output tile 2c and values 4..7 the same rows of tile 2c + 1.
+inline int kidx32(int c, int g, int j) { return 32 * c + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4)); }
+
+// Pack one matrix of `rows` x `kdim` (zero-padded to the tiles and chunks) in fragment-major
+// order: fragment (c, t) at frag0 + c * ntiles + t, lane 16g + i holding row 16t + i.
+template <class Fn>
+void pack_frags(std::vector<uint16_t>& out, size_t frag0, int ntiles, int nch, int rows, int kdim, bool split,
+                Fn&& w)
+{
+    for (int c = 0; c < nch; ++c)
+        for (int t = 0; t < ntiles; ++t)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 8; ++j) {
+                    const int row = 16 * t + (lane & 15), k = kidx32(c, lane >> 4, j);
+                    const double v = (row < rows && k < kdim) ? w(row, k) : 0.0;
+                    const uint16_t hb = bf16_bits((float)v);
+                    const size_t i = (frag0 + (size_t)c * ntiles + t) * XF_ELEMS + lane * 8 + j;
+                    out[i] = hb;
+                    out[i + 512] = split ? bf16_bits((float)(v - (double)bf16_float(hb))) : 0;
+                }
+}
+
 // Dense matrix (row-major, `rows` x `cols`) in each plane's element type.
 struct Planes {
     int precision;
@@ -186,6 +210,7 @@ struct dpk_ctx {
     hipStream_t stream = nullptr;        // own stream for the host entry point
     hipStream_t last_stream = nullptr;   // stream of the last frame
     size_t acc_size = 8;
+    int ncu = 256;                       // compute units of the device
     // device model
     void* evec = nullptr;
     void* emat = nullptr;
@@ -256,9 +281,12 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
     p = take(sizeof(double) * 3 * n * nc); if (base) c->nl_r = (double*)p;
     p = take(c->acc_size * n * E2 * 4); if (base) c->T = p;
     p = take(c->acc_size * n * E2 * 4); if (base) c->dT = p;
-    // fitting scratch: one row per atom slot of the fitting grid (padding lanes get their own rows)
-    const int64_t nfit = (n + FIT_AF - 1) / FIT_AF * FIT_AF;
-    p = take(c->acc_size * nfit * (c->acc_size == 8 ? 6 : 3) * FW); if (base) c->act = p;
+    // fitting scratch, for every atom slot of the fitting grid (padding lanes get their own rows):
+    // FP64 [slots][6][240]; BF16 paths [blocks][3][16][tiles][64][4] (XF_ACT floats per 16 slots),
+    // with at most 63 padding slots in either grid
+    const int64_t nfit = (n + FIT_AF - 1) / FIT_AF * FIT_AF + FIT_AF;
+    p = take(c->acc_size == 8 ? sizeof(double) * nfit * 6 * FW : sizeof(float) * (nfit / 16) * XF_ACT);
+    if (base) c->act = p;
     p = take(sizeof(double) * n); if (base) c->Ei = (double*)p;
     p = take(sizeof(double) * 3 * n); if (base) c->F = (double*)p;
     p = take(sizeof(double) * 9 * nvb); if (base) { c->vir_part = (double*)p; c->vir_blocks = nvb; }
@@ -409,7 +437,9 @@ int upload_model(dpk_ctx* c)
     std::vector<double> ev((size_t)nets * EVEC, 0.0), fv((size_t)nt * FVEC, 0.0);
     Planes em, fm;
     em.init(prec, (size_t)nets * EM_SIZE);
-    fm.init(prec, (size_t)nt * FM_SIZE);
+    if (f64) fm.init(prec, (size_t)nt * FM_SIZE);
+    std::vector<uint16_t> fx;
+    if (!f64) fx.assign((size_t)nt * XF_NFRAG * XF_ELEMS, 0);
     for (int n = 0; n < nets; ++n) {
         const Layer* L = &m->emb[(size_t)n * 3];
         double* v = &ev[(size_t)n * EVEC];
@@ -437,6 +467,19 @@ int upload_model(dpk_ctx* c)
         }
         v[FV_B4] = L[3].b[0];
         v[FV_WH4] = L[3].wh[0];
+        if (!f64) {
+            // fragment-major BF16 packing: W[in][out] of each layer, read as W^T (forward) or W (backward)
+            const bool split = prec == DPK_MIXED;
+            const size_t f0 = (size_t)t * XF_NFRAG;
+            const double *W1 = L[0].W, *W2 = L[1].W, *W3 = L[2].W;
+            pack_frags(fx, f0 + XF_W1F, 15, XF_NCH1, FW, DD, split, [&](int o, int f) { return W1[(size_t)f * FW + o]; });
+            pack_frags(fx, f0 + XF_W2F, 15, XF_NCH2, FW, FW, split, [&](int o, int i) { return W2[(size_t)i * FW + o]; });
+            pack_frags(fx, f0 + XF_W3F, 15, XF_NCH2, FW, FW, split, [&](int o, int i) { return W3[(size_t)i * FW + o]; });
+            pack_frags(fx, f0 + XF_W3B, 15, XF_NCH2, FW, FW, split, [&](int i, int o) { return W3[(size_t)i * FW + o]; });
+            pack_frags(fx, f0 + XF_W2B, 15, XF_NCH2, FW, FW, split, [&](int i, int o) { return W2[(size_t)i * FW + o]; });
+            pack_frags(fx, f0 + XF_W1B, E2, XF_NCH2, DD, FW, split, [&](int f, int o) { return W1[(size_t)f * FW + o]; });
+            continue;
+        }
         const size_t base = (size_t)t * FM_SIZE;
         for (int f = 0; f < DD; ++f)
             for (int o = 0; o < FW; ++o) {
@@ -464,9 +507,13 @@ int upload_model(dpk_ctx* c)
         if ((rc = upload(&c->fvec, fvf.data(), fvf.size()))) return rc;
     }
     if ((rc = upload_planes(&c->emat, em))) return rc;
-    if ((rc = upload_planes(&c->fmat, fm))) return rc;
+    if (f64) {
+        if ((rc = upload_planes(&c->fmat, fm))) return rc;
+    } else if ((rc = upload(&c->fmat, fx.data(), fx.size()))) {
+        return rc;
+    }
     c->model_bytes = ev.size() * c->acc_size + fv.size() * c->acc_size +
-                     (f64 ? em.d.size() * 8 + fm.d.size() * 8 : (em.h.size() + em.l.size() + fm.h.size() + fm.l.size()) * 2);
+                     (f64 ? em.d.size() * 8 + fm.d.size() * 8 : (em.h.size() + em.l.size() + fx.size()) * 2);
     if (m->tabulated) {
         if (f64) {
             if ((rc = upload(&c->table, m->table.data(), m->table.size()))) return rc;
@@ -574,6 +621,8 @@ int dpk_ctx_create(const dpk_model* m, int device, int precision, size_t hbm_bud
     c->budget = hbm_budget_bytes;
     c->strict = strict_sel;
     c->acc_size = precision == DPK_FP64 ? 8 : 4;
+    if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->ncu < 1)
+        c->ncu = 256;
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return fail(DPK_E_DEVICE, "hipStreamCreate failed");
@@ -679,6 +728,7 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     FitArgs fa;
     fa.natoms = n;
     fa.ntypes = nt;
+    fa.ncu = c->ncu;
     fa.itype = c->itype;
     fa.toff = c->toff;
     fa.fvec = c->fvec;
@@ -1146,6 +1196,7 @@ int dpk_server_create(const dpk_model* m, int device, int precision, int nslots,
             c->device = device;
             c->precision = precision;
             c->acc_size = c0->acc_size;
+            c->ncu = c0->ncu;
             c->evec = c0->evec; c->emat = c0->emat; c->fvec = c0->fvec; c->fmat = c0->fmat; c->table = c0->table;
             c->model_bytes = c0->model_bytes;
             c->owns_model = false;

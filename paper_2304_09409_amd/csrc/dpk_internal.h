@@ -32,6 +32,24 @@ constexpr int64_t FM_W2 = FM_W2T + FW * FW;
 constexpr int64_t FM_W3T = FM_W2 + FW * FW;
 constexpr int64_t FM_W3 = FM_W3T + FW * FW;
 constexpr int64_t FM_SIZE = FM_W3 + FW * FW;
+// Fragment-major fitting weights of the BF16 paths (split and plain). A fragment is the A operand
+// of one v_mfma_f32_16x16x32_bf16 for one 16-row tile and one 32-wide K-chunk: the BF16 hi parts
+// of the 64 lanes (8 values, 16 B each), then the lo parts. Lane 16g + i holds row 16t + i and
+// the K values kidx32(c, g, j), j = 0..7, so that the output tile pair (2c, 2c+1) of one layer
+// is the K-chunk c of the next. K of the 240-wide layers is zero-padded to 256 (8 chunks).
+// Offsets in fragments per type; fragment (c, t) of a matrix sits at base + c * ntiles + t.
+constexpr int XF_ELEMS = 1024;                 // BF16 values per fragment (hi 512 + lo 512)
+constexpr int XF_NCH1 = DD / 32;               // 50 K-chunks of layer 1
+constexpr int XF_NCH2 = 8;                     // K-chunks of the 240-wide layers
+constexpr int XF_W1F = 0;                      // layer 1 forward: rows = 240 outputs, K = 1600
+constexpr int XF_W2F = XF_W1F + XF_NCH1 * 15;  // layer 2 forward: rows = outputs, K = inputs
+constexpr int XF_W3F = XF_W2F + XF_NCH2 * 15;
+constexpr int XF_W3B = XF_W3F + XF_NCH2 * 15;  // layer 3 backward: rows = inputs, K = outputs
+constexpr int XF_W2B = XF_W3B + XF_NCH2 * 15;
+constexpr int XF_W1B = XF_W2B + XF_NCH2 * 15;  // layer 1 backward: rows = 1600 D entries, K = outputs
+constexpr int XF_NFRAG = XF_W1B + XF_NCH2 * 100;
+constexpr int XF_ACT = 3 * 16 * 256;           // fitting scratch floats per 16-atom tile
+
 constexpr int64_t EM_W2T = 0;                          // [64][32]
 constexpr int64_t EM_W3T = N2P * K2P;                  // [112][64]
 constexpr int64_t EM_SIZE = EM_W3T + N3P * N2P;
@@ -84,13 +102,14 @@ struct EmbArgs {
 
 struct FitArgs {
     int natoms, ntypes;
+    int ncu;                // compute units of the device (sizes the BF16 fitting grid)
     const int* itype;
     const int* toff;        // [ntypes+1] internal type offsets (device)
     const void* fvec;       // [ntypes][FVEC] acc type
-    const void* fmat;       // [planes][ntypes][FM_SIZE] weight type
+    const void* fmat;       // FP64: [ntypes][FM_SIZE]; BF16 paths: [ntypes][XF_NFRAG][XF_ELEMS]
     const void* T;          // [N][100][4]
     void* dT;               // [N][100][4]
-    void* act;              // [N][3][240] forward activations (scratch)
+    void* act;              // forward activations and gradients (scratch)
     double* Ei;             // [N]
 };
 

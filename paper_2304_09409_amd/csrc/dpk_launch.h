@@ -25,5 +25,8 @@ int fit_atoms_per_block(int precision);
 void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s);
 void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s);
 void launch_fit(int precision, const FitArgs& a, hipStream_t s);
+// BF16 fitting kernel (split = three products); 16-atom tiles per block for a frame of natoms
+void launch_fitx(bool split, const FitArgs& a, hipStream_t s);
+int fitx_tiles_per_block(int natoms, int ncu);
 
 }  // namespace dpk

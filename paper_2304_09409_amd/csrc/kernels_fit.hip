@@ -1,0 +1,477 @@
+// kernels_fit.hip -- fitting net of the BF16 paths (split BF16 and plain BF16).
+//
+// Fitting net F_0 (Sec. II.A.2, eq. fitting_energy) for every atom, forward E_i and the input
+// gradient dE_i/dT through D = T T_<^T (Sec. II.A.1). The products run on
+// v_mfma_f32_16x16x32_bf16, which issues twice the K of the 16x16x16 form in the same cycles.
+//
+// Work split: a block holds NAT tiles of 16 atoms and four waves; wave w owns the 16-row feature
+// tiles w, w+4, w+8, w+12 (< 15) of every layer for all atoms of the block, and in the backward
+// dD product the D-row tiles w, w+4, ... Weights are read by exactly one wave each, straight from
+// global memory (fragment-major, one coalesced 1 KB load per plane), one K-chunk ahead. The B
+// operands (D for layer 1, then h_l or ga_l) are shared through LDS as split BF16 fragments; a
+// layer's output tiles 2c and 2c+1 fill the two halves of K-chunk c of the next layer (the
+// weights' K order matches, see XF_* in dpk_internal.h). D is formed from T by the wave that owns
+// the atom tile, a group of K-chunks ahead, so layer 1 has one barrier per group.
+// Blocks are placed so that each XCD (block b runs on XCD b % 8) works on a contiguous range of
+// atoms: with atoms sorted by species, an XCD's L2 mostly holds one species' weights.
+#include <hip/hip_runtime.h>
+#include "dpk_internal.h"
+#include "dpk_launch.h"
+
+namespace dpk {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+struct F8 {
+    bf8 h, l;
+};
+
+constexpr int FX_G = 4;    // layer-1 K-chunks per D group
+constexpr int FX_MG = 4;   // D-row tiles per pass of the dD product
+
+// FP32 hyperbolic tangent on the hardware exp2 and reciprocal: 1 - 2 / (2^(2x log2 e) + 1).
+__device__ __forceinline__ float fx_tanh(float x)
+{
+    const float e = __builtin_amdgcn_exp2f(x * 2.885390081777927f);
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+// acc += a b with a, b split as hi + lo: lo*hi + hi*lo + hi*hi (SPLIT), or hi*hi only.
+template <bool SPLIT>
+__device__ __forceinline__ void mma32(f4& c, const F8& a, const F8& b)
+{
+    if constexpr (SPLIT) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, c, 0, 0, 0);
+    }
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
+}
+
+// One lane's part of a fragment: hi at lane*8, lo at 512 + lane*8 (global memory or LDS).
+template <bool SPLIT>
+__device__ __forceinline__ F8 ld_frag(const __bf16* f, int lane)
+{
+    F8 r;
+    r.h = *reinterpret_cast<const bf8*>(f + lane * 8);
+    if constexpr (SPLIT) r.l = *reinterpret_cast<const bf8*>(f + 512 + lane * 8);
+    else r.l = bf8{};
+    return r;
+}
+
+// Write four values (half `half` of a lane's eight) of a fragment in LDS, split into hi and lo.
+template <bool SPLIT>
+__device__ __forceinline__ void st_half(__bf16* f, int lane, int half, const float* x)
+{
+    bf4 hi, lo;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        hi[r] = (__bf16)x[r];
+        lo[r] = (__bf16)(x[r] - (float)hi[r]);
+    }
+    *reinterpret_cast<bf4*>(f + lane * 8 + half * 4) = hi;
+    if constexpr (SPLIT) *reinterpret_cast<bf4*>(f + 512 + lane * 8 + half * 4) = lo;
+}
+
+template <int NAT, bool SPLIT>
+__global__ void __launch_bounds__(256) k_fitx(FitArgs A)
+{
+    constexpr int NA = 16 * NAT;                       // atoms per block
+    constexpr int FR = XF_ELEMS;
+    // B operands [K-chunk][atom tile] (layer 1: two groups of FX_G chunks); at the end the
+    // per-wave dT partials (floats) of the D rows n < 16.
+    __shared__ __attribute__((aligned(16))) __bf16 s_b[XF_NCH2 * NAT * FR];
+    __shared__ float s_e[4][NA];
+    __shared__ __attribute__((aligned(16))) float s_p1[NA][16][4];
+    __shared__ __attribute__((aligned(16))) float s_tq[NA][16][4];     // T rows n < 16 of the block's atoms
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int nblk = gridDim.x, xcd = blockIdx.x & 7, per = nblk >> 3, rem = nblk & 7;
+    const int blk = xcd * per + min(xcd, rem) + (blockIdx.x >> 3);
+    const int a0 = blk * NA;
+    if (a0 >= A.natoms) return;
+    const int a1 = min(a0 + NA, A.natoms);
+    const int t_lo = A.itype[a0], t_hi = A.itype[a1 - 1];
+    const float* Tg = reinterpret_cast<const float*>(A.T);
+    float* dTg = reinterpret_cast<float*>(A.dT);
+    float* scr = reinterpret_cast<float*>(A.act) + (size_t)blk * NAT * XF_ACT;
+    const int nown = wave < 3 ? 4 : 3;                 // feature tiles w + 4i < 15
+
+    int atom[NAT];
+    const float* Trow[NAT];
+#pragma unroll
+    for (int a = 0; a < NAT; ++a) {
+        atom[a] = a0 + 16 * a + c16;
+        Trow[a] = Tg + (size_t)(atom[a] < A.natoms ? atom[a] : a0) * (E2 * 4);
+    }
+    // activation scratch of (layer l, feature tile t, atom tile a): this lane's four values
+    auto sp = [&](int l, int t, int a) { return scr + (((l * 16 + t) * NAT + a) * 64 + lane) * 4; };
+    auto sb = [&](int c, int a) { return s_b + (c * NAT + a) * FR; };
+
+#pragma unroll 1
+    for (int ti = t_lo; ti <= t_hi; ++ti) {
+        const float* fv = reinterpret_cast<const float*>(A.fvec) + (size_t)ti * FVEC;
+        const __bf16* W = reinterpret_cast<const __bf16*>(A.fmat) + (size_t)ti * XF_NFRAG * FR;
+        bool mine[NAT];
+#pragma unroll
+        for (int a = 0; a < NAT; ++a) mine[a] = atom[a] < A.natoms && A.itype[atom[a]] == ti;
+
+        f4 acc[4][NAT];
+        float h[4][NAT][4];
+        auto zero_acc = [&]() {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int a = 0; a < NAT; ++a) acc[i][a] = f4{0.f, 0.f, 0.f, 0.f};
+        };
+        // acc[i][a] += sum over the 8 K-chunks of W(own tile i, c) B(c, a), B from s_b
+        auto gemm8 = [&](const __bf16* Wm) {
+            zero_acc();
+            F8 An[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < nown) An[i] = ld_frag<SPLIT>(Wm + (wave + 4 * i) * FR, lane);
+#pragma unroll
+            for (int c = 0; c < XF_NCH2; ++c) {
+                F8 Ac[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) Ac[i] = An[i];
+                if (c + 1 < XF_NCH2) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (i < nown) An[i] = ld_frag<SPLIT>(Wm + ((c + 1) * 15 + wave + 4 * i) * FR, lane);
+                }
+                F8 B[NAT];
+#pragma unroll
+                for (int a = 0; a < NAT; ++a) B[a] = ld_frag<SPLIT>(sb(c, a), lane);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (i < nown) {
+#pragma unroll
+                        for (int a = 0; a < NAT; ++a) mma32<SPLIT>(acc[i][a], Ac[i], B[a]);
+                    }
+            }
+        };
+        auto vec4 = [&](int off, int t) { return *reinterpret_cast<const f4*>(fv + off + 16 * t + 4 * g); };
+
+        __syncthreads();   // s_b, s_e, s_p1 of the previous species are no longer read
+        for (int idx = threadIdx.x; idx < NA * 16; idx += 256) {
+            const int al = idx >> 4, n = idx & 15;
+            const int at = a0 + al < A.natoms ? a0 + al : a0;
+            *reinterpret_cast<f4*>(&s_tq[al][n][0]) = *reinterpret_cast<const f4*>(Tg + ((size_t)at * E2 + n) * 4);
+        }
+        // ------------------------------------------------------------ layer 1: D (1600) -> 240
+        // D fragment of K-chunk c for atom tile `wave`: lane group g holds D[2c][4g+r] and
+        // D[2c+1][4g+r], D[m][n] = sum_k T[m][k] T[n][k] (Sec. II.A.1, D = T T_<^T).
+        float Tn[4][4];
+        if (wave < NAT) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const f4 v = *reinterpret_cast<const f4*>(Trow[wave] + (4 * g + r) * 4);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) Tn[r][k] = v[k];
+            }
+        }
+        auto dfrag = [&](int c, __bf16* f) {
+            const f4 ta = *reinterpret_cast<const f4*>(Trow[wave] + (2 * c) * 4);
+            const f4 tb = *reinterpret_cast<const f4*>(Trow[wave] + (2 * c + 1) * 4);
+            float d0[4], d1[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                d0[r] = ta[0] * Tn[r][0] + ta[1] * Tn[r][1] + ta[2] * Tn[r][2] + ta[3] * Tn[r][3];
+                d1[r] = tb[0] * Tn[r][0] + tb[1] * Tn[r][1] + tb[2] * Tn[r][2] + tb[3] * Tn[r][3];
+            }
+            st_half<SPLIT>(f, lane, 0, d0);
+            st_half<SPLIT>(f, lane, 1, d1);
+        };
+        if (wave < NAT) {
+#pragma unroll
+            for (int cc = 0; cc < FX_G; ++cc) dfrag(cc, sb(cc, wave));
+        }
+        __syncthreads();
+        {
+            zero_acc();
+            const __bf16* Wm = W + (size_t)XF_W1F * FR;
+            F8 An[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < nown) An[i] = ld_frag<SPLIT>(Wm + (wave + 4 * i) * FR, lane);
+            constexpr int NGRP = (XF_NCH1 + FX_G - 1) / FX_G;
+#pragma unroll 1
+            for (int grp = 0; grp < NGRP; ++grp) {
+                const int p = grp & 1;
+#pragma unroll
+                for (int cc = 0; cc < FX_G; ++cc) {
+                    const int c = grp * FX_G + cc;
+                    if (c < XF_NCH1) {
+                        F8 Ac[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) Ac[i] = An[i];
+                        if (c + 1 < XF_NCH1) {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                if (i < nown) An[i] = ld_frag<SPLIT>(Wm + ((c + 1) * 15 + wave + 4 * i) * FR, lane);
+                        }
+                        F8 B[NAT];
+#pragma unroll
+                        for (int a = 0; a < NAT; ++a) B[a] = ld_frag<SPLIT>(sb(p * FX_G + cc, a), lane);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (i < nown) {
+#pragma unroll
+                                for (int a = 0; a < NAT; ++a) mma32<SPLIT>(acc[i][a], Ac[i], B[a]);
+                            }
+                        const int cn = c + FX_G;
+                        if (wave < NAT && cn < XF_NCH1) dfrag(cn, sb((p ^ 1) * FX_G + cc, wave));
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // a1 = tanh(W1 D + b1), h1 = wh1 a1
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (i < nown) {
+                const int t = wave + 4 * i;
+                const f4 b = vec4(FV_B1, t), wh = vec4(FV_WH1, t);
+#pragma unroll
+                for (int a = 0; a < NAT; ++a) {
+                    f4 av;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        av[r] = fx_tanh(acc[i][a][r] + b[r]);
+                        h[i][a][r] = wh[r] * av[r];
+                    }
+                    *reinterpret_cast<f4*>(sp(0, t, a)) = av;
+                    st_half<SPLIT>(sb(t >> 1, a), lane, t & 1, h[i][a]);
+                }
+            }
+        if (wave == 3) {   // feature tile 15 does not exist: the second half of K-chunk 7 is zero
+            const float z[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int a = 0; a < NAT; ++a) st_half<SPLIT>(sb(7, a), lane, 1, z);
+        }
+        __syncthreads();
+        // ------------------------------------------------------------ layers 2, 3: h += wh tanh(W h + b)
+#pragma unroll 1
+        for (int layer = 2; layer <= 3; ++layer) {
+            gemm8(W + (size_t)(layer == 2 ? XF_W2F : XF_W3F) * FR);
+            __syncthreads();
+            const int ob = layer == 2 ? FV_B2 : FV_B3, ow = layer == 2 ? FV_WH2 : FV_WH3;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < nown) {
+                    const int t = wave + 4 * i;
+                    const f4 b = vec4(ob, t), wh = vec4(ow, t);
+#pragma unroll
+                    for (int a = 0; a < NAT; ++a) {
+                        f4 av;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            av[r] = fx_tanh(acc[i][a][r] + b[r]);
+                            h[i][a][r] += wh[r] * av[r];
+                        }
+                        *reinterpret_cast<f4*>(sp(layer - 1, t, a)) = av;
+                        if (layer == 2) st_half<SPLIT>(sb(t >> 1, a), lane, t & 1, h[i][a]);
+                    }
+                }
+            if (layer == 2) __syncthreads();
+        }
+        // ------------------------------------------------------------ energy E_i = wh4 (w4 . h3 + b4)
+        {
+            float e[NAT];
+#pragma unroll
+            for (int a = 0; a < NAT; ++a) e[a] = 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < nown) {
+                    const f4 w4 = vec4(FV_W4, wave + 4 * i);
+#pragma unroll
+                    for (int a = 0; a < NAT; ++a)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) e[a] += w4[r] * h[i][a][r];
+                }
+#pragma unroll
+            for (int a = 0; a < NAT; ++a) {
+                e[a] += __shfl_xor(e[a], 16);
+                e[a] += __shfl_xor(e[a], 32);
+                if (g == 0) s_e[wave][16 * a + c16] = e[a];
+            }
+        }
+        // ------------------------------------------------------------ backward through layers 3, 2
+        // gh3 = wh4 w4, ga3 = gh3 wh3 (1 - a3^2); gh_{l-1} = W_l^T ga_l + gh_l, ga_l = gh_l wh_l (1 - a_l^2)
+        const float wh4 = fv[FV_WH4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (i < nown) {
+                const int t = wave + 4 * i;
+                const f4 w4 = vec4(FV_W4, t), wh = vec4(FV_WH3, t);
+#pragma unroll
+                for (int a = 0; a < NAT; ++a) {
+                    const f4 av = *reinterpret_cast<const f4*>(sp(2, t, a));
+                    float ga[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        h[i][a][r] = wh4 * w4[r];
+                        ga[r] = h[i][a][r] * wh[r] * (1.f - av[r] * av[r]);
+                    }
+                    st_half<SPLIT>(sb(t >> 1, a), lane, t & 1, ga);
+                }
+            }
+        __syncthreads();
+        if (threadIdx.x < NA) {
+            const int at = a0 + threadIdx.x;
+            if (at < A.natoms && A.itype[at] == ti)
+                A.Ei[at] = (double)wh4 * ((double)s_e[0][threadIdx.x] + (double)s_e[1][threadIdx.x] +
+                                          (double)s_e[2][threadIdx.x] + (double)s_e[3][threadIdx.x] + (double)fv[FV_B4]);
+        }
+#pragma unroll 1
+        for (int layer = 3; layer >= 2; --layer) {
+            gemm8(W + (size_t)(layer == 3 ? XF_W3B : XF_W2B) * FR);
+            __syncthreads();
+            const int ow = layer == 3 ? FV_WH2 : FV_WH1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < nown) {
+                    const int t = wave + 4 * i;
+                    const f4 wh = vec4(ow, t);
+#pragma unroll
+                    for (int a = 0; a < NAT; ++a) {
+                        const f4 av = *reinterpret_cast<const f4*>(sp(layer - 2, t, a));
+                        float ga[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            h[i][a][r] += acc[i][a][r];
+                            ga[r] = h[i][a][r] * wh[r] * (1.f - av[r] * av[r]);
+                        }
+                        st_half<SPLIT>(sb(t >> 1, a), lane, t & 1, ga);
+                    }
+                }
+            __syncthreads();
+        }
+        // ------------------------------------------------------------ dD = W1 ga1 and dT
+        // D-row tile m of dD holds dD[m][n = 4g + r] for 16 atoms. dT[m][k] collects
+        // sum_n dD[m][n] T[n][k] (part 1, reduced over lane groups) and, for rows n < 16,
+        // sum_m dD[m][n] T[m][k] (part 2, q2, per wave; reduced over waves at the end).
+        {
+            float q2[NAT][4][4];
+#pragma unroll
+            for (int a = 0; a < NAT; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) q2[a][r][k] = 0.f;
+            const __bf16* Wm = W + (size_t)XF_W1B * FR;
+            constexpr int NMT = E2 / 4;                // D-row tiles per wave: wave + 4 j
+#pragma unroll 1
+            for (int j0 = 0; j0 < NMT; j0 += FX_MG) {
+                const int nm = min(FX_MG, NMT - j0);
+                f4 dd[FX_MG][NAT];
+#pragma unroll
+                for (int j = 0; j < FX_MG; ++j)
+#pragma unroll
+                    for (int a = 0; a < NAT; ++a) dd[j][a] = f4{0.f, 0.f, 0.f, 0.f};
+                F8 An[FX_MG];
+#pragma unroll
+                for (int j = 0; j < FX_MG; ++j)
+                    if (j < nm) An[j] = ld_frag<SPLIT>(Wm + (wave + 4 * (j0 + j)) * FR, lane);
+#pragma unroll 1
+                for (int c = 0; c < XF_NCH2; ++c) {
+                    F8 Ac[FX_MG];
+#pragma unroll
+                    for (int j = 0; j < FX_MG; ++j) Ac[j] = An[j];
+                    if (c + 1 < XF_NCH2) {
+#pragma unroll
+                        for (int j = 0; j < FX_MG; ++j)
+                            if (j < nm) An[j] = ld_frag<SPLIT>(Wm + ((c + 1) * E2 + wave + 4 * (j0 + j)) * FR, lane);
+                    }
+                    F8 B[NAT];
+#pragma unroll
+                    for (int a = 0; a < NAT; ++a) B[a] = ld_frag<SPLIT>(sb(c, a), lane);
+#pragma unroll
+                    for (int j = 0; j < FX_MG; ++j)
+                        if (j < nm) {
+#pragma unroll
+                            for (int a = 0; a < NAT; ++a) mma32<SPLIT>(dd[j][a], Ac[j], B[a]);
+                        }
+                }
+#pragma unroll
+                for (int j = 0; j < FX_MG; ++j)
+                    if (j < nm) {
+                        const int m = wave + 4 * (j0 + j);
+#pragma unroll
+                        for (int a = 0; a < NAT; ++a) {
+                            const f4 tm = *reinterpret_cast<const f4*>(Trow[a] + m * 4);
+                            float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const f4 tn = *reinterpret_cast<const f4*>(&s_tq[16 * a + c16][4 * g + r][0]);
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) {
+                                    part[k] += dd[j][a][r] * tn[k];
+                                    q2[a][r][k] += dd[j][a][r] * tm[k];
+                                }
+                            }
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                part[k] += __shfl_xor(part[k], 16);
+                                part[k] += __shfl_xor(part[k], 32);
+                            }
+                            if (g == 0) {
+                                const f4 pv = {part[0], part[1], part[2], part[3]};
+                                if (m < 16) *reinterpret_cast<f4*>(&s_p1[16 * a + c16][m][0]) = pv;
+                                else if (mine[a]) *reinterpret_cast<f4*>(dTg + ((size_t)atom[a] * E2 + m) * 4) = pv;
+                            }
+                        }
+                    }
+            }
+            __syncthreads();   // every wave is done with ga1 in s_b
+            float* qs = reinterpret_cast<float*>(s_b);   // [wave][atom tile][lane][16]
+#pragma unroll
+            for (int a = 0; a < NAT; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    *reinterpret_cast<f4*>(qs + ((wave * NAT + a) * 64 + lane) * 16 + 4 * r) =
+                        f4{q2[a][r][0], q2[a][r][1], q2[a][r][2], q2[a][r][3]};
+            __syncthreads();
+            // rows n < 16 of dT: part 1 + the four waves' part 2
+            for (int idx = threadIdx.x; idx < NA * 16; idx += 256) {
+                const int al = idx >> 4, n = idx & 15;
+                const int at = a0 + al;
+                if (at < A.natoms && A.itype[at] == ti) {
+                    const int a = al >> 4, lp = (n >> 2) * 16 + (al & 15), r = n & 3;
+                    f4 v = *reinterpret_cast<const f4*>(&s_p1[al][n][0]);
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) v += *reinterpret_cast<const f4*>(qs + ((w * NAT + a) * 64 + lp) * 16 + 4 * r);
+                    *reinterpret_cast<f4*>(dTg + ((size_t)at * E2 + n) * 4) = v;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+int fitx_tiles_per_block(int natoms, int ncu)
+{
+    // four 16-atom tiles per block when that still gives every compute unit a block, else three
+    return (natoms + 63) / 64 >= ncu ? 4 : 3;
+}
+
+void launch_fitx(bool split, const FitArgs& a, hipStream_t s)
+{
+    if (a.natoms <= 0) return;
+    const int nat = fitx_tiles_per_block(a.natoms, a.ncu);
+    dim3 grid((a.natoms + 16 * nat - 1) / (16 * nat)), block(256);
+    if (nat == 4) {
+        if (split) hipLaunchKernelGGL((k_fitx<4, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_fitx<4, false>), grid, block, 0, s, a);
+    } else {
+        if (split) hipLaunchKernelGGL((k_fitx<3, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_fitx<3, false>), grid, block, 0, s, a);
+    }
+}
+
+}  // namespace dpk

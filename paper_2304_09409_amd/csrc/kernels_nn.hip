@@ -700,15 +700,13 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
 }
 
 // ---------------------------------------------------------------------------------------------
-// Fitting net F_0 (Sec. II.A.2, eq. fitting_energy): forward E_i and the input gradient dE_i/dT
-// through D = T T_<^T. Each wave owns 16 atoms and computes all 240 features of every layer, so
-// a layer's output tiles are the next layer's B operand in registers (no exchange between
-// waves). The four waves of a block share the weight K-chunks, staged through LDS with
-// register double buffering. Forward activations go to a per-atom scratch row (L2-resident) for
-// the backward pass.
+// Fitting net F_0 of the FP64 path (Sec. II.A.2, eq. fitting_energy): forward E_i and the input
+// gradient dE_i/dT through D = T T_<^T. Each wave owns 16 atoms and computes all 240 features of
+// every layer; the four waves of a block share the weight K-chunks, staged through LDS with
+// register double buffering. (The BF16 paths use k_fitx in kernels_fit.hip.)
 // ---------------------------------------------------------------------------------------------
 
-// Weight staging for the fitting kernel. A stage is ROWS rows x KC columns (K) of a row-major
+// Weight staging for the FP64 fitting kernel. A stage is ROWS rows x KC columns (K) of a row-major
 // matrix in global memory, stored per plane (BF16 hi, BF16 lo) or once (FP64). In LDS each row
 // holds KC/4 groups of four K values; a group is [hi0..3 lo0..3] (16 B) or [four doubles] (32 B),
 // exactly one lane's A fragment, and rows are padded by 16 B so the 16 rows a wave reads at once
@@ -775,243 +773,8 @@ __device__ __forceinline__ typename P::frag fit_afrag(const char* base, int row,
     return f;
 }
 
-template <class P> struct FitCfg {
-    static constexpr int KC1 = sizeof(typename P::wt) == 8 ? 16 : 32;   // layer-1 stage width
-};
-
-template <class P>
-__global__ void __launch_bounds__(256) k_fit(FitArgs A)
-{
-    typedef typename P::acc acc;
-    typedef typename P::wt wt;
-    typedef typename P::accv accv;
-    typedef typename P::frag frag;
-    constexpr int KC1 = FitCfg<P>::KC1;
-    typedef FitStage<P, FW, KC1> S1;     // layer 1: W1^T rows (240) x KC1
-    typedef FitStage<P, FW, 16> S2;      // 240 x 240 layers: 240 rows x 16
-    typedef FitStage<P, 16, FW> SD;      // dD: W1 rows 16m..16m+15 x 240
-    constexpr int BUFB = (S1::BYTES > S2::BYTES ? (S1::BYTES > SD::BYTES ? S1::BYTES : SD::BYTES)
-                                                : (S2::BYTES > SD::BYTES ? S2::BYTES : SD::BYTES));
-    __shared__ __attribute__((aligned(32))) char s_w[2][BUFB];
-    __shared__ acc s_p1[4][16][16][4];
-
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
-    const int a0 = blockIdx.x * FIT_AF;
-    const int a1 = min(a0 + FIT_AF, A.natoms);
-    if (a0 >= a1) return;
-    const int t_lo = A.itype[a0], t_hi = A.itype[a1 - 1];
-    const acc* Tin = reinterpret_cast<const acc*>(A.T);
-    acc* dTout = reinterpret_cast<acc*>(A.dT);
-    acc* act = reinterpret_cast<acc*>(A.act);
-    const int atom = a0 + 16 * wave + c16;
-    const bool real = atom < A.natoms;
-    const int arow = real ? atom : a0;              // rows past the end read a valid row
-    const acc* Ta = Tin + (size_t)arow * E2 * 4;
-    auto T_at = [&](int idx) { return Ta[idx]; };
-    acc* actrow = act + (size_t)atom * 3 * FW;   // the scratch has a row for every lane of the grid
-
-    for (int ti = t_lo; ti <= t_hi; ++ti) {
-        const bool mine = real && A.itype[atom] == ti;
-        const acc* fv = reinterpret_cast<const acc*>(A.fvec) + (size_t)ti * FVEC;
-        const wt* fm = reinterpret_cast<const wt*>(A.fmat) + (size_t)ti * FM_SIZE;
-        const int64_t plane = (int64_t)A.ntypes * FM_SIZE;
-
-        acc Tn[4][4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) Tn[v][k] = T_at(P::kidx(0, g, v) * 4 + k);
-
-        acc h[15][4];
-        accv accs[15];
-        // ---------------------------------------------------------- layer 1: 1600 -> 240
-        {
-#pragma unroll
-            for (int t = 0; t < 15; ++t) zero4(accs[t]);
-            S1 st;
-            __syncthreads();
-            st.load(fm + FM_W1T, DD, plane, 0);
-            st.store(s_w[0]);
-            __syncthreads();
-            constexpr int NCH = DD / KC1;
-#pragma unroll 1
-            for (int c = 0; c < NCH; ++c) {
-                if (c + 1 < NCH) st.load(fm + FM_W1T, DD, plane, KC1 * (c + 1));
-                const char* buf = s_w[c & 1];
-#pragma unroll
-                for (int sub = 0; sub < KC1 / 16; ++sub) {
-                    const int m = c * (KC1 / 16) + sub;      // K-chunk of 16 = row m of D
-                    const acc T0 = T_at(m * 4 + 0), T1 = T_at(m * 4 + 1), T2 = T_at(m * 4 + 2), T3 = T_at(m * 4 + 3);
-                    acc d[4];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) d[v] = T0 * Tn[v][0] + T1 * Tn[v][1] + T2 * Tn[v][2] + T3 * Tn[v][3];
-                    const frag B = P::make(d[0], d[1], d[2], d[3]);
-#pragma unroll
-                    for (int t = 0; t < 15; ++t) P::mma(accs[t], fit_afrag<P, S1::ROWB>(buf, 16 * t + c16, 4 * sub + g), B);
-                }
-                if (c + 1 < NCH) st.store(s_w[(c + 1) & 1]);
-                __syncthreads();
-            }
-#pragma unroll
-            for (int t = 0; t < 15; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int n = 16 * t + P::orow(g, r);
-                    const acc av = P::act(accs[t][r] + fv[FV_B1 + n]);
-                    actrow[n] = av;
-                    h[t][r] = fv[FV_WH1 + n] * av;
-                }
-        }
-        // ---------------------------------------------------------- 240 x 240 products
-        // y = W^T x (forward, weights FM_W2T / FM_W3T) or W x (backward, FM_W2 / FM_W3), with the
-        // B operand of K-chunk c taken from output tile c of the previous step (x[c][]).
-        auto gemm240 = [&](int64_t mo, acc (&x)[15][4]) {
-#pragma unroll
-            for (int t = 0; t < 15; ++t) zero4(accs[t]);
-            S2 st;
-            __syncthreads();
-            st.load(fm + mo, FW, plane, 0);
-            st.store(s_w[0]);
-            __syncthreads();
-#pragma unroll
-            for (int c = 0; c < 15; ++c) {
-                if (c + 1 < 15) st.load(fm + mo, FW, plane, 16 * (c + 1));
-                const char* buf = s_w[c & 1];
-                const frag B = P::make(x[c][0], x[c][1], x[c][2], x[c][3]);
-#pragma unroll
-                for (int t = 0; t < 15; ++t) P::mma(accs[t], fit_afrag<P, S2::ROWB>(buf, 16 * t + c16, g), B);
-                if (c + 1 < 15) st.store(s_w[(c + 1) & 1]);
-                __syncthreads();
-            }
-        };
-#pragma unroll 1
-        for (int layer = 2; layer <= 3; ++layer) {
-            gemm240(layer == 2 ? FM_W2T : FM_W3T, h);
-            const int ob = layer == 2 ? FV_B2 : FV_B3, ow = layer == 2 ? FV_WH2 : FV_WH3;
-#pragma unroll
-            for (int t = 0; t < 15; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int n = 16 * t + P::orow(g, r);
-                    const acc av = P::act(accs[t][r] + fv[ob + n]);
-                    actrow[(layer - 1) * FW + n] = av;
-                    h[t][r] = fv[ow + n] * av + h[t][r];
-                }
-        }
-        // ---------------------------------------------------------- energy
-        {
-            acc e = 0;
-#pragma unroll
-            for (int t = 0; t < 15; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) e += h[t][r] * fv[FV_W4 + 16 * t + P::orow(g, r)];
-            e += __shfl_xor(e, 16);
-            e += __shfl_xor(e, 32);
-            if (g == 0 && mine) A.Ei[atom] = (double)fv[FV_WH4] * ((double)e + (double)fv[FV_B4]);
-        }
-        // ---------------------------------------------------------- backward through layers 3, 2
-        // h[][] now holds gh = dE/dh of the current layer's output
-#pragma unroll
-        for (int t = 0; t < 15; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) h[t][r] = fv[FV_WH4] * fv[FV_W4 + 16 * t + P::orow(g, r)];
-#pragma unroll 1
-        for (int layer = 3; layer >= 2; --layer) {
-            const int ow = layer == 3 ? FV_WH3 : FV_WH2;
-            acc ga[15][4];
-#pragma unroll
-            for (int t = 0; t < 15; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int n = 16 * t + P::orow(g, r);
-                    const acc av = actrow[(layer - 1) * FW + n];
-                    ga[t][r] = h[t][r] * fv[ow + n] * (1 - av * av);
-                }
-            gemm240(layer == 3 ? FM_W3 : FM_W2, ga);
-#pragma unroll
-            for (int t = 0; t < 15; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) h[t][r] = accs[t][r] + h[t][r];   // skip connection
-        }
-        frag G1[15];
-#pragma unroll
-        for (int t = 0; t < 15; ++t) {
-            acc x[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int n = 16 * t + P::orow(g, r);
-                const acc av = actrow[n];
-                x[r] = h[t][r] * fv[FV_WH1 + n] * (1 - av * av);
-            }
-            G1[t] = P::make(x[0], x[1], x[2], x[3]);
-        }
-        // ---------------------------------------------------------- dD = W1 ga1 and dT
-        // Tile m holds dD[m][n = orow(g, r)] of this lane's atom. dT_mk collects
-        // sum_n dD_mn T_nk (part 1) and, for m < 16, sum_p dD_pm T_pk (part 2, in q2).
-        acc q2[4][4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) q2[r][k] = 0;
-        {
-            SD st;
-            __syncthreads();
-            st.load(fm + FM_W1, FW, plane, 0);
-            st.store(s_w[0]);
-            __syncthreads();
-#pragma unroll 1
-            for (int m = 0; m < E2; ++m) {
-                if (m + 1 < E2) st.load(fm + FM_W1 + (int64_t)(m + 1) * 16 * FW, FW, plane, 0);
-                const char* buf = s_w[m & 1];
-                accv dd;
-                zero4(dd);
-#pragma unroll
-                for (int c = 0; c < 15; ++c) P::mma(dd, fit_afrag<P, SD::ROWB>(buf, c16, 4 * c + g), G1[c]);
-                const acc T0 = T_at(m * 4 + 0), T1 = T_at(m * 4 + 1), T2 = T_at(m * 4 + 2), T3 = T_at(m * 4 + 3);
-                acc part[4] = {0, 0, 0, 0};
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    part[0] += dd[r] * Tn[r][0];
-                    part[1] += dd[r] * Tn[r][1];
-                    part[2] += dd[r] * Tn[r][2];
-                    part[3] += dd[r] * Tn[r][3];
-                    q2[r][0] += dd[r] * T0;
-                    q2[r][1] += dd[r] * T1;
-                    q2[r][2] += dd[r] * T2;
-                    q2[r][3] += dd[r] * T3;
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    part[k] += __shfl_xor(part[k], 16);
-                    part[k] += __shfl_xor(part[k], 32);
-                }
-                if (g == 0) {
-                    if (m < 16) {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) s_p1[wave][c16][m][k] = part[k];
-                    } else if (mine) {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) dTout[((size_t)atom * E2 + m) * 4 + k] = part[k];
-                    }
-                }
-                if (m + 1 < E2) st.store(s_w[(m + 1) & 1]);
-                __syncthreads();
-            }
-        }
-        // rows n < 16: part 1 (LDS) + part 2 (this lane's q2)
-        if (mine) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int n = P::orow(g, r);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) dTout[((size_t)atom * E2 + n) * 4 + k] = s_p1[wave][c16][n][k] + q2[r][k];
-            }
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------------------------
-// FP64 fitting net: the same computation as k_fit with FP64 MFMA. FP64 accumulators take twice the
+// FP64 fitting net with FP64 MFMA. FP64 accumulators take twice the
 // registers, so every product runs in passes of eight 16-row output tiles and the layer outputs go
 // to a per-atom scratch row instead of registers. Values are stored in the K order the FP64 MFMA
 // lanes read (position 16c + 4g + v holds logical index 16c + g + 4v): the four outputs a lane
@@ -1280,8 +1043,7 @@ void launch_fit(int precision, const FitArgs& a, hipStream_t s)
 {
     dim3 grid((a.natoms + FIT_AF - 1) / FIT_AF), block(256);
     if (precision == 0) hipLaunchKernelGGL(k_fit_f64, grid, block, 0, s, a);
-    else if (precision == 1) hipLaunchKernelGGL((k_fit<PMIX>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_fit<PBF16>), grid, block, 0, s, a);
+    else launch_fitx(precision == 1, a, s);
 }
 
 }  // namespace dpk
