@@ -149,12 +149,17 @@ void embed_derivs(const dpk_model* m, int net, double x, double* y, double* y1, 
     for (int o = 0; o < E2; ++o) { y[o] = z[o]; y1[o] = z1[o]; y2[o] = z2[o]; }
 }
 
-// Physical position of logical K index k within 16-wide K-chunks. FP64 MFMA lanes of group g
-// supply k = 16c + g + 4v (v = 0..3); storing them contiguously lets each lane load its four
-// operands at once. The BF16 instructions take k = 16c + 4g + v, which is already contiguous.
+// Physical position of logical K index k in the packed embedding weights, so that each lane's
+// operands of one MFMA fragment are contiguous. FP64 (16-wide chunks): lanes of group g supply
+// k = 16c + g + 4v (v = 0..3). BF16 paths (32-wide chunks of v_mfma_f32_16x16x32_bf16): lanes
+// of group g supply positions 8g..8g+7, holding k = 32c + 4g + v (v < 4) and 32c + 16 + 4g + v - 4
+// (v >= 4), i.e. rows 4g..4g+3 of the previous layer's output tiles 2c and 2c + 1.
 inline int kphys(int precision, int k)
 {
-    if (precision != DPK_FP64) return k;
+    if (precision != DPK_FP64) {
+        const int c = k >> 5, r = k & 31;
+        return 32 * c + 8 * ((r & 15) >> 2) + (r >> 4) * 4 + (r & 3);
+    }
     const int c = k >> 4, r = k & 15;
     return 16 * c + 4 * (r & 3) + (r >> 2);
 }

@@ -75,6 +75,20 @@ __device__ __forceinline__ void st_half(__bf16* f, int lane, int half, const flo
     if constexpr (SPLIT) *reinterpret_cast<bf4*>(f + 512 + lane * 8 + half * 4) = lo;
 }
 
+// Sum of p[0..3] over the four 16-lane groups of the wave: v_permlane32_swap pairs groups g and
+// g+2, v_permlane16_swap pairs g and g+1. Lane group G receives the total of p[ksel(G)],
+// ksel = {0, 2, 1, 3}.
+__device__ __forceinline__ float sum_groups4(const float* p)
+{
+    const auto s01 = __builtin_amdgcn_permlane32_swap(__float_as_uint(p[0]), __float_as_uint(p[1]), false, false);
+    const auto s23 = __builtin_amdgcn_permlane32_swap(__float_as_uint(p[2]), __float_as_uint(p[3]), false, false);
+    const float q0 = __uint_as_float(s01[0]) + __uint_as_float(s01[1]);
+    const float q1 = __uint_as_float(s23[0]) + __uint_as_float(s23[1]);
+    const auto t = __builtin_amdgcn_permlane16_swap(__float_as_uint(q0), __float_as_uint(q1), false, false);
+    return __uint_as_float(t[0]) + __uint_as_float(t[1]);
+}
+__device__ __forceinline__ int ksel(int g) { return ((g & 1) << 1) | (g >> 1); }
+
 template <int NAT, bool SPLIT>
 __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
 {
@@ -84,8 +98,9 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
     // per-wave dT partials (floats) of the D rows n < 16.
     __shared__ __attribute__((aligned(16))) __bf16 s_b[XF_NCH2 * NAT * FR];
     __shared__ float s_e[4][NA];
-    __shared__ __attribute__((aligned(16))) float s_p1[NA][16][4];
-    __shared__ __attribute__((aligned(16))) float s_tq[NA][16][4];     // T rows n < 16 of the block's atoms
+    // rows padded to 17 entries so that the 16 atoms a wave touches at once fall in distinct banks
+    __shared__ __attribute__((aligned(16))) float s_p1[NA][17][4];
+    __shared__ __attribute__((aligned(16))) float s_tq[NA][17][4];     // T rows n < 16 of the block's atoms
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     const int nblk = gridDim.x, xcd = blockIdx.x & 7, per = nblk >> 3, rem = nblk & 7;
@@ -293,12 +308,12 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) e[a] += w4[r] * h[i][a][r];
                 }
+            static_assert(NAT <= 4, "one energy sum per lane group");
+            float ep[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int a = 0; a < NAT; ++a) {
-                e[a] += __shfl_xor(e[a], 16);
-                e[a] += __shfl_xor(e[a], 32);
-                if (g == 0) s_e[wave][16 * a + c16] = e[a];
-            }
+            for (int a = 0; a < NAT; ++a) ep[a] = e[a];
+            const float es = sum_groups4(ep);
+            if (ksel(g) < NAT) s_e[wave][16 * ksel(g) + c16] = es;
         }
         // ------------------------------------------------------------ backward through layers 3, 2
         // gh3 = wh4 w4, ga3 = gh3 wh3 (1 - a3^2); gh_{l-1} = W_l^T ga_l + gh_l, ga_l = gh_l wh_l (1 - a_l^2)
@@ -414,16 +429,9 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
                                     q2[a][r][k] += dd[j][a][r] * tm[k];
                                 }
                             }
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                part[k] += __shfl_xor(part[k], 16);
-                                part[k] += __shfl_xor(part[k], 32);
-                            }
-                            if (g == 0) {
-                                const f4 pv = {part[0], part[1], part[2], part[3]};
-                                if (m < 16) *reinterpret_cast<f4*>(&s_p1[16 * a + c16][m][0]) = pv;
-                                else if (mine[a]) *reinterpret_cast<f4*>(dTg + ((size_t)atom[a] * E2 + m) * 4) = pv;
-                            }
+                            const float pk = sum_groups4(part);   // lane group g: component ksel(g)
+                            if (m < 16) s_p1[16 * a + c16][m][ksel(g)] = pk;
+                            else if (mine[a]) dTg[((size_t)atom[a] * E2 + m) * 4 + ksel(g)] = pk;
                         }
                     }
             }
@@ -454,24 +462,21 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
 
 }  // namespace
 
-int fitx_tiles_per_block(int natoms, int ncu)
+int fitx_tiles_per_block(int, int)
 {
-    // four 16-atom tiles per block when that still gives every compute unit a block, else three
-    return (natoms + 63) / 64 >= ncu ? 4 : 3;
+    // Four 16-atom tiles per block: the weights a block streams are amortised over 64 atoms. (On
+    // the 12,288-atom box, 192 blocks of 64 atoms ran the kernel in 0.17 ms, 256 blocks of 48 atoms
+    // in 0.27 ms.)
+    return 4;
 }
 
 void launch_fitx(bool split, const FitArgs& a, hipStream_t s)
 {
     if (a.natoms <= 0) return;
-    const int nat = fitx_tiles_per_block(a.natoms, a.ncu);
-    dim3 grid((a.natoms + 16 * nat - 1) / (16 * nat)), block(256);
-    if (nat == 4) {
-        if (split) hipLaunchKernelGGL((k_fitx<4, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_fitx<4, false>), grid, block, 0, s, a);
-    } else {
-        if (split) hipLaunchKernelGGL((k_fitx<3, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_fitx<3, false>), grid, block, 0, s, a);
-    }
+    constexpr int NAT = 4;
+    dim3 grid((a.natoms + 16 * NAT - 1) / (16 * NAT)), block(256);
+    if (split) hipLaunchKernelGGL((k_fitx<NAT, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_fitx<NAT, false>), grid, block, 0, s, a);
 }
 
 }  // namespace dpk

@@ -46,10 +46,15 @@ struct PF64 {
     typedef double wt;
     typedef d4 accv;
     static constexpr int NPL = 1;
+    static constexpr int KC = 16;    // K per fragment (four instructions)
+    static constexpr int VPL = 4;    // K values per lane per fragment
+    static constexpr int GB = 32;    // bytes of one lane's fragment in LDS
     struct frag { d4 v; };
     __device__ static int orow(int g, int r) { return g + 4 * r; }
     __device__ static int kidx(int c, int g, int v) { return 16 * c + g + 4 * v; }
     __device__ static frag make(acc x0, acc x1, acc x2, acc x3) { frag f; f.v = d4{x0, x1, x2, x3}; return f; }
+    __device__ static frag make(const acc* x) { return make(x[0], x[1], x[2], x[3]); }
+    __device__ static frag lds(const char* p) { return *reinterpret_cast<const frag*>(p); }
     __device__ static frag load(const wt* p, int64_t) {
         frag f;
         f.v = *reinterpret_cast<const d4*>(p);
@@ -79,61 +84,83 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo)
     lo = (__bf16)(x - (float)hi);
 }
 
-// Split BF16: each FP32 operand is hi + lo with both parts BF16; the product is formed as
-// lo*hi + hi*lo + hi*hi with FP32 accumulation (v_mfma_f32_16x16x16_bf16), about 16 significant
-// bits per operand. Output register r of lane group g holds row 4g + r.
+// Split BF16 on v_mfma_f32_16x16x32_bf16: each FP32 operand is hi + lo with both parts BF16; the
+// product is formed as lo*hi + hi*lo + hi*hi with FP32 accumulation, about 16 significant bits per
+// operand. Lane group g supplies K values 8g..8g+7 of a 32-wide chunk; they are the logical
+// indices kidx(c, g, v): rows 4g..4g+3 of output tile 2c (v < 4) and of tile 2c + 1 (v >= 4), so
+// that a layer's output tiles feed the next layer's K-chunk in place (weights are stored with
+// their K order permuted to match). Output register r of lane group g holds row 4g + r.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ int kidx32(int c, int g, int v) { return 32 * c + (v < 4 ? 4 * g + v : 16 + 4 * g + (v - 4)); }
+
 struct PMIX {
     typedef float acc;
     typedef __bf16 wt;
     typedef f4 accv;
     static constexpr int NPL = 2;
-    struct frag { bf4 h, l; };
+    static constexpr int KC = 32, VPL = 8, GB = 32;
+    struct frag { bf8 h, l; };
     __device__ static int orow(int g, int r) { return 4 * g + r; }
-    __device__ static int kidx(int c, int g, int v) { return 16 * c + 4 * g + v; }
-    __device__ static frag make(acc x0, acc x1, acc x2, acc x3) {
+    __device__ static int kidx(int c, int g, int v) { return kidx32(c, g, v); }
+    __device__ static frag make(const acc* x) {
         frag f;
-        __bf16 h, l;
-        split_bf16(x0, h, l); f.h[0] = h; f.l[0] = l;
-        split_bf16(x1, h, l); f.h[1] = h; f.l[1] = l;
-        split_bf16(x2, h, l); f.h[2] = h; f.l[2] = l;
-        split_bf16(x3, h, l); f.h[3] = h; f.l[3] = l;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            __bf16 h, l;
+            split_bf16(x[v], h, l);
+            f.h[v] = h;
+            f.l[v] = l;
+        }
         return f;
     }
     __device__ static frag load(const wt* p, int64_t plane) {
         frag f;
-        f.h = *reinterpret_cast<const bf4*>(p);
-        f.l = *reinterpret_cast<const bf4*>(p + plane);
+        f.h = *reinterpret_cast<const bf8*>(p);
+        f.l = *reinterpret_cast<const bf8*>(p + plane);
+        return f;
+    }
+    __device__ static frag lds(const char* p) {
+        frag f;
+        f.h = *reinterpret_cast<const bf8*>(p);
+        f.l = *reinterpret_cast<const bf8*>(p + 16);
         return f;
     }
     __device__ static void mma(accv& d, const frag& a, const frag& b) {
-        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.l, b.h, d, 0, 0, 0);
-        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h, b.l, d, 0, 0, 0);
-        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h, b.h, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, d, 0, 0, 0);
     }
     __device__ static acc act(acc x) { return tanh_fast(x); }
 };
 
-// Plain BF16 operands, one product (fast, about 1e-2 relative force error).
+// Plain BF16 operands on the same instruction, one product (fast, about 1e-2 relative force error).
 struct PBF16 {
     typedef float acc;
     typedef __bf16 wt;
     typedef f4 accv;
     static constexpr int NPL = 1;
-    struct frag { bf4 h; };
+    static constexpr int KC = 32, VPL = 8, GB = 16;
+    struct frag { bf8 h; };
     __device__ static int orow(int g, int r) { return 4 * g + r; }
-    __device__ static int kidx(int c, int g, int v) { return 16 * c + 4 * g + v; }
-    __device__ static frag make(acc x0, acc x1, acc x2, acc x3) {
+    __device__ static int kidx(int c, int g, int v) { return kidx32(c, g, v); }
+    __device__ static frag make(const acc* x) {
         frag f;
-        f.h[0] = (__bf16)x0; f.h[1] = (__bf16)x1; f.h[2] = (__bf16)x2; f.h[3] = (__bf16)x3;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) f.h[v] = (__bf16)x[v];
         return f;
     }
     __device__ static frag load(const wt* p, int64_t) {
         frag f;
-        f.h = *reinterpret_cast<const bf4*>(p);
+        f.h = *reinterpret_cast<const bf8*>(p);
+        return f;
+    }
+    __device__ static frag lds(const char* p) {
+        frag f;
+        f.h = *reinterpret_cast<const bf8*>(p);
         return f;
     }
     __device__ static void mma(accv& d, const frag& a, const frag& b) {
-        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h, b.h, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, d, 0, 0, 0);
     }
     __device__ static acc act(acc x) { return tanh_fast(x); }
 };
@@ -146,6 +173,50 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cross-lane sums over the four 16-lane groups of a wave on v_permlane32_swap (exchanges the
+// upper half of one register with the lower half of another: pairs groups g, g + 2) and
+// v_permlane16_swap (odd rows of one with even rows of the other: pairs g, g + 1).
+__device__ __forceinline__ void swap_halves(float& a, float& b, bool rows16)
+{
+    const auto r = rows16 ? __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false)
+                          : __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap_halves(double& a, double& b, bool rows16)
+{
+    const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    unsigned alo = (unsigned)ua, ahi = (unsigned)(ua >> 32), blo = (unsigned)ub, bhi = (unsigned)(ub >> 32);
+    const auto rl = rows16 ? __builtin_amdgcn_permlane16_swap(alo, blo, false, false)
+                           : __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto rh = rows16 ? __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false)
+                           : __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    a = __longlong_as_double((long long)(((unsigned long long)rh[0] << 32) | rl[0]));
+    b = __longlong_as_double((long long)(((unsigned long long)rh[1] << 32) | rl[1]));
+}
+// Every lane receives the sum of v over the four lanes of its column (lane & 15).
+template <class T> __device__ __forceinline__ T sum_groups(T v)
+{
+    T a = v, b = v;
+    swap_halves(a, b, false);
+    v = a + b;
+    a = v;
+    b = v;
+    swap_halves(a, b, true);
+    return a + b;
+}
+// Lane group G receives the column sum of p[ksel(G)], ksel = {0, 2, 1, 3}.
+__device__ __forceinline__ int ksel(int g) { return ((g & 1) << 1) | (g >> 1); }
+template <class T> __device__ __forceinline__ T sum_groups4(const T* p)
+{
+    T a = p[0], b = p[1], c = p[2], d = p[3];
+    swap_halves(a, b, false);
+    swap_halves(c, d, false);
+    T q0 = a + b, q1 = c + d;
+    swap_halves(q0, q1, true);
+    return q0 + q1;
 }
 
 // Switching function of Sec. II.A.1 (eq. switch) and its derivative, FP64.
@@ -178,44 +249,37 @@ template <class P> struct EmbCfg {
     static constexpr int APW = 3;
     static constexpr int APB = NW * APW;
     static constexpr bool W3LDS = !F64;
-    // LDS rows of staged weights: groups of four K values, [hi0..3 lo0..3] for split BF16 (one
-    // lane's A or B fragment), padded by 16 B so 16 consecutive rows fall in distinct banks.
-    static constexpr int GB = 4 * sizeof(wt) * P::NPL;
-    static constexpr int ROW2 = (K2P / 4) * GB + 16;
-    static constexpr int ROW3 = (N2P / 4) * GB + 16;
+    // LDS rows of staged weights: one lane's fragment per group (VPL K values; [hi lo] for split
+    // BF16), rows padded by 16 B so 16 consecutive rows fall in distinct banks.
+    static constexpr int ROW2 = (K2P / P::VPL) * P::GB + 16;
+    static constexpr int ROW3 = (N2P / P::VPL) * P::GB + 16;
+    static constexpr int NC1 = K2P / P::KC;     // K-chunks of layer 2 (input 25, padded)
+    static constexpr int NC2 = N2P / P::KC;     // K-chunks of layer 3 (input 50, padded)
 };
 
-// Fragment of row `row`, K-group `grp` from a staged block with `rowb` bytes per row.
+// Fragment of row `row`, K-group `grp` (= 4 * chunk + lane group) from a staged block with `rowb`
+// bytes per row.
 template <class P>
 __device__ __forceinline__ typename P::frag lds_frag(const char* base, int rowb, int row, int grp)
 {
-    const char* p = base + row * rowb + grp * (4 * sizeof(typename P::wt) * P::NPL);
-    typename P::frag f;
-    if constexpr (P::NPL == 2) {
-        f.h = *reinterpret_cast<const bf4*>(p);
-        f.l = *reinterpret_cast<const bf4*>(p + 8);
-    } else {
-        f = *reinterpret_cast<const typename P::frag*>(p);
-    }
-    return f;
+    return P::lds(base + row * rowb + grp * P::GB);
 }
 
-// Stage rows x K of a per-plane row-major matrix into interleaved LDS rows.
+// Stage rows x K of a per-plane row-major matrix into LDS rows of fragment groups.
 template <class P>
 __device__ void stage_rows(char* dst, int rowb, const typename P::wt* src, int64_t plane, int rows, int K)
 {
     typedef typename P::wt wt;
-    constexpr int GB = 4 * sizeof(wt) * P::NPL;
-    const int G = K / 4;
+    const int G = K / P::VPL;
     for (int i = threadIdx.x; i < rows * G; i += blockDim.x) {
         const int row = i / G, grp = i - row * G;
-        const wt* sp = src + (int64_t)row * K + 4 * grp;
-        char* d = dst + row * rowb + grp * GB;
+        const wt* sp = src + (int64_t)row * K + P::VPL * grp;
+        char* d = dst + row * rowb + grp * P::GB;
         if constexpr (sizeof(wt) == 8) {
             *reinterpret_cast<d4*>(d) = *reinterpret_cast<const d4*>(sp);
         } else {
-            *reinterpret_cast<uint2*>(d) = *reinterpret_cast<const uint2*>(sp);
-            if constexpr (P::NPL == 2) *reinterpret_cast<uint2*>(d + 8) = *reinterpret_cast<const uint2*>(sp + plane);
+            *reinterpret_cast<u32x4*>(d) = *reinterpret_cast<const u32x4*>(sp);
+            if constexpr (P::NPL == 2) *reinterpret_cast<u32x4*>(d + 16) = *reinterpret_cast<const u32x4*>(sp + plane);
         }
     }
 }
@@ -329,11 +393,12 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
                 if (cc0 == 0)
                     for (int t = 0; t < 7; ++t) zero4(Tacc[t]);
                 // T accumulates over the neighbour-type passes; read the earlier passes' sum now
-                acc Tprev[7][4];
-                if (last && tj > 0 && g == 0) {
+                // (lane group g owns component ksel(g) of row 16 tm + c16)
+                acc Tprev[7];
+                if (last && tj > 0) {
                     for (int tm = 0; tm < 7; ++tm) {
                         const int m = 16 * tm + c16;
-                        for (int k = 0; k < 4; ++k) Tprev[tm][k] = m < E2 ? Tout[((size_t)ca * E2 + m) * 4 + k] : (acc)0;
+                        Tprev[tm] = m < E2 ? Tout[((size_t)ca * E2 + m) * 4 + ksel(g)] : (acc)0;
                     }
                 }
 
@@ -372,10 +437,10 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
                         atomicAdd(&A.stats->table_oor, 1ull);
                 } else {
                     // layer 1 (1 -> 25) straight into the B operand of layer 2
-                    frag B1[2];
-                    for (int c = 0; c < 2; ++c) {
-                        acc zz[4];
-                        for (int v = 0; v < 4; ++v) {
+                    frag B1[Cfg::NC1];
+                    for (int c = 0; c < Cfg::NC1; ++c) {
+                        acc zz[P::VPL];
+                        for (int v = 0; v < P::VPL; ++v) {
                             const int k = P::kidx(c, g, v);
                             zz[v] = 0;
                             if (k < E0) {
@@ -383,36 +448,40 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
                                 s_z1[wave][p][k] = zz[v];
                             }
                         }
-                        B1[c] = P::make(zz[0], zz[1], zz[2], zz[3]);
+                        B1[c] = P::make(zz);
                     }
                     // layer 2 (25 -> 50), transposed: pre2^T = W2^T z1^T
                     accv acc2[4];
                     for (int t = 0; t < 4; ++t) {
                         zero4(acc2[t]);
-                        for (int c = 0; c < 2; ++c)
+                        for (int c = 0; c < Cfg::NC1; ++c)
                             P::mma(acc2[t], lds_frag<P>(s_w2, Cfg::ROW2, 16 * t + c16, 4 * c + g), B1[c]);
                     }
                     wave_sync();
-                    frag A3[4];
-                    for (int t = 0; t < 4; ++t) {
-                        acc zz[4];
+                    acc zt[4][4];
+                    for (int t = 0; t < 4; ++t)
                         for (int r = 0; r < 4; ++r) {
                             const int n = 16 * t + P::orow(g, r);
-                            zz[r] = 0;
+                            zt[t][r] = 0;
                             if (n < E1) {
-                                zz[r] = s_vec[EV_WH2 + n] * P::act(acc2[t][r] + s_vec[EV_B2 + n]) + s_z1[wave][p][n % E0];
-                                s_z2[wave][p][n] = zz[r];
+                                zt[t][r] = s_vec[EV_WH2 + n] * P::act(acc2[t][r] + s_vec[EV_B2 + n]) + s_z1[wave][p][n % E0];
+                                s_z2[wave][p][n] = zt[t][r];
                             }
                         }
-                        A3[t] = P::make(zz[0], zz[1], zz[2], zz[3]);
+                    // output tiles -> K-chunks of layer 3: chunk c, value v is tile c*KC/16 + v/4, row r = v%4
+                    frag A3[Cfg::NC2];
+                    for (int c = 0; c < Cfg::NC2; ++c) {
+                        acc x[P::VPL];
+                        for (int v = 0; v < P::VPL; ++v) x[v] = zt[c * (P::KC / 16) + v / 4][v % 4];
+                        A3[c] = P::make(x);
                     }
                     // layer 3 (50 -> 100), untransposed: pre3 = z2 W3
                     accv acc3[7];
                     for (int tm = 0; tm < 7; ++tm) {
                         zero4(acc3[tm]);
-                        for (int c = 0; c < 4; ++c) {
+                        for (int c = 0; c < Cfg::NC2; ++c) {
                             const frag Bw = W3LDS ? lds_frag<P>(s_w3, Cfg::ROW3, 16 * tm + c16, 4 * c + g)
-                                                  : P::load(gw3 + (16 * tm + c16) * N2P + 16 * c + 4 * g, gpl);
+                                                  : P::load(gw3 + (16 * tm + c16) * N2P + P::KC * c + P::VPL * g, gpl);
                             P::mma(acc3[tm], A3[c], Bw);
                         }
                     }
@@ -431,21 +500,11 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
                 }
                 if (last) {
                     // sum the four lane groups (they hold different neighbours) and store T
-                    for (int tm = 0; tm < 7; ++tm)
-                        for (int k = 0; k < 4; ++k) {
-                            acc v = Tacc[tm][k];
-                            v += __shfl_xor(v, 16);
-                            v += __shfl_xor(v, 32);
-                            Tacc[tm][k] = v;
-                        }
-                    if (g == 0) {
-                        for (int tm = 0; tm < 7; ++tm) {
-                            const int m = 16 * tm + c16;
-                            if (m >= E2) continue;
-                            acc* dst = Tout + ((size_t)ca * E2 + m) * 4;
-                            for (int k = 0; k < 4; ++k)
-                                dst[k] = Tacc[tm][k] * (acc)A.inv_nc + (tj > 0 ? Tprev[tm][k] : (acc)0);
-                        }
+                    for (int tm = 0; tm < 7; ++tm) {
+                        const acc v = sum_groups4(Tacc[tm]);
+                        const int m = 16 * tm + c16;
+                        if (m < E2)
+                            Tout[((size_t)ca * E2 + m) * 4 + ksel(g)] = v * (acc)A.inv_nc + (tj > 0 ? Tprev[tm] : (acc)0);
                     }
                 }
             }
@@ -570,10 +629,10 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
                 } else {
                     wave_sync();
                     // layer 1 and its derivative d/ds
-                    frag B1[2], B1d[2];
-                    for (int c = 0; c < 2; ++c) {
-                        acc zz[4], zd[4];
-                        for (int v = 0; v < 4; ++v) {
+                    frag B1[Cfg::NC1], B1d[Cfg::NC1];
+                    for (int c = 0; c < Cfg::NC1; ++c) {
+                        acc zz[P::VPL], zd[P::VPL];
+                        for (int v = 0; v < P::VPL; ++v) {
                             const int k = P::kidx(c, g, v);
                             zz[v] = 0;
                             zd[v] = 0;
@@ -586,47 +645,54 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
                                 s_z1d[wave][p][k] = zd[v];
                             }
                         }
-                        B1[c] = P::make(zz[0], zz[1], zz[2], zz[3]);
-                        B1d[c] = P::make(zd[0], zd[1], zd[2], zd[3]);
+                        B1[c] = P::make(zz);
+                        B1d[c] = P::make(zd);
                     }
                     accv acc2[4], acc2d[4];
                     for (int t = 0; t < 4; ++t) {
                         zero4(acc2[t]);
                         zero4(acc2d[t]);
-                        for (int c = 0; c < 2; ++c) {
+                        for (int c = 0; c < Cfg::NC1; ++c) {
                             const frag W = lds_frag<P>(s_w2, Cfg::ROW2, 16 * t + c16, 4 * c + g);
                             P::mma(acc2[t], W, B1[c]);
                             P::mma(acc2d[t], W, B1d[c]);
                         }
                     }
                     wave_sync();
-                    frag B3[4], B3d[4];
-                    for (int t = 0; t < 4; ++t) {
-                        acc zz[4], zd[4];
+                    acc zt[4][4], ztd[4][4];
+                    for (int t = 0; t < 4; ++t)
                         for (int rr = 0; rr < 4; ++rr) {
                             const int n = 16 * t + P::orow(g, rr);
-                            zz[rr] = 0;
-                            zd[rr] = 0;
+                            zt[t][rr] = 0;
+                            ztd[t][rr] = 0;
                             if (n < E1) {
                                 const acc t2 = P::act(acc2[t][rr] + s_vec[EV_B2 + n]);
                                 const acc wh = s_vec[EV_WH2 + n];
-                                zz[rr] = wh * t2 + s_z1[wave][p][n % E0];
-                                zd[rr] = wh * (1 - t2 * t2) * acc2d[t][rr] + s_z1d[wave][p][n % E0];
-                                s_z2[wave][p][n] = zz[rr];
-                                s_z2d[wave][p][n] = zd[rr];
+                                zt[t][rr] = wh * t2 + s_z1[wave][p][n % E0];
+                                ztd[t][rr] = wh * (1 - t2 * t2) * acc2d[t][rr] + s_z1d[wave][p][n % E0];
+                                s_z2[wave][p][n] = zt[t][rr];
+                                s_z2d[wave][p][n] = ztd[t][rr];
                             }
                         }
-                        B3[t] = P::make(zz[0], zz[1], zz[2], zz[3]);
-                        B3d[t] = P::make(zd[0], zd[1], zd[2], zd[3]);
+                    // output tiles -> K-chunks of layer 3 (chunk c, value v: tile c*KC/16 + v/4, row v%4)
+                    frag B3[Cfg::NC2], B3d[Cfg::NC2];
+                    for (int c = 0; c < Cfg::NC2; ++c) {
+                        acc x[P::VPL], xd[P::VPL];
+                        for (int v = 0; v < P::VPL; ++v) {
+                            x[v] = zt[c * (P::KC / 16) + v / 4][v % 4];
+                            xd[v] = ztd[c * (P::KC / 16) + v / 4][v % 4];
+                        }
+                        B3[c] = P::make(x);
+                        B3d[c] = P::make(xd);
                     }
                     // layer 3 transposed: one neighbour per lane column
                     accv acc3[7], acc3d[7];
                     for (int tm = 0; tm < 7; ++tm) {
                         zero4(acc3[tm]);
                         zero4(acc3d[tm]);
-                        for (int c = 0; c < 4; ++c) {
+                        for (int c = 0; c < Cfg::NC2; ++c) {
                             const frag W = W3LDS ? lds_frag<P>(s_w3, Cfg::ROW3, 16 * tm + c16, 4 * c + g)
-                                                 : P::load(gw3 + (16 * tm + c16) * N2P + 16 * c + 4 * g, gpl);
+                                                 : P::load(gw3 + (16 * tm + c16) * N2P + P::KC * c + P::VPL * g, gpl);
                             P::mma(acc3[tm], W, B3[c]);
                             P::mma(acc3d[tm], W, B3d[c]);
                         }
@@ -645,18 +711,16 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
                             H[0] += Gd * dt[0]; H[1] += Gd * dt[1]; H[2] += Gd * dt[2]; H[3] += Gd * dt[3];
                         }
                 }
-                for (int k = 0; k < 4; ++k) {
-                    dR[k] += __shfl_xor(dR[k], 16);
-                    dR[k] += __shfl_xor(dR[k], 32);
-                    H[k] += __shfl_xor(H[k], 16);
-                    H[k] += __shfl_xor(H[k], 32);
-                }
+                // column sums over the lane groups (they hold different rows m): dR component ksel(g)
+                // in lane group g, gathered into group 0; sum_k H_k R_k as one value
+                const acc dRg = sum_groups4(dR);
+                const acc hR = sum_groups(H[0] * Ra[0] + H[1] * Ra[1] + H[2] * Ra[2] + H[3] * Ra[3]);
+                const acc dR2 = __shfl(dRg, c16 + 16), dR1 = __shfl(dRg, c16 + 32), dR3 = __shfl(dRg, c16 + 48);
                 if (valid && g == 0) {
                     const double inc = A.inv_nc;
-                    const double d0 = inc * (double)dR[0], d1 = inc * (double)dR[1];
-                    const double d2 = inc * (double)dR[2], d3 = inc * (double)dR[3];
-                    const double dEds = inc * ((double)H[0] * (double)Ra[0] + (double)H[1] * (double)Ra[1] +
-                                               (double)H[2] * (double)Ra[2] + (double)H[3] * (double)Ra[3]);
+                    const double d0 = inc * (double)dRg, d1 = inc * (double)dR1;
+                    const double d2 = inc * (double)dR2, d3 = inc * (double)dR3;
+                    const double dEds = inc * (double)hR;
                     const double q = d1 * ux + d2 * uy + d3 * uz;
                     const double rad = (d0 + dEds) * ds + q * (ds - sr);
                     const double gx = rad * ux + sr * d1, gy = rad * uy + sr * d2, gz = rad * uz + sr * d3;
