@@ -250,18 +250,21 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
                                               const int* cell_of, const int* cell_start, const double4* cand,
                                               GeomParams gp, int* nl_j, double* nl_r, int* nnei, DevStats* st)
 {
-    __shared__ unsigned long long khi[CAP], klo[CAP];
-    __shared__ int kq[CAP];          // flat candidate index, moved with its key
-    __shared__ int s_base[NL_STENCIL + 1], s_start[NL_STENCIL], s_code[NL_STENCIL];
-    __shared__ int tcnt[MAXT];
+    // LDS sized per launch (nlist_lds_bytes): keys of CAP candidates, then the stencil tables
+    extern __shared__ __attribute__((aligned(16))) unsigned long long nl_lds[];
+    unsigned long long* khi = nl_lds;
+    unsigned long long* klo = khi + CAP;
+    int* kq = reinterpret_cast<int*>(klo + CAP);   // flat candidate index, moved with its key
+    const int S = (2 * gp.K[0] + 1) * (2 * gp.K[1] + 1) * (2 * gp.K[2] + 1);
+    int* s_base = kq + CAP;                        // [S + 1]
+    int* s_start = s_base + S + 1;                 // [S]
+    int* s_code = s_start + S;                     // [S]
     const int a = blockIdx.x, lane = threadIdx.x;
-    if (lane < MAXT) tcnt[lane] = 0;
     const double pi[3] = {pos[3 * (size_t)a], pos[3 * (size_t)a + 1], pos[3 * (size_t)a + 2]};
     const long long self_tag = (long long)a;
     const int ci = cell_of[a];
     const int bi[3] = {ci % gp.nb[0], (ci / gp.nb[0]) % gp.nb[1], ci / (gp.nb[0] * gp.nb[1])};
-    const int w0 = 2 * gp.K[0] + 1, w1 = 2 * gp.K[1] + 1, w2 = 2 * gp.K[2] + 1;
-    const int S = w0 * w1 * w2;
+    const int w1 = 2 * gp.K[1] + 1, w2 = 2 * gp.K[2] + 1;
     const int self_code = (64 << 14) | (64 << 7) | 64;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
@@ -312,6 +315,8 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
     __syncthreads();
 
     int count = 0;   // wave-uniform
+    int tcount[MAXT];   // wave-uniform, per type (may exceed CAP)
+    for (int t = 0; t < MAXT; ++t) tcount[t] = 0;
     int b = 0;       // this lane's current stencil bin
     for (int q0 = 0; q0 < total; q0 += 64 * NL_UNROLL) {
         double4 c4[NL_UNROLL];
@@ -348,18 +353,19 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
                 }
             }
             const unsigned long long m = __ballot(pass);
+            const int tj = (int)((unsigned long long)tag >> 60);
             if (pass) {
                 const int idx = count + __popcll(m & lt);
                 if (idx < CAP) {
-                    const int tj = (int)((unsigned long long)tag >> 60);
                     const unsigned long long jo = ((unsigned long long)tag >> 30) & 0x3fffffffull;
                     const unsigned long long rb = (unsigned long long)__double_as_longlong(r2);
                     khi[idx] = ((unsigned long long)tj << 59) | (rb >> 5);
                     klo[idx] = ((rb & 31ull) << 59) | (jo << 21) | (unsigned long long)code;
                     kq[idx] = cq[u];
-                    atomicAdd(&tcnt[tj], 1);
                 }
             }
+            // per-type counts from ballots (no shared-word atomics)
+            for (int t = 0; t < gp.ntypes; ++t) tcount[t] += __popcll(__ballot(pass && tj == t));
             count += __popcll(m);
         }
     }
@@ -371,42 +377,77 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
     if (count > CAP) count = CAP;
     int S2 = 64;
     while (S2 < count) S2 <<= 1;
-    for (int q = count + lane; q < S2; q += 64) { khi[q] = ~0ull; klo[q] = ~0ull; kq[q] = 0; }
     __syncthreads();
+    // Bitonic sort of the S2 <= CAP keys in registers: element e of this lane is position
+    // lane + 64 e. Pairs 64 or more apart sit in one lane; closer pairs are exchanged across lanes.
+    constexpr int E = CAP / 64;
+    const int EA = S2 >> 6;   // active elements per lane
+    unsigned long long kh[E], kl[E];
+    int kx[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane + 64 * e;
+        const bool have = i < count;
+        kh[e] = have ? khi[i] : ~0ull;
+        kl[e] = have ? klo[i] : ~0ull;
+        kx[e] = have ? kq[i] : 0;
+    }
     for (int k = 2; k <= S2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = lane; i < S2; i += 64) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const unsigned long long ah = khi[i], al = klo[i], bh = khi[ixj], bl = klo[ixj];
-                    const bool up = (i & k) == 0;
-                    if (key_less(bh, bl, ah, al) == up) {
-                        khi[i] = bh; klo[i] = bl; khi[ixj] = ah; klo[ixj] = al;
-                        const int t = kq[i];
-                        kq[i] = kq[ixj];
-                        kq[ixj] = t;
+            if (j >= 64) {
+#pragma unroll
+                for (int eb = 1; eb < E; eb <<= 1) {
+                    if (eb != (j >> 6)) continue;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        if ((e & eb) || e >= EA) continue;
+                        const int f = e | eb;
+                        const bool up = ((lane + 64 * e) & k) == 0;
+                        if (key_less(kh[f], kl[f], kh[e], kl[e]) == up) {
+                            const unsigned long long th = kh[e], tl = kl[e];
+                            const int tx = kx[e];
+                            kh[e] = kh[f]; kl[e] = kl[f]; kx[e] = kx[f];
+                            kh[f] = th; kl[f] = tl; kx[f] = tx;
+                        }
+                    }
+                }
+            } else {
+                const bool lower = (lane & j) == 0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if (e >= EA) continue;
+                    const unsigned long long ph = __shfl_xor(kh[e], j), pl = __shfl_xor(kl[e], j);
+                    const int px = __shfl_xor(kx[e], j);
+                    const bool up = ((lane + 64 * e) & k) == 0;
+                    const bool take = (lower == up) ? key_less(ph, pl, kh[e], kl[e]) : key_less(kh[e], kl[e], ph, pl);
+                    if (take) {
+                        kh[e] = ph;
+                        kl[e] = pl;
+                        kx[e] = px;
                     }
                 }
             }
-            __syncthreads();
         }
     }
     int tstart[MAXT], kept[MAXT];
     int acc = 0, drops = 0;
     for (int t = 0; t < gp.ntypes; ++t) {
         tstart[t] = acc;
-        acc += tcnt[t];
-        kept[t] = tcnt[t] < gp.sel[t] ? tcnt[t] : gp.sel[t];
-        drops += tcnt[t] - kept[t];
+        acc += tcount[t];
+        kept[t] = tcount[t] < gp.sel[t] ? tcount[t] : gp.sel[t];
+        drops += tcount[t] - kept[t];
     }
     const size_t rowj = (size_t)a * gp.nc;
-    for (int q = lane; q < count; q += 64) {
-        const int t = (int)(khi[q] >> 59);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int q = lane + 64 * e;
+        if (q >= count) continue;
+        const int t = (int)(kh[e] >> 59);
         const int rank = q - tstart[t];
         if (rank < gp.sel[t]) {
-            const int code = (int)(klo[q] & ((1ull << 21) - 1));
+            const int code = (int)(kl[e] & ((1ull << 21) - 1));
             const int n0 = (code >> 14) - 64, n1 = ((code >> 7) & 127) - 64, n2 = (code & 127) - 64;
-            const double4 c4 = cand[kq[q]];
+            const double4 c4 = cand[kx[e]];
             const int j = (int)(__double_as_longlong(c4.w) & 0x3fffffffll);
             double sh[3];
             image_shift(gp, n0, n1, n2, sh);
@@ -523,15 +564,19 @@ void launch_nlist(int n, const double* pos, const int* perm, const int* inv_perm
                   int* nnei, DevStats* st, hipStream_t s)
 {
     // candidate buffer sized from the expected count within r_c (the synchronous entry point reruns
-    // a frame that overflowed with the largest buffer)
-    if (gp.cap <= 256)
-        hipLaunchKernelGGL((k_nlist<256>), dim3(n), dim3(64), 0, s, n, pos, perm, inv_perm, cell_of, cell_start, cand,
-                           gp, nl_j, nl_r, nnei, st);
-    else if (gp.cap <= 512)
-        hipLaunchKernelGGL((k_nlist<512>), dim3(n), dim3(64), 0, s, n, pos, perm, inv_perm, cell_of, cell_start, cand,
-                           gp, nl_j, nl_r, nnei, st);
+    // a frame that overflowed with the largest buffer); LDS = 20 B per candidate slot + 12 B per
+    // stencil bin, so small stencils leave room for more resident waves
+    const int S = (2 * gp.K[0] + 1) * (2 * gp.K[1] + 1) * (2 * gp.K[2] + 1);
+    const int cap = gp.cap <= 256 ? 256 : (gp.cap <= 512 ? 512 : NL_CAP);
+    const size_t lds = (size_t)cap * 20 + (size_t)(3 * S + 1) * 4;
+    if (cap == 256)
+        hipLaunchKernelGGL((k_nlist<256>), dim3(n), dim3(64), lds, s, n, pos, perm, inv_perm, cell_of, cell_start,
+                           cand, gp, nl_j, nl_r, nnei, st);
+    else if (cap == 512)
+        hipLaunchKernelGGL((k_nlist<512>), dim3(n), dim3(64), lds, s, n, pos, perm, inv_perm, cell_of, cell_start,
+                           cand, gp, nl_j, nl_r, nnei, st);
     else
-        hipLaunchKernelGGL((k_nlist<NL_CAP>), dim3(n), dim3(64), 0, s, n, pos, perm, inv_perm, cell_of, cell_start,
+        hipLaunchKernelGGL((k_nlist<NL_CAP>), dim3(n), dim3(64), lds, s, n, pos, perm, inv_perm, cell_of, cell_start,
                            cand, gp, nl_j, nl_r, nnei, st);
 }
 
