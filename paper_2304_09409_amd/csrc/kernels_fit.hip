@@ -30,7 +30,6 @@ struct F8 {
 };
 
 constexpr int FX_G = 4;    // layer-1 K-chunks per D group
-constexpr int FX_MG = 4;   // D-row tiles per pass of the dD product
 
 // FP32 hyperbolic tangent on the hardware exp2 and reciprocal: 1 - 2 / (2^(2x log2 e) + 1).
 __device__ __forceinline__ float fx_tanh(float x)
@@ -89,15 +88,18 @@ __device__ __forceinline__ float sum_groups4(const float* p)
 }
 __device__ __forceinline__ int ksel(int g) { return ((g & 1) << 1) | (g >> 1); }
 
-template <int NAT, bool SPLIT>
-__global__ void __launch_bounds__(256) k_fitx(FitArgs A)
+template <int NAT, bool SPLIT, int NW>
+__global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
 {
     constexpr int NA = 16 * NAT;                       // atoms per block
     constexpr int FR = XF_ELEMS;
+    constexpr int TPW = (15 + NW - 1) / NW;            // feature tiles per wave (at most)
+    constexpr int NWA = NW / NAT;                      // waves sharing one atom tile's D fragments
+    static_assert(NW % NAT == 0 && NW % 4 == 0, "wave layout");
     // B operands [K-chunk][atom tile] (layer 1: two groups of FX_G chunks); at the end the
     // per-wave dT partials (floats) of the D rows n < 16.
     __shared__ __attribute__((aligned(16))) __bf16 s_b[XF_NCH2 * NAT * FR];
-    __shared__ float s_e[4][NA];
+    __shared__ float s_e[NW][NA];
     // rows padded to 17 entries so that the 16 atoms a wave touches at once fall in distinct banks
     __shared__ __attribute__((aligned(16))) float s_p1[NA][17][4];
     __shared__ __attribute__((aligned(16))) float s_tq[NA][17][4];     // T rows n < 16 of the block's atoms
@@ -112,15 +114,8 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
     const float* Tg = reinterpret_cast<const float*>(A.T);
     float* dTg = reinterpret_cast<float*>(A.dT);
     float* scr = reinterpret_cast<float*>(A.act) + (size_t)blk * NAT * XF_ACT;
-    const int nown = wave < 3 ? 4 : 3;                 // feature tiles w + 4i < 15
+    const int nown = (15 - wave + NW - 1) / NW;       // feature tiles wave + NW i < 15
 
-    int atom[NAT];
-    const float* Trow[NAT];
-#pragma unroll
-    for (int a = 0; a < NAT; ++a) {
-        atom[a] = a0 + 16 * a + c16;
-        Trow[a] = Tg + (size_t)(atom[a] < A.natoms ? atom[a] : a0) * (E2 * 4);
-    }
     // activation scratch of (layer l, feature tile t, atom tile a): this lane's four values
     auto sp = [&](int l, int t, int a) { return scr + (((l * 16 + t) * NAT + a) * 64 + lane) * 4; };
     auto sb = [&](int c, int a) { return s_b + (c * NAT + a) * FR; };
@@ -129,40 +124,37 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
     for (int ti = t_lo; ti <= t_hi; ++ti) {
         const float* fv = reinterpret_cast<const float*>(A.fvec) + (size_t)ti * FVEC;
         const __bf16* W = reinterpret_cast<const __bf16*>(A.fmat) + (size_t)ti * XF_NFRAG * FR;
-        bool mine[NAT];
-#pragma unroll
-        for (int a = 0; a < NAT; ++a) mine[a] = atom[a] < A.natoms && A.itype[atom[a]] == ti;
 
-        f4 acc[4][NAT];
-        float h[4][NAT][4];
+        f4 acc[TPW][NAT];
+        float h[TPW][NAT][4];
         auto zero_acc = [&]() {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TPW; ++i)
 #pragma unroll
                 for (int a = 0; a < NAT; ++a) acc[i][a] = f4{0.f, 0.f, 0.f, 0.f};
         };
         // acc[i][a] += sum over the 8 K-chunks of W(own tile i, c) B(c, a), B from s_b
         auto gemm8 = [&](const __bf16* Wm) {
             zero_acc();
-            F8 An[4];
+            F8 An[TPW];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (i < nown) An[i] = ld_frag<SPLIT>(Wm + (wave + 4 * i) * FR, lane);
+            for (int i = 0; i < TPW; ++i)
+                if (i < nown) An[i] = ld_frag<SPLIT>(Wm + (wave + NW * i) * FR, lane);
 #pragma unroll
             for (int c = 0; c < XF_NCH2; ++c) {
-                F8 Ac[4];
+                F8 Ac[TPW];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) Ac[i] = An[i];
+                for (int i = 0; i < TPW; ++i) Ac[i] = An[i];
                 if (c + 1 < XF_NCH2) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        if (i < nown) An[i] = ld_frag<SPLIT>(Wm + ((c + 1) * 15 + wave + 4 * i) * FR, lane);
+                    for (int i = 0; i < TPW; ++i)
+                        if (i < nown) An[i] = ld_frag<SPLIT>(Wm + ((c + 1) * 15 + wave + NW * i) * FR, lane);
                 }
                 F8 B[NAT];
 #pragma unroll
                 for (int a = 0; a < NAT; ++a) B[a] = ld_frag<SPLIT>(sb(c, a), lane);
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < TPW; ++i)
                     if (i < nown) {
 #pragma unroll
                         for (int a = 0; a < NAT; ++a) mma32<SPLIT>(acc[i][a], Ac[i], B[a]);
@@ -172,7 +164,7 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
         auto vec4 = [&](int off, int t) { return *reinterpret_cast<const f4*>(fv + off + 16 * t + 4 * g); };
 
         __syncthreads();   // s_b, s_e, s_p1 of the previous species are no longer read
-        for (int idx = threadIdx.x; idx < NA * 16; idx += 256) {
+        for (int idx = threadIdx.x; idx < NA * 16; idx += 64 * NW) {
             const int al = idx >> 4, n = idx & 15;
             const int at = a0 + al < A.natoms ? a0 + al : a0;
             *reinterpret_cast<f4*>(&s_tq[al][n][0]) = *reinterpret_cast<const f4*>(Tg + ((size_t)at * E2 + n) * 4);
@@ -180,18 +172,19 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
         // ------------------------------------------------------------ layer 1: D (1600) -> 240
         // D fragment of K-chunk c for atom tile `wave`: lane group g holds D[2c][4g+r] and
         // D[2c+1][4g+r], D[m][n] = sum_k T[m][k] T[n][k] (Sec. II.A.1, D = T T_<^T).
+        // wave w forms the D fragments of atom tile wa = w % NAT for the K-chunks cc = ph (mod NWA)
+        const int wa = wave % NAT, ph = wave / NAT;
+        const float* Tw = Tg + (size_t)(a0 + 16 * wa + c16 < A.natoms ? a0 + 16 * wa + c16 : a0) * (E2 * 4);
         float Tn[4][4];
-        if (wave < NAT) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const f4 v = *reinterpret_cast<const f4*>(Trow[wave] + (4 * g + r) * 4);
+        for (int r = 0; r < 4; ++r) {
+            const f4 v = *reinterpret_cast<const f4*>(Tw + (4 * g + r) * 4);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) Tn[r][k] = v[k];
-            }
+            for (int k = 0; k < 4; ++k) Tn[r][k] = v[k];
         }
         auto dfrag = [&](int c, __bf16* f) {
-            const f4 ta = *reinterpret_cast<const f4*>(Trow[wave] + (2 * c) * 4);
-            const f4 tb = *reinterpret_cast<const f4*>(Trow[wave] + (2 * c + 1) * 4);
+            const f4 ta = *reinterpret_cast<const f4*>(Tw + (2 * c) * 4);
+            const f4 tb = *reinterpret_cast<const f4*>(Tw + (2 * c + 1) * 4);
             float d0[4], d1[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -201,18 +194,17 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
             st_half<SPLIT>(f, lane, 0, d0);
             st_half<SPLIT>(f, lane, 1, d1);
         };
-        if (wave < NAT) {
 #pragma unroll
-            for (int cc = 0; cc < FX_G; ++cc) dfrag(cc, sb(cc, wave));
-        }
+        for (int cc = 0; cc < FX_G; ++cc)
+            if (cc % NWA == ph) dfrag(cc, sb(cc, wa));
         __syncthreads();
         {
             zero_acc();
             const __bf16* Wm = W + (size_t)XF_W1F * FR;
-            F8 An[4];
+            F8 An[TPW];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (i < nown) An[i] = ld_frag<SPLIT>(Wm + (wave + 4 * i) * FR, lane);
+            for (int i = 0; i < TPW; ++i)
+                if (i < nown) An[i] = ld_frag<SPLIT>(Wm + (wave + NW * i) * FR, lane);
             constexpr int NGRP = (XF_NCH1 + FX_G - 1) / FX_G;
 #pragma unroll 1
             for (int grp = 0; grp < NGRP; ++grp) {
@@ -221,25 +213,25 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
                 for (int cc = 0; cc < FX_G; ++cc) {
                     const int c = grp * FX_G + cc;
                     if (c < XF_NCH1) {
-                        F8 Ac[4];
+                        F8 Ac[TPW];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) Ac[i] = An[i];
+                        for (int i = 0; i < TPW; ++i) Ac[i] = An[i];
                         if (c + 1 < XF_NCH1) {
 #pragma unroll
-                            for (int i = 0; i < 4; ++i)
-                                if (i < nown) An[i] = ld_frag<SPLIT>(Wm + ((c + 1) * 15 + wave + 4 * i) * FR, lane);
+                            for (int i = 0; i < TPW; ++i)
+                                if (i < nown) An[i] = ld_frag<SPLIT>(Wm + ((c + 1) * 15 + wave + NW * i) * FR, lane);
                         }
                         F8 B[NAT];
 #pragma unroll
                         for (int a = 0; a < NAT; ++a) B[a] = ld_frag<SPLIT>(sb(p * FX_G + cc, a), lane);
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
+                        for (int i = 0; i < TPW; ++i)
                             if (i < nown) {
 #pragma unroll
                                 for (int a = 0; a < NAT; ++a) mma32<SPLIT>(acc[i][a], Ac[i], B[a]);
                             }
                         const int cn = c + FX_G;
-                        if (wave < NAT && cn < XF_NCH1) dfrag(cn, sb((p ^ 1) * FX_G + cc, wave));
+                        if (cn < XF_NCH1 && cc % NWA == ph) dfrag(cn, sb((p ^ 1) * FX_G + cc, wa));
                     }
                 }
                 __syncthreads();
@@ -247,9 +239,9 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
         }
         // a1 = tanh(W1 D + b1), h1 = wh1 a1
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TPW; ++i)
             if (i < nown) {
-                const int t = wave + 4 * i;
+                const int t = wave + NW * i;
                 const f4 b = vec4(FV_B1, t), wh = vec4(FV_WH1, t);
 #pragma unroll
                 for (int a = 0; a < NAT; ++a) {
@@ -263,7 +255,7 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
                     st_half<SPLIT>(sb(t >> 1, a), lane, t & 1, h[i][a]);
                 }
             }
-        if (wave == 3) {   // feature tile 15 does not exist: the second half of K-chunk 7 is zero
+        if (wave == NW - 1) {   // feature tile 15 does not exist: the second half of K-chunk 7 is zero
             const float z[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int a = 0; a < NAT; ++a) st_half<SPLIT>(sb(7, a), lane, 1, z);
@@ -276,9 +268,9 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
             __syncthreads();
             const int ob = layer == 2 ? FV_B2 : FV_B3, ow = layer == 2 ? FV_WH2 : FV_WH3;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TPW; ++i)
                 if (i < nown) {
-                    const int t = wave + 4 * i;
+                    const int t = wave + NW * i;
                     const f4 b = vec4(ob, t), wh = vec4(ow, t);
 #pragma unroll
                     for (int a = 0; a < NAT; ++a) {
@@ -300,9 +292,9 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
 #pragma unroll
             for (int a = 0; a < NAT; ++a) e[a] = 0.f;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TPW; ++i)
                 if (i < nown) {
-                    const f4 w4 = vec4(FV_W4, wave + 4 * i);
+                    const f4 w4 = vec4(FV_W4, wave + NW * i);
 #pragma unroll
                     for (int a = 0; a < NAT; ++a)
 #pragma unroll
@@ -319,9 +311,9 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
         // gh3 = wh4 w4, ga3 = gh3 wh3 (1 - a3^2); gh_{l-1} = W_l^T ga_l + gh_l, ga_l = gh_l wh_l (1 - a_l^2)
         const float wh4 = fv[FV_WH4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TPW; ++i)
             if (i < nown) {
-                const int t = wave + 4 * i;
+                const int t = wave + NW * i;
                 const f4 w4 = vec4(FV_W4, t), wh = vec4(FV_WH3, t);
 #pragma unroll
                 for (int a = 0; a < NAT; ++a) {
@@ -339,8 +331,11 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
         if (threadIdx.x < NA) {
             const int at = a0 + threadIdx.x;
             if (at < A.natoms && A.itype[at] == ti)
-                A.Ei[at] = (double)wh4 * ((double)s_e[0][threadIdx.x] + (double)s_e[1][threadIdx.x] +
-                                          (double)s_e[2][threadIdx.x] + (double)s_e[3][threadIdx.x] + (double)fv[FV_B4]);
+            {
+                double es = 0.0;
+                for (int w = 0; w < NW; ++w) es += (double)s_e[w][threadIdx.x];
+                A.Ei[at] = (double)wh4 * (es + (double)fv[FV_B4]);
+            }
         }
 #pragma unroll 1
         for (int layer = 3; layer >= 2; --layer) {
@@ -348,9 +343,9 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
             __syncthreads();
             const int ow = layer == 3 ? FV_WH2 : FV_WH1;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TPW; ++i)
                 if (i < nown) {
-                    const int t = wave + 4 * i;
+                    const int t = wave + NW * i;
                     const f4 wh = vec4(ow, t);
 #pragma unroll
                     for (int a = 0; a < NAT; ++a) {
@@ -370,82 +365,99 @@ __global__ void __launch_bounds__(256) k_fitx(FitArgs A)
         // D-row tile m of dD holds dD[m][n = 4g + r] for 16 atoms. dT[m][k] collects
         // sum_n dD[m][n] T[n][k] (part 1, reduced over lane groups) and, for rows n < 16,
         // sum_m dD[m][n] T[m][k] (part 2, q2, per wave; reduced over waves at the end).
+        // Waves form AG atom groups x 4 row groups: wave w takes atom tiles ag*NATD.. of its
+        // group ag = w % AG and the D-row tiles mw + 4j, mw = w / AG (each W1 fragment is read
+        // by AG waves, each ga1 fragment by 4 waves per atom group).
         {
-            float q2[NAT][4][4];
+            constexpr int AG = NW / 4, NATD = NAT / AG, MGD = NW == 4 ? 4 : 2;
+            const int ag = wave % AG, mw = wave / AG;
+            const float* Td[NATD];
+            int atd[NATD];
+            bool mined[NATD];
 #pragma unroll
-            for (int a = 0; a < NAT; ++a)
+            for (int a2 = 0; a2 < NATD; ++a2) {
+                const int at = a0 + 16 * (ag * NATD + a2) + c16;
+                atd[a2] = at;
+                Td[a2] = Tg + (size_t)(at < A.natoms ? at : a0) * (E2 * 4);
+                mined[a2] = at < A.natoms && A.itype[at] == ti;
+            }
+            float q2[NATD][4][4];
+#pragma unroll
+            for (int a2 = 0; a2 < NATD; ++a2)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) q2[a][r][k] = 0.f;
+                    for (int k = 0; k < 4; ++k) q2[a2][r][k] = 0.f;
             const __bf16* Wm = W + (size_t)XF_W1B * FR;
-            constexpr int NMT = E2 / 4;                // D-row tiles per wave: wave + 4 j
+            constexpr int NMT = E2 / 4;                   // D-row tiles per row group: mw + 4 j
 #pragma unroll 1
-            for (int j0 = 0; j0 < NMT; j0 += FX_MG) {
-                const int nm = min(FX_MG, NMT - j0);
-                f4 dd[FX_MG][NAT];
+            for (int j0 = 0; j0 < NMT; j0 += MGD) {
+                const int nm = min(MGD, NMT - j0);
+                f4 dd[MGD][NATD];
 #pragma unroll
-                for (int j = 0; j < FX_MG; ++j)
+                for (int j = 0; j < MGD; ++j)
 #pragma unroll
-                    for (int a = 0; a < NAT; ++a) dd[j][a] = f4{0.f, 0.f, 0.f, 0.f};
-                F8 An[FX_MG];
+                    for (int a2 = 0; a2 < NATD; ++a2) dd[j][a2] = f4{0.f, 0.f, 0.f, 0.f};
+                F8 An[MGD];
 #pragma unroll
-                for (int j = 0; j < FX_MG; ++j)
-                    if (j < nm) An[j] = ld_frag<SPLIT>(Wm + (wave + 4 * (j0 + j)) * FR, lane);
+                for (int j = 0; j < MGD; ++j)
+                    if (j < nm) An[j] = ld_frag<SPLIT>(Wm + (mw + 4 * (j0 + j)) * FR, lane);
 #pragma unroll 1
                 for (int c = 0; c < XF_NCH2; ++c) {
-                    F8 Ac[FX_MG];
+                    F8 Ac[MGD];
 #pragma unroll
-                    for (int j = 0; j < FX_MG; ++j) Ac[j] = An[j];
+                    for (int j = 0; j < MGD; ++j) Ac[j] = An[j];
                     if (c + 1 < XF_NCH2) {
 #pragma unroll
-                        for (int j = 0; j < FX_MG; ++j)
-                            if (j < nm) An[j] = ld_frag<SPLIT>(Wm + ((c + 1) * E2 + wave + 4 * (j0 + j)) * FR, lane);
+                        for (int j = 0; j < MGD; ++j)
+                            if (j < nm) An[j] = ld_frag<SPLIT>(Wm + ((c + 1) * E2 + mw + 4 * (j0 + j)) * FR, lane);
                     }
-                    F8 B[NAT];
+                    F8 B[NATD];
 #pragma unroll
-                    for (int a = 0; a < NAT; ++a) B[a] = ld_frag<SPLIT>(sb(c, a), lane);
+                    for (int a2 = 0; a2 < NATD; ++a2) B[a2] = ld_frag<SPLIT>(sb(c, ag * NATD + a2), lane);
 #pragma unroll
-                    for (int j = 0; j < FX_MG; ++j)
+                    for (int j = 0; j < MGD; ++j)
                         if (j < nm) {
 #pragma unroll
-                            for (int a = 0; a < NAT; ++a) mma32<SPLIT>(dd[j][a], Ac[j], B[a]);
+                            for (int a2 = 0; a2 < NATD; ++a2) mma32<SPLIT>(dd[j][a2], Ac[j], B[a2]);
                         }
                 }
 #pragma unroll
-                for (int j = 0; j < FX_MG; ++j)
+                for (int j = 0; j < MGD; ++j)
                     if (j < nm) {
-                        const int m = wave + 4 * (j0 + j);
+                        const int m = mw + 4 * (j0 + j);
 #pragma unroll
-                        for (int a = 0; a < NAT; ++a) {
-                            const f4 tm = *reinterpret_cast<const f4*>(Trow[a] + m * 4);
+                        for (int a2 = 0; a2 < NATD; ++a2) {
+                            const int al = 16 * (ag * NATD + a2) + c16;   // atom within the block
+                            const f4 tm = *reinterpret_cast<const f4*>(Td[a2] + m * 4);
                             float part[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                             for (int r = 0; r < 4; ++r) {
-                                const f4 tn = *reinterpret_cast<const f4*>(&s_tq[16 * a + c16][4 * g + r][0]);
+                                const f4 tn = *reinterpret_cast<const f4*>(&s_tq[al][4 * g + r][0]);
 #pragma unroll
                                 for (int k = 0; k < 4; ++k) {
-                                    part[k] += dd[j][a][r] * tn[k];
-                                    q2[a][r][k] += dd[j][a][r] * tm[k];
+                                    part[k] += dd[j][a2][r] * tn[k];
+                                    q2[a2][r][k] += dd[j][a2][r] * tm[k];
                                 }
                             }
                             const float pk = sum_groups4(part);   // lane group g: component ksel(g)
-                            if (m < 16) s_p1[16 * a + c16][m][ksel(g)] = pk;
-                            else if (mine[a]) dTg[((size_t)atom[a] * E2 + m) * 4 + ksel(g)] = pk;
+                            if (m < 16) s_p1[al][m][ksel(g)] = pk;
+                            else if (mined[a2]) dTg[((size_t)atd[a2] * E2 + m) * 4 + ksel(g)] = pk;
                         }
                     }
             }
             __syncthreads();   // every wave is done with ga1 in s_b
-            float* qs = reinterpret_cast<float*>(s_b);   // [wave][atom tile][lane][16]
+            // part 2 partials: slot (row group, atom tile) [lane][16], each written by one wave
+            float* qs = reinterpret_cast<float*>(s_b);
 #pragma unroll
-            for (int a = 0; a < NAT; ++a)
+            for (int a2 = 0; a2 < NATD; ++a2)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    *reinterpret_cast<f4*>(qs + ((wave * NAT + a) * 64 + lane) * 16 + 4 * r) =
-                        f4{q2[a][r][0], q2[a][r][1], q2[a][r][2], q2[a][r][3]};
+                    *reinterpret_cast<f4*>(qs + ((mw * NAT + ag * NATD + a2) * 64 + lane) * 16 + 4 * r) =
+                        f4{q2[a2][r][0], q2[a2][r][1], q2[a2][r][2], q2[a2][r][3]};
             __syncthreads();
-            // rows n < 16 of dT: part 1 + the four waves' part 2
-            for (int idx = threadIdx.x; idx < NA * 16; idx += 256) {
+            // rows n < 16 of dT: part 1 + the four row groups' part 2
+            for (int idx = threadIdx.x; idx < NA * 16; idx += 64 * NW) {
                 const int al = idx >> 4, n = idx & 15;
                 const int at = a0 + al;
                 if (at < A.natoms && A.itype[at] == ti) {
@@ -473,10 +485,10 @@ int fitx_tiles_per_block(int, int)
 void launch_fitx(bool split, const FitArgs& a, hipStream_t s)
 {
     if (a.natoms <= 0) return;
-    constexpr int NAT = 4;
-    dim3 grid((a.natoms + 16 * NAT - 1) / (16 * NAT)), block(256);
-    if (split) hipLaunchKernelGGL((k_fitx<NAT, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_fitx<NAT, false>), grid, block, 0, s, a);
+    constexpr int NAT = 4, NW = 8;
+    dim3 grid((a.natoms + 16 * NAT - 1) / (16 * NAT)), block(64 * NW);
+    if (split) hipLaunchKernelGGL((k_fitx<NAT, true, NW>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_fitx<NAT, false, NW>), grid, block, 0, s, a);
 }
 
 }  // namespace dpk
