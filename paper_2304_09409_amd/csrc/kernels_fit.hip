@@ -60,6 +60,25 @@ __device__ __forceinline__ F8 ld_frag(const __bf16* f, int lane)
     return r;
 }
 
+// Buffer-resource loads of the (read-only) weights: the per-lane part of an address is one VGPR
+// offset (lane * 16 B) shared by all loads, the fragment offset a scalar. Keeps 64-bit per-lane
+// addresses out of the register file; loads past num_records read 0.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+// Weight fragment f of the buffer r (fragment-major, XF_ELEMS BF16 values = 2 KB each).
+template <bool SPLIT>
+__device__ __forceinline__ F8 ld_wfrag(rsrc_t r, int lane16, int f)
+{
+    F8 x;
+    x.h = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(r, lane16, f * 2048, 0));
+    if constexpr (SPLIT) x.l = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(r, lane16, f * 2048 + 1024, 0));
+    else x.l = bf8{};
+    return x;
+}
+
 // Write four values (half `half` of a lane's eight) of a fragment in LDS, split into hi and lo.
 template <bool SPLIT>
 __device__ __forceinline__ void st_half(__bf16* f, int lane, int half, const float* x)
@@ -104,7 +123,8 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
     __shared__ __attribute__((aligned(16))) float s_p1[NA][17][4];
     __shared__ __attribute__((aligned(16))) float s_tq[NA][17][4];     // T rows n < 16 of the block's atoms
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar registers)
+    const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     const int nblk = gridDim.x, xcd = blockIdx.x & 7, per = nblk >> 3, rem = nblk & 7;
     const int blk = xcd * per + min(xcd, rem) + (blockIdx.x >> 3);
     const int a0 = blk * NA;
@@ -117,13 +137,21 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
     const int nown = (15 - wave + NW - 1) / NW;       // feature tiles wave + NW i < 15
 
     // activation scratch of (layer l, feature tile t, atom tile a): this lane's four values
-    auto sp = [&](int l, int t, int a) { return scr + (((l * 16 + t) * NAT + a) * 64 + lane) * 4; };
+    const int lane16 = lane * 16;
+    // this lane's four values of (layer l, feature tile t, atom tile a) in the scratch: a
+    // wave-uniform base plus the lane's 16-byte offset (read back by the same lane)
+    const unsigned ulane16 = (unsigned)lane16;
+    auto sptr = [&](int l, int t, int a) {
+        char* base = reinterpret_cast<char*>(scr) + (unsigned)(((l * 16 + t) * NAT + a) * 1024);
+        return reinterpret_cast<f4*>(base + ulane16);
+    };
     auto sb = [&](int c, int a) { return s_b + (c * NAT + a) * FR; };
 
 #pragma unroll 1
     for (int ti = t_lo; ti <= t_hi; ++ti) {
         const float* fv = reinterpret_cast<const float*>(A.fvec) + (size_t)ti * FVEC;
         const __bf16* W = reinterpret_cast<const __bf16*>(A.fmat) + (size_t)ti * XF_NFRAG * FR;
+        const rsrc_t wrs = make_rsrc(W, XF_NFRAG * FR * 2);
 
         f4 acc[TPW][NAT];
         float h[TPW][NAT][4];
@@ -133,13 +161,21 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
 #pragma unroll
                 for (int a = 0; a < NAT; ++a) acc[i][a] = f4{0.f, 0.f, 0.f, 0.f};
         };
-        // acc[i][a] += sum over the 8 K-chunks of W(own tile i, c) B(c, a), B from s_b
-        auto gemm8 = [&](const __bf16* Wm) {
+        // First K-chunk weight fragments of the next 240-wide product, requested before the
+        // preceding epilogue and barrier so that their latency is hidden.
+        F8 Apf[TPW];
+        auto prefetch8 = [&](int wb) {
+#pragma unroll
+            for (int i = 0; i < TPW; ++i)
+                if (i < nown) Apf[i] = ld_wfrag<SPLIT>(wrs, lane16, wb + wave + NW * i);
+        };
+        // acc[i][a] = sum over the 8 K-chunks of W(own tile i, c) B(c, a), B from s_b; Apf must
+        // hold the first chunk of product wb (prefetch8)
+        auto gemm8 = [&](int wb) {
             zero_acc();
             F8 An[TPW];
 #pragma unroll
-            for (int i = 0; i < TPW; ++i)
-                if (i < nown) An[i] = ld_frag<SPLIT>(Wm + (wave + NW * i) * FR, lane);
+            for (int i = 0; i < TPW; ++i) An[i] = Apf[i];
 #pragma unroll
             for (int c = 0; c < XF_NCH2; ++c) {
                 F8 Ac[TPW];
@@ -148,7 +184,7 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
                 if (c + 1 < XF_NCH2) {
 #pragma unroll
                     for (int i = 0; i < TPW; ++i)
-                        if (i < nown) An[i] = ld_frag<SPLIT>(Wm + ((c + 1) * 15 + wave + NW * i) * FR, lane);
+                        if (i < nown) An[i] = ld_wfrag<SPLIT>(wrs, lane16, wb + (c + 1) * 15 + wave + NW * i);
                 }
                 F8 B[NAT];
 #pragma unroll
@@ -200,11 +236,11 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
         __syncthreads();
         {
             zero_acc();
-            const __bf16* Wm = W + (size_t)XF_W1F * FR;
+            const int wb = XF_W1F;
             F8 An[TPW];
 #pragma unroll
             for (int i = 0; i < TPW; ++i)
-                if (i < nown) An[i] = ld_frag<SPLIT>(Wm + (wave + NW * i) * FR, lane);
+                if (i < nown) An[i] = ld_wfrag<SPLIT>(wrs, lane16, wb + wave + NW * i);
             constexpr int NGRP = (XF_NCH1 + FX_G - 1) / FX_G;
 #pragma unroll 1
             for (int grp = 0; grp < NGRP; ++grp) {
@@ -219,7 +255,7 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
                         if (c + 1 < XF_NCH1) {
 #pragma unroll
                             for (int i = 0; i < TPW; ++i)
-                                if (i < nown) An[i] = ld_frag<SPLIT>(Wm + ((c + 1) * 15 + wave + NW * i) * FR, lane);
+                                if (i < nown) An[i] = ld_wfrag<SPLIT>(wrs, lane16, wb + (c + 1) * 15 + wave + NW * i);
                         }
                         F8 B[NAT];
 #pragma unroll
@@ -237,6 +273,7 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
                 __syncthreads();
             }
         }
+        prefetch8(XF_W2F);
         // a1 = tanh(W1 D + b1), h1 = wh1 a1
 #pragma unroll
         for (int i = 0; i < TPW; ++i)
@@ -251,7 +288,7 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
                         av[r] = fx_tanh(acc[i][a][r] + b[r]);
                         h[i][a][r] = wh[r] * av[r];
                     }
-                    *reinterpret_cast<f4*>(sp(0, t, a)) = av;
+                    *sptr(0, t, a) = av;
                     st_half<SPLIT>(sb(t >> 1, a), lane, t & 1, h[i][a]);
                 }
             }
@@ -264,7 +301,8 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
         // ------------------------------------------------------------ layers 2, 3: h += wh tanh(W h + b)
 #pragma unroll 1
         for (int layer = 2; layer <= 3; ++layer) {
-            gemm8(W + (size_t)(layer == 2 ? XF_W2F : XF_W3F) * FR);
+            gemm8(layer == 2 ? XF_W2F : XF_W3F);
+            prefetch8(layer == 2 ? XF_W3F : XF_W3B);
             __syncthreads();
             const int ob = layer == 2 ? FV_B2 : FV_B3, ow = layer == 2 ? FV_WH2 : FV_WH3;
 #pragma unroll
@@ -280,7 +318,7 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
                             av[r] = fx_tanh(acc[i][a][r] + b[r]);
                             h[i][a][r] += wh[r] * av[r];
                         }
-                        *reinterpret_cast<f4*>(sp(layer - 1, t, a)) = av;
+                        *sptr(layer - 1, t, a) = av;
                         if (layer == 2) st_half<SPLIT>(sb(t >> 1, a), lane, t & 1, h[i][a]);
                     }
                 }
@@ -317,7 +355,7 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
                 const f4 w4 = vec4(FV_W4, t), wh = vec4(FV_WH3, t);
 #pragma unroll
                 for (int a = 0; a < NAT; ++a) {
-                    const f4 av = *reinterpret_cast<const f4*>(sp(2, t, a));
+                    const f4 av = *sptr(2, t, a);
                     float ga[4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
@@ -339,7 +377,8 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
         }
 #pragma unroll 1
         for (int layer = 3; layer >= 2; --layer) {
-            gemm8(W + (size_t)(layer == 3 ? XF_W3B : XF_W2B) * FR);
+            gemm8(layer == 3 ? XF_W3B : XF_W2B);
+            if (layer == 3) prefetch8(XF_W2B);
             __syncthreads();
             const int ow = layer == 3 ? FV_WH2 : FV_WH1;
 #pragma unroll
@@ -349,7 +388,7 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
                     const f4 wh = vec4(ow, t);
 #pragma unroll
                     for (int a = 0; a < NAT; ++a) {
-                        const f4 av = *reinterpret_cast<const f4*>(sp(layer - 2, t, a));
+                        const f4 av = *sptr(layer - 2, t, a);
                         float ga[4];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
@@ -388,63 +427,80 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
                 for (int r = 0; r < 4; ++r)
 #pragma unroll
                     for (int k = 0; k < 4; ++k) q2[a2][r][k] = 0.f;
-            const __bf16* Wm = W + (size_t)XF_W1B * FR;
+            const int wb = XF_W1B;
             constexpr int NMT = E2 / 4;                   // D-row tiles per row group: mw + 4 j
+            constexpr int NPASS = (NMT + MGD - 1) / MGD;
+            // one flat loop over (pass, K-chunk): the weight fragments of the next step, also
+            // across a pass boundary, are requested one step ahead
+            auto wfrag = [&](int pass, int c, int j) {
+                return ld_wfrag<SPLIT>(wrs, lane16, wb + c * E2 + mw + 4 * (pass * MGD + j));
+            };
+            F8 An[MGD];
+#pragma unroll
+            for (int j = 0; j < MGD; ++j)
+                if (j < NMT) An[j] = wfrag(0, 0, j);
+            f4 dd[MGD][NATD];
+            f4 tmv[MGD][NATD];
 #pragma unroll 1
-            for (int j0 = 0; j0 < NMT; j0 += MGD) {
-                const int nm = min(MGD, NMT - j0);
-                f4 dd[MGD][NATD];
-#pragma unroll
-                for (int j = 0; j < MGD; ++j)
-#pragma unroll
-                    for (int a2 = 0; a2 < NATD; ++a2) dd[j][a2] = f4{0.f, 0.f, 0.f, 0.f};
-                F8 An[MGD];
-#pragma unroll
-                for (int j = 0; j < MGD; ++j)
-                    if (j < nm) An[j] = ld_frag<SPLIT>(Wm + (mw + 4 * (j0 + j)) * FR, lane);
-#pragma unroll 1
-                for (int c = 0; c < XF_NCH2; ++c) {
-                    F8 Ac[MGD];
-#pragma unroll
-                    for (int j = 0; j < MGD; ++j) Ac[j] = An[j];
-                    if (c + 1 < XF_NCH2) {
-#pragma unroll
-                        for (int j = 0; j < MGD; ++j)
-                            if (j < nm) An[j] = ld_frag<SPLIT>(Wm + ((c + 1) * E2 + mw + 4 * (j0 + j)) * FR, lane);
-                    }
-                    F8 B[NATD];
-#pragma unroll
-                    for (int a2 = 0; a2 < NATD; ++a2) B[a2] = ld_frag<SPLIT>(sb(c, ag * NATD + a2), lane);
+            for (int step = 0; step < NPASS * XF_NCH2; ++step) {
+                const int pass = step / XF_NCH2, c = step - pass * XF_NCH2;
+                const int nm = min(MGD, NMT - pass * MGD);
+                if (c == 0) {
 #pragma unroll
                     for (int j = 0; j < MGD; ++j)
-                        if (j < nm) {
 #pragma unroll
-                            for (int a2 = 0; a2 < NATD; ++a2) mma32<SPLIT>(dd[j][a2], Ac[j], B[a2]);
+                        for (int a2 = 0; a2 < NATD; ++a2) {
+                            dd[j][a2] = f4{0.f, 0.f, 0.f, 0.f};
+                            // rows T[m] of this pass, used by the epilogue
+                            const int m = mw + 4 * (pass * MGD + (j < nm ? j : 0));
+                            tmv[j][a2] = *reinterpret_cast<const f4*>(Td[a2] + m * 4);
                         }
                 }
+                F8 Ac[MGD];
+#pragma unroll
+                for (int j = 0; j < MGD; ++j) Ac[j] = An[j];
+                if (step + 1 < NPASS * XF_NCH2) {
+                    const int pn = (step + 1) / XF_NCH2, cn = step + 1 - pn * XF_NCH2;
+                    const int nmn = min(MGD, NMT - pn * MGD);
+#pragma unroll
+                    for (int j = 0; j < MGD; ++j)
+                        if (j < nmn) An[j] = wfrag(pn, cn, j);
+                }
+                F8 B[NATD];
+#pragma unroll
+                for (int a2 = 0; a2 < NATD; ++a2) B[a2] = ld_frag<SPLIT>(sb(c, ag * NATD + a2), lane);
 #pragma unroll
                 for (int j = 0; j < MGD; ++j)
                     if (j < nm) {
-                        const int m = mw + 4 * (j0 + j);
 #pragma unroll
-                        for (int a2 = 0; a2 < NATD; ++a2) {
-                            const int al = 16 * (ag * NATD + a2) + c16;   // atom within the block
-                            const f4 tm = *reinterpret_cast<const f4*>(Td[a2] + m * 4);
-                            float part[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                const f4 tn = *reinterpret_cast<const f4*>(&s_tq[al][4 * g + r][0]);
-#pragma unroll
-                                for (int k = 0; k < 4; ++k) {
-                                    part[k] += dd[j][a2][r] * tn[k];
-                                    q2[a2][r][k] += dd[j][a2][r] * tm[k];
-                                }
-                            }
-                            const float pk = sum_groups4(part);   // lane group g: component ksel(g)
-                            if (m < 16) s_p1[al][m][ksel(g)] = pk;
-                            else if (mined[a2]) dTg[((size_t)atd[a2] * E2 + m) * 4 + ksel(g)] = pk;
-                        }
+                        for (int a2 = 0; a2 < NATD; ++a2) mma32<SPLIT>(dd[j][a2], Ac[j], B[a2]);
                     }
+                if (c == XF_NCH2 - 1) {
+#pragma unroll
+                    for (int a2 = 0; a2 < NATD; ++a2) {
+                        const int al = 16 * (ag * NATD + a2) + c16;   // atom within the block
+                        f4 tn[4];                                     // T rows 4g..4g+3 of the atom
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) tn[r] = *reinterpret_cast<const f4*>(&s_tq[al][4 * g + r][0]);
+#pragma unroll
+                        for (int j = 0; j < MGD; ++j)
+                            if (j < nm) {
+                                const int m = mw + 4 * (pass * MGD + j);
+                                const f4 tm = tmv[j][a2];
+                                float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                                    for (int k = 0; k < 4; ++k) {
+                                        part[k] += dd[j][a2][r] * tn[r][k];
+                                        q2[a2][r][k] += dd[j][a2][r] * tm[k];
+                                    }
+                                const float pk = sum_groups4(part);   // lane group g: component ksel(g)
+                                if (m < 16) s_p1[al][m][ksel(g)] = pk;
+                                else if (mined[a2]) dTg[((size_t)atd[a2] * E2 + m) * 4 + ksel(g)] = pk;
+                            }
+                    }
+                }
             }
             __syncthreads();   // every wave is done with ga1 in s_b
             // part 2 partials: slot (row group, atom tile) [lane][16], each written by one wave
