@@ -239,6 +239,8 @@ __device__ __forceinline__ void switch_fn(double r, double rs, double rc, double
     }
 }
 
+constexpr int ZS = 20;   // row stride (floats) of the feature-major skip buffers; 16 neighbours used
+
 // Launch shape of the embedding kernels: NW waves per block, APW atoms per wave. Split-BF16 runs
 // 8 waves (two per SIMD) sharing one staged net; FP64 runs 4 and keeps W3^T in global memory
 // (L1/L2) to leave LDS for the wider activation buffers.
@@ -349,12 +351,16 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
     __shared__ acc s_vec[EVEC];
     __shared__ __attribute__((aligned(16))) char s_w2[TAB ? 16 : N2P * Cfg::ROW2];
     __shared__ __attribute__((aligned(16))) char s_w3[(TAB || !W3LDS) ? 16 : N3P * Cfg::ROW3];
-    __shared__ acc s_z1[TAB ? 1 : NW][16][E0 + 1];
+    // layer outputs kept for the skip connections. z1 is stored feature-major with rows of ZS = 20
+    // (lane (p, g) touches feature f0 + 4g of neighbour p: bank 16g + p, conflict-free); z2 is
+    // neighbour-major here because the untransposed layer 3 reads it as (neighbour 4g + r, feature p).
+    __shared__ acc s_z1[TAB ? 1 : NW][E0][ZS];
     __shared__ acc s_z2[TAB ? 1 : NW][16][E1 + 2];
     __shared__ acc s_R[NW][16][4];
     __shared__ double s_x[NW][16];
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar registers)
+    const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     const int a0 = blockIdx.x * APB;
     const int a1 = min(a0 + APB, A.natoms);
     if (a0 >= a1) return;
@@ -445,7 +451,7 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
                             zz[v] = 0;
                             if (k < E0) {
                                 zz[v] = s_vec[EV_WH1 + k] * P::act((acc)s * s_vec[EV_W1 + k] + s_vec[EV_B1 + k]);
-                                s_z1[wave][p][k] = zz[v];
+                                s_z1[wave][k][p] = zz[v];
                             }
                         }
                         B1[c] = P::make(zz);
@@ -464,7 +470,7 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
                             const int n = 16 * t + P::orow(g, r);
                             zt[t][r] = 0;
                             if (n < E1) {
-                                zt[t][r] = s_vec[EV_WH2 + n] * P::act(acc2[t][r] + s_vec[EV_B2 + n]) + s_z1[wave][p][n % E0];
+                                zt[t][r] = s_vec[EV_WH2 + n] * P::act(acc2[t][r] + s_vec[EV_B2 + n]) + s_z1[wave][n % E0][p];
                                 s_z2[wave][p][n] = zt[t][r];
                             }
                         }
@@ -532,14 +538,17 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
     __shared__ acc s_vec[EVEC];
     __shared__ __attribute__((aligned(16))) char s_w2[TAB ? 16 : N2P * Cfg::ROW2];
     __shared__ __attribute__((aligned(16))) char s_w3[(TAB || !W3LDS) ? 16 : N3P * Cfg::ROW3];
-    __shared__ acc s_z1[TAB ? 1 : NW][16][E0 + 1];
-    __shared__ acc s_z1d[TAB ? 1 : NW][16][E0 + 1];
-    __shared__ acc s_z2[TAB ? 1 : NW][16][E1 + 2];
-    __shared__ acc s_z2d[TAB ? 1 : NW][16][E1 + 2];
+    // layer outputs and their s-derivatives for the skip connections, feature-major with rows of
+    // ZS = 20: every access is lane (p, g) -> feature f0 + 4g of neighbour p, bank 16g + p
+    __shared__ acc s_z1[TAB ? 1 : NW][E0][ZS];
+    __shared__ acc s_z1d[TAB ? 1 : NW][E0][ZS];
+    __shared__ acc s_z2[TAB ? 1 : NW][E1][ZS];
+    __shared__ acc s_z2d[TAB ? 1 : NW][E1][ZS];
     __shared__ __attribute__((aligned(16))) acc s_dT[NW][E2][4];
     __shared__ double s_vir[NW][9];
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar registers)
+    const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     const int a0 = blockIdx.x * APB;
     const int a1 = min(a0 + APB, A.natoms);
     double vir[9];
@@ -641,8 +650,8 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
                                 const acc t1 = P::act((acc)s * w1 + s_vec[EV_B1 + k]);
                                 zz[v] = wh * t1;
                                 zd[v] = wh * (1 - t1 * t1) * w1;
-                                s_z1[wave][p][k] = zz[v];
-                                s_z1d[wave][p][k] = zd[v];
+                                s_z1[wave][k][p] = zz[v];
+                                s_z1d[wave][k][p] = zd[v];
                             }
                         }
                         B1[c] = P::make(zz);
@@ -668,10 +677,10 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
                             if (n < E1) {
                                 const acc t2 = P::act(acc2[t][rr] + s_vec[EV_B2 + n]);
                                 const acc wh = s_vec[EV_WH2 + n];
-                                zt[t][rr] = wh * t2 + s_z1[wave][p][n % E0];
-                                ztd[t][rr] = wh * (1 - t2 * t2) * acc2d[t][rr] + s_z1d[wave][p][n % E0];
-                                s_z2[wave][p][n] = zt[t][rr];
-                                s_z2d[wave][p][n] = ztd[t][rr];
+                                zt[t][rr] = wh * t2 + s_z1[wave][n % E0][p];
+                                ztd[t][rr] = wh * (1 - t2 * t2) * acc2d[t][rr] + s_z1d[wave][n % E0][p];
+                                s_z2[wave][n][p] = zt[t][rr];
+                                s_z2d[wave][n][p] = ztd[t][rr];
                             }
                         }
                     // output tiles -> K-chunks of layer 3 (chunk c, value v: tile c*KC/16 + v/4, row v%4)
@@ -704,8 +713,8 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
                             if (m >= E2) continue;
                             const acc t3 = P::act(acc3[tm][rr] + s_vec[EV_B3 + m]);
                             const acc wh = s_vec[EV_WH3 + m];
-                            const acc G = wh * t3 + s_z2[wave][p][m % E1];
-                            const acc Gd = wh * (1 - t3 * t3) * acc3d[tm][rr] + s_z2d[wave][p][m % E1];
+                            const acc G = wh * t3 + s_z2[wave][m % E1][p];
+                            const acc Gd = wh * (1 - t3 * t3) * acc3d[tm][rr] + s_z2d[wave][m % E1][p];
                             const acc* dt = s_dT[wave][m];
                             dR[0] += G * dt[0]; dR[1] += G * dt[1]; dR[2] += G * dt[2]; dR[3] += G * dt[3];
                             H[0] += Gd * dt[0]; H[1] += Gd * dt[1]; H[2] += Gd * dt[2]; H[3] += Gd * dt[3];
@@ -859,7 +868,8 @@ __global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
     __shared__ __attribute__((aligned(32))) char s_w[2][SW::BYTES];
     __shared__ acc s_p1[4][16][16][4];
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar registers)
+    const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     const int a0 = blockIdx.x * FIT_AF;
     const int a1 = min(a0 + FIT_AF, A.natoms);
     if (a0 >= a1) return;
