@@ -22,25 +22,42 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Published MI355X peaks (dense) and derived per-unit ceilings used for the roofline fields.
+# Published MI355X peaks (dense) used for the roofline fields.
 PEAK = {
     "hbm": 8000.0,          # GB/s
     "fp64_mfma": 78.6,      # TFLOP/s
     "bf16_mfma": 2500.0,    # TFLOP/s
+    "fp32_valu": 157.3,     # TFLOP/s (256 CU x 4 SIMD x 16 lanes x 2 flop x 2 (packed) x 2.4 GHz)
 }
+
+# Algorithmic FP32 vector work per real neighbour pair of the BF16-path embedding kernels (the
+# GEMMs of layers 2 and 3 run on the matrix cores and are not counted here). tanh is counted as
+# 6 flop (scale, exp, add, reciprocal, fused multiply-add), an FMA as 2.
+#   forward: layer 1 25 x (2 pre + 6 tanh + 1 scale) + layer 2 50 x (1 bias + 6 + 2 skip)
+#            + layer 3 100 x (1 + 6 + 2 + 8 for T += G R)                         = 2,375 flop
+#   adjoint: layer 1 25 x (2 + 6 + 1 + 4 derivative) + layer 2 50 x (1 + 6 + 2 + 5)
+#            + layer 3 100 x (1 + 6 + 2 + 5 + 8 dE/dR + 8 dE/ds) + chain rule ~50  = 4,075 flop
+VALU_FLOP_PER_PAIR = {"embed_fwd": 2375.0, "embed_bwd": 4075.0}
 
 
 def work_per_launch(stage: str, precision: str, natoms: int, npairs: int, nc: int):
-    """Algorithmic work of one launch of a stage: (bound, amount, peak, unit).
+    """Algorithmic work of one launch of a stage against the unit that bounds it: (bound, amount,
+    peak, unit).
 
-    Per real neighbour pair: embedding layers 2 + 3 = 2 (25*50 + 50*100) = 12,500 flop, layer 1
-    50 flop, contraction G^T R 800 flop. The forward kernel computes G once (13,350 flop per
-    pair); the adjoint re-evaluates G and dG/ds (25,100), then dE/dR = G dT and (dG/ds) dT
-    (1,600) and the chain rule (~50): 26,750 flop per pair. Fitting per atom: D = T T_<^T 12,800,
-    forward 2 (1600*240 + 2*240^2 + 240) = 998,880, input gradient 2 (1600*240 + 2*240^2) =
-    998,400, dT 25,600: 2,035,680 flop. The neighbour list moves, per atom, the coordinates of the
-    candidates it reads once (24 B x 27 bins' atoms is served from cache) and writes its list:
-    N_c (4 B index + 24 B vector) + the per-type counts."""
+    Matrix work per real neighbour pair: embedding layers 2 + 3 = 2 (25*50 + 50*100) = 12,500
+    flop, layer 1 50 flop, contraction G^T R 800 flop. The forward kernel computes G once (13,350
+    flop per pair); the adjoint re-evaluates G and dG/ds (25,100), then dE/dR = G dT and (dG/ds)
+    dT (1,600) and the chain rule (~50): 26,750 flop per pair. Fitting per atom: D = T T_<^T
+    12,800, forward 2 (1600*240 + 2*240^2 + 240) = 998,880, input gradient 2 (1600*240 +
+    2*240^2) = 998,400, dT 25,600: 2,035,680 flop. The neighbour list moves, per atom, the
+    coordinates of the candidates it reads once (24 B x 27 bins' atoms is served from cache) and
+    writes its list: N_c (4 B index + 24 B vector) + the per-type counts.
+
+    FP64 path: every stage is priced against the FP64 matrix peak. BF16 paths: the fitting net
+    against the BF16 matrix peak (each FP32-accurate product is three BF16 products, so a
+    saturated kernel shows 1/3); the embedding kernels are bound by the vector ALU (the
+    activations and their derivatives; counters show the VALU far busier than the matrix cores)
+    and are priced by VALU_FLOP_PER_PAIR against the FP32 vector peak."""
     if stage == "embed_fwd":
         flops = 13350.0 * npairs
     elif stage == "embed_bwd":
@@ -52,9 +69,8 @@ def work_per_launch(stage: str, precision: str, natoms: int, npairs: int, nc: in
         return "hbm", bytes_ / 1e9, PEAK["hbm"], "GB/s"
     if precision == "fp64":
         return "mfma", flops / 1e12, PEAK["fp64_mfma"], "TFLOP/s"
-    # mixed: the contractions run on the BF16 matrix cores, each FP32 product as three BF16
-    # products (hi*hi + hi*lo + lo*hi); achieved counts the algorithmic flops once, so the
-    # fraction of the BF16 dense peak is at most 1/3 even for a saturated kernel.
+    if stage in VALU_FLOP_PER_PAIR:
+        return "alu", VALU_FLOP_PER_PAIR[stage] * npairs / 1e12, PEAK["fp32_valu"], "TFLOP/s"
     return "mfma", flops / 1e12, PEAK["bf16_mfma"], "TFLOP/s"
 
 
@@ -248,6 +264,12 @@ def main():
     achieved = amount / (head["stage_ms"][dom] * 1e-3)
     roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": stored_traffic(dom, "mixed")}
+    stage_roof = {}
+    for st in ("nlist", "embed_fwd", "fit", "embed_bwd"):
+        b_, a_, p_, u_ = work_per_launch(st, "mixed", n, npairs, model.nc)
+        ach = a_ / (head["stage_ms"][st] * 1e-3)
+        stage_roof[st] = {"bound": b_, "achieved": ach, "peak": p_, "unit": u_, "frac": ach / p_,
+                          "ms": head["stage_ms"][st]}
     fp64_dom = max(runs["fp64"]["stage_ms"], key=runs["fp64"]["stage_ms"].get)
     b2, a2, p2, u2 = work_per_launch(fp64_dom, "fp64", n, npairs, model.nc)
     ach2 = a2 / (runs["fp64"]["stage_ms"][fp64_dom] * 1e-3)
@@ -277,6 +299,7 @@ def main():
         "speedup_mixed_vs_fp64": head["value"] / runs["fp64"]["value"],
         "force_error_vs_oracle": errs or None,
         "roofline": roof,
+        "stage_roofline": stage_roof,
         "serving": serving,
         "cpu_baseline": cpu,
     }
