@@ -234,6 +234,11 @@ struct dpk_ctx {
     int *nl_j, *nnei, *h_atype, *bcount, *boff;
     double *pos, *nl_r, *Ei, *F, *vir_part, *bbox, *h_coord, *h_out;
     double4* cand;
+    int* frame_of;                       // batched frames: frame of each internal atom
+    double* vir_atom;                    // batched frames: virial per centre atom [N][9]
+    FrameDesc* fd;                       // batched frames: [BATCH_MAX_FRAMES]
+    GeomParams* gps;                     // batched frames: [BATCH_MAX_FRAMES]
+    void* pin_desc = nullptr;            // pinned staging of fd and gps
     void *T, *dT, *act;
     DevStats* stats;
     int64_t vir_blocks = 0;
@@ -298,7 +303,11 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
     p = take(sizeof(double) * 8); if (base) c->bbox = (double*)p;
     p = take(sizeof(double) * 3 * n); if (base) c->h_coord = (double*)p;
     p = take(sizeof(int) * n); if (base) c->h_atype = (int*)p;
-    p = take(sizeof(double) * (10 + 4 * n)); if (base) c->h_out = (double*)p;
+    p = take(sizeof(double) * (10 * BATCH_MAX_FRAMES + 4 * n)); if (base) c->h_out = (double*)p;
+    p = take(sizeof(int) * n); if (base) c->frame_of = (int*)p;
+    p = take(sizeof(double) * 9 * n); if (base) c->vir_atom = (double*)p;
+    p = take(sizeof(FrameDesc) * BATCH_MAX_FRAMES); if (base) c->fd = (FrameDesc*)p;
+    p = take(sizeof(GeomParams) * BATCH_MAX_FRAMES); if (base) c->gps = (GeomParams*)p;
     return off;
 }
 
@@ -531,6 +540,157 @@ int upload_model(dpk_ctx* c)
     return DPK_OK;
 }
 
+// Embedding, fitting and adjoint over n atoms (internal order), after the neighbour list.
+// vir_atom == nullptr: virial as per-block partials; else per centre atom (batched frames).
+void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* vir_atom, std::vector<hipEvent_t>* ev, hipStream_t s)
+{
+    const dpk_model* m = c->model;
+    const int nt = m->desc.ntypes;
+    EmbArgs ea;
+    std::memset(&ea, 0, sizeof(ea));
+    ea.natoms = n;
+    ea.ntypes = nt;
+    ea.nc = m->nc;
+    ea.type_one_side = m->desc.type_one_side;
+    for (int t = 0; t < nt; ++t) ea.off[t] = gp.off[t];
+    ea.itype = c->itype;
+    ea.nnei = c->nnei;
+    ea.nl_j = c->nl_j;
+    ea.nl_r = c->nl_r;
+    ea.rs = m->desc.rcut_smth;
+    ea.rc = m->desc.rcut;
+    ea.inv_nc = 1.0 / m->nc;
+    ea.evec = c->evec;
+    ea.emat = c->emat;
+    ea.table = c->table;
+    ea.tab_dx = m->tab_dx;
+    ea.tab_nint = m->tab_nint;
+    ea.T = c->T;
+    ea.dT = c->dT;
+    ea.F = c->F;
+    ea.vir_part = c->vir_part;
+    ea.vir_atom = vir_atom;
+    ea.stats = c->stats;
+    const bool tab = m->tabulated;
+    prof_mark(ev, DPK_STAGE_EMBED_FWD, s);
+    launch_embed_fwd(c->precision, tab, ea, s);
+
+    FitArgs fa;
+    fa.natoms = n;
+    fa.ntypes = nt;
+    fa.ncu = c->ncu;
+    fa.itype = c->itype;
+    fa.toff = c->toff;
+    fa.fvec = c->fvec;
+    fa.fmat = c->fmat;
+    fa.T = c->T;
+    fa.dT = c->dT;
+    fa.act = c->act;
+    fa.Ei = c->Ei;
+    prof_mark(ev, DPK_STAGE_FIT, s);
+    launch_fit(c->precision, fa, s);
+
+    prof_mark(ev, DPK_STAGE_EMBED_BWD, s);
+    launch_embed_bwd(c->precision, tab, ea, s);
+}
+
+// One frame of a batch: host copies of the coordinates (for an open cluster's bounding box) and
+// of the cell.
+struct BatchFrame {
+    int64_t natoms;
+    const double* coord;
+    const double* box;
+    bool want_ei;
+};
+
+int frame_geometry(dpk_ctx* c, const BatchFrame& f, GeomParams& gp)
+{
+    c->cur_natoms = f.natoms;
+    if (f.box) return setup_geometry(c, f.box, nullptr, gp);
+    double bb[6] = {1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < f.natoms; ++i)
+        for (int k = 0; k < 3; ++k) {
+            bb[k] = std::min(bb[k], f.coord[3 * i + k]);
+            bb[3 + k] = std::max(bb[3 + k], f.coord[3 * i + k]);
+        }
+    return setup_geometry(c, nullptr, bb, gp);
+}
+
+// Layout of a batch: per-frame geometry and offsets, total atoms and concatenated bins (ncell + 1
+// entries per frame), the largest stencil and candidate buffer. Outputs of frame f start at
+// fd[f].out_off doubles: E, virial[9], F[3n] and, if asked for, E_i[n].
+int batch_plan(dpk_ctx* c, int nf, const BatchFrame* fr, GeomParams* gps, FrameDesc* fd, int64_t* natoms,
+               int64_t* ncells, int* max_stencil, int* max_cap, int64_t* out_doubles)
+{
+    if (nf < 1 || nf > BATCH_MAX_FRAMES) return fail(DPK_E_INVALID_ARG, "batch of %d frames", nf);
+    int64_t n = 0, nc = 0, out = 0;
+    int ms = 0, mc = 0;
+    for (int f = 0; f < nf; ++f) {
+        int rc = frame_geometry(c, fr[f], gps[f]);
+        if (rc) return rc;
+        const int64_t ncell = (int64_t)gps[f].nb[0] * gps[f].nb[1] * gps[f].nb[2];
+        if (fr[f].natoms > prep_small_max_atoms() || ncell > prep_small_max_cells())
+            return fail(DPK_E_INVALID_ARG, "frame of %lld atoms / %lld bins is too large for a batch",
+                        (long long)fr[f].natoms, (long long)ncell);
+        std::memset(&fd[f], 0, sizeof(FrameDesc));
+        fd[f].atom_off = (int)n;
+        fd[f].natoms = (int)fr[f].natoms;
+        fd[f].cell_off = (int)nc;
+        fd[f].ncell = (int)ncell;
+        fd[f].out_off = (int)out;
+        fd[f].want_ei = fr[f].want_ei ? 1 : 0;
+        n += fr[f].natoms;
+        nc += ncell + 1;
+        out += 10 + (fr[f].want_ei ? 4 : 3) * fr[f].natoms;
+        ms = std::max(ms, (2 * gps[f].K[0] + 1) * (2 * gps[f].K[1] + 1) * (2 * gps[f].K[2] + 1));
+        mc = std::max(mc, gps[f].cap);
+    }
+    *natoms = n;
+    *ncells = nc;
+    *max_stencil = ms;
+    *max_cap = mc;
+    *out_doubles = out;
+    return DPK_OK;
+}
+
+// Several frames in one launch per stage (serving): coordinates and types of all frames
+// concatenated in caller order on the device; results of frame f at d_out + fd[f].out_off.
+int compute_batch(dpk_ctx* c, int nf, const BatchFrame* fr, const double* d_coord, const int* d_atype,
+                  double* d_out, hipStream_t s)
+{
+    GeomParams gps[BATCH_MAX_FRAMES];
+    FrameDesc fd[BATCH_MAX_FRAMES];
+    int64_t n, ncells, outd;
+    int ms, mc, rc;
+    if ((rc = batch_plan(c, nf, fr, gps, fd, &n, &ncells, &ms, &mc, &outd))) return rc;
+    if ((rc = ensure_ws(c, n, ncells))) return rc;
+    if (!c->pin_desc &&
+        hipHostMalloc(&c->pin_desc, (sizeof(FrameDesc) + sizeof(GeomParams)) * BATCH_MAX_FRAMES) != hipSuccess) {
+        c->pin_desc = nullptr;
+        return fail(DPK_E_OOM, "pinned staging of the batch descriptors failed");
+    }
+    // the previous use of the staging has completed: this context's last frame is done
+    if (c->last_stream) HIPCHK(hipStreamSynchronize(c->last_stream));
+    FrameDesc* pfd = (FrameDesc*)c->pin_desc;
+    GeomParams* pgp = (GeomParams*)(pfd + BATCH_MAX_FRAMES);
+    std::memcpy(pfd, fd, sizeof(FrameDesc) * nf);
+    std::memcpy(pgp, gps, sizeof(GeomParams) * nf);
+    HIPCHK(hipMemcpyAsync(c->fd, pfd, sizeof(FrameDesc) * nf, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->gps, pgp, sizeof(GeomParams) * nf, hipMemcpyHostToDevice, s));
+    const int nt = c->model->desc.ntypes;
+    launch_batch_prep(nf, nt, d_coord, d_atype, c->gps, c->fd, c->tcount, c->toff, c->perm, c->inv_perm, c->itype,
+                      c->frame_of, c->stats, c->pos, c->cell_of, c->cell_start, c->cand, c->F, c->vir_atom, s);
+    launch_nlist((int)n, c->pos, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cand, gps[0], c->nl_j, c->nl_r,
+                 c->nnei, c->stats, s, c->gps, c->fd, c->frame_of, ms, mc);
+    run_network(c, (int)n, gps[0], c->vir_atom, nullptr, s);
+    launch_finalize_batch(nf, c->fd, c->inv_perm, c->Ei, c->vir_atom, c->F, d_out, s);
+    HIPCHK(hipGetLastError());
+    c->last_stream = s;
+    c->last_n = n;
+    c->last_nvp = 0;
+    return DPK_OK;
+}
+
 }  // namespace
 
 // =============================================================================================
@@ -652,6 +812,7 @@ void dpk_ctx_free(dpk_ctx* c)
         hipFree(c->evec); hipFree(c->emat); hipFree(c->fvec); hipFree(c->fmat); hipFree(c->table);
     }
     hipFree(c->ws);
+    hipHostFree(c->pin_desc);
     for (auto& set : c->prof_events)
         for (auto e : set) hipEventDestroy(e);
     if (c->stream) hipStreamDestroy(c->stream);
@@ -694,59 +855,18 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
 
     std::vector<hipEvent_t>* ev = prof_frame(c);
     prof_mark(ev, DPK_STAGE_PREP, s);
-    launch_types(n, d_atype, nt, c->tcount, c->toff, c->bcount, c->boff, c->perm, c->inv_perm, c->itype,
-                 c->cell_count, (int)ncell, c->stats, s);
-    launch_cells(n, d_coord, c->perm, c->itype, gp, c->pos, c->cell_of, c->cell_count, c->cell_start, c->cursor,
-                 c->cell_atoms, c->cand, c->F, s);
+    if (!launch_prep_small(n, d_coord, d_atype, nt, gp, c->tcount, c->toff, c->perm, c->inv_perm, c->itype, c->stats,
+                           c->pos, c->cell_of, c->cell_start, c->cand, c->F, s)) {
+        launch_types(n, d_atype, nt, c->tcount, c->toff, c->bcount, c->boff, c->perm, c->inv_perm, c->itype,
+                     c->cell_count, (int)ncell, c->stats, s);
+        launch_cells(n, d_coord, c->perm, c->itype, gp, c->pos, c->cell_of, c->cell_count, c->cell_start, c->cursor,
+                     c->cell_atoms, c->cand, c->F, s);
+    }
     prof_mark(ev, DPK_STAGE_NLIST, s);
     launch_nlist(n, c->pos, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cand, gp, c->nl_j, c->nl_r, c->nnei,
                  c->stats, s);
 
-    EmbArgs ea;
-    std::memset(&ea, 0, sizeof(ea));
-    ea.natoms = n;
-    ea.ntypes = nt;
-    ea.nc = m->nc;
-    ea.type_one_side = m->desc.type_one_side;
-    for (int t = 0; t < nt; ++t) ea.off[t] = gp.off[t];
-    ea.itype = c->itype;
-    ea.nnei = c->nnei;
-    ea.nl_j = c->nl_j;
-    ea.nl_r = c->nl_r;
-    ea.rs = m->desc.rcut_smth;
-    ea.rc = m->desc.rcut;
-    ea.inv_nc = 1.0 / m->nc;
-    ea.evec = c->evec;
-    ea.emat = c->emat;
-    ea.table = c->table;
-    ea.tab_dx = m->tab_dx;
-    ea.tab_nint = m->tab_nint;
-    ea.T = c->T;
-    ea.dT = c->dT;
-    ea.F = c->F;
-    ea.vir_part = c->vir_part;
-    ea.stats = c->stats;
-    const bool tab = m->tabulated;
-    prof_mark(ev, DPK_STAGE_EMBED_FWD, s);
-    launch_embed_fwd(c->precision, tab, ea, s);
-
-    FitArgs fa;
-    fa.natoms = n;
-    fa.ntypes = nt;
-    fa.ncu = c->ncu;
-    fa.itype = c->itype;
-    fa.toff = c->toff;
-    fa.fvec = c->fvec;
-    fa.fmat = c->fmat;
-    fa.T = c->T;
-    fa.dT = c->dT;
-    fa.act = c->act;
-    fa.Ei = c->Ei;
-    prof_mark(ev, DPK_STAGE_FIT, s);
-    launch_fit(c->precision, fa, s);
-
-    prof_mark(ev, DPK_STAGE_EMBED_BWD, s);
-    launch_embed_bwd(c->precision, tab, ea, s);
+    run_network(c, n, gp, nullptr, ev, s);
     prof_mark(ev, DPK_STAGE_FINAL, s);
     const int nvp = (n + embed_atoms_per_block(c->precision) - 1) / embed_atoms_per_block(c->precision);
     launch_finalize(n, c->Ei, nvp, c->vir_part, d_energy, d_virial, c->perm, c->F, d_force, d_atom_energy, s);
@@ -920,7 +1040,10 @@ int64_t now_ns()
 struct Request {
     uint64_t ticket = 0;
     dpk_frame f{};
-    int64_t need = 0;          // workspace bytes
+    int64_t need = 0;          // workspace bytes of the frame alone
+    int64_t ncell = 0;         // bins of the frame
+    int64_t out_off = 0;       // first double of its outputs in the slot's output staging
+    bool solo = false;         // run alone (after its batch reported a data error)
     int state = 0;             // 0 queued, 1 running, 2 done
     int result = 0;
     std::string err;
@@ -930,7 +1053,7 @@ struct Request {
 struct Slot {
     dpk_ctx* ctx = nullptr;
     hipEvent_t done = nullptr;
-    Request* req = nullptr;
+    std::vector<Request*> reqs;        // the batch in flight (empty: idle)
     int64_t sim = -1;
     double* pin_coord = nullptr;
     int* pin_type = nullptr;
@@ -1000,14 +1123,13 @@ int64_t resident_bytes(dpk_server* s)
     return b;
 }
 
-void finish(dpk_server* s, Slot& sl, int rc, const std::string& msg)
+void finish_one(dpk_server* s, Request* r, const double* out, int rc, const std::string& msg)
 {
-    Request* r = sl.req;
     r->result = rc;
     r->err = msg;
     if (rc == DPK_OK) {
         const int64_t n = r->f.natoms;
-        const double* o = sl.pin_out;
+        const double* o = out + r->out_off;
         *r->f.energy = o[0];
         std::memcpy(r->f.virial, o + 1, sizeof(double) * 9);
         std::memcpy(r->f.force, o + 10, sizeof(double) * 3 * n);
@@ -1018,17 +1140,46 @@ void finish(dpk_server* s, Slot& sl, int rc, const std::string& msg)
     }
     r->t_done = now_ns();
     r->state = 2;
-    sl.req = nullptr;
 }
 
-int launch(dpk_server* s, Slot& sl, Request* r)
+void finish(dpk_server* s, Slot& sl, int rc, const std::string& msg)
+{
+    for (Request* r : sl.reqs) finish_one(s, r, sl.pin_out, rc, msg);
+    sl.reqs.clear();
+}
+
+// Workspace bytes of the first k queued frames run as one batch.
+int64_t batch_need(dpk_ctx* c, const std::deque<Request*>& q, int k)
+{
+    if (k == 1) return q[0]->need;
+    int64_t n = 0, nc = 0;
+    for (int i = 0; i < k; ++i) {
+        n += q[i]->f.natoms;
+        nc += q[i]->ncell + 1;
+    }
+    return (int64_t)layout_ws(c, n, nc, nullptr);
+}
+
+bool batchable(const Request* r)
+{
+    return !r->solo && r->f.natoms <= prep_small_max_atoms() && r->ncell <= prep_small_max_cells();
+}
+
+// Run a batch of frames on a slot: one frame through the single-frame path, several through the
+// batched launches; host staging in pinned buffers, one copy each way.
+int launch(dpk_server* s, Slot& sl, const std::vector<Request*>& batch)
 {
     dpk_ctx* c = sl.ctx;
-    const int64_t n = r->f.natoms;
-    int64_t need, ncell;
-    int rc = frame_need(c, r->f, &need, &ncell);
-    if (rc) return rc;
-    if ((rc = ensure_ws(c, n, ncell))) return rc;
+    int64_t n = 0, outd = 0;
+    for (Request* r : batch) {
+        r->out_off = outd;
+        n += r->f.natoms;
+        outd += 10 + (r->f.atom_energy ? 4 : 3) * r->f.natoms;
+    }
+    int rc;
+    if (batch.size() == 1) {
+        if ((rc = ensure_ws(c, n, batch[0]->ncell))) return rc;
+    }
     if (sl.pin_cap < n) {
         hipHostFree(sl.pin_coord);
         hipHostFree(sl.pin_type);
@@ -1037,30 +1188,58 @@ int launch(dpk_server* s, Slot& sl, Request* r)
         const int64_t cap = std::max<int64_t>(n, 1024);
         if (hipHostMalloc((void**)&sl.pin_coord, sizeof(double) * 3 * cap) != hipSuccess ||
             hipHostMalloc((void**)&sl.pin_type, sizeof(int) * cap) != hipSuccess ||
-            hipHostMalloc((void**)&sl.pin_out, sizeof(double) * (10 + 4 * cap)) != hipSuccess)
+            hipHostMalloc((void**)&sl.pin_out, sizeof(double) * (10 * BATCH_MAX_FRAMES + 4 * cap)) != hipSuccess)
             return fail(DPK_E_OOM, "pinned host staging of %lld atoms failed", (long long)cap);
         sl.pin_cap = cap;
     }
-    std::memcpy(sl.pin_coord, r->f.coord, sizeof(double) * 3 * n);
-    std::memcpy(sl.pin_type, r->f.atype, sizeof(int) * n);
+    int64_t off = 0;
+    for (Request* r : batch) {
+        std::memcpy(sl.pin_coord + 3 * off, r->f.coord, sizeof(double) * 3 * r->f.natoms);
+        std::memcpy(sl.pin_type + off, r->f.atype, sizeof(int) * r->f.natoms);
+        off += r->f.natoms;
+    }
     hipStream_t st = c->stream;
-    HIPCHK(hipMemcpyAsync(c->h_coord, sl.pin_coord, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(c->h_atype, sl.pin_type, sizeof(int) * n, hipMemcpyHostToDevice, st));
-    double* o = c->h_out;
-    rc = dpk_compute_device(c, n, c->h_coord, c->h_atype, r->f.box, o, o + 10, o + 1,
-                            r->f.atom_energy ? o + 10 + 3 * n : nullptr, st);
-    if (rc) return rc;
-    HIPCHK(hipMemcpyAsync(sl.pin_out, o, sizeof(double) * (10 + (r->f.atom_energy ? 4 : 3) * n),
-                          hipMemcpyDeviceToHost, st));
+    if (batch.size() > 1) {
+        // the workspace (device coordinate buffers included) is sized by the plan
+        std::vector<BatchFrame> fr(batch.size());
+        for (size_t i = 0; i < batch.size(); ++i)
+            fr[i] = BatchFrame{batch[i]->f.natoms, batch[i]->f.coord, batch[i]->f.box, batch[i]->f.atom_energy != nullptr};
+        GeomParams gps[BATCH_MAX_FRAMES];
+        FrameDesc fd[BATCH_MAX_FRAMES];
+        int64_t nn, ncells, od;
+        int ms, mc;
+        if ((rc = batch_plan(c, (int)fr.size(), fr.data(), gps, fd, &nn, &ncells, &ms, &mc, &od))) return rc;
+        if ((rc = ensure_ws(c, nn, ncells))) return rc;
+        HIPCHK(hipMemcpyAsync(c->h_coord, sl.pin_coord, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(c->h_atype, sl.pin_type, sizeof(int) * n, hipMemcpyHostToDevice, st));
+        if ((rc = compute_batch(c, (int)fr.size(), fr.data(), c->h_coord, c->h_atype, c->h_out, st))) return rc;
+    } else {
+        Request* r = batch[0];
+        HIPCHK(hipMemcpyAsync(c->h_coord, sl.pin_coord, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(c->h_atype, sl.pin_type, sizeof(int) * n, hipMemcpyHostToDevice, st));
+        double* o = c->h_out;
+        rc = dpk_compute_device(c, n, c->h_coord, c->h_atype, r->f.box, o, o + 10, o + 1,
+                                r->f.atom_energy ? o + 10 + 3 * n : nullptr, st);
+        if (rc) return rc;
+    }
+    HIPCHK(hipMemcpyAsync(sl.pin_out, c->h_out, sizeof(double) * outd, hipMemcpyDeviceToHost, st));
     HIPCHK(hipEventRecord(sl.done, st));
-    if (sl.sim >= 0 && sl.sim == r->f.simulation) s->st.slot_reuse++;
-    sl.sim = r->f.simulation;
-    sl.req = r;
-    r->state = 1;
-    r->t_start = now_ns();
+    const int64_t sim = batch[0]->f.simulation;
+    if (sl.sim >= 0 && sl.sim == sim) s->st.slot_reuse++;
+    sl.sim = sim;
+    sl.reqs = batch;
+    const int64_t t = now_ns();
+    for (Request* r : batch) {
+        r->state = 1;
+        r->t_start = t;
+    }
     return DPK_OK;
 }
 
+// Scheduler thread: completes finished batches, then admits queued frames in arrival order. A
+// free slot takes the longest prefix of the queue (up to BATCH_MAX_FRAMES frames small enough for
+// the batched launches) whose combined workspace the admission rule accepts; the head is never
+// overtaken, so nothing starves, and under light load batches stay short.
 void scheduler(dpk_server* s)
 {
     hipSetDevice(s->device);
@@ -1072,7 +1251,7 @@ void scheduler(dpk_server* s)
         {
             std::unique_lock<std::mutex> lk(s->mu);
             for (auto& sl : s->slots) {
-                if (!sl.req) continue;
+                if (sl.reqs.empty()) continue;
                 hipError_t q = hipEventQuery(sl.done);
                 if (q == hipErrorNotReady) continue;
                 int rc = DPK_OK;
@@ -1084,51 +1263,78 @@ void scheduler(dpk_server* s)
                     rc = dpk_ctx_check(sl.ctx);
                     if (rc) msg = g_err;
                 }
-                finish(s, sl, rc, msg);
+                if (rc != DPK_OK && rc != DPK_E_DEVICE && sl.reqs.size() > 1) {
+                    // a data error of one frame fails the batch: run its frames again one by one,
+                    // ahead of the queue, so that only the faulty frame reports the error
+                    for (auto it = sl.reqs.rbegin(); it != sl.reqs.rend(); ++it) {
+                        (*it)->solo = true;
+                        (*it)->state = 0;
+                        s->queue.push_front(*it);
+                    }
+                    sl.reqs.clear();
+                } else {
+                    finish(s, sl, rc, msg);
+                }
                 progressed = true;
             }
             while (!s->queue.empty()) {
-                Request* r = s->queue.front();
                 for (int k = 0; k < ns; ++k) {
-                    busy[k] = s->slots[k].req != nullptr;
+                    busy[k] = !s->slots[k].reqs.empty();
                     bytes[k] = (int64_t)s->slots[k].ctx->ws_bytes;
                     sims[k] = s->slots[k].sim;
                 }
+                Request* r = s->queue.front();
+                // longest admissible prefix of batchable frames (the head alone otherwise)
+                int take = 1;
                 int32_t slot = -1, rel = 0;
                 int plan = dpk_admit_plan(ns, busy.data(), bytes.data(), sims.data(), r->need, r->f.simulation,
                                           s->budget, s->model_bytes, &slot, &rel);
+                if (plan > 0 && batchable(r)) {
+                    const int kmax = (int)std::min<size_t>(s->queue.size(), BATCH_MAX_FRAMES);
+                    for (int k = 2; k <= kmax; ++k) {
+                        if (!batchable(s->queue[k - 1])) break;
+                        int32_t sk = -1, rk = 0;
+                        const int64_t need = batch_need(s->slots[0].ctx, s->queue, k);
+                        if (dpk_admit_plan(ns, busy.data(), bytes.data(), sims.data(), need, r->f.simulation,
+                                           s->budget, s->model_bytes, &sk, &rk) <= 0)
+                            break;
+                        take = k;
+                        slot = sk;
+                        rel = rk;
+                    }
+                }
                 if (plan == 0) {
                     bool any_idle = false;
                     for (int k = 0; k < ns; ++k) any_idle |= !busy[k];
                     if (any_idle) s->st.budget_waits++;
                     break;
                 }
-                s->queue.pop_front();
+                std::vector<Request*> batch(s->queue.begin(), s->queue.begin() + take);
+                s->queue.erase(s->queue.begin(), s->queue.begin() + take);
                 int rc = DPK_OK;
                 if (plan < 0) {
                     rc = plan;
                     g_err = "frame does not fit the server's HBM budget";
                 } else {
+                    const int64_t need = batch_need(s->slots[0].ctx, std::deque<Request*>(batch.begin(), batch.end()),
+                                                    take);
                     if (rel) {
                         for (int k = 0; k < ns; ++k)
                             if (!busy[k] && k != slot) release_ws(s->slots[k].ctx);
-                        if ((int64_t)s->slots[slot].ctx->ws_bytes > r->need) release_ws(s->slots[slot].ctx);
+                        if ((int64_t)s->slots[slot].ctx->ws_bytes > need) release_ws(s->slots[slot].ctx);
                     }
-                    rc = launch(s, s->slots[slot], r);
+                    rc = launch(s, s->slots[slot], batch);
                     s->st.peak_bytes = std::max(s->st.peak_bytes, resident_bytes(s));
                 }
                 if (rc) {
-                    Slot tmp;
-                    tmp.req = r;
-                    r->state = 1;
-                    finish(s, tmp, rc, g_err);
-                    if (s->slots[slot >= 0 ? slot : 0].req == r) s->slots[slot].req = nullptr;
+                    for (Request* b : batch) finish_one(s, b, nullptr, rc, g_err);
+                    if (slot >= 0) s->slots[slot].reqs.clear();
                 }
                 progressed = true;
             }
             if (progressed) s->cv.notify_all();
             bool idle = s->queue.empty();
-            for (auto& sl : s->slots) idle &= sl.req == nullptr;
+            for (auto& sl : s->slots) idle &= sl.reqs.empty();
             if (s->stop && idle) break;
         }
         if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -1235,9 +1441,11 @@ int dpk_server_submit(dpk_server* s, const dpk_frame* f, uint64_t* ticket)
         return fail(DPK_E_INVALID_ARG, "bad frame");
     auto r = std::make_unique<Request>();
     r->f = *f;
-    int64_t ncell;
-    int rc = frame_need(s->slots[0].ctx, *f, &r->need, &ncell);
+    int rc = frame_need(s->slots[0].ctx, *f, &r->need, &r->ncell);
     if (rc) return rc;
+    const int nt = s->model->desc.ntypes;
+    bool bad = false;
+    for (int64_t i = 0; i < f->natoms; ++i) bad |= f->atype[i] < 0 || f->atype[i] >= nt;
     if (s->budget && r->need + s->model_bytes > s->budget)
         return fail(DPK_E_BUDGET, "frame of %lld atoms needs %lld workspace bytes; budget %lld with model %lld",
                     (long long)f->natoms, (long long)r->need, (long long)s->budget, (long long)s->model_bytes);
@@ -1245,9 +1453,16 @@ int dpk_server_submit(dpk_server* s, const dpk_frame* f, uint64_t* ticket)
     r->ticket = s->next_ticket++;
     r->t_submit = now_ns();
     *ticket = r->ticket;
-    s->queue.push_back(r.get());
-    s->reqs[r->ticket] = std::move(r);
     s->st.submitted++;
+    if (bad) {
+        // the frame fails alone, without a device launch (the ticket reports the error)
+        r->state = 1;
+        finish_one(s, r.get(), nullptr, DPK_E_TYPE_RANGE, "an atom type is outside [0, " + std::to_string(nt) + ")");
+        s->cv.notify_all();
+    } else {
+        s->queue.push_back(r.get());
+    }
+    s->reqs[r->ticket] = std::move(r);
     return DPK_OK;
 }
 

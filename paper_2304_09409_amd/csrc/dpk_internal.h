@@ -79,6 +79,20 @@ struct DevStats {
     int pad;
 };
 
+// One frame of a batch evaluated in shared launches (serving).
+constexpr int BATCH_MAX_FRAMES = 64;
+struct FrameDesc {
+    int atom_off;          // first atom (caller order over the batch) and first candidate record
+    int natoms;
+    int cell_off;          // first of the frame's ncell + 1 entries in the concatenated cell_start
+    int ncell;
+    int out_off;           // first double of the frame's outputs: E, virial[9], F[3n], E_i[n]
+    int want_ei;           // write E_i
+    int type_base[MAXT];   // device: per-frame type counts, then internal position of the frame's first atom of each type
+    int bad;               // device: an atom type was out of range
+    int pad;
+};
+
 // Arguments of the embedding kernels.
 struct EmbArgs {
     int natoms, ntypes, nc, type_one_side;
@@ -97,6 +111,7 @@ struct EmbArgs {
     const void* dT;          // [N][100][4] (backward input)
     double* F;               // [N][3] internal order (backward output, atomics)
     double* vir_part;        // [gridDim][9]
+    double* vir_atom;        // [N][9] virial per centre atom (batched frames), or nullptr
     DevStats* stats;
 };
 

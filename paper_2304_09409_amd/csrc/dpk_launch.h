@@ -9,12 +9,28 @@ void launch_zero(void* p, size_t bytes, hipStream_t s);
 void launch_types(int n, const int* atype, int ntypes, int* tcount, int* toff, int* bcount, int* boff, int* perm,
                   int* inv_perm, int* itype, int* cell_count, int ncell, DevStats* st, hipStream_t s);
 void launch_bbox(int n, const double* coord, double* out, hipStream_t s);
+// All preparation phases in one workgroup; false (nothing launched) when the frame is too large.
+bool launch_prep_small(int n, const double* coord, const int* atype, int ntypes, const GeomParams& gp, int* tcount,
+                       int* toff, int* perm, int* inv_perm, int* itype, DevStats* st, double* pos, int* cell_of,
+                       int* cell_start, double4* cand, double* f_int, hipStream_t s);
 void launch_cells(int n, const double* coord, const int* perm, const int* itype, const GeomParams& gp, double* pos,
                   int* cell_of, int* cell_count, int* cell_start, int* cursor, int* cell_atoms, double4* cand,
                   double* f_int, hipStream_t s);
+// Single frame: gp by value, gps == nullptr. Batch: gps/fd/frame_of on the device and the largest
+// stencil and candidate buffer of the batch's frames.
 void launch_nlist(int n, const double* pos, const int* perm, const int* inv_perm, const int* cell_of,
                   const int* cell_start, const double4* cand, const GeomParams& gp, int* nl_j, double* nl_r,
-                  int* nnei, DevStats* st, hipStream_t s);
+                  int* nnei, DevStats* st, hipStream_t s, const GeomParams* gps = nullptr,
+                  const FrameDesc* fd = nullptr, const int* frame_of = nullptr, int max_stencil = 0, int max_cap = 0);
+// Batched frames (each at most prep_small_max_atoms() atoms and prep_small_max_cells() bins).
+void launch_batch_prep(int nframes, int ntypes, const double* coord, const int* atype, const GeomParams* gps,
+                       FrameDesc* fd, int* tcount, int* toff, int* perm, int* inv_perm, int* itype, int* frame_of,
+                       DevStats* st, double* pos, int* cell_of, int* cell_start, double4* cand, double* f_int,
+                       double* vir_atom, hipStream_t s);
+void launch_finalize_batch(int nframes, const FrameDesc* fd, const int* inv_perm, const double* ei,
+                           const double* vir_atom, const double* f_int, double* out, hipStream_t s);
+int prep_small_max_atoms();
+int prep_small_max_cells();
 void launch_finalize(int n, const double* ei, int nvp, const double* vir_part, double* energy, double* virial,
                      const int* perm, const double* f_int, double* force, double* atom_energy, hipStream_t s);
 void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s);

@@ -202,6 +202,267 @@ __global__ void k_cell_fill(int n, const int* cell_of, int* cursor, int* cell_at
     cell_atoms[slot] = a;
 }
 
+// ---- fused preparation for frames of up to PS_MAX_ATOMS atoms and PS_MAX_CELLS bins --------
+// One workgroup runs every preparation phase with barriers in between instead of seven dependent
+// launches: type counts (ballots), the stable type partition (chunks of 1024 atoms in caller
+// order, ballot ranks), wrap and bin (bin counts as LDS atomics), the bin scan, and the bin fill,
+// which writes the candidate records directly. Results equal those of the multi-kernel path,
+// except the order of atoms within a bin, which nothing downstream depends on (the neighbour
+// list sorts its hits by a key that is unique per candidate).
+constexpr int PS_THREADS = 1024;
+constexpr int PS_APT = 8;                           // atoms per thread, held in registers
+constexpr int PS_MAX_ATOMS = PS_THREADS * PS_APT;   // 8192
+constexpr int PS_MAX_CELLS = 8192;
+
+__device__ __forceinline__ void wrap_bin_one(const GeomParams& gp, const double* x, double* p, int* b)
+{
+    if (gp.periodic) {
+        double s[3];
+        for (int c = 0; c < 3; ++c) {
+            s[c] = (x[0] * gp.hinv[c] + x[1] * gp.hinv[3 + c]) + x[2] * gp.hinv[6 + c];
+            s[c] -= floor(s[c]);
+            if (s[c] >= 1.0) s[c] = 0.0;
+        }
+        for (int c = 0; c < 3; ++c) p[c] = (s[0] * gp.h[c] + s[1] * gp.h[3 + c]) + s[2] * gp.h[6 + c];
+        for (int c = 0; c < 3; ++c) {
+            const int bb = (int)floor(s[c] * gp.nb[c]);
+            b[c] = bb < 0 ? 0 : (bb >= gp.nb[c] ? gp.nb[c] - 1 : bb);
+        }
+    } else {
+        for (int c = 0; c < 3; ++c) {
+            p[c] = x[c];
+            const int bb = (int)floor((x[c] - gp.origin[c]) / gp.binw[c]);
+            b[c] = bb < 0 ? 0 : (bb >= gp.nb[c] ? gp.nb[c] - 1 : bb);
+        }
+    }
+}
+
+// One frame's preparation in one workgroup. Single frame (BATCH = false): counts the types itself
+// and zeroes the statistics block. Frame f of a batch (BATCH = true): the per-type internal bases
+// come from k_batch_scan; atoms, candidate records and bins sit at the frame's offsets.
+template <bool BATCH>
+__device__ __forceinline__ void prep_frame(int f, int n, int atom_off, const double* coord, const int* atype,
+                                           int ntypes, const GeomParams& gp, int ncell, int cell_off,
+                                           const int* type_base, int* tcount, int* toff, int* perm, int* inv_perm,
+                                           int* itype, int* frame_of, DevStats* st, double* pos, int* cell_of,
+                                           int* cell_start, double4* cand, double* f_int, double* vir_atom)
+{
+    __shared__ int s_cnt[PS_MAX_CELLS];        // bin counts, then bin cursors
+    __shared__ int s_w[PS_THREADS / 64][MAXT]; // per-wave type counts
+    __shared__ int s_base[MAXT];               // next internal position per type
+    __shared__ int s_part[PS_THREADS];         // scan partials
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (!BATCH && tid < (int)(sizeof(DevStats) / 4)) reinterpret_cast<int*>(st)[tid] = 0;
+    for (int c = tid; c < ncell; c += PS_THREADS) s_cnt[c] = 0;
+    if (BATCH && tid < ntypes) s_base[tid] = type_base[tid];
+    __syncthreads();   // the statistics block is zero before anything raises a flag in it
+    // types of this thread's atoms tid + PS_THREADS j, read once
+    int tv[PS_APT];
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < PS_APT; ++j) {
+        const int a = tid + PS_THREADS * j;
+        const int t0 = a < n ? atype[atom_off + a] : 0;
+        bad |= t0 < 0 || t0 >= ntypes;
+        tv[j] = a < n ? clamp_type(t0, ntypes) : -1;
+    }
+    if (!BATCH) {
+        if (__ballot(bad) != 0 && lane == 0) atomicExch(&st->err_type, 1);
+        for (int k = 0; k < ntypes; ++k) {
+            int v = 0;
+#pragma unroll
+            for (int j = 0; j < PS_APT; ++j) v += tv[j] == k;
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) s_w[wid][k] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int k = 0; k < ntypes; ++k) {
+                int c = 0;
+                for (int w = 0; w < PS_THREADS / 64; ++w) c += s_w[w][k];
+                toff[k] = acc;
+                tcount[k] = c;
+                s_base[k] = acc;
+                acc += c;
+            }
+            toff[ntypes] = acc;
+        }
+        __syncthreads();
+    }
+    // stable partition by type: chunk j = atoms PS_THREADS j .. in caller order; this thread's
+    // internal positions are kept for the next phase
+    int qv[PS_APT];
+#pragma unroll
+    for (int j = 0; j < PS_APT; ++j) {
+        qv[j] = -1;
+        if (PS_THREADS * j >= n) continue;   // uniform
+        const int a = tid + PS_THREADS * j;
+        const int t = tv[j];
+        unsigned long long mine = 0;
+        for (int k = 0; k < ntypes; ++k) {
+            const unsigned long long m = __ballot(t == k);
+            if (t == k) mine = m;
+            if (lane == 0) s_w[wid][k] = __popcll(m);
+        }
+        __syncthreads();
+        if (t >= 0) {
+            int before = s_base[t];
+            for (int w = 0; w < wid; ++w) before += s_w[w][t];
+            const int q = before + __popcll(mine & lt);
+            qv[j] = q;
+            perm[q] = atom_off + a;
+            inv_perm[atom_off + a] = q;
+            itype[q] = t;
+            if (BATCH) frame_of[q] = f;
+        }
+        __syncthreads();
+        if (tid < ntypes) {
+            int c = 0;
+            for (int w = 0; w < PS_THREADS / 64; ++w) c += s_w[w][tid];
+            s_base[tid] += c;
+        }
+        __syncthreads();
+    }
+    // wrap and bin this thread's atoms (caller index atom_off + a, internal index qv[j]); zero the
+    // frame's force (and, batched, virial) accumulators
+    double xv[PS_APT][3];
+#pragma unroll
+    for (int j = 0; j < PS_APT; ++j) {
+        const int a = atom_off + tid + PS_THREADS * j;
+        for (int c = 0; c < 3; ++c) xv[j][c] = qv[j] >= 0 ? coord[3 * (size_t)a + c] : 0.0;
+    }
+    int cv[PS_APT];
+#pragma unroll
+    for (int j = 0; j < PS_APT; ++j) {
+        cv[j] = -1;
+        const int q = qv[j];
+        if (q < 0) continue;
+        double p[3];
+        int b[3];
+        wrap_bin_one(gp, xv[j], p, b);
+        for (int c = 0; c < 3; ++c) {
+            pos[3 * (size_t)q + c] = p[c];
+            xv[j][c] = p[c];
+            f_int[3 * (size_t)q + c] = 0.0;
+        }
+        if (BATCH)
+            for (int k = 0; k < 9; ++k) vir_atom[9 * (size_t)q + k] = 0.0;
+        const int cell = (b[2] * gp.nb[1] + b[1]) * gp.nb[0] + b[0];
+        cell_of[q] = cell;
+        cv[j] = cell;
+        atomicAdd(&s_cnt[cell], 1);
+    }
+    __syncthreads();
+    // exclusive scan of the bin counts: contiguous segments per thread, then a scan of the partials
+    const int seg = (ncell + PS_THREADS - 1) / PS_THREADS;
+    const int c0 = tid * seg, c1 = min(c0 + seg, ncell);
+    int sum = 0;
+    for (int c = c0; c < c1; ++c) sum += s_cnt[c];
+    s_part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < PS_THREADS; o <<= 1) {
+        const int v = tid >= o ? s_part[tid - o] : 0;
+        __syncthreads();
+        s_part[tid] += v;
+        __syncthreads();
+    }
+    int run = s_part[tid] - sum;
+    for (int c = c0; c < c1; ++c) {
+        const int v = s_cnt[c];
+        cell_start[cell_off + c] = atom_off + run;
+        s_cnt[c] = run;   // cursor
+        run += v;
+    }
+    if (tid == 0) cell_start[cell_off + ncell] = atom_off + n;
+    __syncthreads();
+    // bin fill: candidate records in bin order (tag: internal index, caller index, type)
+#pragma unroll
+    for (int j = 0; j < PS_APT; ++j) {
+        const int q = qv[j];
+        if (q < 0) continue;
+        const int slot = atomicAdd(&s_cnt[cv[j]], 1);
+        const long long tag = (long long)q | ((long long)(atom_off + tid + PS_THREADS * j) << 30) |
+                              ((long long)tv[j] << 60);
+        cand[atom_off + slot] = make_double4(xv[j][0], xv[j][1], xv[j][2], __longlong_as_double(tag));
+    }
+}
+
+__global__ void __launch_bounds__(PS_THREADS) k_prep_small(int n, const double* coord, const int* atype, int ntypes,
+                                                            GeomParams gp, int ncell, int* tcount, int* toff, int* perm,
+                                                            int* inv_perm, int* itype, DevStats* st, double* pos,
+                                                            int* cell_of, int* cell_start, double4* cand, double* f_int)
+{
+    prep_frame<false>(0, n, 0, coord, atype, ntypes, gp, ncell, 0, nullptr, tcount, toff, perm, inv_perm, itype,
+                      nullptr, st, pos, cell_of, cell_start, cand, f_int, nullptr);
+}
+
+// ---- batched frames (serving): per-frame type counts, cross-frame type bases, per-frame prep --
+
+__global__ void __launch_bounds__(256) k_batch_count(const int* atype, int ntypes, FrameDesc* fd)
+{
+    __shared__ int s_c[4][MAXT];
+    __shared__ int s_bad[4];
+    FrameDesc& d = fd[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int cnt[MAXT];
+    for (int k = 0; k < MAXT; ++k) cnt[k] = 0;
+    bool bad = false;
+    for (int a = tid; a < d.natoms; a += 256) {
+        const int t0 = atype[d.atom_off + a];
+        bad |= t0 < 0 || t0 >= ntypes;
+        const int t = clamp_type(t0, ntypes);
+        for (int k = 0; k < MAXT; ++k) cnt[k] += t == k;
+    }
+    for (int k = 0; k < MAXT; ++k) {
+        int v = cnt[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) s_c[wid][k] = v;
+    }
+    if (lane == 0) s_bad[wid] = __ballot(bad) != 0;
+    __syncthreads();
+    if (tid < MAXT) d.type_base[tid] = s_c[0][tid] + s_c[1][tid] + s_c[2][tid] + s_c[3][tid];
+    if (tid == 0) d.bad = s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3];
+}
+
+// Per-type totals and each frame's internal base per type (atoms sorted by type over the whole
+// batch, frames in order within a type); zeroes the statistics block of the batch.
+__global__ void k_batch_scan(int nframes, int ntypes, FrameDesc* fd, int* tcount, int* toff, DevStats* st)
+{
+    if (threadIdx.x < (int)(sizeof(DevStats) / 4)) reinterpret_cast<int*>(st)[threadIdx.x] = 0;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    int acc = 0, bad = 0;
+    for (int t = 0; t < ntypes; ++t) {
+        toff[t] = acc;
+        int c = 0;
+        for (int f = 0; f < nframes; ++f) {
+            const int v = fd[f].type_base[t];
+            fd[f].type_base[t] = acc + c;
+            c += v;
+        }
+        tcount[t] = c;
+        acc += c;
+    }
+    toff[ntypes] = acc;
+    for (int f = 0; f < nframes; ++f) bad |= fd[f].bad;
+    if (bad) st->err_type = 1;
+}
+
+__global__ void __launch_bounds__(PS_THREADS) k_prep_batch(const double* coord, const int* atype, int ntypes,
+                                                            const GeomParams* gps, const FrameDesc* fd, int* perm,
+                                                            int* inv_perm, int* itype, int* frame_of, double* pos,
+                                                            int* cell_of, int* cell_start, double4* cand, double* f_int,
+                                                            double* vir_atom)
+{
+    const int f = blockIdx.x;
+    const FrameDesc& d = fd[f];
+    prep_frame<true>(f, d.natoms, d.atom_off, coord, atype, ntypes, gps[f], d.ncell, d.cell_off, d.type_base,
+                     nullptr, nullptr, perm, inv_perm, itype, frame_of, nullptr, pos, cell_of, cell_start, cand, f_int,
+                     vir_atom);
+}
+
 // ---- neighbour list: one wave per centre atom --------------------------------------------
 // Candidate records are stored in bin order (k_cell_pack): position and a tag holding the
 // internal index, the caller index and the type (30 + 30 + 4 bits), so one 32-B load gives
@@ -245,11 +506,17 @@ __device__ __forceinline__ void image_shift(const GeomParams& gp, int n0, int n1
 
 constexpr int NL_UNROLL = 4;
 
-template <int CAP>
+// BATCH: atom a belongs to frame frame_of[a]; its geometry is gps[frame] and its bins start at
+// fd[frame].cell_off of the concatenated cell_start (candidate records hold batch-wide indices).
+template <int CAP, bool BATCH>
 __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const int* perm, const int* inv_perm,
-                                              const int* cell_of, const int* cell_start, const double4* cand,
-                                              GeomParams gp, int* nl_j, double* nl_r, int* nnei, DevStats* st)
+                                              const int* cell_of, const int* cell_start0, const double4* cand,
+                                              GeomParams gp0, const GeomParams* gps, const FrameDesc* fd,
+                                              const int* frame_of, int* nl_j, double* nl_r, int* nnei, DevStats* st)
 {
+    const int fr = BATCH ? frame_of[blockIdx.x] : 0;
+    const GeomParams& gp = BATCH ? gps[fr] : gp0;
+    const int* cell_start = BATCH ? cell_start0 + fd[fr].cell_off : cell_start0;
     // LDS sized per launch (nlist_lds_bytes): keys of CAP candidates, then the stencil tables
     extern __shared__ __attribute__((aligned(16))) unsigned long long nl_lds[];
     unsigned long long* khi = nl_lds;
@@ -516,6 +783,35 @@ __global__ void k_output(int n, const int* perm, const double* f_int, const doub
     if (atom_energy) atom_energy[i] = ei[a];
 }
 
+// Batched frames: per frame (one block each) E = sum E_i and the virial = sum over the frame's
+// atoms of their per-atom virial, both in a fixed order, and the frame's forces (and E_i) in its
+// caller order. Output of frame f at out + out_off: E, virial[9], F[3n], E_i[n].
+__global__ void __launch_bounds__(256) k_finalize_batch(const FrameDesc* fd, const int* inv_perm, const double* ei,
+                                                        const double* vir_atom, const double* f_int, double* out)
+{
+    __shared__ double red[10][256];
+    const FrameDesc& d = fd[blockIdx.x];
+    const int tid = threadIdx.x;
+    double* o = out + d.out_off;
+    double acc[10];
+    for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+    for (int a = tid; a < d.natoms; a += 256) {
+        const int q = inv_perm[d.atom_off + a];
+        acc[0] += ei[q];
+        for (int k = 0; k < 9; ++k) acc[1 + k] += vir_atom[9 * (size_t)q + k];
+        for (int c = 0; c < 3; ++c) o[10 + 3 * (size_t)a + c] = f_int[3 * (size_t)q + c];
+        if (d.want_ei) o[10 + 3 * (size_t)d.natoms + a] = ei[q];
+    }
+    for (int k = 0; k < 10; ++k) red[k][tid] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int k = 0; k < 10; ++k) red[k][tid] += red[k][tid + w];
+        __syncthreads();
+    }
+    if (tid < 10) o[tid] = red[tid][0];
+}
+
 // Debug: neighbour list in caller numbering, rows in caller order.
 __global__ void k_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out)
 {
@@ -542,6 +838,37 @@ void launch_types(int n, const int* atype, int ntypes, int* tcount, int* toff, i
     hipLaunchKernelGGL(k_type_scatter, dim3(nb), dim3(TP_BLOCK), 0, s, n, atype, ntypes, boff, perm, inv_perm, itype);
 }
 
+bool launch_prep_small(int n, const double* coord, const int* atype, int ntypes, const GeomParams& gp, int* tcount,
+                       int* toff, int* perm, int* inv_perm, int* itype, DevStats* st, double* pos, int* cell_of,
+                       int* cell_start, double4* cand, double* f_int, hipStream_t s)
+{
+    const int ncell = gp.nb[0] * gp.nb[1] * gp.nb[2];
+    if (n > PS_MAX_ATOMS || ncell > PS_MAX_CELLS) return false;
+    hipLaunchKernelGGL(k_prep_small, dim3(1), dim3(PS_THREADS), 0, s, n, coord, atype, ntypes, gp, ncell, tcount, toff,
+                       perm, inv_perm, itype, st, pos, cell_of, cell_start, cand, f_int);
+    return true;
+}
+
+void launch_batch_prep(int nframes, int ntypes, const double* coord, const int* atype, const GeomParams* gps,
+                       FrameDesc* fd, int* tcount, int* toff, int* perm, int* inv_perm, int* itype, int* frame_of,
+                       DevStats* st, double* pos, int* cell_of, int* cell_start, double4* cand, double* f_int,
+                       double* vir_atom, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_count, dim3(nframes), dim3(256), 0, s, atype, ntypes, fd);
+    hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(64), 0, s, nframes, ntypes, fd, tcount, toff, st);
+    hipLaunchKernelGGL(k_prep_batch, dim3(nframes), dim3(PS_THREADS), 0, s, coord, atype, ntypes, gps, fd, perm,
+                       inv_perm, itype, frame_of, pos, cell_of, cell_start, cand, f_int, vir_atom);
+}
+
+void launch_finalize_batch(int nframes, const FrameDesc* fd, const int* inv_perm, const double* ei,
+                           const double* vir_atom, const double* f_int, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize_batch, dim3(nframes), dim3(256), 0, s, fd, inv_perm, ei, vir_atom, f_int, out);
+}
+
+int prep_small_max_atoms() { return PS_MAX_ATOMS; }
+int prep_small_max_cells() { return PS_MAX_CELLS; }
+
 void launch_bbox(int n, const double* coord, double* out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bbox, dim3(1), dim3(1024), 0, s, n, coord, out);
@@ -561,23 +888,31 @@ void launch_cells(int n, const double* coord, const int* perm, const int* itype,
 
 void launch_nlist(int n, const double* pos, const int* perm, const int* inv_perm, const int* cell_of,
                   const int* cell_start, const double4* cand, const GeomParams& gp, int* nl_j, double* nl_r,
-                  int* nnei, DevStats* st, hipStream_t s)
+                  int* nnei, DevStats* st, hipStream_t s, const GeomParams* gps, const FrameDesc* fd,
+                  const int* frame_of, int max_stencil, int max_cap)
 {
     // candidate buffer sized from the expected count within r_c (the synchronous entry point reruns
     // a frame that overflowed with the largest buffer); LDS = 20 B per candidate slot + 12 B per
-    // stencil bin, so small stencils leave room for more resident waves
-    const int S = (2 * gp.K[0] + 1) * (2 * gp.K[1] + 1) * (2 * gp.K[2] + 1);
-    const int cap = gp.cap <= 256 ? 256 : (gp.cap <= 512 ? 512 : NL_CAP);
+    // stencil bin, so small stencils leave room for more resident waves. A batch passes the
+    // largest stencil and buffer of its frames.
+    const bool batch = gps != nullptr;
+    const int S = batch ? max_stencil : (2 * gp.K[0] + 1) * (2 * gp.K[1] + 1) * (2 * gp.K[2] + 1);
+    const int want = batch ? max_cap : gp.cap;
+    const int cap = want <= 256 ? 256 : (want <= 512 ? 512 : NL_CAP);
     const size_t lds = (size_t)cap * 20 + (size_t)(3 * S + 1) * 4;
-    if (cap == 256)
-        hipLaunchKernelGGL((k_nlist<256>), dim3(n), dim3(64), lds, s, n, pos, perm, inv_perm, cell_of, cell_start,
-                           cand, gp, nl_j, nl_r, nnei, st);
-    else if (cap == 512)
-        hipLaunchKernelGGL((k_nlist<512>), dim3(n), dim3(64), lds, s, n, pos, perm, inv_perm, cell_of, cell_start,
-                           cand, gp, nl_j, nl_r, nnei, st);
-    else
-        hipLaunchKernelGGL((k_nlist<NL_CAP>), dim3(n), dim3(64), lds, s, n, pos, perm, inv_perm, cell_of, cell_start,
-                           cand, gp, nl_j, nl_r, nnei, st);
+#define DPK_NL(C, B)                                                                                              \
+    hipLaunchKernelGGL((k_nlist<C, B>), dim3(n), dim3(64), lds, s, n, pos, perm, inv_perm, cell_of, cell_start,   \
+                       cand, gp, gps, fd, frame_of, nl_j, nl_r, nnei, st)
+    if (batch) {
+        if (cap == 256) DPK_NL(256, true);
+        else if (cap == 512) DPK_NL(512, true);
+        else DPK_NL(NL_CAP, true);
+    } else {
+        if (cap == 256) DPK_NL(256, false);
+        else if (cap == 512) DPK_NL(512, false);
+        else DPK_NL(NL_CAP, false);
+    }
+#undef DPK_NL
 }
 
 void launch_finalize(int n, const double* ei, int nvp, const double* vir_part, double* energy, double* virial,

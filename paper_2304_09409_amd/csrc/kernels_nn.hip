@@ -753,6 +753,19 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
                     if (lane == 0)
                         for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&A.F[3 * (size_t)ca + k], Fi[k]);
                     Fi[0] = Fi[1] = Fi[2] = 0.0;
+                    if (A.vir_atom) {
+                        // batched frames: this atom's share of the virial, kept per centre atom
+                        // (lane group 0 holds the pair terms; one wave owns the atom in every pass)
+                        for (int k = 0; k < 9; ++k) {
+                            double v = vir[k];
+                            v += __shfl_xor(v, 1);
+                            v += __shfl_xor(v, 2);
+                            v += __shfl_xor(v, 4);
+                            v += __shfl_xor(v, 8);
+                            vir[k] = 0.0;
+                            if (lane == 0) A.vir_atom[9 * (size_t)ca + k] += v;
+                        }
+                    }
                 }
             }
         }
