@@ -106,11 +106,13 @@ def stored_traffic(stage: str, precision: str):
     return None
 
 
-def serving_bench(dpk, synth, n_sims=16, steps=16, slots=4, load=0.7, seed=2023):
+def serving_bench(dpk, synth, n_sims=16, steps=16, slots=4, load=0.7, seed=2023, budget_frames=8.0):
     """Requests from n_sims concurrent simulations (sizes log-uniform in [50, 3000], 2-type 1:2 or
     3-type 2:1:1 frames at 0.1 atoms/A^3; consecutive frames of a simulation are small random
     displacements), round-robin over the simulations. First all requests at once (saturated
-    throughput X), then Poisson arrivals at load * X / mean size; latency = completion - arrival."""
+    throughput X), then Poisson arrivals at load * X / mean size; latency = completion - arrival.
+    HBM budget: the model plus budget_frames times the workspace of the largest frame (admission
+    limits batch sizes to what that holds)."""
     import math
     rng = np.random.default_rng(seed)
     sizes = np.exp(rng.uniform(math.log(50), math.log(3000), n_sims)).astype(int)
@@ -125,17 +127,19 @@ def serving_bench(dpk, synth, n_sims=16, steps=16, slots=4, load=0.7, seed=2023)
     model_bytes = probe.stats()["workspace_bytes"]
     big = max(probe.workspace_bytes(len(t)) for _, t, _ in sims) - model_bytes
     probe.close()
-    budget = int(model_bytes + 2.5 * big)
+    budget = int(model_bytes + budget_frames * big)
     total_atoms = sum(len(r[1]) for r in reqs)
     srv = dpk.Server(model, precision="mixed", nslots=slots, budget_bytes=budget)
     # warm-up: one frame per simulation
     for tk in [srv.submit(c, t, b, simulation=sid) for sid, (c, t, b) in enumerate(sims)]:
         tk.result()
+    s0 = srv.stats()
     t0 = time.monotonic_ns()
     tickets = [srv.submit(c, t, b, simulation=sid) for c, t, b, sid in reqs]
     for tk in tickets:
         tk.result()
     t1 = time.monotonic_ns()
+    s1 = srv.stats()
     x_sat = total_atoms / ((t1 - t0) * 1e-9)
     mean_n = total_atoms / len(reqs)
     lam = load * x_sat / mean_n
@@ -159,13 +163,16 @@ def serving_bench(dpk, synth, n_sims=16, steps=16, slots=4, load=0.7, seed=2023)
     st = srv.stats()
     srv.close()
     lat = np.array(lat)
+    batch_sat = (s1["completed"] - s0["completed"]) / max(1, s1["launches"] - s0["launches"])
+    batch_poisson = (st["completed"] - s1["completed"]) / max(1, st["launches"] - s1["launches"])
     return {"requests": len(reqs), "simulations": n_sims, "slots": slots, "budget_bytes": budget,
             "mean_atoms": mean_n, "saturated_atom_steps_per_s": x_sat, "load": load,
             "arrival_rate_req_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
             "throughput_atom_steps_per_s": total_atoms / ((last - start) * 1e-9),
             "peak_bytes": st["peak_bytes"], "budget_waits": st["budget_waits"],
-            "slot_reuse": st["slot_reuse"], "precision": "mixed"}
+            "slot_reuse": st["slot_reuse"], "mean_batch_saturated": batch_sat,
+            "mean_batch_poisson": batch_poisson, "precision": "mixed"}
 
 
 def main():
@@ -235,7 +242,8 @@ def main():
     if serving:
         print(f"# serving: p50 {serving['p50_ms']:.3f} ms, p99 {serving['p99_ms']:.3f} ms at "
               f"{serving['arrival_rate_req_per_s']:.0f} req/s; saturated {serving['saturated_atom_steps_per_s']:.4g} "
-              f"atom-steps/s", file=sys.stderr, flush=True)
+              f"atom-steps/s; mean batch {serving['mean_batch_saturated']:.1f} (saturated), "
+              f"{serving['mean_batch_poisson']:.1f} (Poisson)", file=sys.stderr, flush=True)
 
     cpu = None
     errs = {}

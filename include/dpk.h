@@ -174,9 +174,14 @@ int dpk_debug_descriptor(dpk_ctx *c, double *T, double *dT);
  * A server owns nslots device slots on one GPU (each a context with its own stream and workspace,
  * sharing one copy of the model). A scheduler thread admits queued frames in arrival order as
  * soon as a slot is idle and the HBM budget (model + every slot's workspace) allows, freeing idle
- * slots' workspaces when that makes room; admitted frames run concurrently on their slots'
- * streams. Frames that name the same simulation go back to the slot that ran its previous frame
- * when it is idle, reusing that slot's device buffers (cell list, neighbour list, descriptor).
+ * slots' workspaces when that makes room; admitted work runs concurrently on the slots' streams.
+ * A free slot takes the longest prefix of the queue that the budget admits (up to 64 frames of at
+ * most 8192 atoms each) as one batch: one launch per stage for all of its frames, atoms of all
+ * frames sorted by type together, each frame with its own cell, bins and results. The head of
+ * the queue is never overtaken. A frame with an atom type out of range fails at submission
+ * (DPK_E_TYPE_RANGE on its ticket); if a batch reports another data error, its frames run again
+ * one by one so that only the faulty frame fails. Batches go back to the slot that ran the
+ * previous frame of their first frame's simulation when it is idle, reusing its device buffers.
  * -------------------------------------------------------------------------------------------- */
 typedef struct dpk_server dpk_server;
 
@@ -196,7 +201,8 @@ typedef struct {
     int64_t submitted, completed, failed;
     int64_t peak_bytes;        /* largest device footprint (model + slot workspaces) reached     */
     int64_t budget_waits;      /* admissions delayed because the budget was full                  */
-    int64_t slot_reuse;        /* frames that ran on the slot of their simulation's previous frame */
+    int64_t slot_reuse;        /* batches that ran on the slot of their simulation's previous frame */
+    int64_t launches;          /* batches launched (frames completed / launches = mean batch size) */
 } dpk_server_counters;
 
 /* hbm_budget_bytes = 0: no bound. nslots in 1..64. */

@@ -1226,6 +1226,7 @@ int launch(dpk_server* s, Slot& sl, const std::vector<Request*>& batch)
     HIPCHK(hipEventRecord(sl.done, st));
     const int64_t sim = batch[0]->f.simulation;
     if (sl.sim >= 0 && sl.sim == sim) s->st.slot_reuse++;
+    s->st.launches++;
     sl.sim = sim;
     sl.reqs = batch;
     const int64_t t = now_ns();
@@ -1237,9 +1238,11 @@ int launch(dpk_server* s, Slot& sl, const std::vector<Request*>& batch)
 }
 
 // Scheduler thread: completes finished batches, then admits queued frames in arrival order. A
-// free slot takes the longest prefix of the queue (up to BATCH_MAX_FRAMES frames small enough for
-// the batched launches) whose combined workspace the admission rule accepts; the head is never
-// overtaken, so nothing starves, and under light load batches stay short.
+// free slot takes a prefix of the queue as one batch (up to BATCH_MAX_FRAMES frames small enough
+// for the batched launches): it grows while the admission rule accepts the combined workspace,
+// up to BATCH_TARGET_ATOMS atoms and the slot's share of the budget. The head is never
+// overtaken, so nothing starves; under light load batches stay short.
+constexpr int64_t BATCH_TARGET_ATOMS = 4096;
 void scheduler(dpk_server* s)
 {
     hipSetDevice(s->device);
@@ -1290,11 +1293,17 @@ void scheduler(dpk_server* s)
                 int plan = dpk_admit_plan(ns, busy.data(), bytes.data(), sims.data(), r->need, r->f.simulation,
                                           s->budget, s->model_bytes, &slot, &rel);
                 if (plan > 0 && batchable(r)) {
+                    // a batch grows until it holds BATCH_TARGET_ATOMS atoms or its workspace would
+                    // exceed this slot's share of the budget, so that every slot can run at once
                     const int kmax = (int)std::min<size_t>(s->queue.size(), BATCH_MAX_FRAMES);
-                    for (int k = 2; k <= kmax; ++k) {
+                    const int64_t share = s->budget ? (s->budget - s->model_bytes) / ns : INT64_MAX;
+                    int64_t atoms = r->f.natoms;
+                    for (int k = 2; k <= kmax && atoms < BATCH_TARGET_ATOMS; ++k) {
                         if (!batchable(s->queue[k - 1])) break;
                         int32_t sk = -1, rk = 0;
                         const int64_t need = batch_need(s->slots[0].ctx, s->queue, k);
+                        if (need > share) break;
+                        atoms += s->queue[k - 1]->f.natoms;
                         if (dpk_admit_plan(ns, busy.data(), bytes.data(), sims.data(), need, r->f.simulation,
                                            s->budget, s->model_bytes, &sk, &rk) <= 0)
                             break;

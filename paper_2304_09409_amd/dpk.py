@@ -235,7 +235,8 @@ class _Frame(C.Structure):
 
 class _Counters(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
-                ("peak_bytes", C.c_int64), ("budget_waits", C.c_int64), ("slot_reuse", C.c_int64)]
+                ("peak_bytes", C.c_int64), ("budget_waits", C.c_int64), ("slot_reuse", C.c_int64),
+                ("launches", C.c_int64)]
 
 
 def _server_sigs(L):

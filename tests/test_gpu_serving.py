@@ -1,7 +1,8 @@
 """Serving: frames of uneven size from several simulations admitted into device slots.
 
 * every frame's result in the mix equals the same frame computed alone (same precision), to the
-  reordering of FP64 force atomics (1e-12 eV/A absolute, 1e-12 relative energy);
+  reordering of FP64 force atomics and of the energy/virial sums (1e-12 eV/A absolute, 1e-12
+  relative energy); frames submitted together run as batches (fewer launches than frames);
 * FP64 server results match the CPU oracle within 1e-10 eV/A;
 * under an HBM budget that holds about two frames, admission waits, the device footprint never
   exceeds the budget, and every frame completes with the same result;
@@ -60,6 +61,7 @@ def test_mix_equals_alone(dpk, model):
     st = srv.stats()
     print(f"  stats {st}", flush=True)
     assert st["completed"] == 24 and st["failed"] == 0
+    assert st["launches"] < st["completed"]   # frames queued together ran as batches
     srv.close()
 
 
