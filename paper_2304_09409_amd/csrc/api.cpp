@@ -256,6 +256,8 @@ struct dpk_ctx {
 
 namespace {
 
+int check_stats(const dpk_ctx* c, const DevStats& st);
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Byte layout of the workspace for n atoms and ncell bins; if base != nullptr, assign views.
@@ -886,6 +888,16 @@ int dpk_ctx_check(dpk_ctx* c)
     HIPCHK(hipStreamSynchronize(c->last_stream));
     DevStats st;
     HIPCHK(hipMemcpy(&st, c->stats, sizeof(st), hipMemcpyDeviceToHost));
+    return check_stats(c, st);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Error status of a finished frame from a host copy of its statistics block.
+int check_stats(const dpk_ctx* c, const DevStats& st)
+{
     if (st.err_type) return fail(DPK_E_TYPE_RANGE, "an atom type is outside [0, %d)", c->model->desc.ntypes);
     if (st.err_overflow)
         return fail(DPK_E_NBR_OVERFLOW, "%d atoms within r_c of one atom exceed the selection buffer (%d)", st.max_cand,
@@ -894,6 +906,10 @@ int dpk_ctx_check(dpk_ctx* c)
         return fail(DPK_E_NBR_OVERFLOW, "%llu neighbours cut by sel (strict mode)", (unsigned long long)st.nbr_dropped);
     return DPK_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int dpk_compute(dpk_ctx* c, int64_t natoms, const double* coord, const int32_t* atype, const double* box, double* energy,
                 double* force, double* virial, double* atom_energy)
@@ -1044,6 +1060,7 @@ struct Request {
     int64_t ncell = 0;         // bins of the frame
     int64_t out_off = 0;       // first double of its outputs in the slot's output staging
     bool solo = false;         // run alone (after its batch reported a data error)
+    bool big_cap = false;      // largest candidate buffer (after overflowing the estimated one)
     int state = 0;             // 0 queued, 1 running, 2 done
     int result = 0;
     std::string err;
@@ -1059,6 +1076,7 @@ struct Slot {
     int* pin_type = nullptr;
     double* pin_out = nullptr;
     int64_t pin_cap = 0;
+    DevStats* pin_stats = nullptr;     // host copy of the batch's statistics block
 };
 
 void release_ws(dpk_ctx* c)
@@ -1073,9 +1091,22 @@ void release_ws(dpk_ctx* c)
     c->cap_cells = 0;
 }
 
-// Workspace bytes of a frame (cell grid from the host copy of the frame).
-int frame_need(dpk_ctx* c, const dpk_frame& f, int64_t* need, int64_t* ncell)
+// Host-only context with the sizes of a slot's context, for workspace planning off the slots.
+void plan_ctx(const dpk_ctx* c0, dpk_ctx* p)
 {
+    p->model = c0->model;
+    p->device = c0->device;
+    p->precision = c0->precision;
+    p->acc_size = c0->acc_size;
+    p->ncu = c0->ncu;
+}
+
+// Workspace bytes of a frame (cell grid from the host copy of the frame); proto sizes the layout.
+int frame_need(const dpk_ctx* proto, const dpk_frame& f, int64_t* need, int64_t* ncell)
+{
+    dpk_ctx cc;
+    plan_ctx(proto, &cc);
+    dpk_ctx* c = &cc;
     GeomParams gp;
     int rc;
     c->cur_natoms = f.natoms;
@@ -1112,6 +1143,7 @@ struct dpk_server {
     std::atomic<bool> stop{false};
     dpk_server_counters st{};
     int64_t model_bytes = 0;
+    dpk_ctx plan;                      // host-only context for workspace sizing (never launched on)
 };
 
 namespace {
@@ -1123,41 +1155,27 @@ int64_t resident_bytes(dpk_server* s)
     return b;
 }
 
-void finish_one(dpk_server* s, Request* r, const double* out, int rc, const std::string& msg)
+// Copy a finished frame's results from its slot's output staging into the caller's buffers (the
+// caller reads them only after the frame is published).
+void copy_result(Request* r, const double* out)
+{
+    const int64_t n = r->f.natoms;
+    const double* o = out + r->out_off;
+    *r->f.energy = o[0];
+    std::memcpy(r->f.virial, o + 1, sizeof(double) * 9);
+    std::memcpy(r->f.force, o + 10, sizeof(double) * 3 * n);
+    if (r->f.atom_energy) std::memcpy(r->f.atom_energy, o + 10 + 3 * n, sizeof(double) * n);
+}
+
+// Mark a frame finished (server lock held).
+void publish(dpk_server* s, Request* r, int rc, const std::string& msg)
 {
     r->result = rc;
     r->err = msg;
-    if (rc == DPK_OK) {
-        const int64_t n = r->f.natoms;
-        const double* o = out + r->out_off;
-        *r->f.energy = o[0];
-        std::memcpy(r->f.virial, o + 1, sizeof(double) * 9);
-        std::memcpy(r->f.force, o + 10, sizeof(double) * 3 * n);
-        if (r->f.atom_energy) std::memcpy(r->f.atom_energy, o + 10 + 3 * n, sizeof(double) * n);
-        s->st.completed++;
-    } else {
-        s->st.failed++;
-    }
+    if (rc == DPK_OK) s->st.completed++;
+    else s->st.failed++;
     r->t_done = now_ns();
     r->state = 2;
-}
-
-void finish(dpk_server* s, Slot& sl, int rc, const std::string& msg)
-{
-    for (Request* r : sl.reqs) finish_one(s, r, sl.pin_out, rc, msg);
-    sl.reqs.clear();
-}
-
-// Workspace bytes of the first k queued frames run as one batch.
-int64_t batch_need(dpk_ctx* c, const std::deque<Request*>& q, int k)
-{
-    if (k == 1) return q[0]->need;
-    int64_t n = 0, nc = 0;
-    for (int i = 0; i < k; ++i) {
-        n += q[i]->f.natoms;
-        nc += q[i]->ncell + 1;
-    }
-    return (int64_t)layout_ws(c, n, nc, nullptr);
 }
 
 bool batchable(const Request* r)
@@ -1166,8 +1184,10 @@ bool batchable(const Request* r)
 }
 
 // Run a batch of frames on a slot: one frame through the single-frame path, several through the
-// batched launches; host staging in pinned buffers, one copy each way.
-int launch(dpk_server* s, Slot& sl, const std::vector<Request*>& batch)
+// batched launches; host staging in pinned buffers, one copy each way, the statistics block
+// copied back beside the outputs. Called by the scheduler thread without the server lock: the
+// slot and its context belong to that thread alone.
+int launch(Slot& sl, const std::vector<Request*>& batch)
 {
     dpk_ctx* c = sl.ctx;
     int64_t n = 0, outd = 0;
@@ -1177,6 +1197,7 @@ int launch(dpk_server* s, Slot& sl, const std::vector<Request*>& batch)
         outd += 10 + (r->f.atom_energy ? 4 : 3) * r->f.natoms;
     }
     int rc;
+    c->force_big_cap = batch.size() == 1 && batch[0]->big_cap;
     if (batch.size() == 1) {
         if ((rc = ensure_ws(c, n, batch[0]->ncell))) return rc;
     }
@@ -1200,10 +1221,10 @@ int launch(dpk_server* s, Slot& sl, const std::vector<Request*>& batch)
     }
     hipStream_t st = c->stream;
     if (batch.size() > 1) {
-        // the workspace (device coordinate buffers included) is sized by the plan
         std::vector<BatchFrame> fr(batch.size());
         for (size_t i = 0; i < batch.size(); ++i)
             fr[i] = BatchFrame{batch[i]->f.natoms, batch[i]->f.coord, batch[i]->f.box, batch[i]->f.atom_energy != nullptr};
+        // the workspace (device coordinate buffers included) is sized by the plan before staging
         GeomParams gps[BATCH_MAX_FRAMES];
         FrameDesc fd[BATCH_MAX_FRAMES];
         int64_t nn, ncells, od;
@@ -1223,25 +1244,19 @@ int launch(dpk_server* s, Slot& sl, const std::vector<Request*>& batch)
         if (rc) return rc;
     }
     HIPCHK(hipMemcpyAsync(sl.pin_out, c->h_out, sizeof(double) * outd, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(sl.pin_stats, c->stats, sizeof(DevStats), hipMemcpyDeviceToHost, st));
     HIPCHK(hipEventRecord(sl.done, st));
-    const int64_t sim = batch[0]->f.simulation;
-    if (sl.sim >= 0 && sl.sim == sim) s->st.slot_reuse++;
-    s->st.launches++;
-    sl.sim = sim;
-    sl.reqs = batch;
-    const int64_t t = now_ns();
-    for (Request* r : batch) {
-        r->state = 1;
-        r->t_start = t;
-    }
     return DPK_OK;
 }
 
-// Scheduler thread: completes finished batches, then admits queued frames in arrival order. A
-// free slot takes a prefix of the queue as one batch (up to BATCH_MAX_FRAMES frames small enough
-// for the batched launches): it grows while the admission rule accepts the combined workspace,
-// up to BATCH_TARGET_ATOMS atoms and the slot's share of the budget. The head is never
-// overtaken, so nothing starves; under light load batches stay short.
+// Scheduler thread. Each pass (1) polls the slots' events and copies the results of finished
+// batches, (2) under the server lock publishes them, re-queues the frames of a batch that hit a
+// data error, and admits queued frames in arrival order, (3) launches the admitted batches
+// without the lock, so that submit, poll and wait never wait for a launch. A free slot takes a
+// prefix of the queue as one batch (up to BATCH_MAX_FRAMES frames small enough for the batched
+// launches): it grows while the admission rule accepts the combined workspace, up to
+// BATCH_TARGET_ATOMS atoms and the slot's share of the budget. The head is never overtaken, so
+// nothing starves; under light load batches stay short.
 constexpr int64_t BATCH_TARGET_ATOMS = 4096;
 void scheduler(dpk_server* s)
 {
@@ -1249,37 +1264,67 @@ void scheduler(dpk_server* s)
     const int ns = (int)s->slots.size();
     std::vector<int32_t> busy(ns);
     std::vector<int64_t> bytes(ns), sims(ns);
+    struct Finished {
+        int slot, rc;
+        std::string msg;
+    };
+    struct Admitted {
+        int slot;
+        std::vector<Request*> reqs;
+        int rc;
+        std::string msg;
+    };
+    std::vector<Finished> fin;
+    std::vector<Admitted> adm;
     while (true) {
-        bool progressed = false;
+        // (1) finished batches: the slot state belongs to this thread
+        fin.clear();
+        for (int k = 0; k < ns; ++k) {
+            Slot& sl = s->slots[k];
+            if (sl.reqs.empty()) continue;
+            const hipError_t q = hipEventQuery(sl.done);
+            if (q == hipErrorNotReady) continue;
+            Finished f{k, DPK_OK, std::string()};
+            if (q != hipSuccess) {
+                f.rc = DPK_E_DEVICE;
+                f.msg = hipGetErrorString(q);
+            } else {
+                f.rc = check_stats(sl.ctx, *sl.pin_stats);
+                if (f.rc) f.msg = g_err;
+            }
+            if (f.rc == DPK_OK)
+                for (Request* r : sl.reqs) copy_result(r, sl.pin_out);
+            fin.push_back(std::move(f));
+        }
+        adm.clear();
+        bool stop_now = false;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            for (auto& sl : s->slots) {
-                if (sl.reqs.empty()) continue;
-                hipError_t q = hipEventQuery(sl.done);
-                if (q == hipErrorNotReady) continue;
-                int rc = DPK_OK;
-                std::string msg;
-                if (q != hipSuccess) {
-                    rc = DPK_E_DEVICE;
-                    msg = hipGetErrorString(q);
-                } else {
-                    rc = dpk_ctx_check(sl.ctx);
-                    if (rc) msg = g_err;
-                }
-                if (rc != DPK_OK && rc != DPK_E_DEVICE && sl.reqs.size() > 1) {
+            // (2) publish, or re-queue ahead of the queue
+            for (Finished& f : fin) {
+                Slot& sl = s->slots[f.slot];
+                const bool data_err = f.rc != DPK_OK && f.rc != DPK_E_DEVICE;
+                if (data_err && sl.reqs.size() > 1) {
                     // a data error of one frame fails the batch: run its frames again one by one,
-                    // ahead of the queue, so that only the faulty frame reports the error
+                    // so that only the faulty frame reports the error
                     for (auto it = sl.reqs.rbegin(); it != sl.reqs.rend(); ++it) {
                         (*it)->solo = true;
                         (*it)->state = 0;
                         s->queue.push_front(*it);
                     }
-                    sl.reqs.clear();
+                } else if (f.rc == DPK_E_NBR_OVERFLOW && !sl.reqs[0]->big_cap) {
+                    // a locally dense frame overflowed the estimated candidate buffer: once more
+                    // with the largest
+                    Request* r = sl.reqs[0];
+                    r->big_cap = true;
+                    r->state = 0;
+                    s->queue.push_front(r);
                 } else {
-                    finish(s, sl, rc, msg);
+                    for (Request* r : sl.reqs) publish(s, r, f.rc, f.msg);
                 }
-                progressed = true;
+                sl.reqs.clear();
             }
+            // admission
             while (!s->queue.empty()) {
                 for (int k = 0; k < ns; ++k) {
                     busy[k] = !s->slots[k].reqs.empty();
@@ -1287,27 +1332,30 @@ void scheduler(dpk_server* s)
                     sims[k] = s->slots[k].sim;
                 }
                 Request* r = s->queue.front();
-                // longest admissible prefix of batchable frames (the head alone otherwise)
                 int take = 1;
+                int64_t need = r->need;
                 int32_t slot = -1, rel = 0;
-                int plan = dpk_admit_plan(ns, busy.data(), bytes.data(), sims.data(), r->need, r->f.simulation,
-                                          s->budget, s->model_bytes, &slot, &rel);
+                const int plan = dpk_admit_plan(ns, busy.data(), bytes.data(), sims.data(), r->need,
+                                                r->f.simulation, s->budget, s->model_bytes, &slot, &rel);
                 if (plan > 0 && batchable(r)) {
-                    // a batch grows until it holds BATCH_TARGET_ATOMS atoms or its workspace would
-                    // exceed this slot's share of the budget, so that every slot can run at once
+                    // longest admissible prefix of batchable frames
                     const int kmax = (int)std::min<size_t>(s->queue.size(), BATCH_MAX_FRAMES);
                     const int64_t share = s->budget ? (s->budget - s->model_bytes) / ns : INT64_MAX;
-                    int64_t atoms = r->f.natoms;
+                    int64_t atoms = r->f.natoms, cells = r->ncell + 1;
                     for (int k = 2; k <= kmax && atoms < BATCH_TARGET_ATOMS; ++k) {
-                        if (!batchable(s->queue[k - 1])) break;
+                        const Request* q = s->queue[k - 1];
+                        if (!batchable(q)) break;
+                        const int64_t nk = (int64_t)layout_ws(&s->plan, atoms + q->f.natoms, cells + q->ncell + 1,
+                                                              nullptr);
+                        if (nk > share) break;
                         int32_t sk = -1, rk = 0;
-                        const int64_t need = batch_need(s->slots[0].ctx, s->queue, k);
-                        if (need > share) break;
-                        atoms += s->queue[k - 1]->f.natoms;
-                        if (dpk_admit_plan(ns, busy.data(), bytes.data(), sims.data(), need, r->f.simulation,
+                        if (dpk_admit_plan(ns, busy.data(), bytes.data(), sims.data(), nk, r->f.simulation,
                                            s->budget, s->model_bytes, &sk, &rk) <= 0)
                             break;
+                        atoms += q->f.natoms;
+                        cells += q->ncell + 1;
                         take = k;
+                        need = nk;
                         slot = sk;
                         rel = rk;
                     }
@@ -1320,33 +1368,56 @@ void scheduler(dpk_server* s)
                 }
                 std::vector<Request*> batch(s->queue.begin(), s->queue.begin() + take);
                 s->queue.erase(s->queue.begin(), s->queue.begin() + take);
-                int rc = DPK_OK;
                 if (plan < 0) {
-                    rc = plan;
-                    g_err = "frame does not fit the server's HBM budget";
-                } else {
-                    const int64_t need = batch_need(s->slots[0].ctx, std::deque<Request*>(batch.begin(), batch.end()),
-                                                    take);
-                    if (rel) {
-                        for (int k = 0; k < ns; ++k)
-                            if (!busy[k] && k != slot) release_ws(s->slots[k].ctx);
-                        if ((int64_t)s->slots[slot].ctx->ws_bytes > need) release_ws(s->slots[slot].ctx);
-                    }
-                    rc = launch(s, s->slots[slot], batch);
-                    s->st.peak_bytes = std::max(s->st.peak_bytes, resident_bytes(s));
+                    for (Request* b : batch) publish(s, b, plan, "frame does not fit the server's HBM budget");
+                    continue;
                 }
-                if (rc) {
-                    for (Request* b : batch) finish_one(s, b, nullptr, rc, g_err);
-                    if (slot >= 0) s->slots[slot].reqs.clear();
+                Slot& sl = s->slots[slot];
+                if (rel) {
+                    for (int k = 0; k < ns; ++k)
+                        if (!busy[k] && k != slot) release_ws(s->slots[k].ctx);
+                    if ((int64_t)sl.ctx->ws_bytes > need) release_ws(sl.ctx);
                 }
-                progressed = true;
+                // reserve the slot; its workspace grows to the batch's during the launch
+                const int64_t sim = r->f.simulation;
+                if (sl.sim >= 0 && sl.sim == sim) s->st.slot_reuse++;
+                s->st.launches++;
+                sl.sim = sim;
+                sl.reqs = batch;
+                const int64_t t = now_ns();
+                for (Request* b : batch) {
+                    b->state = 1;
+                    b->t_start = t;
+                }
+                adm.push_back(Admitted{slot, std::move(batch), DPK_OK, std::string()});
             }
-            if (progressed) s->cv.notify_all();
+            if (!fin.empty()) s->cv.notify_all();
             bool idle = s->queue.empty();
             for (auto& sl : s->slots) idle &= sl.reqs.empty();
-            if (s->stop && idle) break;
+            stop_now = s->stop && idle;
         }
-        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        if (stop_now) break;
+        // (3) launch without the lock
+        bool failed = false;
+        for (Admitted& a : adm) {
+            a.rc = launch(s->slots[a.slot], a.reqs);
+            if (a.rc) {
+                a.msg = g_err;
+                failed = true;
+            }
+        }
+        if (!adm.empty()) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (Admitted& a : adm) {
+                if (a.rc) {
+                    for (Request* r : a.reqs) publish(s, r, a.rc, a.msg);
+                    s->slots[a.slot].reqs.clear();
+                }
+            }
+            s->st.peak_bytes = std::max(s->st.peak_bytes, resident_bytes(s));
+            if (failed) s->cv.notify_all();
+        }
+        if (fin.empty() && adm.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
 
@@ -1425,9 +1496,14 @@ int dpk_server_create(const dpk_model* m, int device, int precision, int nslots,
             if (rc) g_err = "hipStreamCreate failed";
         }
         if (!rc && hipEventCreateWithFlags(&s->slots[k].done, hipEventDisableTiming) != hipSuccess) rc = DPK_E_DEVICE;
+        if (!rc && hipHostMalloc((void**)&s->slots[k].pin_stats, sizeof(DevStats)) != hipSuccess) {
+            s->slots[k].pin_stats = nullptr;
+            rc = fail(DPK_E_OOM, "pinned statistics staging failed");
+        }
         if (rc) {
             for (int q = k; q >= 0; --q) {
                 if (s->slots[q].done) hipEventDestroy(s->slots[q].done);
+                hipHostFree(s->slots[q].pin_stats);
                 if (s->slots[q].ctx) dpk_ctx_free(s->slots[q].ctx);
             }
             delete s;
@@ -1435,6 +1511,7 @@ int dpk_server_create(const dpk_model* m, int device, int precision, int nslots,
         }
     }
     s->model_bytes = (int64_t)s->slots[0].ctx->model_bytes;
+    plan_ctx(s->slots[0].ctx, &s->plan);
     if (s->budget && s->model_bytes > s->budget) {
         dpk_server_free(s);
         return fail(DPK_E_BUDGET, "model alone exceeds the server budget");
@@ -1450,7 +1527,7 @@ int dpk_server_submit(dpk_server* s, const dpk_frame* f, uint64_t* ticket)
         return fail(DPK_E_INVALID_ARG, "bad frame");
     auto r = std::make_unique<Request>();
     r->f = *f;
-    int rc = frame_need(s->slots[0].ctx, *f, &r->need, &r->ncell);
+    int rc = frame_need(&s->plan, *f, &r->need, &r->ncell);
     if (rc) return rc;
     const int nt = s->model->desc.ntypes;
     bool bad = false;
@@ -1465,8 +1542,7 @@ int dpk_server_submit(dpk_server* s, const dpk_frame* f, uint64_t* ticket)
     s->st.submitted++;
     if (bad) {
         // the frame fails alone, without a device launch (the ticket reports the error)
-        r->state = 1;
-        finish_one(s, r.get(), nullptr, DPK_E_TYPE_RANGE, "an atom type is outside [0, " + std::to_string(nt) + ")");
+        publish(s, r.get(), DPK_E_TYPE_RANGE, "an atom type is outside [0, " + std::to_string(nt) + ")");
         s->cv.notify_all();
     } else {
         s->queue.push_back(r.get());
@@ -1530,6 +1606,7 @@ void dpk_server_free(dpk_server* s)
         hipHostFree(sl.pin_coord);
         hipHostFree(sl.pin_type);
         hipHostFree(sl.pin_out);
+        hipHostFree(sl.pin_stats);
     }
     // slots past the first share its model buffers: free them first
     for (size_t k = s->slots.size(); k-- > 0;)

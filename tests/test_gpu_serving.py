@@ -6,7 +6,9 @@
 * FP64 server results match the CPU oracle within 1e-10 eV/A;
 * under an HBM budget that holds about two frames, admission waits, the device footprint never
   exceeds the budget, and every frame completes with the same result;
-* a bad frame fails alone (its error code), and a frame larger than the budget is refused.
+* a bad frame fails alone (its error code), and a frame larger than the budget is refused;
+* a locally dense frame in a large cell, whose candidate buffer sized from the mean density
+  overflows, is run again with the largest buffer and equals the single-frame result.
 """
 import sys
 
@@ -126,3 +128,23 @@ def test_errors_are_isolated(dpk, model):
         small.submit(*big)
     assert e.value.code == dpk.DPK_E_BUDGET
     small.close()
+
+
+def test_dense_frame_retried_with_large_buffer(dpk, model):
+    say("serving: locally dense frame overflows the estimated candidate buffer")
+    fr = _frames(2, 21)
+    # 400 atoms at 3.5x liquid density in a 40 A cell: about 300 within r_c of an inner atom,
+    # while the mean density of the cell predicts a few
+    c, t, _ = synth.serving_frame(400, 5, 3, density=0.35)
+    dense = (c + 15.0, t, np.diag([40.0] * 3))
+    ctx = dpk.Context(model, precision="mixed")
+    alone = [ctx.compute(*f) for f in (fr[0], dense, fr[1])]
+    ctx.close()
+    srv = dpk.Server(model, precision="mixed", nslots=2)
+    tickets = [srv.submit(*f) for f in (fr[0], dense, fr[1])]
+    for f, a, tk in zip((fr[0], dense, fr[1]), alone, tickets):
+        _compare(tk.result(), a, len(f[1]))
+    st = srv.stats()
+    print(f"  stats {st}", flush=True)
+    assert st["completed"] == 3 and st["failed"] == 0
+    srv.close()
