@@ -67,16 +67,21 @@ struct PF64 {
         d = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[3], b.v[3], d, 0, 0, 0);
     }
     __device__ static acc act(acc x) { return tanh(x); }
+    // tanh(x + b) from the bias as staged (unscaled)
+    __device__ static acc act_b(acc x, acc b) { return tanh(x + b); }
+    static constexpr double BIAS_SCALE = 1.0;
 };
 
-// FP32 hyperbolic tangent: 1 - 2 / (exp(2x) + 1), with exp(2x) = 2^(2x log2 e) on the hardware
-// exp2 and the hardware reciprocal. Saturates to +-1 without overflow trouble (2^inf = inf,
-// 1/inf = 0). Absolute error about 1e-7.
-__device__ __forceinline__ float tanh_fast(float x)
+// FP32 hyperbolic tangent: 1 - 2 / (exp(2x) + 1), with exp(2x) = 2^(K x), K = 2 log2 e, on the
+// hardware exp2 and the hardware reciprocal. Saturates to +-1 without overflow trouble (2^inf =
+// inf, 1/inf = 0). Absolute error about 1e-7. tanh_scaled takes y = K x, so that a bias staged as
+// K b folds into one FMA: tanh(x + b) = tanh_scaled(K x + K b).
+constexpr float TANH_K = 2.885390081777927f;
+__device__ __forceinline__ float tanh_scaled(float y)
 {
-    float e = __builtin_amdgcn_exp2f(x * 2.885390081777927f);
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y) + 1.0f);
 }
+__device__ __forceinline__ float tanh_fast(float x) { return tanh_scaled(x * TANH_K); }
 
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo)
 {
@@ -131,6 +136,9 @@ struct PMIX {
         d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, d, 0, 0, 0);
     }
     __device__ static acc act(acc x) { return tanh_fast(x); }
+    // tanh(x + b) from the bias as staged (K b)
+    __device__ static acc act_b(acc x, acc kb) { return tanh_scaled(__builtin_fmaf(x, TANH_K, kb)); }
+    static constexpr float BIAS_SCALE = TANH_K;
 };
 
 // Plain BF16 operands on the same instruction, one product (fast, about 1e-2 relative force error).
@@ -163,6 +171,9 @@ struct PBF16 {
         d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, d, 0, 0, 0);
     }
     __device__ static acc act(acc x) { return tanh_fast(x); }
+    // tanh(x + b) from the bias as staged (K b)
+    __device__ static acc act_b(acc x, acc kb) { return tanh_scaled(__builtin_fmaf(x, TANH_K, kb)); }
+    static constexpr float BIAS_SCALE = TANH_K;
 };
 
 template <class V> __device__ __forceinline__ void zero4(V& v) { v[0] = 0; v[1] = 0; v[2] = 0; v[3] = 0; }
@@ -219,20 +230,21 @@ template <class T> __device__ __forceinline__ T sum_groups4(const T* p)
     return q0 + q1;
 }
 
-// Switching function of Sec. II.A.1 (eq. switch) and its derivative, FP64.
-__device__ __forceinline__ void switch_fn(double r, double rs, double rc, double& s, double& ds)
+// Switching function of Sec. II.A.1 (eq. switch) and its derivative, FP64, from r, ir = 1/r and
+// inv_w = 1/(rc - rs) (no division here: the caller's 1/r is the only one per neighbour).
+__device__ __forceinline__ void switch_fn(double r, double ir, double rs, double rc, double inv_w, double& s,
+                                          double& ds)
 {
     if (r < rs) {
-        s = 1.0 / r;
-        ds = -1.0 / (r * r);
+        s = ir;
+        ds = -ir * ir;
     } else if (r < rc) {
-        double x = (r - rs) / (rc - rs);
+        double x = (r - rs) * inv_w;
         double x2 = x * x;
         double u = x2 * x * (x * (15.0 - 6.0 * x) - 10.0) + 1.0;
         double du = -30.0 * x2 * (x - 1.0) * (x - 1.0);
-        double ir = 1.0 / r;
         s = u * ir;
-        ds = du * ir / (rc - rs) - u * ir * ir;
+        ds = du * ir * inv_w - u * ir * ir;
     } else {
         s = 0.0;
         ds = 0.0;
@@ -294,7 +306,11 @@ __device__ void stage_net(const EmbArgs& A, int net, typename P::acc* s_vec, cha
     typedef typename P::wt wt;
     typedef EmbCfg<P> Cfg;
     const acc* ev = reinterpret_cast<const acc*>(A.evec) + (size_t)net * EVEC;
-    for (int i = threadIdx.x; i < EVEC; i += blockDim.x) s_vec[i] = ev[i];
+    // biases of layers 2 and 3 staged pre-scaled for P::act_b
+    for (int i = threadIdx.x; i < EVEC; i += blockDim.x) {
+        const bool bias = (i >= EV_B2 && i < EV_B2 + N2P) || (i >= EV_B3 && i < EV_B3 + N3P);
+        s_vec[i] = bias ? ev[i] * (acc)P::BIAS_SCALE : ev[i];
+    }
     const int nets = A.type_one_side ? A.ntypes : A.ntypes * A.ntypes;
     const wt* src = reinterpret_cast<const wt*>(A.emat) + (size_t)net * EM_SIZE;
     const int64_t plane = (int64_t)nets * EM_SIZE;
@@ -361,6 +377,7 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar registers)
     const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const double inv_w = 1.0 / (A.rc - A.rs);
     const int a0 = blockIdx.x * APB;
     const int a1 = min(a0 + APB, A.natoms);
     if (a0 >= a1) return;
@@ -412,10 +429,11 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
                 const bool valid = cc0 + p < cnp;
                 double s = 0.0, R[4] = {0.0, 0.0, 0.0, 0.0};
                 if (valid) {
-                    double r = sqrt(x * x + y * y + z * z);
+                    const double r = sqrt(x * x + y * y + z * z);
+                    const double ir = 1.0 / r;
                     double ds;
-                    switch_fn(r, A.rs, A.rc, s, ds);
-                    double sr = s / r;
+                    switch_fn(r, ir, A.rs, A.rc, inv_w, s, ds);
+                    const double sr = s * ir;
                     R[0] = s; R[1] = sr * x; R[2] = sr * y; R[3] = sr * z;
                 }
                 wave_sync();
@@ -470,7 +488,7 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
                             const int n = 16 * t + P::orow(g, r);
                             zt[t][r] = 0;
                             if (n < E1) {
-                                zt[t][r] = s_vec[EV_WH2 + n] * P::act(acc2[t][r] + s_vec[EV_B2 + n]) + s_z1[wave][n % E0][p];
+                                zt[t][r] = s_vec[EV_WH2 + n] * P::act_b(acc2[t][r], s_vec[EV_B2 + n]) + s_z1[wave][n % E0][p];
                                 s_z2[wave][p][n] = zt[t][r];
                             }
                         }
@@ -499,7 +517,7 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
                         const acc wh = s_vec[EV_WH3 + m], bb = s_vec[EV_B3 + m];
                         for (int r = 0; r < 4; ++r) {
                             const int q = P::orow(g, r);
-                            const acc G = wh * P::act(acc3[tm][r] + bb) + s_z2[wave][q][m % E1];
+                            const acc G = wh * P::act_b(acc3[tm][r], bb) + s_z2[wave][q][m % E1];
                             for (int k = 0; k < 4; ++k) Tacc[tm][k] += G * s_R[wave][q][k];
                         }
                     }
@@ -549,6 +567,7 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar registers)
     const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const double inv_w = 1.0 / (A.rc - A.rs);
     const int a0 = blockIdx.x * APB;
     const int a1 = min(a0 + APB, A.natoms);
     double vir[9];
@@ -609,12 +628,12 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
 
                 const int p = c16;
                 const bool valid = cc0 + p < cnp;
-                double r = 1.0, s = 0.0, ds = 0.0;
+                double ir = 1.0, s = 0.0, ds = 0.0;
                 if (valid) {
-                    r = sqrt(x * x + y * y + z * z);
-                    switch_fn(r, A.rs, A.rc, s, ds);
+                    const double r = sqrt(x * x + y * y + z * z);
+                    ir = 1.0 / r;
+                    switch_fn(r, ir, A.rs, A.rc, inv_w, s, ds);
                 }
-                const double ir = 1.0 / r;
                 const double ux = x * ir, uy = y * ir, uz = z * ir, sr = s * ir;
                 const acc Ra[4] = {(acc)s, (acc)(sr * x), (acc)(sr * y), (acc)(sr * z)};
                 acc dR[4] = {0, 0, 0, 0}, H[4] = {0, 0, 0, 0};
@@ -675,7 +694,7 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
                             zt[t][rr] = 0;
                             ztd[t][rr] = 0;
                             if (n < E1) {
-                                const acc t2 = P::act(acc2[t][rr] + s_vec[EV_B2 + n]);
+                                const acc t2 = P::act_b(acc2[t][rr], s_vec[EV_B2 + n]);
                                 const acc wh = s_vec[EV_WH2 + n];
                                 zt[t][rr] = wh * t2 + s_z1[wave][n % E0][p];
                                 ztd[t][rr] = wh * (1 - t2 * t2) * acc2d[t][rr] + s_z1d[wave][n % E0][p];
@@ -711,7 +730,7 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
                         for (int rr = 0; rr < 4; ++rr) {
                             const int m = 16 * tm + P::orow(g, rr);
                             if (m >= E2) continue;
-                            const acc t3 = P::act(acc3[tm][rr] + s_vec[EV_B3 + m]);
+                            const acc t3 = P::act_b(acc3[tm][rr], s_vec[EV_B3 + m]);
                             const acc wh = s_vec[EV_WH3 + m];
                             const acc G = wh * t3 + s_z2[wave][m % E1][p];
                             const acc Gd = wh * (1 - t3 * t3) * acc3d[tm][rr] + s_z2d[wave][m % E1][p];
