@@ -265,7 +265,7 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
 {
     const dpk_model* m = c->model;
     const int nt = m->desc.ntypes, nc = m->nc;
-    const int64_t nvb = (n + embed_atoms_per_block(c->precision) - 1) / embed_atoms_per_block(c->precision);
+    const int64_t nvb = embed_bwd_max_blocks(c->precision, n);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char* p = base ? base + off : nullptr;
@@ -554,6 +554,8 @@ void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* vir_atom, std:
     ea.ntypes = nt;
     ea.nc = m->nc;
     ea.type_one_side = m->desc.type_one_side;
+    ea.ncu = c->ncu;
+    ea.apw = 1;
     for (int t = 0; t < nt; ++t) ea.off[t] = gp.off[t];
     ea.itype = c->itype;
     ea.nnei = c->nnei;
@@ -655,6 +657,17 @@ int batch_plan(dpk_ctx* c, int nf, const BatchFrame* fr, GeomParams* gps, FrameD
     return DPK_OK;
 }
 
+// Pinned staging of a batch's frame descriptors and geometries (allocated once per context).
+int ensure_pin_desc(dpk_ctx* c)
+{
+    if (c->pin_desc) return DPK_OK;
+    if (hipHostMalloc(&c->pin_desc, (sizeof(FrameDesc) + sizeof(GeomParams)) * BATCH_MAX_FRAMES) != hipSuccess) {
+        c->pin_desc = nullptr;
+        return fail(DPK_E_OOM, "pinned staging of the batch descriptors failed");
+    }
+    return DPK_OK;
+}
+
 // Several frames in one launch per stage (serving): coordinates and types of all frames
 // concatenated in caller order on the device; results of frame f at d_out + fd[f].out_off.
 int compute_batch(dpk_ctx* c, int nf, const BatchFrame* fr, const double* d_coord, const int* d_atype,
@@ -666,11 +679,7 @@ int compute_batch(dpk_ctx* c, int nf, const BatchFrame* fr, const double* d_coor
     int ms, mc, rc;
     if ((rc = batch_plan(c, nf, fr, gps, fd, &n, &ncells, &ms, &mc, &outd))) return rc;
     if ((rc = ensure_ws(c, n, ncells))) return rc;
-    if (!c->pin_desc &&
-        hipHostMalloc(&c->pin_desc, (sizeof(FrameDesc) + sizeof(GeomParams)) * BATCH_MAX_FRAMES) != hipSuccess) {
-        c->pin_desc = nullptr;
-        return fail(DPK_E_OOM, "pinned staging of the batch descriptors failed");
-    }
+    if ((rc = ensure_pin_desc(c))) return rc;
     // the previous use of the staging has completed: this context's last frame is done
     if (c->last_stream) HIPCHK(hipStreamSynchronize(c->last_stream));
     FrameDesc* pfd = (FrameDesc*)c->pin_desc;
@@ -870,7 +879,7 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
 
     run_network(c, n, gp, nullptr, ev, s);
     prof_mark(ev, DPK_STAGE_FINAL, s);
-    const int nvp = (n + embed_atoms_per_block(c->precision) - 1) / embed_atoms_per_block(c->precision);
+    const int nvp = embed_bwd_blocks(c->precision, n, c->ncu);
     launch_finalize(n, c->Ei, nvp, c->vir_part, d_energy, d_virial, c->perm, c->F, d_force, d_atom_energy, s);
     prof_mark(ev, DPK_NSTAGES, s);
     HIPCHK(hipGetLastError());
@@ -1091,6 +1100,11 @@ void release_ws(dpk_ctx* c)
     c->cap_cells = 0;
 }
 
+// A batch grows to at least BATCH_TARGET_ATOMS atoms when frames queue up; the pinned staging
+// reserved per slot holds such a batch plus one more frame of the largest batchable size.
+constexpr int64_t BATCH_TARGET_ATOMS = 4096;
+constexpr int64_t PIN_RESERVE_ATOMS = BATCH_TARGET_ATOMS + 8192;
+
 // Host-only context with the sizes of a slot's context, for workspace planning off the slots.
 void plan_ctx(const dpk_ctx* c0, dpk_ctx* p)
 {
@@ -1178,6 +1192,25 @@ void publish(dpk_server* s, Request* r, int rc, const std::string& msg)
     r->state = 2;
 }
 
+// Pinned host staging of a slot for n atoms. The server reserves PIN_RESERVE_ATOMS per slot at
+// creation: pinning host memory while frames are submitted stalls the submitting threads (page
+// faults wait for the pinning), so only a frame larger than the reserve grows it later.
+int ensure_pinned(Slot& sl, int64_t n)
+{
+    if (sl.pin_cap >= n) return DPK_OK;
+    hipHostFree(sl.pin_coord);
+    hipHostFree(sl.pin_type);
+    hipHostFree(sl.pin_out);
+    sl.pin_coord = nullptr; sl.pin_type = nullptr; sl.pin_out = nullptr; sl.pin_cap = 0;
+    const int64_t cap = std::max<int64_t>(n, 1024);
+    if (hipHostMalloc((void**)&sl.pin_coord, sizeof(double) * 3 * cap) != hipSuccess ||
+        hipHostMalloc((void**)&sl.pin_type, sizeof(int) * cap) != hipSuccess ||
+        hipHostMalloc((void**)&sl.pin_out, sizeof(double) * (10 * BATCH_MAX_FRAMES + 4 * cap)) != hipSuccess)
+        return fail(DPK_E_OOM, "pinned host staging of %lld atoms failed", (long long)cap);
+    sl.pin_cap = cap;
+    return DPK_OK;
+}
+
 bool batchable(const Request* r)
 {
     return !r->solo && r->f.natoms <= prep_small_max_atoms() && r->ncell <= prep_small_max_cells();
@@ -1201,18 +1234,7 @@ int launch(Slot& sl, const std::vector<Request*>& batch)
     if (batch.size() == 1) {
         if ((rc = ensure_ws(c, n, batch[0]->ncell))) return rc;
     }
-    if (sl.pin_cap < n) {
-        hipHostFree(sl.pin_coord);
-        hipHostFree(sl.pin_type);
-        hipHostFree(sl.pin_out);
-        sl.pin_coord = nullptr; sl.pin_type = nullptr; sl.pin_out = nullptr; sl.pin_cap = 0;
-        const int64_t cap = std::max<int64_t>(n, 1024);
-        if (hipHostMalloc((void**)&sl.pin_coord, sizeof(double) * 3 * cap) != hipSuccess ||
-            hipHostMalloc((void**)&sl.pin_type, sizeof(int) * cap) != hipSuccess ||
-            hipHostMalloc((void**)&sl.pin_out, sizeof(double) * (10 * BATCH_MAX_FRAMES + 4 * cap)) != hipSuccess)
-            return fail(DPK_E_OOM, "pinned host staging of %lld atoms failed", (long long)cap);
-        sl.pin_cap = cap;
-    }
+    if ((rc = ensure_pinned(sl, n))) return rc;
     int64_t off = 0;
     for (Request* r : batch) {
         std::memcpy(sl.pin_coord + 3 * off, r->f.coord, sizeof(double) * 3 * r->f.natoms);
@@ -1257,7 +1279,6 @@ int launch(Slot& sl, const std::vector<Request*>& batch)
 // launches): it grows while the admission rule accepts the combined workspace, up to
 // BATCH_TARGET_ATOMS atoms and the slot's share of the budget. The head is never overtaken, so
 // nothing starves; under light load batches stay short.
-constexpr int64_t BATCH_TARGET_ATOMS = 4096;
 void scheduler(dpk_server* s)
 {
     hipSetDevice(s->device);
@@ -1500,10 +1521,15 @@ int dpk_server_create(const dpk_model* m, int device, int precision, int nslots,
             s->slots[k].pin_stats = nullptr;
             rc = fail(DPK_E_OOM, "pinned statistics staging failed");
         }
+        if (!rc) rc = ensure_pinned(s->slots[k], PIN_RESERVE_ATOMS);
+        if (!rc) rc = ensure_pin_desc(s->slots[k].ctx);
         if (rc) {
             for (int q = k; q >= 0; --q) {
                 if (s->slots[q].done) hipEventDestroy(s->slots[q].done);
                 hipHostFree(s->slots[q].pin_stats);
+                hipHostFree(s->slots[q].pin_coord);
+                hipHostFree(s->slots[q].pin_type);
+                hipHostFree(s->slots[q].pin_out);
                 if (s->slots[q].ctx) dpk_ctx_free(s->slots[q].ctx);
             }
             delete s;

@@ -96,6 +96,8 @@ struct FrameDesc {
 // Arguments of the embedding kernels.
 struct EmbArgs {
     int natoms, ntypes, nc, type_one_side;
+    int ncu;                 // compute units of the device (sizes the launch)
+    int apw;                 // atoms per wave (set by the launcher)
     int off[MAXT];
     const int* itype;        // [N] type of internal atom
     const int* nnei;         // [N][ntypes] kept neighbours per type block

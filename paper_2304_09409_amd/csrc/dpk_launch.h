@@ -36,7 +36,10 @@ void launch_finalize(int n, const double* ei, int nvp, const double* vir_part, d
 void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s);
 
 // precision: 0 = FP64, 1 = split-BF16 (three products), 2 = BF16 (one product)
-int embed_atoms_per_block(int precision);
+// blocks of the embedding backward for a frame (one virial partial each), and their maximum over
+// launch shapes (workspace sizing)
+int embed_bwd_blocks(int precision, int64_t natoms, int ncu);
+int64_t embed_bwd_max_blocks(int precision, int64_t natoms);
 int fit_atoms_per_block(int precision);
 void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s);
 void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s);

@@ -253,15 +253,20 @@ __device__ __forceinline__ void switch_fn(double r, double ir, double rs, double
 
 constexpr int ZS = 20;   // row stride (floats) of the feature-major skip buffers; 16 neighbours used
 
-// Launch shape of the embedding kernels: NW waves per block, APW atoms per wave. Split-BF16 runs
-// 8 waves (two per SIMD) sharing one staged net; FP64 runs 4 and keeps W3^T in global memory
-// (L1/L2) to leave LDS for the wider activation buffers.
-template <class P> struct EmbCfg {
+// Launch shape of the embedding kernels: NW waves per block share one staged net; each wave takes
+// A.apw atoms, chosen per launch (embed_apw) between 1 and APW_MAX so that a large frame gets about
+// one block per CU (fewer net stagings per atom) and a small one still spreads over the CUs. FP64
+// runs 4 waves and keeps W3^T in global memory (L1/L2) to leave LDS for the wider activation
+// buffers. The FP32-accumulating policies run:
+//   * forward (network): 12 waves, three per SIMD, in at most 168 VGPRs: the third wave per SIMD
+//     hides more of the exp/rcp and LDS latency;
+//   * forward (table): 8 waves (the polynomial path needs more registers);
+//   * backward: 8 waves (its per-wave activation buffers fill the LDS).
+template <class P, bool FWD = false, bool TAB = false> struct EmbCfg {
     typedef typename P::wt wt;
     static constexpr bool F64 = sizeof(typename P::acc) == 8;
-    static constexpr int NW = F64 ? 4 : 8;
-    static constexpr int APW = 3;
-    static constexpr int APB = NW * APW;
+    static constexpr int NW = F64 ? 4 : (FWD && !TAB ? 12 : 8);
+    static constexpr int APW_MAX = F64 ? 3 : (FWD ? (TAB ? 3 : 4) : 6);
     static constexpr bool W3LDS = !F64;
     // LDS rows of staged weights: one lane's fragment per group (VPL K values; [hi lo] for split
     // BF16), rows padded by 16 B so 16 consecutive rows fall in distinct banks.
@@ -355,14 +360,15 @@ struct ChunkWalk {
 // net each) that add into T[a]; the same lane owns T[a][m][k] in every pass.
 // ---------------------------------------------------------------------------------------------
 template <class P, bool TAB>
-__global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
+__global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(EmbArgs A)
 {
     typedef typename P::acc acc;
     typedef typename P::wt wt;
     typedef typename P::accv accv;
     typedef typename P::frag frag;
-    typedef EmbCfg<P> Cfg;
-    constexpr int NW = Cfg::NW, APW = Cfg::APW, APB = Cfg::APB;
+    typedef EmbCfg<P, true, TAB> Cfg;
+    constexpr int NW = Cfg::NW;
+    const int APW = A.apw, APB = NW * APW;
     constexpr bool W3LDS = Cfg::W3LDS;
     __shared__ acc s_vec[EVEC];
     __shared__ __attribute__((aligned(16))) char s_w2[TAB ? 16 : N2P * Cfg::ROW2];
@@ -415,15 +421,6 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
                 w.fetch(A, tj, c16);
                 if (cc0 == 0)
                     for (int t = 0; t < 7; ++t) zero4(Tacc[t]);
-                // T accumulates over the neighbour-type passes; read the earlier passes' sum now
-                // (lane group g owns component ksel(g) of row 16 tm + c16)
-                acc Tprev[7];
-                if (last && tj > 0) {
-                    for (int tm = 0; tm < 7; ++tm) {
-                        const int m = 16 * tm + c16;
-                        Tprev[tm] = m < E2 ? Tout[((size_t)ca * E2 + m) * 4 + ksel(g)] : (acc)0;
-                    }
-                }
 
                 const int p = c16;
                 const bool valid = cc0 + p < cnp;
@@ -523,12 +520,20 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
                     }
                 }
                 if (last) {
+                    // T accumulates over the neighbour-type passes (lane group g owns component
+                    // ksel(g) of row 16 tm + c16); the earlier passes' sum is read only here, so
+                    // that it holds no registers during the network
+                    acc Tprev[7];
+                    for (int tm = 0; tm < 7; ++tm) {
+                        const int m = 16 * tm + c16;
+                        Tprev[tm] = (tj > 0 && m < E2) ? Tout[((size_t)ca * E2 + m) * 4 + ksel(g)] : (acc)0;
+                    }
                     // sum the four lane groups (they hold different neighbours) and store T
                     for (int tm = 0; tm < 7; ++tm) {
                         const acc v = sum_groups4(Tacc[tm]);
                         const int m = 16 * tm + c16;
                         if (m < E2)
-                            Tout[((size_t)ca * E2 + m) * 4 + ksel(g)] = v * (acc)A.inv_nc + (tj > 0 ? Tprev[tm] : (acc)0);
+                            Tout[((size_t)ca * E2 + m) * 4 + ksel(g)] = v * (acc)A.inv_nc + Tprev[tm];
                     }
                 }
             }
@@ -543,14 +548,15 @@ __global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_fwd(EmbArgs A)
 //   F_i += g_ij, F_j -= g_ij (FP64 atomics), Xi_ab -= g_ij,a r_ij,b (FP64, per-block partials).
 // ---------------------------------------------------------------------------------------------
 template <class P, bool TAB>
-__global__ void __launch_bounds__(EmbCfg<P>::NW * 64) k_embed_bwd(EmbArgs A)
+__global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(EmbArgs A)
 {
     typedef typename P::acc acc;
     typedef typename P::wt wt;
     typedef typename P::accv accv;
     typedef typename P::frag frag;
-    typedef EmbCfg<P> Cfg;
-    constexpr int NW = Cfg::NW, APW = Cfg::APW, APB = Cfg::APB;
+    typedef EmbCfg<P, false, TAB> Cfg;
+    constexpr int NW = Cfg::NW;
+    const int APW = A.apw, APB = NW * APW;
     constexpr bool W3LDS = Cfg::W3LDS;
     constexpr int DTL = (E2 * 4 + 63) / 64;     // dT values per lane
     __shared__ acc s_vec[EVEC];
@@ -1111,23 +1117,59 @@ __global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
 // ---------------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------------
-int embed_atoms_per_block(int precision)
+// Atoms per wave of one launch (see EmbCfg).
+static int embed_apw(int nw, int apw_max, int64_t natoms, int ncu)
 {
-    return precision == 0 ? EmbCfg<PF64>::APB : EmbCfg<PMIX>::APB;
+    const int64_t a = natoms / ((int64_t)nw * (ncu > 0 ? ncu : 1));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(apw_max, a));
+}
+
+template <class P>
+static int embed_bwd_blocks_p(int64_t natoms, int ncu)
+{
+    typedef EmbCfg<P, false, false> Cfg;
+    static_assert(EmbCfg<P, false, true>::NW == Cfg::NW && EmbCfg<P, false, true>::APW_MAX == Cfg::APW_MAX,
+                  "table and network backward shapes agree");
+    const int64_t apb = (int64_t)Cfg::NW * embed_apw(Cfg::NW, Cfg::APW_MAX, natoms, ncu);
+    return (int)((natoms + apb - 1) / apb);
+}
+
+int embed_bwd_blocks(int precision, int64_t natoms, int ncu)
+{
+    if (precision == 0) return embed_bwd_blocks_p<PF64>(natoms, ncu);
+    if (precision == 1) return embed_bwd_blocks_p<PMIX>(natoms, ncu);
+    return embed_bwd_blocks_p<PBF16>(natoms, ncu);
+}
+
+int64_t embed_bwd_max_blocks(int precision, int64_t natoms)
+{
+    const int nw = precision == 0 ? EmbCfg<PF64>::NW : EmbCfg<PMIX>::NW;
+    static_assert(EmbCfg<PBF16>::NW == EmbCfg<PMIX>::NW, "backward shapes");
+    return (natoms + nw - 1) / nw;
 }
 int fit_atoms_per_block(int) { return FIT_AF; }
+
+template <class P, bool FWD, bool TAB>
+static void launch_embed_shape(const EmbArgs& a0, hipStream_t s)
+{
+    typedef EmbCfg<P, FWD, TAB> Cfg;
+    EmbArgs a = a0;
+    a.apw = embed_apw(Cfg::NW, Cfg::APW_MAX, a.natoms, a.ncu);
+    const int apb = Cfg::NW * a.apw;
+    const dim3 grid((a.natoms + apb - 1) / apb), block(Cfg::NW * 64);
+    if constexpr (FWD) hipLaunchKernelGGL((k_embed_fwd<P, TAB>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_embed_bwd<P, TAB>), grid, block, 0, s, a);
+}
 
 template <class P>
 static void launch_embed(bool fwd, bool table, const EmbArgs& a, hipStream_t s)
 {
-    typedef EmbCfg<P> Cfg;
-    dim3 grid((a.natoms + Cfg::APB - 1) / Cfg::APB), block(Cfg::NW * 64);
     if (fwd) {
-        if (table) hipLaunchKernelGGL((k_embed_fwd<P, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_embed_fwd<P, false>), grid, block, 0, s, a);
+        if (table) launch_embed_shape<P, true, true>(a, s);
+        else launch_embed_shape<P, true, false>(a, s);
     } else {
-        if (table) hipLaunchKernelGGL((k_embed_bwd<P, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_embed_bwd<P, false>), grid, block, 0, s, a);
+        if (table) launch_embed_shape<P, false, true>(a, s);
+        else launch_embed_shape<P, false, false>(a, s);
     }
 }
 
