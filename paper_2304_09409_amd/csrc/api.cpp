@@ -229,8 +229,9 @@ struct dpk_ctx {
     size_t ws_bytes = 0;
     int64_t cap_atoms = 0;
     int64_t cap_cells = 0;
+    bool cells_clear = false;            // cell_count is all zero (the multi-block preparation keeps it so)
     // views of the workspace (valid for the capacity)
-    int *perm, *inv_perm, *itype, *tcount, *toff, *cell_of, *cell_atoms, *cell_count, *cell_start, *cursor;
+    int *perm, *inv_perm, *itype, *tcount, *toff, *cell_of, *cell_tmp, *cell_count, *cell_start, *cursor;
     int *nl_j, *nnei, *h_atype, *bcount, *boff;
     double *pos, *nl_r, *Ei, *F, *vir_part, *bbox, *h_coord, *h_out;
     double4* cand;
@@ -278,12 +279,12 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
     p = take(sizeof(int) * n); if (base) c->itype = (int*)p;
     p = take(sizeof(int) * MAXT); if (base) c->tcount = (int*)p;
     p = take(sizeof(int) * (MAXT + 1)); if (base) c->toff = (int*)p;
-    p = take(sizeof(int) * MAXT * ((n + 1023) / 1024)); if (base) c->bcount = (int*)p;
-    p = take(sizeof(int) * MAXT * ((n + 1023) / 1024)); if (base) c->boff = (int*)p;
+    p = take(sizeof(int) * MAXT * ((n + PREP_BLOCK - 1) / PREP_BLOCK)); if (base) c->bcount = (int*)p;
+    p = take(sizeof(int) * MAXT * ((n + PREP_BLOCK - 1) / PREP_BLOCK)); if (base) c->boff = (int*)p;
     p = take(sizeof(DevStats)); if (base) c->stats = (DevStats*)p;
     p = take(sizeof(double) * 3 * n); if (base) c->pos = (double*)p;
     p = take(sizeof(int) * n); if (base) c->cell_of = (int*)p;
-    p = take(sizeof(int) * n); if (base) c->cell_atoms = (int*)p;
+    p = take(sizeof(int) * n); if (base) c->cell_tmp = (int*)p;
     p = take(sizeof(double4) * n); if (base) c->cand = (double4*)p;
     p = take(sizeof(int) * ncell); if (base) c->cell_count = (int*)p;
     p = take(sizeof(int) * (ncell + 1)); if (base) c->cell_start = (int*)p;
@@ -355,6 +356,7 @@ int ensure_ws(dpk_ctx* c, int64_t n, int64_t ncell)
     c->ws_bytes = bytes;
     c->cap_atoms = nn;
     c->cap_cells = ncl;
+    c->cells_clear = false;
     layout_ws(c, nn, ncl, (char*)p);
     return DPK_OK;
 }
@@ -868,10 +870,12 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     prof_mark(ev, DPK_STAGE_PREP, s);
     if (!launch_prep_small(n, d_coord, d_atype, nt, gp, c->tcount, c->toff, c->perm, c->inv_perm, c->itype, c->stats,
                            c->pos, c->cell_of, c->cell_start, c->cand, c->F, s)) {
-        launch_types(n, d_atype, nt, c->tcount, c->toff, c->bcount, c->boff, c->perm, c->inv_perm, c->itype,
-                     c->cell_count, (int)ncell, c->stats, s);
-        launch_cells(n, d_coord, c->perm, c->itype, gp, c->pos, c->cell_of, c->cell_count, c->cell_start, c->cursor,
-                     c->cell_atoms, c->cand, c->F, s);
+        if (!c->cells_clear) launch_zero(c->cell_count, sizeof(int) * (size_t)c->cap_cells, s);
+        c->cells_clear = false;
+        launch_prep_large(n, d_coord, d_atype, nt, gp, c->tcount, c->toff, c->bcount, c->boff, c->perm, c->inv_perm,
+                          c->itype, c->stats, c->pos, c->cell_of, c->cell_count, c->cell_start, c->cursor, c->cell_tmp,
+                          c->cand, c->F, s);
+        c->cells_clear = true;   // its scan clears the counts it read
     }
     prof_mark(ev, DPK_STAGE_NLIST, s);
     launch_nlist(n, c->pos, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cand, gp, c->nl_j, c->nl_r, c->nnei,

@@ -17,6 +17,7 @@ constexpr int MAXT = 8;
 constexpr int NL_CAP = 1024;      // candidate buffer of the neighbour-list kernel (per atom)
 constexpr int NL_STENCIL = 343;   // bins visited per atom at most: (2K+1)^3 with K <= 3
 constexpr int FIT_AF = 64;        // atoms per block of the fitting kernels (16 per wave)
+constexpr int PREP_BLOCK = 256;   // atoms per block of the multi-block preparation
 
 // Offsets inside one packed embedding vector block.
 constexpr int EV_W1 = 0, EV_B1 = K2P, EV_WH1 = 2 * K2P, EV_B2 = 3 * K2P, EV_WH2 = 3 * K2P + N2P,

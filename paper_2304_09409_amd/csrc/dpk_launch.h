@@ -6,16 +6,17 @@
 namespace dpk {
 
 void launch_zero(void* p, size_t bytes, hipStream_t s);
-void launch_types(int n, const int* atype, int ntypes, int* tcount, int* toff, int* bcount, int* boff, int* perm,
-                  int* inv_perm, int* itype, int* cell_count, int ncell, DevStats* st, hipStream_t s);
+// Preparation of a frame of any size in three launches; cell_count is zero on entry and on exit
+// (the caller clears it once after allocating it); cell_tmp holds n ints of scratch.
+void launch_prep_large(int n, const double* coord, const int* atype, int ntypes, const GeomParams& gp, int* tcount,
+                       int* toff, int* bcount, int* boff, int* perm, int* inv_perm, int* itype, DevStats* st,
+                       double* pos, int* cell_of, int* cell_count, int* cell_start, int* cursor, int* cell_tmp,
+                       double4* cand, double* f_int, hipStream_t s);
 void launch_bbox(int n, const double* coord, double* out, hipStream_t s);
 // All preparation phases in one workgroup; false (nothing launched) when the frame is too large.
 bool launch_prep_small(int n, const double* coord, const int* atype, int ntypes, const GeomParams& gp, int* tcount,
                        int* toff, int* perm, int* inv_perm, int* itype, DevStats* st, double* pos, int* cell_of,
                        int* cell_start, double4* cand, double* f_int, hipStream_t s);
-void launch_cells(int n, const double* coord, const int* perm, const int* itype, const GeomParams& gp, double* pos,
-                  int* cell_of, int* cell_count, int* cell_start, int* cursor, int* cell_atoms, double4* cand,
-                  double* f_int, hipStream_t s);
 // Single frame: gp by value, gps == nullptr. Batch: gps/fd/frame_of on the device and the largest
 // stencil and candidate buffer of the batch's frames.
 void launch_nlist(int n, const double* pos, const int* perm, const int* inv_perm, const int* cell_of,

@@ -27,83 +27,11 @@ void launch_zero(void* p, size_t bytes, hipStream_t s)
 }
 
 // ---- atom types: validation, counts, stable partition by type (atoms are kept sorted by
-// species so that each fitting GEMM and each embedding net runs over contiguous atoms) ----
-// Three passes over blocks of 1024 atoms: per-block type counts (k_type_count), a scan of the
-// counts over blocks (k_type_scan), and a scatter in which every block ranks its atoms of each
-// type with ballots (k_type_scatter). The order within a type is the caller order (stable).
-constexpr int TP_BLOCK = 1024;
-
-// Zero the per-frame counters and the bin counts.
-__global__ void k_frame_init(int* tcount, DevStats* st, int* cell_count, int ncell)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < MAXT) tcount[i] = 0;
-    if (i < (int)(sizeof(DevStats) / 4)) reinterpret_cast<int*>(st)[i] = 0;
-    for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_count[c] = 0;
-}
+// species so that each fitting GEMM and each embedding net runs over contiguous atoms; the order
+// within a type is the caller order) ----
+constexpr int TP_BLOCK = PREP_BLOCK;   // atoms per block of the multi-block preparation
 
 __device__ __forceinline__ int clamp_type(int t, int ntypes) { return t < 0 ? 0 : (t >= ntypes ? ntypes - 1 : t); }
-
-__global__ void __launch_bounds__(TP_BLOCK) k_type_count(int n, const int* atype, int ntypes, int* bcount, DevStats* st)
-{
-    __shared__ int h[MAXT];
-    if (threadIdx.x < MAXT) h[threadIdx.x] = 0;
-    __syncthreads();
-    const int i = blockIdx.x * TP_BLOCK + threadIdx.x;
-    if (i < n) {
-        // Out-of-range types raise the error flag and are counted as the nearest valid type,
-        // the same clamp the scatter applies, so the permutation stays complete.
-        const int t0 = atype[i];
-        if (t0 < 0 || t0 >= ntypes) atomicExch(&st->err_type, 1);
-        atomicAdd(&h[clamp_type(t0, ntypes)], 1);
-    }
-    __syncthreads();
-    if (threadIdx.x < MAXT) bcount[blockIdx.x * MAXT + threadIdx.x] = h[threadIdx.x];
-}
-
-// bcount[b][t] -> exclusive offsets boff[b][t] = toff[t] + sum over earlier blocks; toff[ntypes+1].
-__global__ void __launch_bounds__(64) k_type_scan(int nblocks, int ntypes, const int* bcount, int* boff, int* toff,
-                                                  int* tcount)
-{
-    if (threadIdx.x != 0) return;
-    int acc = 0;
-    for (int t = 0; t < ntypes; ++t) {
-        toff[t] = acc;
-        int c = 0;
-        for (int b = 0; b < nblocks; ++b) {
-            boff[b * MAXT + t] = acc + c;
-            c += bcount[b * MAXT + t];
-        }
-        tcount[t] = c;
-        acc += c;
-    }
-    toff[ntypes] = acc;
-}
-
-__global__ void __launch_bounds__(TP_BLOCK) k_type_scatter(int n, const int* atype, int ntypes, const int* boff,
-                                                           int* perm, int* inv_perm, int* itype)
-{
-    __shared__ int wsum[TP_BLOCK / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int i = blockIdx.x * TP_BLOCK + tid;
-    const int t = i < n ? clamp_type(atype[i], ntypes) : -1;
-    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int k = 0; k < ntypes; ++k) {
-        const bool f = (t == k);
-        const unsigned long long m = __ballot(f);
-        if (lane == 0) wsum[wid] = __popcll(m);
-        __syncthreads();
-        int before = 0;
-        for (int w = 0; w < wid; ++w) before += wsum[w];
-        if (f) {
-            const int pos = boff[blockIdx.x * MAXT + k] + before + __popcll(m & lt);
-            perm[pos] = i;
-            inv_perm[i] = pos;
-            itype[pos] = k;
-        }
-        __syncthreads();
-    }
-}
 
 // Bounding box of an open cluster: out = {min xyz, max xyz}.
 __global__ void __launch_bounds__(1024) k_bbox(int n, const double* coord, double* out)
@@ -127,79 +55,6 @@ __global__ void __launch_bounds__(1024) k_bbox(int n, const double* coord, doubl
         __syncthreads();
     }
     if (threadIdx.x < 6) out[threadIdx.x] = red[threadIdx.x][0];
-}
-
-// Wrap into the cell (periodic) and assign bins. Fractional s = r h^-1 (row vector), wrapped to
-// [0,1), and the wrapped position s h, each component summed in the fixed order 0, 1, 2.
-__global__ void k_wrap_bin(int n, const double* coord, const int* perm, GeomParams gp, double* pos,
-                           int* cell_of, int* cell_count, double* f_int)
-{
-    int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= n) return;
-    f_int[3 * (size_t)a] = 0.0;   // the force accumulator of this frame (filled by atomics later)
-    f_int[3 * (size_t)a + 1] = 0.0;
-    f_int[3 * (size_t)a + 2] = 0.0;
-    int i = perm[a];
-    double x[3] = {coord[3 * (size_t)i], coord[3 * (size_t)i + 1], coord[3 * (size_t)i + 2]};
-    int b[3];
-    double p[3];
-    if (gp.periodic) {
-        double s[3];
-        for (int c = 0; c < 3; ++c) {
-            s[c] = (x[0] * gp.hinv[c] + x[1] * gp.hinv[3 + c]) + x[2] * gp.hinv[6 + c];
-            s[c] -= floor(s[c]);
-            if (s[c] >= 1.0) s[c] = 0.0;
-        }
-        for (int c = 0; c < 3; ++c) p[c] = (s[0] * gp.h[c] + s[1] * gp.h[3 + c]) + s[2] * gp.h[6 + c];
-        for (int c = 0; c < 3; ++c) {
-            int bb = (int)floor(s[c] * gp.nb[c]);
-            b[c] = bb < 0 ? 0 : (bb >= gp.nb[c] ? gp.nb[c] - 1 : bb);
-        }
-    } else {
-        for (int c = 0; c < 3; ++c) {
-            p[c] = x[c];
-            int bb = (int)floor((x[c] - gp.origin[c]) / gp.binw[c]);
-            b[c] = bb < 0 ? 0 : (bb >= gp.nb[c] ? gp.nb[c] - 1 : bb);
-        }
-    }
-    for (int c = 0; c < 3; ++c) pos[3 * (size_t)a + c] = p[c];
-    int cell = (b[2] * gp.nb[1] + b[1]) * gp.nb[0] + b[0];
-    cell_of[a] = cell;
-    atomicAdd(&cell_count[cell], 1);
-}
-
-// Exclusive scan of the bin counts (one block).
-__global__ void __launch_bounds__(1024) k_cell_scan(int ncell, const int* count, int* start, int* cursor)
-{
-    __shared__ int part[1024];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < ncell; base += 1024) {
-        int i = base + threadIdx.x;
-        int v = i < ncell ? count[i] : 0;
-        part[threadIdx.x] = v;
-        __syncthreads();
-        for (int s = 1; s < 1024; s <<= 1) {
-            int add = (int)threadIdx.x >= s ? part[threadIdx.x - s] : 0;
-            __syncthreads();
-            part[threadIdx.x] += add;
-            __syncthreads();
-        }
-        if (i < ncell) { start[i] = carry + part[threadIdx.x] - v; cursor[i] = start[i]; }
-        __syncthreads();
-        if (threadIdx.x == 1023) carry += part[1023];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) start[ncell] = carry;
-}
-
-__global__ void k_cell_fill(int n, const int* cell_of, int* cursor, int* cell_atoms)
-{
-    int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= n) return;
-    int slot = atomicAdd(&cursor[cell_of[a]], 1);
-    cell_atoms[slot] = a;
 }
 
 // ---- fused preparation for frames of up to PS_MAX_ATOMS atoms and PS_MAX_CELLS bins --------
@@ -389,6 +244,143 @@ __device__ __forceinline__ void prep_frame(int f, int n, int atom_off, const dou
     }
 }
 
+// ---- preparation of larger frames in three launches ---------------------------------------
+// Blocks of TP_BLOCK atoms in caller order.
+//   k_prep_count: per-block type counts (types clamped; the scatter raises the error flag) and
+//                 the bin of every atom, counted into cell_count with atomics. cell_count is zero
+//                 on entry: k_prep_scan clears what it read, and the host clears the array after
+//                 allocating it.
+//   k_prep_scan (one block): clears the statistics block, scans the block type counts over blocks
+//                 and the bin counts (bin starts and fill cursors), and clears the bin counts.
+//   k_prep_scatter: the stable partition by type (ballot ranks within the block plus the block's
+//                 base), the wrapped position and bin in internal order (wrap_bin_one again, the
+//                 same bits as in k_prep_count), zeroed force accumulators, and the candidate
+//                 record of every atom at the next free slot of its bin (the order within a bin
+//                 is not fixed: the neighbour list sorts its hits by a key unique per candidate).
+__global__ void __launch_bounds__(TP_BLOCK) k_prep_count(int n, const double* coord, const int* atype, int ntypes,
+                                                         GeomParams gp, int* bcount, int* cell_tmp, int* cell_count)
+{
+    __shared__ int h[MAXT];
+    if (threadIdx.x < MAXT) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int i = blockIdx.x * TP_BLOCK + threadIdx.x;
+    if (i < n) {
+        atomicAdd(&h[clamp_type(atype[i], ntypes)], 1);
+        const double x[3] = {coord[3 * (size_t)i], coord[3 * (size_t)i + 1], coord[3 * (size_t)i + 2]};
+        double p[3];
+        int b[3];
+        wrap_bin_one(gp, x, p, b);
+        const int cell = (b[2] * gp.nb[1] + b[1]) * gp.nb[0] + b[0];
+        cell_tmp[i] = cell;
+        atomicAdd(&cell_count[cell], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < MAXT) bcount[blockIdx.x * MAXT + threadIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of v[0..m) by one block of 1024 threads (passes of 1024 with a carry): out[i] =
+// base + sum of v[0..i); returns the total to every thread. part holds 1024 ints of LDS.
+__device__ int block_scan_1024(int m, const int* v, int vstride, int* out, int ostride, int base, int* part,
+                               int* carry)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) *carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < m; b0 += 1024) {
+        const int i = b0 + tid;
+        const int x = i < m ? v[(size_t)i * vstride] : 0;
+        part[tid] = x;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int add = tid >= o ? part[tid - o] : 0;
+            __syncthreads();
+            part[tid] += add;
+            __syncthreads();
+        }
+        if (i < m) out[(size_t)i * ostride] = base + *carry + part[tid] - x;
+        __syncthreads();
+        if (tid == 1023) *carry += part[1023];
+        __syncthreads();
+    }
+    const int total = *carry;
+    __syncthreads();   // every thread has read the total before the next scan resets it
+    return total;
+}
+
+__global__ void __launch_bounds__(1024) k_prep_scan(int nblocks, int ntypes, const int* bcount, int* boff, int* toff,
+                                                    int* tcount, int ncell, int* cell_count, int* cell_start,
+                                                    int* cursor, DevStats* st)
+{
+    __shared__ int part[1024];
+    __shared__ int carry;
+    const int tid = threadIdx.x;
+    if (tid < (int)(sizeof(DevStats) / 4)) reinterpret_cast<int*>(st)[tid] = 0;
+    // types: block offsets within each type (type t's atoms follow those of types < t)
+    int acc = 0;
+    for (int t = 0; t < ntypes; ++t) {
+        const int c = block_scan_1024(nblocks, bcount + t, MAXT, boff + t, MAXT, acc, part, &carry);
+        if (tid == 0) {
+            toff[t] = acc;
+            tcount[t] = c;
+        }
+        acc += c;
+    }
+    if (tid == 0) toff[ntypes] = acc;
+    // bins: starts and fill cursors; the counts are cleared for the next frame
+    const int total = block_scan_1024(ncell, cell_count, 1, cell_start, 1, 0, part, &carry);
+    for (int i = tid; i < ncell; i += 1024) {
+        cursor[i] = cell_start[i];
+        cell_count[i] = 0;
+    }
+    if (tid == 0) cell_start[ncell] = total;
+}
+
+__global__ void __launch_bounds__(TP_BLOCK) k_prep_scatter(int n, const double* coord, const int* atype, int ntypes,
+                                                           GeomParams gp, const int* boff, const int* cell_tmp,
+                                                           int* perm, int* inv_perm, int* itype, double* pos,
+                                                           int* cell_of, int* cursor, double4* cand, double* f_int,
+                                                           DevStats* st)
+{
+    __shared__ int wsum[TP_BLOCK / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int i = blockIdx.x * TP_BLOCK + tid;
+    int t = -1;
+    if (i < n) {
+        const int t0 = atype[i];
+        if (t0 < 0 || t0 >= ntypes) atomicExch(&st->err_type, 1);
+        t = clamp_type(t0, ntypes);
+    }
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int q = -1;
+    for (int k = 0; k < ntypes; ++k) {
+        const bool f = (t == k);
+        const unsigned long long m = __ballot(f);
+        if (lane == 0) wsum[wid] = __popcll(m);
+        __syncthreads();
+        int before = 0;
+        for (int w = 0; w < wid; ++w) before += wsum[w];
+        if (f) q = boff[blockIdx.x * MAXT + k] + before + __popcll(m & lt);
+        __syncthreads();
+    }
+    if (q < 0) return;
+    perm[q] = i;
+    inv_perm[i] = q;
+    itype[q] = t;
+    const double x[3] = {coord[3 * (size_t)i], coord[3 * (size_t)i + 1], coord[3 * (size_t)i + 2]};
+    double p[3];
+    int b[3];
+    wrap_bin_one(gp, x, p, b);
+    const int cell = cell_tmp[i];
+    for (int c = 0; c < 3; ++c) {
+        pos[3 * (size_t)q + c] = p[c];
+        f_int[3 * (size_t)q + c] = 0.0;
+    }
+    cell_of[q] = cell;
+    const int slot = atomicAdd(&cursor[cell], 1);
+    const long long tag = (long long)q | ((long long)i << 30) | ((long long)t << 60);
+    cand[slot] = make_double4(p[0], p[1], p[2], __longlong_as_double(tag));
+}
+
 __global__ void __launch_bounds__(PS_THREADS) k_prep_small(int n, const double* coord, const int* atype, int ntypes,
                                                             GeomParams gp, int ncell, int* tcount, int* toff, int* perm,
                                                             int* inv_perm, int* itype, DevStats* st, double* pos,
@@ -464,7 +456,7 @@ __global__ void __launch_bounds__(PS_THREADS) k_prep_batch(const double* coord, 
 }
 
 // ---- neighbour list: one wave per centre atom --------------------------------------------
-// Candidate records are stored in bin order (k_cell_pack): position and a tag holding the
+// Candidate records are stored in bin order (by the preparation): position and a tag holding the
 // internal index, the caller index and the type (30 + 30 + 4 bits), so one 32-B load gives
 // everything the candidate test and the output need.
 // The wave first loads the ranges of all stencil bins at once (one lane per bin) and scans their
@@ -476,17 +468,6 @@ __global__ void __launch_bounds__(PS_THREADS) k_prep_batch(const double* coord, 
 // (r^2 is a non-negative double, whose bit pattern orders like its value). A bitonic sort in LDS
 // orders them; the first sel[t] of each type fill that type's block of slots, the rest are
 // counted as dropped; unfilled slots get index -1.
-
-__global__ void k_cell_pack(int n, const int* cell_atoms, const double* pos, const int* perm, const int* itype,
-                            double4* cand)
-{
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const int a = cell_atoms[q];
-    const long long tag = (long long)a | ((long long)perm[a] << 30) | ((long long)itype[a] << 60);
-    cand[q] = make_double4(pos[3 * (size_t)a], pos[3 * (size_t)a + 1], pos[3 * (size_t)a + 2],
-                           __longlong_as_double(tag));
-}
 
 __device__ __forceinline__ bool key_less(unsigned long long ah, unsigned long long al,
                                          unsigned long long bh, unsigned long long bl)
@@ -825,17 +806,19 @@ __global__ void k_debug_nlist(int n, int nc, const int* perm, const int* nl_j, i
 
 // ---- launchers --------------------------------------------------------------------------
 
-void launch_types(int n, const int* atype, int ntypes, int* tcount, int* toff, int* bcount, int* boff, int* perm,
-                  int* inv_perm, int* itype, int* cell_count, int ncell, DevStats* st, hipStream_t s)
+void launch_prep_large(int n, const double* coord, const int* atype, int ntypes, const GeomParams& gp, int* tcount,
+                       int* toff, int* bcount, int* boff, int* perm, int* inv_perm, int* itype, DevStats* st,
+                       double* pos, int* cell_of, int* cell_count, int* cell_start, int* cursor, int* cell_tmp,
+                       double4* cand, double* f_int, hipStream_t s)
 {
     const int nb = (n + TP_BLOCK - 1) / TP_BLOCK;
-    int ib = (ncell + 255) / 256;
-    if (ib < 1) ib = 1;
-    if (ib > 1024) ib = 1024;
-    hipLaunchKernelGGL(k_frame_init, dim3(ib), dim3(256), 0, s, tcount, st, cell_count, ncell);
-    hipLaunchKernelGGL(k_type_count, dim3(nb), dim3(TP_BLOCK), 0, s, n, atype, ntypes, bcount, st);
-    hipLaunchKernelGGL(k_type_scan, dim3(1), dim3(64), 0, s, nb, ntypes, bcount, boff, toff, tcount);
-    hipLaunchKernelGGL(k_type_scatter, dim3(nb), dim3(TP_BLOCK), 0, s, n, atype, ntypes, boff, perm, inv_perm, itype);
+    const int ncell = gp.nb[0] * gp.nb[1] * gp.nb[2];
+    hipLaunchKernelGGL(k_prep_count, dim3(nb), dim3(TP_BLOCK), 0, s, n, coord, atype, ntypes, gp, bcount, cell_tmp,
+                       cell_count);
+    hipLaunchKernelGGL(k_prep_scan, dim3(1), dim3(1024), 0, s, nb, ntypes, bcount, boff, toff, tcount, ncell,
+                       cell_count, cell_start, cursor, st);
+    hipLaunchKernelGGL(k_prep_scatter, dim3(nb), dim3(TP_BLOCK), 0, s, n, coord, atype, ntypes, gp, boff, cell_tmp,
+                       perm, inv_perm, itype, pos, cell_of, cursor, cand, f_int, st);
 }
 
 bool launch_prep_small(int n, const double* coord, const int* atype, int ntypes, const GeomParams& gp, int* tcount,
@@ -872,18 +855,6 @@ int prep_small_max_cells() { return PS_MAX_CELLS; }
 void launch_bbox(int n, const double* coord, double* out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bbox, dim3(1), dim3(1024), 0, s, n, coord, out);
-}
-
-void launch_cells(int n, const double* coord, const int* perm, const int* itype, const GeomParams& gp, double* pos,
-                  int* cell_of, int* cell_count, int* cell_start, int* cursor, int* cell_atoms, double4* cand,
-                  double* f_int, hipStream_t s)
-{
-    int ncell = gp.nb[0] * gp.nb[1] * gp.nb[2];
-    hipLaunchKernelGGL(k_wrap_bin, dim3((n + 255) / 256), dim3(256), 0, s, n, coord, perm, gp, pos, cell_of,
-                       cell_count, f_int);
-    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, ncell, cell_count, cell_start, cursor);
-    hipLaunchKernelGGL(k_cell_fill, dim3((n + 255) / 256), dim3(256), 0, s, n, cell_of, cursor, cell_atoms);
-    hipLaunchKernelGGL(k_cell_pack, dim3((n + 255) / 256), dim3(256), 0, s, n, cell_atoms, pos, perm, itype, cand);
 }
 
 void launch_nlist(int n, const double* pos, const int* perm, const int* inv_perm, const int* cell_of,
