@@ -248,7 +248,6 @@ struct dpk_ctx {
     bool force_big_cap = false;
     // last frame
     int64_t last_n = 0;
-    int64_t last_nvp = 0;
     // stage profiler: one set of DPK_NSTAGES + 1 events per profiled frame
     bool profiling = false;
     std::vector<std::vector<hipEvent_t>> prof_events;
@@ -302,7 +301,7 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
     if (base) c->act = p;
     p = take(sizeof(double) * n); if (base) c->Ei = (double*)p;
     p = take(sizeof(double) * 3 * n); if (base) c->F = (double*)p;
-    p = take(sizeof(double) * 9 * nvb); if (base) { c->vir_part = (double*)p; c->vir_blocks = nvb; }
+    p = take(sizeof(double) * 10 * nvb); if (base) { c->vir_part = (double*)p; c->vir_blocks = nvb; }
     p = take(sizeof(double) * 8); if (base) c->bbox = (double*)p;
     p = take(sizeof(double) * 3 * n); if (base) c->h_coord = (double*)p;
     p = take(sizeof(int) * n); if (base) c->h_atype = (int*)p;
@@ -546,7 +545,11 @@ int upload_model(dpk_ctx* c)
 
 // Embedding, fitting and adjoint over n atoms (internal order), after the neighbour list.
 // vir_atom == nullptr: virial as per-block partials; else per centre atom (batched frames).
-void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* vir_atom, std::vector<hipEvent_t>* ev, hipStream_t s)
+// Embedding, fitting and the backward pass. F: force accumulator in caller order (zeroed by the
+// preparation). Single frame (single = true): per-block partials [E, virial] and E_i in caller
+// order (atom_energy, if not nullptr); batch: per-atom virials (vir_atom).
+void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* F, double* vir_atom, bool single,
+                 double* atom_energy, std::vector<hipEvent_t>* ev, hipStream_t s)
 {
     const dpk_model* m = c->model;
     const int nt = m->desc.ntypes;
@@ -573,10 +576,15 @@ void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* vir_atom, std:
     ea.tab_nint = m->tab_nint;
     ea.T = c->T;
     ea.dT = c->dT;
-    ea.F = c->F;
+    ea.perm = c->perm;
+    ea.F = F;
     ea.vir_part = c->vir_part;
     ea.vir_atom = vir_atom;
     ea.stats = c->stats;
+    if (single) {
+        ea.Ei = c->Ei;
+        ea.atom_energy = atom_energy;
+    }
     const bool tab = m->tabulated;
     prof_mark(ev, DPK_STAGE_EMBED_FWD, s);
     launch_embed_fwd(c->precision, tab, ea, s);
@@ -695,12 +703,11 @@ int compute_batch(dpk_ctx* c, int nf, const BatchFrame* fr, const double* d_coor
                       c->frame_of, c->stats, c->pos, c->cell_of, c->cell_start, c->cand, c->F, c->vir_atom, s);
     launch_nlist((int)n, c->pos, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cand, gps[0], c->nl_j, c->nl_r,
                  c->nnei, c->stats, s, c->gps, c->fd, c->frame_of, ms, mc);
-    run_network(c, (int)n, gps[0], c->vir_atom, nullptr, s);
+    run_network(c, (int)n, gps[0], c->F, c->vir_atom, false, nullptr, nullptr, s);
     launch_finalize_batch(nf, c->fd, c->inv_perm, c->Ei, c->vir_atom, c->F, d_out, s);
     HIPCHK(hipGetLastError());
     c->last_stream = s;
     c->last_n = n;
-    c->last_nvp = 0;
     return DPK_OK;
 }
 
@@ -866,30 +873,29 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     if ((rc = ensure_ws(c, n, ncell))) return rc;
     const int nt = m->desc.ntypes;
 
+    // the forces accumulate straight into d_force (caller order), which the preparation zeroes
     std::vector<hipEvent_t>* ev = prof_frame(c);
     prof_mark(ev, DPK_STAGE_PREP, s);
     if (!launch_prep_small(n, d_coord, d_atype, nt, gp, c->tcount, c->toff, c->perm, c->inv_perm, c->itype, c->stats,
-                           c->pos, c->cell_of, c->cell_start, c->cand, c->F, s)) {
+                           c->pos, c->cell_of, c->cell_start, c->cand, d_force, s)) {
         if (!c->cells_clear) launch_zero(c->cell_count, sizeof(int) * (size_t)c->cap_cells, s);
         c->cells_clear = false;
         launch_prep_large(n, d_coord, d_atype, nt, gp, c->tcount, c->toff, c->bcount, c->boff, c->perm, c->inv_perm,
                           c->itype, c->stats, c->pos, c->cell_of, c->cell_count, c->cell_start, c->cursor, c->cell_tmp,
-                          c->cand, c->F, s);
+                          c->cand, d_force, s);
         c->cells_clear = true;   // its scan clears the counts it read
     }
     prof_mark(ev, DPK_STAGE_NLIST, s);
     launch_nlist(n, c->pos, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cand, gp, c->nl_j, c->nl_r, c->nnei,
                  c->stats, s);
 
-    run_network(c, n, gp, nullptr, ev, s);
+    run_network(c, n, gp, d_force, nullptr, true, d_atom_energy, ev, s);
     prof_mark(ev, DPK_STAGE_FINAL, s);
-    const int nvp = embed_bwd_blocks(c->precision, n, c->ncu);
-    launch_finalize(n, c->Ei, nvp, c->vir_part, d_energy, d_virial, c->perm, c->F, d_force, d_atom_energy, s);
+    launch_finalize(embed_bwd_blocks(c->precision, n, c->ncu), c->vir_part, d_energy, d_virial, s);
     prof_mark(ev, DPK_NSTAGES, s);
     HIPCHK(hipGetLastError());
     c->last_stream = s;
     c->last_n = n;
-    c->last_nvp = nvp;
     return DPK_OK;
 }
 
@@ -1090,6 +1096,7 @@ struct Slot {
     double* pin_out = nullptr;
     int64_t pin_cap = 0;
     DevStats* pin_stats = nullptr;     // host copy of the batch's statistics block
+    int64_t expect = 0;                // workspace bytes once the admitted batch is launched
 };
 
 void release_ws(dpk_ctx* c)
@@ -1352,13 +1359,17 @@ void scheduler(dpk_server* s)
             // admission
             while (!s->queue.empty()) {
                 for (int k = 0; k < ns; ++k) {
+                    // a slot admitted earlier in this pass is launched (and its workspace grown)
+                    // only after the pass: count what it will hold
                     busy[k] = !s->slots[k].reqs.empty();
                     bytes[k] = (int64_t)s->slots[k].ctx->ws_bytes;
+                    if (busy[k]) bytes[k] = std::max(bytes[k], s->slots[k].expect);
                     sims[k] = s->slots[k].sim;
                 }
                 Request* r = s->queue.front();
                 int take = 1;
                 int64_t need = r->need;
+                int64_t batch_atoms = r->f.natoms, batch_cells = r->ncell;   // the workspace the launch sizes
                 int32_t slot = -1, rel = 0;
                 const int plan = dpk_admit_plan(ns, busy.data(), bytes.data(), sims.data(), r->need,
                                                 r->f.simulation, s->budget, s->model_bytes, &slot, &rel);
@@ -1381,6 +1392,8 @@ void scheduler(dpk_server* s)
                         cells += q->ncell + 1;
                         take = k;
                         need = nk;
+                        batch_atoms = atoms;
+                        batch_cells = cells;
                         slot = sk;
                         rel = rk;
                     }
@@ -1402,6 +1415,18 @@ void scheduler(dpk_server* s)
                     for (int k = 0; k < ns; ++k)
                         if (!busy[k] && k != slot) release_ws(s->slots[k].ctx);
                     if ((int64_t)sl.ctx->ws_bytes > need) release_ws(sl.ctx);
+                }
+                sl.expect = need;
+                if (sl.ctx->ws) {
+                    // the workspace grows to the larger capacity in atoms and in bins, which can
+                    // exceed both its current size and this launch's need: under a budget it starts
+                    // afresh then, so that it holds what the admission counted
+                    const bool fits = batch_atoms <= sl.ctx->cap_atoms && batch_cells <= sl.ctx->cap_cells;
+                    const int64_t grown = fits ? (int64_t)sl.ctx->ws_bytes
+                                               : (int64_t)layout_ws(&s->plan, std::max(batch_atoms, sl.ctx->cap_atoms),
+                                                                    std::max(batch_cells, sl.ctx->cap_cells), nullptr);
+                    if (s->budget && grown > std::max((int64_t)sl.ctx->ws_bytes, need)) release_ws(sl.ctx);
+                    else sl.expect = grown;
                 }
                 // reserve the slot; its workspace grows to the batch's during the launch
                 const int64_t sim = r->f.simulation;

@@ -102,7 +102,7 @@ struct EmbArgs {
     int off[MAXT];
     const int* itype;        // [N] type of internal atom
     const int* nnei;         // [N][ntypes] kept neighbours per type block
-    const int* nl_j;         // [N][nc]
+    const int* nl_j;         // [N][nc] caller index of each kept neighbour, -1 past the kept ones
     const double* nl_r;      // [N][nc][3]
     double rs, rc, inv_nc;
     // network (packed per policy) or table
@@ -112,10 +112,15 @@ struct EmbArgs {
     double tab_dx; int tab_nint;
     void* T;                 // [N][100][4] of acc type (forward output)
     const void* dT;          // [N][100][4] (backward input)
-    double* F;               // [N][3] internal order (backward output, atomics)
-    double* vir_part;        // [gridDim][9]
+    const int* perm;         // [N] caller index of each internal atom
+    double* F;               // [N][3] caller order (backward output, atomics; zero on entry)
+    double* vir_part;        // [gridDim][10]: E of the block's atoms (single frame), virial
     double* vir_atom;        // [N][9] virial per centre atom (batched frames), or nullptr
     DevStats* stats;
+    // single frame (nullptr for a batch): E_i of the fitting net, summed per block into vir_part
+    // and copied to atom_energy (caller order) if that is not nullptr
+    const double* Ei;        // [N] internal order
+    double* atom_energy;     // [N] caller order, or nullptr
 };
 
 struct FitArgs {

@@ -32,15 +32,15 @@ void launch_finalize_batch(int nframes, const FrameDesc* fd, const int* inv_perm
                            const double* vir_atom, const double* f_int, double* out, hipStream_t s);
 int prep_small_max_atoms();
 int prep_small_max_cells();
-void launch_finalize(int n, const double* ei, int nvp, const double* vir_part, double* energy, double* virial,
-                     const int* perm, const double* f_int, double* force, double* atom_energy, hipStream_t s);
 void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s);
 
 // precision: 0 = FP64, 1 = split-BF16 (three products), 2 = BF16 (one product)
-// blocks of the embedding backward for a frame (one virial partial each), and their maximum over
-// launch shapes (workspace sizing)
+// blocks of the embedding backward for a frame (one [E, virial] partial each), and their maximum
+// over launch shapes (workspace sizing)
 int embed_bwd_blocks(int precision, int64_t natoms, int ncu);
 int64_t embed_bwd_max_blocks(int precision, int64_t natoms);
+// E and the virial of a single frame from the backward pass's nb partials [E, virial[9]]
+void launch_finalize(int nb, const double* part, double* energy, double* virial, hipStream_t s);
 int fit_atoms_per_block(int precision);
 void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s);
 void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s);

@@ -622,7 +622,8 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
         atomicMax(&st->max_cand, count);
         if (count > CAP) atomicExch(&st->err_overflow, 1);
     }
-    if (count > CAP) count = CAP;
+    const bool overflow = count > CAP;   // wave-uniform; the frame is flagged and its list incomplete
+    if (overflow) count = CAP;
     int S2 = 64;
     while (S2 < count) S2 <<= 1;
     __syncthreads();
@@ -677,12 +678,26 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
             }
         }
     }
+    // per-type counts of the sorted keys: every hit, unless the buffer overflowed; then only the
+    // stored hits count, so that each type block starts where its keys do and every slot the
+    // list claims is written (the overflowed frame is reported and not used)
+    int tsorted[MAXT];
+    for (int t = 0; t < gp.ntypes; ++t) tsorted[t] = tcount[t];
+    if (overflow) {
+        for (int t = 0; t < gp.ntypes; ++t) {
+            int c = 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                c += __popcll(__ballot(lane + 64 * e < count && (int)(kh[e] >> 59) == t));
+            tsorted[t] = c;
+        }
+    }
     int tstart[MAXT], kept[MAXT];
     int acc = 0, drops = 0;
     for (int t = 0; t < gp.ntypes; ++t) {
         tstart[t] = acc;
-        acc += tcount[t];
-        kept[t] = tcount[t] < gp.sel[t] ? tcount[t] : gp.sel[t];
+        acc += tsorted[t];
+        kept[t] = tsorted[t] < gp.sel[t] ? tsorted[t] : gp.sel[t];
         drops += tcount[t] - kept[t];
     }
     const size_t rowj = (size_t)a * gp.nc;
@@ -696,7 +711,7 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
             const int code = (int)(kl[e] & ((1ull << 21) - 1));
             const int n0 = (code >> 14) - 64, n1 = ((code >> 7) & 127) - 64, n2 = (code & 127) - 64;
             const double4 c4 = cand[kx[e]];
-            const int j = (int)(__double_as_longlong(c4.w) & 0x3fffffffll);
+            const int j = (int)((__double_as_longlong(c4.w) >> 30) & 0x3fffffffll);   // caller index
             double sh[3];
             image_shift(gp, n0, n1, n2, sh);
             const size_t slot = rowj + gp.off[t] + rank;
@@ -720,48 +735,24 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
 
 // ---- reductions and output ----------------------------------------------------------------
 
-// E = sum_i E_i and Xi = sum of per-block partials, in a fixed order (one block of 1008 threads).
-// Energy: strided partial sums, then a tree. Virial: thread t sums component t % 9 of the
-// partials t, t + 1008, ... (1008 = 112 * 9 keeps the component fixed and the reads coalesced),
-// then 9 threads add their component's 112 partial sums in order.
-constexpr int FIN_T = 1008;
-
-__global__ void __launch_bounds__(1024) k_finalize(int n, const double* ei, int nvp, const double* vir_part,
-                                                    double* energy, double* virial)
+// Single frame: E and the virial from the embedding backward's block partials [E, virial[9]], in a
+// fixed order: thread t < 250 sums component t % 10 of the partials t / 10, t / 10 + 25, ..., then
+// ten threads add their component's 25 sums.
+__global__ void __launch_bounds__(256) k_finalize(int nb, const double* part, double* energy, double* virial)
 {
-    __shared__ double red[1024];
+    __shared__ double red[256];
     const int t = threadIdx.x;
-    double e = 0.0;
-    for (int i = t; i < n; i += FIN_T) e += ei[i];
-    red[t] = e;
-    if (t < 1024 - FIN_T) red[FIN_T + t] = 0.0;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
-    if (t == 0) *energy = red[0];
-    __syncthreads();
     double v = 0.0;
-    const size_t total = 9 * (size_t)nvp;
-    for (size_t i = t; i < total; i += FIN_T) v += vir_part[i];
+    if (t < 250)
+        for (int i = t; i < 10 * nb; i += 250) v += part[i];
     red[t] = v;
     __syncthreads();
-    if (t < 9) {
-        double s = 0.0;
-        for (int k = t; k < FIN_T; k += 9) s += red[k];
-        virial[t] = s;
+    if (t < 10) {
+        double x = 0.0;
+        for (int k = t; k < 250; k += 10) x += red[k];
+        if (t == 0) *energy = x;
+        else virial[t - 1] = x;
     }
-}
-
-__global__ void k_output(int n, const int* perm, const double* f_int, const double* ei, double* force,
-                         double* atom_energy)
-{
-    int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= n) return;
-    int i = perm[a];
-    for (int c = 0; c < 3; ++c) force[3 * (size_t)i + c] = f_int[3 * (size_t)a + c];
-    if (atom_energy) atom_energy[i] = ei[a];
 }
 
 // Batched frames: per frame (one block each) E = sum E_i and the virial = sum over the frame's
@@ -780,7 +771,7 @@ __global__ void __launch_bounds__(256) k_finalize_batch(const FrameDesc* fd, con
         const int q = inv_perm[d.atom_off + a];
         acc[0] += ei[q];
         for (int k = 0; k < 9; ++k) acc[1 + k] += vir_atom[9 * (size_t)q + k];
-        for (int c = 0; c < 3; ++c) o[10 + 3 * (size_t)a + c] = f_int[3 * (size_t)q + c];
+        for (int c = 0; c < 3; ++c) o[10 + 3 * (size_t)a + c] = f_int[3 * ((size_t)d.atom_off + a) + c];
         if (d.want_ei) o[10 + 3 * (size_t)d.natoms + a] = ei[q];
     }
     for (int k = 0; k < 10; ++k) red[k][tid] = acc[k];
@@ -793,15 +784,12 @@ __global__ void __launch_bounds__(256) k_finalize_batch(const FrameDesc* fd, con
     if (tid < 10) o[tid] = red[tid][0];
 }
 
-// Debug: neighbour list in caller numbering, rows in caller order.
+// Debug: neighbour list (caller numbering already), rows in caller order.
 __global__ void k_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out)
 {
     int a = blockIdx.x;
     int i = perm[a];
-    for (int s = threadIdx.x; s < nc; s += blockDim.x) {
-        int j = nl_j[(size_t)a * nc + s];
-        out[(size_t)i * nc + s] = j < 0 ? -1 : perm[j];
-    }
+    for (int s = threadIdx.x; s < nc; s += blockDim.x) out[(size_t)i * nc + s] = nl_j[(size_t)a * nc + s];
 }
 
 // ---- launchers --------------------------------------------------------------------------
@@ -841,6 +829,11 @@ void launch_batch_prep(int nframes, int ntypes, const double* coord, const int* 
     hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(64), 0, s, nframes, ntypes, fd, tcount, toff, st);
     hipLaunchKernelGGL(k_prep_batch, dim3(nframes), dim3(PS_THREADS), 0, s, coord, atype, ntypes, gps, fd, perm,
                        inv_perm, itype, frame_of, pos, cell_of, cell_start, cand, f_int, vir_atom);
+}
+
+void launch_finalize(int nb, const double* part, double* energy, double* virial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, nb, part, energy, virial);
 }
 
 void launch_finalize_batch(int nframes, const FrameDesc* fd, const int* inv_perm, const double* ei,
@@ -884,13 +877,6 @@ void launch_nlist(int n, const double* pos, const int* perm, const int* inv_perm
         else DPK_NL(NL_CAP, false);
     }
 #undef DPK_NL
-}
-
-void launch_finalize(int n, const double* ei, int nvp, const double* vir_part, double* energy, double* virial,
-                     const int* perm, const double* f_int, double* force, double* atom_energy, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_T), 0, s, n, ei, nvp, vir_part, energy, virial);
-    hipLaunchKernelGGL(k_output, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, f_int, ei, force, atom_energy);
 }
 
 void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s)

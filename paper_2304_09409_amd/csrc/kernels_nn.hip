@@ -327,9 +327,11 @@ __device__ void stage_net(const EmbArgs& A, int net, typename P::acc* s_vec, cha
 // next item's neighbour vector and index loaded one item ahead.
 struct ChunkWalk {
     int i, a, np, c0;
+    int ac;   // caller index of atom a (backward pass), loaded when the walk reaches the atom
     bool have;
     double px, py, pz;
     int pj;
+    template <bool J = false>
     __device__ __forceinline__ bool find_atom(const EmbArgs& A, int a0, int a1, int wave, int nw, int apw, int ti,
                                               int tj, bool skip_empty) {
         for (; i < apw; ++i) {
@@ -338,10 +340,13 @@ struct ChunkWalk {
             if (A.itype[a] != ti) continue;
             np = A.nnei[(size_t)a * A.ntypes + tj];
             if (skip_empty && np == 0) continue;
+            if (J) ac = A.perm[a];
             return true;
         }
         return false;
     }
+    // J: also the neighbour's caller index (the backward pass adds forces in caller order)
+    template <bool J = false>
     __device__ __forceinline__ void fetch(const EmbArgs& A, int tj, int c16) {
         px = py = pz = 0.0;
         pj = 0;
@@ -349,7 +354,7 @@ struct ChunkWalk {
             const size_t slot = (size_t)a * A.nc + A.off[tj] + c0 + c16;
             const double* v = A.nl_r + 3 * slot;
             px = v[0]; py = v[1]; pz = v[2];
-            pj = A.nl_j[slot];
+            if (J) pj = A.nl_j[slot];
         }
     }
 };
@@ -404,6 +409,7 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
             ChunkWalk w;
             w.i = 0;
             w.c0 = 0;
+            w.ac = 0;
             w.have = w.find_atom(A, a0, a1, wave, NW, APW, ti, tj, false);
             w.fetch(A, tj, c16);
             acc Tacc[7][4];
@@ -545,7 +551,8 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
 // Backward (input gradient only): re-evaluate G_j and dG_j/ds, then
 //   dE/dR_j = N_c^-1 G_j dT,  dE/ds_j|_G = N_c^-1 sum_m dG_jm/ds (dT R_j)_m,
 //   g_ij = dE/dr_ij = [(dR_0 + dE/ds) s' + q (s' - s/r)] r^ + (s/r) dR_{1:3},  q = dR_{1:3} . r^,
-//   F_i += g_ij, F_j -= g_ij (FP64 atomics), Xi_ab -= g_ij,a r_ij,b (FP64, per-block partials).
+//   F_i += g_ij, F_j -= g_ij (FP64 atomics into caller order), Xi_ab -= g_ij,a r_ij,b (FP64,
+//   per-block partials, with E over the block's atoms for a single frame).
 // ---------------------------------------------------------------------------------------------
 template <class P, bool TAB>
 __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(EmbArgs A)
@@ -595,8 +602,9 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
             ChunkWalk w;
             w.i = 0;
             w.c0 = 0;
-            w.have = w.find_atom(A, a0, a1, wave, NW, APW, ti, tj, true);
-            w.fetch(A, tj, c16);
+            w.ac = 0;
+            w.have = w.find_atom<true>(A, a0, a1, wave, NW, APW, ti, tj, true);
+            w.fetch<true>(A, tj, c16);
             acc pdT[DTL];
             for (int q = 0; q < DTL; ++q) {
                 const int e = lane + 64 * q;
@@ -606,16 +614,16 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
             while (w.have) {
                 const double x = w.px, y = w.py, z = w.pz;
                 const int jn = w.pj;
-                const int ca = w.a, cc0 = w.c0, cnp = w.np;
+                const int ca = w.a, cac = w.ac, cc0 = w.c0, cnp = w.np;
                 bool last = false;
                 w.c0 += 16;
                 if (w.c0 >= w.np) {
                     ++w.i;
                     w.c0 = 0;
-                    w.have = w.find_atom(A, a0, a1, wave, NW, APW, ti, tj, true);
+                    w.have = w.find_atom<true>(A, a0, a1, wave, NW, APW, ti, tj, true);
                     last = true;
                 }
-                w.fetch(A, tj, c16);
+                w.fetch<true>(A, tj, c16);
                 if (cc0 == 0) {
                     // the prefetched dT of this atom goes to LDS; the next atom's is requested
                     wave_sync();
@@ -776,7 +784,7 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                         Fi[k] = v;
                     }
                     if (lane == 0)
-                        for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&A.F[3 * (size_t)ca + k], Fi[k]);
+                        for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&A.F[3 * (size_t)cac + k], Fi[k]);
                     Fi[0] = Fi[1] = Fi[2] = 0.0;
                     if (A.vir_atom) {
                         // batched frames: this atom's share of the virial, kept per centre atom
@@ -803,10 +811,23 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
     if (lane == 0)
         for (int k = 0; k < 9; ++k) s_vir[wave][k] = vir[k];
     __syncthreads();
+    // block partial [E, virial]: the virial over the waves, E over this block's atoms (a shuffle
+    // tree, a fixed order; single frame), and E_i in caller order if asked for
+    double* part = A.vir_part + 10 * (size_t)blockIdx.x;
     if (threadIdx.x < 9) {
         double v = 0.0;
         for (int q = 0; q < NW; ++q) v += s_vir[q][threadIdx.x];
-        A.vir_part[9 * (size_t)blockIdx.x + threadIdx.x] = v;
+        part[1 + threadIdx.x] = v;
+    }
+    if (A.Ei) {
+        if (threadIdx.x < 64) {
+            double e = 0.0;
+            for (int a = a0 + lane; a < a1; a += 64) e += A.Ei[a];
+            for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
+            if (lane == 0) part[0] = e;
+        }
+        if (A.atom_energy)
+            for (int a = a0 + (int)threadIdx.x; a < a1; a += NW * 64) A.atom_energy[A.perm[a]] = A.Ei[a];
     }
 }
 
