@@ -486,6 +486,15 @@ __device__ __forceinline__ void image_shift(const GeomParams& gp, int n0, int n1
 }
 
 constexpr int NL_UNROLL = 4;
+constexpr int RANK_MAX = 256;   // hits per atom up to which the neighbour list ranks instead of sorting
+
+// Ordering of LDS traffic between the lanes of the (single-wave) workgroup.
+__device__ __forceinline__ void wave_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 // BATCH: atom a belongs to frame frame_of[a]; its geometry is gps[frame] and its bins start at
 // fd[frame].cell_off of the concatenated cell_start (candidate records hold batch-wide indices).
@@ -627,8 +636,7 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
     int S2 = 64;
     while (S2 < count) S2 <<= 1;
     __syncthreads();
-    // Bitonic sort of the S2 <= CAP keys in registers: element e of this lane is position
-    // lane + 64 e. Pairs 64 or more apart sit in one lane; closer pairs are exchanged across lanes.
+    // Element e of this lane is key lane + 64 e; the keys are then put in order.
     constexpr int E = CAP / 64;
     const int EA = S2 >> 6;   // active elements per lane
     unsigned long long kh[E], kl[E];
@@ -641,6 +649,60 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
         kl[e] = have ? klo[i] : ~0ull;
         kx[e] = have ? kq[i] : 0;
     }
+    if (count <= RANK_MAX) {
+        // Rank sort (up to RANK_MAX keys): a key's position is the number of smaller keys, counted
+        // against every stored key read once from LDS (one broadcast per key, no exchange chain).
+        // The high words decide unless two are equal (equal type and r^2 to 2^-47, i.e. in practice
+        // equal distances): equal ranks then collide in a slot check and the ranks are recounted on
+        // the full 128-bit keys, which are unique.
+        int rk[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) rk[e] = 0;
+        for (int q = 0; q < count; ++q) {
+            const unsigned long long h = khi[q];
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (e < EA) rk[e] += h < kh[e] ? 1 : 0;
+        }
+        wave_barrier();
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (e < EA && lane + 64 * e < count) kq[rk[e]] = lane + 64 * e;
+        wave_barrier();
+        bool clash = false;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (e < EA && lane + 64 * e < count) clash |= kq[rk[e]] != lane + 64 * e;
+        if (__ballot(clash) != 0) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) rk[e] = 0;
+            for (int q = 0; q < count; ++q) {
+                const unsigned long long h = khi[q], l = klo[q];
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    if (e < EA) rk[e] += key_less(h, l, kh[e], kl[e]) ? 1 : 0;
+            }
+        }
+        wave_barrier();
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (e < EA && lane + 64 * e < count) {
+                khi[rk[e]] = kh[e];
+                klo[rk[e]] = kl[e];
+                kq[rk[e]] = kx[e];
+            }
+        wave_barrier();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = lane + 64 * e;
+            const bool have = e < EA && i < count;
+            kh[e] = have ? khi[i] : ~0ull;
+            kl[e] = have ? klo[i] : ~0ull;
+            kx[e] = have ? kq[i] : 0;
+        }
+    } else {
+    // Bitonic sort of the S2 <= CAP keys in registers. Pairs 64 or more apart sit in one lane;
+    // closer pairs are exchanged across lanes.
     for (int k = 2; k <= S2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             if (j >= 64) {
@@ -677,6 +739,7 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
                 }
             }
         }
+    }
     }
     // per-type counts of the sorted keys: every hit, unless the buffer overflowed; then only the
     // stored hits count, so that each type block starts where its keys do and every slot the

@@ -96,6 +96,17 @@ def fcc_box(n_cell: int, lattice: float, seed: int, sigma: float = 0.05):
     return coord.astype(np.float64), atype, box.astype(np.float64)
 
 
+def tie_lattice(n: int = 8, spacing: float = 2.0):
+    """Unjittered 2-type simple-cubic frame (types by the parity of i + j + k) in a cubic cell of
+    n * spacing: with spacing and cell length powers of two every coordinate, wrapped position and
+    squared distance is exact, so many neighbours sit at exactly equal distances (ties)."""
+    g = np.arange(n)
+    sites = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    coord = sites.astype(np.float64) * spacing
+    atype = (sites.sum(axis=1) % 2).astype(np.int32)
+    return coord, atype, np.diag([n * spacing] * 3).astype(np.float64)
+
+
 def serving_frame(natoms: int, seed: int, ntypes: int, density: float = 0.1,
                   sigma: float = 0.1):
     """One request frame: simple-cubic sites at the given density, random subset, jitter."""

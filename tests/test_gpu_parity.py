@@ -85,6 +85,7 @@ FRAMES = {
     "open_cluster60": ("water", lambda: synth.serving_frame(60, 3, 2)[:2] + (None,)),
     "triclinic400": ("serve", lambda: _triclinic()),
     "fcc500_truncated": ("fcc", lambda: synth.fcc_box(5, 3.6, 1)),
+    "lattice512_ties": ("water", lambda: synth.tie_lattice()),
 }
 
 

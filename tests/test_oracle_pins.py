@@ -375,12 +375,16 @@ def test_nlist_brute_force_and_cell_list_agree(case, water_oracle, serve_oracle,
     assert d0 == d1
 
 
-@pytest.mark.parametrize("case", ["serve50", "fcc_trunc"])
-def test_nlist_is_sorted_per_type_and_keeps_nearest(case, serve_oracle, fcc_oracle):
+@pytest.mark.parametrize("case", ["serve50", "fcc_trunc", "lattice_ties"])
+def test_nlist_is_sorted_per_type_and_keeps_nearest(case, serve_oracle, fcc_oracle, water_oracle):
+    # lattice_ties: exact equal distances everywhere (Sec. III.B.1 orders by type, distance, index;
+    # equal distances fall to the index), and the nearest-sel truncation cuts through a tied shell
     if case == "serve50":
         o, (c, t, b) = serve_oracle, synth.serving_frame(50, 4, 3)
-    else:
+    elif case == "fcc_trunc":
         o, (c, t, b) = fcc_oracle, synth.fcc_box(5, 3.6, 1)
+    else:
+        o, (c, t, b) = water_oracle, synth.tie_lattice()
     nl, rij, ndrop = o.nlist(c, t, b)
     ref = _brute_neighbours(c, t, b, o.model["rcut"])
     sel = o.model["sel"]
@@ -400,7 +404,7 @@ def test_nlist_is_sorted_per_type_and_keeps_nearest(case, serve_oracle, fcc_orac
             assert np.all(np.diff(r) >= 0)                            # ascending distance
             assert np.all(t[got] == a)
     assert ndrop == total_drop
-    if case == "fcc_trunc":
+    if case in ("fcc_trunc", "lattice_ties"):
         assert ndrop > 0
 
 
