@@ -511,8 +511,9 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
     extern __shared__ __attribute__((aligned(16))) unsigned long long nl_lds[];
     unsigned long long* khi = nl_lds;
     unsigned long long* klo = khi + CAP;
-    int* kq = reinterpret_cast<int*>(klo + CAP);   // flat candidate index, moved with its key
     const int S = (2 * gp.K[0] + 1) * (2 * gp.K[1] + 1) * (2 * gp.K[2] + 1);
+    double* s_sh = reinterpret_cast<double*>(klo + CAP);   // [S][3] image shift of each stencil bin
+    int* kq = reinterpret_cast<int*>(s_sh + 3 * S);       // flat candidate index, moved with its key
     int* s_base = kq + CAP;                        // [S + 1]
     int* s_start = s_base + S + 1;                 // [S]
     int* s_code = s_start + S;                     // [S]
@@ -565,6 +566,10 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
             s_base[sidx] = total + incl - cnt;
             s_start[sidx] = start;
             s_code[sidx] = code;
+            // the bin's image shift, once (the same expression the output uses, so the same bits)
+            double sh[3];
+            image_shift(gp, (code >> 14) - 64, ((code >> 7) & 127) - 64, (code & 127) - 64, sh);
+            for (int c = 0; c < 3; ++c) s_sh[3 * sidx + c] = sh[c];
         }
         total += __shfl(incl, 63);
     }
@@ -598,9 +603,7 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
             if (bin[u] >= 0) {
                 code = s_code[bin[u]];
                 tag = __double_as_longlong(c4[u].w);
-                const int nn0 = (code >> 14) - 64, nn1 = ((code >> 7) & 127) - 64, nn2 = (code & 127) - 64;
-                double sh[3];
-                image_shift(gp, nn0, nn1, nn2, sh);
+                const double* sh = s_sh + 3 * bin[u];
                 if (!((tag & 0x3fffffffll) == self_tag && code == self_code)) {
                     const double d0 = (c4[u].x + sh[0]) - pi[0];
                     const double d1 = (c4[u].y + sh[1]) - pi[1];
@@ -919,14 +922,14 @@ void launch_nlist(int n, const double* pos, const int* perm, const int* inv_perm
                   const int* frame_of, int max_stencil, int max_cap)
 {
     // candidate buffer sized from the expected count within r_c (the synchronous entry point reruns
-    // a frame that overflowed with the largest buffer); LDS = 20 B per candidate slot + 12 B per
+    // a frame that overflowed with the largest buffer); LDS = 20 B per candidate slot + 36 B per
     // stencil bin, so small stencils leave room for more resident waves. A batch passes the
     // largest stencil and buffer of its frames.
     const bool batch = gps != nullptr;
     const int S = batch ? max_stencil : (2 * gp.K[0] + 1) * (2 * gp.K[1] + 1) * (2 * gp.K[2] + 1);
     const int want = batch ? max_cap : gp.cap;
     const int cap = want <= 256 ? 256 : (want <= 512 ? 512 : NL_CAP);
-    const size_t lds = (size_t)cap * 20 + (size_t)(3 * S + 1) * 4;
+    const size_t lds = (size_t)cap * 20 + (size_t)S * 24 + (size_t)(3 * S + 1) * 4;
 #define DPK_NL(C, B)                                                                                              \
     hipLaunchKernelGGL((k_nlist<C, B>), dim3(n), dim3(64), lds, s, n, pos, perm, inv_perm, cell_of, cell_start,   \
                        cand, gp, gps, fd, frame_of, nl_j, nl_r, nnei, st)
