@@ -151,12 +151,12 @@ int dpk_ctx_stats(dpk_ctx *c, dpk_stats *out);
  * durations (milliseconds, one per stage) and the number of frames since profiling was enabled.
  * Enabling resets the sums. For timing tools (no effect on results). */
 enum {
-    DPK_STAGE_PREP = 0,      /* type partition, wrap into the cell, bin counting            */
+    DPK_STAGE_PREP = 0,      /* type partition, wrap into the cell, bins, candidate records */
     DPK_STAGE_NLIST = 1,     /* candidate search, sorted per-type selection                 */
     DPK_STAGE_EMBED_FWD = 2, /* environment rows, embedding net, contraction T              */
     DPK_STAGE_FIT = 3,       /* descriptor, fitting net forward and input gradient           */
-    DPK_STAGE_EMBED_BWD = 4, /* embedding re-evaluation, adjoint, force and virial scatter   */
-    DPK_STAGE_FINAL = 5,     /* energy and virial sums, output permutation                   */
+    DPK_STAGE_EMBED_BWD = 4, /* embedding re-evaluation, adjoint, forces, block E and virial */
+    DPK_STAGE_FINAL = 5,     /* energy and virial sums over the blocks                       */
     DPK_NSTAGES = 6
 };
 int dpk_ctx_profile(dpk_ctx *c, int enable);
