@@ -86,6 +86,8 @@ FRAMES = {
     "triclinic400": ("serve", lambda: _triclinic()),
     "fcc500_truncated": ("fcc", lambda: synth.fcc_box(5, 3.6, 1)),
     "lattice512_ties": ("water", lambda: synth.tie_lattice()),
+    # more than 8,192 atoms: the multi-block preparation, here with open-boundary bins
+    "open_cluster9000": ("water", lambda: synth.serving_frame(9000, 5, 2)[:2] + (None,)),
 }
 
 
