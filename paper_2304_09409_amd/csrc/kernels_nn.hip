@@ -178,6 +178,18 @@ struct PBF16 {
 
 template <class V> __device__ __forceinline__ void zero4(V& v) { v[0] = 0; v[1] = 0; v[2] = 0; v[3] = 0; }
 
+// Rank-1 updates on the matrix cores. v_mfma_f32_4x4x1f32 runs 16 independent 4 x 4 x 1 products,
+// one per block of four lanes b: register i of lane 4b + j gains A(lane 4b + i) * B(lane 4b + j).
+// With a = X[lane % 4] (an entry of a 4-vector X that is the same for the lane's quad) and b the
+// lane's own scalar y, register k of every lane gains X[k] * y: 16 products per instruction, none
+// wasted. The forward embedding kernel contracts T += G^T R this way (its layer-3 output puts one
+// feature per lane and the neighbours in registers), which keeps its 16 FMAs per (feature,
+// neighbour-quad) off the vector ALUs and its accumulators out of the general registers.
+__device__ __forceinline__ void outer4(f4& d, float a, float b)
+{
+    d = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, d, 0, 0, 0);
+}
+
 // Wave-scope ordering of LDS traffic between lanes of one wave.
 __device__ __forceinline__ void wave_sync()
 {
@@ -258,14 +270,15 @@ constexpr int ZS = 20;   // row stride (floats) of the feature-major skip buffer
 // one block per CU (fewer net stagings per atom) and a small one still spreads over the CUs. FP64
 // runs 4 waves and keeps W3^T in global memory (L1/L2) to leave LDS for the wider activation
 // buffers. The FP32-accumulating policies run:
-//   * forward (network): 12 waves, three per SIMD, in at most 168 VGPRs: the third wave per SIMD
-//     hides more of the exp/rcp and LDS latency;
+//   * forward (network): 16 waves, four per SIMD, in at most 128 VGPRs (the contraction's
+//     accumulators live in the matrix cores' operands, see outer4): the extra waves per SIMD hide
+//     more of the exp/rcp, MFMA and LDS latency;
 //   * forward (table): 8 waves (the polynomial path needs more registers);
 //   * backward: 8 waves (its per-wave activation buffers fill the LDS).
 template <class P, bool FWD = false, bool TAB = false> struct EmbCfg {
     typedef typename P::wt wt;
     static constexpr bool F64 = sizeof(typename P::acc) == 8;
-    static constexpr int NW = F64 ? 4 : (FWD && !TAB ? 12 : 8);
+    static constexpr int NW = F64 ? 4 : (FWD && !TAB ? 16 : 8);
     static constexpr int APW_MAX = F64 ? 3 : (FWD ? (TAB ? 3 : 4) : 6);
     static constexpr bool W3LDS = !F64;
     // LDS rows of staged weights: one lane's fragment per group (VPL K values; [hi lo] for split
@@ -412,7 +425,7 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
             w.ac = 0;
             w.have = w.find_atom(A, a0, a1, wave, NW, APW, ti, tj, false);
             w.fetch(A, tj, c16);
-            acc Tacc[7][4];
+            accv Tacc[7];
             while (w.have) {
                 const double x = w.px, y = w.py, z = w.pz;
                 const int ca = w.a, cc0 = w.c0, cnp = w.np;
@@ -444,20 +457,34 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
                     for (int k = 0; k < 4; ++k) s_R[wave][p][k] = (acc)R[k];
                     s_x[wave][p] = s;
                 }
+                // T[m][k] += G_qm R_qk for feature m = 16 tm + c16 and neighbour q = orow(g, r) of this
+                // lane: FP64 on the VALU; FP32 as outer4 with A = R_q[lane % 4] (register k gets
+                // R_qk G_qm: all of T's row m over lane group g's neighbours)
+                float Rq[4];
+                auto add_G = [&](int tm, int r, int q, acc G) {
+                    if constexpr (Cfg::F64) {
+                        for (int k = 0; k < 4; ++k) Tacc[tm][k] += G * s_R[wave][q][k];
+                    } else {
+                        outer4(Tacc[tm], Rq[r], G);
+                    }
+                };
                 if (TAB) {
                     wave_sync();
+                    if constexpr (!Cfg::F64)
+                        for (int r = 0; r < 4; ++r) Rq[r] = s_R[wave][P::orow(g, r)][c16 & 3];
                     for (int tm = 0; tm < 7; ++tm) {
                         const int m = 16 * tm + c16;
-                        if (m >= E2) continue;
+                        if (Cfg::F64 && m >= E2) continue;
                         for (int r = 0; r < 4; ++r) {
                             const int q = P::orow(g, r);
                             const double xs = s_x[wave][q];
                             int li = (int)floor(xs / A.tab_dx);
                             li = li < 0 ? 0 : (li >= A.tab_nint ? A.tab_nint - 1 : li);
                             const acc t = (acc)(xs - li * A.tab_dx);
-                            const acc* cf = tab + ((size_t)li * E2 + m) * 6;
-                            const acc G = ((((cf[0] * t + cf[1]) * t + cf[2]) * t + cf[3]) * t + cf[4]) * t + cf[5];
-                            for (int k = 0; k < 4; ++k) Tacc[tm][k] += G * s_R[wave][q][k];
+                            const acc* cf = tab + ((size_t)li * E2 + (m < E2 ? m : 0)) * 6;
+                            acc G = ((((cf[0] * t + cf[1]) * t + cf[2]) * t + cf[3]) * t + cf[4]) * t + cf[5];
+                            if (m >= E2) G = 0;   // rows past 100 are not stored
+                            add_G(tm, r, q, G);
                         }
                     }
                     if (g == 0 && valid && (s < 0.0 || s > A.tab_nint * A.tab_dx))
@@ -513,15 +540,18 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
                         }
                     }
                     wave_sync();
-                    // G = w_hat tanh(pre3 + b) + {z2, z2}; contraction T += G^T R
+                    if constexpr (!Cfg::F64)
+                        for (int r = 0; r < 4; ++r) Rq[r] = s_R[wave][P::orow(g, r)][c16 & 3];
+                    // G = w_hat tanh(pre3 + b) + {z2, z2}; contraction T += G^T R (features past
+                    // 100 have zero weights, finite G, and rows of T that are never stored)
                     for (int tm = 0; tm < 7; ++tm) {
                         const int m = 16 * tm + c16;
-                        if (m >= E2) continue;
+                        if (Cfg::F64 && m >= E2) continue;
                         const acc wh = s_vec[EV_WH3 + m], bb = s_vec[EV_B3 + m];
                         for (int r = 0; r < 4; ++r) {
                             const int q = P::orow(g, r);
                             const acc G = wh * P::act_b(acc3[tm][r], bb) + s_z2[wave][q][m % E1];
-                            for (int k = 0; k < 4; ++k) Tacc[tm][k] += G * s_R[wave][q][k];
+                            add_G(tm, r, q, G);
                         }
                     }
                 }
@@ -536,7 +566,8 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
                     }
                     // sum the four lane groups (they hold different neighbours) and store T
                     for (int tm = 0; tm < 7; ++tm) {
-                        const acc v = sum_groups4(Tacc[tm]);
+                        const acc tv[4] = {Tacc[tm][0], Tacc[tm][1], Tacc[tm][2], Tacc[tm][3]};
+                        const acc v = sum_groups4(tv);
                         const int m = 16 * tm + c16;
                         if (m < E2)
                             Tout[((size_t)ca * E2 + m) * 4 + ksel(g)] = v * (acc)A.inv_nc + Tprev[tm];
