@@ -169,6 +169,21 @@ inline int kphys(int precision, int k)
 // previous layer's output tile 2c and values 4..7 the same rows of tile 2c + 1.
 inline int kidx32(int c, int g, int j) { return 32 * c + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4)); }
 
+// Row position of register u of lane group g in embedding layer l (the K position of layer 1, the
+// output row of layers 2 and 3) for the precision's MFMA layout: FP64 lanes of group g hold K
+// values 16c + g + 4v and output rows g + 4r of each tile, the BF16 paths K values kidx32(c, g, v)
+// and output rows 4g + r.
+inline int emb_pos(int precision, int l, int g, int u)
+{
+    const bool f64 = precision == DPK_FP64;
+    if (l == 1) {
+        const int vpl = f64 ? 4 : 8, c = u / vpl, v = u % vpl;
+        return f64 ? 16 * c + g + 4 * v : kidx32(c, g, v);
+    }
+    const int r = u & 3;
+    return 16 * (u >> 2) + (f64 ? g + 4 * r : 4 * g + r);
+}
+
 // Pack one matrix of `rows` x `kdim` (zero-padded to the tiles and chunks) in fragment-major
 // order: fragment (c, t) at frag0 + c * ntiles + t, lane 16g + i holding row 16t + i.
 template <class Fn>
@@ -457,21 +472,36 @@ int upload_model(dpk_ctx* c)
     if (f64) fm.init(prec, (size_t)nt * FM_SIZE);
     std::vector<uint16_t> fx;
     if (!f64) fx.assign((size_t)nt * XF_NFRAG * XF_ELEMS, 0);
+    // feature at each row position of the embedding layers in the skip-aligned order (-1: padding,
+    // zero weights)
+    int f1[K2P], f2[N2P], f3[N3P];
+    for (int g = 0; g < 4; ++g) {
+        for (int u = 0; u < K2P / 4; ++u) f1[emb_pos(prec, 1, g, u)] = emb_feat(1, g, u);
+        for (int u = 0; u < N2P / 4; ++u) f2[emb_pos(prec, 2, g, u)] = emb_feat(2, g, u);
+        for (int u = 0; u < N3P / 4; ++u) f3[emb_pos(prec, 3, g, u)] = emb_feat(3, g, u);
+    }
     for (int n = 0; n < nets; ++n) {
         const Layer* L = &m->emb[(size_t)n * 3];
         double* v = &ev[(size_t)n * EVEC];
-        for (int k = 0; k < E0; ++k) {
-            v[EV_W1 + k] = L[0].W[k];
-            v[EV_B1 + k] = L[0].b[k];
-            v[EV_WH1 + k] = L[0].wh[k];
-        }
-        for (int k = 0; k < E1; ++k) { v[EV_B2 + k] = L[1].b[k]; v[EV_WH2 + k] = L[1].wh[k]; }
-        for (int k = 0; k < E2; ++k) { v[EV_B3 + k] = L[2].b[k]; v[EV_WH3 + k] = L[2].wh[k]; }
+        for (int k = 0; k < K2P; ++k)
+            if (f1[k] >= 0) {
+                v[EV_W1 + k] = L[0].W[f1[k]];
+                v[EV_B1 + k] = L[0].b[f1[k]];
+                v[EV_WH1 + k] = L[0].wh[f1[k]];
+            }
+        for (int k = 0; k < N2P; ++k)
+            if (f2[k] >= 0) { v[EV_B2 + k] = L[1].b[f2[k]]; v[EV_WH2 + k] = L[1].wh[f2[k]]; }
+        for (int k = 0; k < N3P; ++k)
+            if (f3[k] >= 0) { v[EV_B3 + k] = L[2].b[f3[k]]; v[EV_WH3 + k] = L[2].wh[f3[k]]; }
         const size_t base = (size_t)n * EM_SIZE;
-        for (int k = 0; k < E0; ++k)
-            for (int o = 0; o < E1; ++o) em.set(base + EM_W2T + (size_t)o * K2P + kphys(prec, k), L[1].W[k * E1 + o]);
-        for (int k = 0; k < E1; ++k)
-            for (int o = 0; o < E2; ++o) em.set(base + EM_W3T + (size_t)o * N2P + kphys(prec, k), L[2].W[k * E2 + o]);
+        for (int k = 0; k < K2P; ++k)
+            for (int o = 0; o < N2P; ++o)
+                if (f1[k] >= 0 && f2[o] >= 0)
+                    em.set(base + EM_W2T + (size_t)o * K2P + kphys(prec, k), L[1].W[f1[k] * E1 + f2[o]]);
+        for (int k = 0; k < N2P; ++k)
+            for (int o = 0; o < N3P; ++o)
+                if (f2[k] >= 0 && f3[o] >= 0)
+                    em.set(base + EM_W3T + (size_t)o * N2P + kphys(prec, k), L[2].W[f2[k] * E2 + f3[o]]);
     }
     for (int t = 0; t < nt; ++t) {
         const Layer* L = &m->fit[(size_t)t * 4];

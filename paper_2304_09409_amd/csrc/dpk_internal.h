@@ -51,6 +51,37 @@ constexpr int XF_W1B = XF_W2B + XF_NCH2 * 15;  // layer 1 backward: rows = 1600 
 constexpr int XF_NFRAG = XF_W1B + XF_NCH2 * 100;
 constexpr int XF_ACT = 3 * 16 * 256;           // fitting scratch floats per 16-atom tile
 
+// Skip-aligned feature order of the embedding net (network path; the table path keeps features in
+// order). The layer widths double (25 -> 50 -> 100), so each layer adds its input to its output
+// with feature o taking input o mod n_in (Sec. II.A.6, eq. NN). Every layer is evaluated with one
+// neighbour per lane column and a lane group g holding a fixed set of rows in registers u; the
+// features are placed so that the input of every skip sits in the same lane, at register u / 2:
+//   layer 1, register u1 of group g: feature kb(g) + u1 for u1 < ns(g) (ns = 7, 6, 6, 6), else none;
+//   layer 2, register u2: feature f1(u2 / 2) + 25 (u2 % 2);
+//   layer 3, register u3: feature f2(u3 / 2) + 50 (u3 % 2).
+// That fills 7 + 6 + 6 + 6 = 25, 50 and 100 features with 7, 4 and 7 padding rows, whose weights
+// are zero (their outputs are exactly zero). Registers map to row positions through the
+// instruction's layout: layer-1 register u = c VPL + v is K position kidx(c, g, v); register u of
+// layers 2 and 3 is row 16 (u / 4) + orow(g, u % 4).
+__host__ __device__ constexpr int emb_ns(int g) { return g == 0 ? 7 : 6; }
+__host__ __device__ constexpr int emb_kb(int g) { return g == 0 ? 0 : 6 * g + 1; }
+// feature held by register u of lane group g in layer l (1, 2, 3), or -1 for a padding row
+__host__ __device__ constexpr int emb_feat(int l, int g, int u)
+{
+    const int u1 = u >> (l - 1);
+    if (u1 >= emb_ns(g)) return -1;
+    const int k = emb_kb(g) + u1;
+    return l == 1 ? k : (l == 2 ? k + E0 * (u & 1) : k + E0 * ((u >> 1) & 1) + E1 * (u & 1));
+}
+// lane group and register of layer-3 feature f (inverse of emb_feat(3, ., .))
+__host__ __device__ constexpr void emb_reg3(int f, int& g, int& u)
+{
+    const int h3 = f >= E1 ? 1 : 0, n = f - E1 * h3;
+    const int h2 = n >= E0 ? 1 : 0, k = n - E0 * h2;
+    g = k < 7 ? 0 : (k - 1) / 6;
+    u = 4 * (k - emb_kb(g)) + 2 * h2 + h3;
+}
+
 constexpr int64_t EM_W2T = 0;                          // [64][32]
 constexpr int64_t EM_W3T = N2P * K2P;                  // [112][64]
 constexpr int64_t EM_SIZE = EM_W3T + N3P * N2P;

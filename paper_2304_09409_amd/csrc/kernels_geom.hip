@@ -801,23 +801,36 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
 
 // ---- reductions and output ----------------------------------------------------------------
 
+// Compensated (Neumaier) running sum: the error of a long sum stays about one rounding of the
+// result instead of growing with the number of terms (this file is built without FMA contraction,
+// which the compensation relies on).
+struct NeumaierSum {
+    double s = 0.0, c = 0.0;
+    __device__ void add(double x) {
+        const double t = s + x;
+        c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    __device__ double value() const { return s + c; }
+};
+
 // Single frame: E and the virial from the embedding backward's block partials [E, virial[9]], in a
-// fixed order: thread t < 250 sums component t % 10 of the partials t / 10, t / 10 + 25, ..., then
-// ten threads add their component's 25 sums.
+// fixed order with compensated sums: thread t < 250 sums component t % 10 of the partials t / 10,
+// t / 10 + 25, ..., then ten threads add their component's 25 sums.
 __global__ void __launch_bounds__(256) k_finalize(int nb, const double* part, double* energy, double* virial)
 {
     __shared__ double red[256];
     const int t = threadIdx.x;
-    double v = 0.0;
+    NeumaierSum v;
     if (t < 250)
-        for (int i = t; i < 10 * nb; i += 250) v += part[i];
-    red[t] = v;
+        for (int i = t; i < 10 * nb; i += 250) v.add(part[i]);
+    red[t] = v.value();
     __syncthreads();
     if (t < 10) {
-        double x = 0.0;
-        for (int k = t; k < 250; k += 10) x += red[k];
-        if (t == 0) *energy = x;
-        else virial[t - 1] = x;
+        NeumaierSum x;
+        for (int k = t; k < 250; k += 10) x.add(red[k]);
+        if (t == 0) *energy = x.value();
+        else virial[t - 1] = x.value();
     }
 }
 

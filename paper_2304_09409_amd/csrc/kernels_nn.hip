@@ -15,9 +15,13 @@
 //   * Embedding, per chunk of 16 neighbours of one centre atom: layer 1 (1 -> 25) on the VALU
 //     straight into B-operand layout; layer 2 (25 -> 50) transposed (W^T as A, activations as B);
 //     forward pass: layer 3 (50 -> 100) untransposed (activations as A), which puts 4 neighbours
-//     in each lane's registers for the contraction T += G^T R done on the VALU; backward pass:
-//     layer 3 transposed, which keeps one neighbour per lane column so the reductions over the
-//     100 channels (dE/dR_j and dE/ds_j) are lane-local plus two cross-group shuffles.
+//     in each lane's registers for the contraction T += G^T R; backward pass: layer 3 transposed,
+//     which keeps one neighbour per lane column so the reductions over the 100 channels (dE/dR_j
+//     and dE/ds_j) are lane-local plus two cross-group shuffles. Both contractions run as rank-1
+//     updates on the matrix cores (outer4) in the FP32-accumulating paths.
+//   * The features of the embedding net are stored in a skip-aligned order (emb_feat): the input
+//     of every skip connection is a register of the same lane, so no layer output goes through
+//     LDS except the forward pass's layer 2 (the untransposed layer 3 reads it transposed).
 //   * The backward pass re-evaluates the net with its forward-mode derivative d/ds (the input is
 //     a scalar), rather than storing G: G would cost 400 B per neighbour in HBM.
 //   * Fitting: 16 atoms per wave, all 240 features per wave; every layer transposed (W^T as A)
@@ -51,6 +55,8 @@ struct PF64 {
     static constexpr int GB = 32;    // bytes of one lane's fragment in LDS
     struct frag { d4 v; };
     __device__ static int orow(int g, int r) { return g + 4 * r; }
+    __device__ static int ogrp(int row) { return row & 3; }    // inverse of orow
+    __device__ static int oreg(int row) { return row >> 2; }
     __device__ static int kidx(int c, int g, int v) { return 16 * c + g + 4 * v; }
     __device__ static frag make(acc x0, acc x1, acc x2, acc x3) { frag f; f.v = d4{x0, x1, x2, x3}; return f; }
     __device__ static frag make(const acc* x) { return make(x[0], x[1], x[2], x[3]); }
@@ -106,6 +112,8 @@ struct PMIX {
     static constexpr int KC = 32, VPL = 8, GB = 32;
     struct frag { bf8 h, l; };
     __device__ static int orow(int g, int r) { return 4 * g + r; }
+    __device__ static int ogrp(int row) { return row >> 2; }   // inverse of orow
+    __device__ static int oreg(int row) { return row & 3; }
     __device__ static int kidx(int c, int g, int v) { return kidx32(c, g, v); }
     __device__ static frag make(const acc* x) {
         frag f;
@@ -150,6 +158,8 @@ struct PBF16 {
     static constexpr int KC = 32, VPL = 8, GB = 16;
     struct frag { bf8 h; };
     __device__ static int orow(int g, int r) { return 4 * g + r; }
+    __device__ static int ogrp(int row) { return row >> 2; }   // inverse of orow
+    __device__ static int oreg(int row) { return row & 3; }
     __device__ static int kidx(int c, int g, int v) { return kidx32(c, g, v); }
     __device__ static frag make(const acc* x) {
         frag f;
@@ -183,8 +193,9 @@ template <class V> __device__ __forceinline__ void zero4(V& v) { v[0] = 0; v[1] 
 // With a = X[lane % 4] (an entry of a 4-vector X that is the same for the lane's quad) and b the
 // lane's own scalar y, register k of every lane gains X[k] * y: 16 products per instruction, none
 // wasted. The forward embedding kernel contracts T += G^T R this way (its layer-3 output puts one
-// feature per lane and the neighbours in registers), which keeps its 16 FMAs per (feature,
-// neighbour-quad) off the vector ALUs and its accumulators out of the general registers.
+// feature per lane and the neighbours in registers), the backward kernel dE/dR_j = G dT and
+// dE/ds_j = (dG/ds) dT (one row m per lane quad, one neighbour per lane): the FMAs leave the vector
+// ALUs and the accumulators the general registers.
 __device__ __forceinline__ void outer4(f4& d, float a, float b)
 {
     d = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, d, 0, 0, 0);
@@ -263,7 +274,10 @@ __device__ __forceinline__ void switch_fn(double r, double ir, double rs, double
     }
 }
 
-constexpr int ZS = 20;   // row stride (floats) of the feature-major skip buffers; 16 neighbours used
+// Row stride of the forward pass's neighbour-major layer-2 buffer (64 rows used): a multiple of 4
+// but not of 8, so the reads at (neighbour orow(g, r), row n) of the four lane groups fall in
+// different banks.
+constexpr int Z2S = 68;
 
 // Launch shape of the embedding kernels: NW waves per block share one staged net; each wave takes
 // A.apw atoms, chosen per launch (embed_apw) between 1 and APW_MAX so that a large frame gets about
@@ -274,11 +288,12 @@ constexpr int ZS = 20;   // row stride (floats) of the feature-major skip buffer
 //     accumulators live in the matrix cores' operands, see outer4): the extra waves per SIMD hide
 //     more of the exp/rcp, MFMA and LDS latency;
 //   * forward (table): 8 waves (the polynomial path needs more registers);
-//   * backward: 8 waves (its per-wave activation buffers fill the LDS).
+//   * backward: 12 waves, three per SIMD, in at most 168 VGPRs (skips in registers, the
+//     contraction on the matrix cores, the pair sums of force and virial in LDS).
 template <class P, bool FWD = false, bool TAB = false> struct EmbCfg {
     typedef typename P::wt wt;
     static constexpr bool F64 = sizeof(typename P::acc) == 8;
-    static constexpr int NW = F64 ? 4 : (FWD && !TAB ? 16 : 8);
+    static constexpr int NW = F64 ? 4 : (FWD ? (TAB ? 8 : 16) : 12);
     static constexpr int APW_MAX = F64 ? 3 : (FWD ? (TAB ? 3 : 4) : 6);
     static constexpr bool W3LDS = !F64;
     // LDS rows of staged weights: one lane's fragment per group (VPL K values; [hi lo] for split
@@ -391,11 +406,9 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
     __shared__ acc s_vec[EVEC];
     __shared__ __attribute__((aligned(16))) char s_w2[TAB ? 16 : N2P * Cfg::ROW2];
     __shared__ __attribute__((aligned(16))) char s_w3[(TAB || !W3LDS) ? 16 : N3P * Cfg::ROW3];
-    // layer outputs kept for the skip connections. z1 is stored feature-major with rows of ZS = 20
-    // (lane (p, g) touches feature f0 + 4g of neighbour p: bank 16g + p, conflict-free); z2 is
-    // neighbour-major here because the untransposed layer 3 reads it as (neighbour 4g + r, feature p).
-    __shared__ acc s_z1[TAB ? 1 : NW][E0][ZS];
-    __shared__ acc s_z2[TAB ? 1 : NW][16][E1 + 2];
+    // layer-2 outputs for the skip into layer 3, neighbour-major: the untransposed layer 3 reads
+    // them as (neighbour orow(g, r), row of the lane's column); the layer-1 skip stays in registers
+    __shared__ acc s_z2[TAB ? 1 : NW][16][Z2S];
     __shared__ acc s_R[NW][16][4];
     __shared__ double s_x[NW][16];
 
@@ -490,19 +503,18 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
                     if (g == 0 && valid && (s < 0.0 || s > A.tab_nint * A.tab_dx))
                         atomicAdd(&A.stats->table_oor, 1ull);
                 } else {
-                    // layer 1 (1 -> 25) straight into the B operand of layer 2
+                    // layer 1 (1 -> 25) straight into the B operand of layer 2 (register u = c VPL + v;
+                    // padding rows have zero weights and give exact zeros)
                     frag B1[Cfg::NC1];
+                    acc z1[Cfg::NC1 * P::VPL];
+#pragma unroll
                     for (int c = 0; c < Cfg::NC1; ++c) {
-                        acc zz[P::VPL];
+#pragma unroll
                         for (int v = 0; v < P::VPL; ++v) {
                             const int k = P::kidx(c, g, v);
-                            zz[v] = 0;
-                            if (k < E0) {
-                                zz[v] = s_vec[EV_WH1 + k] * P::act((acc)s * s_vec[EV_W1 + k] + s_vec[EV_B1 + k]);
-                                s_z1[wave][k][p] = zz[v];
-                            }
+                            z1[c * P::VPL + v] = s_vec[EV_WH1 + k] * P::act((acc)s * s_vec[EV_W1 + k] + s_vec[EV_B1 + k]);
                         }
-                        B1[c] = P::make(zz);
+                        B1[c] = P::make(&z1[c * P::VPL]);
                     }
                     // layer 2 (25 -> 50), transposed: pre2^T = W2^T z1^T
                     accv acc2[4];
@@ -512,15 +524,15 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
                             P::mma(acc2[t], lds_frag<P>(s_w2, Cfg::ROW2, 16 * t + c16, 4 * c + g), B1[c]);
                     }
                     wave_sync();
+                    // skip: register u = 4t + r of layer 2 adds register u / 2 of layer 1 (same lane)
                     acc zt[4][4];
+#pragma unroll
                     for (int t = 0; t < 4; ++t)
+#pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int n = 16 * t + P::orow(g, r);
-                            zt[t][r] = 0;
-                            if (n < E1) {
-                                zt[t][r] = s_vec[EV_WH2 + n] * P::act_b(acc2[t][r], s_vec[EV_B2 + n]) + s_z1[wave][n % E0][p];
-                                s_z2[wave][p][n] = zt[t][r];
-                            }
+                            zt[t][r] = s_vec[EV_WH2 + n] * P::act_b(acc2[t][r], s_vec[EV_B2 + n]) + z1[(4 * t + r) >> 1];
+                            s_z2[wave][p][n] = zt[t][r];
                         }
                     // output tiles -> K-chunks of layer 3: chunk c, value v is tile c*KC/16 + v/4, row r = v%4
                     frag A3[Cfg::NC2];
@@ -542,15 +554,19 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
                     wave_sync();
                     if constexpr (!Cfg::F64)
                         for (int r = 0; r < 4; ++r) Rq[r] = s_R[wave][P::orow(g, r)][c16 & 3];
-                    // G = w_hat tanh(pre3 + b) + {z2, z2}; contraction T += G^T R (features past
-                    // 100 have zero weights, finite G, and rows of T that are never stored)
+                    // G = w_hat tanh(pre3 + b) + z2 at the skip source of row m = 16 tm + c16 (its
+                    // register u in lane group ogrp(c16) takes layer-2 register u / 2 of that group);
+                    // contraction T += G^T R (padding rows have zero weights, G = 0, and are not stored)
+                    const int gc = P::ogrp(c16), rc = P::oreg(c16);
                     for (int tm = 0; tm < 7; ++tm) {
                         const int m = 16 * tm + c16;
-                        if (Cfg::F64 && m >= E2) continue;
+                        if (Cfg::F64 && emb_feat(3, gc, 4 * tm + rc) < 0) continue;
+                        const int u2 = (4 * tm + rc) >> 1;
+                        const int n2 = 16 * (u2 >> 2) + P::orow(gc, u2 & 3);
                         const acc wh = s_vec[EV_WH3 + m], bb = s_vec[EV_B3 + m];
                         for (int r = 0; r < 4; ++r) {
                             const int q = P::orow(g, r);
-                            const acc G = wh * P::act_b(acc3[tm][r], bb) + s_z2[wave][q][m % E1];
+                            const acc G = wh * P::act_b(acc3[tm][r], bb) + s_z2[wave][q][n2];
                             add_G(tm, r, q, G);
                         }
                     }
@@ -559,18 +575,22 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
                     // T accumulates over the neighbour-type passes (lane group g owns component
                     // ksel(g) of row 16 tm + c16); the earlier passes' sum is read only here, so
                     // that it holds no registers during the network
+                    // (row 16 tm + c16 is feature f: the same row for the table, the skip-aligned
+                    // order for the network; f < 0 is a padding row)
+                    const int gc = P::ogrp(c16), rc = P::oreg(c16);
+                    auto feat = [&](int tm) { return TAB ? (16 * tm + c16 < E2 ? 16 * tm + c16 : -1) : emb_feat(3, gc, 4 * tm + rc); };
                     acc Tprev[7];
                     for (int tm = 0; tm < 7; ++tm) {
-                        const int m = 16 * tm + c16;
-                        Tprev[tm] = (tj > 0 && m < E2) ? Tout[((size_t)ca * E2 + m) * 4 + ksel(g)] : (acc)0;
+                        const int f = feat(tm);
+                        Tprev[tm] = (tj > 0 && f >= 0) ? Tout[((size_t)ca * E2 + f) * 4 + ksel(g)] : (acc)0;
                     }
                     // sum the four lane groups (they hold different neighbours) and store T
                     for (int tm = 0; tm < 7; ++tm) {
                         const acc tv[4] = {Tacc[tm][0], Tacc[tm][1], Tacc[tm][2], Tacc[tm][3]};
                         const acc v = sum_groups4(tv);
-                        const int m = 16 * tm + c16;
-                        if (m < E2)
-                            Tout[((size_t)ca * E2 + m) * 4 + ksel(g)] = v * (acc)A.inv_nc + Tprev[tm];
+                        const int f = feat(tm);
+                        if (f >= 0)
+                            Tout[((size_t)ca * E2 + f) * 4 + ksel(g)] = v * (acc)A.inv_nc + Tprev[tm];
                     }
                 }
             }
@@ -600,22 +620,19 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
     __shared__ acc s_vec[EVEC];
     __shared__ __attribute__((aligned(16))) char s_w2[TAB ? 16 : N2P * Cfg::ROW2];
     __shared__ __attribute__((aligned(16))) char s_w3[(TAB || !W3LDS) ? 16 : N3P * Cfg::ROW3];
-    // layer outputs and their s-derivatives for the skip connections, feature-major with rows of
-    // ZS = 20: every access is lane (p, g) -> feature f0 + 4g of neighbour p, bank 16g + p
-    __shared__ acc s_z1[TAB ? 1 : NW][E0][ZS];
-    __shared__ acc s_z1d[TAB ? 1 : NW][E0][ZS];
-    __shared__ acc s_z2[TAB ? 1 : NW][E1][ZS];
-    __shared__ acc s_z2d[TAB ? 1 : NW][E1][ZS];
-    __shared__ __attribute__((aligned(16))) acc s_dT[NW][E2][4];
-    __shared__ double s_vir[NW][9];
+    // dT of the wave's current atom by layer-3 row (the feature's row position; padding rows zero)
+    __shared__ __attribute__((aligned(16))) acc s_dT[NW][N3P][4];
+    // per neighbour column of a wave: [0, 3) the centre atom's force over its pairs, [3, 12) the
+    // virial sum -g r^T over the wave's pairs (kept here rather than in every lane's registers)
+    __shared__ __attribute__((aligned(16))) double s_pair[NW][16][12];
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar registers)
     const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    for (int e = lane; e < N3P * 4; e += 64) s_dT[wave][e >> 2][e & 3] = 0;
+    for (int e = lane; e < 16 * 12; e += 64) s_pair[wave][e / 12][e % 12] = 0.0;
     const double inv_w = 1.0 / (A.rc - A.rs);
     const int a0 = blockIdx.x * APB;
     const int a1 = min(a0 + APB, A.natoms);
-    double vir[9];
-    for (int k = 0; k < 9; ++k) vir[k] = 0.0;
     const int nets = A.type_one_side ? A.ntypes : A.ntypes * A.ntypes;
     const acc* dTin = reinterpret_cast<const acc*>(A.dT);
     const int t_lo = a0 < a1 ? A.itype[a0] : 0, t_hi = a0 < a1 ? A.itype[a1 - 1] : -1;
@@ -641,7 +658,6 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                 const int e = lane + 64 * q;
                 pdT[q] = (w.have && e < E2 * 4) ? dTin[(size_t)w.a * E2 * 4 + e] : (acc)0;
             }
-            double Fi[3] = {0.0, 0.0, 0.0};
             while (w.have) {
                 const double x = w.px, y = w.py, z = w.pz;
                 const int jn = w.pj;
@@ -656,11 +672,17 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                 }
                 w.fetch<true>(A, tj, c16);
                 if (cc0 == 0) {
-                    // the prefetched dT of this atom goes to LDS; the next atom's is requested
+                    // the prefetched dT of this atom goes to LDS, feature f to its layer-3 row; the
+                    // next atom's is requested
                     wave_sync();
                     for (int q = 0; q < DTL; ++q) {
-                        const int e = lane + 64 * q;
-                        if (e < E2 * 4) s_dT[wave][e >> 2][e & 3] = pdT[q];
+                        const int e = lane + 64 * q, f = e >> 2;
+                        if (e < E2 * 4) {
+                            int gf = 0, uf = 0;
+                            emb_reg3(f, gf, uf);
+                            const int row = TAB ? f : 16 * (uf >> 2) + P::orow(gf, uf & 3);
+                            s_dT[wave][row][e & 3] = pdT[q];
+                        }
                     }
                     wave_sync();
                 }
@@ -679,8 +701,6 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                     ir = 1.0 / r;
                     switch_fn(r, ir, A.rs, A.rc, inv_w, s, ds);
                 }
-                const double ux = x * ir, uy = y * ir, uz = z * ir, sr = s * ir;
-                const acc Ra[4] = {(acc)s, (acc)(sr * x), (acc)(sr * y), (acc)(sr * z)};
                 acc dR[4] = {0, 0, 0, 0}, H[4] = {0, 0, 0, 0};
                 if (TAB) {
                     int li = (int)floor(s / A.tab_dx);
@@ -700,26 +720,22 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                             }
                         }
                 } else {
-                    wave_sync();
-                    // layer 1 and its derivative d/ds
+                    // layer 1 and its derivative d/ds (register u = c VPL + v; padding rows have zero
+                    // weights and give exact zeros)
                     frag B1[Cfg::NC1], B1d[Cfg::NC1];
+                    acc z1[Cfg::NC1 * P::VPL], z1d[Cfg::NC1 * P::VPL];
+#pragma unroll
                     for (int c = 0; c < Cfg::NC1; ++c) {
-                        acc zz[P::VPL], zd[P::VPL];
+#pragma unroll
                         for (int v = 0; v < P::VPL; ++v) {
                             const int k = P::kidx(c, g, v);
-                            zz[v] = 0;
-                            zd[v] = 0;
-                            if (k < E0) {
-                                const acc w1 = s_vec[EV_W1 + k], wh = s_vec[EV_WH1 + k];
-                                const acc t1 = P::act((acc)s * w1 + s_vec[EV_B1 + k]);
-                                zz[v] = wh * t1;
-                                zd[v] = wh * (1 - t1 * t1) * w1;
-                                s_z1[wave][k][p] = zz[v];
-                                s_z1d[wave][k][p] = zd[v];
-                            }
+                            const acc w1 = s_vec[EV_W1 + k], wh = s_vec[EV_WH1 + k];
+                            const acc t1 = P::act((acc)s * w1 + s_vec[EV_B1 + k]);
+                            z1[c * P::VPL + v] = wh * t1;
+                            z1d[c * P::VPL + v] = wh * (1 - t1 * t1) * w1;
                         }
-                        B1[c] = P::make(zz);
-                        B1d[c] = P::make(zd);
+                        B1[c] = P::make(&z1[c * P::VPL]);
+                        B1d[c] = P::make(&z1d[c * P::VPL]);
                     }
                     accv acc2[4], acc2d[4];
                     for (int t = 0; t < 4; ++t) {
@@ -731,21 +747,17 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                             P::mma(acc2d[t], W, B1d[c]);
                         }
                     }
-                    wave_sync();
+                    // skip: register u = 4t + rr of layer 2 adds register u / 2 of layer 1 (same lane)
                     acc zt[4][4], ztd[4][4];
+#pragma unroll
                     for (int t = 0; t < 4; ++t)
+#pragma unroll
                         for (int rr = 0; rr < 4; ++rr) {
-                            const int n = 16 * t + P::orow(g, rr);
-                            zt[t][rr] = 0;
-                            ztd[t][rr] = 0;
-                            if (n < E1) {
-                                const acc t2 = P::act_b(acc2[t][rr], s_vec[EV_B2 + n]);
-                                const acc wh = s_vec[EV_WH2 + n];
-                                zt[t][rr] = wh * t2 + s_z1[wave][n % E0][p];
-                                ztd[t][rr] = wh * (1 - t2 * t2) * acc2d[t][rr] + s_z1d[wave][n % E0][p];
-                                s_z2[wave][n][p] = zt[t][rr];
-                                s_z2d[wave][n][p] = ztd[t][rr];
-                            }
+                            const int n = 16 * t + P::orow(g, rr), u1 = (4 * t + rr) >> 1;
+                            const acc t2 = P::act_b(acc2[t][rr], s_vec[EV_B2 + n]);
+                            const acc wh = s_vec[EV_WH2 + n];
+                            zt[t][rr] = wh * t2 + z1[u1];
+                            ztd[t][rr] = wh * (1 - t2 * t2) * acc2d[t][rr] + z1d[u1];
                         }
                     // output tiles -> K-chunks of layer 3 (chunk c, value v: tile c*KC/16 + v/4, row v%4)
                     frag B3[Cfg::NC2], B3d[Cfg::NC2];
@@ -758,34 +770,60 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                         B3[c] = P::make(x);
                         B3d[c] = P::make(xd);
                     }
-                    // layer 3 transposed: one neighbour per lane column
-                    accv acc3[7], acc3d[7];
-                    for (int tm = 0; tm < 7; ++tm) {
-                        zero4(acc3[tm]);
-                        zero4(acc3d[tm]);
+                    // layer 3 transposed (one neighbour per lane column), one output tile at a time:
+                    // the products of tile tm + 1 are issued before the epilogue of tile tm, so only
+                    // two tiles of accumulators are live
+                    auto mm3 = [&](int tm, accv& o, accv& od) {
+                        zero4(o);
+                        zero4(od);
+#pragma unroll
                         for (int c = 0; c < Cfg::NC2; ++c) {
                             const frag W = W3LDS ? lds_frag<P>(s_w3, Cfg::ROW3, 16 * tm + c16, 4 * c + g)
                                                  : P::load(gw3 + (16 * tm + c16) * N2P + P::KC * c + P::VPL * g, gpl);
-                            P::mma(acc3[tm], W, B3[c]);
-                            P::mma(acc3d[tm], W, B3d[c]);
+                            P::mma(o, W, B3[c]);
+                            P::mma(od, W, B3d[c]);
                         }
-                    }
-                    wave_sync();
-                    for (int tm = 0; tm < 7; ++tm)
+                    };
+                    f4 dRq, Hq;   // FP32 paths: the contraction's accumulators (see outer4)
+                    // skip: register u = 4 tm + rr of layer 3 adds register u / 2 of layer 2 (same
+                    // lane); padding rows give G = Gd = 0 against zero rows of dT
+                    auto epi3 = [&](int tm, const accv& o, const accv& od) {
+#pragma unroll
                         for (int rr = 0; rr < 4; ++rr) {
-                            const int m = 16 * tm + P::orow(g, rr);
-                            if (m >= E2) continue;
-                            const acc t3 = P::act_b(acc3[tm][rr], s_vec[EV_B3 + m]);
+                            const int m = 16 * tm + P::orow(g, rr), u2 = (4 * tm + rr) >> 1;
+                            const acc t3 = P::act_b(o[rr], s_vec[EV_B3 + m]);
                             const acc wh = s_vec[EV_WH3 + m];
-                            const acc G = wh * t3 + s_z2[wave][m % E1][p];
-                            const acc Gd = wh * (1 - t3 * t3) * acc3d[tm][rr] + s_z2d[wave][m % E1][p];
-                            const acc* dt = s_dT[wave][m];
-                            dR[0] += G * dt[0]; dR[1] += G * dt[1]; dR[2] += G * dt[2]; dR[3] += G * dt[3];
-                            H[0] += Gd * dt[0]; H[1] += Gd * dt[1]; H[2] += Gd * dt[2]; H[3] += Gd * dt[3];
+                            const acc G = wh * t3 + zt[u2 >> 2][u2 & 3];
+                            const acc Gd = wh * (1 - t3 * t3) * od[rr] + ztd[u2 >> 2][u2 & 3];
+                            if constexpr (Cfg::F64) {
+                                const acc* dt = s_dT[wave][m];
+                                dR[0] += G * dt[0]; dR[1] += G * dt[1]; dR[2] += G * dt[2]; dR[3] += G * dt[3];
+                                H[0] += Gd * dt[0]; H[1] += Gd * dt[1]; H[2] += Gd * dt[2]; H[3] += Gd * dt[3];
+                            } else {
+                                // rank-1 updates on the matrix cores: every lane of a quad has the
+                                // same row m, so register k gains dT[m][k] G (and dT[m][k] Gd)
+                                const acc dtq = s_dT[wave][m][lane & 3];
+                                outer4(dRq, dtq, G);
+                                outer4(Hq, dtq, Gd);
+                            }
                         }
+                    };
+                    zero4(dRq);
+                    zero4(Hq);
+                    accv a3[2], a3d[2];
+                    mm3(0, a3[0], a3d[0]);
+#pragma unroll
+                    for (int tm = 0; tm < 7; ++tm) {
+                        if (tm + 1 < 7) mm3(tm + 1, a3[(tm + 1) & 1], a3d[(tm + 1) & 1]);
+                        epi3(tm, a3[tm & 1], a3d[tm & 1]);
+                    }
+                    if constexpr (!Cfg::F64)
+                        for (int k = 0; k < 4; ++k) { dR[k] = dRq[k]; H[k] = Hq[k]; }
                 }
                 // column sums over the lane groups (they hold different rows m): dR component ksel(g)
                 // in lane group g, gathered into group 0; sum_k H_k R_k as one value
+                const double ux = x * ir, uy = y * ir, uz = z * ir, sr = s * ir;
+                const acc Ra[4] = {(acc)s, (acc)(sr * x), (acc)(sr * y), (acc)(sr * z)};
                 const acc dRg = sum_groups4(dR);
                 const acc hR = sum_groups(H[0] * Ra[0] + H[1] * Ra[1] + H[2] * Ra[2] + H[3] * Ra[3]);
                 const acc dR2 = __shfl(dRg, c16 + 16), dR1 = __shfl(dRg, c16 + 32), dR3 = __shfl(dRg, c16 + 48);
@@ -800,54 +838,43 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                     unsafeAtomicAdd(&A.F[3 * (size_t)jn], -gx);
                     unsafeAtomicAdd(&A.F[3 * (size_t)jn + 1], -gy);
                     unsafeAtomicAdd(&A.F[3 * (size_t)jn + 2], -gz);
-                    Fi[0] += gx; Fi[1] += gy; Fi[2] += gz;
-                    vir[0] -= gx * x; vir[1] -= gx * y; vir[2] -= gx * z;
-                    vir[3] -= gy * x; vir[4] -= gy * y; vir[5] -= gy * z;
-                    vir[6] -= gz * x; vir[7] -= gz * y; vir[8] -= gz * z;
+                    double* pa = s_pair[wave][p];
+                    pa[0] += gx; pa[1] += gy; pa[2] += gz;
+                    pa[3] -= gx * x; pa[4] -= gx * y; pa[5] -= gx * z;
+                    pa[6] -= gy * x; pa[7] -= gy * y; pa[8] -= gy * z;
+                    pa[9] -= gz * x; pa[10] -= gz * y; pa[11] -= gz * z;
                 }
                 if (last) {
-                    for (int k = 0; k < 3; ++k) {
-                        double v = Fi[k];
+                    // the centre atom's force (and, for batched frames, its share of the virial:
+                    // one wave owns the atom in every pass) summed over the 16 columns
+                    wave_sync();
+                    const int nk = A.vir_atom ? 12 : 3;
+                    for (int k = 0; k < nk; ++k) {
+                        double v = s_pair[wave][c16][k];
                         v += __shfl_xor(v, 1);
                         v += __shfl_xor(v, 2);
                         v += __shfl_xor(v, 4);
                         v += __shfl_xor(v, 8);
-                        Fi[k] = v;
-                    }
-                    if (lane == 0)
-                        for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&A.F[3 * (size_t)cac + k], Fi[k]);
-                    Fi[0] = Fi[1] = Fi[2] = 0.0;
-                    if (A.vir_atom) {
-                        // batched frames: this atom's share of the virial, kept per centre atom
-                        // (lane group 0 holds the pair terms; one wave owns the atom in every pass)
-                        for (int k = 0; k < 9; ++k) {
-                            double v = vir[k];
-                            v += __shfl_xor(v, 1);
-                            v += __shfl_xor(v, 2);
-                            v += __shfl_xor(v, 4);
-                            v += __shfl_xor(v, 8);
-                            vir[k] = 0.0;
-                            if (lane == 0) A.vir_atom[9 * (size_t)ca + k] += v;
+                        if (lane == 0) {
+                            if (k < 3) unsafeAtomicAdd(&A.F[3 * (size_t)cac + k], v);
+                            else A.vir_atom[9 * (size_t)ca + k - 3] += v;
                         }
                     }
+                    wave_sync();
+                    if (g == 0)
+                        for (int k = 0; k < nk; ++k) s_pair[wave][c16][k] = 0.0;
                 }
             }
         }
     }
-    for (int k = 0; k < 9; ++k) {
-        double v = vir[k];
-        for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
-        vir[k] = v;
-    }
-    if (lane == 0)
-        for (int k = 0; k < 9; ++k) s_vir[wave][k] = vir[k];
     __syncthreads();
-    // block partial [E, virial]: the virial over the waves, E over this block's atoms (a shuffle
-    // tree, a fixed order; single frame), and E_i in caller order if asked for
+    // block partial [E, virial]: the virial over the waves' columns, E over this block's atoms (a
+    // shuffle tree, a fixed order; single frame), and E_i in caller order if asked for
     double* part = A.vir_part + 10 * (size_t)blockIdx.x;
     if (threadIdx.x < 9) {
         double v = 0.0;
-        for (int q = 0; q < NW; ++q) v += s_vir[q][threadIdx.x];
+        for (int q = 0; q < NW; ++q)
+            for (int c = 0; c < 16; ++c) v += s_pair[q][c][3 + threadIdx.x];
         part[1 + threadIdx.x] = v;
     }
     if (A.Ei) {
