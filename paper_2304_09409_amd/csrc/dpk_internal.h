@@ -86,6 +86,18 @@ constexpr int64_t EM_W2T = 0;                          // [64][32]
 constexpr int64_t EM_W3T = N2P * K2P;                  // [112][64]
 constexpr int64_t EM_SIZE = EM_W3T + N3P * N2P;
 
+// Split BF16 of two FP32 values: hi = bf16(x) (round to nearest even), lo = bf16(x - hi), so
+// hi + lo is within 2^-17 of x. Written on two-element vectors so that each conversion is one
+// packed v_cvt_pk_bf16_f32 (two values per instruction) instead of one per value.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split_bf16x2(float x0, float x1, bf16x2_t& hi, bf16x2_t& lo)
+{
+    const f32x2_t x = {x0, x1};
+    hi = __builtin_convertvector(x, bf16x2_t);
+    lo = __builtin_convertvector(x - __builtin_convertvector(hi, f32x2_t), bf16x2_t);
+}
+
 // Geometry of the frame for neighbour search.
 struct GeomParams {
     int periodic;

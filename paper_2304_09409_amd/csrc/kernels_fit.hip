@@ -85,9 +85,11 @@ __device__ __forceinline__ void st_half(__bf16* f, int lane, int half, const flo
 {
     bf4 hi, lo;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        hi[r] = (__bf16)x[r];
-        lo[r] = (__bf16)(x[r] - (float)hi[r]);
+    for (int r = 0; r < 4; r += 2) {
+        bf16x2_t h, l;
+        split_bf16x2(x[r], x[r + 1], h, l);
+        hi[r] = h[0]; hi[r + 1] = h[1];
+        lo[r] = l[0]; lo[r + 1] = l[1];
     }
     *reinterpret_cast<bf4*>(f + lane * 8 + half * 4) = hi;
     if constexpr (SPLIT) *reinterpret_cast<bf4*>(f + 512 + lane * 8 + half * 4) = lo;

@@ -89,12 +89,6 @@ __device__ __forceinline__ float tanh_scaled(float y)
 }
 __device__ __forceinline__ float tanh_fast(float x) { return tanh_scaled(x * TANH_K); }
 
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo)
-{
-    hi = (__bf16)x;
-    lo = (__bf16)(x - (float)hi);
-}
-
 // Split BF16 on v_mfma_f32_16x16x32_bf16: each FP32 operand is hi + lo with both parts BF16; the
 // product is formed as lo*hi + hi*lo + hi*hi with FP32 accumulation, about 16 significant bits per
 // operand. Lane group g supplies K values 8g..8g+7 of a 32-wide chunk; they are the logical
@@ -118,11 +112,11 @@ struct PMIX {
     __device__ static frag make(const acc* x) {
         frag f;
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            __bf16 h, l;
-            split_bf16(x[v], h, l);
-            f.h[v] = h;
-            f.l[v] = l;
+        for (int v = 0; v < 8; v += 2) {
+            bf16x2_t h, l;
+            split_bf16x2(x[v], x[v + 1], h, l);
+            f.h[v] = h[0]; f.h[v + 1] = h[1];
+            f.l[v] = l[0]; f.l[v + 1] = l[1];
         }
         return f;
     }
@@ -164,7 +158,11 @@ struct PBF16 {
     __device__ static frag make(const acc* x) {
         frag f;
 #pragma unroll
-        for (int v = 0; v < 8; ++v) f.h[v] = (__bf16)x[v];
+        for (int v = 0; v < 8; v += 2) {
+            const bf16x2_t h = __builtin_convertvector((f32x2_t){x[v], x[v + 1]}, bf16x2_t);
+            f.h[v] = h[0];
+            f.h[v + 1] = h[1];
+        }
         return f;
     }
     __device__ static frag load(const wt* p, int64_t) {
