@@ -116,7 +116,8 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
     constexpr int FR = XF_ELEMS;
     constexpr int TPW = (15 + NW - 1) / NW;            // feature tiles per wave (at most)
     constexpr int NWA = NW / NAT;                      // waves sharing one atom tile's D fragments
-    static_assert(NW % NAT == 0 && NW % 4 == 0, "wave layout");
+    // the dD phase splits the waves into NW / 4 atom groups of NAT / (NW / 4) atom tiles each
+    static_assert(NW % NAT == 0 && NW % 4 == 0 && NAT % (NW / 4) == 0, "wave layout");
     // B operands [K-chunk][atom tile] (layer 1: two groups of FX_G chunks); at the end the
     // per-wave dT partials (floats) of the D rows n < 16.
     __shared__ __attribute__((aligned(16))) __bf16 s_b[XF_NCH2 * NAT * FR];
