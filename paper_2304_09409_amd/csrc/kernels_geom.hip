@@ -496,6 +496,62 @@ __device__ __forceinline__ void wave_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Rank sort of count <= RANK_MAX keys held as element e = 0..EA-1 of each lane (key lane + 64 e):
+// a key's position is the number of smaller keys, counted against every stored key read once from
+// LDS (one broadcast per key, no exchange chain). The high words decide unless two are equal
+// (equal type and r^2 to 2^-47, i.e. in practice equal distances): equal ranks then collide in a
+// slot check and the ranks are recounted on the full 128-bit keys, which are unique. EA is a
+// template argument so that only the active elements are compared.
+template <int EA, int E>
+__device__ __forceinline__ void rank_keys(int count, int lane, unsigned long long* khi, unsigned long long* klo,
+                                          int* kq, unsigned long long (&kh)[E], unsigned long long (&kl)[E],
+                                          int (&kx)[E])
+{
+    int rk[EA];
+#pragma unroll
+    for (int e = 0; e < EA; ++e) rk[e] = 0;
+    for (int q = 0; q < count; ++q) {
+        const unsigned long long h = khi[q];
+#pragma unroll
+        for (int e = 0; e < EA; ++e) rk[e] += h < kh[e] ? 1 : 0;
+    }
+    wave_barrier();
+#pragma unroll
+    for (int e = 0; e < EA; ++e)
+        if (lane + 64 * e < count) kq[rk[e]] = lane + 64 * e;
+    wave_barrier();
+    bool clash = false;
+#pragma unroll
+    for (int e = 0; e < EA; ++e)
+        if (lane + 64 * e < count) clash |= kq[rk[e]] != lane + 64 * e;
+    if (__ballot(clash) != 0) {
+#pragma unroll
+        for (int e = 0; e < EA; ++e) rk[e] = 0;
+        for (int q = 0; q < count; ++q) {
+            const unsigned long long h = khi[q], l = klo[q];
+#pragma unroll
+            for (int e = 0; e < EA; ++e) rk[e] += key_less(h, l, kh[e], kl[e]) ? 1 : 0;
+        }
+    }
+    wave_barrier();
+#pragma unroll
+    for (int e = 0; e < EA; ++e)
+        if (lane + 64 * e < count) {
+            khi[rk[e]] = kh[e];
+            klo[rk[e]] = kl[e];
+            kq[rk[e]] = kx[e];
+        }
+    wave_barrier();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane + 64 * e;
+        const bool have = e < EA && i < count;
+        kh[e] = have ? khi[i] : ~0ull;
+        kl[e] = have ? klo[i] : ~0ull;
+        kx[e] = have ? kq[i] : 0;
+    }
+}
+
 // BATCH: atom a belongs to frame frame_of[a]; its geometry is gps[frame] and its bins start at
 // fd[frame].cell_off of the concatenated cell_start (candidate records hold batch-wide indices).
 template <int CAP, bool BATCH>
@@ -652,57 +708,12 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
         kl[e] = have ? klo[i] : ~0ull;
         kx[e] = have ? kq[i] : 0;
     }
+    static_assert(RANK_MAX <= 256, "rank sort dispatch covers at most four keys per lane");
     if (count <= RANK_MAX) {
-        // Rank sort (up to RANK_MAX keys): a key's position is the number of smaller keys, counted
-        // against every stored key read once from LDS (one broadcast per key, no exchange chain).
-        // The high words decide unless two are equal (equal type and r^2 to 2^-47, i.e. in practice
-        // equal distances): equal ranks then collide in a slot check and the ranks are recounted on
-        // the full 128-bit keys, which are unique.
-        int rk[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) rk[e] = 0;
-        for (int q = 0; q < count; ++q) {
-            const unsigned long long h = khi[q];
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-                if (e < EA) rk[e] += h < kh[e] ? 1 : 0;
-        }
-        wave_barrier();
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-            if (e < EA && lane + 64 * e < count) kq[rk[e]] = lane + 64 * e;
-        wave_barrier();
-        bool clash = false;
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-            if (e < EA && lane + 64 * e < count) clash |= kq[rk[e]] != lane + 64 * e;
-        if (__ballot(clash) != 0) {
-#pragma unroll
-            for (int e = 0; e < E; ++e) rk[e] = 0;
-            for (int q = 0; q < count; ++q) {
-                const unsigned long long h = khi[q], l = klo[q];
-#pragma unroll
-                for (int e = 0; e < E; ++e)
-                    if (e < EA) rk[e] += key_less(h, l, kh[e], kl[e]) ? 1 : 0;
-            }
-        }
-        wave_barrier();
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-            if (e < EA && lane + 64 * e < count) {
-                khi[rk[e]] = kh[e];
-                klo[rk[e]] = kl[e];
-                kq[rk[e]] = kx[e];
-            }
-        wave_barrier();
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int i = lane + 64 * e;
-            const bool have = e < EA && i < count;
-            kh[e] = have ? khi[i] : ~0ull;
-            kl[e] = have ? klo[i] : ~0ull;
-            kx[e] = have ? kq[i] : 0;
-        }
+        if (EA == 1) rank_keys<1>(count, lane, khi, klo, kq, kh, kl, kx);
+        else if (EA == 2) rank_keys<2>(count, lane, khi, klo, kq, kh, kl, kx);
+        else if (EA == 3) rank_keys<3>(count, lane, khi, klo, kq, kh, kl, kx);
+        else rank_keys<4>(count, lane, khi, klo, kq, kh, kl, kx);
     } else {
     // Bitonic sort of the S2 <= CAP keys in registers. Pairs 64 or more apart sit in one lane;
     // closer pairs are exchanged across lanes.
