@@ -460,7 +460,8 @@ __global__ void __launch_bounds__(PS_THREADS) k_prep_batch(const double* coord, 
 // internal index, the caller index and the type (30 + 30 + 4 bits), so one 32-B load gives
 // everything the candidate test and the output need.
 // The wave first loads the ranges of all stencil bins at once (one lane per bin) and scans their
-// sizes; it then sweeps the flat candidate range, several candidates per lane in flight.
+// sizes; it then sweeps the flat candidate range, several candidates per lane in flight (each
+// lane finds its candidate's bin by binary search in the scanned offsets).
 // Candidates within r_c are compacted into LDS as 128-bit keys that compare like
 // (type, r^2, caller index j, image n0, n1, n2):
 //   hi = type << 59 | bits(r^2) >> 5
@@ -584,20 +585,31 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
 
     // ranges of every stencil bin, scanned across the wave
     int total = 0;   // wave-uniform
+    // stencil index -> offsets: divisions by w2 and w1 w2 (at most 49) of an index below 343 as a
+    // multiply by ceil(2^16 / d) and a shift, exact in that range
+    const unsigned m2 = (65536u + w2 - 1) / w2, m12 = (65536u + w1 * w2 - 1) / (w1 * w2);
     for (int sb = 0; sb < S; sb += 64) {
         const int sidx = sb + lane;
         int cnt = 0, start = 0, code = 0;
         if (sidx < S) {
-            const int o0 = sidx / (w1 * w2) - gp.K[0];
-            const int o1 = (sidx / w2) % w1 - gp.K[1];
-            const int o2 = sidx % w2 - gp.K[2];
+            const int d12 = (int)(((unsigned)sidx * m12) >> 16), d2 = (int)(((unsigned)sidx * m2) >> 16);
+            const int o0 = d12 - gp.K[0];
+            const int o1 = d2 - d12 * w1 - gp.K[1];
+            const int o2 = sidx - d2 * w2 - gp.K[2];
             const int tg[3] = {bi[0] + o0, bi[1] + o1, bi[2] + o2};
             int nn[3], bb[3];
             bool skip = false;
             for (int c = 0; c < 3; ++c) {
                 if (gp.periodic) {
-                    int q = tg[c] / gp.nb[c];
-                    if ((tg[c] % gp.nb[c] != 0) && (tg[c] < 0)) --q;
+                    // image (floor division by the bins per axis); at least K bins per axis leave
+                    // tg within one box length of the cell, so the image is -1, 0 or 1
+                    int q;
+                    if (gp.nb[c] >= gp.K[c]) {
+                        q = tg[c] < 0 ? -1 : (tg[c] >= gp.nb[c] ? 1 : 0);
+                    } else {
+                        q = tg[c] / gp.nb[c];
+                        if ((tg[c] % gp.nb[c] != 0) && (tg[c] < 0)) --q;
+                    }
                     nn[c] = q;
                     bb[c] = tg[c] - q * gp.nb[c];
                 } else {
@@ -644,7 +656,14 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
             const int q = q0 + 64 * u + lane;
             bin[u] = -1;
             if (q < total) {
-                while (s_base[b + 1] <= q) ++b;
+                // bin of flat candidate q: the last b with s_base[b] <= q (s_base is non-decreasing
+                // with s_base[S] = total > q); q only grows, so the search starts at the last bin
+                int hi = S;
+                while (hi - b > 1) {
+                    const int mid = (b + hi) >> 1;
+                    if (s_base[mid] <= q) b = mid;
+                    else hi = mid;
+                }
                 bin[u] = b;
                 cq[u] = s_start[b] + (q - s_base[b]);
                 c4[u] = cand[cq[u]];
