@@ -251,38 +251,25 @@ template <class T> __device__ __forceinline__ T sum_groups4(const T* p)
     return q0 + q1;
 }
 
-// Switching function of Sec. II.A.1 (eq. switch) and its derivative, in the accumulation precision
-// T of the path (FP64, or FP32 in the BF16 paths), from r, ir = 1/r and inv_w = 1/(rc - rs) (no
-// division here: the caller's 1/r is the only one per neighbour).
-template <class T>
-__device__ __forceinline__ void switch_fn(T r, T ir, T rs, T rc, T inv_w, T& s, T& ds)
+// Switching function of Sec. II.A.1 (eq. switch) and its derivative, FP64, from r, ir = 1/r and
+// inv_w = 1/(rc - rs) (no division here: the caller's 1/r is the only one per neighbour).
+__device__ __forceinline__ void switch_fn(double r, double ir, double rs, double rc, double inv_w, double& s,
+                                          double& ds)
 {
     if (r < rs) {
         s = ir;
         ds = -ir * ir;
     } else if (r < rc) {
-        const T x = (r - rs) * inv_w;
-        const T x2 = x * x;
-        const T u = x2 * x * (x * ((T)15 - (T)6 * x) - (T)10) + (T)1;
-        const T du = (T)-30 * x2 * (x - (T)1) * (x - (T)1);
+        double x = (r - rs) * inv_w;
+        double x2 = x * x;
+        double u = x2 * x * (x * (15.0 - 6.0 * x) - 10.0) + 1.0;
+        double du = -30.0 * x2 * (x - 1.0) * (x - 1.0);
         s = u * ir;
         ds = du * ir * inv_w - u * ir * ir;
     } else {
-        s = 0;
-        ds = 0;
+        s = 0.0;
+        ds = 0.0;
     }
-}
-// |r| and 1/|r|: correctly rounded in FP64; the hardware square root and reciprocal (about 1 ulp)
-// in FP32, where the BF16 paths' error budget leaves ample room.
-__device__ __forceinline__ void geo_norm(double x, double y, double z, double& r, double& ir)
-{
-    r = sqrt(x * x + y * y + z * z);
-    ir = 1.0 / r;
-}
-__device__ __forceinline__ void geo_norm(float x, float y, float z, float& r, float& ir)
-{
-    r = __builtin_amdgcn_sqrtf(x * x + y * y + z * z);
-    ir = __builtin_amdgcn_rcpf(r);
 }
 
 // Row stride of the forward pass's neighbour-major layer-2 buffer (64 rows used): a multiple of 4
@@ -467,19 +454,18 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
 
                 const int p = c16;
                 const bool valid = cc0 + p < cnp;
-                // environment row R = s (1, r/|r|), in the accumulation precision
-                acc s = 0, R[4] = {0, 0, 0, 0};
+                double s = 0.0, R[4] = {0.0, 0.0, 0.0, 0.0};
                 if (valid) {
-                    const acc xa = (acc)x, ya = (acc)y, za = (acc)z;
-                    acc r, ir, ds;
-                    geo_norm(xa, ya, za, r, ir);
-                    switch_fn<acc>(r, ir, (acc)A.rs, (acc)A.rc, (acc)inv_w, s, ds);
-                    const acc sr = s * ir;
-                    R[0] = s; R[1] = sr * xa; R[2] = sr * ya; R[3] = sr * za;
+                    const double r = sqrt(x * x + y * y + z * z);
+                    const double ir = 1.0 / r;
+                    double ds;
+                    switch_fn(r, ir, A.rs, A.rc, inv_w, s, ds);
+                    const double sr = s * ir;
+                    R[0] = s; R[1] = sr * x; R[2] = sr * y; R[3] = sr * z;
                 }
                 wave_sync();
                 if (g == 0) {
-                    for (int k = 0; k < 4; ++k) s_R[wave][p][k] = R[k];
+                    for (int k = 0; k < 4; ++k) s_R[wave][p][k] = (acc)R[k];
                     s_x[wave][p] = s;
                 }
                 // T[m][k] += G_qm R_qk for feature m = 16 tm + c16 and neighbour q = orow(g, r) of this
@@ -707,14 +693,11 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
 
                 const int p = c16;
                 const bool valid = cc0 + p < cnp;
-                // geometry and (below) the chain rule in the accumulation precision; the force and
-                // virial sums stay FP64
-                const acc xa = (acc)x, ya = (acc)y, za = (acc)z;
-                acc ir = 1, s = 0, ds = 0;
+                double ir = 1.0, s = 0.0, ds = 0.0;
                 if (valid) {
-                    acc r;
-                    geo_norm(xa, ya, za, r, ir);
-                    switch_fn<acc>(r, ir, (acc)A.rs, (acc)A.rc, (acc)inv_w, s, ds);
+                    const double r = sqrt(x * x + y * y + z * z);
+                    ir = 1.0 / r;
+                    switch_fn(r, ir, A.rs, A.rc, inv_w, s, ds);
                 }
                 acc dR[4] = {0, 0, 0, 0}, H[4] = {0, 0, 0, 0};
                 if (TAB) {
@@ -837,19 +820,19 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                 }
                 // column sums over the lane groups (they hold different rows m): dR component ksel(g)
                 // in lane group g, gathered into group 0; sum_k H_k R_k as one value
-                const acc ux = xa * ir, uy = ya * ir, uz = za * ir, sr = s * ir;
-                const acc Ra[4] = {s, sr * xa, sr * ya, sr * za};
+                const double ux = x * ir, uy = y * ir, uz = z * ir, sr = s * ir;
+                const acc Ra[4] = {(acc)s, (acc)(sr * x), (acc)(sr * y), (acc)(sr * z)};
                 const acc dRg = sum_groups4(dR);
                 const acc hR = sum_groups(H[0] * Ra[0] + H[1] * Ra[1] + H[2] * Ra[2] + H[3] * Ra[3]);
                 const acc dR2 = __shfl(dRg, c16 + 16), dR1 = __shfl(dRg, c16 + 32), dR3 = __shfl(dRg, c16 + 48);
                 if (valid && g == 0) {
-                    const acc inc = (acc)A.inv_nc;
-                    const acc d0 = inc * dRg, d1 = inc * dR1, d2 = inc * dR2, d3 = inc * dR3;
-                    const acc dEds = inc * hR;
-                    const acc q = d1 * ux + d2 * uy + d3 * uz;
-                    const acc rad = (d0 + dEds) * ds + q * (ds - sr);
-                    const double gx = (double)(rad * ux + sr * d1), gy = (double)(rad * uy + sr * d2),
-                                 gz = (double)(rad * uz + sr * d3);
+                    const double inc = A.inv_nc;
+                    const double d0 = inc * (double)dRg, d1 = inc * (double)dR1;
+                    const double d2 = inc * (double)dR2, d3 = inc * (double)dR3;
+                    const double dEds = inc * (double)hR;
+                    const double q = d1 * ux + d2 * uy + d3 * uz;
+                    const double rad = (d0 + dEds) * ds + q * (ds - sr);
+                    const double gx = rad * ux + sr * d1, gy = rad * uy + sr * d2, gz = rad * uz + sr * d3;
                     unsafeAtomicAdd(&A.F[3 * (size_t)jn], -gx);
                     unsafeAtomicAdd(&A.F[3 * (size_t)jn + 1], -gy);
                     unsafeAtomicAdd(&A.F[3 * (size_t)jn + 2], -gz);
