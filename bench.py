@@ -191,6 +191,47 @@ def _serving_timed(srv, sims, reqs, rng, load, slots, budget, n_sims):
             "mean_batch_poisson": batch_poisson, "precision": "mixed"}
 
 
+def tabulated_bench(dpk, synth, torch, steps, warmup):
+    """The 32,000-atom fcc box (20^3 cells, rc 8.0 A, sel 138) with the tabulated embedding (stride
+    0.01): ms/step, atom-steps/s and stage times of the mixed and FP64 paths. Its parity with the
+    oracle's table is tested at this size; here it is timed only."""
+    c, t, b = synth.fcc_32000()
+    n = len(t)
+    model = dpk.Model(synth.FCC_MODEL, synth.fcc_params()).tabulate(0.01, 0.5)
+    dev = torch.device("cuda:0")
+    coord = torch.tensor(c, dtype=torch.float64, device=dev)
+    atype = torch.tensor(t, dtype=torch.int32, device=dev)
+    energy = torch.zeros(1, dtype=torch.float64, device=dev)
+    force = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+    virial = torch.zeros(9, dtype=torch.float64, device=dev)
+    out = {"workload": "fcc metal, 32,000 atoms (20^3 cells, a 3.6 A, jitter 0.05 A), periodic; se_e2_a rc 8.0 A, "
+                       "rc_smth 2.0 A, sel [138], tabulated embedding (stride 0.01), fitting (240,240,240,1)",
+           "atoms": n}
+    for prec in ("mixed", "fp64"):
+        ctx = dpk.Context(model, precision=prec)
+        for _ in range(warmup):
+            ctx.compute_device(coord, atype, b, energy, force, virial)
+        ctx.check()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.compute_device(coord, atype, b, energy, force, virial)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stage_ms, nframes = ctx.profile_read()
+        ctx.profile(False)
+        ctx.check()
+        ms = (t1 - t0) * 1e3 / steps
+        out[prec] = {"ms_per_step": ms, "value": n / (ms * 1e-3),
+                     "stage_ms": {k: v / nframes for k, v in stage_ms.items()},
+                     "neighbours_dropped_by_sel": ctx.stats()["nbr_dropped"]}
+        print(f"# tabulated fcc32000 {prec}: {ms:.3f} ms/step, {n / (ms * 1e-3):.4g} atom-steps/s, stages (ms) "
+              + ", ".join(f"{k} {v:.3f}" for k, v in out[prec]["stage_ms"].items()), file=sys.stderr, flush=True)
+        ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +239,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (latency) section")
+    ap.add_argument("--no-table", action="store_true", help="skip the tabulated-embedding (fcc) section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device-to-device (the reference for hardware byte counters)")
     args = ap.parse_args()
@@ -254,6 +296,8 @@ def main():
               + ", ".join(f"{k} {v:.3f}" for k, v in runs[prec]["stage_ms"].items()), file=sys.stderr, flush=True)
         ctx.close()
 
+    tabulated = None if args.no_table else tabulated_bench(dpk, synth, torch, max(1, args.steps // 2),
+                                                            max(1, args.warmup // 2))
     serving = None if args.no_serving else serving_bench(dpk, synth)
     if serving:
         print(f"# serving: p50 {serving['p50_ms']:.3f} ms, p99 {serving['p99_ms']:.3f} ms at "
@@ -324,6 +368,7 @@ def main():
         "force_error_vs_oracle": errs or None,
         "roofline": roof,
         "stage_roofline": stage_roof,
+        "tabulated": tabulated,
         "serving": serving,
         "cpu_baseline": cpu,
     }

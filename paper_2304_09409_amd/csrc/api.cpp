@@ -295,7 +295,7 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
     p = take(sizeof(int) * (MAXT + 1)); if (base) c->toff = (int*)p;
     p = take(sizeof(int) * MAXT * ((n + PREP_BLOCK - 1) / PREP_BLOCK)); if (base) c->bcount = (int*)p;
     p = take(sizeof(int) * MAXT * ((n + PREP_BLOCK - 1) / PREP_BLOCK)); if (base) c->boff = (int*)p;
-    p = take(sizeof(DevStats)); if (base) c->stats = (DevStats*)p;
+    p = take(sizeof(int) * STATS_WORDS); if (base) c->stats = (DevStats*)p;   // with the drop counters
     p = take(sizeof(double) * 3 * n); if (base) c->pos = (double*)p;
     p = take(sizeof(int) * n); if (base) c->cell_of = (int*)p;
     p = take(sizeof(int) * n); if (base) c->cell_tmp = (int*)p;
@@ -412,6 +412,9 @@ int setup_geometry(dpk_ctx* c, const double* box, const double* bbox, GeomParams
             const double* b = h + 3 * ((k + 2) % 3);
             const double cx = a[1] * b[2] - a[2] * b[1], cy = a[2] * b[0] - a[0] * b[2], cz = a[0] * b[1] - a[1] * b[0];
             const double width = det / std::sqrt(cx * cx + cy * cy + cz * cz);
+            // bins of at least r_c (a 3 x 3 x 3 stencil; bins of r_c / 2 visit less volume, 15.6 r_c^3
+            // against 27 r_c^3, but their 125-bin stencil set-up cost more than that saved on the
+            // water and fcc boxes)
             int nb = (int)std::floor(width / rc);
             if (nb < 1) nb = 1;
             if (nb > 256) nb = 256;
@@ -734,7 +737,7 @@ int compute_batch(dpk_ctx* c, int nf, const BatchFrame* fr, const double* d_coor
     launch_nlist((int)n, c->pos, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cand, gps[0], c->nl_j, c->nl_r,
                  c->nnei, c->stats, s, c->gps, c->fd, c->frame_of, ms, mc);
     run_network(c, (int)n, gps[0], c->F, c->vir_atom, false, nullptr, nullptr, s);
-    launch_finalize_batch(nf, c->fd, c->inv_perm, c->Ei, c->vir_atom, c->F, d_out, s);
+    launch_finalize_batch(nf, c->fd, c->inv_perm, c->Ei, c->vir_atom, c->F, d_out, c->stats, s);
     HIPCHK(hipGetLastError());
     c->last_stream = s;
     c->last_n = n;
@@ -921,7 +924,7 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
 
     run_network(c, n, gp, d_force, nullptr, true, d_atom_energy, ev, s);
     prof_mark(ev, DPK_STAGE_FINAL, s);
-    launch_finalize(embed_bwd_blocks(c->precision, n, c->ncu), c->vir_part, d_energy, d_virial, s);
+    launch_finalize(embed_bwd_blocks(c->precision, n, c->ncu), c->vir_part, d_energy, d_virial, c->stats, s);
     prof_mark(ev, DPK_NSTAGES, s);
     HIPCHK(hipGetLastError());
     c->last_stream = s;

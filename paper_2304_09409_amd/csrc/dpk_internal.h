@@ -123,6 +123,17 @@ struct DevStats {
     int pad;
 };
 
+// Neighbours dropped by sel are counted per atom into NL_DROP_SLOTS counters that follow the
+// statistics block in memory (atom a adds to counter a mod NL_DROP_SLOTS: one shared counter
+// serialised every atom's atomic), cleared with the block at the start of a frame and added into
+// nbr_dropped by the frame's final reduction.
+constexpr int NL_DROP_SLOTS = 256;
+constexpr int STATS_WORDS = (int)((sizeof(DevStats) + sizeof(unsigned long long) * NL_DROP_SLOTS) / 4);
+__host__ __device__ inline unsigned long long* drop_slots(DevStats* st)
+{
+    return reinterpret_cast<unsigned long long*>(st + 1);
+}
+
 // One frame of a batch evaluated in shared launches (serving).
 constexpr int BATCH_MAX_FRAMES = 64;
 struct FrameDesc {

@@ -29,7 +29,7 @@ void launch_batch_prep(int nframes, int ntypes, const double* coord, const int* 
                        DevStats* st, double* pos, int* cell_of, int* cell_start, double4* cand, double* f_int,
                        double* vir_atom, hipStream_t s);
 void launch_finalize_batch(int nframes, const FrameDesc* fd, const int* inv_perm, const double* ei,
-                           const double* vir_atom, const double* f_int, double* out, hipStream_t s);
+                           const double* vir_atom, const double* f_int, double* out, DevStats* st, hipStream_t s);
 int prep_small_max_atoms();
 int prep_small_max_cells();
 void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s);
@@ -39,8 +39,9 @@ void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* ou
 // over launch shapes (workspace sizing)
 int embed_bwd_blocks(int precision, int64_t natoms, int ncu);
 int64_t embed_bwd_max_blocks(int precision, int64_t natoms);
-// E and the virial of a single frame from the backward pass's nb partials [E, virial[9]]
-void launch_finalize(int nb, const double* part, double* energy, double* virial, hipStream_t s);
+// E and the virial of a single frame from the backward pass's nb partials [E, virial[9]], and the
+// frame's dropped-neighbour count into st
+void launch_finalize(int nb, const double* part, double* energy, double* virial, DevStats* st, hipStream_t s);
 int fit_atoms_per_block(int precision);
 void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s);
 void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s);

@@ -108,7 +108,8 @@ __device__ __forceinline__ void prep_frame(int f, int n, int atom_off, const dou
     __shared__ int s_part[PS_THREADS];         // scan partials
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (!BATCH && tid < (int)(sizeof(DevStats) / 4)) reinterpret_cast<int*>(st)[tid] = 0;
+    if (!BATCH)
+        for (int w = tid; w < STATS_WORDS; w += PS_THREADS) reinterpret_cast<int*>(st)[w] = 0;
     for (int c = tid; c < ncell; c += PS_THREADS) s_cnt[c] = 0;
     if (BATCH && tid < ntypes) s_base[tid] = type_base[tid];
     __syncthreads();   // the statistics block is zero before anything raises a flag in it
@@ -314,7 +315,7 @@ __global__ void __launch_bounds__(1024) k_prep_scan(int nblocks, int ntypes, con
     __shared__ int part[1024];
     __shared__ int carry;
     const int tid = threadIdx.x;
-    if (tid < (int)(sizeof(DevStats) / 4)) reinterpret_cast<int*>(st)[tid] = 0;
+    for (int w = tid; w < STATS_WORDS; w += (int)blockDim.x) reinterpret_cast<int*>(st)[w] = 0;
     // types: block offsets within each type (type t's atoms follow those of types < t)
     int acc = 0;
     for (int t = 0; t < ntypes; ++t) {
@@ -422,7 +423,7 @@ __global__ void __launch_bounds__(256) k_batch_count(const int* atype, int ntype
 // batch, frames in order within a type); zeroes the statistics block of the batch.
 __global__ void k_batch_scan(int nframes, int ntypes, FrameDesc* fd, int* tcount, int* toff, DevStats* st)
 {
-    if (threadIdx.x < (int)(sizeof(DevStats) / 4)) reinterpret_cast<int*>(st)[threadIdx.x] = 0;
+    for (int w = threadIdx.x; w < STATS_WORDS; w += (int)blockDim.x) reinterpret_cast<int*>(st)[w] = 0;
     __syncthreads();
     if (threadIdx.x != 0) return;
     int acc = 0, bad = 0;
@@ -497,20 +498,27 @@ __device__ __forceinline__ void wave_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Rank sort of count <= RANK_MAX keys held as element e = 0..EA-1 of each lane (key lane + 64 e):
-// a key's position is the number of smaller keys, counted against every stored key read once from
-// LDS (one broadcast per key, no exchange chain). The high words decide unless two are equal
+// Rank sort of count <= RANK_MAX keys in LDS, EA = ceil(count / 64) of them per lane (key lane +
+// 64 e): a key's position is the number of smaller keys, counted against every stored key read once
+// from LDS (one broadcast per key, no exchange chain). The high words decide unless two are equal
 // (equal type and r^2 to 2^-47, i.e. in practice equal distances): equal ranks then collide in a
-// slot check and the ranks are recounted on the full 128-bit keys, which are unique. EA is a
-// template argument so that only the active elements are compared.
-template <int EA, int E>
+// slot check and the ranks are recounted on the full 128-bit keys, which are unique. The keys end
+// sorted in LDS.
+template <int EA>
 __device__ __forceinline__ void rank_keys(int count, int lane, unsigned long long* khi, unsigned long long* klo,
-                                          int* kq, unsigned long long (&kh)[E], unsigned long long (&kl)[E],
-                                          int (&kx)[E])
+                                          int* kq)
 {
-    int rk[EA];
+    unsigned long long kh[EA], kl[EA];
+    int kx[EA], rk[EA];
 #pragma unroll
-    for (int e = 0; e < EA; ++e) rk[e] = 0;
+    for (int e = 0; e < EA; ++e) {
+        const int i = lane + 64 * e;
+        const bool have = i < count;
+        kh[e] = have ? khi[i] : ~0ull;
+        kl[e] = have ? klo[i] : ~0ull;
+        kx[e] = have ? kq[i] : 0;
+        rk[e] = 0;
+    }
     for (int q = 0; q < count; ++q) {
         const unsigned long long h = khi[q];
 #pragma unroll
@@ -543,14 +551,36 @@ __device__ __forceinline__ void rank_keys(int count, int lane, unsigned long lon
             kq[rk[e]] = kx[e];
         }
     wave_barrier();
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = lane + 64 * e;
-        const bool have = e < EA && i < count;
-        kh[e] = have ? khi[i] : ~0ull;
-        kl[e] = have ? klo[i] : ~0ull;
-        kx[e] = have ? kq[i] : 0;
+}
+
+// Bitonic sort in LDS of count keys (padded to a power of two with keys that order last): the path
+// for more than RANK_MAX atoms within r_c, rare, kept out of registers so that the buffer size does
+// not set the kernel's register count.
+__device__ void bitonic_keys_lds(int count, int lane, unsigned long long* khi, unsigned long long* klo, int* kq)
+{
+    int n2 = 64;
+    while (n2 < count) n2 <<= 1;
+    for (int i = count + lane; i < n2; i += 64) {
+        khi[i] = ~0ull;
+        klo[i] = ~0ull;
+        kq[i] = 0;
     }
+    wave_barrier();
+    for (int k = 2; k <= n2; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int p = lane; p < (n2 >> 1); p += 64) {
+                const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));   // p with a zero bit inserted at j
+                const int l = i | j;
+                const bool up = (i & k) == 0;
+                const unsigned long long ih = khi[i], il = klo[i], lh = khi[l], ll = klo[l];
+                if (key_less(lh, ll, ih, il) == up) {
+                    const int ix = kq[i];
+                    khi[i] = lh; klo[i] = ll; kq[i] = kq[l];
+                    khi[l] = ih; klo[l] = il; kq[l] = ix;
+                }
+            }
+            wave_barrier();
+        }
 }
 
 // BATCH: atom a belongs to frame frame_of[a]; its geometry is gps[frame] and its bins start at
@@ -711,68 +741,17 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
     }
     const bool overflow = count > CAP;   // wave-uniform; the frame is flagged and its list incomplete
     if (overflow) count = CAP;
-    int S2 = 64;
-    while (S2 < count) S2 <<= 1;
     __syncthreads();
-    // Element e of this lane is key lane + 64 e; the keys are then put in order.
-    constexpr int E = CAP / 64;
-    const int EA = S2 >> 6;   // active elements per lane
-    unsigned long long kh[E], kl[E];
-    int kx[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = lane + 64 * e;
-        const bool have = i < count;
-        kh[e] = have ? khi[i] : ~0ull;
-        kl[e] = have ? klo[i] : ~0ull;
-        kx[e] = have ? kq[i] : 0;
-    }
+    // the keys are put in order in LDS
     static_assert(RANK_MAX <= 256, "rank sort dispatch covers at most four keys per lane");
     if (count <= RANK_MAX) {
-        if (EA == 1) rank_keys<1>(count, lane, khi, klo, kq, kh, kl, kx);
-        else if (EA == 2) rank_keys<2>(count, lane, khi, klo, kq, kh, kl, kx);
-        else if (EA == 3) rank_keys<3>(count, lane, khi, klo, kq, kh, kl, kx);
-        else rank_keys<4>(count, lane, khi, klo, kq, kh, kl, kx);
+        const int ER = (count + 63) >> 6;
+        if (ER <= 1) rank_keys<1>(count, lane, khi, klo, kq);
+        else if (ER == 2) rank_keys<2>(count, lane, khi, klo, kq);
+        else if (ER == 3) rank_keys<3>(count, lane, khi, klo, kq);
+        else rank_keys<4>(count, lane, khi, klo, kq);
     } else {
-    // Bitonic sort of the S2 <= CAP keys in registers. Pairs 64 or more apart sit in one lane;
-    // closer pairs are exchanged across lanes.
-    for (int k = 2; k <= S2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j >= 64) {
-#pragma unroll
-                for (int eb = 1; eb < E; eb <<= 1) {
-                    if (eb != (j >> 6)) continue;
-#pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        if ((e & eb) || e >= EA) continue;
-                        const int f = e | eb;
-                        const bool up = ((lane + 64 * e) & k) == 0;
-                        if (key_less(kh[f], kl[f], kh[e], kl[e]) == up) {
-                            const unsigned long long th = kh[e], tl = kl[e];
-                            const int tx = kx[e];
-                            kh[e] = kh[f]; kl[e] = kl[f]; kx[e] = kx[f];
-                            kh[f] = th; kl[f] = tl; kx[f] = tx;
-                        }
-                    }
-                }
-            } else {
-                const bool lower = (lane & j) == 0;
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    if (e >= EA) continue;
-                    const unsigned long long ph = __shfl_xor(kh[e], j), pl = __shfl_xor(kl[e], j);
-                    const int px = __shfl_xor(kx[e], j);
-                    const bool up = ((lane + 64 * e) & k) == 0;
-                    const bool take = (lower == up) ? key_less(ph, pl, kh[e], kl[e]) : key_less(kh[e], kl[e], ph, pl);
-                    if (take) {
-                        kh[e] = ph;
-                        kl[e] = pl;
-                        kx[e] = px;
-                    }
-                }
-            }
-        }
-    }
+        bitonic_keys_lds(count, lane, khi, klo, kq);
     }
     // per-type counts of the sorted keys: every hit, unless the buffer overflowed; then only the
     // stored hits count, so that each type block starts where its keys do and every slot the
@@ -782,9 +761,10 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
     if (overflow) {
         for (int t = 0; t < gp.ntypes; ++t) {
             int c = 0;
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-                c += __popcll(__ballot(lane + 64 * e < count && (int)(kh[e] >> 59) == t));
+            for (int q0 = 0; q0 < count; q0 += 64) {
+                const int q = q0 + lane;
+                c += __popcll(__ballot(q < count && (int)(khi[q] >> 59) == t));
+            }
             tsorted[t] = c;
         }
     }
@@ -797,16 +777,14 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
         drops += tcount[t] - kept[t];
     }
     const size_t rowj = (size_t)a * gp.nc;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int q = lane + 64 * e;
-        if (q >= count) continue;
-        const int t = (int)(kh[e] >> 59);
+    for (int q = lane; q < count; q += 64) {
+        const unsigned long long kh = khi[q], kl = klo[q];
+        const int t = (int)(kh >> 59);
         const int rank = q - tstart[t];
         if (rank < gp.sel[t]) {
-            const int code = (int)(kl[e] & ((1ull << 21) - 1));
+            const int code = (int)(kl & ((1ull << 21) - 1));
             const int n0 = (code >> 14) - 64, n1 = ((code >> 7) & 127) - 64, n2 = (code & 127) - 64;
-            const double4 c4 = cand[kx[e]];
+            const double4 c4 = cand[kq[q]];
             const int j = (int)((__double_as_longlong(c4.w) >> 30) & 0x3fffffffll);   // caller index
             double sh[3];
             image_shift(gp, n0, n1, n2, sh);
@@ -826,7 +804,7 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
         }
     }
     if (lane < gp.ntypes) nnei[(size_t)a * gp.ntypes + lane] = kept[lane];
-    if (lane == 0 && drops) atomicAdd(&st->nbr_dropped, (unsigned long long)drops);
+    if (lane == 0 && drops) atomicAdd(drop_slots(st) + (a & (NL_DROP_SLOTS - 1)), (unsigned long long)drops);
 }
 
 // ---- reductions and output ----------------------------------------------------------------
@@ -846,8 +824,19 @@ struct NeumaierSum {
 
 // Single frame: E and the virial from the embedding backward's block partials [E, virial[9]], in a
 // fixed order with compensated sums: thread t < 250 sums component t % 10 of the partials t / 10,
-// t / 10 + 25, ..., then ten threads add their component's 25 sums.
-__global__ void __launch_bounds__(256) k_finalize(int nb, const double* part, double* energy, double* virial)
+// t / 10 + 25, ..., then ten threads add their component's 25 sums. Also the frame's count of
+// neighbours dropped by sel from its per-atom counters (one wave, lane = its lane index).
+__device__ void sum_drop_slots(DevStats* st, int lane)
+{
+    const unsigned long long* ds = drop_slots(st);
+    unsigned long long v = 0;
+    for (int i = lane; i < NL_DROP_SLOTS; i += 64) v += ds[i];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) st->nbr_dropped = v;
+}
+
+__global__ void __launch_bounds__(256) k_finalize(int nb, const double* part, double* energy, double* virial,
+                                                  DevStats* st)
 {
     __shared__ double red[256];
     const int t = threadIdx.x;
@@ -862,17 +851,20 @@ __global__ void __launch_bounds__(256) k_finalize(int nb, const double* part, do
         if (t == 0) *energy = x.value();
         else virial[t - 1] = x.value();
     }
+    if (t >= 192) sum_drop_slots(st, t - 192);   // the fourth wave, beside the ten sums above
 }
 
 // Batched frames: per frame (one block each) E = sum E_i and the virial = sum over the frame's
 // atoms of their per-atom virial, both in a fixed order, and the frame's forces (and E_i) in its
 // caller order. Output of frame f at out + out_off: E, virial[9], F[3n], E_i[n].
 __global__ void __launch_bounds__(256) k_finalize_batch(const FrameDesc* fd, const int* inv_perm, const double* ei,
-                                                        const double* vir_atom, const double* f_int, double* out)
+                                                        const double* vir_atom, const double* f_int, double* out,
+                                                        DevStats* st)
 {
     __shared__ double red[10][256];
     const FrameDesc& d = fd[blockIdx.x];
     const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid < 64) sum_drop_slots(st, tid);   // one count for the batch
     double* o = out + d.out_off;
     double acc[10];
     for (int k = 0; k < 10; ++k) acc[k] = 0.0;
@@ -940,15 +932,15 @@ void launch_batch_prep(int nframes, int ntypes, const double* coord, const int* 
                        inv_perm, itype, frame_of, pos, cell_of, cell_start, cand, f_int, vir_atom);
 }
 
-void launch_finalize(int nb, const double* part, double* energy, double* virial, hipStream_t s)
+void launch_finalize(int nb, const double* part, double* energy, double* virial, DevStats* st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, nb, part, energy, virial);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, nb, part, energy, virial, st);
 }
 
 void launch_finalize_batch(int nframes, const FrameDesc* fd, const int* inv_perm, const double* ei,
-                           const double* vir_atom, const double* f_int, double* out, hipStream_t s)
+                           const double* vir_atom, const double* f_int, double* out, DevStats* st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize_batch, dim3(nframes), dim3(256), 0, s, fd, inv_perm, ei, vir_atom, f_int, out);
+    hipLaunchKernelGGL(k_finalize_batch, dim3(nframes), dim3(256), 0, s, fd, inv_perm, ei, vir_atom, f_int, out, st);
 }
 
 int prep_small_max_atoms() { return PS_MAX_ATOMS; }
