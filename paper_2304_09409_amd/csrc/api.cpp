@@ -237,6 +237,11 @@ struct dpk_ctx {
     void* fvec = nullptr;
     void* fmat = nullptr;
     void* table = nullptr;
+    // the table as uploaded when the context was created (a later dpk_model_tabulate does not
+    // change what this context evaluates)
+    bool tab = false;
+    double tab_dx = 0.0;
+    int tab_nint = 0;
     size_t model_bytes = 0;
     bool owns_model = true;              // false for server slots sharing the first slot's copy
     // workspace
@@ -572,6 +577,9 @@ int upload_model(dpk_ctx* c)
             if ((rc = upload(&c->table, tf.data(), tf.size()))) return rc;
         }
         c->model_bytes += m->table.size() * c->acc_size;
+        c->tab = true;
+        c->tab_dx = m->tab_dx;
+        c->tab_nint = m->tab_nint;
     }
     return DPK_OK;
 }
@@ -605,8 +613,8 @@ void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* F, double* vir
     ea.evec = c->evec;
     ea.emat = c->emat;
     ea.table = c->table;
-    ea.tab_dx = m->tab_dx;
-    ea.tab_nint = m->tab_nint;
+    ea.tab_dx = c->tab_dx;
+    ea.tab_nint = c->tab_nint;
     ea.T = c->T;
     ea.dT = c->dT;
     ea.perm = c->perm;
@@ -618,7 +626,7 @@ void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* F, double* vir
         ea.Ei = c->Ei;
         ea.atom_energy = atom_energy;
     }
-    const bool tab = m->tabulated;
+    const bool tab = c->tab;
     prof_mark(ev, DPK_STAGE_EMBED_FWD, s);
     launch_embed_fwd(c->precision, tab, ea, s);
 
@@ -1572,6 +1580,7 @@ int dpk_server_create(const dpk_model* m, int device, int precision, int nslots,
             c->acc_size = c0->acc_size;
             c->ncu = c0->ncu;
             c->evec = c0->evec; c->emat = c0->emat; c->fvec = c0->fvec; c->fmat = c0->fmat; c->table = c0->table;
+            c->tab = c0->tab; c->tab_dx = c0->tab_dx; c->tab_nint = c0->tab_nint;
             c->model_bytes = c0->model_bytes;
             c->owns_model = false;
             rc = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess ? DPK_OK : DPK_E_DEVICE;

@@ -350,23 +350,49 @@ __device__ void stage_net(const EmbArgs& A, int net, typename P::acc* s_vec, cha
 }
 
 // Per-wave walk over (atom, 16-neighbour chunk) work items of one (type_i, type_j) pass, with the
-// next item's neighbour vector and index loaded one item ahead.
+// next item's neighbour vector and index loaded one item ahead. With LDSW the wave's atoms' type,
+// neighbour count and caller index are loaded once per pass into a small LDS table (wl) and read
+// from there when the walk reaches an atom: a global load there has to wait for every vector
+// memory operation in flight (force atomics, prefetches), since that counter is in order. (The
+// table backward pass uses it; in the network passes it cost more registers than it saved.)
+constexpr int WL_MAX = 8;   // atoms per wave at most (APW_MAX)
+template <bool LDSW = false>
 struct ChunkWalk {
     int i, a, np, c0;
-    int ac;   // caller index of atom a (backward pass), loaded when the walk reaches the atom
+    int ac;   // caller index of atom a (backward pass)
     bool have;
     double px, py, pz;
     int pj;
+    // wl: this wave's [2][WL_MAX] LDS table (type << 16 | neighbour count of atom k; its caller index)
     template <bool J = false>
-    __device__ __forceinline__ bool find_atom(const EmbArgs& A, int a0, int a1, int wave, int nw, int apw, int ti,
-                                              int tj, bool skip_empty) {
+    __device__ __forceinline__ void load_atoms(int* wl, const EmbArgs& A, int a0, int a1, int wave, int nw, int apw,
+                                               int tj, int lane) {
+        if (!LDSW) return;
+        const int a = a0 + wave + nw * lane;
+        if (lane < apw) {
+            wl[lane] = a < a1 ? (A.itype[a] << 16) | A.nnei[(size_t)a * A.ntypes + tj] : -1;
+            if (J) wl[WL_MAX + lane] = a < a1 ? A.perm[a] : 0;
+        }
+        wave_sync();
+    }
+    template <bool J = false>
+    __device__ __forceinline__ bool find_atom(const EmbArgs& A, const int* wl, int a0, int a1, int wave, int nw,
+                                              int apw, int ti, int tj, bool skip_empty) {
         for (; i < apw; ++i) {
             a = a0 + wave + nw * i;
             if (a >= a1) return false;
-            if (A.itype[a] != ti) continue;
-            np = A.nnei[(size_t)a * A.ntypes + tj];
-            if (skip_empty && np == 0) continue;
-            if (J) ac = A.perm[a];
+            if constexpr (LDSW) {
+                const int tn = __builtin_amdgcn_readfirstlane(wl[i]);
+                if ((tn >> 16) != ti) continue;
+                np = tn & 0xffff;
+                if (skip_empty && np == 0) continue;
+                if (J) ac = __builtin_amdgcn_readfirstlane(wl[WL_MAX + i]);
+            } else {
+                if (A.itype[a] != ti) continue;
+                np = A.nnei[(size_t)a * A.ntypes + tj];
+                if (skip_empty && np == 0) continue;
+                if (J) ac = A.perm[a];
+            }
             return true;
         }
         return false;
@@ -430,11 +456,11 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
             const acc* tab = reinterpret_cast<const acc*>(A.table) + (size_t)net * A.tab_nint * E2 * 6;
             acc* Tout = reinterpret_cast<acc*>(A.T);
 
-            ChunkWalk w;
+            ChunkWalk<> w;
             w.i = 0;
             w.c0 = 0;
             w.ac = 0;
-            w.have = w.find_atom(A, a0, a1, wave, NW, APW, ti, tj, false);
+            w.have = w.find_atom(A, nullptr, a0, a1, wave, NW, APW, ti, tj, false);
             w.fetch(A, tj, c16);
             accv Tacc[7];
             while (w.have) {
@@ -445,7 +471,7 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
                 if (w.c0 >= w.np) {
                     ++w.i;
                     w.c0 = 0;
-                    w.have = w.find_atom(A, a0, a1, wave, NW, APW, ti, tj, false);
+                    w.have = w.find_atom(A, nullptr, a0, a1, wave, NW, APW, ti, tj, false);
                     last = true;
                 }
                 w.fetch(A, tj, c16);
@@ -623,11 +649,37 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
     // per neighbour column of a wave: [0, 3) the centre atom's force over its pairs, [3, 12) the
     // virial sum -g r^T over the wave's pairs (kept here rather than in every lane's registers)
     __shared__ __attribute__((aligned(16))) double s_pair[NW][16][12];
+    // table path: force scatter deferred by one chunk (per column -g of the last chunk's pair and
+    // the neighbour's caller index, -1: none; the centre force of an atom that ended, and its
+    // caller index) and the LDS atom table of the walk
+    __shared__ __attribute__((aligned(16))) double s_defer[TAB ? NW : 1][16][4];
+    __shared__ __attribute__((aligned(16))) double s_defc[TAB ? NW : 1][4];
+    __shared__ int s_wl[TAB ? NW : 1][2 * WL_MAX];
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar registers)
     const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     for (int e = lane; e < N3P * 4; e += 64) s_dT[wave][e >> 2][e & 3] = 0;
     for (int e = lane; e < 16 * 12; e += 64) s_pair[wave][e / 12][e % 12] = 0.0;
+    if (TAB && g == 0) s_defer[wave][c16][3] = -1.0;
+    if (TAB && lane == 0) s_defc[wave][3] = -1.0;
+    // the atomics deferred from the previous chunk (each lane issues what it stored itself)
+    auto issue_deferred = [&]() {
+        if (g == 0) {
+            const double* d = s_defer[wave][c16];
+            const int jd = (int)d[3];
+            if (jd >= 0) {
+                unsafeAtomicAdd(&A.F[3 * (size_t)jd], d[0]);
+                unsafeAtomicAdd(&A.F[3 * (size_t)jd + 1], d[1]);
+                unsafeAtomicAdd(&A.F[3 * (size_t)jd + 2], d[2]);
+                s_defer[wave][c16][3] = -1.0;
+            }
+        }
+        if (lane == 0 && s_defc[wave][3] >= 0.0) {
+            const int cd = (int)s_defc[wave][3];
+            for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&A.F[3 * (size_t)cd + k], s_defc[wave][k]);
+            s_defc[wave][3] = -1.0;
+        }
+    };
     const double inv_w = 1.0 / (A.rc - A.rs);
     const int a0 = blockIdx.x * APB;
     const int a1 = min(a0 + APB, A.natoms);
@@ -645,12 +697,13 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
             const int64_t gpl = (int64_t)nets * EM_SIZE;
             const acc* tab = reinterpret_cast<const acc*>(A.table) + (size_t)net * A.tab_nint * E2 * 6;
 
-            ChunkWalk w;
+            ChunkWalk<TAB> w;
             w.i = 0;
             w.c0 = 0;
             w.ac = 0;
-            w.have = w.find_atom<true>(A, a0, a1, wave, NW, APW, ti, tj, true);
-            w.fetch<true>(A, tj, c16);
+            w.template load_atoms<true>(s_wl[TAB ? wave : 0], A, a0, a1, wave, NW, APW, tj, lane);
+            w.have = w.template find_atom<true>(A, s_wl[TAB ? wave : 0], a0, a1, wave, NW, APW, ti, tj, true);
+            w.template fetch<true>(A, tj, c16);
             acc pdT[DTL];
             for (int q = 0; q < DTL; ++q) {
                 const int e = lane + 64 * q;
@@ -665,10 +718,10 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                 if (w.c0 >= w.np) {
                     ++w.i;
                     w.c0 = 0;
-                    w.have = w.find_atom<true>(A, a0, a1, wave, NW, APW, ti, tj, true);
+                    w.have = w.template find_atom<true>(A, s_wl[TAB ? wave : 0], a0, a1, wave, NW, APW, ti, tj, true);
                     last = true;
                 }
-                w.fetch<true>(A, tj, c16);
+                w.template fetch<true>(A, tj, c16);
                 if (cc0 == 0) {
                     // the prefetched dT of this atom goes to LDS, feature f to its layer-3 row; the
                     // next atom's is requested
@@ -698,6 +751,14 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                     const double r = sqrt(x * x + y * y + z * z);
                     ir = 1.0 / r;
                     switch_fn(r, ir, A.rs, A.rc, inv_w, s, ds);
+                }
+                // table path: the previous chunk's force atomics are issued after this chunk's
+                // prefetches and dT staging, where no wait on the vector memory counter follows
+                // for a while (that counter is in order, so any wait would include them)
+                if constexpr (TAB) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    issue_deferred();
+                    __builtin_amdgcn_sched_barrier(0);
                 }
                 acc dR[4] = {0, 0, 0, 0}, H[4] = {0, 0, 0, 0};
                 if (TAB) {
@@ -833,9 +894,14 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                     const double q = d1 * ux + d2 * uy + d3 * uz;
                     const double rad = (d0 + dEds) * ds + q * (ds - sr);
                     const double gx = rad * ux + sr * d1, gy = rad * uy + sr * d2, gz = rad * uz + sr * d3;
-                    unsafeAtomicAdd(&A.F[3 * (size_t)jn], -gx);
-                    unsafeAtomicAdd(&A.F[3 * (size_t)jn + 1], -gy);
-                    unsafeAtomicAdd(&A.F[3 * (size_t)jn + 2], -gz);
+                    if constexpr (TAB) {
+                        double* dfr = s_defer[wave][p];
+                        dfr[0] = -gx; dfr[1] = -gy; dfr[2] = -gz; dfr[3] = (double)jn;
+                    } else {
+                        unsafeAtomicAdd(&A.F[3 * (size_t)jn], -gx);
+                        unsafeAtomicAdd(&A.F[3 * (size_t)jn + 1], -gy);
+                        unsafeAtomicAdd(&A.F[3 * (size_t)jn + 2], -gz);
+                    }
                     double* pa = s_pair[wave][p];
                     pa[0] += gx; pa[1] += gy; pa[2] += gz;
                     pa[3] -= gx * x; pa[4] -= gx * y; pa[5] -= gx * z;
@@ -854,15 +920,21 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                         v += __shfl_xor(v, 4);
                         v += __shfl_xor(v, 8);
                         if (lane == 0) {
-                            if (k < 3) unsafeAtomicAdd(&A.F[3 * (size_t)cac + k], v);
-                            else A.vir_atom[9 * (size_t)ca + k - 3] += v;
+                            if (k < 3) {
+                                if constexpr (TAB) s_defc[wave][k] = v;
+                                else unsafeAtomicAdd(&A.F[3 * (size_t)cac + k], v);
+                            } else {
+                                A.vir_atom[9 * (size_t)ca + k - 3] += v;
+                            }
                         }
                     }
+                    if (TAB && lane == 0) s_defc[wave][3] = (double)cac;
                     wave_sync();
                     if (g == 0)
                         for (int k = 0; k < nk; ++k) s_pair[wave][c16][k] = 0.0;
                 }
             }
+            if constexpr (TAB) issue_deferred();   // the pass's last chunk
         }
     }
     __syncthreads();

@@ -206,6 +206,25 @@ def test_tabulated_fcc_32000(dpk, precision):
     ctx.close()
 
 
+def test_context_keeps_the_model_it_was_created_with(dpk):
+    """A context evaluates the model as it was when the context was created: tabulating the model
+    afterwards (here a table that covers s < 0.1 only, so that its use shows in the out-of-range
+    count) leaves the context on the network, and a new context uses the table."""
+    say("tabulate after context creation")
+    spec, params = synth.FCC_MODEL, synth.fcc_params()
+    model = dpk.Model(spec, params)
+    c, t, b = synth.fcc_box(5, 3.6, 1)
+    ctx = dpk.Context(model, precision="fp64")
+    model.tabulate(0.01, 0.1)
+    check_fp64(ctx.compute(c, t, b), oracle_of("fcc").compute(c, t, b), len(t))
+    assert ctx.stats()["table_out_of_range"] == 0
+    ctx2 = dpk.Context(model, precision="fp64")
+    ctx2.compute(c, t, b)
+    assert ctx2.stats()["table_out_of_range"] > 0
+    ctx.close()
+    ctx2.close()
+
+
 def test_errors_are_reported(dpk):
     say("error paths")
     spec, params, model = model_of(dpk, "water")
