@@ -225,6 +225,41 @@ def test_context_keeps_the_model_it_was_created_with(dpk):
     ctx2.close()
 
 
+def _degenerate_frames():
+    """Frames at the edges of the method (water model, r_s 0.5 A, r_c 6.0 A): one atom (no
+    neighbours, F = 0); a pair inside r_s (the 1/r branch of the switching function) next to a pair
+    in the switching band; pairs just inside and just outside r_c; atoms of one type only (the
+    other type's blocks empty). Periodic boxes of 20 A and the same frames with open boundaries."""
+    box = np.eye(3) * 20.0
+    out = {}
+    out["single"] = (np.array([[3.0, 4.0, 5.0]]), np.array([0], dtype=np.int32))
+    out["pair_inside_rs"] = (np.array([[5.0, 5.0, 5.0], [5.3, 5.0, 5.0], [5.0, 7.1, 5.0]]),
+                             np.array([0, 1, 1], dtype=np.int32))
+    out["pairs_at_rc"] = (np.array([[2.0, 2.0, 2.0], [2.0, 2.0, 7.9999], [10.0, 10.0, 10.0],
+                                    [10.0, 16.0001, 10.0]]), np.array([0, 1, 0, 1], dtype=np.int32))
+    rng = np.random.default_rng(11)
+    out["one_type"] = (rng.uniform(0.0, 20.0, (40, 3)), np.ones(40, dtype=np.int32))
+    frames = {}
+    for name, (c, t) in out.items():
+        frames[name + "_periodic"] = (c, t, box)
+        frames[name + "_open"] = (c, t, None)
+    return frames
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_degenerate_frames(dpk, precision):
+    spec, params, model = model_of(dpk, "water")
+    ctx = dpk.Context(model, precision=precision)
+    for name, (c, t, b) in _degenerate_frames().items():
+        say(f"{precision} {name}")
+        ref = oracle_of("water").compute(c, t, b)
+        got = ctx.compute(c, t, b)
+        (check_fp64 if precision == "fp64" else check_mixed)(got, ref, len(t))
+        if name.startswith("single"):
+            assert np.all(got["force"] == 0.0)
+    ctx.close()
+
+
 def test_errors_are_reported(dpk):
     say("error paths")
     spec, params, model = model_of(dpk, "water")
