@@ -932,7 +932,7 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
 
     run_network(c, n, gp, d_force, nullptr, true, d_atom_energy, ev, s);
     prof_mark(ev, DPK_STAGE_FINAL, s);
-    launch_finalize(embed_bwd_blocks(c->precision, n, c->ncu), c->vir_part, d_energy, d_virial, c->stats, s);
+    launch_finalize(embed_bwd_blocks(c->precision, c->tab, n, c->ncu), c->vir_part, d_energy, d_virial, c->stats, s);
     prof_mark(ev, DPK_NSTAGES, s);
     HIPCHK(hipGetLastError());
     c->last_stream = s;

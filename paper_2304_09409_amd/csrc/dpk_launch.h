@@ -35,9 +35,10 @@ int prep_small_max_cells();
 void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s);
 
 // precision: 0 = FP64, 1 = split-BF16 (three products), 2 = BF16 (one product)
-// blocks of the embedding backward for a frame (one [E, virial] partial each), and their maximum
-// over launch shapes (workspace sizing)
-int embed_bwd_blocks(int precision, int64_t natoms, int ncu);
+// blocks of the embedding backward for a frame on the network or the table path (one [E, virial]
+// partial each; the two paths have their own launch shapes), and their maximum over launch shapes
+// (workspace sizing)
+int embed_bwd_blocks(int precision, bool table, int64_t natoms, int ncu);
 int64_t embed_bwd_max_blocks(int precision, int64_t natoms);
 // E and the virial of a single frame from the backward pass's nb partials [E, virial[9]], and the
 // frame's dropped-neighbour count into st

@@ -279,9 +279,9 @@ constexpr int Z2S = 68;
 
 // Launch shape of the embedding kernels: NW waves per block share one staged net; each wave takes
 // A.apw atoms, chosen per launch (embed_apw) between 1 and APW_MAX so that a large frame gets about
-// one block per CU (fewer net stagings per atom) and a small one still spreads over the CUs. FP64
-// runs 4 waves and keeps W3^T in global memory (L1/L2) to leave LDS for the wider activation
-// buffers. The FP32-accumulating policies run:
+// one block per CU (fewer net stagings per atom) and a small one still spreads over the CUs. Every
+// path stages W3^T in LDS. FP64 runs 8 waves (network; two per SIMD, in at most 256 registers) or
+// 4 (table; three blocks per CU). The FP32-accumulating policies run:
 //   * forward (network): 16 waves, four per SIMD, in at most 128 VGPRs (the contraction's
 //     accumulators live in the matrix cores' operands, see outer4): the extra waves per SIMD hide
 //     more of the exp/rcp, MFMA and LDS latency;
@@ -291,9 +291,9 @@ constexpr int Z2S = 68;
 template <class P, bool FWD = false, bool TAB = false> struct EmbCfg {
     typedef typename P::wt wt;
     static constexpr bool F64 = sizeof(typename P::acc) == 8;
-    static constexpr int NW = F64 ? 4 : (FWD ? (TAB ? 8 : 16) : 12);
+    static constexpr int NW = F64 ? (TAB ? 4 : 8) : (FWD ? (TAB ? 8 : 16) : 12);
     static constexpr int APW_MAX = F64 ? 3 : (FWD ? (TAB ? 3 : 4) : 6);
-    static constexpr bool W3LDS = !F64;
+    static constexpr bool W3LDS = true;
     // LDS rows of staged weights: one lane's fragment per group (VPL K values; [hi lo] for split
     // BF16), rows padded by 16 B so 16 consecutive rows fall in distinct banks.
     static constexpr int ROW2 = (K2P / P::VPL) * P::GB + 16;
@@ -1273,27 +1273,28 @@ static int embed_apw(int nw, int apw_max, int64_t natoms, int ncu)
     return (int)std::max<int64_t>(1, std::min<int64_t>(apw_max, a));
 }
 
-template <class P>
+template <class P, bool TAB>
 static int embed_bwd_blocks_p(int64_t natoms, int ncu)
 {
-    typedef EmbCfg<P, false, false> Cfg;
-    static_assert(EmbCfg<P, false, true>::NW == Cfg::NW && EmbCfg<P, false, true>::APW_MAX == Cfg::APW_MAX,
-                  "table and network backward shapes agree");
+    typedef EmbCfg<P, false, TAB> Cfg;
     const int64_t apb = (int64_t)Cfg::NW * embed_apw(Cfg::NW, Cfg::APW_MAX, natoms, ncu);
     return (int)((natoms + apb - 1) / apb);
 }
 
-int embed_bwd_blocks(int precision, int64_t natoms, int ncu)
+int embed_bwd_blocks(int precision, bool table, int64_t natoms, int ncu)
 {
-    if (precision == 0) return embed_bwd_blocks_p<PF64>(natoms, ncu);
-    if (precision == 1) return embed_bwd_blocks_p<PMIX>(natoms, ncu);
-    return embed_bwd_blocks_p<PBF16>(natoms, ncu);
+    if (precision == 0) return table ? embed_bwd_blocks_p<PF64, true>(natoms, ncu) : embed_bwd_blocks_p<PF64, false>(natoms, ncu);
+    if (precision == 1) return table ? embed_bwd_blocks_p<PMIX, true>(natoms, ncu) : embed_bwd_blocks_p<PMIX, false>(natoms, ncu);
+    return table ? embed_bwd_blocks_p<PBF16, true>(natoms, ncu) : embed_bwd_blocks_p<PBF16, false>(natoms, ncu);
 }
 
+// at least one atom per wave: the smallest block (in atoms) over both paths bounds the count
 int64_t embed_bwd_max_blocks(int precision, int64_t natoms)
 {
-    const int nw = precision == 0 ? EmbCfg<PF64>::NW : EmbCfg<PMIX>::NW;
-    static_assert(EmbCfg<PBF16>::NW == EmbCfg<PMIX>::NW, "backward shapes");
+    const int nw = precision == 0 ? std::min(EmbCfg<PF64, false, false>::NW, EmbCfg<PF64, false, true>::NW)
+                                  : std::min(EmbCfg<PMIX, false, false>::NW, EmbCfg<PMIX, false, true>::NW);
+    static_assert(EmbCfg<PBF16, false, false>::NW == EmbCfg<PMIX, false, false>::NW &&
+                  EmbCfg<PBF16, false, true>::NW == EmbCfg<PMIX, false, true>::NW, "backward shapes");
     return (natoms + nw - 1) / nw;
 }
 int fit_atoms_per_block(int) { return FIT_AF; }
