@@ -1023,7 +1023,7 @@ struct FitStage {
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int q = threadIdx.x + 256 * p;
-            if (q < TOTAL) {
+            if (TOTAL % 256 == 0 || q < TOTAL) {
                 const int pl = q / (ROWS * PPR), rem = q - pl * ROWS * PPR;
                 const int row = rem / PPR, pc = rem - row * PPR;
                 const int rs = row < nrows ? row : nrows - 1;
@@ -1035,7 +1035,7 @@ struct FitStage {
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int q = threadIdx.x + 256 * p;
-            if (q < TOTAL) {
+            if (TOTAL % 256 == 0 || q < TOTAL) {
                 const int pl = q / (ROWS * PPR), rem = q - pl * ROWS * PPR;
                 const int row = rem / PPR, pc = rem - row * PPR;
                 char* rowp = dst + row * ROWB;
@@ -1074,7 +1074,8 @@ __device__ __forceinline__ typename P::frag fit_afrag(const char* base, int row,
 // lanes read (position 16c + 4g + v holds logical index 16c + g + 4v): the four outputs a lane
 // produces and the four B-operand values it later reads are the same 32 bytes, written and read by
 // the same lane, so the scratch row needs no synchronisation.
-// Scratch row per atom: a1, a2, a3 (tanh outputs), ga (two ping-pong buffers), gh.
+// Scratch row per atom: a1, a2, a3 (tanh outputs), ga (two ping-pong buffers), gh; during the
+// forward pass the slots of the second ga buffer and of gh hold the inputs of layers 2 and 3.
 // ---------------------------------------------------------------------------------------------
 constexpr int F64_TP = 8;
 constexpr int FS_A1 = 0, FS_A2 = FW, FS_A3 = 2 * FW, FS_GA = 3 * FW, FS_GB = 4 * FW, FS_GH = 5 * FW, FS_ROW = 6 * FW;
@@ -1117,9 +1118,11 @@ __global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
             for (int k = 0; k < 4; ++k) Tn[v][k] = Ta[P::kidx(0, g, v) * 4 + k];
 
         // y = W x for ntiles 16-row output tiles of the row-major matrix at fm + mo (K columns,
-        // stored in the MFMA K order); x for K-chunk c comes from bsrc(c); epi(t, out) receives
-        // output tile t (rows 16t + orow(g, r)).
-        auto gemm = [&](int64_t mo, int K, int ntiles, auto&& bsrc, auto&& epi) {
+        // stored in the MFMA K order); x for K-chunk c is make(fetch(c)), where fetch(c) is the one
+        // memory read (32 B per lane) and make works on registers only; epi(t, out) receives
+        // output tile t (rows 16t + orow(g, r)). Reads retire in issue order, so each chunk's
+        // fetch is issued one chunk ahead and before the weight loads it would otherwise wait on.
+        auto gemm = [&](int64_t mo, int K, int ntiles, auto&& fetch, auto&& make, auto&& epi) {
             const int nchunk = K / 16;
 #pragma unroll 1
             for (int t0 = 0; t0 < ntiles; t0 += F64_TP) {
@@ -1127,25 +1130,39 @@ __global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
                 accv accs[F64_TP];
 #pragma unroll
                 for (int t = 0; t < F64_TP; ++t) zero4(accs[t]);
-                SW st;
+                // Weight chunks are fetched two ahead (two register stages in flight, alternated by
+                // unrolling the chunk loop twice) and staged through two LDS buffers: chunk c + 1
+                // goes to LDS after chunk c's products, into the buffer the previous barrier freed.
+                // Every read is unconditional (past the last chunk it repeats the last one), so that
+                // the compiler's in-order wait counts stay exact instead of draining all reads.
+                SW st0, st1;
                 const double* src = fm + mo + (int64_t)16 * t0 * K;
+                const int clast = nchunk - 1;
                 __syncthreads();
-                st.load(src, K, 0, 0, 16 * nt);
-                st.store(s_w[0]);
+                d4 x0 = fetch(0), x1 = {0, 0, 0, 0};
+                st0.load(src, K, 0, 0, 16 * nt);
+                st0.store(s_w[0]);
+                st1.load(src, K, 0, 16 * min(1, clast), 16 * nt);
                 __syncthreads();
-                frag Bn = bsrc(0);
-#pragma unroll 1
-                for (int c = 0; c < nchunk; ++c) {
-                    if (c + 1 < nchunk) st.load(src, K, 0, 16 * (c + 1), 16 * nt);
-                    const frag B = Bn;
-                    if (c + 1 < nchunk) Bn = bsrc(c + 1);
+                // chunk c from LDS; `nxt` holds chunk c + 1 in flight, `fut` receives chunk c + 2;
+                // xc holds chunk c's fetch, xn receives chunk c + 1's
+                auto step = [&](int c, SW& nxt, SW& fut, const d4& xc, d4& xn) {
+                    xn = fetch(min(c + 1, clast));
+                    fut.load(src, K, 0, 16 * min(c + 2, clast), 16 * nt);
+                    const frag B = make(xc);
                     const char* buf = s_w[c & 1];
 #pragma unroll
                     for (int t = 0; t < F64_TP; ++t)
                         if (t < nt) P::mma(accs[t], fit_afrag<P, SW::ROWB>(buf, 16 * t + c16, g), B);
-                    if (c + 1 < nchunk) st.store(s_w[(c + 1) & 1]);
+                    nxt.store(s_w[(c + 1) & 1]);
                     __syncthreads();
+                };
+#pragma unroll 1
+                for (int c = 0; c + 1 < nchunk; c += 2) {
+                    step(c, st1, st0, x0, x1);
+                    step(c + 1, st0, st1, x1, x0);
                 }
+                if (nchunk & 1) step(clast, st1, st0, x0, x1);
 #pragma unroll
                 for (int t = 0; t < F64_TP; ++t)
                     if (t < nt) {
@@ -1155,15 +1172,13 @@ __global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
             }
         };
         auto vec = [&](int off, int t, int r) { return fv[off + 16 * t + P::orow(g, r)]; };
-        auto kv = [&](int off, int c, int v) { return fv[off + P::kidx(c, g, v)]; };
-        auto rdfrag = [&](int off, int c) {
-            const d4 x = rd4(off + 16 * c + 4 * g);
-            return P::make(x[0], x[1], x[2], x[3]);
-        };
+        auto rdrow = [&](int off) { return [&, off](int c) { return rd4(off + 16 * c + 4 * g); }; };
+        auto asis = [](const d4& x) { return P::make(x[0], x[1], x[2], x[3]); };
 
         // a = tanh(y + b) in place over the 15 tiles of a layer output (a loop, so that the
-        // activation is inlined once rather than once per tile)
-        auto activate = [&](int off, int boff) {
+        // activation is inlined once rather than once per tile); side(t, a) forms the next
+        // layer's input from it
+        auto activate = [&](int off, int boff, auto&& side) {
 #pragma unroll 1
             for (int t = 0; t < 15; ++t) {
                 const d4 y = rd4(off + 16 * t + 4 * g);
@@ -1171,40 +1186,38 @@ __global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) a[r] = P::act(y[r] + vec(boff, t, r));
                 wr4(off + 16 * t + 4 * g, a);
+                side(t, a);
             }
         };
 
         // ---------------------------------------------------------- forward
         // layer 1: a1 = tanh(W1 D + b1), D formed on the fly from T (Eq. 7)
-        gemm(FM_W1T, DD, 15,
-             [&](int c) {
-                 const acc T0 = Ta[c * 4 + 0], T1 = Ta[c * 4 + 1], T2 = Ta[c * 4 + 2], T3 = Ta[c * 4 + 3];
+        gemm(FM_W1T, DD, 15, [&](int c) { return *reinterpret_cast<const d4*>(Ta + c * 4); },
+             [&](const d4& T) {
                  acc d[4];
 #pragma unroll
-                 for (int v = 0; v < 4; ++v) d[v] = T0 * Tn[v][0] + T1 * Tn[v][1] + T2 * Tn[v][2] + T3 * Tn[v][3];
+                 for (int v = 0; v < 4; ++v) d[v] = T[0] * Tn[v][0] + T[1] * Tn[v][1] + T[2] * Tn[v][2] + T[3] * Tn[v][3];
                  return P::make(d[0], d[1], d[2], d[3]);
              },
              [&](int t, const acc* o) { wr4(FS_A1 + 16 * t + 4 * g, o); });
-        activate(FS_A1, FV_B1);
-        // layer 2 input h1 = wh1 a1; layer 3 input h2 = wh2 a2 + h1
-        gemm(FM_W2T, FW, 15,
-             [&](int c) {
-                 const d4 x1 = rd4(FS_A1 + 16 * c + 4 * g);
-                 return P::make(kv(FV_WH1, c, 0) * x1[0], kv(FV_WH1, c, 1) * x1[1], kv(FV_WH1, c, 2) * x1[2],
-                                kv(FV_WH1, c, 3) * x1[3]);
-             },
-             [&](int t, const acc* o) { wr4(FS_A2 + 16 * t + 4 * g, o); });
-        activate(FS_A2, FV_B2);
-        gemm(FM_W3T, FW, 15,
-             [&](int c) {
-                 const d4 x1 = rd4(FS_A1 + 16 * c + 4 * g), x2 = rd4(FS_A2 + 16 * c + 4 * g);
-                 acc h[4];
+        // layer 2 input h1 = wh1 a1 and layer 3 input h2 = wh2 a2 + h1, formed as the activations
+        // are, in the slots GB and GH (the backward pass's, free until then)
+        activate(FS_A1, FV_B1, [&](int t, const acc* a) {
+            acc h[4];
 #pragma unroll
-                 for (int v = 0; v < 4; ++v) h[v] = kv(FV_WH2, c, v) * x2[v] + kv(FV_WH1, c, v) * x1[v];
-                 return P::make(h[0], h[1], h[2], h[3]);
-             },
-             [&](int t, const acc* o) { wr4(FS_A3 + 16 * t + 4 * g, o); });
-        activate(FS_A3, FV_B3);
+            for (int r = 0; r < 4; ++r) h[r] = vec(FV_WH1, t, r) * a[r];
+            wr4(FS_GB + 16 * t + 4 * g, h);
+        });
+        gemm(FM_W2T, FW, 15, rdrow(FS_GB), asis, [&](int t, const acc* o) { wr4(FS_A2 + 16 * t + 4 * g, o); });
+        activate(FS_A2, FV_B2, [&](int t, const acc* a) {
+            const d4 h1 = rd4(FS_GB + 16 * t + 4 * g);
+            acc h[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h[r] = vec(FV_WH2, t, r) * a[r] + h1[r];
+            wr4(FS_GH + 16 * t + 4 * g, h);
+        });
+        gemm(FM_W3T, FW, 15, rdrow(FS_GH), asis, [&](int t, const acc* o) { wr4(FS_A3 + 16 * t + 4 * g, o); });
+        activate(FS_A3, FV_B3, [](int, const acc*) {});
         // ---------------------------------------------------------- energy (Eq. 9) and ga3
         {
             acc e = 0;
@@ -1227,7 +1240,7 @@ __global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
         }
         // ---------------------------------------------------------- backward through layers 3, 2
         // gh2 = W3^T ga3 + gh3 with gh3 = wh4 w4; ga2 = gh2 wh2 (1 - a2^2)
-        gemm(FM_W3, FW, 15, [&](int c) { return rdfrag(FS_GA, c); },
+        gemm(FM_W3, FW, 15, rdrow(FS_GA), asis,
              [&](int t, const acc* o) {
                  const d4 x2 = rd4(FS_A2 + 16 * t + 4 * g);
                  acc gh[4], ga[4];
@@ -1240,7 +1253,7 @@ __global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
                  wr4(FS_GB + 16 * t + 4 * g, ga);
              });
         // gh1 = W2^T ga2 + gh2; ga1 = gh1 wh1 (1 - a1^2)
-        gemm(FM_W2, FW, 15, [&](int c) { return rdfrag(FS_GB, c); },
+        gemm(FM_W2, FW, 15, rdrow(FS_GB), asis,
              [&](int t, const acc* o) {
                  const d4 x1 = rd4(FS_A1 + 16 * t + 4 * g), gh2 = rd4(FS_GH + 16 * t + 4 * g);
                  acc ga[4];
@@ -1256,7 +1269,7 @@ __global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int k = 0; k < 4; ++k) q2[r][k] = 0;
-        gemm(FM_W1, FW, E2, [&](int c) { return rdfrag(FS_GA, c); },
+        gemm(FM_W1, FW, E2, rdrow(FS_GA), asis,
              [&](int m, const acc* dd) {
                  const acc T0 = Ta[m * 4 + 0], T1 = Ta[m * 4 + 1], T2 = Ta[m * 4 + 2], T3 = Ta[m * 4 + 3];
                  acc part[4] = {0, 0, 0, 0};
