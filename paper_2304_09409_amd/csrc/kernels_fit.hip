@@ -221,9 +221,12 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
 #pragma unroll
             for (int k = 0; k < 4; ++k) Tn[r][k] = v[k];
         }
-        auto dfrag = [&](int c, __bf16* f) {
-            const f4 ta = *reinterpret_cast<const f4*>(Tw + (2 * c) * 4);
-            const f4 tb = *reinterpret_cast<const f4*>(Tw + (2 * c + 1) * 4);
+        // T rows 2c and 2c + 1 of this lane's atom, and the D fragment of K-chunk c formed from them
+        auto trows = [&](int c, f4& ta, f4& tb) {
+            ta = *reinterpret_cast<const f4*>(Tw + (2 * c) * 4);
+            tb = *reinterpret_cast<const f4*>(Tw + (2 * c + 1) * 4);
+        };
+        auto dform = [&](const f4& ta, const f4& tb, __bf16* f) {
             float d0[4], d1[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -235,18 +238,26 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
         };
 #pragma unroll
         for (int cc = 0; cc < FX_G; ++cc)
-            if (cc % NWA == ph) dfrag(cc, sb(cc, wa));
+            if (cc % NWA == ph) {
+                f4 ta, tb;
+                trows(cc, ta, tb);
+                dform(ta, tb, sb(cc, wa));
+            }
         __syncthreads();
         {
             zero_acc();
             const int wb = XF_W1F;
             F8 An[TPW];
 #pragma unroll
-            for (int i = 0; i < TPW; ++i)
-                if (i < nown) An[i] = ld_wfrag<SPLIT>(wrs, lane16, wb + wave + NW * i);
+            for (int i = 0; i < TPW; ++i) An[i] = ld_wfrag<SPLIT>(wrs, lane16, wb + wave + NW * i);
             constexpr int NGRP = (XF_NCH1 + FX_G - 1) / FX_G;
-#pragma unroll 1
-            for (int grp = 0; grp < NGRP; ++grp) {
+            // One group of FX_G K-chunks. Reads retire in issue order, so the T rows of the D
+            // fragment formed after a chunk's products are read before that chunk's weight
+            // prefetch, and every read is unconditional (clamped to valid rows and fragments; a
+            // wave with fewer tiles reads one it does not use): a read skipped by a branch would
+            // make the compiler drain all reads in flight. The last, partial group is peeled so
+            // that its chunk bounds are constants.
+            auto group = [&](int grp) {
                 const int p = grp & 1;
 #pragma unroll
                 for (int cc = 0; cc < FX_G; ++cc) {
@@ -255,11 +266,12 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
                         F8 Ac[TPW];
 #pragma unroll
                         for (int i = 0; i < TPW; ++i) Ac[i] = An[i];
-                        if (c + 1 < XF_NCH1) {
+                        const int cn = c + FX_G;
+                        f4 ta, tb;
+                        trows(min(cn, XF_NCH1 - 1), ta, tb);
+                        const int c1 = min(c + 1, XF_NCH1 - 1);
 #pragma unroll
-                            for (int i = 0; i < TPW; ++i)
-                                if (i < nown) An[i] = ld_wfrag<SPLIT>(wrs, lane16, wb + (c + 1) * 15 + wave + NW * i);
-                        }
+                        for (int i = 0; i < TPW; ++i) An[i] = ld_wfrag<SPLIT>(wrs, lane16, wb + c1 * 15 + wave + NW * i);
                         F8 B[NAT];
 #pragma unroll
                         for (int a = 0; a < NAT; ++a) B[a] = ld_frag<SPLIT>(sb(p * FX_G + cc, a), lane);
@@ -269,12 +281,14 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
 #pragma unroll
                                 for (int a = 0; a < NAT; ++a) mma32<SPLIT>(acc[i][a], Ac[i], B[a]);
                             }
-                        const int cn = c + FX_G;
-                        if (cn < XF_NCH1 && cc % NWA == ph) dfrag(cn, sb((p ^ 1) * FX_G + cc, wa));
+                        if (cn < XF_NCH1 && cc % NWA == ph) dform(ta, tb, sb((p ^ 1) * FX_G + cc, wa));
                     }
                 }
                 __syncthreads();
-            }
+            };
+#pragma unroll 1
+            for (int grp = 0; grp < NGRP - 1; ++grp) group(grp);
+            group(NGRP - 1);
         }
         prefetch8(XF_W2F);
         // a1 = tanh(W1 D + b1), h1 = wh1 a1
