@@ -431,17 +431,22 @@ struct ChunkWalk {
         }
         return false;
     }
-    // J: also the neighbour's caller index (the backward pass adds forces in caller order)
+    // Prefetch of the chunk's r_ij; J: also the neighbour's caller index (the backward pass adds
+    // forces in caller order). The reads are unconditional and their values used as read: a lane past its atom's kept
+    // neighbours reads another slot of the atom's row (clamped to the row; slot 0 once the walk
+    // has ended). Every slot of every row holds finite values (padding is written as zero), and
+    // the kernels use r of such a lane only under `valid` or multiplied by its zero s. A read
+    // under a branch, or a select of its value, makes the compiler wait for this prefetch early
+    // (reads retire in order).
     template <bool J = false>
     __device__ __forceinline__ void fetch(const EmbArgs& A, int tj, int c16) {
-        px = py = pz = 0.0;
-        pj = 0;
-        if (have && c0 + c16 < np) {
-            const size_t slot = (size_t)a * A.nc + A.off[tj] + c0 + c16;
-            const double* v = A.nl_r + 3 * slot;
-            px = v[0]; py = v[1]; pz = v[2];
-            if (J) pj = A.nl_j[slot];
-        }
+        const int e = min(A.off[tj] + c0 + c16, A.nc - 1);
+        const size_t slot = have ? (size_t)a * A.nc + e : 0;
+        const double* v = A.nl_r + 3 * slot;
+        px = v[0];
+        py = v[1];
+        pz = v[2];
+        if (J) pj = A.nl_j[slot];
     }
 };
 
@@ -743,6 +748,9 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                 const int e = lane + 64 * q;
                 pdT[q] = (w.have && e < E2 * 4) ? dTin[(size_t)w.a * E2 * 4 + e] : (acc)0;
             }
+            // the first chunk's r and j are in place before the loop, as every later chunk's are
+            // at the end of the previous one, so the loop itself never waits for them
+            asm volatile("" ::"v"(w.px), "v"(w.py), "v"(w.pz), "v"(w.pj));
             while (w.have) {
                 const double x = w.px, y = w.py, z = w.pz;
                 const int jn = w.pj;
@@ -920,6 +928,10 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                 const acc dRg = sum_groups4(dR);
                 const acc hR = sum_groups(H[0] * Ra[0] + H[1] * Ra[1] + H[2] * Ra[2] + H[3] * Ra[3]);
                 const acc dR2 = __shfl(dRg, c16 + 16), dR1 = __shfl(dRg, c16 + 32), dR3 = __shfl(dRg, c16 + 48);
+                // The next chunk's prefetched r and j are put in place here, after this chunk's work
+                // and before its force atomics: reads and atomics retire in order, so waiting for the
+                // prefetch after the atomics (where the compiler otherwise sinks it) waits for them too.
+                asm volatile("" ::"v"(w.px), "v"(w.py), "v"(w.pz), "v"(w.pj));
                 if (valid && g == 0) {
                     const double inc = A.inv_nc;
                     const double d0 = inc * (double)dRg, d1 = inc * (double)dR1;
