@@ -690,10 +690,11 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
     __shared__ __attribute__((aligned(16))) double s_pair[NW][16][12];
     // table path: force scatter deferred by one chunk (per column -g of the last chunk's pair and
     // the neighbour's caller index, -1: none; the centre force of an atom that ended, and its
-    // caller index) and the LDS atom table of the walk
+    // caller index); every path: the LDS atom table of the walk (its reads do not wait on the
+    // in-order vector memory counter, which also holds the force atomics)
     __shared__ __attribute__((aligned(16))) double s_defer[TAB ? NW : 1][16][4];
     __shared__ __attribute__((aligned(16))) double s_defc[TAB ? NW : 1][4];
-    __shared__ int s_wl[TAB ? NW : 1][2 * WL_MAX];
+    __shared__ int s_wl[NW][2 * WL_MAX];
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar registers)
     const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
@@ -736,12 +737,12 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
             const int64_t gpl = (int64_t)nets * EM_SIZE;
             const acc* tab = reinterpret_cast<const acc*>(A.table) + (size_t)net * A.tab_nint * E2 * 6;
 
-            ChunkWalk<TAB> w;
+            ChunkWalk<true> w;
             w.i = 0;
             w.c0 = 0;
             w.ac = 0;
-            w.template load_atoms<true>(s_wl[TAB ? wave : 0], A, a0, a1, wave, NW, APW, tj, lane);
-            w.have = w.template find_atom<true>(A, s_wl[TAB ? wave : 0], a0, a1, wave, NW, APW, ti, tj, true);
+            w.template load_atoms<true>(s_wl[wave], A, a0, a1, wave, NW, APW, tj, lane);
+            w.have = w.template find_atom<true>(A, s_wl[wave], a0, a1, wave, NW, APW, ti, tj, true);
             w.template fetch<true>(A, tj, c16);
             acc pdT[DTL];
             for (int q = 0; q < DTL; ++q) {
@@ -760,7 +761,7 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                 if (w.c0 >= w.np) {
                     ++w.i;
                     w.c0 = 0;
-                    w.have = w.template find_atom<true>(A, s_wl[TAB ? wave : 0], a0, a1, wave, NW, APW, ti, tj, true);
+                    w.have = w.template find_atom<true>(A, s_wl[wave], a0, a1, wave, NW, APW, ti, tj, true);
                     last = true;
                 }
                 w.template fetch<true>(A, tj, c16);
