@@ -311,7 +311,8 @@ def main():
         from oracle import Oracle
         o = Oracle(synth.WATER_MODEL, synth.water_params())
         reps, elapsed, ref = 0, 0.0, None
-        while reps < 3 and (reps == 0 or elapsed < 10.0):
+        # whole frames until about 10 s of oracle work (at least one, at most 30)
+        while reps < 30 and (reps == 0 or elapsed < 10.0):
             ts = time.perf_counter()
             ref = o.compute(c, t, b)
             elapsed += time.perf_counter() - ts
