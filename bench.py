@@ -294,6 +294,16 @@ def main():
                           virial=virial.cpu().numpy().reshape(3, 3).copy(), stats=st)
         print(f"# {prec}: {ms:.3f} ms/step, {n / (ms * 1e-3):.4g} atom-steps/s, stages (ms) "
               + ", ".join(f"{k} {v:.3f}" for k, v in runs[prec]["stage_ms"].items()), file=sys.stderr, flush=True)
+        # the same frame through the host-buffer entry point (synchronous; host-to-device and
+        # device-to-host copies included): reported beside the device-resident rate, never as it
+        ctx.compute(c, t, b)
+        hreps = max(3, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(hreps):
+            ctx.compute(c, t, b)
+        runs[prec]["host_buffer_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / hreps
+        print(f"# {prec}: host-buffer entry point {runs[prec]['host_buffer_ms_per_step']:.3f} ms/step",
+              file=sys.stderr, flush=True)
         ctx.close()
 
     tabulated = None if args.no_table else tabulated_bench(dpk, synth, torch, max(1, args.steps // 2),
@@ -365,6 +375,7 @@ def main():
                  "roofline": {"kernel": fp64_dom, "bound": b2, "achieved": ach2, "peak": p2, "unit": u2,
                               "frac": ach2 / p2, "traffic": stored_traffic(fp64_dom, "fp64")}},
         "mixed_stage_ms": head["stage_ms"],
+        "host_buffer_ms_per_step": {p: runs[p]["host_buffer_ms_per_step"] for p in runs},
         "speedup_mixed_vs_fp64": head["value"] / runs["fp64"]["value"],
         "force_error_vs_oracle": errs or None,
         "roofline": roof,
