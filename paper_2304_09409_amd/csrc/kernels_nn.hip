@@ -432,12 +432,12 @@ struct ChunkWalk {
         return false;
     }
     // Prefetch of the chunk's r_ij; J: also the neighbour's caller index (the backward pass adds
-    // forces in caller order). The reads are unconditional and their values used as read: a lane past its atom's kept
-    // neighbours reads another slot of the atom's row (clamped to the row; slot 0 once the walk
-    // has ended). Every slot of every row holds finite values (padding is written as zero), and
-    // the kernels use r of such a lane only under `valid` or multiplied by its zero s. A read
-    // under a branch, or a select of its value, makes the compiler wait for this prefetch early
-    // (reads retire in order).
+    // forces in caller order). The reads are unconditional and their values used as read: a lane
+    // past its atom's kept neighbours reads another slot of the atom's row (clamped to the row;
+    // slot 0 once the walk has ended). Every slot of every row holds finite values (padding is
+    // written as zero), and the kernels use r of such a lane only under `valid` or multiplied by
+    // its zero s. A read under a branch, or a select of its value, makes the compiler wait for
+    // this prefetch early (reads retire in order).
     template <bool J = false>
     __device__ __forceinline__ void fetch(const EmbArgs& A, int tj, int c16) {
         const int e = min(A.off[tj] + c0 + c16, A.nc - 1);
