@@ -464,3 +464,146 @@ def test_tabulated_model_close_to_network(fcc_oracle):
     net = o.compute(c, t, b)
     assert abs(tab["energy"] - net["energy"]) / len(t) < 1e-8
     assert np.abs(tab["force"] - net["force"]).max() < 1e-6
+
+
+# ---------------------------------------------------------------------------------------------
+# Forward values of the layers (Sec. II.A.6, eq. NN), checked against numpy written here from the
+# layer definition y = w_hat * tanh(x W + b) (+ x, or + {x, x}) on special cases where the deeper
+# layers are switched off, so each layer's output is visible in G or E_i. Non-unit timestep
+# vectors and nonzero output biases make a dropped w_hat or bias visible.
+# ---------------------------------------------------------------------------------------------
+
+def _layers(model, params):
+    """[(W, b, w_hat)] views of every layer in blob order (embedding nets, then fitting nets)."""
+    out, off = [], 0
+    for nin, nout in synth.layer_shapes(model):
+        W = params[off:off + nin * nout].reshape(nin, nout)
+        off += nin * nout
+        b = params[off:off + nout]
+        off += nout
+        wh = params[off:off + nout]
+        off += nout
+        out.append((W, b, wh))
+    assert off == params.size
+    return out
+
+
+def _noisy_water_params():
+    return synth.make_params(synth.WATER_MODEL, 77, synth.WATER_OUT_SCALE, synth.WATER_FIT_IN,
+                             timestep_sigma=0.3)
+
+
+def test_embedding_layer_values_closed_form():
+    """Layer 1 (1 -> 25, no skip) is exactly w_hat1 tanh(s W1 + b1). With layers 2 and 3 switched
+    off (W = b = 0, tanh 0 = 0) every doubling skip repeats its input, so G = [z1 z1 z1 z1]; with
+    layer 3 alone switched off, G = [z2 z2] with z2 = [z1 z1] + w_hat2 tanh(z1 W2 + b2). A tanh
+    applied after a skip, a dropped bias or timestep, or a transposed W fails one of these."""
+    m = synth.WATER_MODEL
+    base = _noisy_water_params()
+    for net in (0, 3):
+        for x in (0.03, 0.61, 1.7):
+            p = base.copy()
+            L = _layers(m, p)
+            (W1, b1, h1), (W2, b2, h2), (W3, b3, h3) = L[3 * net:3 * net + 3]
+            z1 = h1 * np.tanh(x * W1[0] + b1)
+            z2 = np.concatenate([z1, z1]) + h2 * np.tanh(z1 @ W2 + b2)
+            W3[:] = 0.0
+            b3[:] = 0.0
+            y = Oracle(m, p).embed(net, x)[0]
+            np.testing.assert_allclose(y, np.concatenate([z2, z2]), rtol=1e-14, atol=1e-15)
+            W2[:] = 0.0
+            b2[:] = 0.0
+            y = Oracle(m, p).embed(net, x)[0]
+            np.testing.assert_allclose(y, np.tile(z1, 4), rtol=1e-14, atol=1e-15)
+
+
+def test_fitting_layer_values_closed_form():
+    """Fitting net (1600 -> 240 -> 240 -> 240 -> 1): with layers 2 and 3 switched off (tanh 0 = 0)
+    the two 240 -> 240 skips pass h1 through, so E_i = w_hat4 (h1 . V4 + c4) with
+    h1 = w_hat1 tanh(d V1 + c1) (the output layer linear, reading R3); with layer 3 alone off,
+    h3 = h2 = h1 + w_hat2 tanh(h1 V2 + c2). A tanh on the output layer, a skip on the first layer,
+    or a dropped c4 / w_hat4 fails one of these."""
+    m = synth.WATER_MODEL
+    base = _noisy_water_params()
+    nemb = 3 * m["ntypes"] ** 2
+    rng = np.random.default_rng(5)
+    for t in (0, 1):
+        p = base.copy()
+        L = _layers(m, p)
+        (V1, c1, w1), (V2, c2, w2), (V3, c3, w3), (V4, c4, w4) = L[nemb + 4 * t:nemb + 4 * t + 4]
+        c4[:] = 0.8                                  # the generator leaves the output bias at 0
+        V4 *= 30.0                                   # output of order several eV: tanh(E) != E
+        d = rng.normal(0.0, 1e-3, 1600)
+        h1 = w1 * np.tanh(d @ V1 + c1)
+        h2 = h1 + w2 * np.tanh(h1 @ V2 + c2)
+        V3[:] = 0.0
+        c3[:] = 0.0
+        e = Oracle(m, p).fit(t, d)[0]
+        ref = w4[0] * (h2 @ V4[:, 0] + c4[0])
+        assert abs(ref) > 2.0
+        assert e == pytest.approx(ref, rel=1e-13, abs=1e-13)
+        V2[:] = 0.0
+        c2[:] = 0.0
+        e = Oracle(m, p).fit(t, d)[0]
+        assert e == pytest.approx(w4[0] * (h1 @ V4[:, 0] + c4[0]), rel=1e-13, abs=1e-13)
+
+
+def test_type_one_side_equals_duplicated_pair_nets():
+    """Per-species nets (Sec. II.A.1): with type_one_side the net depends on the neighbour's type
+    only, which is the N_t^2 model whose net (a_i, a_j) is a copy of net a_j for every a_i."""
+    one = dict(synth.SERVE_MODEL, type_one_side=True)
+    p1 = synth.make_params(one, 31, synth.SERVE_OUT_SCALE, synth.SERVE_FIT_IN, timestep_sigma=0.2)
+    nt = one["ntypes"]
+    emb_len = sum(i * o + 2 * o for i, o in synth.layer_shapes(one)[:3])
+    nets1 = [p1[k * emb_len:(k + 1) * emb_len] for k in range(nt)]
+    fit = p1[nt * emb_len:]
+    p2 = np.concatenate([nets1[tj] for ti in range(nt) for tj in range(nt)] + [fit])
+    two = dict(synth.SERVE_MODEL, type_one_side=False)
+    c, t, b = synth.serving_frame(300, 17, 3)
+    a = Oracle(one, p1).compute(c, t, b)
+    z = Oracle(two, p2).compute(c, t, b)
+    assert a["energy"] == z["energy"]
+    np.testing.assert_array_equal(a["force"], z["force"])
+    np.testing.assert_array_equal(a["virial"], z["virial"])
+    # and it is a different model from the N_t^2 one with independent nets
+    z2 = Oracle(two, synth.make_params(two, 31, synth.SERVE_OUT_SCALE, synth.SERVE_FIT_IN)).compute(c, t, b)
+    assert abs(z2["energy"] - a["energy"]) > 1e-3
+
+
+def test_table_out_of_range_extrapolates_last_piece(fcc_oracle):
+    """Reading R9: an input past the table's range x > L_c dx uses the last interval's quintic,
+    extrapolated. The quintic is built here independently of the printed coefficient formulas, as
+    the solution of the six Hermite conditions (y, y', y'' at both nodes, from the net), and
+    evaluated past the node; the oracle must agree and flag the input as out of range. Below zero
+    the first piece is used the same way."""
+    o = fcc_oracle
+    dx, nint = 0.01, 50
+    coef = o.table(dx, nint)
+
+    def hermite(l, x):
+        # power basis in u = (x - x_l) / dx (well conditioned): p = sum_k a_k u^k
+        y0, d0, s0 = o.embed(0, l * dx)
+        y1, d1, s1 = o.embed(0, (l + 1) * dx)
+        A = np.array([[1, 0, 0, 0, 0, 0], [0, 1, 0, 0, 0, 0], [0, 0, 2, 0, 0, 0],
+                      [1, 1, 1, 1, 1, 1], [0, 1, 2, 3, 4, 5], [0, 0, 2, 6, 12, 20]], dtype=float)
+        rhs = np.stack([y0, d0 * dx, s0 * dx ** 2, y1, d1 * dx, s1 * dx ** 2])   # [6, M]
+        a = np.linalg.solve(A, rhs)
+        u = (x - l * dx) / dx
+        val = sum(a[k] * u ** k for k in range(6))
+        der = sum(k * a[k] * u ** (k - 1) for k in range(1, 6)) / dx
+        return val, der
+
+    for x, l in ((0.5 + 0.004, nint - 1), (0.5 + 0.03, nint - 1), (0.62, nint - 1), (-0.002, 0)):
+        y, dy, oor = o.table_eval(coef, dx, 0, x)
+        assert oor
+        ry, rdy = hermite(l, x)
+        # the top coefficients are of the order of their own rounding (a_5 ~ 1e-15 in u), which
+        # extrapolation u units past the node amplifies by about u^5
+        u = max(1.0, abs(x - l * dx) / dx)
+        np.testing.assert_allclose(y, ry, rtol=1e-9, atol=1e-13 * u ** 5)
+        np.testing.assert_allclose(dy, rdy, rtol=1e-7, atol=5e-13 * u ** 4 / dx)
+    # inside the range: the same construction, not flagged
+    y, dy, oor = o.table_eval(coef, dx, 0, 0.2371)
+    assert not oor
+    ry, rdy = hermite(23, 0.2371)
+    np.testing.assert_allclose(y, ry, rtol=1e-9, atol=1e-10)
