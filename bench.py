@@ -22,56 +22,87 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Published MI355X peaks (dense) used for the roofline fields.
+# MI355X peaks used for the roofline fields: AMD's published dense figures, and the vector-ALU
+# rate from the unit counts. All HIP code here is built with packed FP32 disabled, so the FP32
+# vector peak is the non-packed one: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz.
 PEAK = {
     "hbm": 8000.0,          # GB/s
-    "fp64_mfma": 78.6,      # TFLOP/s
-    "bf16_mfma": 2500.0,    # TFLOP/s
-    "fp32_valu": 157.3,     # TFLOP/s (256 CU x 4 SIMD x 16 lanes x 2 flop x 2 (packed) x 2.4 GHz)
+    "fp64": 78.6,           # TFLOP/s, FP64 matrix = FP64 vector
+    "fp32_mfma": 157.3,     # TFLOP/s
+    "bf16_mfma": 2500.0,    # TFLOP/s, dense
+    "fp32_valu": 78.6,      # TFLOP/s, non-packed
 }
 
-# Algorithmic FP32 vector work per real neighbour pair of the BF16-path embedding kernels (the
-# GEMMs of layers 2 and 3 run on the matrix cores and are not counted here). tanh is counted as
-# 6 flop (scale, exp, add, reciprocal, fused multiply-add), an FMA as 2.
-#   forward: layer 1 25 x (2 pre + 6 tanh + 1 scale) + layer 2 50 x (1 bias + 6 + 2 skip)
-#            + layer 3 100 x (1 + 6 + 2 + 8 for T += G R)                         = 2,375 flop
-#   adjoint: layer 1 25 x (2 + 6 + 1 + 4 derivative) + layer 2 50 x (1 + 6 + 2 + 5)
-#            + layer 3 100 x (1 + 6 + 2 + 5 + 8 dE/dR + 8 dE/ds) + chain rule ~50  = 4,075 flop
+# Algorithmic work per unit (the method's arithmetic on real, kept neighbours only; forward and
+# input gradient, no weight gradients):
+#   embedding net, per pair: 2 (25 + 25*50 + 50*100) = 12,550 flop forward; the input-gradient
+#     pass needs the same products again (12,550) on top of the contraction's;
+#   tabulated embedding, per pair: 100 features x 5 FMA for G (1,000 flop) and x 4 FMA for dG/ds
+#     (800 flop);
+#   contraction, per pair: T += G^T R 800 flop, dE/dR = G dT and dE/dG . R 1,600 flop;
+#   environment row and chain rule, per pair: about 50 flop (FP64);
+#   fitting, per atom: D = T T_<^T 12,800 + dE/dT 25,600 + 2 x 2 (1600*240 + 2*240^2 + 240)
+#     = 2,036,160 flop.
+NET_PAIR, TAB_VAL_PAIR, TAB_DER_PAIR = 12550.0, 1000.0, 800.0
+CONTRACT_FWD, CONTRACT_BWD, ENV_PAIR = 800.0, 1600.0, 50.0
+FIT_ATOM = 2036160.0
+
+# FP32 vector work per pair of the BF16-path network kernels (activations, derivatives, the
+# contractions, the chain rule; tanh counted as 6 flop), a second view beside the matrix roofline:
+#   forward: layer 1 25 x (2 + 6 + 1) + layer 2 50 x (1 + 6 + 2) + layer 3 100 x (1 + 6 + 2 + 8)
+#            = 2,375 flop
+#   adjoint: layer 1 25 x (2 + 6 + 1 + 4) + layer 2 50 x (1 + 6 + 2 + 5)
+#            + layer 3 100 x (1 + 6 + 2 + 5 + 8 + 8) + chain rule ~50 = 4,075 flop
 VALU_FLOP_PER_PAIR = {"embed_fwd": 2375.0, "embed_bwd": 4075.0}
 
+# End-to-end ceilings (atom-steps/s) of each workload and mode: the binding unit's time per
+# atom-step from the algorithmic work above.
+#   water FP64: 4.53 MFLOP at 78.6 TF -> 1.73e7; water mixed: about 16.6 k tanh + epilogues on the
+#   vector ALU, BF16 matrix work 1.8 ns -> 1.6e8; water FP32: 4.27 MFLOP of dense GEMM at 157.3 TF
+#   (27 ns) -> 3.7e7; fcc tabulated FP32: the fitting GEMM, 2.04 MFLOP at 157.3 TF -> 7.9e7;
+#   fcc tabulated FP64: 2.62 MFLOP at 78.6 TF -> 3.0e7; fcc tabulated mixed: the table and
+#   contraction on the vector ALU, 138 x 5,300 flop at 78.6 TF (9.3 ns; the split-BF16 fitting
+#   needs 2.4 ns) -> 1.07e8.
+CEILING = {("water", "fp64"): 1.73e7, ("water", "mixed"): 1.6e8, ("water", "fp32"): 3.7e7,
+           ("water", "bf16"): 1.6e8, ("fcc_table", "fp32"): 7.9e7, ("fcc_table", "fp64"): 3.0e7,
+           ("fcc_table", "mixed"): 1.07e8}
 
-def work_per_launch(stage: str, precision: str, natoms: int, npairs: int, nc: int):
-    """Algorithmic work of one launch of a stage against the unit that bounds it: (bound, amount,
-    peak, unit).
 
-    Matrix work per real neighbour pair: embedding layers 2 + 3 = 2 (25*50 + 50*100) = 12,500
-    flop, layer 1 50 flop, contraction G^T R 800 flop. The forward kernel computes G once (13,350
-    flop per pair); the adjoint re-evaluates G and dG/ds (25,100), then dE/dR = G dT and (dG/ds)
-    dT (1,600) and the chain rule (~50): 26,750 flop per pair. Fitting per atom: D = T T_<^T
-    12,800, forward 2 (1600*240 + 2*240^2 + 240) = 998,880, input gradient 2 (1600*240 +
-    2*240^2) = 998,400, dT 25,600: 2,035,680 flop. The neighbour list moves, per atom, the
-    coordinates of the candidates it reads once (24 B x 27 bins' atoms is served from cache) and
-    writes its list: N_c (4 B index + 24 B vector) + the per-type counts.
+def matrix_peak(precision: str):
+    return {"fp64": PEAK["fp64"], "fp32": PEAK["fp32_mfma"]}.get(precision, PEAK["bf16_mfma"])
 
-    FP64 path: every stage is priced against the FP64 matrix peak. BF16 paths: the fitting net
-    against the BF16 matrix peak (each FP32-accurate product is three BF16 products, so a
-    saturated kernel shows 1/3); the embedding kernels are bound by the vector ALU (the
-    activations and their derivatives; counters show the VALU far busier than the matrix cores)
-    and are priced by VALU_FLOP_PER_PAIR against the FP32 vector peak."""
-    if stage == "embed_fwd":
-        flops = 13350.0 * npairs
-    elif stage == "embed_bwd":
-        flops = 26750.0 * npairs
-    elif stage == "fit":
-        flops = 2035680.0 * natoms
-    else:
+
+def work_per_launch(stage: str, precision: str, natoms: int, npairs: int, nc: int, table: bool = False):
+    """Algorithmic work of one launch of a stage and the peak of the unit it is priced against:
+    (bound, amount, peak, unit). Network kernels and the fitting net against the matrix peak of
+    the precision their GEMMs run in (split BF16: the BF16 peak, three products per algorithmic
+    flop, so a saturated kernel would show 1/3); tabulated embedding kernels (no GEMM) against the
+    vector peak of their precision; the neighbour list against HBM."""
+    if stage == "nlist":
         bytes_ = natoms * (nc * 28 + 8 + 24 + 4)
         return "hbm", bytes_ / 1e9, PEAK["hbm"], "GB/s"
-    if precision == "fp64":
-        return "mfma", flops / 1e12, PEAK["fp64_mfma"], "TFLOP/s"
-    if stage in VALU_FLOP_PER_PAIR:
-        return "alu", VALU_FLOP_PER_PAIR[stage] * npairs / 1e12, PEAK["fp32_valu"], "TFLOP/s"
-    return "mfma", flops / 1e12, PEAK["bf16_mfma"], "TFLOP/s"
+    if stage == "fit":
+        return "mfma", FIT_ATOM * natoms / 1e12, matrix_peak(precision), "TFLOP/s"
+    if table:
+        # the forward pass needs G only; the adjoint needs G and dG/ds
+        per = (TAB_VAL_PAIR + CONTRACT_FWD if stage == "embed_fwd" else TAB_VAL_PAIR + TAB_DER_PAIR + CONTRACT_BWD) + ENV_PAIR
+        peak = PEAK["fp64"] if precision == "fp64" else PEAK["fp32_valu"]
+        return "alu", per * npairs / 1e12, peak, "TFLOP/s"
+    per = NET_PAIR + ENV_PAIR + (CONTRACT_FWD if stage == "embed_fwd" else CONTRACT_BWD)
+    return "mfma", per * npairs / 1e12, matrix_peak(precision), "TFLOP/s"
+
+
+def stage_rooflines(stage_ms: dict, precision: str, natoms: int, npairs: int, nc: int, table: bool = False):
+    out = {}
+    for st in ("nlist", "embed_fwd", "fit", "embed_bwd"):
+        b_, a_, p_, u_ = work_per_launch(st, precision, natoms, npairs, nc, table)
+        ach = a_ / (stage_ms[st] * 1e-3)
+        out[st] = {"bound": b_, "achieved": ach, "peak": p_, "unit": u_, "frac": ach / p_, "ms": stage_ms[st]}
+        if not table and precision in ("mixed", "bf16") and st in VALU_FLOP_PER_PAIR:
+            v = VALU_FLOP_PER_PAIR[st] * npairs / 1e12 / (stage_ms[st] * 1e-3)
+            out[st]["valu_view"] = {"achieved": v, "peak": PEAK["fp32_valu"], "unit": "TFLOP/s",
+                                    "frac": v / PEAK["fp32_valu"]}
+    return out
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_water12288.txt")
@@ -106,7 +137,7 @@ def stored_traffic(stage: str, precision: str):
     return None
 
 
-def serving_bench(dpk, synth, n_sims=16, steps=16, slots=4, load=0.7, seed=2023, budget_frames=8.0):
+def serving_bench(dpk, synth, n_sims=16, steps=16, slots=4, load=0.7, seed=2023, budget_frames=3.0):
     """Requests from n_sims concurrent simulations (sizes log-uniform in [50, 3000], 2-type 1:2 or
     3-type 2:1:1 frames at 0.1 atoms/A^3; consecutive frames of a simulation are small random
     displacements), round-robin over the simulations. First all requests at once (saturated
@@ -191,45 +222,148 @@ def _serving_timed(srv, sims, reqs, rng, load, slots, budget, n_sims):
             "mean_batch_poisson": batch_poisson, "precision": "mixed"}
 
 
-def tabulated_bench(dpk, synth, torch, steps, warmup):
-    """The 32,000-atom fcc box (20^3 cells, rc 8.0 A, sel 138) with the tabulated embedding (stride
-    0.01): ms/step, atom-steps/s and stage times of the mixed and FP64 paths. Its parity with the
-    oracle's table is tested at this size; here it is timed only."""
-    c, t, b = synth.fcc_32000()
+def time_frame(dpk, torch, model, prec, c, t, b, steps, warmup, median_of=0):
+    """Device-resident timing of one frame: warm-up, then `steps` evaluations back to back (mean
+    ms/step) with the stage profiler on; with median_of > 0 also that many single synchronised
+    evaluations (median ms). Returns the result dict and the context (caller closes it)."""
     n = len(t)
-    model = dpk.Model(synth.FCC_MODEL, synth.fcc_params()).tabulate(0.01, 0.5)
     dev = torch.device("cuda:0")
     coord = torch.tensor(c, dtype=torch.float64, device=dev)
     atype = torch.tensor(t, dtype=torch.int32, device=dev)
     energy = torch.zeros(1, dtype=torch.float64, device=dev)
     force = torch.zeros((n, 3), dtype=torch.float64, device=dev)
     virial = torch.zeros(9, dtype=torch.float64, device=dev)
+    ctx = dpk.Context(model, precision=prec)
+    for _ in range(warmup):
+        ctx.compute_device(coord, atype, b, energy, force, virial)
+    ctx.check()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.compute_device(coord, atype, b, energy, force, virial)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage_ms, nframes = ctx.profile_read()
+    ctx.profile(False)
+    ctx.check()
+    ms = (t1 - t0) * 1e3 / steps
+    out = dict(ms_per_step=ms, value=n / (ms * 1e-3), stage_ms={k: v / nframes for k, v in stage_ms.items()},
+               stats=ctx.stats())
+    if median_of:
+        single = []
+        for _ in range(median_of):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            ctx.compute_device(coord, atype, b, energy, force, virial)
+            torch.cuda.synchronize()
+            single.append((time.perf_counter() - ts) * 1e3)
+        ctx.check()
+        out["median_ms"] = float(np.median(single))
+        out["median_value"] = n / (out["median_ms"] * 1e-3)
+    out["force"] = force.cpu().numpy().copy()
+    out["energy"] = float(energy.item())
+    out["virial"] = virial.cpu().numpy().reshape(3, 3).copy()
+    out["_inputs"] = (coord, atype, energy, force, virial)
+    return out, ctx
+
+
+def e2e(workload: str, prec: str, value: float):
+    ceil = CEILING.get((workload, prec))
+    return None if ceil is None else {"ceiling": ceil, "unit": "atom-steps/s", "frac": value / ceil}
+
+
+def public(run: dict, keep=("ms_per_step", "value", "median_ms", "median_value", "stage_ms")):
+    return {k: run[k] for k in keep if k in run}
+
+
+def tabulated_bench(dpk, synth, torch, steps, warmup, precisions):
+    """The 32,000-atom fcc box (20^3 cells, rc 8.0 A, sel 138) with the tabulated embedding (stride
+    0.01): ms/step, atom-steps/s, stage times and stage rooflines per precision. Its parity with
+    the oracle's table is tested at this size; here it is timed only."""
+    c, t, b = synth.fcc_32000()
+    n = len(t)
+    model = dpk.Model(synth.FCC_MODEL, synth.fcc_params()).tabulate(0.01, 0.5)
     out = {"workload": "fcc metal, 32,000 atoms (20^3 cells, a 3.6 A, jitter 0.05 A), periodic; se_e2_a rc 8.0 A, "
                        "rc_smth 2.0 A, sel [138], tabulated embedding (stride 0.01), fitting (240,240,240,1)",
            "atoms": n}
-    for prec in ("mixed", "fp64"):
-        ctx = dpk.Context(model, precision=prec)
-        for _ in range(warmup):
-            ctx.compute_device(coord, atype, b, energy, force, virial)
-        ctx.check()
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            ctx.compute_device(coord, atype, b, energy, force, virial)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        stage_ms, nframes = ctx.profile_read()
-        ctx.profile(False)
-        ctx.check()
-        ms = (t1 - t0) * 1e3 / steps
-        out[prec] = {"ms_per_step": ms, "value": n / (ms * 1e-3),
-                     "stage_ms": {k: v / nframes for k, v in stage_ms.items()},
-                     "neighbours_dropped_by_sel": ctx.stats()["nbr_dropped"]}
-        print(f"# tabulated fcc32000 {prec}: {ms:.3f} ms/step, {n / (ms * 1e-3):.4g} atom-steps/s, stages (ms) "
-              + ", ".join(f"{k} {v:.3f}" for k, v in out[prec]["stage_ms"].items()), file=sys.stderr, flush=True)
+    npairs = None
+    for prec in precisions:
+        r, ctx = time_frame(dpk, torch, model, prec, c, t, b, steps, warmup)
+        if npairs is None:
+            npairs = int((ctx.debug_nlist(n) >= 0).sum())
+            out["neighbour_pairs"] = npairs
         ctx.close()
+        out[prec] = public(r)
+        out[prec]["neighbours_dropped_by_sel"] = r["stats"]["nbr_dropped"]
+        out[prec]["stage_roofline"] = stage_rooflines(r["stage_ms"], prec, n, npairs, model.nc, table=True)
+        out[prec]["e2e_roofline"] = e2e("fcc_table", prec, r["value"])
+        print(f"# tabulated fcc32000 {prec}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4g} atom-steps/s, stages (ms) "
+              + ", ".join(f"{k} {v:.3f}" for k, v in r["stage_ms"].items()), file=sys.stderr, flush=True)
     return out
+
+
+def large_bench(dpk, synth, torch, precisions, median_of=10):
+    """The 110,592-atom water box (36,864 molecules at water density, 103.38 A): median of
+    `median_of` synchronised evaluations per precision, with stage times."""
+    c, t, b = synth.water_110592()
+    n = len(t)
+    model = dpk.Model(synth.WATER_MODEL, synth.water_params())
+    out = {"workload": "water-like box, 110,592 atoms (36,864 molecules), cubic 103.38 A periodic, water model",
+           "atoms": n}
+    for prec in precisions:
+        r, ctx = time_frame(dpk, torch, model, prec, c, t, b, 3, 2, median_of=median_of)
+        ctx.close()
+        out[prec] = public(r)
+        out[prec]["e2e_roofline"] = e2e("water", prec, r["median_value"])
+        print(f"# water110592 {prec}: median {r['median_ms']:.3f} ms/step, {r['median_value']:.4g} atom-steps/s",
+              file=sys.stderr, flush=True)
+    return out
+
+
+def host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "logical_cpus": os.cpu_count()}
+
+
+def cpu_baseline(synth, c, t, b):
+    """The FP64 oracle (test infrastructure, never tuned) on the host: the full 12,288-atom frame
+    once on all threads (also the reference of the force errors), and the 192-atom box on one
+    thread. A bounded sample: about 1-3 s of CPU work."""
+    from oracle import Oracle
+    o = Oracle(synth.WATER_MODEL, synth.water_params())
+    threads = o.threads()
+    ts = time.perf_counter()
+    ref = o.compute(c, t, b)
+    full = time.perf_counter() - ts
+    c0, t0, b0 = synth.water_192()
+    o.set_threads(1)
+    reps, el = 0, 0.0
+    while reps < 20 and (reps == 0 or el < 1.0):
+        ts = time.perf_counter()
+        o.compute(c0, t0, b0)
+        el += time.perf_counter() - ts
+        reps += 1
+    o.set_threads(threads)
+    info = host_cpu()
+    cpu = {"value": len(t) / full, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"the full 12,288-atom frame (E+F+virial) once on {threads} OpenMP threads, {full:.2f} s",
+           "single_thread": {"value": len(t0) * reps / el, "unit": "atom-steps/s",
+                             "sample": f"the 192-atom water box, {reps} evaluations on 1 thread, {el:.2f} s"},
+           **info}
+    return cpu, ref
 
 
 def main():
@@ -240,6 +374,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (latency) section")
     ap.add_argument("--no-table", action="store_true", help="skip the tabulated-embedding (fcc) section")
+    ap.add_argument("--no-large", action="store_true", help="skip the 110,592-atom water box")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device-to-device (the reference for hardware byte counters)")
     args = ap.parse_args()
@@ -261,39 +396,14 @@ def main():
     c, t, b = synth.water_12288()
     n = len(t)
     model = dpk.Model(synth.WATER_MODEL, synth.water_params())
-    dev = torch.device("cuda:0")
-    coord = torch.tensor(c, dtype=torch.float64, device=dev)
-    atype = torch.tensor(t, dtype=torch.int32, device=dev)
-    energy = torch.zeros(1, dtype=torch.float64, device=dev)
-    force = torch.zeros((n, 3), dtype=torch.float64, device=dev)
-    virial = torch.zeros(9, dtype=torch.float64, device=dev)
     runs = {}
     npairs = None
-    for prec in ("fp64", "mixed"):
-        ctx = dpk.Context(model, precision=prec)
-        for _ in range(args.warmup):
-            ctx.compute_device(coord, atype, b, energy, force, virial)
-        ctx.check()
+    for prec in PRECISIONS_TIMED:
+        r, ctx = time_frame(dpk, torch, model, prec, c, t, b, args.steps, args.warmup)
         if npairs is None:
             npairs = int((ctx.debug_nlist(n) >= 0).sum())
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ctx.compute_device(coord, atype, b, energy, force, virial)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        stage_ms, nframes = ctx.profile_read()
-        ctx.profile(False)
-        ctx.check()
-        st = ctx.stats()
-        ms = (t1 - t0) * 1e3 / args.steps
-        runs[prec] = dict(ms_per_step=ms, value=n / (ms * 1e-3),
-                          stage_ms={k: v / nframes for k, v in stage_ms.items()},
-                          force=force.cpu().numpy().copy(), energy=float(energy.item()),
-                          virial=virial.cpu().numpy().reshape(3, 3).copy(), stats=st)
-        print(f"# {prec}: {ms:.3f} ms/step, {n / (ms * 1e-3):.4g} atom-steps/s, stages (ms) "
-              + ", ".join(f"{k} {v:.3f}" for k, v in runs[prec]["stage_ms"].items()), file=sys.stderr, flush=True)
+        print(f"# {prec}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4g} atom-steps/s, stages (ms) "
+              + ", ".join(f"{k} {v:.3f}" for k, v in r["stage_ms"].items()), file=sys.stderr, flush=True)
         # the same frame through the host-buffer entry point (synchronous; host-to-device and
         # device-to-host copies included): reported beside the device-resident rate, never as it
         ctx.compute(c, t, b)
@@ -301,34 +411,26 @@ def main():
         t0 = time.perf_counter()
         for _ in range(hreps):
             ctx.compute(c, t, b)
-        runs[prec]["host_buffer_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / hreps
-        print(f"# {prec}: host-buffer entry point {runs[prec]['host_buffer_ms_per_step']:.3f} ms/step",
+        r["host_buffer_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / hreps
+        print(f"# {prec}: host-buffer entry point {r['host_buffer_ms_per_step']:.3f} ms/step",
               file=sys.stderr, flush=True)
         ctx.close()
+        runs[prec] = r
 
+    large = None if args.no_large else large_bench(dpk, synth, torch, ("fp64", "mixed"))
     tabulated = None if args.no_table else tabulated_bench(dpk, synth, torch, max(1, args.steps // 2),
-                                                            max(1, args.warmup // 2))
+                                                            max(1, args.warmup // 2), TABLE_PRECISIONS)
     serving = None if args.no_serving else serving_bench(dpk, synth)
     if serving:
         print(f"# serving: p50 {serving['p50_ms']:.3f} ms, p99 {serving['p99_ms']:.3f} ms at "
               f"{serving['arrival_rate_req_per_s']:.0f} req/s; saturated {serving['saturated_atom_steps_per_s']:.4g} "
               f"atom-steps/s; mean batch {serving['mean_batch_saturated']:.1f} (saturated), "
-              f"{serving['mean_batch_poisson']:.1f} (Poisson)", file=sys.stderr, flush=True)
+              f"{serving['mean_batch_poisson']:.1f} (Poisson), budget waits {serving['budget_waits']}",
+              file=sys.stderr, flush=True)
 
-    cpu = None
-    errs = {}
+    cpu, errs = None, {}
     if not args.no_cpu:
-        from oracle import Oracle
-        o = Oracle(synth.WATER_MODEL, synth.water_params())
-        reps, elapsed, ref = 0, 0.0, None
-        # whole frames until about 10 s of oracle work (at least one, at most 30)
-        while reps < 30 and (reps == 0 or elapsed < 10.0):
-            ts = time.perf_counter()
-            ref = o.compute(c, t, b)
-            elapsed += time.perf_counter() - ts
-            reps += 1
-        cpu = {"value": n * reps / elapsed, "unit": "atom-steps/s", "cores": o.threads(), "kind": "oracle",
-               "sample": f"the full 12,288-atom frame (E+F+virial), {reps} evaluation(s), {elapsed:.1f} s"}
+        cpu, ref = cpu_baseline(synth, c, t, b)
         for prec, r in runs.items():
             d = r["force"] - ref["force"]
             errs[prec] = {"max_abs_force_err": float(np.abs(d).max()),
@@ -338,20 +440,24 @@ def main():
         errs["rms_force"] = float(np.sqrt((ref["force"] ** 2).mean()))
 
     head = runs["mixed"]
-    dom = max(head["stage_ms"], key=head["stage_ms"].get)
-    bound, amount, peak, unit = work_per_launch(dom, "mixed", n, npairs, model.nc)
-    achieved = amount / (head["stage_ms"][dom] * 1e-3)
-    roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": stored_traffic(dom, "mixed")}
-    stage_roof = {}
-    for st in ("nlist", "embed_fwd", "fit", "embed_bwd"):
-        b_, a_, p_, u_ = work_per_launch(st, "mixed", n, npairs, model.nc)
-        ach = a_ / (head["stage_ms"][st] * 1e-3)
-        stage_roof[st] = {"bound": b_, "achieved": ach, "peak": p_, "unit": u_, "frac": ach / p_,
-                          "ms": head["stage_ms"][st]}
-    fp64_dom = max(runs["fp64"]["stage_ms"], key=runs["fp64"]["stage_ms"].get)
-    b2, a2, p2, u2 = work_per_launch(fp64_dom, "fp64", n, npairs, model.nc)
-    ach2 = a2 / (runs["fp64"]["stage_ms"][fp64_dom] * 1e-3)
+    stage_roof = {p: stage_rooflines(r["stage_ms"], p, n, npairs, model.nc) for p, r in runs.items()}
+    kernel_stages = ("nlist", "embed_fwd", "fit", "embed_bwd")
+    dom = max(kernel_stages, key=lambda k: head["stage_ms"][k])
+    sr = stage_roof["mixed"][dom]
+    roof = {"kernel": dom, "bound": sr["bound"], "achieved": sr["achieved"], "peak": sr["peak"], "unit": sr["unit"],
+            "frac": sr["frac"], "traffic": stored_traffic(dom, "mixed")}
+    if "valu_view" in sr:
+        roof["valu_view"] = sr["valu_view"]
+    others = {}
+    for p, r in runs.items():
+        if p == "mixed":
+            continue
+        d = max(kernel_stages, key=lambda k: r["stage_ms"][k])
+        q = stage_roof[p][d]
+        others[p] = dict(public(r), host_buffer_ms_per_step=r["host_buffer_ms_per_step"],
+                         roofline={"kernel": d, "bound": q["bound"], "achieved": q["achieved"], "peak": q["peak"],
+                                   "unit": q["unit"], "frac": q["frac"], "traffic": stored_traffic(d, p)},
+                         e2e_roofline=e2e("water", p, r["value"]))
 
     line = {
         "metric": "atom-steps/s (E+F+virial) mixed vs FP64 at stated force error; p50/p99 latency",
@@ -370,22 +476,24 @@ def main():
                                "se_e2_a rc 6.0 A, rc_smth 0.5 A, sel [46,92], embedding (25,50,100), "
                                "M_< 16, fitting (240,240,240,1), 2 types",
                    "atoms": n, "neighbour_pairs": npairs, "mode": "mixed"},
-        "fp64": {"value": runs["fp64"]["value"], "ms_per_step": runs["fp64"]["ms_per_step"],
-                 "stage_ms": runs["fp64"]["stage_ms"],
-                 "roofline": {"kernel": fp64_dom, "bound": b2, "achieved": ach2, "peak": p2, "unit": u2,
-                              "frac": ach2 / p2, "traffic": stored_traffic(fp64_dom, "fp64")}},
+        "roofline": roof,
+        "e2e_roofline": e2e("water", "mixed", head["value"]),
+        "cpu_baseline": cpu,
         "mixed_stage_ms": head["stage_ms"],
         "host_buffer_ms_per_step": {p: runs[p]["host_buffer_ms_per_step"] for p in runs},
         "speedup_mixed_vs_fp64": head["value"] / runs["fp64"]["value"],
         "force_error_vs_oracle": errs or None,
-        "roofline": roof,
         "stage_roofline": stage_roof,
+        "large_frame": large,
         "tabulated": tabulated,
         "serving": serving,
-        "cpu_baseline": cpu,
     }
+    line.update(others)
     print(json.dumps(line))
 
+
+PRECISIONS_TIMED = ("fp64", "mixed")
+TABLE_PRECISIONS = ("mixed", "fp64")
 
 if __name__ == "__main__":
     main()

@@ -131,11 +131,13 @@ int dpk_compute(dpk_ctx *c, int64_t natoms, const double *coord, const int32_t *
  * HOST pointer (9 doubles) or NULL. All work is enqueued on hip_stream (a hipStream_t, NULL for
  * the default stream) and the call returns without waiting, except with box == NULL, where it
  * waits once for the cluster's bounding box. The outputs are valid once the stream reaches this
- * point. Type-range and overflow errors found on the device are reported by the next
- * dpk_ctx_check() (or the next call of a synchronising entry point). The per-atom candidate
- * buffer of the neighbour search is sized from the frame's mean density (twice the expected count
- * within r_c, at least 256, at most 1024); a frame with a locally denser spot can report
- * DPK_E_NBR_OVERFLOW here, where dpk_compute reruns it with the 1024-entry buffer. */
+ * point. The call itself returns only argument, box, budget and launch errors: errors found on
+ * the device (an atom type out of range, DPK_E_TYPE_RANGE; a candidate-buffer overflow,
+ * DPK_E_NBR_OVERFLOW, after which that frame's E, F and virial are not valid) are reported by the
+ * next dpk_ctx_check(). The per-atom candidate buffer of the neighbour search is sized from the
+ * frame's mean density (twice the expected count within r_c, at least 256, at most 1024) unless
+ * dpk_ctx_set_candidate_capacity fixed it; after an overflow the caller reruns the frame with
+ * the 1024-entry buffer, as dpk_compute does by itself. */
 int dpk_compute_device(dpk_ctx *c, int64_t natoms, const double *d_coord,
                        const int32_t *d_atype, const double *box, double *d_energy,
                        double *d_force, double *d_virial, double *d_atom_energy,
@@ -143,6 +145,12 @@ int dpk_compute_device(dpk_ctx *c, int64_t natoms, const double *d_coord,
 
 /* Wait for the context's last stream and report device-side errors of the last frame. */
 int dpk_ctx_check(dpk_ctx *c);
+
+/* Candidate-buffer entries per atom of the neighbour search for the frames that follow: 0 (sized
+ * from each frame's mean density, the default), 256, 512 or 1024 (the largest; a frame that
+ * overflows it has more than 1024 atoms within r_c of one atom). Any other value is
+ * DPK_E_INVALID_ARG. Open clusters always use 1024. */
+int dpk_ctx_set_candidate_capacity(dpk_ctx *c, int entries);
 
 int dpk_ctx_stats(dpk_ctx *c, dpk_stats *out);
 
@@ -216,6 +224,10 @@ int dpk_server_submit(dpk_server *s, const dpk_frame *f, uint64_t *ticket);
 int dpk_server_poll(dpk_server *s, uint64_t ticket, int *done);
 /* Block until the frame finishes; returns its result code (error text via dpk_last_error). */
 int dpk_server_wait(dpk_server *s, uint64_t ticket);
+/* Forget a finished frame's record (its result code and times); the ticket is unknown afterwards.
+ * DPK_E_INVALID_ARG if the frame is still queued or running. Records of finished frames are kept
+ * until released (or until dpk_server_free). */
+int dpk_server_release(dpk_server *s, uint64_t ticket);
 /* Host steady-clock nanoseconds of the frame's submission, start on the device and completion
  * (times[3]); valid once the frame is done. */
 int dpk_server_times(dpk_server *s, uint64_t ticket, int64_t *times);

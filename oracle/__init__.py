@@ -57,6 +57,8 @@ def _load():
             lib.orc_compute.argtypes = [mp, C.c_long, dp, ip, dp, C.c_int, dp, C.c_double, C.c_int,
                                         dp, dp, dp, dp, lp, lp, ip, dp, dp]
             lib.orc_num_threads.restype = C.c_int
+            lib.orc_set_num_threads.argtypes = [C.c_int]
+            lib.orc_set_num_threads.restype = None
             _lib = lib
     return _lib
 
@@ -172,3 +174,6 @@ class Oracle:
 
     def threads(self) -> int:
         return self.lib.orc_num_threads()
+
+    def set_threads(self, n: int):
+        self.lib.orc_set_num_threads(int(n))

@@ -4,6 +4,6 @@ Submodules:
   synth    seeded synthetic frames and random-initialised parameters (no method arithmetic)
   dpk      ctypes binding of the HIP library libdpk.so (C ABI declared in include/dpk.h)
   torch_op torch.autograd.Function over the device entry point
-  serving  continuous-batching request loop over the device entry points
+  build    in-tree build of libdpk.so (hipcc, gfx950)
 """
 __all__ = ["synth"]

@@ -266,6 +266,7 @@ struct dpk_ctx {
     // frame being set up (for the candidate-buffer estimate) and the overflow retry switch
     int64_t cur_natoms = 0;
     bool force_big_cap = false;
+    int cap_fixed = 0;                   // candidate-buffer entries set by the caller (0: estimated)
     // last frame
     int64_t last_n = 0;
     // stage profiler: one set of DPK_NSTAGES + 1 events per profiled frame
@@ -429,7 +430,9 @@ int setup_geometry(dpk_ctx* c, const double* box, const double* bbox, GeomParams
         // expected atoms within r_c at the frame's mean density, doubled plus a margin
         const double expect = (double)c->cur_natoms / det * 4.18879020478639 * rc * rc * rc;
         const double want = 2.0 * expect + 64.0;
-        gp.cap = c->force_big_cap ? NL_CAP : (want <= 256.0 ? 256 : (want <= 512.0 ? 512 : NL_CAP));
+        gp.cap = c->force_big_cap ? NL_CAP
+                 : c->cap_fixed     ? c->cap_fixed
+                                    : (want <= 256.0 ? 256 : (want <= 512.0 ? 512 : NL_CAP));
         if ((2 * gp.K[0] + 1) * (2 * gp.K[1] + 1) * (2 * gp.K[2] + 1) > NL_STENCIL)
             return fail(DPK_E_BOX, "cell too thin for r_c: a width below r_c/3 needs more than %d image bins", NL_STENCIL);
     } else {
@@ -937,6 +940,15 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     HIPCHK(hipGetLastError());
     c->last_stream = s;
     c->last_n = n;
+    return DPK_OK;
+}
+
+int dpk_ctx_set_candidate_capacity(dpk_ctx* c, int entries)
+{
+    if (!c) return fail(DPK_E_INVALID_ARG, "NULL context");
+    if (entries != 0 && entries != 256 && entries != 512 && entries != NL_CAP)
+        return fail(DPK_E_INVALID_ARG, "candidate capacity must be 0, 256, 512 or %d", NL_CAP);
+    c->cap_fixed = entries;
     return DPK_OK;
 }
 
@@ -1680,6 +1692,18 @@ int dpk_server_times(dpk_server* s, uint64_t ticket, int64_t* times)
     times[0] = it->second->t_submit;
     times[1] = it->second->t_start;
     times[2] = it->second->t_done;
+    return DPK_OK;
+}
+
+int dpk_server_release(dpk_server* s, uint64_t ticket)
+{
+    if (!s) return fail(DPK_E_INVALID_ARG, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(DPK_E_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    if (it->second->state != 2)
+        return fail(DPK_E_INVALID_ARG, "ticket %llu is still queued or running", (unsigned long long)ticket);
+    s->reqs.erase(it);
     return DPK_OK;
 }
 

@@ -69,6 +69,7 @@ def lib():
         L.dpk_compute.argtypes = [vp, C.c_int64, dp, ip, dp, dp, dp, dp, dp]
         L.dpk_compute_device.argtypes = [vp, C.c_int64, vp, vp, dp, vp, vp, vp, vp, vp]
         L.dpk_ctx_check.argtypes = [vp]
+        L.dpk_ctx_set_candidate_capacity.argtypes = [vp, C.c_int]
         L.dpk_ctx_stats.argtypes = [vp, C.POINTER(_Stats)]
         L.dpk_ctx_profile.argtypes = [vp, C.c_int]
         L.dpk_ctx_profile_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
@@ -194,6 +195,27 @@ class Context:
     def check(self):
         _check(lib().dpk_ctx_check(self.handle))
 
+    def set_candidate_capacity(self, entries: int):
+        """Candidate-buffer entries per atom for the following frames (0 = from the density)."""
+        _check(lib().dpk_ctx_set_candidate_capacity(self.handle, int(entries)))
+
+    def compute_device_checked(self, coord, atype, box, energy, force, virial, atom_energy=None, stream=None):
+        """compute_device, then wait for the frame and report its device-side errors; a frame that
+        overflowed the candidate buffer sized from its mean density runs once more with the
+        largest buffer (as the host-buffer entry point does)."""
+        self.compute_device(coord, atype, box, energy, force, virial, atom_energy, stream)
+        try:
+            self.check()
+        except DpkError as e:
+            if e.code != DPK_E_NBR_OVERFLOW:
+                raise
+            self.set_candidate_capacity(1024)
+            try:
+                self.compute_device(coord, atype, box, energy, force, virial, atom_energy, stream)
+                self.check()
+            finally:
+                self.set_candidate_capacity(0)
+
     def stats(self) -> dict:
         s = _Stats()
         _check(lib().dpk_ctx_stats(self.handle, C.byref(s)))
@@ -249,6 +271,7 @@ def _server_sigs(L):
     L.dpk_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int)]
     L.dpk_server_wait.argtypes = [vp, C.c_uint64]
     L.dpk_server_times.argtypes = [vp, C.c_uint64, i64p]
+    L.dpk_server_release.argtypes = [vp, C.c_uint64]
     L.dpk_server_stats.argtypes = [vp, C.POINTER(_Counters)]
     L.dpk_server_free.argtypes = [vp]
     L.dpk_server_free.restype = None
@@ -272,10 +295,12 @@ def admit_plan(busy, slot_bytes, slot_sim, need, simulation=-1, budget=0, model_
 
 
 class Ticket:
-    """A submitted frame: keeps its host buffers alive until the result is read."""
+    """A submitted frame. The server holds the frame's host buffers until the frame has finished,
+    whether or not this object is still alive; dropping it releases the server's record of the
+    frame (at once if the frame has finished, else once it has)."""
 
-    def __init__(self, server, tid, keep, out):
-        self.server, self.id, self._keep, self.out = server, tid, keep, out
+    def __init__(self, server, tid, out):
+        self.server, self.id, self.out = server, tid, out
 
     def done(self) -> int:
         return self.server.poll(self)
@@ -283,6 +308,11 @@ class Ticket:
     def result(self) -> dict:
         self.server.wait(self)
         return self.out
+
+    def __del__(self):
+        srv = getattr(self, "server", None)
+        if srv is not None:
+            srv._drop(self.id)
 
 
 class Server:
@@ -293,6 +323,11 @@ class Server:
         L = lib()
         _server_sigs(L)
         self.model = model
+        # frames not yet seen finished: ticket id -> the host buffers the server reads and writes
+        # (kept here, not only in the Ticket, so that a dropped Ticket cannot free them early)
+        self._live = {}
+        self._orphans = set()   # dropped tickets whose frames had not finished yet
+        self._nsub = 0
         h = C.c_void_p()
         _check(L.dpk_server_create(model.handle, device, PRECISIONS[precision], nslots, budget_bytes, C.byref(h)))
         self.handle = h
@@ -308,15 +343,45 @@ class Server:
         t = C.c_uint64()
         _check(lib().dpk_server_submit(self.handle, C.byref(fr), C.byref(t)))
         out = {"energy_buf": e, "force": f, "virial_buf": v, "atom_energy": ae}
-        return Ticket(self, t.value, (coord, atype, box), out)
+        self._live[t.value] = (coord, atype, box, out)
+        self._nsub += 1
+        if self._nsub % 64 == 0:
+            self._reap()
+        return Ticket(self, t.value, out)
 
-    def poll(self, ticket: Ticket) -> int:
+    def _state(self, tid: int) -> int:
         d = C.c_int()
-        _check(lib().dpk_server_poll(self.handle, ticket.id, C.byref(d)))
+        _check(lib().dpk_server_poll(self.handle, tid, C.byref(d)))
         return d.value
 
+    def _reap(self):
+        """Drop the buffers of frames that have finished; release the records of dropped tickets."""
+        for tid in list(self._live):
+            if self._state(tid) != 0:
+                del self._live[tid]
+                if tid in self._orphans:
+                    self._orphans.discard(tid)
+                    lib().dpk_server_release(self.handle, tid)
+
+    def _drop(self, tid: int):
+        if getattr(self, "handle", None) is None or _lib is None:
+            return
+        if tid in self._live and self._state(tid) == 0:
+            self._orphans.add(tid)          # released once it has finished
+            return
+        self._live.pop(tid, None)
+        _lib.dpk_server_release(self.handle, tid)
+
+    def poll(self, ticket: Ticket) -> int:
+        d = self._state(ticket.id)
+        if d != 0:
+            self._live.pop(ticket.id, None)
+        return d
+
     def wait(self, ticket: Ticket):
-        _check(lib().dpk_server_wait(self.handle, ticket.id))
+        rc = lib().dpk_server_wait(self.handle, ticket.id)
+        self._live.pop(ticket.id, None)
+        _check(rc)
         o = ticket.out
         o["energy"] = float(o["energy_buf"][0])
         o["virial"] = o["virial_buf"].reshape(3, 3)
@@ -334,8 +399,10 @@ class Server:
 
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:
-            _lib.dpk_server_free(self.handle)
+            _lib.dpk_server_free(self.handle)   # waits for every queued frame
             self.handle = None
+        self._live = {}
+        self._orphans = set()
 
     def __del__(self):
         self.close()

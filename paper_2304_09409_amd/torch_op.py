@@ -20,7 +20,10 @@ class DPEnergyFunction(torch.autograd.Function):
         energy = torch.zeros(1, dtype=torch.float64, device=dev)
         force = torch.empty((n, 3), dtype=torch.float64, device=dev)
         virial = torch.empty((3, 3), dtype=torch.float64, device=dev)
-        context.compute_device(coord.detach().contiguous(), atype, box, energy, force, virial)
+        # waits for the frame: device-side errors (atom types out of range, a candidate buffer
+        # overflowed in a locally dense spot, which is rerun with the largest buffer) are raised
+        # here instead of returning wrong values
+        context.compute_device_checked(coord.detach().contiguous(), atype, box, energy, force, virial)
         fctx.save_for_backward(force)
         fctx.mark_non_differentiable(force, virial)
         return energy, force, virial

@@ -120,7 +120,7 @@ def test_fp64_matches_oracle(dpk, case):
     ctx.close()
 
 
-@pytest.mark.parametrize("case", ["water192", "serve50_3type_small_cell", "serve700_2type", "open_cluster60"])
+@pytest.mark.parametrize("case", list(FRAMES))
 def test_mixed_matches_oracle(dpk, case):
     say(f"mixed {case}")
     mname, make = FRAMES[case]
@@ -133,16 +133,79 @@ def test_mixed_matches_oracle(dpk, case):
     ctx.close()
 
 
-def test_bf16_reports_error(dpk):
-    say("bf16 water192")
-    c, t, b = synth.water_192()
-    spec, params, model = model_of(dpk, "water")
-    ref = oracle_of("water").compute(c, t, b)
+@pytest.mark.parametrize("case", ["water192", "serve700_2type"])
+def test_bf16_within_its_bound(dpk, case):
+    """One BF16 product per GEMM: each operand keeps 8 significant bits (relative rounding 2^-9),
+    so the network's outputs carry errors of order 1e-2 relative. Bound, from a numpy emulation of
+    BF16 operands on the 192-atom box (max 4e-2 eV/A at RMS(F) about 1 eV/A): every force
+    component within 0.15 eV/A and the RMS error within 2 % of RMS(F)."""
+    say(f"bf16 {case}")
+    mname, make = FRAMES[case]
+    c, t, b = make()
+    spec, params, model = model_of(dpk, mname)
+    ref = oracle_of(mname).compute(c, t, b)
     ctx = dpk.Context(model, precision="bf16")
     got = ctx.compute(c, t, b)
-    df = np.abs(got["force"] - ref["force"]).max()
-    print(f"  bf16 max|dF| {df:.3e}", flush=True)
-    assert np.isfinite(got["force"]).all() and df < 0.5
+    d = got["force"] - ref["force"]
+    df = np.abs(d).max()
+    rms, frms = np.sqrt((d ** 2).mean()), np.sqrt((ref["force"] ** 2).mean())
+    print(f"  bf16 max|dF| {df:.3e}  rms|dF| {rms:.3e}  RMS(F) {frms:.3e}", flush=True)
+    assert np.isfinite(got["force"]).all()
+    assert df <= 0.15
+    assert rms <= 0.02 * frms
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_type_one_side_matches_oracle(dpk, precision):
+    """Per-species embedding nets indexed by the neighbour's type only (type_one_side, Sec.
+    II.A.1), with non-unit timestep vectors, on a 3-type frame and a triclinic one."""
+    spec = dict(synth.SERVE_MODEL, type_one_side=True)
+    params = synth.make_params(spec, 31, synth.SERVE_OUT_SCALE, synth.SERVE_FIT_IN, timestep_sigma=0.2)
+    from oracle import Oracle
+    o = Oracle(spec, params)
+    model = dpk.Model(spec, params)
+    ctx = dpk.Context(model, precision=precision)
+    for name, (c, t, b) in (("serve700_3type", synth.serving_frame(700, 19, 3)), ("triclinic400", _triclinic())):
+        say(f"type_one_side {precision} {name}")
+        ref = o.compute(c, t, b)
+        got = ctx.compute(c, t, b)
+        (check_fp64 if precision == "fp64" else check_mixed)(got, ref, len(t))
+    ctx.close()
+
+
+def _fcc_with_close_pairs():
+    """fcc 500-atom box with three atoms pushed towards a neighbour, to 1.55-1.9 A: inside r_s = 2 A,
+    where s = 1/r > 0.5 lies past the table's range [0, 0.5]."""
+    c, t, b = synth.fcc_box(5, 3.6, 1)
+    c = c.copy()
+    for i, r in ((0, 1.55), (100, 1.75), (333, 1.9)):
+        d = c[i] - c[:, :]
+        d -= np.round(d / b[0, 0]) * b[0, 0]
+        dist = np.linalg.norm(d, axis=1)
+        dist[i] = 1e9
+        j = int(np.argmin(dist))
+        u = (c[j] - c[i]) - np.round((c[j] - c[i]) / b[0, 0]) * b[0, 0]
+        u /= np.linalg.norm(u)
+        c[j] = c[i] + r * u
+    return c, t, b
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_table_out_of_range_inputs(dpk, precision):
+    """Table inputs past its range use the last piece extrapolated (reading R9) and are counted:
+    forces against the oracle's evaluation of the same table and the same count."""
+    say(f"table out of range {precision}")
+    spec, params = synth.FCC_MODEL, synth.fcc_params()
+    model = dpk.Model(spec, params).tabulate(0.01, 0.5)
+    o = oracle_of("fcc")
+    c, t, b = _fcc_with_close_pairs()
+    ref = o.compute(c, t, b, table=o.table(0.01, 50), dx=0.01)
+    assert ref["table_oor"] >= 6
+    ctx = dpk.Context(model, precision=precision)
+    got = ctx.compute(c, t, b)
+    (check_fp64 if precision == "fp64" else check_mixed)(got, ref, len(t))
+    assert ctx.stats()["table_out_of_range"] == ref["table_oor"]
     ctx.close()
 
 

@@ -92,6 +92,7 @@ def test_tight_budget_admission(dpk, model):
     ctx.close()
     budget = int(model_bytes + 2.5 * need)
     srv = dpk.Server(model, precision="mixed", nslots=4, budget_bytes=budget)
+    # a full queue: four idle slots, a budget for about two of the largest frames
     tickets = [srv.submit(c, t, b, simulation=k) for k, (c, t, b) in enumerate(fr)]
     outs = [tk.result() for tk in tickets]
     for (c, t, b), a, o in zip(fr, alone, outs):
@@ -100,6 +101,7 @@ def test_tight_budget_admission(dpk, model):
     print(f"  budget {budget} peak {st['peak_bytes']} waits {st['budget_waits']}", flush=True)
     assert st["completed"] == 16
     assert st["peak_bytes"] <= budget
+    assert st["budget_waits"] > 0          # the budget, not the slots, delayed admissions
     srv.close()
 
 
@@ -147,4 +149,59 @@ def test_dense_frame_retried_with_large_buffer(dpk, model):
     st = srv.stats()
     print(f"  stats {st}", flush=True)
     assert st["completed"] == 3 and st["failed"] == 0
+    srv.close()
+
+
+def _dense_frame():
+    # 400 atoms at 3.5x liquid density in a 40 A cell (as above)
+    c, t, _ = synth.serving_frame(400, 5, 3, density=0.35)
+    return c + 15.0, t, np.diag([40.0] * 3)
+
+
+def test_dense_frame_through_autograd(dpk, model):
+    """The autograd forward waits for its frame and reruns a candidate-buffer overflow with the
+    largest buffer: its E, F and virial equal the host entry point's (which does the same)."""
+    import torch
+    from paper_2304_09409_amd.torch_op import DPEnergy
+    say("autograd: locally dense frame")
+    c, t, b = _dense_frame()
+    ctx = dpk.Context(model, precision="mixed")
+    ref = ctx.compute(c, t, b)
+    ctx.close()
+    mod = DPEnergy(model, precision="mixed")
+    coord = torch.tensor(c, device="cuda", requires_grad=True)
+    E, F, V = mod(coord, torch.tensor(t, device="cuda", dtype=torch.int32), b)
+    got = {"energy": E.item(), "force": F.cpu().numpy(), "virial": V.cpu().numpy()}
+    _compare(got, ref, len(t))
+    # an atom type out of range is an error, not a silent result
+    bad = torch.tensor(t, device="cuda", dtype=torch.int32)
+    bad[3] = 7
+    with pytest.raises(dpk.DpkError) as e:
+        mod(coord, bad, b)
+    assert e.value.code == dpk.DPK_E_TYPE_RANGE
+
+
+def test_dropped_tickets(dpk, model):
+    """Tickets dropped before their frames finish: the server keeps the frames' buffers until they
+    are done, every frame completes, and the records of dropped tickets are released."""
+    import gc
+    say("serving: dropped tickets")
+    fr = _frames(40, 31)
+    srv = dpk.Server(model, precision="mixed", nslots=3)
+    for k, (c, t, b) in enumerate(fr):
+        srv.submit(c.copy(), t.copy(), b, simulation=k % 5)   # ticket dropped at once
+    gc.collect()
+    keep = srv.submit(*fr[0])
+    ref = keep.result()
+    ctx = dpk.Context(model, precision="mixed")
+    _compare(ref, ctx.compute(*fr[0]), len(fr[0][1]))
+    ctx.close()
+    import time
+    t0 = time.monotonic()
+    while srv.stats()["completed"] + srv.stats()["failed"] < 41 and time.monotonic() - t0 < 60.0:
+        time.sleep(0.01)
+    srv._reap()
+    st = srv.stats()
+    assert st["completed"] == 41 and st["failed"] == 0
+    assert not srv._orphans and list(srv._live) == []
     srv.close()
