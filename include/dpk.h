@@ -143,6 +143,25 @@ int dpk_compute_device(dpk_ctx *c, int64_t natoms, const double *d_coord,
                        double *d_force, double *d_virial, double *d_atom_energy,
                        void *hip_stream);
 
+/* The device-pointer entry point for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation. Same arguments, layout,
+ * results and stream semantics as dpk_compute_device, with a periodic box required (box == NULL
+ * is DPK_E_INVALID_ARG: an open cluster's bounding box is read back to the host). The call makes
+ * no device allocation and no hipMalloc/hipFree: the frame's workspace (cell list, neighbour
+ * list, descriptor, fitting scratch, block partials, statistics) lives in one fixed region of
+ * 256 MiB per device, part of the library's image and held until the process ends. A frame whose
+ * workspace exceeds it is rejected with DPK_E_BUDGET (with the water model of cfg. sel [46, 92]:
+ * about 24,000 atoms in DPK_MIXED, 11,000 in DPK_FP64). Every call on a device shares that
+ * region, which keeps the last call's contents (the library clears what must start at zero):
+ * calls that overlap on one device, from any context or thread, race and give wrong results, so
+ * the caller serialises them (one stream, or events). dpk_ctx_check, dpk_ctx_stats and the debug
+ * dumps after such a call read the region; the context's own workspace is left as it was. The
+ * stage profiler records nothing for these calls. */
+int dpk_compute_device_noalloc(dpk_ctx *c, int64_t natoms, const double *d_coord,
+                               const int32_t *d_atype, const double *box, double *d_energy,
+                               double *d_force, double *d_virial, double *d_atom_energy,
+                               void *hip_stream);
+
 /* Wait for the context's last stream and report device-side errors of the last frame. */
 int dpk_ctx_check(dpk_ctx *c);
 

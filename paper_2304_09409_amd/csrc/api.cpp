@@ -250,6 +250,8 @@ struct dpk_ctx {
     int64_t cap_atoms = 0;
     int64_t cap_cells = 0;
     bool cells_clear = false;            // cell_count is all zero (the multi-block preparation keeps it so)
+    bool views_scratch = false;          // the views below point into the device's shared scratch
+    void* scratch = nullptr;             // that scratch (allocation-free entry point), this device's copy
     // views of the workspace (valid for the capacity)
     int *perm, *inv_perm, *itype, *tcount, *toff, *cell_of, *cell_tmp, *cell_count, *cell_start, *cursor;
     int *nl_j, *nnei, *h_atype, *bcount, *boff;
@@ -354,7 +356,14 @@ inline void prof_mark(std::vector<hipEvent_t>* ev, int k, hipStream_t s)
 
 int ensure_ws(dpk_ctx* c, int64_t n, int64_t ncell)
 {
-    if (n <= c->cap_atoms && ncell <= c->cap_cells && c->ws) return DPK_OK;
+    if (n <= c->cap_atoms && ncell <= c->cap_cells && c->ws) {
+        if (c->views_scratch) {
+            // the last frame ran in the shared scratch: point the views back at this workspace
+            layout_ws(c, c->cap_atoms, c->cap_cells, (char*)c->ws);
+            c->views_scratch = false;
+        }
+        return DPK_OK;
+    }
     int64_t nn = std::max<int64_t>(n, c->cap_atoms), ncl = std::max<int64_t>(ncell, c->cap_cells);
     size_t bytes = layout_ws(c, nn, ncl, nullptr);
     if (c->budget && bytes + c->model_bytes > c->budget)
@@ -377,6 +386,7 @@ int ensure_ws(dpk_ctx* c, int64_t n, int64_t ncell)
     c->cap_atoms = nn;
     c->cap_cells = ncl;
     c->cells_clear = false;
+    c->views_scratch = false;
     layout_ws(c, nn, ncl, (char*)p);
     return DPK_OK;
 }
@@ -652,6 +662,39 @@ void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* F, double* vir
     launch_embed_bwd(c->precision, tab, ea, s);
 }
 
+// The launches of one frame on the views laid out for it. shared: the views point into the
+// device's shared scratch, which keeps whatever the last call left, so the bin counts are cleared
+// every time, and no profiler event is recorded.
+void enqueue_frame(dpk_ctx* c, int n, const double* d_coord, const int* d_atype, const GeomParams& gp,
+                   double* d_energy, double* d_force, double* d_virial, double* d_atom_energy, hipStream_t s,
+                   bool shared)
+{
+    const int nt = c->model->desc.ntypes;
+    // the forces accumulate straight into d_force (caller order), which the preparation zeroes
+    std::vector<hipEvent_t>* ev = shared ? nullptr : prof_frame(c);
+    prof_mark(ev, DPK_STAGE_PREP, s);
+    if (!launch_prep_small(n, d_coord, d_atype, nt, gp, c->tcount, c->toff, c->perm, c->inv_perm, c->itype, c->stats,
+                           c->pos, c->cell_of, c->cell_start, c->cand, d_force, s)) {
+        if (shared) {
+            launch_zero(c->cell_count, sizeof(int) * (size_t)gp.nb[0] * gp.nb[1] * gp.nb[2], s);
+        } else {
+            if (!c->cells_clear) launch_zero(c->cell_count, sizeof(int) * (size_t)c->cap_cells, s);
+            c->cells_clear = false;
+        }
+        launch_prep_large(n, d_coord, d_atype, nt, gp, c->tcount, c->toff, c->bcount, c->boff, c->perm, c->inv_perm,
+                          c->itype, c->stats, c->pos, c->cell_of, c->cell_count, c->cell_start, c->cursor, c->cell_tmp,
+                          c->cand, d_force, s);
+        if (!shared) c->cells_clear = true;   // its scan clears the counts it read
+    }
+    prof_mark(ev, DPK_STAGE_NLIST, s);
+    launch_nlist(n, c->pos, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cand, gp, c->nl_j, c->nl_r, c->nnei,
+                 c->stats, s);
+    run_network(c, n, gp, d_force, nullptr, true, d_atom_energy, ev, s);
+    prof_mark(ev, DPK_STAGE_FINAL, s);
+    launch_finalize(embed_bwd_blocks(c->precision, c->tab, n, c->ncu), c->vir_part, d_energy, d_virial, c->stats, s);
+    prof_mark(ev, DPK_NSTAGES, s);
+}
+
 // One frame of a batch: host copies of the coordinates (for an open cluster's bounding box) and
 // of the cell.
 struct BatchFrame {
@@ -858,6 +901,8 @@ int dpk_ctx_create(const dpk_model* m, int device, int precision, size_t hbm_bud
     }
     int rc = upload_model(c);
     if (rc) { dpk_ctx_free(c); return rc; }
+    // the allocation-free entry point's scratch on this device (looked up once per device)
+    if (scratch_region(device, &c->scratch) != 0) c->scratch = nullptr;
     if (c->budget && c->model_bytes > c->budget) {
         dpk_ctx_free(c);
         return fail(DPK_E_BUDGET, "model needs %zu device bytes, budget %zu", c->model_bytes, hbm_budget_bytes);
@@ -897,7 +942,6 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     if (natoms < 1 || natoms > (1LL << 30)) return fail(DPK_E_INVALID_ARG, "natoms = %lld", (long long)natoms);
     HIPCHK(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)hip_stream;
-    const dpk_model* m = c->model;
     const int n = (int)natoms;
     int rc;
     GeomParams gp;
@@ -915,28 +959,40 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     }
     const int64_t ncell = (int64_t)gp.nb[0] * gp.nb[1] * gp.nb[2];
     if ((rc = ensure_ws(c, n, ncell))) return rc;
-    const int nt = m->desc.ntypes;
+    enqueue_frame(c, n, d_coord, d_atype, gp, d_energy, d_force, d_virial, d_atom_energy, s, false);
+    HIPCHK(hipGetLastError());
+    c->last_stream = s;
+    c->last_n = n;
+    return DPK_OK;
+}
 
-    // the forces accumulate straight into d_force (caller order), which the preparation zeroes
-    std::vector<hipEvent_t>* ev = prof_frame(c);
-    prof_mark(ev, DPK_STAGE_PREP, s);
-    if (!launch_prep_small(n, d_coord, d_atype, nt, gp, c->tcount, c->toff, c->perm, c->inv_perm, c->itype, c->stats,
-                           c->pos, c->cell_of, c->cell_start, c->cand, d_force, s)) {
-        if (!c->cells_clear) launch_zero(c->cell_count, sizeof(int) * (size_t)c->cap_cells, s);
-        c->cells_clear = false;
-        launch_prep_large(n, d_coord, d_atype, nt, gp, c->tcount, c->toff, c->bcount, c->boff, c->perm, c->inv_perm,
-                          c->itype, c->stats, c->pos, c->cell_of, c->cell_count, c->cell_start, c->cursor, c->cell_tmp,
-                          c->cand, d_force, s);
-        c->cells_clear = true;   // its scan clears the counts it read
-    }
-    prof_mark(ev, DPK_STAGE_NLIST, s);
-    launch_nlist(n, c->pos, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cand, gp, c->nl_j, c->nl_r, c->nnei,
-                 c->stats, s);
-
-    run_network(c, n, gp, d_force, nullptr, true, d_atom_energy, ev, s);
-    prof_mark(ev, DPK_STAGE_FINAL, s);
-    launch_finalize(embed_bwd_blocks(c->precision, c->tab, n, c->ncu), c->vir_part, d_energy, d_virial, c->stats, s);
-    prof_mark(ev, DPK_NSTAGES, s);
+int dpk_compute_device_noalloc(dpk_ctx* c, int64_t natoms, const double* d_coord, const int32_t* d_atype,
+                               const double* box, double* d_energy, double* d_force, double* d_virial,
+                               double* d_atom_energy, void* hip_stream)
+{
+    if (!c || !d_coord || !d_atype || !d_energy || !d_force || !d_virial) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    if (!box)
+        return fail(DPK_E_INVALID_ARG, "the allocation-free entry point needs a periodic box (an open cluster's "
+                                       "bounding box is read back to the host; use dpk_compute_device)");
+    if (natoms < 1 || natoms > (1LL << 30)) return fail(DPK_E_INVALID_ARG, "natoms = %lld", (long long)natoms);
+    if (!c->scratch) return fail(DPK_E_DEVICE, "no scratch region on device %d", c->device);
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int n = (int)natoms;
+    int rc;
+    GeomParams gp;
+    c->cur_natoms = natoms;
+    if ((rc = setup_geometry(c, box, nullptr, gp))) return rc;
+    const int64_t ncell = (int64_t)gp.nb[0] * gp.nb[1] * gp.nb[2];
+    const size_t need = layout_ws(c, n, ncell, nullptr);
+    if (need > SCRATCH_BYTES)
+        return fail(DPK_E_BUDGET, "a frame of %lld atoms and %lld bins needs %zu workspace bytes; the "
+                                  "allocation-free entry point holds %zu", (long long)natoms, (long long)ncell, need,
+                    SCRATCH_BYTES);
+    // views into the shared scratch for this frame (the context's own workspace is untouched)
+    layout_ws(c, n, ncell, (char*)c->scratch);
+    c->views_scratch = true;
+    enqueue_frame(c, n, d_coord, d_atype, gp, d_energy, d_force, d_virial, d_atom_energy, s, true);
     HIPCHK(hipGetLastError());
     c->last_stream = s;
     c->last_n = n;

@@ -6,6 +6,13 @@
 namespace dpk {
 
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+// Bytes of the per-device workspace of the allocation-free entry point, and the number of devices
+// it is tracked for.
+constexpr size_t SCRATCH_BYTES = (size_t)256 << 20;
+constexpr int MAX_DEVICES = 64;
+// Device address of that workspace on `device`, which must be the current device (looked up once
+// per device, then cached); 0 on success, -1 if the lookup failed.
+int scratch_region(int device, void** ptr);
 // Preparation of a frame of any size in three launches; cell_count is zero on entry and on exit
 // (the caller clears it once after allocating it); cell_tmp holds n ints of scratch.
 void launch_prep_large(int n, const double* coord, const int* atype, int ntypes, const GeomParams& gp, int* tcount,

@@ -5,6 +5,9 @@
 // neighbour selection (Sec. II.A: n(i), capacities padded to N_c; Sec. III.B.1: order by type,
 // distance, index) is a deterministic function of the input bits.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
+
 #include "dpk_internal.h"
 #include "dpk_launch.h"
 
@@ -24,6 +27,33 @@ void launch_zero(void* p, size_t bytes, hipStream_t s)
     int blocks = (int)((words + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, s, (unsigned int*)p, words);
+}
+
+// Workspace of the allocation-free entry point: one array per device, held from the library's
+// load until the process ends, shared by every call on that device. In host code `scratch` names
+// a host-side stand-in; kernels get the device address that scratch_region looks up.
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+int scratch_region(int device, void** ptr)
+{
+    if (device < 0 || device >= MAX_DEVICES) return -1;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        // the caller has made `device` current: this is that device's copy of the array
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return -1;
+        }
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return 0;
 }
 
 // ---- atom types: validation, counts, stable partition by type (atoms are kept sorted by

@@ -68,6 +68,7 @@ def lib():
         L.dpk_ctx_workspace_bytes.restype = C.c_int64
         L.dpk_compute.argtypes = [vp, C.c_int64, dp, ip, dp, dp, dp, dp, dp]
         L.dpk_compute_device.argtypes = [vp, C.c_int64, vp, vp, dp, vp, vp, vp, vp, vp]
+        L.dpk_compute_device_noalloc.argtypes = [vp, C.c_int64, vp, vp, dp, vp, vp, vp, vp, vp]
         L.dpk_ctx_check.argtypes = [vp]
         L.dpk_ctx_set_candidate_capacity.argtypes = [vp, C.c_int]
         L.dpk_ctx_stats.argtypes = [vp, C.POINTER(_Stats)]
@@ -174,10 +175,12 @@ class Context:
             out["atom_energy"] = ae
         return out
 
-    def compute_device(self, coord, atype, box, energy, force, virial, atom_energy=None, stream=None):
+    def compute_device(self, coord, atype, box, energy, force, virial, atom_energy=None, stream=None,
+                       noalloc: bool = False):
         """torch tensors on the GPU (float64 coord [N,3], int32 atype [N]; outputs float64 energy [1],
         force [N,3], virial [9] or [3,3]); box a host array or None. Asynchronous on `stream`
-        (default: torch's current stream)."""
+        (default: torch's current stream). noalloc: the allocation-free entry point (periodic box,
+        workspace in the device's shared fixed region)."""
         import torch
         n = coord.shape[0]
         for t, dt in ((coord, torch.float64), (atype, torch.int32), (energy, torch.float64),
@@ -187,7 +190,8 @@ class Context:
         if stream is None:
             stream = torch.cuda.current_stream(coord.device)
         hbox = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(9)
-        _check(lib().dpk_compute_device(self.handle, n, coord.data_ptr(), atype.data_ptr(), _dp(hbox),
+        fn = lib().dpk_compute_device_noalloc if noalloc else lib().dpk_compute_device
+        _check(fn(self.handle, n, coord.data_ptr(), atype.data_ptr(), _dp(hbox),
                                         energy.data_ptr(), force.data_ptr(), virial.data_ptr(),
                                         None if atom_energy is None else atom_energy.data_ptr(),
                                         stream.cuda_stream))
