@@ -89,16 +89,43 @@ typedef struct {
     int64_t workspace_bytes;      /* device bytes held by the context                          */
 } dpk_stats;
 
-/* Last error message of the calling thread ("" if none). */
+/* Last error message of the calling thread ("" if none). Never NULL; valid until the next
+ * failing call on the same thread. */
 const char *dpk_last_error(void);
 
-/* Create a model from a description and its FP64 parameter blob (nparams values, layout
- * above). The blob is copied; the caller keeps ownership of params. */
+/* Create a model (Sec. II.A: E = sum_i F_0(D^i); Sec. II.A.1: se_e2_a descriptor with per-species
+ * embedding nets; Sec. II.A.2: per-species fitting nets; Sec. II.A.6, eq. NN: the layer form) from
+ * a description and its FP64 parameter blob of nparams values in the layout above. The blob is
+ * copied; the caller keeps ownership of desc and params. DPK_E_INVALID_ARG for a NULL pointer, a
+ * bad description (ntypes outside 1..8, negative sel, sum of sel outside 1..4096, not
+ * 0 < rcut_smth < rcut) or a blob of the wrong size; DPK_E_UNIMPLEMENTED for widths other than
+ * emb (25, 50, 100), axis 16, fit (240, 240, 240). *out is NULL on failure. */
 int dpk_model_create(const dpk_model_desc *desc, const double *params, int64_t nparams,
                      dpk_model **out);
 
-/* Number of FP64 values the blob of desc must hold. */
+/* Number of FP64 values the blob of desc must hold (the layer sizes of Sec. II.A.1 and II.A.2
+ * with the layout above), or -1 for a NULL desc or ntypes outside 1..8. */
 int64_t dpk_model_param_count(const dpk_model_desc *desc);
+
+/* Read a model file (the frozen model the paper's C API loads, Sec. III.A): the magic
+ * "DPKMODEL", a uint64 little-endian header length, a versioned JSON header (format
+ * "dpk-se_e2_a", version 1: ntypes, sel, rcut, rcut_smth, embedding, axis, fitting,
+ * type_one_side, nparams, compression = null or {stride, x_max}), zero padding to a multiple of 8
+ * bytes, then the FP64 blob (little-endian binary64, layout above). A compressed model's table is
+ * rebuilt from the parameters at load (Sec. II.A.6), exactly as dpk_model_tabulate builds it.
+ * DPK_E_INVALID_ARG for an unreadable, truncated or malformed file (the message says which key);
+ * the checks of dpk_model_create apply. The caller frees *out with dpk_model_free. */
+int dpk_model_load(const char *path, dpk_model **out);
+
+/* Write m to path in the format dpk_model_load reads (for a compressed model, its stride and
+ * range; the table itself is not stored). DPK_E_INVALID_ARG if the file cannot be written. */
+int dpk_model_save(const dpk_model *m, const char *path);
+
+/* Copy out a model's description (desc, if not NULL), its FP64 blob (params, if not NULL:
+ * dpk_model_param_count(desc) values, caller-owned) and its table stride and range (0 for a model
+ * without table). */
+int dpk_model_describe(const dpk_model *m, dpk_model_desc *desc, double *params,
+                       double *tab_stride, double *tab_xmax);
 
 /* Replace the embedding nets by quintic tables (Sec. II.A.6, eq. compress): nodes at
  * x_l = l * stride, l = 0..L_c with L_c = ceil(x_max / stride), values and first and second
@@ -106,29 +133,43 @@ int64_t dpk_model_param_count(const dpk_model_desc *desc);
  * variable is the net input x = s(r). Contexts created afterwards use the table. */
 int dpk_model_tabulate(dpk_model *m, double stride, double x_max);
 
+/* Free a model (NULL is ignored). Contexts created from it must be freed first. */
 void dpk_model_free(dpk_model *m);
 
-/* Create a context on HIP device `device` with precision DPK_FP64, DPK_MIXED or DPK_BF16.
- * hbm_budget_bytes bounds the context's workspace (0 = no bound). strict_sel != 0 makes a
- * neighbour cut by sel an error (DPK_E_NBR_OVERFLOW) instead of a counted truncation. */
+/* Create a context on HIP device `device` with precision DPK_FP64, DPK_MIXED or DPK_BF16 (the
+ * paper's FP64 and reduced-precision inference, Sec. IV; the precision of each step is listed at
+ * the precision enum). The model's weights (and table, if the model is compressed at this point)
+ * are packed for the precision and copied to the device; the model must outlive the context.
+ * hbm_budget_bytes bounds model + workspace (0 = no bound; DPK_E_BUDGET if the model alone
+ * exceeds it). strict_sel != 0 makes a neighbour cut by sel (reading R6 of the design notes: the
+ * nearest sel[t] are kept) an error, DPK_E_NBR_OVERFLOW, instead of a counted truncation.
+ * DPK_E_INVALID_ARG for a NULL pointer, an unknown precision or a missing device. */
 int dpk_ctx_create(const dpk_model *m, int device, int precision, size_t hbm_budget_bytes,
                    int strict_sel, dpk_ctx **out);
 
+/* Wait for the context's work, free its device memory and streams (NULL is ignored). */
 void dpk_ctx_free(dpk_ctx *c);
 
-/* Device bytes of the model plus the workspace of a frame of natoms atoms (cell grid counted at
- * one bin per atom, an upper bound at liquid densities). */
+/* Device bytes of the model plus the workspace of a frame of natoms atoms (neighbour list of N_c
+ * entries per atom, Sec. II.A; descriptor and fitting scratch; the cell grid counted at one bin
+ * per atom, an upper bound at liquid densities); -1 for a NULL context or natoms < 1. */
 int64_t dpk_ctx_workspace_bytes(const dpk_ctx *c, int64_t natoms);
 
-/* Host-pointer entry point: copies the frame to the device, evaluates it and copies the results
- * back; returns after the results are in the caller's buffers. energy: 1 double; force:
- * natoms*3; virial: 9; atom_energy: natoms or NULL. */
+/* Host-pointer entry point: E, F and the virial of one frame (Sec. II.A.2: E = sum_i E_i,
+ * F_i = -dE/dr_i, Xi_ab = -sum_g dE/dh_ga h_gb; atom_energy receives E_i). Copies the frame to the
+ * device, evaluates it and copies the results back; returns after the results are in the
+ * caller's buffers (all host pointers, caller-owned; energy: 1 double; force: natoms*3; virial: 9;
+ * atom_energy: natoms or NULL). A frame that overflows the candidate buffer sized from its mean
+ * density is rerun once with the largest buffer. Errors: DPK_E_INVALID_ARG (NULL, natoms < 1),
+ * DPK_E_TYPE_RANGE, DPK_E_BOX (det h <= 0, or a cell thinner than r_c / 3), DPK_E_NBR_OVERFLOW
+ * (more than 1024 atoms within r_c of one atom, or strict mode and a neighbour cut by sel),
+ * DPK_E_BUDGET, DPK_E_OOM, DPK_E_DEVICE. */
 int dpk_compute(dpk_ctx *c, int64_t natoms, const double *coord, const int32_t *atype,
                 const double *box, double *energy, double *force, double *virial,
                 double *atom_energy);
 
-/* Device-pointer entry point: d_coord, d_atype and the outputs are device pointers; box is a
- * HOST pointer (9 doubles) or NULL. All work is enqueued on hip_stream (a hipStream_t, NULL for
+/* Device-pointer entry point, the same evaluation as dpk_compute (Sec. II.A.2): d_coord,
+ * d_atype and the outputs are device pointers; box is a HOST pointer (9 doubles) or NULL. All work is enqueued on hip_stream (a hipStream_t, NULL for
  * the default stream) and the call returns without waiting, except with box == NULL, where it
  * waits once for the cluster's bounding box. The outputs are valid once the stream reaches this
  * point. The call itself returns only argument, box, budget and launch errors: errors found on
@@ -142,6 +183,15 @@ int dpk_compute_device(dpk_ctx *c, int64_t natoms, const double *d_coord,
                        const int32_t *d_atype, const double *box, double *d_energy,
                        double *d_force, double *d_virial, double *d_atom_energy,
                        void *hip_stream);
+
+/* As dpk_compute_device with the cell h (Sec. II.A.2: h_ab = component b of lattice vector a) in
+ * DEVICE memory: d_box points to 9 doubles on the context's device, or is NULL (open cluster).
+ * The box is read back to the host in stream order (one wait on hip_stream), since the cell list
+ * and the image stencil are set up on the host; everything else is as dpk_compute_device. */
+int dpk_compute_device_dbox(dpk_ctx *c, int64_t natoms, const double *d_coord,
+                            const int32_t *d_atype, const double *d_box, double *d_energy,
+                            double *d_force, double *d_virial, double *d_atom_energy,
+                            void *hip_stream);
 
 /* The device-pointer entry point for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation. Same arguments, layout,
@@ -162,7 +212,9 @@ int dpk_compute_device_noalloc(dpk_ctx *c, int64_t natoms, const double *d_coord
                                double *d_force, double *d_virial, double *d_atom_energy,
                                void *hip_stream);
 
-/* Wait for the context's last stream and report device-side errors of the last frame. */
+/* Wait for the context's last stream and report device-side errors of the last frame:
+ * DPK_E_TYPE_RANGE, DPK_E_NBR_OVERFLOW (candidate buffer, or a cut by sel in strict mode), or a
+ * failed HIP call (DPK_E_DEVICE); DPK_OK before any frame. */
 int dpk_ctx_check(dpk_ctx *c);
 
 /* Candidate-buffer entries per atom of the neighbour search for the frames that follow: 0 (sized
@@ -171,6 +223,10 @@ int dpk_ctx_check(dpk_ctx *c);
  * DPK_E_INVALID_ARG. Open clusters always use 1024. */
 int dpk_ctx_set_candidate_capacity(dpk_ctx *c, int entries);
 
+/* Statistics of the last frame (waits for it): neighbours cut by sel (reading R6; Sec. II.A pads
+ * lists to N_c), table inputs outside the table's range (Sec. II.A.6; reading R9: the nearest
+ * piece is extrapolated), the largest number of atoms within r_c of one atom, and the device
+ * bytes the context holds. */
 int dpk_ctx_stats(dpk_ctx *c, dpk_stats *out);
 
 /* Stage profiler. While enabled, every frame records HIP events on its stream around each stage
@@ -186,18 +242,24 @@ enum {
     DPK_STAGE_FINAL = 5,     /* energy and virial sums over the blocks                       */
     DPK_NSTAGES = 6
 };
+/* Enable (1) or disable (0) the profiler; waits for the context's last frame. */
 int dpk_ctx_profile(dpk_ctx *c, int enable);
+/* stage_ms: DPK_NSTAGES doubles (host, caller-owned); frames: 1 int64 or NULL. */
 int dpk_ctx_profile_read(dpk_ctx *c, double *stage_ms, int64_t *frames);
 
-/* Stage dumps of the last computed frame (host buffers, caller order), for parity tests.
- * nlist: natoms * N_c neighbour indices (caller numbering, -1 padding), in the per-type block
- * order of Sec. II.A.1 sorted by (distance, index, image). */
+/* Stage dumps of the last computed frame (host buffers, caller-owned, caller order), for parity
+ * tests; DPK_E_INVALID_ARG before any frame. nlist: natoms * N_c neighbour indices (caller
+ * numbering, -1 padding), the per-type blocks of Sec. II.A.1 (N_c padding, Sec. II.A), each
+ * sorted by (distance, index, image) as Sec. III.B.1 orders them. */
 int dpk_debug_nlist(dpk_ctx *c, int32_t *nlist);
-/* T = N_c^-1 G^T R (natoms * M * 4) and dE/dT (natoms * M * 4), as FP64. */
+/* The descriptor factor T = N_c^-1 G^T R of Sec. II.A.1 (natoms * M * 4: atom, feature m,
+ * component k) and dE/dT (same layout), as FP64. */
 int dpk_debug_descriptor(dpk_ctx *c, double *T, double *dT);
 
 /* ---------------------------------------------------------------------------------------------
- * Serving: continuous admission of frames of uneven size from many concurrent simulations.
+ * Serving: continuous admission of frames of uneven size from many concurrent simulations (the
+ * paper's inference interfaces serve MD codes frame by frame, Sec. III.A and III.D; here frames of
+ * many simulations share the device).
  * A server owns nslots device slots on one GPU (each a context with its own stream and workspace,
  * sharing one copy of the model). A scheduler thread admits queued frames in arrival order as
  * soon as a slot is idle and the HBM budget (model + every slot's workspace) allows, freeing idle
@@ -232,11 +294,16 @@ typedef struct {
     int64_t launches;          /* batches launched (frames completed / launches = mean batch size) */
 } dpk_server_counters;
 
-/* hbm_budget_bytes = 0: no bound. nslots in 1..64. */
+/* Create a server for model m (which must outlive it) on `device` with a precision as for
+ * dpk_ctx_create. hbm_budget_bytes bounds model + all slot workspaces (0: no bound); nslots in
+ * 1..64, else DPK_E_INVALID_ARG. Starts the scheduler thread. */
 int dpk_server_create(const dpk_model *m, int device, int precision, int nslots,
                       size_t hbm_budget_bytes, dpk_server **out);
-/* Queue a frame; returns at once with a ticket. DPK_E_BUDGET if the frame alone exceeds the
- * budget. The frame's buffers must stay valid until dpk_server_poll reports it done. */
+/* Queue a frame (E, F, virial as dpk_compute; host buffers, caller-owned); returns at once with a
+ * ticket. DPK_E_INVALID_ARG for a NULL pointer or natoms < 1, DPK_E_BOX for a bad cell,
+ * DPK_E_BUDGET if the frame alone exceeds the budget. The server reads coord, atype and box and
+ * writes the outputs until the frame is done: the caller keeps them valid until dpk_server_poll or
+ * dpk_server_wait reports it done. */
 int dpk_server_submit(dpk_server *s, const dpk_frame *f, uint64_t *ticket);
 /* *done = 0 while queued or running, 1 when finished successfully, or the frame's (negative)
  * error code. Never blocks. */
@@ -250,6 +317,7 @@ int dpk_server_release(dpk_server *s, uint64_t ticket);
 /* Host steady-clock nanoseconds of the frame's submission, start on the device and completion
  * (times[3]); valid once the frame is done. */
 int dpk_server_times(dpk_server *s, uint64_t ticket, int64_t *times);
+/* Counters since creation (a consistent snapshot). */
 int dpk_server_stats(dpk_server *s, dpk_server_counters *out);
 /* Waits for every queued frame, then frees the server and its slots. */
 void dpk_server_free(dpk_server *s);

@@ -26,6 +26,7 @@ SOURCES = {
     "kernels_nn.hip": [],
     "kernels_fit.hip": [],
     "api.cpp": ["-ffp-contract=off"],
+    "model_file.cpp": [],
 }
 
 

@@ -92,6 +92,7 @@ struct dpk_model {
     std::vector<Layer> fit;   // [ntypes][4]
     bool tabulated = false;
     double tab_dx = 0.0;
+    double tab_xmax = 0.0;
     int tab_nint = 0;
     std::vector<double> table;   // [nets][nint][100][6]
 };
@@ -870,9 +871,30 @@ int dpk_model_tabulate(dpk_model* m, double stride, double x_max)
     }
     m->tabulated = true;
     m->tab_dx = dx;
+    m->tab_xmax = x_max;
     m->tab_nint = nint;
     return DPK_OK;
 }
+
+int dpk_model_describe(const dpk_model* m, dpk_model_desc* desc, double* params, double* tab_stride,
+                       double* tab_xmax)
+{
+    if (!m) return fail(DPK_E_INVALID_ARG, "NULL model");
+    if (desc) *desc = m->desc;
+    if (params) std::memcpy(params, m->params.data(), sizeof(double) * m->params.size());
+    if (tab_stride) *tab_stride = m->tabulated ? m->tab_dx : 0.0;
+    if (tab_xmax) *tab_xmax = m->tabulated ? m->tab_xmax : 0.0;
+    return DPK_OK;
+}
+
+}  // extern "C"
+
+int dpk::set_error(int code, const char* msg)
+{
+    return fail(code, "%s", msg);
+}
+
+extern "C" {
 
 void dpk_model_free(dpk_model* m) { delete m; }
 
@@ -964,6 +986,23 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     c->last_stream = s;
     c->last_n = n;
     return DPK_OK;
+}
+
+int dpk_compute_device_dbox(dpk_ctx* c, int64_t natoms, const double* d_coord, const int32_t* d_atype,
+                            const double* d_box, double* d_energy, double* d_force, double* d_virial,
+                            double* d_atom_energy, void* hip_stream)
+{
+    if (!c) return fail(DPK_E_INVALID_ARG, "NULL context");
+    double hbox[9];
+    if (d_box) {
+        HIPCHK(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)hip_stream;
+        // in stream order, so a box written by the caller's earlier work on this stream is seen
+        HIPCHK(hipMemcpyAsync(hbox, d_box, sizeof(hbox), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return dpk_compute_device(c, natoms, d_coord, d_atype, d_box ? hbox : nullptr, d_energy, d_force, d_virial,
+                              d_atom_energy, hip_stream);
 }
 
 int dpk_compute_device_noalloc(dpk_ctx* c, int64_t natoms, const double* d_coord, const int32_t* d_atype,

@@ -5,6 +5,9 @@
 
 namespace dpk {
 
+// Set the calling thread's error message (dpk_last_error) and return code.
+int set_error(int code, const char* msg);
+
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 // Bytes of the per-device workspace of the allocation-free entry point, and the number of devices
 // it is tracked for.

@@ -59,6 +59,10 @@ def lib():
         L.dpk_model_param_count.restype = C.c_int64
         L.dpk_model_create.argtypes = [C.POINTER(_Desc), dp, C.c_int64, C.POINTER(vp)]
         L.dpk_model_tabulate.argtypes = [vp, C.c_double, C.c_double]
+        L.dpk_model_load.argtypes = [C.c_char_p, C.POINTER(vp)]
+        L.dpk_model_save.argtypes = [vp, C.c_char_p]
+        L.dpk_model_describe.argtypes = [vp, C.POINTER(_Desc), dp, dp, dp]
+        L.dpk_compute_device_dbox.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.dpk_model_free.argtypes = [vp]
         L.dpk_model_free.restype = None
         L.dpk_ctx_create.argtypes = [vp, C.c_int, C.c_int, C.c_size_t, C.c_int, C.POINTER(vp)]
@@ -112,18 +116,47 @@ def param_count(model: dict) -> int:
     return int(lib().dpk_model_param_count(C.byref(d)))
 
 
+def _desc_dict(d: _Desc) -> dict:
+    return dict(ntypes=d.ntypes, sel=[d.sel[t] for t in range(d.ntypes)], rcut=d.rcut, rcut_smth=d.rcut_smth,
+                emb=list(d.emb), axis=d.axis, fit=list(d.fit), type_one_side=bool(d.type_one_side))
+
+
 class Model:
     """An immutable se_e2_a model (description + FP64 parameter blob)."""
 
-    def __init__(self, model: dict, params: np.ndarray):
-        self.desc_dict = dict(model)
-        self._desc = make_desc(model)
-        p = np.ascontiguousarray(params, dtype=np.float64)
-        h = C.c_void_p()
-        _check(lib().dpk_model_create(C.byref(self._desc), _dp(p), p.size, C.byref(h)))
+    def __init__(self, model: dict, params: np.ndarray, _handle=None):
+        if _handle is None:
+            self._desc = make_desc(model)
+            p = np.ascontiguousarray(params, dtype=np.float64)
+            h = C.c_void_p()
+            _check(lib().dpk_model_create(C.byref(self._desc), _dp(p), p.size, C.byref(h)))
+        else:
+            h = _handle
         self.handle = h
+        self.desc_dict = dict(model)
         self.nc = int(sum(model["sel"]))
         self.ntypes = int(model["ntypes"])
+
+    @classmethod
+    def load(cls, path: str) -> "Model":
+        """A model from a file written by save() (dpk_model_load)."""
+        h = C.c_void_p()
+        _check(lib().dpk_model_load(os.fsencode(path), C.byref(h)))
+        d = _Desc()
+        _check(lib().dpk_model_describe(h, C.byref(d), None, None, None))
+        return cls(_desc_dict(d), None, _handle=h)
+
+    def save(self, path: str):
+        _check(lib().dpk_model_save(self.handle, os.fsencode(path)))
+
+    def describe(self):
+        """(description dict, FP64 parameters, table stride, table range)."""
+        d = _Desc()
+        st, xm = C.c_double(), C.c_double()
+        _check(lib().dpk_model_describe(self.handle, C.byref(d), None, C.byref(st), C.byref(xm)))
+        p = np.empty(lib().dpk_model_param_count(C.byref(d)))
+        _check(lib().dpk_model_describe(self.handle, C.byref(d), _dp(p), None, None))
+        return _desc_dict(d), p, st.value, xm.value
 
     def tabulate(self, stride: float, x_max: float):
         _check(lib().dpk_model_tabulate(self.handle, stride, x_max))
