@@ -492,8 +492,8 @@ def main():
     print(json.dumps(line))
 
 
-PRECISIONS_TIMED = ("fp64", "mixed")
-TABLE_PRECISIONS = ("mixed", "fp64")
+PRECISIONS_TIMED = ("fp64", "mixed", "fp32")
+TABLE_PRECISIONS = ("mixed", "fp32", "fp64")
 
 if __name__ == "__main__":
     main()

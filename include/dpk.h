@@ -60,7 +60,11 @@ enum {
     DPK_MIXED = 1,  /* embedding and fitting GEMMs as three BF16 MFMA products (hi*hi + hi*lo +
                        lo*hi) with FP32 accumulation; FP32 activations; FP64 geometry, switching
                        function, force chain rule, force and virial accumulation, energy sum  */
-    DPK_BF16 = 2    /* as DPK_MIXED with one BF16 product per GEMM (fast, about 1e-2 relative) */
+    DPK_BF16 = 2,   /* as DPK_MIXED with one BF16 product per GEMM (fast, about 1e-2 relative) */
+    DPK_FP32 = 3    /* the paper's FP32 inference (Sec. IV): embedding and fitting GEMMs on FP32 MFMA
+                       (v_mfma_f32_16x16x4f32), FP32 activations and an FP32 table; FP64 geometry,
+                       switching function, force chain rule, force and virial accumulation, and
+                       energy sum, as in DPK_MIXED                                              */
 };
 
 #define DPK_MAX_TYPES 8
@@ -136,7 +140,7 @@ int dpk_model_tabulate(dpk_model *m, double stride, double x_max);
 /* Free a model (NULL is ignored). Contexts created from it must be freed first. */
 void dpk_model_free(dpk_model *m);
 
-/* Create a context on HIP device `device` with precision DPK_FP64, DPK_MIXED or DPK_BF16 (the
+/* Create a context on HIP device `device` with precision DPK_FP64, DPK_MIXED, DPK_BF16 or DPK_FP32 (the
  * paper's FP64 and reduced-precision inference, Sec. IV; the precision of each step is listed at
  * the precision enum). The model's weights (and table, if the model is compressed at this point)
  * are packed for the precision and copied to the device; the model must outlive the context.

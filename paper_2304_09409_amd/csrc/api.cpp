@@ -157,6 +157,7 @@ void embed_derivs(const dpk_model* m, int net, double x, double* y, double* y1, 
 // (v >= 4), i.e. rows 4g..4g+3 of the previous layer's output tiles 2c and 2c + 1.
 inline int kphys(int precision, int k)
 {
+    if (precision == DPK_FP32) return k;   // lane group g holds K values 16c + 4g + v: already contiguous
     if (precision != DPK_FP64) {
         const int c = k >> 5, r = k & 31;
         return 32 * c + 8 * ((r & 15) >> 2) + (r >> 4) * 4 + (r & 3);
@@ -172,12 +173,13 @@ inline int kidx32(int c, int g, int j) { return 32 * c + (j < 4 ? 4 * g + j : 16
 
 // Row position of register u of lane group g in embedding layer l (the K position of layer 1, the
 // output row of layers 2 and 3) for the precision's MFMA layout: FP64 lanes of group g hold K
-// values 16c + g + 4v and output rows g + 4r of each tile, the BF16 paths K values kidx32(c, g, v)
-// and output rows 4g + r.
+// values 16c + g + 4v and output rows g + 4r of each tile, FP32 K values 16c + 4g + v and output
+// rows 4g + r, the BF16 paths K values kidx32(c, g, v) and output rows 4g + r.
 inline int emb_pos(int precision, int l, int g, int u)
 {
     const bool f64 = precision == DPK_FP64;
     if (l == 1) {
+        if (precision == DPK_FP32) return 16 * (u / 4) + 4 * g + u % 4;
         const int vpl = f64 ? 4 : 8, c = u / vpl, v = u % vpl;
         return f64 ? 16 * c + g + 4 * v : kidx32(c, g, v);
     }
@@ -208,14 +210,17 @@ void pack_frags(std::vector<uint16_t>& out, size_t frag0, int ntiles, int nch, i
 struct Planes {
     int precision;
     std::vector<double> d;     // FP64
+    std::vector<float> f;      // FP32
     std::vector<uint16_t> h, l;
     void init(int prec, size_t n) {
         precision = prec;
         if (prec == DPK_FP64) d.assign(n, 0.0);
+        else if (prec == DPK_FP32) f.assign(n, 0.0f);
         else { h.assign(n, 0); if (prec == DPK_MIXED) l.assign(n, 0); }
     }
     void set(size_t i, double v) {
         if (precision == DPK_FP64) { d[i] = v; return; }
+        if (precision == DPK_FP32) { f[i] = (float)v; return; }
         const uint16_t hb = bf16_bits((float)v);
         h[i] = hb;
         if (precision == DPK_MIXED) l[i] = bf16_bits((float)(v - (double)bf16_float(hb)));
@@ -321,7 +326,8 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
     // FP64 [slots][6][240]; BF16 paths [blocks][3][16][tiles][64][4] (XF_ACT floats per 16 slots),
     // with at most 63 padding slots in either grid
     const int64_t nfit = (n + FIT_AF - 1) / FIT_AF * FIT_AF + FIT_AF;
-    p = take(c->acc_size == 8 ? sizeof(double) * nfit * 6 * FW : sizeof(float) * (nfit / 16) * XF_ACT);
+    const bool dense_fit = c->precision == DPK_FP64 || c->precision == DPK_FP32;
+    p = take(dense_fit ? c->acc_size * nfit * 6 * FW : sizeof(float) * (nfit / 16) * XF_ACT);
     if (base) c->act = p;
     p = take(sizeof(double) * n); if (base) c->Ei = (double*)p;
     p = take(sizeof(double) * 3 * n); if (base) c->F = (double*)p;
@@ -477,6 +483,7 @@ int upload(void** dst, const T* src, size_t n)
 int upload_planes(void** dst, const Planes& P)
 {
     if (P.precision == DPK_FP64) return upload(dst, P.d.data(), P.d.size());
+    if (P.precision == DPK_FP32) return upload(dst, P.f.data(), P.f.size());
     std::vector<uint16_t> all(P.h);
     all.insert(all.end(), P.l.begin(), P.l.end());
     return upload(dst, all.data(), all.size());
@@ -488,12 +495,15 @@ int upload_model(dpk_ctx* c)
     const dpk_model* m = c->model;
     const int prec = c->precision, nets = m->nets, nt = m->desc.ntypes;
     const bool f64 = prec == DPK_FP64;
+    // FP64 and FP32 fit on the 16x16x4 MFMA with dense row-major weights (k_fit_dense); the BF16
+    // paths use fragment-major weights (k_fitx)
+    const bool dense = f64 || prec == DPK_FP32;
     std::vector<double> ev((size_t)nets * EVEC, 0.0), fv((size_t)nt * FVEC, 0.0);
     Planes em, fm;
     em.init(prec, (size_t)nets * EM_SIZE);
-    if (f64) fm.init(prec, (size_t)nt * FM_SIZE);
+    if (dense) fm.init(prec, (size_t)nt * FM_SIZE);
     std::vector<uint16_t> fx;
-    if (!f64) fx.assign((size_t)nt * XF_NFRAG * XF_ELEMS, 0);
+    if (!dense) fx.assign((size_t)nt * XF_NFRAG * XF_ELEMS, 0);
     // feature at each row position of the embedding layers in the skip-aligned order (-1: padding,
     // zero weights)
     int f1[K2P], f2[N2P], f3[N3P];
@@ -536,7 +546,7 @@ int upload_model(dpk_ctx* c)
         }
         v[FV_B4] = L[3].b[0];
         v[FV_WH4] = L[3].wh[0];
-        if (!f64) {
+        if (!dense) {
             // fragment-major BF16 packing: W[in][out] of each layer, read as W^T (forward) or W (backward)
             const bool split = prec == DPK_MIXED;
             const size_t f0 = (size_t)t * XF_NFRAG;
@@ -576,13 +586,15 @@ int upload_model(dpk_ctx* c)
         if ((rc = upload(&c->fvec, fvf.data(), fvf.size()))) return rc;
     }
     if ((rc = upload_planes(&c->emat, em))) return rc;
-    if (f64) {
+    if (dense) {
         if ((rc = upload_planes(&c->fmat, fm))) return rc;
     } else if ((rc = upload(&c->fmat, fx.data(), fx.size()))) {
         return rc;
     }
     c->model_bytes = ev.size() * c->acc_size + fv.size() * c->acc_size +
-                     (f64 ? em.d.size() * 8 + fm.d.size() * 8 : (em.h.size() + em.l.size() + fx.size()) * 2);
+                     (f64     ? em.d.size() * 8 + fm.d.size() * 8
+                      : dense ? (em.f.size() + fm.f.size()) * 4
+                              : (em.h.size() + em.l.size() + fx.size()) * 2);
     if (m->tabulated) {
         if (f64) {
             if ((rc = upload(&c->table, m->table.data(), m->table.size()))) return rc;
@@ -903,7 +915,7 @@ int dpk_ctx_create(const dpk_model* m, int device, int precision, size_t hbm_bud
 {
     if (!m || !out) return fail(DPK_E_INVALID_ARG, "NULL argument");
     *out = nullptr;
-    if (precision < DPK_FP64 || precision > DPK_BF16) return fail(DPK_E_INVALID_ARG, "unknown precision %d", precision);
+    if (precision < DPK_FP64 || precision > DPK_FP32) return fail(DPK_E_INVALID_ARG, "unknown precision %d", precision);
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(DPK_E_INVALID_ARG, "device %d not present (%d devices)", device, ndev);

@@ -44,7 +44,7 @@ int prep_small_max_atoms();
 int prep_small_max_cells();
 void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s);
 
-// precision: 0 = FP64, 1 = split-BF16 (three products), 2 = BF16 (one product)
+// precision: 0 = FP64, 1 = split-BF16 (three products), 2 = BF16 (one product), 3 = FP32
 // blocks of the embedding backward for a frame on the network or the table path (one [E, virial]
 // partial each; the two paths have their own launch shapes), and their maximum over launch shapes
 // (workspace sizing)

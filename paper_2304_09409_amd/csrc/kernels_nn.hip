@@ -218,6 +218,39 @@ struct PBF16 {
     static constexpr float BIAS_SCALE = TANH_K;
 };
 
+// FP32 on v_mfma_f32_16x16x4f32, four instructions per 16-wide K-chunk (the FP32 precision of
+// the paper's reduced-precision inference, Sec. IV). In instruction v lane group g supplies one K
+// value, register v of its fragment; with kidx(c, g, v) = 16c + 4g + v that is row 4g + v of the
+// previous layer's output tile c, which is exactly what output register v of lane group g holds
+// (orow(g, r) = 4g + r, probed on gfx950), so a layer's output is the next layer's B operand in
+// place and the weights are stored in plain K order.
+struct PF32 {
+    typedef float acc;
+    typedef float wt;
+    typedef f4 accv;
+    static constexpr int NPL = 1;
+    static constexpr int KC = 16, VPL = 4, GB = 16;
+    struct frag { f4 v; };
+    __device__ static int orow(int g, int r) { return 4 * g + r; }
+    __device__ static int ogrp(int row) { return row >> 2; }   // inverse of orow
+    __device__ static int oreg(int row) { return row & 3; }
+    __device__ static int kidx(int c, int g, int v) { return 16 * c + 4 * g + v; }
+    __device__ static frag make(acc x0, acc x1, acc x2, acc x3) { frag f; f.v = f4{x0, x1, x2, x3}; return f; }
+    __device__ static frag make(const acc* x) { return make(x[0], x[1], x[2], x[3]); }
+    __device__ static frag lds(const char* p) { frag f; f.v = *reinterpret_cast<const f4*>(p); return f; }
+    __device__ static frag load(const wt* p, int64_t) { frag f; f.v = *reinterpret_cast<const f4*>(p); return f; }
+    __device__ static void mma(accv& d, const frag& a, const frag& b) {
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[0], b.v[0], d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[1], b.v[1], d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[2], b.v[2], d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[3], b.v[3], d, 0, 0, 0);
+    }
+    __device__ static acc act(acc x) { return tanh_fast(x); }
+    // tanh(x + b) from the bias as staged (K b)
+    __device__ static acc act_b(acc x, acc kb) { return tanh_scaled(__builtin_fmaf(x, TANH_K, kb)); }
+    static constexpr float BIAS_SCALE = TANH_K;
+};
+
 template <class V> __device__ __forceinline__ void zero4(V& v) { v[0] = 0; v[1] = 0; v[2] = 0; v[3] = 0; }
 
 // Rank-1 updates on the matrix cores. v_mfma_f32_4x4x1f32 runs 16 independent 4 x 4 x 1 products,
@@ -1055,6 +1088,9 @@ struct FitStage {
                 if (sizeof(wt) == 8) {
                     // two doubles: half of group pc/2
                     *reinterpret_cast<u32x4*>(rowp + (pc >> 1) * GB + (pc & 1) * 16) = r[p];
+                } else if (sizeof(wt) == 4) {
+                    // four floats: group pc
+                    *reinterpret_cast<u32x4*>(rowp + pc * GB) = r[p];
                 } else {
                     // eight BF16 of one plane: the plane's half of groups 2pc and 2pc+1
                     *reinterpret_cast<uint2*>(rowp + (2 * pc) * GB + pl * 8) = make_uint2(r[p].x, r[p].y);
@@ -1081,11 +1117,12 @@ __device__ __forceinline__ typename P::frag fit_afrag(const char* base, int row,
 }
 
 // ---------------------------------------------------------------------------------------------
-// FP64 fitting net with FP64 MFMA. FP64 accumulators take twice the
-// registers, so every product runs in passes of eight 16-row output tiles and the layer outputs go
-// to a per-atom scratch row instead of registers. Values are stored in the K order the FP64 MFMA
-// lanes read (position 16c + 4g + v holds logical index 16c + g + 4v): the four outputs a lane
-// produces and the four B-operand values it later reads are the same 32 bytes, written and read by
+// Fitting net on the 16x16x4 MFMA of one element type: FP64 (PF64) or FP32 (PF32). FP64
+// accumulators take twice the registers, so every product runs in passes of eight 16-row output
+// tiles and the layer outputs go to a per-atom scratch row instead of registers. Values are stored
+// in the K order the MFMA lanes read (position 16c + 4g + v holds logical index kidx(c, g, v):
+// 16c + g + 4v in FP64, 16c + 4g + v in FP32): the four outputs a lane produces and the four
+// B-operand values it later reads are the same 32 (FP64) or 16 (FP32) bytes, written and read by
 // the same lane, so the scratch row needs no synchronisation.
 // Scratch row per atom: a1, a2, a3 (tanh outputs), ga (two ping-pong buffers), gh; during the
 // forward pass the slots of the second ga buffer and of gh hold the inputs of layers 2 and 3.
@@ -1093,12 +1130,14 @@ __device__ __forceinline__ typename P::frag fit_afrag(const char* base, int row,
 constexpr int F64_TP = 8;
 constexpr int FS_A1 = 0, FS_A2 = FW, FS_A3 = 2 * FW, FS_GA = 3 * FW, FS_GB = 4 * FW, FS_GH = 5 * FW, FS_ROW = 6 * FW;
 
-__global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
+template <class P>
+__global__ void __launch_bounds__(256) k_fit_dense(FitArgs A)
 {
-    typedef PF64 P;
-    typedef double acc;
-    typedef d4 accv;
-    typedef P::frag frag;
+    typedef typename P::acc acc;
+    typedef typename P::accv accv;
+    typedef typename P::wt wt;
+    typedef typename P::frag frag;
+    typedef accv d4;   // four values of the element type (the lane's 4-row output or K group)
     typedef FitStage<P, 16 * F64_TP, 16> SW;
     __shared__ __attribute__((aligned(32))) char s_w[2][SW::BYTES];
     __shared__ acc s_p1[4][16][16][4];
@@ -1123,7 +1162,7 @@ __global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
     for (int ti = t_lo; ti <= t_hi; ++ti) {
         const bool mine = real && A.itype[atom] == ti;
         const acc* fv = reinterpret_cast<const acc*>(A.fvec) + (size_t)ti * FVEC;
-        const double* fm = reinterpret_cast<const double*>(A.fmat) + (size_t)ti * FM_SIZE;
+        const wt* fm = reinterpret_cast<const wt*>(A.fmat) + (size_t)ti * FM_SIZE;
         acc Tn[4][4];
 #pragma unroll
         for (int v = 0; v < 4; ++v)
@@ -1149,7 +1188,7 @@ __global__ void __launch_bounds__(256) k_fit_f64(FitArgs A)
                 // Every read is unconditional (past the last chunk it repeats the last one), so that
                 // the compiler's in-order wait counts stay exact instead of draining all reads.
                 SW st0, st1;
-                const double* src = fm + mo + (int64_t)16 * t0 * K;
+                const wt* src = fm + mo + (int64_t)16 * t0 * K;
                 const int clast = nchunk - 1;
                 __syncthreads();
                 d4 x0 = fetch(0), x1 = {0, 0, 0, 0};
@@ -1345,6 +1384,7 @@ int embed_bwd_blocks(int precision, bool table, int64_t natoms, int ncu)
 {
     if (precision == 0) return table ? embed_bwd_blocks_p<PF64, true>(natoms, ncu) : embed_bwd_blocks_p<PF64, false>(natoms, ncu);
     if (precision == 1) return table ? embed_bwd_blocks_p<PMIX, true>(natoms, ncu) : embed_bwd_blocks_p<PMIX, false>(natoms, ncu);
+    if (precision == 3) return table ? embed_bwd_blocks_p<PF32, true>(natoms, ncu) : embed_bwd_blocks_p<PF32, false>(natoms, ncu);
     return table ? embed_bwd_blocks_p<PBF16, true>(natoms, ncu) : embed_bwd_blocks_p<PBF16, false>(natoms, ncu);
 }
 
@@ -1354,7 +1394,9 @@ int64_t embed_bwd_max_blocks(int precision, int64_t natoms)
     const int nw = precision == 0 ? std::min(EmbCfg<PF64, false, false>::NW, EmbCfg<PF64, false, true>::NW)
                                   : std::min(EmbCfg<PMIX, false, false>::NW, EmbCfg<PMIX, false, true>::NW);
     static_assert(EmbCfg<PBF16, false, false>::NW == EmbCfg<PMIX, false, false>::NW &&
-                  EmbCfg<PBF16, false, true>::NW == EmbCfg<PMIX, false, true>::NW, "backward shapes");
+                  EmbCfg<PBF16, false, true>::NW == EmbCfg<PMIX, false, true>::NW &&
+                  EmbCfg<PF32, false, false>::NW == EmbCfg<PMIX, false, false>::NW &&
+                  EmbCfg<PF32, false, true>::NW == EmbCfg<PMIX, false, true>::NW, "backward shapes");
     return (natoms + nw - 1) / nw;
 }
 int fit_atoms_per_block(int) { return FIT_AF; }
@@ -1387,6 +1429,7 @@ void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s
 {
     if (precision == 0) launch_embed<PF64>(true, table, a, s);
     else if (precision == 1) launch_embed<PMIX>(true, table, a, s);
+    else if (precision == 3) launch_embed<PF32>(true, table, a, s);
     else launch_embed<PBF16>(true, table, a, s);
 }
 
@@ -1394,13 +1437,15 @@ void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s
 {
     if (precision == 0) launch_embed<PF64>(false, table, a, s);
     else if (precision == 1) launch_embed<PMIX>(false, table, a, s);
+    else if (precision == 3) launch_embed<PF32>(false, table, a, s);
     else launch_embed<PBF16>(false, table, a, s);
 }
 
 void launch_fit(int precision, const FitArgs& a, hipStream_t s)
 {
     dim3 grid((a.natoms + FIT_AF - 1) / FIT_AF), block(256);
-    if (precision == 0) hipLaunchKernelGGL(k_fit_f64, grid, block, 0, s, a);
+    if (precision == 0) hipLaunchKernelGGL(k_fit_dense<PF64>, grid, block, 0, s, a);
+    else if (precision == 3) hipLaunchKernelGGL(k_fit_dense<PF32>, grid, block, 0, s, a);
     else launch_fitx(precision == 1, a, s);
 }
 

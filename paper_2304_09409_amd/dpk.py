@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libdpk.so")
 
 DPK_OK, DPK_E_INVALID_ARG, DPK_E_TYPE_RANGE, DPK_E_BOX = 0, -1, -2, -3
 DPK_E_NBR_OVERFLOW, DPK_E_BUDGET, DPK_E_OOM, DPK_E_DEVICE, DPK_E_UNIMPLEMENTED = -4, -5, -6, -7, -8
-PRECISIONS = {"fp64": 0, "mixed": 1, "bf16": 2}
+PRECISIONS = {"fp64": 0, "mixed": 1, "bf16": 2, "fp32": 3}
 MAX_TYPES = 8
 
 

@@ -7,7 +7,9 @@ Tolerances (written here, from the target of the method's mixed-precision study)
   * mixed mode (split-BF16 GEMMs, FP32 activations): every force component within 1e-3 eV/A;
     |dE|/N within max(1e-4 eV, 1e-5 |E|/N) (the per-atom energies carry an offset of up to 190 eV
     in the fcc model, resolved to FP32 precision); |dXi|/N within 1e-3 eV.
-  * BF16 mode: reported only (no bound; about 1e-2 relative).
+  * FP32 mode (FP32 MFMA GEMMs, FP32 activations and table; FP64 geometry and sums): the mixed
+    mode's bounds.
+  * BF16 mode: its own bound (test_bf16_within_its_bound).
 """
 import sys
 
@@ -120,14 +122,15 @@ def test_fp64_matches_oracle(dpk, case):
     ctx.close()
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp32"])
 @pytest.mark.parametrize("case", list(FRAMES))
-def test_mixed_matches_oracle(dpk, case):
-    say(f"mixed {case}")
+def test_reduced_precision_matches_oracle(dpk, case, precision):
+    say(f"{precision} {case}")
     mname, make = FRAMES[case]
     c, t, b = make()
     spec, params, model = model_of(dpk, mname)
     ref = oracle_of(mname).compute(c, t, b)
-    ctx = dpk.Context(model, precision="mixed")
+    ctx = dpk.Context(model, precision=precision)
     got = ctx.compute(c, t, b)
     check_mixed(got, ref, len(t))
     ctx.close()
@@ -156,7 +159,7 @@ def test_bf16_within_its_bound(dpk, case):
     ctx.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
 def test_type_one_side_matches_oracle(dpk, precision):
     """Per-species embedding nets indexed by the neighbour's type only (type_one_side, Sec.
     II.A.1), with non-unit timestep vectors, on a 3-type frame and a triclinic one."""
@@ -191,7 +194,7 @@ def _fcc_with_close_pairs():
     return c, t, b
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
 def test_table_out_of_range_inputs(dpk, precision):
     """Table inputs past its range use the last piece extrapolated (reading R9) and are counted:
     forces against the oracle's evaluation of the same table and the same count."""
@@ -217,14 +220,15 @@ def test_fp64_full_water_12288(dpk):
     ref = oracle_of("water").compute(c, t, b)
     ctx = dpk.Context(model, precision="fp64")
     check_fp64(ctx.compute(c, t, b), ref, len(t))
-    say("mixed water12288")
-    ctx2 = dpk.Context(model, precision="mixed")
-    check_mixed(ctx2.compute(c, t, b), ref, len(t))
+    for prec in ("mixed", "fp32"):
+        say(f"{prec} water12288")
+        ctx2 = dpk.Context(model, precision=prec)
+        check_mixed(ctx2.compute(c, t, b), ref, len(t))
+        ctx2.close()
     ctx.close()
-    ctx2.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
 def test_tabulated_matches_oracle_table(dpk, precision):
     say(f"table {precision} fcc500")
     spec, params = synth.FCC_MODEL, synth.fcc_params()
@@ -246,7 +250,7 @@ def test_tabulated_matches_oracle_table(dpk, precision):
 _fcc32k = {}
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
 def test_tabulated_fcc_32000(dpk, precision):
     """The 32,000-atom fcc box (20^3 cells, rc 8.0 A, sel 138) with the tabulated embedding
     (stride 0.01) at full size, every output against the oracle's evaluation of the same table."""
@@ -309,7 +313,7 @@ def _degenerate_frames():
     return frames
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32"])
 def test_degenerate_frames(dpk, precision):
     spec, params, model = model_of(dpk, "water")
     ctx = dpk.Context(model, precision=precision)
