@@ -261,6 +261,41 @@ int dpk_debug_nlist(dpk_ctx *c, int32_t *nlist);
 int dpk_debug_descriptor(dpk_ctx *c, double *T, double *dT);
 
 /* ---------------------------------------------------------------------------------------------
+ * Model deviation (Sec. II.C): an ensemble of n_m models of one description (same types, sel,
+ * cut-offs, widths, type_one_side and table, different parameters) evaluated on one frame. The
+ * types, cell list and neighbour list are built once for all models; embedding, fitting and
+ * adjoint run for all models together (one launch per stage). With ensemble averages
+ * <y> = n_m^-1 sum_k y_k:
+ *   eps_F,i = sqrt(< |F_i - <F_i>|^2 >),   eps_Xi,ab = N^-1 sqrt(< (Xi_ab - <Xi_ab>)^2 >),
+ * and, for nu >= 0, the relative forms eps_F,i / (|<F_i>| + nu) and eps_Xi,ab / (|<Xi_ab>| + nu)
+ * (the paper's |<Xi>| read per component). Statistics: max, average and min of eps_F,i over the
+ * atoms and of eps_Xi,ab over the nine components.
+ * -------------------------------------------------------------------------------------------- */
+#define DPK_MAX_MODELS 16
+typedef struct dpk_devi dpk_devi;
+
+typedef struct {
+    double f_max, f_avg, f_min;   /* of eps_F,i over the atoms                 */
+    double v_max, v_avg, v_min;   /* of eps_Xi,ab over the nine components     */
+} dpk_devi_stats;
+
+/* Create an ensemble on `device` in `precision` (as dpk_ctx_create) from n_models models in
+ * 1..DPK_MAX_MODELS, each packed and copied to the device (the models must outlive the ensemble).
+ * DPK_E_INVALID_ARG for NULL pointers, a bad count, or models whose descriptions or tables differ
+ * from model 0's. */
+int dpk_devi_create(const dpk_model *const *models, int n_models, int device, int precision,
+                    dpk_devi **out);
+void dpk_devi_free(dpk_devi *d);
+
+/* Evaluate every model on one frame (host buffers as dpk_compute; synchronous) and the deviations.
+ * nu < 0: absolute deviations; nu >= 0: the relative forms. Outputs (host, caller-owned, any may be
+ * NULL): energy [n_models]; force [n_models][natoms][3] (caller atom order); virial
+ * [n_models][9]; eps_f [natoms]; eps_v [9] (Xi_ab at [3a + b]); stats. Errors as dpk_compute. */
+int dpk_devi_compute(dpk_devi *d, int64_t natoms, const double *coord, const int32_t *atype,
+                     const double *box, double nu, double *energy, double *force, double *virial,
+                     double *eps_f, double *eps_v, dpk_devi_stats *stats);
+
+/* ---------------------------------------------------------------------------------------------
  * Serving: continuous admission of frames of uneven size from many concurrent simulations (the
  * paper's inference interfaces serve MD codes frame by frame, Sec. III.A and III.D; here frames of
  * many simulations share the device).

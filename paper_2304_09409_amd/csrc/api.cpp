@@ -249,6 +249,7 @@ struct dpk_ctx {
     double tab_dx = 0.0;
     int tab_nint = 0;
     size_t model_bytes = 0;
+    size_t evec_b = 0, emat_b = 0, fvec_b = 0, fmat_b = 0, table_b = 0;   // bytes of each packed buffer
     bool owns_model = true;              // false for server slots sharing the first slot's copy
     // workspace
     void* ws = nullptr;
@@ -591,10 +592,11 @@ int upload_model(dpk_ctx* c)
     } else if ((rc = upload(&c->fmat, fx.data(), fx.size()))) {
         return rc;
     }
-    c->model_bytes = ev.size() * c->acc_size + fv.size() * c->acc_size +
-                     (f64     ? em.d.size() * 8 + fm.d.size() * 8
-                      : dense ? (em.f.size() + fm.f.size()) * 4
-                              : (em.h.size() + em.l.size() + fx.size()) * 2);
+    c->evec_b = ev.size() * c->acc_size;
+    c->fvec_b = fv.size() * c->acc_size;
+    c->emat_b = f64 ? em.d.size() * 8 : dense ? em.f.size() * 4 : (em.h.size() + em.l.size()) * 2;
+    c->fmat_b = f64 ? fm.d.size() * 8 : dense ? fm.f.size() * 4 : fx.size() * 2;
+    c->model_bytes = c->evec_b + c->fvec_b + c->emat_b + c->fmat_b;
     if (m->tabulated) {
         if (f64) {
             if ((rc = upload(&c->table, m->table.data(), m->table.size()))) return rc;
@@ -602,7 +604,8 @@ int upload_model(dpk_ctx* c)
             std::vector<float> tf(m->table.begin(), m->table.end());
             if ((rc = upload(&c->table, tf.data(), tf.size()))) return rc;
         }
-        c->model_bytes += m->table.size() * c->acc_size;
+        c->table_b = m->table.size() * c->acc_size;
+        c->model_bytes += c->table_b;
         c->tab = true;
         c->tab_dx = m->tab_dx;
         c->tab_nint = m->tab_nint;
@@ -1216,6 +1219,323 @@ int dpk_debug_descriptor(dpk_ctx* c, double* T, double* dT)
             T[dst] = val(bt, src);
             dT[dst] = val(bd, src);
         }
+    return DPK_OK;
+}
+
+}  // extern "C"
+
+// =============================================================================================
+// Model deviation (Sec. II.C): one frame, n_m models of one description. The geometry (a1-a3:
+// types, cell list, neighbour list) is built once; embedding, fitting and adjoint run for all
+// models in one launch per stage (blockIdx.y = model), the models' packed parameters at a fixed
+// stride in one buffer per kind.
+// =============================================================================================
+struct dpk_devi {
+    int nm = 0;
+    dpk_ctx* geo = nullptr;          // model 0's context: device, precision, geometry workspace
+    void *evec = nullptr, *emat = nullptr, *fvec = nullptr, *fmat = nullptr, *table = nullptr;
+    void* buf = nullptr;             // per-model buffers for cap atoms
+    size_t buf_bytes = 0;
+    int64_t cap = 0;
+    // views (model 0; model k at k times the stride)
+    void *T = nullptr, *dT = nullptr, *act = nullptr;
+    double *Ei = nullptr, *F = nullptr, *vir = nullptr, *ev = nullptr, *eps = nullptr;
+    size_t st_T = 0, st_act = 0, st_vir = 0;
+};
+
+namespace {
+
+bool same_desc(const dpk_model_desc& a, const dpk_model_desc& b)
+{
+    if (a.ntypes != b.ntypes || a.rcut != b.rcut || a.rcut_smth != b.rcut_smth || a.axis != b.axis ||
+        a.type_one_side != b.type_one_side)
+        return false;
+    for (int t = 0; t < a.ntypes; ++t)
+        if (a.sel[t] != b.sel[t]) return false;
+    for (int k = 0; k < 3; ++k)
+        if (a.emb[k] != b.emb[k] || a.fit[k] != b.fit[k]) return false;
+    return true;
+}
+
+// Per-model buffers for n atoms: T, dT, fitting scratch, E_i, F (caller order), block partials,
+// and the per-model [E, virial] results, then the per-atom deviation.
+int devi_buffers(dpk_devi* d, int64_t n)
+{
+    if (n <= d->cap && d->buf) return DPK_OK;
+    dpk_ctx* c = d->geo;
+    const int64_t nfit = (n + FIT_AF - 1) / FIT_AF * FIT_AF + FIT_AF;
+    const bool dense_fit = c->precision == DPK_FP64 || c->precision == DPK_FP32;
+    d->st_T = align256(c->acc_size * n * E2 * 4);
+    d->st_act = align256(dense_fit ? c->acc_size * nfit * 6 * FW : sizeof(float) * (nfit / 16) * XF_ACT);
+    d->st_vir = align256(sizeof(double) * 10 * embed_bwd_max_blocks(c->precision, n));
+    const size_t per = 2 * d->st_T + d->st_act + align256(sizeof(double) * n) + align256(sizeof(double) * 3 * n) + d->st_vir;
+    const size_t bytes = per * d->nm + align256(sizeof(double) * 10 * d->nm) + align256(sizeof(double) * n);
+    if (d->buf) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipFree(d->buf));
+        d->buf = nullptr;
+    }
+    if (hipMalloc(&d->buf, bytes) != hipSuccess) {
+        hipGetLastError();
+        d->buf = nullptr;
+        return fail(DPK_E_OOM, "hipMalloc of %zu bytes for the model ensemble failed", bytes);
+    }
+    char* p = (char*)d->buf;
+    const size_t nm = d->nm;
+    d->T = p; p += nm * d->st_T;
+    d->dT = p; p += nm * d->st_T;
+    d->act = p; p += nm * d->st_act;
+    d->Ei = (double*)p; p += nm * align256(sizeof(double) * n);
+    d->F = (double*)p; p += nm * align256(sizeof(double) * 3 * n);
+    d->vir = (double*)p; p += nm * d->st_vir;
+    d->ev = (double*)p; p += align256(sizeof(double) * 10 * nm);
+    d->eps = (double*)p;
+    d->buf_bytes = bytes;
+    d->cap = n;
+    return DPK_OK;
+}
+
+// The ensemble's launches of one frame on stream s: geometry once, then every model per stage.
+void devi_enqueue(dpk_devi* d, int n, const GeomParams& gp, double nu, hipStream_t s)
+{
+    dpk_ctx* c = d->geo;
+    const int nt = c->model->desc.ntypes, nm = d->nm;
+    const size_t stF = align256(sizeof(double) * 3 * n), stE = align256(sizeof(double) * n);
+    for (int k = 1; k < nm; ++k) launch_zero((char*)d->F + k * stF, sizeof(double) * 3 * n, s);
+    if (!launch_prep_small(n, c->h_coord, c->h_atype, nt, gp, c->tcount, c->toff, c->perm, c->inv_perm, c->itype,
+                           c->stats, c->pos, c->cell_of, c->cell_start, c->cand, d->F, s)) {
+        if (!c->cells_clear) launch_zero(c->cell_count, sizeof(int) * (size_t)c->cap_cells, s);
+        launch_prep_large(n, c->h_coord, c->h_atype, nt, gp, c->tcount, c->toff, c->bcount, c->boff, c->perm,
+                          c->inv_perm, c->itype, c->stats, c->pos, c->cell_of, c->cell_count, c->cell_start, c->cursor,
+                          c->cell_tmp, c->cand, d->F, s);
+        c->cells_clear = true;
+    }
+    launch_nlist(n, c->pos, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cand, gp, c->nl_j, c->nl_r, c->nnei,
+                 c->stats, s);
+    EmbArgs ea;
+    std::memset(&ea, 0, sizeof(ea));
+    ea.natoms = n;
+    ea.ntypes = nt;
+    ea.nc = c->model->nc;
+    ea.type_one_side = c->model->desc.type_one_side;
+    ea.ncu = c->ncu;
+    ea.apw = 1;
+    for (int t = 0; t < nt; ++t) ea.off[t] = gp.off[t];
+    ea.itype = c->itype;
+    ea.nnei = c->nnei;
+    ea.nl_j = c->nl_j;
+    ea.nl_r = c->nl_r;
+    ea.rs = c->model->desc.rcut_smth;
+    ea.rc = c->model->desc.rcut;
+    ea.inv_nc = 1.0 / c->model->nc;
+    ea.evec = d->evec;
+    ea.emat = d->emat;
+    ea.table = d->table;
+    ea.tab_dx = c->tab_dx;
+    ea.tab_nint = c->tab_nint;
+    ea.T = d->T;
+    ea.dT = d->dT;
+    ea.perm = c->perm;
+    ea.F = d->F;
+    ea.vir_part = d->vir;
+    ea.stats = c->stats;
+    ea.Ei = d->Ei;
+    ea.nmodels = nm;
+    ea.ms_evec = c->evec_b;
+    ea.ms_emat = c->emat_b;
+    ea.ms_table = c->table_b;
+    ea.ms_T = d->st_T;
+    ea.ms_F = stF;
+    ea.ms_Ei = stE;
+    ea.ms_vir = d->st_vir;
+    launch_embed_fwd(c->precision, c->tab, ea, s);
+    FitArgs fa;
+    std::memset(&fa, 0, sizeof(fa));
+    fa.natoms = n;
+    fa.ntypes = nt;
+    fa.ncu = c->ncu;
+    fa.itype = c->itype;
+    fa.toff = c->toff;
+    fa.fvec = d->fvec;
+    fa.fmat = d->fmat;
+    fa.T = d->T;
+    fa.dT = d->dT;
+    fa.act = d->act;
+    fa.Ei = d->Ei;
+    fa.nmodels = nm;
+    fa.ms_fvec = c->fvec_b;
+    fa.ms_fmat = c->fmat_b;
+    fa.ms_T = d->st_T;
+    fa.ms_act = d->st_act;
+    fa.ms_Ei = stE;
+    launch_fit(c->precision, fa, s);
+    launch_embed_bwd(c->precision, c->tab, ea, s);
+    const int nb = embed_bwd_blocks(c->precision, c->tab, n, c->ncu);
+    for (int k = 0; k < nm; ++k)
+        launch_finalize(nb, (const double*)((const char*)d->vir + k * d->st_vir), d->ev + 10 * k, d->ev + 10 * k + 1,
+                        c->stats, s);
+    launch_force_devi(n, nm, d->F, (int64_t)(stF / sizeof(double)), nu, d->eps, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpk_devi_create(const dpk_model* const* models, int n_models, int device, int precision, dpk_devi** out)
+{
+    if (!models || !out || n_models < 1 || n_models > DPK_MAX_MODELS)
+        return fail(DPK_E_INVALID_ARG, "need 1..%d models", DPK_MAX_MODELS);
+    *out = nullptr;
+    for (int k = 0; k < n_models; ++k) {
+        if (!models[k]) return fail(DPK_E_INVALID_ARG, "NULL model %d", k);
+        if (!same_desc(models[k]->desc, models[0]->desc))
+            return fail(DPK_E_INVALID_ARG, "model %d has another description than model 0 (the ensemble shares "
+                                           "its neighbour list)", k);
+        if (models[k]->tabulated != models[0]->tabulated ||
+            (models[k]->tabulated && (models[k]->tab_dx != models[0]->tab_dx || models[k]->tab_nint != models[0]->tab_nint)))
+            return fail(DPK_E_INVALID_ARG, "model %d is compressed differently from model 0", k);
+    }
+    auto* d = new dpk_devi;
+    d->nm = n_models;
+    int rc = dpk_ctx_create(models[0], device, precision, 0, 0, &d->geo);
+    if (rc) { delete d; return rc; }
+    dpk_ctx* c = d->geo;
+    struct Kind { void** all; size_t bytes; void* dpk_ctx::*src; };
+    const Kind kinds[5] = {{&d->evec, c->evec_b, &dpk_ctx::evec}, {&d->emat, c->emat_b, &dpk_ctx::emat},
+                           {&d->fvec, c->fvec_b, &dpk_ctx::fvec}, {&d->fmat, c->fmat_b, &dpk_ctx::fmat},
+                           {&d->table, c->table_b, &dpk_ctx::table}};
+    for (const Kind& kd : kinds) {
+        if (!kd.bytes) continue;
+        if (hipMalloc(kd.all, kd.bytes * n_models) != hipSuccess) {
+            hipGetLastError();
+            *kd.all = nullptr;
+            dpk_devi_free(d);
+            return fail(DPK_E_OOM, "hipMalloc of the ensemble's parameters failed");
+        }
+    }
+    // pack each model as a context would and copy it into its slot of the shared buffers
+    for (int k = 0; k < n_models; ++k) {
+        dpk_ctx* ck = c;
+        if (k > 0 && (rc = dpk_ctx_create(models[k], device, precision, 0, 0, &ck))) {
+            dpk_devi_free(d);
+            return rc;
+        }
+        for (const Kind& kd : kinds)
+            if (kd.bytes && hipMemcpy((char*)*kd.all + k * kd.bytes, ck->*kd.src, kd.bytes, hipMemcpyDeviceToDevice) !=
+                                hipSuccess) {
+                if (ck != c) dpk_ctx_free(ck);
+                dpk_devi_free(d);
+                return fail(DPK_E_DEVICE, "copy of model %d's parameters failed", k);
+            }
+        if (ck != c) dpk_ctx_free(ck);
+    }
+    *out = d;
+    return DPK_OK;
+}
+
+void dpk_devi_free(dpk_devi* d)
+{
+    if (!d) return;
+    if (d->geo) {
+        hipSetDevice(d->geo->device);
+        hipStreamSynchronize(d->geo->stream);
+        dpk_ctx_free(d->geo);
+    }
+    hipFree(d->evec); hipFree(d->emat); hipFree(d->fvec); hipFree(d->fmat); hipFree(d->table);
+    hipFree(d->buf);
+    delete d;
+}
+
+int dpk_devi_compute(dpk_devi* d, int64_t natoms, const double* coord, const int32_t* atype, const double* box,
+                     double nu, double* energy, double* force, double* virial, double* eps_f, double* eps_v,
+                     dpk_devi_stats* stats)
+{
+    if (!d || !coord || !atype) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    if (natoms < 1 || natoms > (1LL << 30)) return fail(DPK_E_INVALID_ARG, "natoms = %lld", (long long)natoms);
+    dpk_ctx* c = d->geo;
+    HIPCHK(hipSetDevice(c->device));
+    GeomParams gp;
+    int rc;
+    c->cur_natoms = natoms;
+    auto geom = [&]() {
+        if (box) return setup_geometry(c, box, nullptr, gp);
+        double bb[6] = {1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+        for (int64_t i = 0; i < natoms; ++i)
+            for (int k = 0; k < 3; ++k) {
+                bb[k] = std::min(bb[k], coord[3 * i + k]);
+                bb[3 + k] = std::max(bb[3 + k], coord[3 * i + k]);
+            }
+        return setup_geometry(c, nullptr, bb, gp);
+    };
+    if ((rc = geom())) return rc;
+    if ((rc = ensure_ws(c, natoms, (int64_t)gp.nb[0] * gp.nb[1] * gp.nb[2]))) return rc;
+    if ((rc = devi_buffers(d, natoms))) return rc;
+    const int n = (int)natoms, nm = d->nm;
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemcpyAsync(c->h_coord, coord, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->h_atype, atype, sizeof(int) * n, hipMemcpyHostToDevice, s));
+    devi_enqueue(d, n, gp, nu, s);
+    HIPCHK(hipGetLastError());
+    c->last_stream = s;
+    c->last_n = n;
+    rc = dpk_ctx_check(c);
+    if (rc == DPK_E_NBR_OVERFLOW && !c->strict) {
+        // a locally dense frame overflowed the estimated candidate buffer: once more with the largest
+        c->force_big_cap = true;
+        rc = geom();
+        if (rc == DPK_OK) {
+            devi_enqueue(d, n, gp, nu, s);
+            rc = dpk_ctx_check(c);
+        }
+        c->force_big_cap = false;
+    }
+    if (rc) return rc;
+    std::vector<double> ev(10 * (size_t)nm), eps(n);
+    HIPCHK(hipMemcpy(ev.data(), d->ev, sizeof(double) * ev.size(), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(eps.data(), d->eps, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (force) {
+        const size_t stF = align256(sizeof(double) * 3 * n);
+        for (int k = 0; k < nm; ++k)
+            HIPCHK(hipMemcpy(force + (size_t)k * 3 * n, (const char*)d->F + k * stF, sizeof(double) * 3 * n,
+                             hipMemcpyDeviceToHost));
+    }
+    for (int k = 0; k < nm; ++k) {
+        if (energy) energy[k] = ev[10 * k];
+        if (virial) std::memcpy(virial + 9 * k, &ev[10 * k + 1], sizeof(double) * 9);
+    }
+    if (eps_f) std::memcpy(eps_f, eps.data(), sizeof(double) * n);
+    // virial deviation (nine components, FP64 on the host) and the statistics
+    double ev9[9];
+    for (int ab = 0; ab < 9; ++ab) {
+        double mean = 0.0, var = 0.0;
+        for (int k = 0; k < nm; ++k) mean += ev[10 * k + 1 + ab];
+        mean /= nm;
+        for (int k = 0; k < nm; ++k) var += (ev[10 * k + 1 + ab] - mean) * (ev[10 * k + 1 + ab] - mean);
+        double e = std::sqrt(var / nm) / (double)n;
+        if (nu >= 0.0) e /= std::fabs(mean) + nu;
+        ev9[ab] = e;
+    }
+    if (eps_v) std::memcpy(eps_v, ev9, sizeof(ev9));
+    if (stats) {
+        double fmax = eps[0], fmin = eps[0], fsum = 0.0;
+        for (int i = 0; i < n; ++i) {
+            fmax = std::max(fmax, eps[i]);
+            fmin = std::min(fmin, eps[i]);
+            fsum += eps[i];
+        }
+        double vmax = ev9[0], vmin = ev9[0], vsum = 0.0;
+        for (int ab = 0; ab < 9; ++ab) {
+            vmax = std::max(vmax, ev9[ab]);
+            vmin = std::min(vmin, ev9[ab]);
+            vsum += ev9[ab];
+        }
+        stats->f_max = fmax;
+        stats->f_avg = fsum / n;
+        stats->f_min = fmin;
+        stats->v_max = vmax;
+        stats->v_avg = vsum / 9.0;
+        stats->v_min = vmin;
+    }
     return DPK_OK;
 }
 

@@ -175,7 +175,36 @@ struct EmbArgs {
     // and copied to atom_energy (caller order) if that is not nullptr
     const double* Ei;        // [N] internal order
     double* atom_energy;     // [N] caller order, or nullptr
+    // Model ensemble (model deviation, one launch for all models): blockIdx.y selects model k,
+    // whose parameters and per-model buffers start k times these byte strides past the pointers
+    // above; the geometry (types, neighbour list, perm) and the statistics block are shared.
+    // nmodels 0 or 1: a single model.
+    int nmodels;
+    int64_t ms_evec, ms_emat, ms_table, ms_T, ms_F, ms_Ei, ms_vir, ms_ae;
 };
+
+// The arguments of the model that blockIdx.y selects.
+template <class T> __host__ __device__ inline T* byte_offset(T* p, int64_t bytes)
+{
+    return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + bytes) : p;
+}
+__device__ inline EmbArgs model_args(const EmbArgs& A0)
+{
+    EmbArgs A = A0;
+    const int64_t k = blockIdx.y;
+    if (k) {
+        A.evec = byte_offset(A0.evec, k * A0.ms_evec);
+        A.emat = byte_offset(A0.emat, k * A0.ms_emat);
+        A.table = byte_offset(A0.table, k * A0.ms_table);
+        A.T = byte_offset(A0.T, k * A0.ms_T);
+        A.dT = byte_offset(A0.dT, k * A0.ms_T);
+        A.F = byte_offset(A0.F, k * A0.ms_F);
+        A.Ei = byte_offset(A0.Ei, k * A0.ms_Ei);
+        A.vir_part = byte_offset(A0.vir_part, k * A0.ms_vir);
+        A.atom_energy = byte_offset(A0.atom_energy, k * A0.ms_ae);
+    }
+    return A;
+}
 
 struct FitArgs {
     int natoms, ntypes;
@@ -188,6 +217,24 @@ struct FitArgs {
     void* dT;               // [N][100][4]
     void* act;              // forward activations and gradients (scratch)
     double* Ei;             // [N]
+    // model ensemble: as in EmbArgs (blockIdx.y = model, byte strides of the per-model pointers)
+    int nmodels;
+    int64_t ms_fvec, ms_fmat, ms_T, ms_act, ms_Ei;
 };
+
+__device__ inline FitArgs model_args(const FitArgs& A0)
+{
+    FitArgs A = A0;
+    const int64_t k = blockIdx.y;
+    if (k) {
+        A.fvec = byte_offset(A0.fvec, k * A0.ms_fvec);
+        A.fmat = byte_offset(A0.fmat, k * A0.ms_fmat);
+        A.T = byte_offset(A0.T, k * A0.ms_T);
+        A.dT = byte_offset(A0.dT, k * A0.ms_T);
+        A.act = byte_offset(A0.act, k * A0.ms_act);
+        A.Ei = byte_offset(A0.Ei, k * A0.ms_Ei);
+    }
+    return A;
+}
 
 }  // namespace dpk

@@ -43,6 +43,8 @@ void launch_finalize_batch(int nframes, const FrameDesc* fd, const int* inv_perm
 int prep_small_max_atoms();
 int prep_small_max_cells();
 void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s);
+// Per-atom force deviation of an ensemble of nm models (model k's forces at F + k * stride doubles).
+void launch_force_devi(int n, int nm, const double* F, int64_t stride, double nu, double* eps, hipStream_t s);
 
 // precision: 0 = FP64, 1 = split-BF16 (three products), 2 = BF16 (one product), 3 = FP32
 // blocks of the embedding backward for a frame on the network or the table path (one [E, virial]

@@ -109,9 +109,10 @@ __device__ __forceinline__ float sum_groups4(const float* p)
 }
 __device__ __forceinline__ int ksel(int g) { return ((g & 1) << 1) | (g >> 1); }
 
-template <int NAT, bool SPLIT, int NW>
-__global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A)
+template <int NAT, bool SPLIT, int NW, bool ENS>
+__global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A_)
 {
+    const FitArgs A = ENS ? model_args(A_) : A_;
     constexpr int NA = 16 * NAT;                       // atoms per block
     constexpr int FR = XF_ELEMS;
     constexpr int TPW = (15 + NW - 1) / NW;            // feature tiles per wave (at most)
@@ -559,9 +560,16 @@ void launch_fitx(bool split, const FitArgs& a, hipStream_t s)
 {
     if (a.natoms <= 0) return;
     constexpr int NAT = 4, NW = 8;
-    dim3 grid((a.natoms + 16 * NAT - 1) / (16 * NAT)), block(64 * NW);
-    if (split) hipLaunchKernelGGL((k_fitx<NAT, true, NW>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_fitx<NAT, false, NW>), grid, block, 0, s, a);
+    const bool ens = a.nmodels > 1;
+    dim3 grid((a.natoms + 16 * NAT - 1) / (16 * NAT), ens ? a.nmodels : 1), block(64 * NW);
+    // ens: one launch for a model ensemble, blockIdx.y = model (a separate instantiation)
+    if (split) {
+        if (ens) hipLaunchKernelGGL((k_fitx<NAT, true, NW, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_fitx<NAT, true, NW, false>), grid, block, 0, s, a);
+    } else {
+        if (ens) hipLaunchKernelGGL((k_fitx<NAT, false, NW, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_fitx<NAT, false, NW, false>), grid, block, 0, s, a);
+    }
 }
 
 }  // namespace dpk

@@ -1010,6 +1010,40 @@ void launch_nlist(int n, const double* pos, const int* perm, const int* inv_perm
 #undef DPK_NL
 }
 
+// Model deviation of the forces (Sec. II.C): over the nm models of an ensemble (ensemble averages
+// with weight 1/nm), eps_i = sqrt(< |F_i - <F_i>|^2 >); with nu >= 0 the relative form
+// eps_i / (|<F_i>| + nu). F holds model k's forces (caller order) at F + k * stride doubles.
+__global__ void k_force_devi(int n, int nm, const double* F, int64_t stride, double nu, double* eps)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    for (int k = 0; k < nm; ++k) {
+        const double* f = F + k * stride + 3 * (size_t)i;
+        m0 += f[0];
+        m1 += f[1];
+        m2 += f[2];
+    }
+    const double inv = 1.0 / nm;
+    m0 *= inv;
+    m1 *= inv;
+    m2 *= inv;
+    double v = 0.0;
+    for (int k = 0; k < nm; ++k) {
+        const double* f = F + k * stride + 3 * (size_t)i;
+        const double d0 = f[0] - m0, d1 = f[1] - m1, d2 = f[2] - m2;
+        v += d0 * d0 + d1 * d1 + d2 * d2;
+    }
+    double e = sqrt(v * inv);
+    if (nu >= 0.0) e /= sqrt(m0 * m0 + m1 * m1 + m2 * m2) + nu;
+    eps[i] = e;
+}
+
+void launch_force_devi(int n, int nm, const double* F, int64_t stride, double nu, double* eps, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_force_devi, dim3((n + 255) / 256), dim3(256), 0, s, n, nm, F, stride, nu, eps);
+}
+
 void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_debug_nlist, dim3(n), dim3(64), 0, s, n, nc, perm, nl_j, out);

@@ -488,9 +488,12 @@ struct ChunkWalk {
 // registers, never stored). The neighbour-type blocks of atom a are separate passes (one staged
 // net each) that add into T[a]; the same lane owns T[a][m][k] in every pass.
 // ---------------------------------------------------------------------------------------------
-template <class P, bool TAB>
-__global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(EmbArgs A)
+template <class P, bool TAB, bool ENS>
+__global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(EmbArgs A_)
 {
+    // ENS: a model ensemble, blockIdx.y selects the model (a separate instantiation, so that the
+    // single-model kernels carry no per-model pointer arithmetic in their registers)
+    const EmbArgs A = ENS ? model_args(A_) : A_;
     typedef typename P::acc acc;
     typedef typename P::wt wt;
     typedef typename P::accv accv;
@@ -596,7 +599,7 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
                             add_G(tm, r, q, G);
                         }
                     }
-                    if (g == 0 && valid && (s < 0.0 || s > A.tab_nint * A.tab_dx))
+                    if (blockIdx.y == 0 && g == 0 && valid && (s < 0.0 || s > A.tab_nint * A.tab_dx))
                         atomicAdd(&A.stats->table_oor, 1ull);
                 } else {
                     // layer 1 (1 -> 25) straight into the B operand of layer 2 (register u = c VPL + v;
@@ -701,9 +704,10 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
 //   F_i += g_ij, F_j -= g_ij (FP64 atomics into caller order), Xi_ab -= g_ij,a r_ij,b (FP64,
 //   per-block partials, with E over the block's atoms for a single frame).
 // ---------------------------------------------------------------------------------------------
-template <class P, bool TAB>
-__global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(EmbArgs A)
+template <class P, bool TAB, bool ENS>
+__global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(EmbArgs A_)
 {
+    const EmbArgs A = ENS ? model_args(A_) : A_;
     typedef typename P::acc acc;
     typedef typename P::wt wt;
     typedef typename P::accv accv;
@@ -1130,9 +1134,10 @@ __device__ __forceinline__ typename P::frag fit_afrag(const char* base, int row,
 constexpr int F64_TP = 8;
 constexpr int FS_A1 = 0, FS_A2 = FW, FS_A3 = 2 * FW, FS_GA = 3 * FW, FS_GB = 4 * FW, FS_GH = 5 * FW, FS_ROW = 6 * FW;
 
-template <class P>
-__global__ void __launch_bounds__(256) k_fit_dense(FitArgs A)
+template <class P, bool ENS>
+__global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
 {
+    const FitArgs A = ENS ? model_args(A_) : A_;
     typedef typename P::acc acc;
     typedef typename P::accv accv;
     typedef typename P::wt wt;
@@ -1408,9 +1413,15 @@ static void launch_embed_shape(const EmbArgs& a0, hipStream_t s)
     EmbArgs a = a0;
     a.apw = embed_apw(Cfg::NW, Cfg::APW_MAX, a.natoms, a.ncu);
     const int apb = Cfg::NW * a.apw;
-    const dim3 grid((a.natoms + apb - 1) / apb), block(Cfg::NW * 64);
-    if constexpr (FWD) hipLaunchKernelGGL((k_embed_fwd<P, TAB>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_embed_bwd<P, TAB>), grid, block, 0, s, a);
+    const bool ens = a.nmodels > 1;
+    const dim3 grid((a.natoms + apb - 1) / apb, ens ? a.nmodels : 1), block(Cfg::NW * 64);
+    if constexpr (FWD) {
+        if (ens) hipLaunchKernelGGL((k_embed_fwd<P, TAB, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_embed_fwd<P, TAB, false>), grid, block, 0, s, a);
+    } else {
+        if (ens) hipLaunchKernelGGL((k_embed_bwd<P, TAB, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_embed_bwd<P, TAB, false>), grid, block, 0, s, a);
+    }
 }
 
 template <class P>
@@ -1443,10 +1454,17 @@ void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s
 
 void launch_fit(int precision, const FitArgs& a, hipStream_t s)
 {
-    dim3 grid((a.natoms + FIT_AF - 1) / FIT_AF), block(256);
-    if (precision == 0) hipLaunchKernelGGL(k_fit_dense<PF64>, grid, block, 0, s, a);
-    else if (precision == 3) hipLaunchKernelGGL(k_fit_dense<PF32>, grid, block, 0, s, a);
-    else launch_fitx(precision == 1, a, s);
+    const bool ens = a.nmodels > 1;
+    dim3 grid((a.natoms + FIT_AF - 1) / FIT_AF, ens ? a.nmodels : 1), block(256);
+    if (precision == 0) {
+        if (ens) hipLaunchKernelGGL((k_fit_dense<PF64, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_fit_dense<PF64, false>), grid, block, 0, s, a);
+    } else if (precision == 3) {
+        if (ens) hipLaunchKernelGGL((k_fit_dense<PF32, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_fit_dense<PF32, false>), grid, block, 0, s, a);
+    } else {
+        launch_fitx(precision == 1, a, s);
+    }
 }
 
 }  // namespace dpk

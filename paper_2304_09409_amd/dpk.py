@@ -283,6 +283,55 @@ class Context:
 
 
 # ------------------------------------------------------------------------------------------
+# Model deviation
+# ------------------------------------------------------------------------------------------
+class _DeviStats(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("f_max", "f_avg", "f_min", "v_max", "v_avg", "v_min")]
+
+
+class Deviation:
+    """An ensemble of models of one description on one device (dpk_devi_*)."""
+
+    def __init__(self, models, device: int = 0, precision: str = "fp64"):
+        L = lib()
+        if not getattr(L, "_devi_sigs", False):
+            L.dpk_devi_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
+            L.dpk_devi_free.argtypes = [C.c_void_p]
+            L.dpk_devi_free.restype = None
+            dp = C.POINTER(C.c_double)
+            L.dpk_devi_compute.argtypes = [C.c_void_p, C.c_int64, dp, C.POINTER(C.c_int32), dp, C.c_double,
+                                           dp, dp, dp, dp, dp, C.POINTER(_DeviStats)]
+            L._devi_sigs = True
+        self.models = list(models)
+        arr = (C.c_void_p * len(self.models))(*[m.handle.value for m in self.models])
+        h = C.c_void_p()
+        _check(L.dpk_devi_create(arr, len(self.models), device, PRECISIONS[precision], C.byref(h)))
+        self.handle = h
+
+    def compute(self, coord, atype, box=None, nu=None) -> dict:
+        coord = np.ascontiguousarray(coord, dtype=np.float64)
+        atype = np.ascontiguousarray(atype, dtype=np.int32)
+        n, nm = coord.shape[0], len(self.models)
+        box = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(9)
+        e, f, v = np.empty(nm), np.empty((nm, n, 3)), np.empty((nm, 9))
+        ef, evv = np.empty(n), np.empty(9)
+        st = _DeviStats()
+        _check(lib().dpk_devi_compute(self.handle, n, _dp(coord), _ip(atype), _dp(box),
+                                      -1.0 if nu is None else float(nu), _dp(e), _dp(f), _dp(v), _dp(ef),
+                                      _dp(evv), C.byref(st)))
+        return {"energy": e, "force": f, "virial": v.reshape(nm, 3, 3), "eps_f": ef, "eps_v": evv.reshape(3, 3),
+                "stats": {k: getattr(st, k) for k, _ in _DeviStats._fields_}}
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.dpk_devi_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+# ------------------------------------------------------------------------------------------
 # Serving
 # ------------------------------------------------------------------------------------------
 class _Frame(C.Structure):

@@ -211,6 +211,14 @@ def fcc_32000(seed: int = 3):
     return fcc_box(20, 3.6, seed)
 
 
+def ensemble_params(model: dict, base: np.ndarray, n_models: int, rel: float = 0.02, seed: int = 77):
+    """Parameters of an ensemble of n_models members: the base parameters with every value
+    multiplied by 1 + N(0, rel) (member 0 included), seeded. A stand-in for models trained from
+    independent initialisations on the same data, whose predictions differ slightly."""
+    rng = np.random.default_rng(seed)
+    return [base * (1.0 + rng.normal(0.0, rel, base.size)) for _ in range(n_models)]
+
+
 def water_params(seed: int = PARAM_SEED) -> np.ndarray:
     return make_params(WATER_MODEL, seed, WATER_OUT_SCALE, WATER_FIT_IN)
 
