@@ -188,6 +188,26 @@ int dpk_compute_device(dpk_ctx *c, int64_t natoms, const double *d_coord,
                        double *d_force, double *d_virial, double *d_atom_energy,
                        void *hip_stream);
 
+/* One domain's share of a spatially decomposed frame (the MD code's domain decomposition, Sec.
+ * III.B.2; third-party MD interfaces, Sec. III.D): atoms 0.. nlocal - 1 are owned, atoms nlocal..
+ * nlocal + nghost - 1 are ghost copies of atoms owned elsewhere (or periodic images), each at the
+ * position its owner's domain sent. There is no cell: every atom within r_c of an owned atom must be
+ * among the owned and ghost atoms. Neighbour lists are built for owned atoms only, over all atoms,
+ * ordered and truncated as Sec. II.A.1 and III.B.1 (the internal search), or (ext_start and
+ * ext_list not NULL) from the caller's candidate lists: owned atom i's candidates are ext_list
+ * [ext_start[i] .. ext_start[i + 1]) (caller indices in [0, nlocal + nghost), any order, no
+ * duplicates, e.g. an MD code's list with a skin), of which those within r_c are ordered and
+ * truncated the same way. E = sum of E_i over owned atoms (atom_energy: nlocal values or NULL);
+ * force: (nlocal + nghost) * 3, the forces on owned atoms and on ghosts from this domain's pairs
+ * (the caller adds each ghost's force to its owner: the reverse exchange); virial = -sum over
+ * pairs with an owned centre of g_ij (x) r_ij, so the domains' virials add up to the frame's. Host
+ * buffers, caller-owned, synchronous. Errors as dpk_compute; DPK_E_INVALID_ARG also for an
+ * ext_start that does not start at 0 or decreases, an index outside [0, nlocal + nghost), or only
+ * one of ext_start/ext_list; DPK_E_UNIMPLEMENTED with ghosts and 8 atom types. */
+int dpk_compute_ghost(dpk_ctx *c, int64_t nlocal, int64_t nghost, const double *coord,
+                      const int32_t *atype, const int32_t *ext_start, const int32_t *ext_list,
+                      double *energy, double *force, double *virial, double *atom_energy);
+
 /* As dpk_compute_device with the cell h (Sec. II.A.2: h_ab = component b of lattice vector a) in
  * DEVICE memory: d_box points to 9 doubles on the context's device, or is NULL (open cluster).
  * The box is read back to the host in stream order (one wait on hip_stream), since the cell list

@@ -56,6 +56,7 @@ def _load():
             lib.orc_nlist.argtypes = [mp, C.c_long, dp, ip, dp, C.c_int, ip, dp, lp]
             lib.orc_compute.argtypes = [mp, C.c_long, dp, ip, dp, C.c_int, dp, C.c_double, C.c_int,
                                         dp, dp, dp, dp, lp, lp, ip, dp, dp]
+            lib.orc_compute_ghost.argtypes = [mp, C.c_long, C.c_long, dp, ip, dp, dp, dp, dp]
             lib.orc_num_threads.restype = C.c_int
             lib.orc_set_num_threads.argtypes = [C.c_int]
             lib.orc_set_num_threads.restype = None
@@ -168,6 +169,21 @@ class Oracle:
         if dumps:
             out.update(nlist=nl, T=T, dT=dT)
         return out
+
+    def compute_ghost(self, coord, atype, nlocal: int):
+        """One domain: atoms [0, nlocal) owned, the rest ghosts (open geometry, no cell)."""
+        coord = np.ascontiguousarray(coord, dtype=np.float64)
+        atype = np.ascontiguousarray(atype, dtype=np.int32)
+        n = coord.shape[0]
+        e = C.c_double()
+        f = np.empty((n, 3))
+        v = np.empty(9)
+        ei = np.empty(nlocal)
+        rc = self.lib.orc_compute_ghost(C.byref(self._m), nlocal, n - nlocal, _dp(coord), _ip(atype), C.byref(e),
+                                        _dp(f), _dp(v), _dp(ei))
+        if rc:
+            raise ValueError(f"orc_compute_ghost failed with code {rc}")
+        return dict(energy=e.value, force=f, virial=v.reshape(3, 3), atom_energy=ei)
 
     def energy(self, coord, atype, box, method: int = 1, table=None, dx: float = 0.0):
         return self.compute(coord, atype, box, method, table, dx)["energy"]

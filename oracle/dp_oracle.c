@@ -496,11 +496,14 @@ int orc_nlist(const orc_model *m, long n, const double *coord, const int *type, 
  *   Xi_ab -= g_ij,a r_ij,b, which is -sum_g dE/dh_ga h_gb for r_ij = (s_j + n - s_i) h.
  * table == NULL selects the network; otherwise table holds orc_table_build() coefficients.
  * Optional dumps: nlist_out [n][N_c], T_out [n][M][4], dT_out [n][M][4].
+ * Centre atoms are 0.. ncentre - 1 (all atoms in orc_compute; the owned atoms of a domain with
+ * ghost atoms in orc_compute_ghost): only they have E_i and contribute pairs; the neighbours of a
+ * centre are taken from all n atoms.
  * ---------------------------------------------------------------------------------------- */
-int orc_compute(const orc_model *m, long n, const double *coord, const int *type, const double *box,
-                int method, const double *table, double tab_dx, int tab_nint,
-                double *energy, double *force, double *virial, double *atom_energy,
-                long *ndrop, long *ntab_oor, int *nlist_out, double *T_out, double *dT_out)
+static int compute_impl(const orc_model *m, long n, long ncentre, const double *coord, const int *type,
+                        const double *box, int method, const double *table, double tab_dx, int tab_nint,
+                        double *energy, double *force, double *virial, double *atom_energy,
+                        long *ndrop, long *ntab_oor, int *nlist_out, double *T_out, double *dT_out)
 {
     int Nc = 0, M = m->emb[2], A = m->axis, nt = m->ntypes;
     int slot_type[4096];
@@ -527,7 +530,7 @@ int orc_compute(const orc_model *m, long n, const double *coord, const int *type
         double *d = malloc(sizeof(double) * (size_t)M * A);
         double *dd = malloc(sizeof(double) * (size_t)M * A);
 #pragma omp for schedule(dynamic, 8)
-        for (long i = 0; i < n; ++i) {
+        for (long i = 0; i < ncentre; ++i) {
             int ti = type[i];
             for (int q = 0; q < 4 * M; ++q) T[q] = 0.0;
             for (int sl = 0; sl < Nc; ++sl) {
@@ -594,7 +597,7 @@ int orc_compute(const orc_model *m, long n, const double *coord, const int *type
     /* serial accumulation in a fixed order */
     double e = 0.0, xi[9] = {0};
     if (force) for (long q = 0; q < 3 * n; ++q) force[q] = 0.0;
-    for (long i = 0; i < n; ++i) {
+    for (long i = 0; i < ncentre; ++i) {
         e += ei[i];
         for (int sl = 0; sl < Nc; ++sl) {
             int j = nlist[i * Nc + sl];
@@ -608,11 +611,36 @@ int orc_compute(const orc_model *m, long n, const double *coord, const int *type
     }
     if (energy) *energy = e;
     if (virial) memcpy(virial, xi, sizeof(xi));
-    if (atom_energy) memcpy(atom_energy, ei, sizeof(double) * (size_t)n);
+    if (atom_energy) memcpy(atom_energy, ei, sizeof(double) * (size_t)ncentre);
     if (nlist_out) memcpy(nlist_out, nlist, sizeof(int) * (size_t)n * Nc);
     if (ntab_oor) *ntab_oor = oor_total;
     free(nlist); free(rij); free(g); free(ei);
     return ORC_OK;
+}
+
+int orc_compute(const orc_model *m, long n, const double *coord, const int *type, const double *box,
+                int method, const double *table, double tab_dx, int tab_nint,
+                double *energy, double *force, double *virial, double *atom_energy,
+                long *ndrop, long *ntab_oor, int *nlist_out, double *T_out, double *dT_out)
+{
+    return compute_impl(m, n, n, coord, type, box, method, table, tab_dx, tab_nint, energy, force, virial,
+                        atom_energy, ndrop, ntab_oor, nlist_out, T_out, dT_out);
+}
+
+/* ------------------------------------------------------------------------------------------
+ * One domain of a spatially decomposed frame (Sec. III.B.2): atoms 0.. nlocal - 1 are owned, the
+ * rest are ghost copies at the positions the neighbouring domains sent; no cell (every atom within
+ * r_c of an owned atom is present). E sums E_i over owned atoms (atom_energy: nlocal values), the
+ * forces cover owned and ghost atoms (a ghost's force belongs to its owner), and the virial sums
+ * the pairs whose centre is owned. ndrop counts the cuts by sel of all atoms' lists (ghosts'
+ * included, as orc_nlist builds every list).
+ * ---------------------------------------------------------------------------------------- */
+int orc_compute_ghost(const orc_model *m, long nlocal, long nghost, const double *coord, const int *type,
+                      double *energy, double *force, double *virial, double *atom_energy)
+{
+    long nd = 0;
+    return compute_impl(m, nlocal + nghost, nlocal, coord, type, NULL, 0, NULL, 0.0, 0, energy, force, virial,
+                        atom_energy, &nd, NULL, NULL, NULL, NULL);
 }
 
 int orc_num_threads(void)

@@ -259,6 +259,8 @@ struct dpk_ctx {
     bool cells_clear = false;            // cell_count is all zero (the multi-block preparation keeps it so)
     bool views_scratch = false;          // the views below point into the device's shared scratch
     void* scratch = nullptr;             // that scratch (allocation-free entry point), this device's copy
+    int* ext_buf = nullptr;              // external neighbour candidates (ghost-atom entry point)
+    size_t ext_cap = 0;                  // ints it holds
     // views of the workspace (valid for the capacity)
     int *perm, *inv_perm, *itype, *tcount, *toff, *cell_of, *cell_tmp, *cell_count, *cell_start, *cursor;
     int *nl_j, *nnei, *h_atype, *bcount, *boff;
@@ -276,8 +278,9 @@ struct dpk_ctx {
     int64_t cur_natoms = 0;
     bool force_big_cap = false;
     int cap_fixed = 0;                   // candidate-buffer entries set by the caller (0: estimated)
-    // last frame
+    // last frame: atoms, and the centre atoms among them (fewer with ghost atoms)
     int64_t last_n = 0;
+    int64_t last_centres = 0;
     // stage profiler: one set of DPK_NSTAGES + 1 events per profiled frame
     bool profiling = false;
     std::vector<std::vector<hipEvent_t>> prof_events;
@@ -660,6 +663,7 @@ void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* F, double* vir
     launch_embed_fwd(c->precision, tab, ea, s);
 
     FitArgs fa;
+    std::memset(&fa, 0, sizeof(fa));   // one model: nmodels and the per-model strides zero
     fa.natoms = n;
     fa.ntypes = nt;
     fa.ncu = c->ncu;
@@ -811,6 +815,7 @@ int compute_batch(dpk_ctx* c, int nf, const BatchFrame* fr, const double* d_coor
     HIPCHK(hipGetLastError());
     c->last_stream = s;
     c->last_n = n;
+    c->last_centres = n;
     return DPK_OK;
 }
 
@@ -958,6 +963,7 @@ void dpk_ctx_free(dpk_ctx* c)
         hipFree(c->evec); hipFree(c->emat); hipFree(c->fvec); hipFree(c->fmat); hipFree(c->table);
     }
     hipFree(c->ws);
+    hipFree(c->ext_buf);
     hipHostFree(c->pin_desc);
     for (auto& set : c->prof_events)
         for (auto e : set) hipEventDestroy(e);
@@ -1000,6 +1006,7 @@ int dpk_compute_device(dpk_ctx* c, int64_t natoms, const double* d_coord, const 
     HIPCHK(hipGetLastError());
     c->last_stream = s;
     c->last_n = n;
+    c->last_centres = n;
     return DPK_OK;
 }
 
@@ -1050,6 +1057,106 @@ int dpk_compute_device_noalloc(dpk_ctx* c, int64_t natoms, const double* d_coord
     HIPCHK(hipGetLastError());
     c->last_stream = s;
     c->last_n = n;
+    c->last_centres = n;
+    return DPK_OK;
+}
+
+int dpk_compute_ghost(dpk_ctx* c, int64_t nlocal, int64_t nghost, const double* coord, const int32_t* atype,
+                      const int32_t* ext_start, const int32_t* ext_list, double* energy, double* force,
+                      double* virial, double* atom_energy)
+{
+    if (!c || !coord || !atype || !energy || !force || !virial) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    if (nlocal < 1 || nghost < 0 || nlocal + nghost > (1LL << 30))
+        return fail(DPK_E_INVALID_ARG, "nlocal = %lld, nghost = %lld", (long long)nlocal, (long long)nghost);
+    if ((ext_start == nullptr) != (ext_list == nullptr))
+        return fail(DPK_E_INVALID_ARG, "ext_start and ext_list go together");
+    const dpk_model* m = c->model;
+    const int nt = m->desc.ntypes;
+    if (nghost > 0 && nt >= MAXT)
+        return fail(DPK_E_UNIMPLEMENTED, "ghost atoms need fewer than %d atom types", MAXT);
+    const int64_t ntot = nlocal + nghost;
+    int64_t next = 0;
+    if (ext_start) {
+        if (ext_start[0] != 0) return fail(DPK_E_INVALID_ARG, "ext_start[0] must be 0");
+        for (int64_t i = 0; i < nlocal; ++i)
+            if (ext_start[i + 1] < ext_start[i]) return fail(DPK_E_INVALID_ARG, "ext_start decreases at %lld", (long long)i);
+        next = ext_start[nlocal];
+        for (int64_t q = 0; q < next; ++q)
+            if (ext_list[q] < 0 || ext_list[q] >= ntot)
+                return fail(DPK_E_INVALID_ARG, "ext_list[%lld] = %d is outside [0, %lld)", (long long)q, ext_list[q],
+                            (long long)ntot);
+    }
+    HIPCHK(hipSetDevice(c->device));
+    // open geometry over owned and ghost atoms (ghosts carry image positions)
+    double bb[6] = {1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < ntot; ++i)
+        for (int k = 0; k < 3; ++k) {
+            bb[k] = std::min(bb[k], coord[3 * i + k]);
+            bb[3 + k] = std::max(bb[3 + k], coord[3 * i + k]);
+        }
+    GeomParams gp;
+    int rc;
+    c->cur_natoms = ntot;
+    if ((rc = setup_geometry(c, nullptr, bb, gp))) return rc;
+    if ((rc = ensure_ws(c, ntot, (int64_t)gp.nb[0] * gp.nb[1] * gp.nb[2]))) return rc;
+    hipStream_t s = c->stream;
+    if (ext_start) {
+        const size_t need = (size_t)(nlocal + 1 + next);
+        if (need > c->ext_cap) {
+            HIPCHK(hipStreamSynchronize(s));
+            hipFree(c->ext_buf);
+            c->ext_buf = nullptr;
+            c->ext_cap = 0;
+            if (hipMalloc((void**)&c->ext_buf, sizeof(int) * need) != hipSuccess) {
+                hipGetLastError();
+                c->ext_buf = nullptr;
+                return fail(DPK_E_OOM, "hipMalloc of %zu bytes for the external neighbour list failed", sizeof(int) * need);
+            }
+            c->ext_cap = need;
+        }
+        HIPCHK(hipMemcpyAsync(c->ext_buf, ext_start, sizeof(int) * (nlocal + 1), hipMemcpyHostToDevice, s));
+        if (next) HIPCHK(hipMemcpyAsync(c->ext_buf + nlocal + 1, ext_list, sizeof(int) * next, hipMemcpyHostToDevice, s));
+    }
+    const int n = (int)ntot, nl = (int)nlocal;
+    HIPCHK(hipMemcpyAsync(c->h_coord, coord, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->h_atype, atype, sizeof(int) * n, hipMemcpyHostToDevice, s));
+    double* o = c->h_out;   // E, virial, F [n][3], E_i [nlocal]
+    double* d_force = o + 10;
+    {
+        if (!launch_prep_small(n, c->h_coord, c->h_atype, nt, gp, c->tcount, c->toff, c->perm, c->inv_perm, c->itype,
+                               c->stats, c->pos, c->cell_of, c->cell_start, c->cand, d_force, s, nl)) {
+            if (!c->cells_clear) launch_zero(c->cell_count, sizeof(int) * (size_t)c->cap_cells, s);
+            c->cells_clear = false;
+            launch_prep_large(n, c->h_coord, c->h_atype, nt, gp, c->tcount, c->toff, c->bcount, c->boff, c->perm,
+                              c->inv_perm, c->itype, c->stats, c->pos, c->cell_of, c->cell_count, c->cell_start,
+                              c->cursor, c->cell_tmp, c->cand, d_force, s, nl);
+            c->cells_clear = true;
+        }
+        // lists for the owned atoms only (internal positions 0.. nlocal - 1); candidates are all atoms
+        if (ext_start)
+            launch_nlist_ext(nl, n, c->pos, c->perm, c->inv_perm, c->itype, c->ext_buf, c->ext_buf + nl + 1, gp,
+                             c->nl_j, c->nl_r, c->nnei, c->stats, s);
+        else
+            launch_nlist(nl, c->pos, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cand, gp, c->nl_j, c->nl_r,
+                         c->nnei, c->stats, s);
+        // descriptor, fitting and adjoint over the owned atoms: E_i of owned atoms only; forces land
+        // on owned and ghost atoms alike (the ghosts' are the caller's to send back to their owners)
+        run_network(c, nl, gp, d_force, nullptr, true, atom_energy ? o + 10 + 3 * n : nullptr, nullptr, s);
+        launch_finalize(embed_bwd_blocks(c->precision, c->tab, nl, c->ncu), c->vir_part, o, o + 1, c->stats, s);
+        HIPCHK(hipGetLastError());
+        c->last_stream = s;
+        c->last_n = n;
+        c->last_centres = nl;
+        // open geometry runs with the largest candidate buffer already: an overflow is final
+        rc = dpk_ctx_check(c);
+    }
+    if (rc) return rc;
+    std::vector<double> host(10 + 3 * (size_t)n + (atom_energy ? nlocal : 0));
+    HIPCHK(hipMemcpy(host.data(), o, sizeof(double) * host.size(), hipMemcpyDeviceToHost));
+    *energy = host[0];
+    std::memcpy(virial, &host[1], sizeof(double) * 9);
+    std::memcpy(force, &host[10], sizeof(double) * 3 * n);
+    if (atom_energy) std::memcpy(atom_energy, &host[10 + 3 * n], sizeof(double) * nlocal);
     return DPK_OK;
 }
 
@@ -1190,7 +1297,7 @@ int dpk_debug_nlist(dpk_ctx* c, int32_t* nlist)
     const int n = (int)c->last_n, nc = c->model->nc;
     int* d = nullptr;
     HIPCHK(hipMalloc(&d, sizeof(int) * (size_t)n * nc));
-    launch_debug_nlist(n, nc, c->perm, c->nl_j, d, c->last_stream);
+    launch_debug_nlist(n, (int)c->last_centres, nc, c->perm, c->nl_j, d, c->last_stream);
     hipError_t e = hipStreamSynchronize(c->last_stream);
     if (e == hipSuccess) e = hipMemcpy(nlist, d, sizeof(int) * (size_t)n * nc, hipMemcpyDeviceToHost);
     hipFree(d);
@@ -1216,8 +1323,9 @@ int dpk_debug_descriptor(dpk_ctx* c, double* T, double* dT)
     for (int64_t a = 0; a < n; ++a)
         for (int64_t k = 0; k < per; ++k) {
             const int64_t src = a * per + k, dst = (int64_t)perm[a] * per + k;
-            T[dst] = val(bt, src);
-            dT[dst] = val(bd, src);
+            const bool centre = a < c->last_centres;   // ghost atoms have no descriptor
+            T[dst] = centre ? val(bt, src) : 0.0;
+            dT[dst] = centre ? val(bd, src) : 0.0;
         }
     return DPK_OK;
 }
@@ -1478,6 +1586,7 @@ int dpk_devi_compute(dpk_devi* d, int64_t natoms, const double* coord, const int
     HIPCHK(hipGetLastError());
     c->last_stream = s;
     c->last_n = n;
+    c->last_centres = n;
     rc = dpk_ctx_check(c);
     if (rc == DPK_E_NBR_OVERFLOW && !c->strict) {
         // a locally dense frame overflowed the estimated candidate buffer: once more with the largest

@@ -179,8 +179,8 @@ struct EmbArgs {
     // whose parameters and per-model buffers start k times these byte strides past the pointers
     // above; the geometry (types, neighbour list, perm) and the statistics block are shared.
     // nmodels 0 or 1: a single model.
-    int nmodels;
-    int64_t ms_evec, ms_emat, ms_table, ms_T, ms_F, ms_Ei, ms_vir, ms_ae;
+    int nmodels = 0;
+    int64_t ms_evec = 0, ms_emat = 0, ms_table = 0, ms_T = 0, ms_F = 0, ms_Ei = 0, ms_vir = 0, ms_ae = 0;
 };
 
 // The arguments of the model that blockIdx.y selects.
@@ -218,8 +218,8 @@ struct FitArgs {
     void* act;              // forward activations and gradients (scratch)
     double* Ei;             // [N]
     // model ensemble: as in EmbArgs (blockIdx.y = model, byte strides of the per-model pointers)
-    int nmodels;
-    int64_t ms_fvec, ms_fmat, ms_T, ms_act, ms_Ei;
+    int nmodels = 0;
+    int64_t ms_fvec = 0, ms_fmat = 0, ms_T = 0, ms_act = 0, ms_Ei = 0;
 };
 
 __device__ inline FitArgs model_args(const FitArgs& A0)

@@ -21,12 +21,14 @@ int scratch_region(int device, void** ptr);
 void launch_prep_large(int n, const double* coord, const int* atype, int ntypes, const GeomParams& gp, int* tcount,
                        int* toff, int* bcount, int* boff, int* perm, int* inv_perm, int* itype, DevStats* st,
                        double* pos, int* cell_of, int* cell_count, int* cell_start, int* cursor, int* cell_tmp,
-                       double4* cand, double* f_int, hipStream_t s);
+                       double4* cand, double* f_int, hipStream_t s, int nlocal = -1);
 void launch_bbox(int n, const double* coord, double* out, hipStream_t s);
 // All preparation phases in one workgroup; false (nothing launched) when the frame is too large.
+// nlocal (both preparations): atoms nlocal.. n - 1 are ghosts, placed after the owned atoms in
+// the internal order (class ntypes, so ntypes < MAXT); -1: no ghosts.
 bool launch_prep_small(int n, const double* coord, const int* atype, int ntypes, const GeomParams& gp, int* tcount,
                        int* toff, int* perm, int* inv_perm, int* itype, DevStats* st, double* pos, int* cell_of,
-                       int* cell_start, double4* cand, double* f_int, hipStream_t s);
+                       int* cell_start, double4* cand, double* f_int, hipStream_t s, int nlocal = -1);
 // Single frame: gp by value, gps == nullptr. Batch: gps/fd/frame_of on the device and the largest
 // stencil and candidate buffer of the batch's frames.
 void launch_nlist(int n, const double* pos, const int* perm, const int* inv_perm, const int* cell_of,
@@ -42,7 +44,12 @@ void launch_finalize_batch(int nframes, const FrameDesc* fd, const int* inv_perm
                            const double* vir_atom, const double* f_int, double* out, DevStats* st, hipStream_t s);
 int prep_small_max_atoms();
 int prep_small_max_cells();
-void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s);
+void launch_debug_nlist(int n, int ncentre, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s);
+// Neighbour lists of the nlocal owned atoms from external candidate lists (CSR by caller index over
+// the owned atoms: ext_start [nlocal + 1], ext [ext_start[nlocal]] caller indices < ntot).
+void launch_nlist_ext(int nlocal, int ntot, const double* pos, const int* perm, const int* inv_perm, const int* itype,
+                      const int* ext_start, const int* ext, const GeomParams& gp, int* nl_j, double* nl_r, int* nnei,
+                      DevStats* st, hipStream_t s);
 // Per-atom force deviation of an ensemble of nm models (model k's forces at F + k * stride doubles).
 void launch_force_devi(int n, int nm, const double* F, int64_t stride, double nu, double* eps, hipStream_t s);
 

@@ -125,8 +125,11 @@ __device__ __forceinline__ void wrap_bin_one(const GeomParams& gp, const double*
 // One frame's preparation in one workgroup. Single frame (BATCH = false): counts the types itself
 // and zeroes the statistics block. Frame f of a batch (BATCH = true): the per-type internal bases
 // come from k_batch_scan; atoms, candidate records and bins sit at the frame's offsets.
+// Ghost atoms (single frame, caller indices nlocal.. n - 1; nlocal = n without ghosts) form one
+// more partition class after the types, so the owned atoms take internal positions 0.. nlocal - 1
+// sorted by type; itype and the candidate records keep every atom's real type.
 template <bool BATCH>
-__device__ __forceinline__ void prep_frame(int f, int n, int atom_off, const double* coord, const int* atype,
+__device__ __forceinline__ void prep_frame(int f, int n, int nlocal, int atom_off, const double* coord, const int* atype,
                                            int ntypes, const GeomParams& gp, int ncell, int cell_off,
                                            const int* type_base, int* tcount, int* toff, int* perm, int* inv_perm,
                                            int* itype, int* frame_of, DevStats* st, double* pos, int* cell_of,
@@ -143,19 +146,22 @@ __device__ __forceinline__ void prep_frame(int f, int n, int atom_off, const dou
     for (int c = tid; c < ncell; c += PS_THREADS) s_cnt[c] = 0;
     if (BATCH && tid < ntypes) s_base[tid] = type_base[tid];
     __syncthreads();   // the statistics block is zero before anything raises a flag in it
-    // types of this thread's atoms tid + PS_THREADS j, read once
-    int tv[PS_APT];
+    // types of this thread's atoms tid + PS_THREADS j, read once; tv is the partition class (the
+    // type, or ntypes for a ghost), rv the type
+    const int ncls = ntypes + (nlocal < n ? 1 : 0);
+    int tv[PS_APT], rv[PS_APT];
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < PS_APT; ++j) {
         const int a = tid + PS_THREADS * j;
         const int t0 = a < n ? atype[atom_off + a] : 0;
         bad |= t0 < 0 || t0 >= ntypes;
-        tv[j] = a < n ? clamp_type(t0, ntypes) : -1;
+        rv[j] = clamp_type(t0, ntypes);
+        tv[j] = a < n ? (a < nlocal ? rv[j] : ntypes) : -1;
     }
     if (!BATCH) {
         if (__ballot(bad) != 0 && lane == 0) atomicExch(&st->err_type, 1);
-        for (int k = 0; k < ntypes; ++k) {
+        for (int k = 0; k < ncls; ++k) {
             int v = 0;
 #pragma unroll
             for (int j = 0; j < PS_APT; ++j) v += tv[j] == k;
@@ -165,7 +171,7 @@ __device__ __forceinline__ void prep_frame(int f, int n, int atom_off, const dou
         __syncthreads();
         if (tid == 0) {
             int acc = 0;
-            for (int k = 0; k < ntypes; ++k) {
+            for (int k = 0; k < ncls; ++k) {
                 int c = 0;
                 for (int w = 0; w < PS_THREADS / 64; ++w) c += s_w[w][k];
                 toff[k] = acc;
@@ -173,7 +179,7 @@ __device__ __forceinline__ void prep_frame(int f, int n, int atom_off, const dou
                 s_base[k] = acc;
                 acc += c;
             }
-            toff[ntypes] = acc;
+            toff[ncls] = acc;
         }
         __syncthreads();
     }
@@ -187,7 +193,7 @@ __device__ __forceinline__ void prep_frame(int f, int n, int atom_off, const dou
         const int a = tid + PS_THREADS * j;
         const int t = tv[j];
         unsigned long long mine = 0;
-        for (int k = 0; k < ntypes; ++k) {
+        for (int k = 0; k < (BATCH ? ntypes : ncls); ++k) {
             const unsigned long long m = __ballot(t == k);
             if (t == k) mine = m;
             if (lane == 0) s_w[wid][k] = __popcll(m);
@@ -200,11 +206,11 @@ __device__ __forceinline__ void prep_frame(int f, int n, int atom_off, const dou
             qv[j] = q;
             perm[q] = atom_off + a;
             inv_perm[atom_off + a] = q;
-            itype[q] = t;
+            itype[q] = rv[j];
             if (BATCH) frame_of[q] = f;
         }
         __syncthreads();
-        if (tid < ntypes) {
+        if (tid < (BATCH ? ntypes : ncls)) {
             int c = 0;
             for (int w = 0; w < PS_THREADS / 64; ++w) c += s_w[w][tid];
             s_base[tid] += c;
@@ -270,7 +276,7 @@ __device__ __forceinline__ void prep_frame(int f, int n, int atom_off, const dou
         if (q < 0) continue;
         const int slot = atomicAdd(&s_cnt[cv[j]], 1);
         const long long tag = (long long)q | ((long long)(atom_off + tid + PS_THREADS * j) << 30) |
-                              ((long long)tv[j] << 60);
+                              ((long long)rv[j] << 60);
         cand[atom_off + slot] = make_double4(xv[j][0], xv[j][1], xv[j][2], __longlong_as_double(tag));
     }
 }
@@ -288,15 +294,16 @@ __device__ __forceinline__ void prep_frame(int f, int n, int atom_off, const dou
 //                 same bits as in k_prep_count), zeroed force accumulators, and the candidate
 //                 record of every atom at the next free slot of its bin (the order within a bin
 //                 is not fixed: the neighbour list sorts its hits by a key unique per candidate).
-__global__ void __launch_bounds__(TP_BLOCK) k_prep_count(int n, const double* coord, const int* atype, int ntypes,
-                                                         GeomParams gp, int* bcount, int* cell_tmp, int* cell_count)
+__global__ void __launch_bounds__(TP_BLOCK) k_prep_count(int n, int nlocal, const double* coord, const int* atype,
+                                                         int ntypes, GeomParams gp, int* bcount, int* cell_tmp,
+                                                         int* cell_count)
 {
     __shared__ int h[MAXT];
     if (threadIdx.x < MAXT) h[threadIdx.x] = 0;
     __syncthreads();
     const int i = blockIdx.x * TP_BLOCK + threadIdx.x;
     if (i < n) {
-        atomicAdd(&h[clamp_type(atype[i], ntypes)], 1);
+        atomicAdd(&h[i < nlocal ? clamp_type(atype[i], ntypes) : ntypes], 1);   // ghosts: one class after the types
         const double x[3] = {coord[3 * (size_t)i], coord[3 * (size_t)i + 1], coord[3 * (size_t)i + 2]};
         double p[3];
         int b[3];
@@ -366,25 +373,27 @@ __global__ void __launch_bounds__(1024) k_prep_scan(int nblocks, int ntypes, con
     if (tid == 0) cell_start[ncell] = total;
 }
 
-__global__ void __launch_bounds__(TP_BLOCK) k_prep_scatter(int n, const double* coord, const int* atype, int ntypes,
-                                                           GeomParams gp, const int* boff, const int* cell_tmp,
-                                                           int* perm, int* inv_perm, int* itype, double* pos,
-                                                           int* cell_of, int* cursor, double4* cand, double* f_int,
-                                                           DevStats* st)
+__global__ void __launch_bounds__(TP_BLOCK) k_prep_scatter(int n, int nlocal, const double* coord, const int* atype,
+                                                           int ntypes, GeomParams gp, const int* boff,
+                                                           const int* cell_tmp, int* perm, int* inv_perm, int* itype,
+                                                           double* pos, int* cell_of, int* cursor, double4* cand,
+                                                           double* f_int, DevStats* st)
 {
     __shared__ int wsum[TP_BLOCK / 64];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int i = blockIdx.x * TP_BLOCK + tid;
-    int t = -1;
+    const int ncls = ntypes + (nlocal < n ? 1 : 0);
+    int t = -1, cls = -1;
     if (i < n) {
         const int t0 = atype[i];
         if (t0 < 0 || t0 >= ntypes) atomicExch(&st->err_type, 1);
         t = clamp_type(t0, ntypes);
+        cls = i < nlocal ? t : ntypes;   // ghosts: one class after the types
     }
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int q = -1;
-    for (int k = 0; k < ntypes; ++k) {
-        const bool f = (t == k);
+    for (int k = 0; k < ncls; ++k) {
+        const bool f = (cls == k);
         const unsigned long long m = __ballot(f);
         if (lane == 0) wsum[wid] = __popcll(m);
         __syncthreads();
@@ -412,13 +421,14 @@ __global__ void __launch_bounds__(TP_BLOCK) k_prep_scatter(int n, const double* 
     cand[slot] = make_double4(p[0], p[1], p[2], __longlong_as_double(tag));
 }
 
-__global__ void __launch_bounds__(PS_THREADS) k_prep_small(int n, const double* coord, const int* atype, int ntypes,
-                                                            GeomParams gp, int ncell, int* tcount, int* toff, int* perm,
-                                                            int* inv_perm, int* itype, DevStats* st, double* pos,
-                                                            int* cell_of, int* cell_start, double4* cand, double* f_int)
+__global__ void __launch_bounds__(PS_THREADS) k_prep_small(int n, int nlocal, const double* coord, const int* atype,
+                                                            int ntypes, GeomParams gp, int ncell, int* tcount,
+                                                            int* toff, int* perm, int* inv_perm, int* itype,
+                                                            DevStats* st, double* pos, int* cell_of, int* cell_start,
+                                                            double4* cand, double* f_int)
 {
-    prep_frame<false>(0, n, 0, coord, atype, ntypes, gp, ncell, 0, nullptr, tcount, toff, perm, inv_perm, itype,
-                      nullptr, st, pos, cell_of, cell_start, cand, f_int, nullptr);
+    prep_frame<false>(0, n, nlocal, 0, coord, atype, ntypes, gp, ncell, 0, nullptr, tcount, toff, perm, inv_perm,
+                      itype, nullptr, st, pos, cell_of, cell_start, cand, f_int, nullptr);
 }
 
 // ---- batched frames (serving): per-frame type counts, cross-frame type bases, per-frame prep --
@@ -481,7 +491,7 @@ __global__ void __launch_bounds__(PS_THREADS) k_prep_batch(const double* coord, 
 {
     const int f = blockIdx.x;
     const FrameDesc& d = fd[f];
-    prep_frame<true>(f, d.natoms, d.atom_off, coord, atype, ntypes, gps[f], d.ncell, d.cell_off, d.type_base,
+    prep_frame<true>(f, d.natoms, d.natoms, d.atom_off, coord, atype, ntypes, gps[f], d.ncell, d.cell_off, d.type_base,
                      nullptr, nullptr, perm, inv_perm, itype, frame_of, nullptr, pos, cell_of, cell_start, cand, f_int,
                      vir_atom);
 }
@@ -611,6 +621,86 @@ __device__ void bitonic_keys_lds(int count, int lane, unsigned long long* khi, u
             }
             wave_barrier();
         }
+}
+
+// The selection of one atom's list from its count hits (keys in LDS: type, r^2, caller index,
+// image code; kq the candidate each key came from; tcount the hits per type, which may exceed the
+// CAP stored keys): keys sorted in LDS, the first sel[t] of each type block written to row a of
+// the list (fetch(kq, code, r, j) gives the candidate's r_ij and caller index), padding -1, the
+// kept counts, and the neighbours dropped by sel.
+template <int CAP, class Fetch>
+__device__ __forceinline__ void nlist_select(int a, int lane, int count, int* tcount, const GeomParams& gp,
+                                             unsigned long long* khi, unsigned long long* klo, int* kq, int* nl_j,
+                                             double* nl_r, int* nnei, DevStats* st, Fetch&& fetch)
+{
+    // one word shared by every atom: only the few atoms that raise the maximum touch it atomically
+    if (lane == 0 && count > __atomic_load_n(&st->max_cand, __ATOMIC_RELAXED)) {
+        atomicMax(&st->max_cand, count);
+        if (count > CAP) atomicExch(&st->err_overflow, 1);
+    }
+    const bool overflow = count > CAP;   // wave-uniform; the frame is flagged and its list incomplete
+    if (overflow) count = CAP;
+    __syncthreads();
+    // the keys are put in order in LDS
+    static_assert(RANK_MAX <= 256, "rank sort dispatch covers at most four keys per lane");
+    if (count <= RANK_MAX) {
+        const int ER = (count + 63) >> 6;
+        if (ER <= 1) rank_keys<1>(count, lane, khi, klo, kq);
+        else if (ER == 2) rank_keys<2>(count, lane, khi, klo, kq);
+        else if (ER == 3) rank_keys<3>(count, lane, khi, klo, kq);
+        else rank_keys<4>(count, lane, khi, klo, kq);
+    } else {
+        bitonic_keys_lds(count, lane, khi, klo, kq);
+    }
+    // per-type counts of the sorted keys: every hit, unless the buffer overflowed; then only the
+    // stored hits count, so that each type block starts where its keys do and every slot the
+    // list claims is written (the overflowed frame is reported and not used)
+    int tsorted[MAXT];
+    for (int t = 0; t < gp.ntypes; ++t) tsorted[t] = tcount[t];
+    if (overflow) {
+        for (int t = 0; t < gp.ntypes; ++t) {
+            int c = 0;
+            for (int q0 = 0; q0 < count; q0 += 64) {
+                const int q = q0 + lane;
+                c += __popcll(__ballot(q < count && (int)(khi[q] >> 59) == t));
+            }
+            tsorted[t] = c;
+        }
+    }
+    int tstart[MAXT], kept[MAXT];
+    int acc = 0, drops = 0;
+    for (int t = 0; t < gp.ntypes; ++t) {
+        tstart[t] = acc;
+        acc += tsorted[t];
+        kept[t] = tsorted[t] < gp.sel[t] ? tsorted[t] : gp.sel[t];
+        drops += tcount[t] - kept[t];
+    }
+    const size_t rowj = (size_t)a * gp.nc;
+    for (int q = lane; q < count; q += 64) {
+        const unsigned long long kh = khi[q], kl = klo[q];
+        const int t = (int)(kh >> 59);
+        const int rank = q - tstart[t];
+        if (rank < gp.sel[t]) {
+            double r[3];
+            int j;
+            fetch(kq[q], (int)(kl & ((1ull << 21) - 1)), r, j);
+            const size_t slot = rowj + gp.off[t] + rank;
+            nl_j[slot] = j;
+            nl_r[3 * slot + 0] = r[0];
+            nl_r[3 * slot + 1] = r[1];
+            nl_r[3 * slot + 2] = r[2];
+        }
+    }
+    for (int s2 = lane; s2 < gp.nc; s2 += 64) {
+        int t = 0;
+        while (t + 1 < gp.ntypes && s2 >= gp.off[t + 1]) ++t;
+        if (s2 - gp.off[t] >= kept[t]) {
+            nl_j[rowj + s2] = -1;
+            for (int c = 0; c < 3; ++c) nl_r[3 * (rowj + s2) + c] = 0.0;
+        }
+    }
+    if (lane < gp.ntypes) nnei[(size_t)a * gp.ntypes + lane] = kept[lane];
+    if (lane == 0 && drops) atomicAdd(drop_slots(st) + (a & (NL_DROP_SLOTS - 1)), (unsigned long long)drops);
 }
 
 // BATCH: atom a belongs to frame frame_of[a]; its geometry is gps[frame] and its bins start at
@@ -764,77 +854,78 @@ __global__ void __launch_bounds__(64) k_nlist(int n, const double* pos, const in
             count += __popcll(m);
         }
     }
-    // one word shared by every atom: only the few atoms that raise the maximum touch it atomically
-    if (lane == 0 && count > __atomic_load_n(&st->max_cand, __ATOMIC_RELAXED)) {
-        atomicMax(&st->max_cand, count);
-        if (count > CAP) atomicExch(&st->err_overflow, 1);
-    }
-    const bool overflow = count > CAP;   // wave-uniform; the frame is flagged and its list incomplete
-    if (overflow) count = CAP;
-    __syncthreads();
-    // the keys are put in order in LDS
-    static_assert(RANK_MAX <= 256, "rank sort dispatch covers at most four keys per lane");
-    if (count <= RANK_MAX) {
-        const int ER = (count + 63) >> 6;
-        if (ER <= 1) rank_keys<1>(count, lane, khi, klo, kq);
-        else if (ER == 2) rank_keys<2>(count, lane, khi, klo, kq);
-        else if (ER == 3) rank_keys<3>(count, lane, khi, klo, kq);
-        else rank_keys<4>(count, lane, khi, klo, kq);
-    } else {
-        bitonic_keys_lds(count, lane, khi, klo, kq);
-    }
-    // per-type counts of the sorted keys: every hit, unless the buffer overflowed; then only the
-    // stored hits count, so that each type block starts where its keys do and every slot the
-    // list claims is written (the overflowed frame is reported and not used)
-    int tsorted[MAXT];
-    for (int t = 0; t < gp.ntypes; ++t) tsorted[t] = tcount[t];
-    if (overflow) {
-        for (int t = 0; t < gp.ntypes; ++t) {
-            int c = 0;
-            for (int q0 = 0; q0 < count; q0 += 64) {
-                const int q = q0 + lane;
-                c += __popcll(__ballot(q < count && (int)(khi[q] >> 59) == t));
+    nlist_select<CAP>(a, lane, count, tcount, gp, khi, klo, kq, nl_j, nl_r, nnei, st,
+                      [&](int q, int code, double* r, int& j) {
+                          const int n0 = (code >> 14) - 64, n1 = ((code >> 7) & 127) - 64, n2 = (code & 127) - 64;
+                          const double4 c4 = cand[q];
+                          j = (int)((__double_as_longlong(c4.w) >> 30) & 0x3fffffffll);   // caller index
+                          double sh[3];
+                          image_shift(gp, n0, n1, n2, sh);
+                          r[0] = (c4.x + sh[0]) - pi[0];
+                          r[1] = (c4.y + sh[1]) - pi[1];
+                          r[2] = (c4.z + sh[2]) - pi[2];
+                      });
+}
+
+// External neighbour candidates (an MD code's own list, with or without a skin; Sec. III.B.2):
+// owned atom a (internal index, caller index i = perm[a]) takes the candidates
+// ext[ext_start[i] .. ext_start[i + 1]), caller indices of owned or ghost atoms in any order,
+// without duplicates. Positions are used as given (open geometry: a ghost carries the image
+// position its owner's domain sent), so r_ij = r_j - r_i; those within r_c are ordered by (type,
+// distance, index) and selected exactly as k_nlist does. Indices outside [0, ntot) and the atom
+// itself are skipped (the host entry point rejects such lists before the launch).
+template <int CAP>
+__global__ void __launch_bounds__(64) k_nlist_ext(int ntot, const double* pos, const int* perm, const int* inv_perm,
+                                                  const int* itype, const int* ext_start, const int* ext,
+                                                  GeomParams gp, int* nl_j, double* nl_r, int* nnei, DevStats* st)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned long long nl_lds[];
+    unsigned long long* khi = nl_lds;
+    unsigned long long* klo = khi + CAP;
+    int* kq = reinterpret_cast<int*>(klo + CAP);   // internal index of the candidate, moved with its key
+    const int a = blockIdx.x, lane = threadIdx.x;
+    const int ci = perm[a];
+    const double pi[3] = {pos[3 * (size_t)a], pos[3 * (size_t)a + 1], pos[3 * (size_t)a + 2]};
+    const int b0 = ext_start[ci], b1 = ext_start[ci + 1];
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int count = 0;   // wave-uniform
+    int tcount[MAXT];
+    for (int t = 0; t < MAXT; ++t) tcount[t] = 0;
+    for (int q0 = b0; q0 < b1; q0 += 64) {
+        const int q = q0 + lane;
+        bool pass = false;
+        double r2 = 0.0;
+        int tj = 0, j = -1, jq = 0;
+        if (q < b1) {
+            j = ext[q];
+            if (j >= 0 && j < ntot && j != ci) {
+                jq = inv_perm[j];
+                tj = itype[jq];
+                const double d0 = pos[3 * (size_t)jq] - pi[0];
+                const double d1 = pos[3 * (size_t)jq + 1] - pi[1];
+                const double d2 = pos[3 * (size_t)jq + 2] - pi[2];
+                r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                pass = r2 < gp.rc2;
             }
-            tsorted[t] = c;
         }
-    }
-    int tstart[MAXT], kept[MAXT];
-    int acc = 0, drops = 0;
-    for (int t = 0; t < gp.ntypes; ++t) {
-        tstart[t] = acc;
-        acc += tsorted[t];
-        kept[t] = tsorted[t] < gp.sel[t] ? tsorted[t] : gp.sel[t];
-        drops += tcount[t] - kept[t];
-    }
-    const size_t rowj = (size_t)a * gp.nc;
-    for (int q = lane; q < count; q += 64) {
-        const unsigned long long kh = khi[q], kl = klo[q];
-        const int t = (int)(kh >> 59);
-        const int rank = q - tstart[t];
-        if (rank < gp.sel[t]) {
-            const int code = (int)(kl & ((1ull << 21) - 1));
-            const int n0 = (code >> 14) - 64, n1 = ((code >> 7) & 127) - 64, n2 = (code & 127) - 64;
-            const double4 c4 = cand[kq[q]];
-            const int j = (int)((__double_as_longlong(c4.w) >> 30) & 0x3fffffffll);   // caller index
-            double sh[3];
-            image_shift(gp, n0, n1, n2, sh);
-            const size_t slot = rowj + gp.off[t] + rank;
-            nl_j[slot] = j;
-            nl_r[3 * slot + 0] = (c4.x + sh[0]) - pi[0];
-            nl_r[3 * slot + 1] = (c4.y + sh[1]) - pi[1];
-            nl_r[3 * slot + 2] = (c4.z + sh[2]) - pi[2];
+        const unsigned long long m = __ballot(pass);
+        if (pass) {
+            const int idx = count + __popcll(m & lt);
+            if (idx < CAP) {
+                const unsigned long long rb = (unsigned long long)__double_as_longlong(r2);
+                khi[idx] = ((unsigned long long)tj << 59) | (rb >> 5);
+                klo[idx] = ((rb & 31ull) << 59) | ((unsigned long long)j << 21);   // no image: code 0
+                kq[idx] = jq;
+            }
         }
+        for (int t = 0; t < gp.ntypes; ++t) tcount[t] += __popcll(__ballot(pass && tj == t));
+        count += __popcll(m);
     }
-    for (int s2 = lane; s2 < gp.nc; s2 += 64) {
-        int t = 0;
-        while (t + 1 < gp.ntypes && s2 >= gp.off[t + 1]) ++t;
-        if (s2 - gp.off[t] >= kept[t]) {
-            nl_j[rowj + s2] = -1;
-            for (int c = 0; c < 3; ++c) nl_r[3 * (rowj + s2) + c] = 0.0;
-        }
-    }
-    if (lane < gp.ntypes) nnei[(size_t)a * gp.ntypes + lane] = kept[lane];
-    if (lane == 0 && drops) atomicAdd(drop_slots(st) + (a & (NL_DROP_SLOTS - 1)), (unsigned long long)drops);
+    nlist_select<CAP>(a, lane, count, tcount, gp, khi, klo, kq, nl_j, nl_r, nnei, st,
+                      [&](int q, int, double* r, int& jj) {
+                          jj = perm[q];
+                          for (int c = 0; c < 3; ++c) r[c] = pos[3 * (size_t)q + c] - pi[c];
+                      });
 }
 
 // ---- reductions and output ----------------------------------------------------------------
@@ -916,11 +1007,12 @@ __global__ void __launch_bounds__(256) k_finalize_batch(const FrameDesc* fd, con
 }
 
 // Debug: neighbour list (caller numbering already), rows in caller order.
-__global__ void k_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out)
+__global__ void k_debug_nlist(int n, int ncentre, int nc, const int* perm, const int* nl_j, int* out)
 {
     int a = blockIdx.x;
     int i = perm[a];
-    for (int s = threadIdx.x; s < nc; s += blockDim.x) out[(size_t)i * nc + s] = nl_j[(size_t)a * nc + s];
+    // atoms past the centres (ghost atoms) have no list
+    for (int s = threadIdx.x; s < nc; s += blockDim.x) out[(size_t)i * nc + s] = a < ncentre ? nl_j[(size_t)a * nc + s] : -1;
 }
 
 // ---- launchers --------------------------------------------------------------------------
@@ -928,26 +1020,29 @@ __global__ void k_debug_nlist(int n, int nc, const int* perm, const int* nl_j, i
 void launch_prep_large(int n, const double* coord, const int* atype, int ntypes, const GeomParams& gp, int* tcount,
                        int* toff, int* bcount, int* boff, int* perm, int* inv_perm, int* itype, DevStats* st,
                        double* pos, int* cell_of, int* cell_count, int* cell_start, int* cursor, int* cell_tmp,
-                       double4* cand, double* f_int, hipStream_t s)
+                       double4* cand, double* f_int, hipStream_t s, int nlocal)
 {
+    if (nlocal < 0) nlocal = n;
     const int nb = (n + TP_BLOCK - 1) / TP_BLOCK;
     const int ncell = gp.nb[0] * gp.nb[1] * gp.nb[2];
-    hipLaunchKernelGGL(k_prep_count, dim3(nb), dim3(TP_BLOCK), 0, s, n, coord, atype, ntypes, gp, bcount, cell_tmp,
-                       cell_count);
-    hipLaunchKernelGGL(k_prep_scan, dim3(1), dim3(1024), 0, s, nb, ntypes, bcount, boff, toff, tcount, ncell,
+    const int ncls = ntypes + (nlocal < n ? 1 : 0);
+    hipLaunchKernelGGL(k_prep_count, dim3(nb), dim3(TP_BLOCK), 0, s, n, nlocal, coord, atype, ntypes, gp, bcount,
+                       cell_tmp, cell_count);
+    hipLaunchKernelGGL(k_prep_scan, dim3(1), dim3(1024), 0, s, nb, ncls, bcount, boff, toff, tcount, ncell,
                        cell_count, cell_start, cursor, st);
-    hipLaunchKernelGGL(k_prep_scatter, dim3(nb), dim3(TP_BLOCK), 0, s, n, coord, atype, ntypes, gp, boff, cell_tmp,
-                       perm, inv_perm, itype, pos, cell_of, cursor, cand, f_int, st);
+    hipLaunchKernelGGL(k_prep_scatter, dim3(nb), dim3(TP_BLOCK), 0, s, n, nlocal, coord, atype, ntypes, gp, boff,
+                       cell_tmp, perm, inv_perm, itype, pos, cell_of, cursor, cand, f_int, st);
 }
 
 bool launch_prep_small(int n, const double* coord, const int* atype, int ntypes, const GeomParams& gp, int* tcount,
                        int* toff, int* perm, int* inv_perm, int* itype, DevStats* st, double* pos, int* cell_of,
-                       int* cell_start, double4* cand, double* f_int, hipStream_t s)
+                       int* cell_start, double4* cand, double* f_int, hipStream_t s, int nlocal)
 {
+    if (nlocal < 0) nlocal = n;
     const int ncell = gp.nb[0] * gp.nb[1] * gp.nb[2];
     if (n > PS_MAX_ATOMS || ncell > PS_MAX_CELLS) return false;
-    hipLaunchKernelGGL(k_prep_small, dim3(1), dim3(PS_THREADS), 0, s, n, coord, atype, ntypes, gp, ncell, tcount, toff,
-                       perm, inv_perm, itype, st, pos, cell_of, cell_start, cand, f_int);
+    hipLaunchKernelGGL(k_prep_small, dim3(1), dim3(PS_THREADS), 0, s, n, nlocal, coord, atype, ntypes, gp, ncell,
+                       tcount, toff, perm, inv_perm, itype, st, pos, cell_of, cell_start, cand, f_int);
     return true;
 }
 
@@ -1044,9 +1139,18 @@ void launch_force_devi(int n, int nm, const double* F, int64_t stride, double nu
     hipLaunchKernelGGL(k_force_devi, dim3((n + 255) / 256), dim3(256), 0, s, n, nm, F, stride, nu, eps);
 }
 
-void launch_debug_nlist(int n, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s)
+void launch_nlist_ext(int nlocal, int ntot, const double* pos, const int* perm, const int* inv_perm, const int* itype,
+                      const int* ext_start, const int* ext, const GeomParams& gp, int* nl_j, double* nl_r, int* nnei,
+                      DevStats* st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_debug_nlist, dim3(n), dim3(64), 0, s, n, nc, perm, nl_j, out);
+    const size_t lds = (size_t)NL_CAP * 20;
+    hipLaunchKernelGGL((k_nlist_ext<NL_CAP>), dim3(nlocal), dim3(64), lds, s, ntot, pos, perm, inv_perm, itype,
+                       ext_start, ext, gp, nl_j, nl_r, nnei, st);
+}
+
+void launch_debug_nlist(int n, int ncentre, int nc, const int* perm, const int* nl_j, int* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_debug_nlist, dim3(n), dim3(64), 0, s, n, ncentre, nc, perm, nl_j, out);
 }
 
 }  // namespace dpk

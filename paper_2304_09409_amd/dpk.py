@@ -63,6 +63,7 @@ def lib():
         L.dpk_model_save.argtypes = [vp, C.c_char_p]
         L.dpk_model_describe.argtypes = [vp, C.POINTER(_Desc), dp, dp, dp]
         L.dpk_compute_device_dbox.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.dpk_compute_ghost.argtypes = [vp, C.c_int64, C.c_int64, dp, ip, ip, ip, dp, dp, dp, dp]
         L.dpk_model_free.argtypes = [vp]
         L.dpk_model_free.restype = None
         L.dpk_ctx_create.argtypes = [vp, C.c_int, C.c_int, C.c_size_t, C.c_int, C.POINTER(vp)]
@@ -203,6 +204,27 @@ class Context:
         ae = np.empty(n) if atom_energy else None
         _check(lib().dpk_compute(self.handle, n, _dp(coord), _ip(atype), _dp(box), C.byref(e), _dp(f), _dp(v),
                                  _dp(ae)))
+        out = dict(energy=e.value, force=f, virial=v.reshape(3, 3))
+        if atom_energy:
+            out["atom_energy"] = ae
+        return out
+
+    def compute_ghost(self, coord, atype, nlocal: int, ext=None, atom_energy: bool = False) -> dict:
+        """One domain: atoms [0, nlocal) owned, the rest ghosts (dpk_compute_ghost). ext: None (the
+        library's own search) or (ext_start [nlocal + 1], ext_list) candidate lists."""
+        coord = np.ascontiguousarray(coord, dtype=np.float64)
+        atype = np.ascontiguousarray(atype, dtype=np.int32)
+        n = coord.shape[0]
+        st = li = None
+        if ext is not None:
+            st = np.ascontiguousarray(ext[0], dtype=np.int32)
+            li = np.ascontiguousarray(ext[1], dtype=np.int32)
+        e = C.c_double()
+        f = np.empty((n, 3))
+        v = np.empty(9)
+        ae = np.empty(nlocal) if atom_energy else None
+        _check(lib().dpk_compute_ghost(self.handle, nlocal, n - nlocal, _dp(coord), _ip(atype), _ip(st), _ip(li),
+                                       C.byref(e), _dp(f), _dp(v), _dp(ae)))
         out = dict(energy=e.value, force=f, virial=v.reshape(3, 3))
         if atom_energy:
             out["atom_energy"] = ae

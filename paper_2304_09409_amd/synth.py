@@ -211,6 +211,48 @@ def fcc_32000(seed: int = 3):
     return fcc_box(20, 3.6, seed)
 
 
+def ghost_bricks(coord, atype, box, nsplit=(2, 2, 2), halo: float = 6.0, seed: int | None = None):
+    """Domain decomposition of a frame in an orthorhombic periodic cell, as an MD code's spatial
+    decomposition hands it to each domain: the cell is cut into nsplit bricks; a brick owns the atoms
+    whose wrapped position lies in it, and receives as ghosts every periodic image of every atom
+    within `halo` of the brick (outside it, or inside as another image). Returns one dict per brick:
+    coord (owned first, then ghosts), atype, nlocal, and owner (the frame index of each atom, so a
+    ghost's force can be added to its owner). seed: shuffle the ghosts' order."""
+    L = np.diag(np.asarray(box, dtype=np.float64))
+    assert np.allclose(np.asarray(box) - np.diag(L), 0.0), "orthorhombic cells only"
+    x = np.asarray(coord, dtype=np.float64)
+    x = x - np.floor(x / L) * L
+    nsplit = np.asarray(nsplit)
+    w = L / nsplit
+    cell = np.minimum((x // w).astype(int), nsplit - 1)
+    shifts = np.array([[a, b, c] for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)], dtype=float)
+    rng = None if seed is None else np.random.default_rng(seed)
+    out = []
+    for bx in range(nsplit[0]):
+        for by in range(nsplit[1]):
+            for bz in range(nsplit[2]):
+                b = np.array([bx, by, bz])
+                lo, hi = b * w, (b + 1) * w
+                own = np.nonzero(np.all(cell == b, axis=1))[0]
+                gidx, gpos = [], []
+                for sh in shifts:
+                    p = x + sh * L
+                    inside = np.all((p >= lo - halo) & (p < hi + halo), axis=1)
+                    if not sh.any():
+                        inside &= ~np.all(cell == b, axis=1)
+                    k = np.nonzero(inside)[0]
+                    gidx.append(k)
+                    gpos.append(p[k])
+                gidx, gpos = np.concatenate(gidx), np.concatenate(gpos)
+                if rng is not None:
+                    pr = rng.permutation(len(gidx))
+                    gidx, gpos = gidx[pr], gpos[pr]
+                out.append({"coord": np.concatenate([x[own], gpos]),
+                            "atype": np.concatenate([np.asarray(atype)[own], np.asarray(atype)[gidx]]).astype(np.int32),
+                            "nlocal": len(own), "owner": np.concatenate([own, gidx])})
+    return out
+
+
 def ensemble_params(model: dict, base: np.ndarray, n_models: int, rel: float = 0.02, seed: int = 77):
     """Parameters of an ensemble of n_models members: the base parameters with every value
     multiplied by 1 + N(0, rel) (member 0 included), seeded. A stand-in for models trained from
