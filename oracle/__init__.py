@@ -34,8 +34,10 @@ def build(force: bool = False) -> str:
 class _Model(C.Structure):
     _fields_ = [("ntypes", C.c_int), ("sel", C.c_int * MAXT), ("rcut", C.c_double),
                 ("rcut_smth", C.c_double), ("emb", C.c_int * 3), ("axis", C.c_int),
-                ("fit", C.c_int * 3), ("type_one_side", C.c_int),
+                ("fit", C.c_int * 3), ("type_one_side", C.c_int), ("descriptor", C.c_int),
                 ("params", C.POINTER(C.c_double))]
+
+DESCRIPTORS = {"se_e2_a": 0, "se_e2_r": 1, "se_e3": 2}
 
 
 def _load():
@@ -89,6 +91,7 @@ class Oracle:
             m.fit[k] = model["fit"][k]
         m.axis = model["axis"]
         m.type_one_side = int(model["type_one_side"])
+        m.descriptor = DESCRIPTORS[model.get("descriptor", "se_e2_a")]
         m.params = _dp(self.params)
         self._m = m
         n = self.lib.orc_param_count(C.byref(m))

@@ -50,6 +50,7 @@ typedef struct {
     int axis;            /* M_<                                              */
     int fit[3];          /* fitting hidden widths, e.g. 240, 240, 240        */
     int type_one_side;   /* 0: one net per (type_i, type_j); 1: one per type_j */
+    int descriptor;      /* 0: se_e2_a (full), 1: se_e2_r (radial-only), 2: se_e3 (three-body) */
     const double *params;
 } orc_model;
 
@@ -86,13 +87,20 @@ void orc_switch(double r, double rs, double rc, double *s, double *ds)
  * ---------------------------------------------------------------------------------------- */
 typedef struct { int nin, nout; const double *W, *b, *wh; } orc_layer;
 
-static int n_emb_nets(const orc_model *m) { return m->type_one_side ? m->ntypes : m->ntypes * m->ntypes; }
+/* se_e3 always has a net per ordered pair of neighbour types (a_j, a_k), Sec. II.A.1 */
+static int n_emb_nets(const orc_model *m)
+{
+    return (m->type_one_side && m->descriptor != 2) ? m->ntypes : m->ntypes * m->ntypes;
+}
+
+/* Width of the descriptor: M x M_< for se_e2_a, M for se_e2_r and se_e3 */
+static int fit_in(const orc_model *m) { return m->descriptor == 0 ? m->emb[2] * m->axis : m->emb[2]; }
 
 long orc_param_count(const orc_model *m)
 {
     long c = 0;
     int e[4] = {1, m->emb[0], m->emb[1], m->emb[2]};
-    int f[5] = {m->emb[2] * m->axis, m->fit[0], m->fit[1], m->fit[2], 1};
+    int f[5] = {fit_in(m), m->fit[0], m->fit[1], m->fit[2], 1};
     for (int k = 0; k < 3; ++k) c += (long)n_emb_nets(m) * (e[k] * e[k + 1] + 2 * e[k + 1]);
     for (int k = 0; k < 4; ++k) c += (long)m->ntypes * (f[k] * f[k + 1] + 2 * f[k + 1]);
     return c;
@@ -119,7 +127,7 @@ static void emb_layers(const orc_model *m, int net, orc_layer L[3])
 static void fit_layers(const orc_model *m, int t, orc_layer L[4])
 {
     int e[4] = {1, m->emb[0], m->emb[1], m->emb[2]};
-    int f[5] = {m->emb[2] * m->axis, m->fit[0], m->fit[1], m->fit[2], 1};
+    int f[5] = {fit_in(m), m->fit[0], m->fit[1], m->fit[2], 1};
     const double *p = m->params;
     for (int n = 0; n < n_emb_nets(m); ++n)
         for (int k = 0; k < 3; ++k) p += (long)e[k] * e[k + 1] + 2 * e[k + 1];
@@ -524,15 +532,17 @@ static int compute_impl(const orc_model *m, long n, long ncentre, const double *
         double *G = malloc(sizeof(double) * (size_t)Nc * M);
         double *dGds = malloc(sizeof(double) * (size_t)Nc * M);
         double *R = malloc(sizeof(double) * (size_t)Nc * 4);
+        double *dRs = malloc(sizeof(double) * (size_t)Nc * 4);   /* se_e3: dE/dR per slot */
         double *S = malloc(sizeof(double) * (size_t)Nc * 3);   /* s, s', r per slot */
         double *T = malloc(sizeof(double) * (size_t)M * 4);
         double *dT = malloc(sizeof(double) * (size_t)M * 4);
         double *d = malloc(sizeof(double) * (size_t)M * A);
         double *dd = malloc(sizeof(double) * (size_t)M * A);
+        double *Gp = malloc(sizeof(double) * (size_t)M), *Gpd = malloc(sizeof(double) * (size_t)M);
 #pragma omp for schedule(dynamic, 8)
         for (long i = 0; i < ncentre; ++i) {
             int ti = type[i];
-            for (int q = 0; q < 4 * M; ++q) T[q] = 0.0;
+            /* environment rows (eq. rij, eq. switch) of the kept slots */
             for (int sl = 0; sl < Nc; ++sl) {
                 if (nlist[i * Nc + sl] < 0) continue;
                 const double *v = rij + (i * Nc + sl) * 3;
@@ -542,6 +552,74 @@ static int compute_impl(const orc_model *m, long n, long ncentre, const double *
                 S[3 * sl] = s; S[3 * sl + 1] = ds; S[3 * sl + 2] = r;
                 R[4 * sl] = s;
                 for (int k = 0; k < 3; ++k) R[4 * sl + 1 + k] = s * v[k] / r;
+            }
+            if (m->descriptor == 2) {
+                /* se_e3 (eq. descrpt-e3, eq. nn-descrpt-e3): theta_ab = R_a . R_b over every ordered
+                 * pair of kept slots (a = b included), G_ab = N^{a_a, a_b}(theta_ab),
+                 * D_m = N_c^-2 sum_ab theta_ab G_ab,m */
+                const double inv2 = inv_nc * inv_nc;
+                for (int mm = 0; mm < M; ++mm) d[mm] = 0.0;
+                for (int a = 0; a < Nc; ++a) {
+                    if (nlist[i * Nc + a] < 0) continue;
+                    for (int b = 0; b < Nc; ++b) {
+                        if (nlist[i * Nc + b] < 0) continue;
+                        double th = 0.0;
+                        for (int k = 0; k < 4; ++k) th += R[4 * a + k] * R[4 * b + k];
+                        int net = slot_type[a] * nt + slot_type[b];
+                        if (table) oor_total += orc_table_eval(m, table, tab_dx, tab_nint, net, th, Gp, Gpd);
+                        else orc_embed_eval(m, net, th, Gp, NULL, NULL);
+                        for (int mm = 0; mm < M; ++mm) d[mm] += th * Gp[mm];
+                    }
+                }
+                for (int mm = 0; mm < M; ++mm) d[mm] *= inv2;
+                ei[i] = orc_fit_eval(m, ti, d, dd);
+                /* dE/dtheta_ab = N_c^-2 sum_m dd_m (G_m + theta G'_m); theta_ab = R_a . R_b gives
+                 * dE/dR_a += dE/dtheta_ab R_b and dE/dR_b += dE/dtheta_ab R_a */
+                for (int q = 0; q < 4 * Nc; ++q) dRs[q] = 0.0;
+                for (int a = 0; a < Nc; ++a) {
+                    if (nlist[i * Nc + a] < 0) continue;
+                    for (int b = 0; b < Nc; ++b) {
+                        if (nlist[i * Nc + b] < 0) continue;
+                        double th = 0.0;
+                        for (int k = 0; k < 4; ++k) th += R[4 * a + k] * R[4 * b + k];
+                        int net = slot_type[a] * nt + slot_type[b];
+                        if (table) orc_table_eval(m, table, tab_dx, tab_nint, net, th, Gp, Gpd);
+                        else orc_embed_eval(m, net, th, Gp, Gpd, NULL);
+                        double de = 0.0;
+                        for (int mm = 0; mm < M; ++mm) de += dd[mm] * (Gp[mm] + th * Gpd[mm]);
+                        de *= inv2;
+                        for (int k = 0; k < 4; ++k) {
+                            dRs[4 * a + k] += de * R[4 * b + k];
+                            dRs[4 * b + k] += de * R[4 * a + k];
+                        }
+                    }
+                }
+                if (T_out) {
+                    for (int q = 0; q < 4 * M; ++q) T_out[i * 4 * M + q] = 0.0;
+                    for (int mm = 0; mm < M; ++mm) T_out[i * 4 * M + 4 * mm] = d[mm];
+                }
+                if (dT_out) {
+                    for (int q = 0; q < 4 * M; ++q) dT_out[i * 4 * M + q] = 0.0;
+                    for (int mm = 0; mm < M; ++mm) dT_out[i * 4 * M + 4 * mm] = dd[mm];
+                }
+                for (int sl = 0; sl < Nc; ++sl) {
+                    double *gv = g + (i * Nc + sl) * 3;
+                    gv[0] = gv[1] = gv[2] = 0.0;
+                    if (nlist[i * Nc + sl] < 0) continue;
+                    const double *dR = dRs + 4 * sl, *v = rij + (i * Nc + sl) * 3;
+                    double s = S[3 * sl], ds = S[3 * sl + 1], r = S[3 * sl + 2];
+                    double u[3] = {v[0] / r, v[1] / r, v[2] / r};
+                    double q = dR[1] * u[0] + dR[2] * u[1] + dR[3] * u[2];
+                    double radial = dR[0] * ds + q * (ds - s / r);
+                    for (int k = 0; k < 3; ++k) gv[k] = radial * u[k] + (s / r) * dR[1 + k];
+                }
+                continue;
+            }
+            /* se_e2_a / se_e2_r: G_j = N(s_j) and T = N_c^-1 G^T R */
+            for (int q = 0; q < 4 * M; ++q) T[q] = 0.0;
+            for (int sl = 0; sl < Nc; ++sl) {
+                if (nlist[i * Nc + sl] < 0) continue;
+                double s = S[3 * sl];
                 int net = m->type_one_side ? slot_type[sl] : ti * nt + slot_type[sl];
                 if (table)
                     oor_total += orc_table_eval(m, table, tab_dx, tab_nint, net, s, G + (size_t)sl * M, dGds + (size_t)sl * M);
@@ -551,21 +629,32 @@ static int compute_impl(const orc_model *m, long n, long ncentre, const double *
                     for (int k = 0; k < 4; ++k) T[4 * mm + k] += G[(size_t)sl * M + mm] * R[4 * sl + k];
             }
             for (int q = 0; q < 4 * M; ++q) T[q] *= inv_nc;
-            for (int mm = 0; mm < M; ++mm)
-                for (int nn = 0; nn < A; ++nn) {
-                    double acc = 0.0;
-                    for (int k = 0; k < 4; ++k) acc += T[4 * mm + k] * T[4 * nn + k];
-                    d[mm * A + nn] = acc;
+            if (m->descriptor == 1) {
+                /* se_e2_r (radial-only, reading: the environment matrix is the one column s):
+                 * D_m = N_c^-1 sum_j s_j G_j,m = T[m][0]; dE/dT[m][0] = dE/dD_m, other columns 0 */
+                for (int mm = 0; mm < M; ++mm) d[mm] = T[4 * mm];
+                ei[i] = orc_fit_eval(m, ti, d, dd);
+                for (int p = 0; p < M; ++p) {
+                    dT[4 * p] = dd[p];
+                    dT[4 * p + 1] = dT[4 * p + 2] = dT[4 * p + 3] = 0.0;
                 }
-            ei[i] = orc_fit_eval(m, ti, d, dd);
-            for (int p = 0; p < M; ++p)
-                for (int k = 0; k < 4; ++k) {
-                    double acc = 0.0;
-                    for (int nn = 0; nn < A; ++nn) acc += dd[p * A + nn] * T[4 * nn + k];
-                    if (p < A)
-                        for (int mm = 0; mm < M; ++mm) acc += dd[mm * A + p] * T[4 * mm + k];
-                    dT[4 * p + k] = acc;
-                }
+            } else {
+                for (int mm = 0; mm < M; ++mm)
+                    for (int nn = 0; nn < A; ++nn) {
+                        double acc = 0.0;
+                        for (int k = 0; k < 4; ++k) acc += T[4 * mm + k] * T[4 * nn + k];
+                        d[mm * A + nn] = acc;
+                    }
+                ei[i] = orc_fit_eval(m, ti, d, dd);
+                for (int p = 0; p < M; ++p)
+                    for (int k = 0; k < 4; ++k) {
+                        double acc = 0.0;
+                        for (int nn = 0; nn < A; ++nn) acc += dd[p * A + nn] * T[4 * nn + k];
+                        if (p < A)
+                            for (int mm = 0; mm < M; ++mm) acc += dd[mm * A + p] * T[4 * mm + k];
+                        dT[4 * p + k] = acc;
+                    }
+            }
             if (T_out) memcpy(T_out + i * 4 * M, T, sizeof(double) * 4 * M);
             if (dT_out) memcpy(dT_out + i * 4 * M, dT, sizeof(double) * 4 * M);
             for (int sl = 0; sl < Nc; ++sl) {
@@ -591,7 +680,7 @@ static int compute_impl(const orc_model *m, long n, long ncentre, const double *
                 for (int k = 0; k < 3; ++k) gv[k] = radial * u[k] + (s / r) * dR[1 + k];
             }
         }
-        free(G); free(dGds); free(R); free(S); free(T); free(dT); free(d); free(dd);
+        free(G); free(dGds); free(R); free(dRs); free(S); free(T); free(dT); free(d); free(dd); free(Gp); free(Gpd);
     }
 
     /* serial accumulation in a fixed order */

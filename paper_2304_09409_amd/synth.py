@@ -33,12 +33,21 @@ FCC_MODEL = dict(ntypes=1, sel=[138], rcut=8.0, rcut_smth=2.0, emb=[25, 50, 100]
 SERVE_MODEL = dict(ntypes=3, sel=[92, 92, 46], rcut=6.0, rcut_smth=0.5, emb=[25, 50, 100],
                    axis=16, fit=[240, 240, 240], type_one_side=False)
 
+# The other DeepPot-SE descriptors on the water-like systems: radial-only two-body embedding
+# (se_e2_r, same cut-offs and capacities) and the three-body embedding (se_e3, whose pair sum over
+# neighbour pairs grows as the square of the neighbour count: shorter cut-off, smaller capacities).
+WATER_R_MODEL = dict(WATER_MODEL, descriptor="se_e2_r")
+WATER_E3_MODEL = dict(ntypes=2, sel=[20, 40], rcut=4.0, rcut_smth=0.5, emb=[25, 50, 100],
+                      axis=16, fit=[240, 240, 240], type_one_side=False, descriptor="se_e3")
+
 # Scales of the first fitting layer and of the output layer, chosen once so that the random
 # models respond to geometry like trained ones: RMS force component about 1 eV/A on the
 # 12,288-atom water box, and about 0.2 eV/A (a thermal metal) on the 32,000-atom fcc box.
 WATER_FIT_IN, WATER_OUT_SCALE = 1000.0, 5.07
 FCC_FIT_IN, FCC_OUT_SCALE = 30.0, 300.0
 SERVE_FIT_IN, SERVE_OUT_SCALE = 1000.0, 5.07
+WATER_R_FIT_IN, WATER_R_OUT_SCALE = 30.0, 10.0
+WATER_E3_FIT_IN, WATER_E3_OUT_SCALE = 300.0, 11.0
 
 PARAM_SEED = 2304
 
@@ -140,11 +149,15 @@ def serving_stream(n_req: int, seed: int, n_min: int = 50, n_max: int = 3000):
 
 
 def layer_shapes(model: dict):
-    """(n_in, n_out) of every layer, embedding nets first, then fitting nets."""
+    """(n_in, n_out) of every layer, embedding nets first, then fitting nets. The descriptor kind
+    ("se_e2_a" default, "se_e2_r", "se_e3") sets the fitting input width (M x M_< or M) and the
+    net count (se_e3: a net per ordered pair of neighbour types)."""
     nt = model["ntypes"]
-    n_emb = nt if model["type_one_side"] else nt * nt
+    desc = model.get("descriptor", "se_e2_a")
+    n_emb = nt if (model["type_one_side"] and desc != "se_e3") else nt * nt
     emb = [1] + list(model["emb"])
-    fit = [model["emb"][-1] * model["axis"]] + list(model["fit"]) + [1]
+    width = model["emb"][-1] * model["axis"] if desc == "se_e2_a" else model["emb"][-1]
+    fit = [width] + list(model["fit"]) + [1]
     shapes = []
     for _ in range(n_emb):
         shapes += [(emb[k], emb[k + 1]) for k in range(len(emb) - 1)]
@@ -166,7 +179,7 @@ def make_params(model: dict, seed: int = PARAM_SEED, out_scale: float = 1.0,
     multiplied by out_scale and its bias is 0."""
     rng = np.random.default_rng(seed)
     nt = model["ntypes"]
-    n_emb = nt if model["type_one_side"] else nt * nt
+    n_emb = nt if (model["type_one_side"] and model.get("descriptor", "se_e2_a") != "se_e3") else nt * nt
     n_emb_layers = n_emb * len(model["emb"])
     shapes = layer_shapes(model)
     n_fit_layers = len(model["fit"]) + 1
@@ -263,6 +276,14 @@ def ensemble_params(model: dict, base: np.ndarray, n_models: int, rel: float = 0
 
 def water_params(seed: int = PARAM_SEED) -> np.ndarray:
     return make_params(WATER_MODEL, seed, WATER_OUT_SCALE, WATER_FIT_IN)
+
+
+def water_r_params(seed: int = PARAM_SEED + 7) -> np.ndarray:
+    return make_params(WATER_R_MODEL, seed, WATER_R_OUT_SCALE, WATER_R_FIT_IN)
+
+
+def water_e3_params(seed: int = PARAM_SEED + 7) -> np.ndarray:
+    return make_params(WATER_E3_MODEL, seed, WATER_E3_OUT_SCALE, WATER_E3_FIT_IN)
 
 
 def fcc_params(seed: int = PARAM_SEED + 1) -> np.ndarray:
