@@ -60,6 +60,8 @@ enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_TYPE = -2, ORC_E_BOX = -3, ORC_E_MEM = 
  * Switching function, Sec. II.A.1 (eq. switch):
  *   s = 1/r for r < r_s;  s = u(x)/r for r_s <= r < r_c with x = (r - r_s)/(r_c - r_s) and
  *   u(x) = x^3 (-6 x^2 + 15 x - 10) + 1;  s = 0 for r >= r_c.
+ *   u is evaluated as (1 - x)^3 (1 + 3 x + 6 x^2), the same polynomial factored: no cancellation
+ *   near x = 1, so s >= 0 holds in floating point too.
  *   ds/dr by the quotient rule, with u'(x) = -30 x^2 (x - 1)^2.
  * ---------------------------------------------------------------------------------------- */
 void orc_switch(double r, double rs, double rc, double *s, double *ds)
@@ -69,7 +71,8 @@ void orc_switch(double r, double rs, double rc, double *s, double *ds)
         *ds = -1.0 / (r * r);
     } else if (r < rc) {
         double x = (r - rs) / (rc - rs);
-        double u = x * x * x * (-6.0 * x * x + 15.0 * x - 10.0) + 1.0;
+        double y = 1.0 - x;
+        double u = y * y * y * (1.0 + 3.0 * x + 6.0 * x * x);
         double du = -30.0 * x * x * (x - 1.0) * (x - 1.0);
         *s = u / r;
         *ds = du / ((rc - rs) * r) - u / (r * r);

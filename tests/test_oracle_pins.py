@@ -36,6 +36,24 @@ def test_switch_special_values(water_oracle):
     assert o.switch(rc + 1.0) == (0.0, 0.0)
 
 
+def test_switch_nonnegative_and_exact_near_cutoff(water_oracle):
+    """eq. switch's quintic against its exact rational value (Fractions of the same double x):
+    relative error below 1e-13 over (r_s, r_c), including the last 1e-4 A before r_c where the
+    expanded form loses every digit to cancellation; never negative."""
+    from fractions import Fraction
+    o = water_oracle
+    rs, rc = o.model["rcut_smth"], o.model["rcut"]
+    rng = np.random.default_rng(5)
+    rr = np.concatenate([np.linspace(rs, rc, 200, endpoint=False)[1:], rc - rng.uniform(0, 1e-4, 200)])
+    for r in rr:
+        s, _ = o.switch(r)
+        assert s >= 0.0
+        x = Fraction((float(r) - rs) / (rc - rs))
+        u = x ** 3 * (-6 * x ** 2 + 15 * x - 10) + 1
+        exact = float(u / Fraction(float(r)))
+        assert abs(s - exact) <= 1e-13 * abs(exact) + 1e-300
+
+
 def test_switch_derivative_matches_fd(water_oracle):
     o = water_oracle
     for r in np.linspace(0.2, 5.9, 23):
