@@ -25,9 +25,10 @@
  *     entry point's stream-ordered completion.
  *
  * Model parameter blob (FP64, flat, owned by the caller during dpk_model_create only):
- *   embedding nets first, net index e = a_i * ntypes + a_j (or e = a_j when type_one_side),
- *   each with layers 1 -> emb[0] -> emb[1] -> emb[2]; then one fitting net per type a_i with
- *   layers (emb[2] * axis) -> fit[0] -> fit[1] -> fit[2] -> 1. Every layer stores
+ *   embedding nets first, net index e = a_i * ntypes + a_j (or e = a_j when type_one_side; for
+ *   se_e3 e = a_j * ntypes + a_k), each with layers 1 -> emb[0] -> emb[1] -> emb[2]; then one
+ *   fitting net per type a_i with layers (emb[2] * axis, or emb[2] for se_e2_r and se_e3) ->
+ *   fit[0] -> fit[1] -> fit[2] -> 1. Every layer stores
  *   W [n_in][n_out] row-major, then b [n_out], then w_hat [n_out]. Hidden layers use tanh with a
  *   skip connection +x when n_out == n_in and +{x,x} when n_out == 2 n_in; the fitting output
  *   layer is linear without skip.
@@ -69,9 +70,20 @@ enum {
 
 #define DPK_MAX_TYPES 8
 
+/* Descriptor kinds (Sec. II.A.1, the DeepPot-SE family):
+ *   DPK_SE_E2_A  two-body embedding, full information: D = N_c^-2 G^T R R^T G_< (M x M_<);
+ *   DPK_SE_E2_R  two-body embedding, radial-only: the environment row is s alone and
+ *                D = N_c^-1 sum_j s_j G_j (M values; the printed radial-only form omits the s
+ *                factor, which with zero padding would make D jump at r_c);
+ *   DPK_SE_E3    three-body embedding (eq. descrpt-e3): D = N_c^-2 (R R^T) : G with
+ *                G_jk = N^{a_j, a_k}(theta_jk), theta_jk = R_j . R_k, over every ordered pair of
+ *                kept neighbours (M values); one net per ordered pair of neighbour types. */
+enum { DPK_SE_E2_A = 0, DPK_SE_E2_R = 1, DPK_SE_E3 = 2 };
+
 /* Model description. sel[] are the per-type neighbour capacities (N_c = sum of sel);
- * emb[] the embedding widths, axis = M_<, fit[] the fitting hidden widths. This build's
- * kernels require emb = {25, 50, 100}, axis = 16, fit = {240, 240, 240}. */
+ * emb[] the embedding widths, axis = M_< (se_e2_a only), fit[] the fitting hidden widths; the
+ * fitting input is M x M_< for se_e2_a and M for the other two. This build's kernels require
+ * emb = {25, 50, 100}, axis = 16, fit = {240, 240, 240}; se_e3 also N_c <= 128. */
 typedef struct {
     int32_t ntypes;
     int32_t sel[DPK_MAX_TYPES];
@@ -80,7 +92,8 @@ typedef struct {
     int32_t emb[3];
     int32_t axis;
     int32_t fit[3];
-    int32_t type_one_side;
+    int32_t type_one_side;   /* se_e2_a / se_e2_r: one net per neighbour type (not per pair)    */
+    int32_t descriptor;      /* DPK_SE_E2_A (0), DPK_SE_E2_R or DPK_SE_E3                       */
 } dpk_model_desc;
 
 typedef struct dpk_model dpk_model;   /* immutable after creation; shareable across contexts  */
@@ -97,13 +110,14 @@ typedef struct {
  * failing call on the same thread. */
 const char *dpk_last_error(void);
 
-/* Create a model (Sec. II.A: E = sum_i F_0(D^i); Sec. II.A.1: se_e2_a descriptor with per-species
- * embedding nets; Sec. II.A.2: per-species fitting nets; Sec. II.A.6, eq. NN: the layer form) from
- * a description and its FP64 parameter blob of nparams values in the layout above. The blob is
- * copied; the caller keeps ownership of desc and params. DPK_E_INVALID_ARG for a NULL pointer, a
- * bad description (ntypes outside 1..8, negative sel, sum of sel outside 1..4096, not
- * 0 < rcut_smth < rcut) or a blob of the wrong size; DPK_E_UNIMPLEMENTED for widths other than
- * emb (25, 50, 100), axis 16, fit (240, 240, 240). *out is NULL on failure. */
+/* Create a model (Sec. II.A: E = sum_i F_0(D^i); Sec. II.A.1: the se_e2_a, se_e2_r or se_e3
+ * descriptor with per-species embedding nets; Sec. II.A.2: per-species fitting nets; Sec. II.A.6,
+ * eq. NN: the layer form) from a description and its FP64 parameter blob of nparams values in the
+ * layout above. The blob is copied; the caller keeps ownership of desc and params.
+ * DPK_E_INVALID_ARG for a NULL pointer, a bad description (ntypes outside 1..8, negative sel, sum
+ * of sel outside 1..4096, not 0 < rcut_smth < rcut, an unknown descriptor) or a blob of the wrong
+ * size; DPK_E_UNIMPLEMENTED for widths other than emb (25, 50, 100), axis 16, fit (240, 240, 240),
+ * or an se_e3 model with N_c > 128. *out is NULL on failure. */
 int dpk_model_create(const dpk_model_desc *desc, const double *params, int64_t nparams,
                      dpk_model **out);
 
@@ -114,7 +128,8 @@ int64_t dpk_model_param_count(const dpk_model_desc *desc);
 /* Read a model file (the frozen model the paper's C API loads, Sec. III.A): the magic
  * "DPKMODEL", a uint64 little-endian header length, a versioned JSON header (format
  * "dpk-se_e2_a", version 1: ntypes, sel, rcut, rcut_smth, embedding, axis, fitting,
- * type_one_side, nparams, compression = null or {stride, x_max}), zero padding to a multiple of 8
+ * type_one_side, descriptor ("se_e2_a" if absent, "se_e2_r", "se_e3"), nparams, compression =
+ * null or {stride, x_max}), zero padding to a multiple of 8
  * bytes, then the FP64 blob (little-endian binary64, layout above). A compressed model's table is
  * rebuilt from the parameters at load (Sec. II.A.6), exactly as dpk_model_tabulate builds it.
  * DPK_E_INVALID_ARG for an unreadable, truncated or malformed file (the message says which key);
@@ -134,7 +149,8 @@ int dpk_model_describe(const dpk_model *m, dpk_model_desc *desc, double *params,
 /* Replace the embedding nets by quintic tables (Sec. II.A.6, eq. compress): nodes at
  * x_l = l * stride, l = 0..L_c with L_c = ceil(x_max / stride), values and first and second
  * derivatives of each net at the nodes, and the paper's coefficient formulas. The table
- * variable is the net input x = s(r). Contexts created afterwards use the table. */
+ * variable is the net input: x = s(r), or theta = R_j . R_k (in [0, 2 s_max^2]) for se_e3.
+ * Contexts created afterwards use the table. */
 int dpk_model_tabulate(dpk_model *m, double stride, double x_max);
 
 /* Free a model (NULL is ignored). Contexts created from it must be freed first. */
@@ -302,7 +318,8 @@ typedef struct {
 /* Create an ensemble on `device` in `precision` (as dpk_ctx_create) from n_models models in
  * 1..DPK_MAX_MODELS, each packed and copied to the device (the models must outlive the ensemble).
  * DPK_E_INVALID_ARG for NULL pointers, a bad count, or models whose descriptions or tables differ
- * from model 0's. */
+ * from model 0's; DPK_E_UNIMPLEMENTED for se_e3 models (the ensemble kernels cover the two-body
+ * descriptors). */
 int dpk_devi_create(const dpk_model *const *models, int n_models, int device, int precision,
                     dpk_devi **out);
 void dpk_devi_free(dpk_devi *d);

@@ -66,11 +66,21 @@ float bf16_float(uint16_t b)
     return f;
 }
 
+// Embedding nets: one per (a_i, a_j), one per a_j (type_one_side), or, for the three-body
+// descriptor, one per ordered pair of neighbour types (a_j, a_k) (Sec. II.A.1).
+int emb_nets(const dpk_model_desc* d)
+{
+    return (d->type_one_side && d->descriptor != DPK_SE_E3) ? d->ntypes : d->ntypes * d->ntypes;
+}
+
+// Width of the descriptor, the fitting net's input: M x M_< (se_e2_a) or M (se_e2_r, se_e3).
+int fit_width(const dpk_model_desc* d) { return d->descriptor == DPK_SE_E2_A ? d->emb[2] * d->axis : d->emb[2]; }
+
 int64_t count_params(const dpk_model_desc* d)
 {
     int e[4] = {1, d->emb[0], d->emb[1], d->emb[2]};
-    int f[5] = {d->emb[2] * d->axis, d->fit[0], d->fit[1], d->fit[2], 1};
-    int64_t nets = d->type_one_side ? d->ntypes : (int64_t)d->ntypes * d->ntypes;
+    int f[5] = {fit_width(d), d->fit[0], d->fit[1], d->fit[2], 1};
+    int64_t nets = emb_nets(d);
     int64_t c = 0;
     for (int k = 0; k < 3; ++k) c += nets * ((int64_t)e[k] * e[k + 1] + 2 * e[k + 1]);
     for (int k = 0; k < 4; ++k) c += (int64_t)d->ntypes * ((int64_t)f[k] * f[k + 1] + 2 * f[k + 1]);
@@ -103,7 +113,7 @@ void index_layers(dpk_model* m)
 {
     const dpk_model_desc& d = m->desc;
     int e[4] = {1, d.emb[0], d.emb[1], d.emb[2]};
-    int f[5] = {d.emb[2] * d.axis, d.fit[0], d.fit[1], d.fit[2], 1};
+    int f[5] = {fit_width(&d), d.fit[0], d.fit[1], d.fit[2], 1};
     const double* p = m->params.data();
     auto take = [&](int nin, int nout) {
         Layer L{nin, nout, p, p + (int64_t)nin * nout, p + (int64_t)nin * nout + nout};
@@ -272,6 +282,7 @@ struct dpk_ctx {
     GeomParams* gps;                     // batched frames: [BATCH_MAX_FRAMES]
     void* pin_desc = nullptr;            // pinned staging of fd and gps
     void *T, *dT, *act;
+    void* env;                           // three-body descriptor: environment rows [N][nc][4]
     DevStats* stats;
     int64_t vir_blocks = 0;
     // frame being set up (for the candidate-buffer estimate) and the overflow retry switch
@@ -293,12 +304,21 @@ int check_stats(const dpk_ctx* c, const DevStats& st);
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+bool is_e3(const dpk_ctx* c) { return c->model->desc.descriptor == DPK_SE_E3; }
+// The fitting net runs on the dense kernel (FP64 or FP32 weights, a scratch row of 6 x 240 per
+// atom) for FP64 and FP32, and for every precision when the descriptor has M values.
+bool dense_fitting(const dpk_ctx* c)
+{
+    return c->precision == DPK_FP64 || c->precision == DPK_FP32 || c->model->desc.descriptor != DPK_SE_E2_A;
+}
+
 // Byte layout of the workspace for n atoms and ncell bins; if base != nullptr, assign views.
 size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
 {
     const dpk_model* m = c->model;
     const int nt = m->desc.ntypes, nc = m->nc;
     const int64_t nvb = embed_bwd_max_blocks(c->precision, n);
+    const bool e3 = c->model->desc.descriptor == DPK_SE_E3;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char* p = base ? base + off : nullptr;
@@ -330,9 +350,10 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
     // FP64 [slots][6][240]; BF16 paths [blocks][3][16][tiles][64][4] (XF_ACT floats per 16 slots),
     // with at most 63 padding slots in either grid
     const int64_t nfit = (n + FIT_AF - 1) / FIT_AF * FIT_AF + FIT_AF;
-    const bool dense_fit = c->precision == DPK_FP64 || c->precision == DPK_FP32;
+    const bool dense_fit = dense_fitting(c);
     p = take(dense_fit ? c->acc_size * nfit * 6 * FW : sizeof(float) * (nfit / 16) * XF_ACT);
     if (base) c->act = p;
+    p = take(e3 ? c->acc_size * n * nc * 4 : 0); if (base) c->env = e3 ? p : nullptr;
     p = take(sizeof(double) * n); if (base) c->Ei = (double*)p;
     p = take(sizeof(double) * 3 * n); if (base) c->F = (double*)p;
     p = take(sizeof(double) * 10 * nvb); if (base) { c->vir_part = (double*)p; c->vir_blocks = nvb; }
@@ -500,12 +521,15 @@ int upload_model(dpk_ctx* c)
     const int prec = c->precision, nets = m->nets, nt = m->desc.ntypes;
     const bool f64 = prec == DPK_FP64;
     // FP64 and FP32 fit on the 16x16x4 MFMA with dense row-major weights (k_fit_dense); the BF16
-    // paths use fragment-major weights (k_fitx)
-    const bool dense = f64 || prec == DPK_FP32;
+    // paths use fragment-major weights (k_fitx), except for a descriptor of M values, which every
+    // precision other than FP64 fits on the dense FP32 kernel
+    const bool radial = m->desc.descriptor != DPK_SE_E2_A;
+    const bool dense = dense_fitting(c);
+    const int fprec = f64 ? DPK_FP64 : DPK_FP32;   // precision of the dense fitting weights
     std::vector<double> ev((size_t)nets * EVEC, 0.0), fv((size_t)nt * FVEC, 0.0);
     Planes em, fm;
     em.init(prec, (size_t)nets * EM_SIZE);
-    if (dense) fm.init(prec, (size_t)nt * FM_SIZE);
+    if (dense) fm.init(fprec, (size_t)nt * FM_SIZE);
     std::vector<uint16_t> fx;
     if (!dense) fx.assign((size_t)nt * XF_NFRAG * XF_ELEMS, 0);
     // feature at each row position of the embedding layers in the skip-aligned order (-1: padding,
@@ -564,19 +588,21 @@ int upload_model(dpk_ctx* c)
             continue;
         }
         const size_t base = (size_t)t * FM_SIZE;
-        for (int f = 0; f < DD; ++f)
+        // layer 1: W1^T [240][K] and W1 [K][240], K = 1600 (M x M_<) or 112 (M, zero-padded)
+        const int nin = radial ? E2 : DD, kw = radial ? N3P : DD;
+        for (int f = 0; f < nin; ++f)
             for (int o = 0; o < FW; ++o) {
                 const double w = L[0].W[(int64_t)f * FW + o];
-                fm.set(base + FM_W1T + (size_t)o * DD + kphys(prec, f), w);
-                fm.set(base + FM_W1 + (size_t)f * FW + kphys(prec, o), w);
+                fm.set(base + FM_W1T + (size_t)o * kw + kphys(fprec, f), w);
+                fm.set(base + FM_W1 + (size_t)f * FW + kphys(fprec, o), w);
             }
         for (int li = 1; li <= 2; ++li) {
             const int64_t mt = li == 1 ? FM_W2T : FM_W3T, mw = li == 1 ? FM_W2 : FM_W3;
             for (int i = 0; i < FW; ++i)
                 for (int o = 0; o < FW; ++o) {
                     const double w = L[li].W[(int64_t)i * FW + o];
-                    fm.set(base + mt + (size_t)o * FW + kphys(prec, i), w);
-                    fm.set(base + mw + (size_t)i * FW + kphys(prec, o), w);
+                    fm.set(base + mt + (size_t)o * FW + kphys(fprec, i), w);
+                    fm.set(base + mw + (size_t)i * FW + kphys(fprec, o), w);
                 }
         }
     }
@@ -597,7 +623,7 @@ int upload_model(dpk_ctx* c)
     }
     c->evec_b = ev.size() * c->acc_size;
     c->fvec_b = fv.size() * c->acc_size;
-    c->emat_b = f64 ? em.d.size() * 8 : dense ? em.f.size() * 4 : (em.h.size() + em.l.size()) * 2;
+    c->emat_b = f64 ? em.d.size() * 8 : prec == DPK_FP32 ? em.f.size() * 4 : (em.h.size() + em.l.size()) * 2;
     c->fmat_b = f64 ? fm.d.size() * 8 : dense ? fm.f.size() * 4 : fx.size() * 2;
     c->model_bytes = c->evec_b + c->fvec_b + c->emat_b + c->fmat_b;
     if (m->tabulated) {
@@ -641,7 +667,11 @@ void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* F, double* vir
     ea.nl_r = c->nl_r;
     ea.rs = m->desc.rcut_smth;
     ea.rc = m->desc.rcut;
-    ea.inv_nc = 1.0 / m->nc;
+    // se_e3: D = N_c^-2 sum over neighbour pairs; its nets are indexed by the pair's types
+    const bool e3 = is_e3(c);
+    ea.inv_nc = e3 ? 1.0 / ((double)m->nc * m->nc) : 1.0 / m->nc;
+    if (e3) ea.type_one_side = 0;
+    ea.env = c->env;
     ea.evec = c->evec;
     ea.emat = c->emat;
     ea.table = c->table;
@@ -660,7 +690,8 @@ void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* F, double* vir
     }
     const bool tab = c->tab;
     prof_mark(ev, DPK_STAGE_EMBED_FWD, s);
-    launch_embed_fwd(c->precision, tab, ea, s);
+    if (e3) launch_e3_env(c->precision, ea, s);
+    launch_embed_fwd(c->precision, tab, ea, s, e3);
 
     FitArgs fa;
     std::memset(&fa, 0, sizeof(fa));   // one model: nmodels and the per-model strides zero
@@ -675,11 +706,12 @@ void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* F, double* vir
     fa.dT = c->dT;
     fa.act = c->act;
     fa.Ei = c->Ei;
+    fa.radial = m->desc.descriptor != DPK_SE_E2_A;
     prof_mark(ev, DPK_STAGE_FIT, s);
     launch_fit(c->precision, fa, s);
 
     prof_mark(ev, DPK_STAGE_EMBED_BWD, s);
-    launch_embed_bwd(c->precision, tab, ea, s);
+    launch_embed_bwd(c->precision, tab, ea, s, e3);
 }
 
 // The launches of one frame on the views laid out for it. shared: the views point into the
@@ -711,7 +743,8 @@ void enqueue_frame(dpk_ctx* c, int n, const double* d_coord, const int* d_atype,
                  c->stats, s);
     run_network(c, n, gp, d_force, nullptr, true, d_atom_energy, ev, s);
     prof_mark(ev, DPK_STAGE_FINAL, s);
-    launch_finalize(embed_bwd_blocks(c->precision, c->tab, n, c->ncu), c->vir_part, d_energy, d_virial, c->stats, s);
+    launch_finalize(embed_bwd_blocks(c->precision, c->tab, n, c->ncu, is_e3(c)), c->vir_part, d_energy, d_virial,
+                    c->stats, s);
     prof_mark(ev, DPK_NSTAGES, s);
 }
 
@@ -850,13 +883,17 @@ int dpk_model_create(const dpk_model_desc* desc, const double* params, int64_t n
         nc += desc->sel[t];
     }
     if (nc < 1 || nc > 4096) return fail(DPK_E_INVALID_ARG, "sum of sel must be in 1..4096");
+    if (desc->descriptor < DPK_SE_E2_A || desc->descriptor > DPK_SE_E3)
+        return fail(DPK_E_INVALID_ARG, "descriptor must be DPK_SE_E2_A, DPK_SE_E2_R or DPK_SE_E3");
+    if (desc->descriptor == DPK_SE_E3 && nc > E3_MAXN)
+        return fail(DPK_E_UNIMPLEMENTED, "the three-body kernels take a sum of sel up to %d", E3_MAXN);
     const int64_t need = count_params(desc);
     if (nparams != need) return fail(DPK_E_INVALID_ARG, "parameter blob has %lld values, model needs %lld",
                                      (long long)nparams, (long long)need);
     dpk_model* m = new dpk_model;
     m->desc = *desc;
     m->params.assign(params, params + nparams);
-    m->nets = desc->type_one_side ? desc->ntypes : desc->ntypes * desc->ntypes;
+    m->nets = emb_nets(desc);
     m->nc = nc;
     index_layers(m);
     *out = m;
@@ -1142,7 +1179,7 @@ int dpk_compute_ghost(dpk_ctx* c, int64_t nlocal, int64_t nghost, const double* 
         // descriptor, fitting and adjoint over the owned atoms: E_i of owned atoms only; forces land
         // on owned and ghost atoms alike (the ghosts' are the caller's to send back to their owners)
         run_network(c, nl, gp, d_force, nullptr, true, atom_energy ? o + 10 + 3 * n : nullptr, nullptr, s);
-        launch_finalize(embed_bwd_blocks(c->precision, c->tab, nl, c->ncu), c->vir_part, o, o + 1, c->stats, s);
+        launch_finalize(embed_bwd_blocks(c->precision, c->tab, nl, c->ncu, is_e3(c)), c->vir_part, o, o + 1, c->stats, s);
         HIPCHK(hipGetLastError());
         c->last_stream = s;
         c->last_n = n;
@@ -1356,7 +1393,7 @@ namespace {
 bool same_desc(const dpk_model_desc& a, const dpk_model_desc& b)
 {
     if (a.ntypes != b.ntypes || a.rcut != b.rcut || a.rcut_smth != b.rcut_smth || a.axis != b.axis ||
-        a.type_one_side != b.type_one_side)
+        a.type_one_side != b.type_one_side || a.descriptor != b.descriptor)
         return false;
     for (int t = 0; t < a.ntypes; ++t)
         if (a.sel[t] != b.sel[t]) return false;
@@ -1372,7 +1409,7 @@ int devi_buffers(dpk_devi* d, int64_t n)
     if (n <= d->cap && d->buf) return DPK_OK;
     dpk_ctx* c = d->geo;
     const int64_t nfit = (n + FIT_AF - 1) / FIT_AF * FIT_AF + FIT_AF;
-    const bool dense_fit = c->precision == DPK_FP64 || c->precision == DPK_FP32;
+    const bool dense_fit = dense_fitting(c);
     d->st_T = align256(c->acc_size * n * E2 * 4);
     d->st_act = align256(dense_fit ? c->acc_size * nfit * 6 * FW : sizeof(float) * (nfit / 16) * XF_ACT);
     d->st_vir = align256(sizeof(double) * 10 * embed_bwd_max_blocks(c->precision, n));
@@ -1476,6 +1513,7 @@ void devi_enqueue(dpk_devi* d, int n, const GeomParams& gp, double nu, hipStream
     fa.ms_T = d->st_T;
     fa.ms_act = d->st_act;
     fa.ms_Ei = stE;
+    fa.radial = c->model->desc.descriptor != DPK_SE_E2_A;
     launch_fit(c->precision, fa, s);
     launch_embed_bwd(c->precision, c->tab, ea, s);
     const int nb = embed_bwd_blocks(c->precision, c->tab, n, c->ncu);
@@ -1503,6 +1541,8 @@ int dpk_devi_create(const dpk_model* const* models, int n_models, int device, in
             (models[k]->tabulated && (models[k]->tab_dx != models[0]->tab_dx || models[k]->tab_nint != models[0]->tab_nint)))
             return fail(DPK_E_INVALID_ARG, "model %d is compressed differently from model 0", k);
     }
+    if (models[0]->desc.descriptor == DPK_SE_E3)
+        return fail(DPK_E_UNIMPLEMENTED, "model deviation covers the two-body descriptors (se_e2_a, se_e2_r)");
     auto* d = new dpk_devi;
     d->nm = n_models;
     int rc = dpk_ctx_create(models[0], device, precision, 0, 0, &d->geo);

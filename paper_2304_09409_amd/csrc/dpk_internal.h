@@ -148,6 +148,10 @@ struct FrameDesc {
     int pad;
 };
 
+// Kept neighbours per atom of the three-body descriptor (sum of sel): the backward pass holds
+// dE/dR of every slot of a wave's atom in LDS.
+constexpr int E3_MAXN = 128;
+
 // Arguments of the embedding kernels.
 struct EmbArgs {
     int natoms, ntypes, nc, type_one_side;
@@ -168,6 +172,7 @@ struct EmbArgs {
     const void* dT;          // [N][100][4] (backward input)
     const int* perm;         // [N] caller index of each internal atom
     double* F;               // [N][3] caller order (backward output, atomics; zero on entry)
+    void* env;               // three-body descriptor: [N][nc][4] environment rows R_j (acc type)
     double* vir_part;        // [gridDim][10]: E of the block's atoms (single frame), virial
     double* vir_atom;        // [N][9] virial per centre atom (batched frames), or nullptr
     DevStats* stats;
@@ -217,6 +222,7 @@ struct FitArgs {
     void* dT;               // [N][100][4]
     void* act;              // forward activations and gradients (scratch)
     double* Ei;             // [N]
+    int radial;             // descriptor of M values D_m = T[m][0] (se_e2_r, se_e3) instead of M x M_<
     // model ensemble: as in EmbArgs (blockIdx.y = model, byte strides of the per-model pointers)
     int nmodels = 0;
     int64_t ms_fvec = 0, ms_fmat = 0, ms_T = 0, ms_act = 0, ms_Ei = 0;

@@ -57,14 +57,15 @@ void launch_force_devi(int n, int nm, const double* F, int64_t stride, double nu
 // blocks of the embedding backward for a frame on the network or the table path (one [E, virial]
 // partial each; the two paths have their own launch shapes), and their maximum over launch shapes
 // (workspace sizing)
-int embed_bwd_blocks(int precision, bool table, int64_t natoms, int ncu);
+int embed_bwd_blocks(int precision, bool table, int64_t natoms, int ncu, bool e3 = false);
 int64_t embed_bwd_max_blocks(int precision, int64_t natoms);
 // E and the virial of a single frame from the backward pass's nb partials [E, virial[9]], and the
 // frame's dropped-neighbour count into st
 void launch_finalize(int nb, const double* part, double* energy, double* virial, DevStats* st, hipStream_t s);
 int fit_atoms_per_block(int precision);
-void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s);
-void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s);
+void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s, bool e3 = false);
+void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s, bool e3 = false);
+void launch_e3_env(int precision, const EmbArgs& a, hipStream_t s);
 void launch_fit(int precision, const FitArgs& a, hipStream_t s);
 // BF16 fitting kernel (split = three products); 16-atom tiles per block for a frame of natoms
 void launch_fitx(bool split, const FitArgs& a, hipStream_t s);

@@ -327,10 +327,12 @@ __device__ __forceinline__ void switch_fn(double r, double ir, double rs, double
         s = ir;
         ds = -ir * ir;
     } else if (r < rc) {
+        // u = x^3 (-6 x^2 + 15 x - 10) + 1 as (1 - x)^3 (1 + 3 x + 6 x^2): no cancellation near
+        // r_c, so s >= 0 (a table counts negative inputs as out of range)
         double x = (r - rs) * inv_w;
-        double x2 = x * x;
-        double u = x2 * x * (x * (15.0 - 6.0 * x) - 10.0) + 1.0;
-        double du = -30.0 * x2 * (x - 1.0) * (x - 1.0);
+        double y = 1.0 - x;
+        double u = y * y * y * (1.0 + x * (3.0 + 6.0 * x));
+        double du = -30.0 * x * x * y * y;
         s = u * ir;
         ds = du * ir * inv_w - u * ir * ir;
     } else {
@@ -483,12 +485,96 @@ struct ChunkWalk {
     }
 };
 
+// Three-body descriptor (Sec. II.A.1, eq. descrpt-e3, eq. nn-descrpt-e3): the rows of the
+// embedding net are the ordered pairs (j, k) of an atom's kept neighbours, with input
+// theta_jk = R_j . R_k. A pass takes one net (a_j, a_k) and walks the pairs of the neighbour-type
+// blocks a_j x a_k of each atom: pair p is (slot off[a_j] + p / n_k, slot off[a_k] + p % n_k), n_k
+// the atom's kept count of type a_k. The two environment rows are loaded one item ahead (they come
+// from the per-frame env buffer, k_e3_env). The pass index q encodes (a_j, a_k) = (q / nt, q % nt).
+template <class P>
+struct PairWalk {
+    typedef typename P::acc acc;
+    typedef typename P::accv accv;
+    int i, a, np, nb, c0, ac;
+    bool have;
+    accv ra, rb;   // environment rows of the item's pair (prefetched)
+    int sa, sb;    // their slots
+    template <bool J = false>
+    __device__ __forceinline__ bool find_atom(const EmbArgs& A, const int*, int a0, int a1, int wave, int nw, int apw,
+                                              int ti, int q, bool skip_empty) {
+        const int nt = A.ntypes, ta = q / nt, tb = q - ta * nt;
+        for (; i < apw; ++i) {
+            a = a0 + wave + nw * i;
+            if (a >= a1) return false;
+            if (A.itype[a] != ti) continue;
+            nb = A.nnei[(size_t)a * nt + tb];
+            np = A.nnei[(size_t)a * nt + ta] * nb;
+            if (skip_empty && np == 0) continue;
+            if (J) ac = A.perm[a];
+            return true;
+        }
+        return false;
+    }
+    // Lanes past the atom's last pair (and every lane once the walk has ended) read the pair of the
+    // first slots, whose rows are finite (padding rows are zero); their values are used only under
+    // `valid`.
+    template <bool J = false>
+    __device__ __forceinline__ void fetch(const EmbArgs& A, int q, int c16) {
+        const int nt = A.ntypes, ta = q / nt, tb = q - ta * nt;
+        int ia = 0, ib = 0;
+        if (have && np > 0) {
+            const int p = min(c0 + c16, np - 1);
+            ia = p / nb;
+            ib = p - ia * nb;
+        }
+        sa = min(A.off[ta] + ia, A.nc - 1);   // (a type with sel 0 starts at nc)
+        sb = min(A.off[tb] + ib, A.nc - 1);
+        const acc* e = reinterpret_cast<const acc*>(A.env) + (have ? (size_t)a * A.nc * 4 : 0);
+        ra = *reinterpret_cast<const accv*>(e + 4 * sa);
+        rb = *reinterpret_cast<const accv*>(e + 4 * sb);
+    }
+    // keep the prefetched rows in place (see the pair walk's use in the backward pass)
+    __device__ __forceinline__ void pin() const { asm volatile("" ::"v"(ra), "v"(rb), "v"(sa), "v"(sb)); }
+};
+
+// Environment rows of the three-body descriptor, R_j = s(r_j) (1, x_j / r_j, y_j / r_j, z_j / r_j)
+// (Sec. II.A.1, eq. rij, eq. switch), for every slot of every atom: zero past an atom's kept
+// neighbours of each type block. One thread per (atom, slot).
+template <class acc>
+__global__ void __launch_bounds__(256) k_e3_env(EmbArgs A)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)A.natoms * A.nc) return;
+    const int a = (int)(e / A.nc), sl = (int)(e - (int64_t)a * A.nc);
+    int t = 0;
+    while (t + 1 < A.ntypes && sl >= A.off[t + 1]) ++t;
+    acc out[4] = {0, 0, 0, 0};
+    if (sl - A.off[t] < A.nnei[(size_t)a * A.ntypes + t]) {
+        const double* v = A.nl_r + 3 * e;
+        const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]), ir = 1.0 / r;
+        double s, ds;
+        switch_fn(r, ir, A.rs, A.rc, 1.0 / (A.rc - A.rs), s, ds);
+        const double sr = s * ir;
+        out[0] = (acc)s;
+        out[1] = (acc)(sr * v[0]);
+        out[2] = (acc)(sr * v[1]);
+        out[3] = (acc)(sr * v[2]);
+    }
+    acc* o = reinterpret_cast<acc*>(A.env) + 4 * e;
+    o[0] = out[0];
+    o[1] = out[1];
+    o[2] = out[2];
+    o[3] = out[3];
+}
+
 // ---------------------------------------------------------------------------------------------
 // Forward: T_a = N_c^-1 sum_j G_j^T R_j for every atom a (G evaluated and contracted in
 // registers, never stored). The neighbour-type blocks of atom a are separate passes (one staged
 // net each) that add into T[a]; the same lane owns T[a][m][k] in every pass.
+// E3 (three-body descriptor): the rows are neighbour pairs (PairWalk) with net input theta and
+// row (theta, 0, 0, 0), so that T[a][m][0] = D_m with A.inv_nc = N_c^-2 and T[a][m][1..3] = 0.
 // ---------------------------------------------------------------------------------------------
-template <class P, bool TAB, bool ENS>
+template <class P, bool TAB, bool ENS, bool E3>
 __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(EmbArgs A_)
 {
     // ENS: a model ensemble, blockIdx.y selects the model (a separate instantiation, so that the
@@ -519,10 +605,11 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
     if (a0 >= a1) return;
     const int t_lo = A.itype[a0], t_hi = A.itype[a1 - 1];
     const int nets = A.type_one_side ? A.ntypes : A.ntypes * A.ntypes;
+    const int npass = E3 ? A.ntypes * A.ntypes : A.ntypes;
 
     for (int ti = t_lo; ti <= t_hi; ++ti) {
-        for (int tj = 0; tj < A.ntypes; ++tj) {
-            const int net = A.type_one_side ? tj : ti * A.ntypes + tj;
+        for (int tj = 0; tj < npass; ++tj) {
+            const int net = (E3 || A.type_one_side) ? tj : ti * A.ntypes + tj;
             __syncthreads();
             if (!TAB) stage_net<P>(A, net, s_vec, s_w2, s_w3);
             __syncthreads();
@@ -531,7 +618,7 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
             const acc* tab = reinterpret_cast<const acc*>(A.table) + (size_t)net * A.tab_nint * E2 * 6;
             acc* Tout = reinterpret_cast<acc*>(A.T);
 
-            ChunkWalk<> w;
+            std::conditional_t<E3, PairWalk<P>, ChunkWalk<>> w;
             w.i = 0;
             w.c0 = 0;
             w.ac = 0;
@@ -539,7 +626,13 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
             w.fetch(A, tj, c16);
             accv Tacc[7];
             while (w.have) {
-                const double x = w.px, y = w.py, z = w.pz;
+                double x = 0.0, y = 0.0, z = 0.0;
+                acc th = 0;
+                if constexpr (E3) {
+                    th = w.ra[0] * w.rb[0] + w.ra[1] * w.rb[1] + w.ra[2] * w.rb[2] + w.ra[3] * w.rb[3];
+                } else {
+                    x = w.px; y = w.py; z = w.pz;
+                }
                 const int ca = w.a, cc0 = w.c0, cnp = w.np;
                 bool last = false;
                 w.c0 += 16;
@@ -557,12 +650,17 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
                 const bool valid = cc0 + p < cnp;
                 double s = 0.0, R[4] = {0.0, 0.0, 0.0, 0.0};
                 if (valid) {
-                    const double r = sqrt(x * x + y * y + z * z);
-                    const double ir = 1.0 / r;
-                    double ds;
-                    switch_fn(r, ir, A.rs, A.rc, inv_w, s, ds);
-                    const double sr = s * ir;
-                    R[0] = s; R[1] = sr * x; R[2] = sr * y; R[3] = sr * z;
+                    if constexpr (E3) {
+                        s = (double)th;
+                        R[0] = s;
+                    } else {
+                        const double r = sqrt(x * x + y * y + z * z);
+                        const double ir = 1.0 / r;
+                        double ds;
+                        switch_fn(r, ir, A.rs, A.rc, inv_w, s, ds);
+                        const double sr = s * ir;
+                        R[0] = s; R[1] = sr * x; R[2] = sr * y; R[3] = sr * z;
+                    }
                 }
                 wave_sync();
                 if (g == 0) {
@@ -703,8 +801,13 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
 //   g_ij = dE/dr_ij = [(dR_0 + dE/ds) s' + q (s' - s/r)] r^ + (s/r) dR_{1:3},  q = dR_{1:3} . r^,
 //   F_i += g_ij, F_j -= g_ij (FP64 atomics into caller order), Xi_ab -= g_ij,a r_ij,b (FP64,
 //   per-block partials, with E over the block's atoms for a single frame).
+// E3 (three-body descriptor, one atom per wave): a pair row gives
+//   dE/dtheta_jk = N_c^-2 sum_m dD_m (G_m + theta dG_m/dtheta)   (dT[m][0] = dE/dD_m),
+// and theta_jk = R_j . R_k adds dE/dtheta R_k to dE/dR_j and dE/dtheta R_j to dE/dR_k (LDS
+// atomics into the wave's slot rows); after the last pass each slot's dE/dR_j goes through the
+// same g_ij formula (with dE/ds folded into dR_0).
 // ---------------------------------------------------------------------------------------------
-template <class P, bool TAB, bool ENS>
+template <class P, bool TAB, bool ENS, bool E3>
 __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(EmbArgs A_)
 {
     const EmbArgs A = ENS ? model_args(A_) : A_;
@@ -729,16 +832,22 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
     // the neighbour's caller index, -1: none; the centre force of an atom that ended, and its
     // caller index); every path: the LDS atom table of the walk (its reads do not wait on the
     // in-order vector memory counter, which also holds the force atomics)
-    __shared__ __attribute__((aligned(16))) double s_defer[TAB ? NW : 1][16][4];
-    __shared__ __attribute__((aligned(16))) double s_defc[TAB ? NW : 1][4];
+    // (the table path defers; the three-body path accumulates per slot instead)
+    constexpr bool DEFER = TAB && !E3;
+    __shared__ __attribute__((aligned(16))) double s_defer[DEFER ? NW : 1][16][4];
+    __shared__ __attribute__((aligned(16))) double s_defc[DEFER ? NW : 1][4];
     __shared__ int s_wl[NW][2 * WL_MAX];
+    // three-body: dE/dR_j of every slot of the wave's atom
+    __shared__ __attribute__((aligned(16))) acc s_dRs[E3 ? NW : 1][E3 ? E3_MAXN : 1][4];
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar registers)
     const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     for (int e = lane; e < N3P * 4; e += 64) s_dT[wave][e >> 2][e & 3] = 0;
     for (int e = lane; e < 16 * 12; e += 64) s_pair[wave][e / 12][e % 12] = 0.0;
-    if (TAB && g == 0) s_defer[wave][c16][3] = -1.0;
-    if (TAB && lane == 0) s_defc[wave][3] = -1.0;
+    if (DEFER && g == 0) s_defer[wave][c16][3] = -1.0;
+    if (DEFER && lane == 0) s_defc[wave][3] = -1.0;
+    if constexpr (E3)
+        for (int e = lane; e < E3_MAXN * 4; e += 64) s_dRs[wave][e >> 2][e & 3] = 0;
     // the atomics deferred from the previous chunk (each lane issues what it stored itself)
     auto issue_deferred = [&]() {
         if (g == 0) {
@@ -763,10 +872,11 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
     const int nets = A.type_one_side ? A.ntypes : A.ntypes * A.ntypes;
     const acc* dTin = reinterpret_cast<const acc*>(A.dT);
     const int t_lo = a0 < a1 ? A.itype[a0] : 0, t_hi = a0 < a1 ? A.itype[a1 - 1] : -1;
+    const int npass = E3 ? A.ntypes * A.ntypes : A.ntypes;
 
     for (int ti = t_lo; ti <= t_hi; ++ti) {
-        for (int tj = 0; tj < A.ntypes; ++tj) {
-            const int net = A.type_one_side ? tj : ti * A.ntypes + tj;
+        for (int tj = 0; tj < npass; ++tj) {
+            const int net = (E3 || A.type_one_side) ? tj : ti * A.ntypes + tj;
             __syncthreads();
             if (!TAB) stage_net<P>(A, net, s_vec, s_w2, s_w3);
             __syncthreads();
@@ -774,11 +884,11 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
             const int64_t gpl = (int64_t)nets * EM_SIZE;
             const acc* tab = reinterpret_cast<const acc*>(A.table) + (size_t)net * A.tab_nint * E2 * 6;
 
-            ChunkWalk<true> w;
+            std::conditional_t<E3, PairWalk<P>, ChunkWalk<true>> w;
             w.i = 0;
             w.c0 = 0;
             w.ac = 0;
-            w.template load_atoms<true>(s_wl[wave], A, a0, a1, wave, NW, APW, tj, lane);
+            if constexpr (!E3) w.template load_atoms<true>(s_wl[wave], A, a0, a1, wave, NW, APW, tj, lane);
             w.have = w.template find_atom<true>(A, s_wl[wave], a0, a1, wave, NW, APW, ti, tj, true);
             w.template fetch<true>(A, tj, c16);
             acc pdT[DTL];
@@ -788,10 +898,19 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
             }
             // the first chunk's r and j are in place before the loop, as every later chunk's are
             // at the end of the previous one, so the loop itself never waits for them
-            asm volatile("" ::"v"(w.px), "v"(w.py), "v"(w.pz), "v"(w.pj));
+            if constexpr (E3) w.pin();
+            else asm volatile("" ::"v"(w.px), "v"(w.py), "v"(w.pz), "v"(w.pj));
             while (w.have) {
-                const double x = w.px, y = w.py, z = w.pz;
-                const int jn = w.pj;
+                double x = 0.0, y = 0.0, z = 0.0;
+                int jn = 0;
+                accv ra, rb;   // three-body: the pair's rows and slots
+                int sa = 0, sb = 0;
+                if constexpr (E3) {
+                    ra = w.ra; rb = w.rb; sa = w.sa; sb = w.sb;
+                } else {
+                    x = w.px; y = w.py; z = w.pz;
+                    jn = w.pj;
+                }
                 const int ca = w.a, cac = w.ac, cc0 = w.c0, cnp = w.np;
                 bool last = false;
                 w.c0 += 16;
@@ -828,14 +947,18 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                 const bool valid = cc0 + p < cnp;
                 double ir = 1.0, s = 0.0, ds = 0.0;
                 if (valid) {
-                    const double r = sqrt(x * x + y * y + z * z);
-                    ir = 1.0 / r;
-                    switch_fn(r, ir, A.rs, A.rc, inv_w, s, ds);
+                    if constexpr (E3) {
+                        s = (double)(ra[0] * rb[0] + ra[1] * rb[1] + ra[2] * rb[2] + ra[3] * rb[3]);
+                    } else {
+                        const double r = sqrt(x * x + y * y + z * z);
+                        ir = 1.0 / r;
+                        switch_fn(r, ir, A.rs, A.rc, inv_w, s, ds);
+                    }
                 }
                 // table path: the previous chunk's force atomics are issued after this chunk's
                 // prefetches and dT staging, where no wait on the vector memory counter follows
                 // for a while (that counter is in order, so any wait would include them)
-                if constexpr (TAB) {
+                if constexpr (DEFER) {
                     __builtin_amdgcn_sched_barrier(0);
                     issue_deferred();
                     __builtin_amdgcn_sched_barrier(0);
@@ -965,11 +1088,24 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                 const acc Ra[4] = {(acc)s, (acc)(sr * x), (acc)(sr * y), (acc)(sr * z)};
                 const acc dRg = sum_groups4(dR);
                 const acc hR = sum_groups(H[0] * Ra[0] + H[1] * Ra[1] + H[2] * Ra[2] + H[3] * Ra[3]);
+                if constexpr (E3) {
+                    // dE/dtheta (lane group 0 holds component 0 of dR), to every group; group g adds
+                    // component g of both rows' gradients
+                    const acc de = __shfl((acc)A.inv_nc * (dRg + hR), c16);
+                    w.pin();
+                    if (valid) {
+                        const acc rag = g == 0 ? ra[0] : g == 1 ? ra[1] : g == 2 ? ra[2] : ra[3];
+                        const acc rbg = g == 0 ? rb[0] : g == 1 ? rb[1] : g == 2 ? rb[2] : rb[3];
+                        atomicAdd(&s_dRs[wave][sa][g], de * rbg);
+                        atomicAdd(&s_dRs[wave][sb][g], de * rag);
+                    }
+                    continue;
+                }
                 const acc dR2 = __shfl(dRg, c16 + 16), dR1 = __shfl(dRg, c16 + 32), dR3 = __shfl(dRg, c16 + 48);
                 // The next chunk's prefetched r and j are put in place here, after this chunk's work
                 // and before its force atomics: reads and atomics retire in order, so waiting for the
                 // prefetch after the atomics (where the compiler otherwise sinks it) waits for them too.
-                asm volatile("" ::"v"(w.px), "v"(w.py), "v"(w.pz), "v"(w.pj));
+                if constexpr (!E3) asm volatile("" ::"v"(w.px), "v"(w.py), "v"(w.pz), "v"(w.pj));
                 if (valid && g == 0) {
                     const double inc = A.inv_nc;
                     const double d0 = inc * (double)dRg, d1 = inc * (double)dR1;
@@ -978,7 +1114,7 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                     const double q = d1 * ux + d2 * uy + d3 * uz;
                     const double rad = (d0 + dEds) * ds + q * (ds - sr);
                     const double gx = rad * ux + sr * d1, gy = rad * uy + sr * d2, gz = rad * uz + sr * d3;
-                    if constexpr (TAB) {
+                    if constexpr (DEFER) {
                         double* dfr = s_defer[wave][p];
                         dfr[0] = -gx; dfr[1] = -gy; dfr[2] = -gz; dfr[3] = (double)jn;
                     } else {
@@ -1005,20 +1141,67 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                         v += __shfl_xor(v, 8);
                         if (lane == 0) {
                             if (k < 3) {
-                                if constexpr (TAB) s_defc[wave][k] = v;
+                                if constexpr (DEFER) s_defc[wave][k] = v;
                                 else unsafeAtomicAdd(&A.F[3 * (size_t)cac + k], v);
                             } else {
                                 A.vir_atom[9 * (size_t)ca + k - 3] += v;
                             }
                         }
                     }
-                    if (TAB && lane == 0) s_defc[wave][3] = (double)cac;
+                    if (DEFER && lane == 0) s_defc[wave][3] = (double)cac;
                     wave_sync();
                     if (g == 0)
                         for (int k = 0; k < nk; ++k) s_pair[wave][c16][k] = 0.0;
                 }
             }
-            if constexpr (TAB) issue_deferred();   // the pass's last chunk
+            if constexpr (DEFER) issue_deferred();   // the pass's last chunk
+        }
+    }
+    if constexpr (E3) {
+        // slot gradients -> forces and virial (Sec. II.A.2) for the wave's atom (apw = 1)
+        wave_sync();
+        const int a = a0 + wave;
+        if (a < a1) {
+            const int nt = A.ntypes;
+            double f[3] = {0.0, 0.0, 0.0}, vir[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            for (int sl = lane; sl < A.nc; sl += 64) {
+                int t = 0;
+                while (t + 1 < nt && sl >= A.off[t + 1]) ++t;
+                if (sl - A.off[t] >= A.nnei[(size_t)a * nt + t]) continue;
+                const size_t slot = (size_t)a * A.nc + sl;
+                const double x = A.nl_r[3 * slot], y = A.nl_r[3 * slot + 1], z = A.nl_r[3 * slot + 2];
+                const int j = A.nl_j[slot];
+                const double r = sqrt(x * x + y * y + z * z), ir = 1.0 / r;
+                double s, ds;
+                switch_fn(r, ir, A.rs, A.rc, inv_w, s, ds);
+                const double ux = x * ir, uy = y * ir, uz = z * ir, sr = s * ir;
+                const double d0 = s_dRs[wave][sl][0], d1 = s_dRs[wave][sl][1], d2 = s_dRs[wave][sl][2],
+                             d3 = s_dRs[wave][sl][3];
+                const double q = d1 * ux + d2 * uy + d3 * uz;
+                const double rad = d0 * ds + q * (ds - sr);
+                const double gx = rad * ux + sr * d1, gy = rad * uy + sr * d2, gz = rad * uz + sr * d3;
+                unsafeAtomicAdd(&A.F[3 * (size_t)j], -gx);
+                unsafeAtomicAdd(&A.F[3 * (size_t)j + 1], -gy);
+                unsafeAtomicAdd(&A.F[3 * (size_t)j + 2], -gz);
+                f[0] += gx; f[1] += gy; f[2] += gz;
+                vir[0] -= gx * x; vir[1] -= gx * y; vir[2] -= gx * z;
+                vir[3] -= gy * x; vir[4] -= gy * y; vir[5] -= gy * z;
+                vir[6] -= gz * x; vir[7] -= gz * y; vir[8] -= gz * z;
+            }
+            auto wsum = [](double v) {
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+                return v;
+            };
+            for (int k = 0; k < 3; ++k) f[k] = wsum(f[k]);
+            for (int k = 0; k < 9; ++k) vir[k] = wsum(vir[k]);
+            if (lane == 0) {
+                const int ac = A.perm[a];
+                for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&A.F[3 * (size_t)ac + k], f[k]);
+                for (int k = 0; k < 9; ++k) {
+                    if (A.vir_atom) A.vir_atom[9 * (size_t)a + k] += vir[k];
+                    else s_pair[wave][0][3 + k] += vir[k];
+                }
+            }
         }
     }
     __syncthreads();
@@ -1130,11 +1313,15 @@ __device__ __forceinline__ typename P::frag fit_afrag(const char* base, int row,
 // the same lane, so the scratch row needs no synchronisation.
 // Scratch row per atom: a1, a2, a3 (tanh outputs), ga (two ping-pong buffers), gh; during the
 // forward pass the slots of the second ga buffer and of gh hold the inputs of layers 2 and 3.
+// RAD: a descriptor of M values D_m = T[m][0] (se_e2_r, se_e3): layer 1 has K = 100 (padded to
+// 112, zero weights past 100; W1^T is [240][112] and W1 [112][240] in the same slots), and the
+// input gradient is dT[m] = (dE/dD_m, 0, 0, 0).
 // ---------------------------------------------------------------------------------------------
 constexpr int F64_TP = 8;
 constexpr int FS_A1 = 0, FS_A2 = FW, FS_A3 = 2 * FW, FS_GA = 3 * FW, FS_GB = 4 * FW, FS_GH = 5 * FW, FS_ROW = 6 * FW;
+constexpr int RAD_K = N3P;   // padded width of a descriptor of M values
 
-template <class P, bool ENS>
+template <class P, bool ENS, bool RAD>
 __global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
 {
     const FitArgs A = ENS ? model_args(A_) : A_;
@@ -1172,7 +1359,7 @@ __global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) Tn[v][k] = Ta[P::kidx(0, g, v) * 4 + k];
+            for (int k = 0; k < 4; ++k) Tn[v][k] = RAD ? (acc)0 : Ta[P::kidx(0, g, v) * 4 + k];
 
         // y = W x for ntiles 16-row output tiles of the row-major matrix at fm + mo (K columns,
         // stored in the MFMA K order); x for K-chunk c is make(fetch(c)), where fetch(c) is the one
@@ -1248,15 +1435,30 @@ __global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
         };
 
         // ---------------------------------------------------------- forward
-        // layer 1: a1 = tanh(W1 D + b1), D formed on the fly from T (Eq. 7)
-        gemm(FM_W1T, DD, 15, [&](int c) { return *reinterpret_cast<const d4*>(Ta + c * 4); },
-             [&](const d4& T) {
-                 acc d[4];
+        // layer 1: a1 = tanh(W1 D + b1), D formed on the fly from T (Eq. 7); RAD: D_m = T[m][0]
+        if constexpr (RAD) {
+            gemm(FM_W1T, RAD_K, 15,
+                 [&](int c) {
+                     d4 x;
 #pragma unroll
-                 for (int v = 0; v < 4; ++v) d[v] = T[0] * Tn[v][0] + T[1] * Tn[v][1] + T[2] * Tn[v][2] + T[3] * Tn[v][3];
-                 return P::make(d[0], d[1], d[2], d[3]);
-             },
-             [&](int t, const acc* o) { wr4(FS_A1 + 16 * t + 4 * g, o); });
+                     for (int v = 0; v < 4; ++v) {
+                         const int m = P::kidx(c, g, v);
+                         x[v] = Ta[(m < E2 ? m : 0) * 4];
+                         if (m >= E2) x[v] = 0;
+                     }
+                     return x;
+                 },
+                 asis, [&](int t, const acc* o) { wr4(FS_A1 + 16 * t + 4 * g, o); });
+        } else {
+            gemm(FM_W1T, DD, 15, [&](int c) { return *reinterpret_cast<const d4*>(Ta + c * 4); },
+                 [&](const d4& T) {
+                     acc d[4];
+#pragma unroll
+                     for (int v = 0; v < 4; ++v) d[v] = T[0] * Tn[v][0] + T[1] * Tn[v][1] + T[2] * Tn[v][2] + T[3] * Tn[v][3];
+                     return P::make(d[0], d[1], d[2], d[3]);
+                 },
+                 [&](int t, const acc* o) { wr4(FS_A1 + 16 * t + 4 * g, o); });
+        }
         // layer 2 input h1 = wh1 a1 and layer 3 input h2 = wh2 a2 + h1, formed as the activations
         // are, in the slots GB and GH (the backward pass's, free until then)
         activate(FS_A1, FV_B1, [&](int t, const acc* a) {
@@ -1319,6 +1521,18 @@ __global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
                  wr4(FS_GA + 16 * t + 4 * g, ga);
              });
         // ---------------------------------------------------------- dD = W1^T ga1 and dT (Eq. 7)
+        if constexpr (RAD) {
+            // rows 16t + orow(g, r) of the 7 tiles are dE/dD_m (m < 100 stored)
+            gemm(FM_W1, FW, RAD_K / 16, rdrow(FS_GA), asis,
+                 [&](int t, const acc* dd) {
+#pragma unroll
+                     for (int r = 0; r < 4; ++r) {
+                         const int m = 16 * t + P::orow(g, r);
+                         if (mine && m < E2) *reinterpret_cast<d4*>(dTout + ((size_t)atom * E2 + m) * 4) = d4{dd[r], 0, 0, 0};
+                     }
+                 });
+            continue;
+        }
         // Tile m of dD holds dD[m][n], n < 16: dT[m] += sum_n dD[m][n] T[n] (reduced over the lane
         // groups, tiles m < 16 parked in LDS) and dT[n] += sum_m dD[m][n] T[m] (kept per lane).
         acc q2[4][4];
@@ -1377,20 +1591,29 @@ static int embed_apw(int nw, int apw_max, int64_t natoms, int ncu)
     return (int)std::max<int64_t>(1, std::min<int64_t>(apw_max, a));
 }
 
+// Atoms per wave of the backward launch: one for the three-body descriptor (a wave keeps its
+// atom's slot gradients in LDS over all passes).
 template <class P, bool TAB>
-static int embed_bwd_blocks_p(int64_t natoms, int ncu)
+static int embed_bwd_apw(int64_t natoms, int ncu, bool e3)
 {
     typedef EmbCfg<P, false, TAB> Cfg;
-    const int64_t apb = (int64_t)Cfg::NW * embed_apw(Cfg::NW, Cfg::APW_MAX, natoms, ncu);
+    return e3 ? 1 : embed_apw(Cfg::NW, Cfg::APW_MAX, natoms, ncu);
+}
+
+template <class P, bool TAB>
+static int embed_bwd_blocks_p(int64_t natoms, int ncu, bool e3)
+{
+    typedef EmbCfg<P, false, TAB> Cfg;
+    const int64_t apb = (int64_t)Cfg::NW * embed_bwd_apw<P, TAB>(natoms, ncu, e3);
     return (int)((natoms + apb - 1) / apb);
 }
 
-int embed_bwd_blocks(int precision, bool table, int64_t natoms, int ncu)
+int embed_bwd_blocks(int precision, bool table, int64_t natoms, int ncu, bool e3)
 {
-    if (precision == 0) return table ? embed_bwd_blocks_p<PF64, true>(natoms, ncu) : embed_bwd_blocks_p<PF64, false>(natoms, ncu);
-    if (precision == 1) return table ? embed_bwd_blocks_p<PMIX, true>(natoms, ncu) : embed_bwd_blocks_p<PMIX, false>(natoms, ncu);
-    if (precision == 3) return table ? embed_bwd_blocks_p<PF32, true>(natoms, ncu) : embed_bwd_blocks_p<PF32, false>(natoms, ncu);
-    return table ? embed_bwd_blocks_p<PBF16, true>(natoms, ncu) : embed_bwd_blocks_p<PBF16, false>(natoms, ncu);
+    if (precision == 0) return table ? embed_bwd_blocks_p<PF64, true>(natoms, ncu, e3) : embed_bwd_blocks_p<PF64, false>(natoms, ncu, e3);
+    if (precision == 1) return table ? embed_bwd_blocks_p<PMIX, true>(natoms, ncu, e3) : embed_bwd_blocks_p<PMIX, false>(natoms, ncu, e3);
+    if (precision == 3) return table ? embed_bwd_blocks_p<PF32, true>(natoms, ncu, e3) : embed_bwd_blocks_p<PF32, false>(natoms, ncu, e3);
+    return table ? embed_bwd_blocks_p<PBF16, true>(natoms, ncu, e3) : embed_bwd_blocks_p<PBF16, false>(natoms, ncu, e3);
 }
 
 // at least one atom per wave: the smallest block (in atoms) over both paths bounds the count
@@ -1406,62 +1629,90 @@ int64_t embed_bwd_max_blocks(int precision, int64_t natoms)
 }
 int fit_atoms_per_block(int) { return FIT_AF; }
 
+// The three-body backward kernels are instantiated explicitly: the host pass emitted no launch stub
+// for the FP64 network variant from its implicit instantiation alone.
+template __global__ void k_embed_bwd<PF64, false, false, true>(EmbArgs);
+template __global__ void k_embed_bwd<PF64, true, false, true>(EmbArgs);
+
+// e3: the three-body descriptor's pair passes (a single model; an ensemble of three-body models
+// is refused by the host).
 template <class P, bool FWD, bool TAB>
-static void launch_embed_shape(const EmbArgs& a0, hipStream_t s)
+static void launch_embed_shape(const EmbArgs& a0, bool e3, hipStream_t s)
 {
     typedef EmbCfg<P, FWD, TAB> Cfg;
     EmbArgs a = a0;
-    a.apw = embed_apw(Cfg::NW, Cfg::APW_MAX, a.natoms, a.ncu);
+    a.apw = FWD ? embed_apw(Cfg::NW, Cfg::APW_MAX, a.natoms, a.ncu) : embed_bwd_apw<P, TAB>(a.natoms, a.ncu, e3);
     const int apb = Cfg::NW * a.apw;
     const bool ens = a.nmodels > 1;
     const dim3 grid((a.natoms + apb - 1) / apb, ens ? a.nmodels : 1), block(Cfg::NW * 64);
     if constexpr (FWD) {
-        if (ens) hipLaunchKernelGGL((k_embed_fwd<P, TAB, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_embed_fwd<P, TAB, false>), grid, block, 0, s, a);
+        if (e3) hipLaunchKernelGGL((k_embed_fwd<P, TAB, false, true>), grid, block, 0, s, a);
+        else if (ens) hipLaunchKernelGGL((k_embed_fwd<P, TAB, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_embed_fwd<P, TAB, false, false>), grid, block, 0, s, a);
     } else {
-        if (ens) hipLaunchKernelGGL((k_embed_bwd<P, TAB, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_embed_bwd<P, TAB, false>), grid, block, 0, s, a);
+        if (e3) hipLaunchKernelGGL((k_embed_bwd<P, TAB, false, true>), grid, block, 0, s, a);
+        else if (ens) hipLaunchKernelGGL((k_embed_bwd<P, TAB, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_embed_bwd<P, TAB, false, false>), grid, block, 0, s, a);
     }
 }
 
 template <class P>
-static void launch_embed(bool fwd, bool table, const EmbArgs& a, hipStream_t s)
+static void launch_embed(bool fwd, bool table, const EmbArgs& a, bool e3, hipStream_t s)
 {
     if (fwd) {
-        if (table) launch_embed_shape<P, true, true>(a, s);
-        else launch_embed_shape<P, true, false>(a, s);
+        if (table) launch_embed_shape<P, true, true>(a, e3, s);
+        else launch_embed_shape<P, true, false>(a, e3, s);
     } else {
-        if (table) launch_embed_shape<P, false, true>(a, s);
-        else launch_embed_shape<P, false, false>(a, s);
+        if (table) launch_embed_shape<P, false, true>(a, e3, s);
+        else launch_embed_shape<P, false, false>(a, e3, s);
     }
 }
 
-void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s)
+void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s, bool e3)
 {
-    if (precision == 0) launch_embed<PF64>(true, table, a, s);
-    else if (precision == 1) launch_embed<PMIX>(true, table, a, s);
-    else if (precision == 3) launch_embed<PF32>(true, table, a, s);
-    else launch_embed<PBF16>(true, table, a, s);
+    if (precision == 0) launch_embed<PF64>(true, table, a, e3, s);
+    else if (precision == 1) launch_embed<PMIX>(true, table, a, e3, s);
+    else if (precision == 3) launch_embed<PF32>(true, table, a, e3, s);
+    else launch_embed<PBF16>(true, table, a, e3, s);
 }
 
-void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s)
+void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s, bool e3)
 {
-    if (precision == 0) launch_embed<PF64>(false, table, a, s);
-    else if (precision == 1) launch_embed<PMIX>(false, table, a, s);
-    else if (precision == 3) launch_embed<PF32>(false, table, a, s);
-    else launch_embed<PBF16>(false, table, a, s);
+    if (precision == 0) launch_embed<PF64>(false, table, a, e3, s);
+    else if (precision == 1) launch_embed<PMIX>(false, table, a, e3, s);
+    else if (precision == 3) launch_embed<PF32>(false, table, a, e3, s);
+    else launch_embed<PBF16>(false, table, a, e3, s);
 }
 
+void launch_e3_env(int precision, const EmbArgs& a, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.natoms * a.nc;
+    if (n == 0) return;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (precision == 0) hipLaunchKernelGGL((k_e3_env<double>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_e3_env<float>), grid, block, 0, s, a);
+}
+
+// The fitting net: FP64 and FP32 on the dense kernel, the BF16 paths on k_fitx; a descriptor of M
+// values (a.radial) always on the dense kernel (FP64, else FP32), whose first layer is then small.
 void launch_fit(int precision, const FitArgs& a, hipStream_t s)
 {
     const bool ens = a.nmodels > 1;
     dim3 grid((a.natoms + FIT_AF - 1) / FIT_AF, ens ? a.nmodels : 1), block(256);
-    if (precision == 0) {
-        if (ens) hipLaunchKernelGGL((k_fit_dense<PF64, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_fit_dense<PF64, false>), grid, block, 0, s, a);
+    if (a.radial) {
+        if (precision == 0) {
+            if (ens) hipLaunchKernelGGL((k_fit_dense<PF64, true, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_fit_dense<PF64, false, true>), grid, block, 0, s, a);
+        } else {
+            if (ens) hipLaunchKernelGGL((k_fit_dense<PF32, true, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_fit_dense<PF32, false, true>), grid, block, 0, s, a);
+        }
+    } else if (precision == 0) {
+        if (ens) hipLaunchKernelGGL((k_fit_dense<PF64, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_fit_dense<PF64, false, false>), grid, block, 0, s, a);
     } else if (precision == 3) {
-        if (ens) hipLaunchKernelGGL((k_fit_dense<PF32, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_fit_dense<PF32, false>), grid, block, 0, s, a);
+        if (ens) hipLaunchKernelGGL((k_fit_dense<PF32, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_fit_dense<PF32, false, false>), grid, block, 0, s, a);
     } else {
         launch_fitx(precision == 1, a, s);
     }

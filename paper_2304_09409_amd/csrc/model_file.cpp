@@ -11,8 +11,8 @@
 //   next H bytes    the JSON header (UTF-8), then zero bytes up to a multiple of 8
 //   then            nparams IEEE-754 binary64 values, in the blob layout of include/dpk.h
 // Header keys: "format" ("dpk-se_e2_a"), "version" (1), "ntypes", "sel", "rcut", "rcut_smth",
-// "embedding", "axis", "fitting", "type_one_side", "nparams", "compression" (null or
-// {"stride", "x_max"}). Unknown keys are ignored; a missing key, a wrong type or another format or
+// "embedding", "axis", "fitting", "type_one_side", "descriptor" ("se_e2_a", "se_e2_r", "se_e3";
+// absent means se_e2_a), "nparams", "compression" (null or {"stride", "x_max"}). Unknown keys are ignored; a missing key, a wrong type or another format or
 // version is DPK_E_INVALID_ARG.
 #include <cmath>
 #include <cstdint>
@@ -178,7 +178,9 @@ int dpk_model_save(const dpk_model* m, const char* path)
          std::to_string(d.emb[2]) + "], \"axis\": " + std::to_string(d.axis);
     h += ", \"fitting\": [" + std::to_string(d.fit[0]) + ", " + std::to_string(d.fit[1]) + ", " +
          std::to_string(d.fit[2]) + "], \"type_one_side\": " + (d.type_one_side ? "true" : "false");
-    h += ", \"nparams\": " + std::to_string((long long)np);
+    h += ", \"descriptor\": \"";
+    h += d.descriptor == DPK_SE_E2_R ? "se_e2_r" : d.descriptor == DPK_SE_E3 ? "se_e3" : "se_e2_a";
+    h += "\", \"nparams\": " + std::to_string((long long)np);
     h += ", \"compression\": ";
     h += stride > 0.0 ? "{\"stride\": " + num17(stride) + ", \"x_max\": " + num17(xmax) + "}" : std::string("null");
     h += "}\n";
@@ -235,6 +237,12 @@ int dpk_model_load(const char* path, dpk_model** out)
         tos->kind != JVal::BOOL || !as_num(root.get("nparams"), &nparams_d))
         return set_error(DPK_E_INVALID_ARG, "model header: a key is missing or has the wrong type");
     d.type_one_side = tos->b ? 1 : 0;
+    // descriptor kind (absent: se_e2_a, the only kind of the first files)
+    const JVal* dk = root.get("descriptor");
+    if (dk && dk->kind == JVal::STR && dk->str == "se_e2_r") d.descriptor = DPK_SE_E2_R;
+    else if (dk && dk->kind == JVal::STR && dk->str == "se_e3") d.descriptor = DPK_SE_E3;
+    else if (dk && !(dk->kind == JVal::STR && dk->str == "se_e2_a"))
+        return set_error(DPK_E_INVALID_ARG, "model header: descriptor must be se_e2_a, se_e2_r or se_e3");
     const int64_t np = dpk_model_param_count(&d);
     if (np < 1 || (double)np != nparams_d)
         return set_error(DPK_E_INVALID_ARG, "model header: nparams does not match the description");

@@ -28,7 +28,9 @@ class DpkError(RuntimeError):
 class _Desc(C.Structure):
     _fields_ = [("ntypes", C.c_int32), ("sel", C.c_int32 * MAX_TYPES), ("rcut", C.c_double),
                 ("rcut_smth", C.c_double), ("emb", C.c_int32 * 3), ("axis", C.c_int32),
-                ("fit", C.c_int32 * 3), ("type_one_side", C.c_int32)]
+                ("fit", C.c_int32 * 3), ("type_one_side", C.c_int32), ("descriptor", C.c_int32)]
+
+DESCRIPTORS = {"se_e2_a": 0, "se_e2_r": 1, "se_e3": 2}
 
 
 class _Stats(C.Structure):
@@ -109,6 +111,7 @@ def make_desc(model: dict) -> _Desc:
         d.fit[k] = model["fit"][k]
     d.axis = model["axis"]
     d.type_one_side = int(model["type_one_side"])
+    d.descriptor = DESCRIPTORS[model.get("descriptor", "se_e2_a")]
     return d
 
 
@@ -118,12 +121,15 @@ def param_count(model: dict) -> int:
 
 
 def _desc_dict(d: _Desc) -> dict:
-    return dict(ntypes=d.ntypes, sel=[d.sel[t] for t in range(d.ntypes)], rcut=d.rcut, rcut_smth=d.rcut_smth,
-                emb=list(d.emb), axis=d.axis, fit=list(d.fit), type_one_side=bool(d.type_one_side))
+    out = dict(ntypes=d.ntypes, sel=[d.sel[t] for t in range(d.ntypes)], rcut=d.rcut, rcut_smth=d.rcut_smth,
+               emb=list(d.emb), axis=d.axis, fit=list(d.fit), type_one_side=bool(d.type_one_side))
+    if d.descriptor:
+        out["descriptor"] = {v: k for k, v in DESCRIPTORS.items()}[d.descriptor]
+    return out
 
 
 class Model:
-    """An immutable se_e2_a model (description + FP64 parameter blob)."""
+    """An immutable model (description + FP64 parameter blob) of one of the descriptor kinds."""
 
     def __init__(self, model: dict, params: np.ndarray, _handle=None):
         if _handle is None:

@@ -27,6 +27,8 @@ def _header(path):
     (synth.WATER_MODEL, synth.water_params, None),
     (synth.FCC_MODEL, synth.fcc_params, (0.01, 0.5)),
     (dict(synth.SERVE_MODEL, type_one_side=True), None, None),
+    (synth.WATER_R_MODEL, synth.water_r_params, (0.005, 2.0)),
+    (synth.WATER_E3_MODEL, synth.water_e3_params, (0.01, 8.0)),
 ])
 def test_round_trip(tmp_path, spec, params, table):
     p = params() if params else synth.make_params(spec, 9, timestep_sigma=0.1)
