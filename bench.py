@@ -321,6 +321,57 @@ def large_bench(dpk, synth, torch, precisions, median_of=10):
     return out
 
 
+# Work per unit of the other DeepPot-SE descriptors (forward and input gradient):
+#   se_e2_r, per neighbour: the embedding net 12,550 flop each way; contraction D_m += s G_m 200,
+#     dE/dG . s and G . dD 400; environment row and chain rule 50; fitting per atom
+#     2 x 2 (100*240 + 2*240^2 + 240) = 557,760 flop.
+#   se_e3, per ordered neighbour pair (j, k), j = k included: theta 7 flop, the net 12,550 each way,
+#     D_m += theta G_m 200, dE/dtheta 400, the two row gradients 16; per neighbour the chain rule
+#     50; the same fitting as se_e2_r.
+FIT_ATOM_M = 557760.0
+E3_PAIR_FWD, E3_PAIR_BWD = NET_PAIR + 207.0, NET_PAIR + 416.0
+R_PAIR_FWD, R_PAIR_BWD = NET_PAIR + 250.0, NET_PAIR + 450.0
+
+
+def descriptor_bench(dpk, synth, torch, steps, warmup, precisions):
+    """se_e2_r (rc 6.0 A, sel [46, 92]) and se_e3 (rc 4.0 A, sel [20, 40]) on the 12,288-atom water
+    box: ms/step, atom-steps/s, stage times, and the embedding and fitting stages against the
+    matrix peak of their precision (work per launch from the counts above: neighbours for se_e2_r,
+    ordered neighbour pairs for se_e3). Parity at this size is tested (test_gpu_descriptors.py)."""
+    c, t, b = synth.water_12288()
+    n = len(t)
+    out = {}
+    for name, spec, params in (("se_e2_r", synth.WATER_R_MODEL, synth.water_r_params),
+                               ("se_e3", synth.WATER_E3_MODEL, synth.water_e3_params)):
+        model = dpk.Model(spec, params())
+        res = {"workload": f"water-like box, 12,288 atoms; {name} rc {spec['rcut']} A, sel {spec['sel']}, "
+                           "embedding (25,50,100), fitting (240,240,240,1)", "atoms": n}
+        units = None
+        for prec in precisions:
+            r, ctx = time_frame(dpk, torch, model, prec, c, t, b, steps, warmup)
+            if units is None:
+                kept = (ctx.debug_nlist(n) >= 0).sum(axis=1).astype(np.int64)
+                units = int(kept.sum()) if name == "se_e2_r" else int((kept ** 2).sum())
+                res["neighbours" if name == "se_e2_r" else "neighbour_pairs_jk"] = units
+                res["neighbours_total"] = int(kept.sum())
+            ctx.close()
+            fw, bw = (R_PAIR_FWD, R_PAIR_BWD) if name == "se_e2_r" else (E3_PAIR_FWD, E3_PAIR_BWD)
+            chain = 0.0 if name == "se_e2_r" else ENV_PAIR * res["neighbours_total"]
+            work = {"embed_fwd": fw * units, "fit": FIT_ATOM_M * n, "embed_bwd": bw * units + chain}
+            roof = {}
+            for st, w in work.items():
+                ach = w / 1e12 / (r["stage_ms"][st] * 1e-3)
+                pk = matrix_peak(prec)
+                roof[st] = {"bound": "mfma", "achieved": ach, "peak": pk, "unit": "TFLOP/s", "frac": ach / pk,
+                            "ms": r["stage_ms"][st]}
+            res[prec] = dict(public(r), stage_roofline=roof)
+            print(f"# {name} water12288 {prec}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4g} atom-steps/s, "
+                  "stages (ms) " + ", ".join(f"{k} {v:.3f}" for k, v in r["stage_ms"].items()),
+                  file=sys.stderr, flush=True)
+        out[name] = res
+    return out
+
+
 def host_cpu():
     model = None
     try:
@@ -375,6 +426,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (latency) section")
     ap.add_argument("--no-table", action="store_true", help="skip the tabulated-embedding (fcc) section")
     ap.add_argument("--no-large", action="store_true", help="skip the 110,592-atom water box")
+    ap.add_argument("--no-descriptors", action="store_true", help="skip the se_e2_r / se_e3 section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device-to-device (the reference for hardware byte counters)")
     args = ap.parse_args()
@@ -420,6 +472,8 @@ def main():
     large = None if args.no_large else large_bench(dpk, synth, torch, ("fp64", "mixed"))
     tabulated = None if args.no_table else tabulated_bench(dpk, synth, torch, max(1, args.steps // 2),
                                                             max(1, args.warmup // 2), TABLE_PRECISIONS)
+    descriptors = None if args.no_descriptors else descriptor_bench(dpk, synth, torch, max(1, args.steps // 2),
+                                                                    max(1, args.warmup // 2), ("fp64", "mixed", "fp32"))
     serving = None if args.no_serving else serving_bench(dpk, synth)
     if serving:
         print(f"# serving: p50 {serving['p50_ms']:.3f} ms, p99 {serving['p99_ms']:.3f} ms at "
@@ -486,6 +540,7 @@ def main():
         "stage_roofline": stage_roof,
         "large_frame": large,
         "tabulated": tabulated,
+        "descriptors": descriptors,
         "serving": serving,
     }
     line.update(others)
