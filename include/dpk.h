@@ -408,6 +408,58 @@ int dpk_admit_plan(int nslots, const int32_t *busy, const int64_t *slot_bytes,
                    int64_t budget_bytes, int64_t model_bytes, int32_t *slot,
                    int32_t *release_idle);
 
+/* ------------------------------------------------------------------------------------------
+ * Training (Sec. II.B, "Trainer"): the loss of eq. loss for one frame and its gradient with
+ * respect to every model parameter, in FP64 on the device, including the force and virial terms
+ * (derivatives of the forces with respect to the parameters: second derivatives of E). The
+ * learning-rate schedule (eq. learning_rate), the prefactor schedule p(tau) and Adam steps on a
+ * device copy of the parameters. se_e2_a models.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct dpk_trainer dpk_trainer;
+
+/* Labels and prefactors of one frame's loss, L = p_e L_E + p_f L_F + p_v L_Xi with
+ * L_E = (E - E*)^2 / N, L_F = sum_k q_k |F_k - F*_k|^2 / (3N), L_Xi = sum_ab (Xi - Xi*)_ab^2 / (9N)
+ * (eq. loss and the per-atom prefactor form L_F^p; q_k = 1/|F*_k|^2 gives the relative form L_F^r).
+ * A NULL label leaves its term out; every pointer is read during the call only. */
+typedef struct {
+    const double *energy;      /* E*, one value, or NULL                                   */
+    const double *force;       /* F* [natoms][3] (caller order), or NULL                   */
+    const double *virial;      /* Xi* [9], or NULL                                         */
+    const double *atom_pref;   /* q_k [natoms], or NULL (all 1)                            */
+    double pe, pf, pv;         /* prefactors p_E, p_F, p_Xi                                */
+} dpk_loss_spec;
+
+/* Copy the model's parameters to `device` (FP64) with zero gradient and Adam moments. The model
+ * is copied; the caller may free it afterwards. DPK_E_UNIMPLEMENTED for se_e2_r and se_e3 models,
+ * DPK_E_INVALID_ARG for NULL pointers, DPK_E_DEVICE / DPK_E_OOM on device failures. */
+int dpk_trainer_create(const dpk_model *m, int device, dpk_trainer **out);
+void dpk_trainer_free(dpk_trainer *t);
+
+/* One frame (host buffers, caller order; box as dpk_compute): evaluate E, F and Xi with the
+ * current parameters, the loss (loss[4] = {L, L_E, L_F, L_Xi}, the terms unweighted), and add
+ * weight * dL/dtheta to the trainer's gradient (weight = 1/B averages a mini-batch of B frames,
+ * eq. loss). energy/force/virial receive the prediction if not NULL. The gradient stays on the
+ * device. Errors as dpk_compute. */
+int dpk_trainer_accumulate(dpk_trainer *t, int64_t natoms, const double *coord, const int32_t *atype,
+                           const double *box, const dpk_loss_spec *spec, double weight, double *loss,
+                           double *energy, double *force, double *virial);
+
+/* Host copy of the accumulated gradient (dpk_model_param_count values, blob layout). */
+int dpk_trainer_gradient(dpk_trainer *t, double *grad);
+/* Clear the accumulated gradient. */
+int dpk_trainer_zero_grad(dpk_trainer *t);
+/* One Adam step (Kingma and Ba) with the accumulated gradient and learning rate lr (moments
+ * beta1, beta2, eps; bias corrections from the trainer's step count), then clear the gradient. */
+int dpk_trainer_adam_step(dpk_trainer *t, double lr, double beta1, double beta2, double eps);
+/* Host copy of the current parameters (blob layout), or replace them (moments and step kept). */
+int dpk_trainer_params(dpk_trainer *t, double *params);
+int dpk_trainer_set_params(dpk_trainer *t, const double *params);
+
+/* eq. learning_rate: lr0 * r^floor(step / decay_steps), r = (lr_stop / lr0)^(decay_steps / stop_steps). */
+double dpk_learning_rate(double lr0, double lr_stop, int64_t step, int64_t stop_steps, int64_t decay_steps);
+/* The prefactor schedule p = p_limit (1 - lr / lr0) + p_start lr / lr0. */
+double dpk_loss_prefactor(double p_start, double p_limit, double lr, double lr0);
+
 #ifdef __cplusplus
 }
 #endif

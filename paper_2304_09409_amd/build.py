@@ -27,6 +27,8 @@ SOURCES = {
     "kernels_fit.hip": [],
     "api.cpp": ["-ffp-contract=off"],
     "model_file.cpp": [],
+    "kernels_train.hip": [],
+    "trainer.cpp": [],
 }
 
 

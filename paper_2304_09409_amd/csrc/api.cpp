@@ -25,6 +25,7 @@
 #include "../../include/dpk.h"
 #include "dpk_internal.h"
 #include "dpk_launch.h"
+#include "dpk_train.h"
 
 using namespace dpk;
 
@@ -717,13 +718,11 @@ void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* F, double* vir
 // The launches of one frame on the views laid out for it. shared: the views point into the
 // device's shared scratch, which keeps whatever the last call left, so the bin counts are cleared
 // every time, and no profiler event is recorded.
-void enqueue_frame(dpk_ctx* c, int n, const double* d_coord, const int* d_atype, const GeomParams& gp,
-                   double* d_energy, double* d_force, double* d_virial, double* d_atom_energy, hipStream_t s,
-                   bool shared)
+// Preparation (partition, wrap, bin; d_force zeroed) and neighbour search of one frame.
+void enqueue_geometry(dpk_ctx* c, int n, const double* d_coord, const int* d_atype, const GeomParams& gp,
+                      double* d_force, hipStream_t s, bool shared, std::vector<hipEvent_t>* ev)
 {
     const int nt = c->model->desc.ntypes;
-    // the forces accumulate straight into d_force (caller order), which the preparation zeroes
-    std::vector<hipEvent_t>* ev = shared ? nullptr : prof_frame(c);
     prof_mark(ev, DPK_STAGE_PREP, s);
     if (!launch_prep_small(n, d_coord, d_atype, nt, gp, c->tcount, c->toff, c->perm, c->inv_perm, c->itype, c->stats,
                            c->pos, c->cell_of, c->cell_start, c->cand, d_force, s)) {
@@ -741,6 +740,15 @@ void enqueue_frame(dpk_ctx* c, int n, const double* d_coord, const int* d_atype,
     prof_mark(ev, DPK_STAGE_NLIST, s);
     launch_nlist(n, c->pos, c->perm, c->inv_perm, c->cell_of, c->cell_start, c->cand, gp, c->nl_j, c->nl_r, c->nnei,
                  c->stats, s);
+}
+
+void enqueue_frame(dpk_ctx* c, int n, const double* d_coord, const int* d_atype, const GeomParams& gp,
+                   double* d_energy, double* d_force, double* d_virial, double* d_atom_energy, hipStream_t s,
+                   bool shared)
+{
+    // the forces accumulate straight into d_force (caller order), which the preparation zeroes
+    std::vector<hipEvent_t>* ev = shared ? nullptr : prof_frame(c);
+    enqueue_geometry(c, n, d_coord, d_atype, gp, d_force, s, shared, ev);
     run_network(c, n, gp, d_force, nullptr, true, d_atom_energy, ev, s);
     prof_mark(ev, DPK_STAGE_FINAL, s);
     launch_finalize(embed_bwd_blocks(c->precision, c->tab, n, c->ncu, is_e3(c)), c->vir_part, d_energy, d_virial,
@@ -2312,3 +2320,60 @@ void dpk_server_free(dpk_server* s)
 }
 
 }  // extern "C"
+
+// Geometry of one host frame for the training path (Sec. II.B needs the same neighbour list as
+// inference): partition, bin and search, with the same candidate-buffer retry as dpk_compute.
+int dpk::frame_geometry(dpk_ctx* c, int64_t natoms, const double* coord, const int32_t* atype, const double* box,
+                        FrameGeom* g)
+{
+    if (!c || !coord || !atype || !g) return fail(DPK_E_INVALID_ARG, "NULL argument");
+    if (natoms < 1 || natoms > (1LL << 30)) return fail(DPK_E_INVALID_ARG, "natoms = %lld", (long long)natoms);
+    HIPCHK(hipSetDevice(c->device));
+    const int n = (int)natoms;
+    hipStream_t s = c->stream;
+    int rc = DPK_OK;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        GeomParams gp;
+        c->cur_natoms = natoms;
+        if (box) {
+            rc = setup_geometry(c, box, nullptr, gp);
+        } else {
+            double bb[6] = {1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+            for (int64_t i = 0; i < natoms; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    bb[k] = std::min(bb[k], coord[3 * i + k]);
+                    bb[3 + k] = std::max(bb[3 + k], coord[3 * i + k]);
+                }
+            rc = setup_geometry(c, nullptr, bb, gp);
+        }
+        if (rc) break;
+        if ((rc = ensure_ws(c, natoms, (int64_t)gp.nb[0] * gp.nb[1] * gp.nb[2]))) break;
+        HIPCHK(hipMemcpyAsync(c->h_coord, coord, sizeof(double) * 3 * natoms, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(c->h_atype, atype, sizeof(int) * natoms, hipMemcpyHostToDevice, s));
+        enqueue_geometry(c, n, c->h_coord, c->h_atype, gp, c->F, s, false, nullptr);
+        HIPCHK(hipGetLastError());
+        c->last_stream = s;
+        c->last_n = n;
+        c->last_centres = n;
+        rc = dpk_ctx_check(c);
+        if (rc == DPK_E_NBR_OVERFLOW && !c->force_big_cap && !c->strict) {
+            c->force_big_cap = true;   // a locally dense frame: once more with the largest buffer
+            continue;
+        }
+        if (rc == DPK_OK) {
+            g->n = n;
+            g->nc = c->model->nc;
+            g->nt = c->model->desc.ntypes;
+            for (int t = 0; t < MAXT; ++t) g->off[t] = gp.off[t];
+            g->itype = c->itype;
+            g->nnei = c->nnei;
+            g->nl_j = c->nl_j;
+            g->nl_r = c->nl_r;
+            g->perm = c->perm;
+            g->stream = s;
+        }
+        break;
+    }
+    c->force_big_cap = false;
+    return rc;
+}

@@ -317,6 +317,112 @@ class _DeviStats(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("f_max", "f_avg", "f_min", "v_max", "v_avg", "v_min")]
 
 
+class _LossSpec(C.Structure):
+    _fields_ = [("energy", C.POINTER(C.c_double)), ("force", C.POINTER(C.c_double)),
+                ("virial", C.POINTER(C.c_double)), ("atom_pref", C.POINTER(C.c_double)),
+                ("pe", C.c_double), ("pf", C.c_double), ("pv", C.c_double)]
+
+
+def _train_sigs(L):
+    if getattr(L, "_train_sigs", False):
+        return
+    vp, dp = C.c_void_p, C.POINTER(C.c_double)
+    L.dpk_trainer_create.argtypes = [vp, C.c_int, C.POINTER(vp)]
+    L.dpk_trainer_free.argtypes = [vp]
+    L.dpk_trainer_free.restype = None
+    L.dpk_trainer_accumulate.argtypes = [vp, C.c_int64, dp, C.POINTER(C.c_int32), dp, C.POINTER(_LossSpec),
+                                         C.c_double, dp, dp, dp, dp]
+    for f in ("dpk_trainer_gradient", "dpk_trainer_params"):
+        getattr(L, f).argtypes = [vp, dp]
+    L.dpk_trainer_set_params.argtypes = [vp, dp]
+    L.dpk_trainer_zero_grad.argtypes = [vp]
+    L.dpk_trainer_adam_step.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
+    L.dpk_learning_rate.argtypes = [C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_int64]
+    L.dpk_learning_rate.restype = C.c_double
+    L.dpk_loss_prefactor.argtypes = [C.c_double] * 4
+    L.dpk_loss_prefactor.restype = C.c_double
+    L._train_sigs = True
+
+
+def learning_rate(lr0: float, lr_stop: float, step: int, stop_steps: int, decay_steps: int) -> float:
+    L = lib()
+    _train_sigs(L)
+    return L.dpk_learning_rate(lr0, lr_stop, step, stop_steps, decay_steps)
+
+
+def loss_prefactor(p_start: float, p_limit: float, lr: float, lr0: float) -> float:
+    L = lib()
+    _train_sigs(L)
+    return L.dpk_loss_prefactor(p_start, p_limit, lr, lr0)
+
+
+class Trainer:
+    """Loss and parameter gradient of frames, Adam steps (dpk_trainer_*), FP64 on one device."""
+
+    def __init__(self, model: Model, device: int = 0):
+        L = lib()
+        _train_sigs(L)
+        h = C.c_void_p()
+        _check(L.dpk_trainer_create(model.handle, device, C.byref(h)))
+        self.handle = h
+        self.nparams = param_count(model.describe()[0])
+
+    def accumulate(self, coord, atype, box=None, energy=None, force=None, virial=None, pe=0.0, pf=0.0, pv=0.0,
+                   atom_pref=None, weight: float = 1.0) -> dict:
+        """One frame: its prediction and loss; weight * dL/dtheta is added to the gradient."""
+        coord = np.ascontiguousarray(coord, dtype=np.float64)
+        atype = np.ascontiguousarray(atype, dtype=np.int32)
+        n = coord.shape[0]
+        box = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(9)
+        keep = []
+
+        def arr(x, shape=None):
+            if x is None:
+                return None
+            a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(shape) if shape else
+                                     np.asarray(x, dtype=np.float64))
+            keep.append(a)
+            return _dp(a)
+
+        spec = _LossSpec(arr(None if energy is None else [energy]), arr(force, (n, 3)), arr(virial, (9,)),
+                         arr(atom_pref, (n,)), float(pe), float(pf), float(pv))
+        loss, e = np.empty(4), C.c_double()
+        f, v = np.empty((n, 3)), np.empty(9)
+        _check(lib().dpk_trainer_accumulate(self.handle, n, _dp(coord), _ip(atype), _dp(box), C.byref(spec),
+                                            float(weight), _dp(loss), C.byref(e), _dp(f), _dp(v)))
+        return {"loss": loss[0], "L_E": loss[1], "L_F": loss[2], "L_Xi": loss[3], "energy": e.value, "force": f,
+                "virial": v.reshape(3, 3)}
+
+    def gradient(self) -> np.ndarray:
+        g = np.empty(self.nparams)
+        _check(lib().dpk_trainer_gradient(self.handle, _dp(g)))
+        return g
+
+    def zero_grad(self):
+        _check(lib().dpk_trainer_zero_grad(self.handle))
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        _check(lib().dpk_trainer_adam_step(self.handle, lr, beta1, beta2, eps))
+
+    def params(self) -> np.ndarray:
+        p = np.empty(self.nparams)
+        _check(lib().dpk_trainer_params(self.handle, _dp(p)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        assert p.size == self.nparams
+        _check(lib().dpk_trainer_set_params(self.handle, _dp(p)))
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.dpk_trainer_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
 class Deviation:
     """An ensemble of models of one description on one device (dpk_devi_*)."""
 
