@@ -372,6 +372,61 @@ def descriptor_bench(dpk, synth, torch, steps, warmup, precisions):
     return out
 
 
+# Training step (Sec. II.B) per frame, FP64: inference (embedding with its unit tangent 2 x 12,550
+# flop per pair, pair forces 1,600; fitting forward and input gradient 2 x 998,400 per atom), the
+# training pass (fitting forward with tangent 2 x 998,400, reverse of values and tangents
+# 2 x 998,400, weight gradients 2 x 998,400 per atom; embedding reverse 2 x 12,550 and weight
+# gradients 2 x 12,550 per pair; contraction with tangent about 3,200 per pair).
+TRAIN_PAIR = 4 * NET_PAIR + 2 * NET_PAIR + 1600.0 + 3200.0
+TRAIN_ATOM = 8 * 998400.0
+
+
+def training_bench(dpk, synth, steps):
+    """One training step on the 12,288-atom water box: the frame's loss and full parameter gradient
+    (energy, force and virial terms) through dpk_trainer_accumulate, then an Adam step; the time of
+    the whole step (host copies and the host-side pair list included), against the FP64 peak."""
+    c, t, b = synth.water_12288()
+    n = len(t)
+    # synthetic labels: a perturbed model's prediction (outside the timed loop)
+    params = synth.water_params()
+    p2 = synth.ensemble_params(synth.WATER_MODEL, params, 2, rel=0.05, seed=5)[1]
+    lctx = dpk.Context(dpk.Model(synth.WATER_MODEL, p2), precision="fp64")
+    ref = lctx.compute(c, t, b)
+    lctx.close()
+    tr = dpk.Trainer(dpk.Model(synth.WATER_MODEL, params))
+    kw = dict(energy=ref["energy"], force=ref["force"], virial=ref["virial"], pe=0.02, pf=1000.0, pv=0.02)
+    r = tr.accumulate(c, t, b, **kw)
+    tr.adam_step(1e-3)
+    ts = time.perf_counter()
+    losses = []
+    for _ in range(steps):
+        r = tr.accumulate(c, t, b, **kw)
+        tr.adam_step(1e-3)
+        losses.append(r["loss"])
+    ms = (time.perf_counter() - ts) * 1e3 / steps
+    tr.close()
+    npairs = None
+    try:
+        m = dpk.Model(synth.WATER_MODEL, params)
+        ctx = dpk.Context(m, precision="fp64")
+        ctx.compute(c, t, b)
+        npairs = int((ctx.debug_nlist(n) >= 0).sum())
+        ctx.close()
+    except Exception:
+        pass
+    work = (TRAIN_PAIR * npairs + TRAIN_ATOM * n) / 1e12 if npairs else None
+    out = {"workload": "water-like box, 12,288 atoms, water model; loss with energy, force and virial terms; "
+                       "FP64 gradient of every parameter + Adam step",
+           "atoms": n, "neighbour_pairs": npairs, "ms_per_step": ms, "frames_per_s": 1e3 / ms,
+           "loss_first_last": [losses[0], losses[-1]]}
+    if work:
+        out["roofline"] = {"bound": "fp64", "achieved": work / (ms * 1e-3), "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                           "frac": work / (ms * 1e-3) / PEAK["fp64"]}
+    print(f"# training water12288: {ms:.2f} ms/step, loss {losses[0]:.4g} -> {losses[-1]:.4g}", file=sys.stderr,
+          flush=True)
+    return out
+
+
 def host_cpu():
     model = None
     try:
@@ -427,6 +482,7 @@ def main():
     ap.add_argument("--no-table", action="store_true", help="skip the tabulated-embedding (fcc) section")
     ap.add_argument("--no-large", action="store_true", help="skip the 110,592-atom water box")
     ap.add_argument("--no-descriptors", action="store_true", help="skip the se_e2_r / se_e3 section")
+    ap.add_argument("--no-train", action="store_true", help="skip the training-step section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device-to-device (the reference for hardware byte counters)")
     args = ap.parse_args()
@@ -474,6 +530,7 @@ def main():
                                                             max(1, args.warmup // 2), TABLE_PRECISIONS)
     descriptors = None if args.no_descriptors else descriptor_bench(dpk, synth, torch, max(1, args.steps // 2),
                                                                     max(1, args.warmup // 2), ("fp64", "mixed", "fp32"))
+    training = None if args.no_train else training_bench(dpk, synth, max(2, args.steps // 4))
     serving = None if args.no_serving else serving_bench(dpk, synth)
     if serving:
         print(f"# serving: p50 {serving['p50_ms']:.3f} ms, p99 {serving['p99_ms']:.3f} ms at "
@@ -541,6 +598,7 @@ def main():
         "large_frame": large,
         "tabulated": tabulated,
         "descriptors": descriptors,
+        "training": training,
         "serving": serving,
     }
     line.update(others)
