@@ -489,8 +489,10 @@ struct ChunkWalk {
 // embedding net are the ordered pairs (j, k) of an atom's kept neighbours, with input
 // theta_jk = R_j . R_k. A pass takes one net (a_j, a_k) and walks the pairs of the neighbour-type
 // blocks a_j x a_k of each atom: pair p is (slot off[a_j] + p / n_k, slot off[a_k] + p % n_k), n_k
-// the atom's kept count of type a_k. The two environment rows are loaded one item ahead (they come
-// from the per-frame env buffer, k_e3_env). The pass index q encodes (a_j, a_k) = (q / nt, q % nt).
+// the atom's kept count of type a_k. Within one type block (a_j = a_k) the pairs (j, k) and (k, j)
+// have the same theta and the same net, so that pass walks k <= j only (p = j (j + 1) / 2 + k) and
+// weighs j != k twice. The two environment rows are loaded one item ahead (they come from the
+// per-frame env buffer, k_e3_env). The pass index q encodes (a_j, a_k) = (q / nt, q % nt).
 template <class P>
 struct PairWalk {
     typedef typename P::acc acc;
@@ -499,6 +501,7 @@ struct PairWalk {
     bool have;
     accv ra, rb;   // environment rows of the item's pair (prefetched)
     int sa, sb;    // their slots
+    acc wgt;       // 1, or 2 for an off-diagonal pair of one type block
     template <bool J = false>
     __device__ __forceinline__ bool find_atom(const EmbArgs& A, const int*, int a0, int a1, int wave, int nw, int apw,
                                               int ti, int q, bool skip_empty) {
@@ -508,7 +511,7 @@ struct PairWalk {
             if (a >= a1) return false;
             if (A.itype[a] != ti) continue;
             nb = A.nnei[(size_t)a * nt + tb];
-            np = A.nnei[(size_t)a * nt + ta] * nb;
+            np = ta == tb ? nb * (nb + 1) / 2 : A.nnei[(size_t)a * nt + ta] * nb;
             if (skip_empty && np == 0) continue;
             if (J) ac = A.perm[a];
             return true;
@@ -522,10 +525,21 @@ struct PairWalk {
     __device__ __forceinline__ void fetch(const EmbArgs& A, int q, int c16) {
         const int nt = A.ntypes, ta = q / nt, tb = q - ta * nt;
         int ia = 0, ib = 0;
+        wgt = 1;
         if (have && np > 0) {
             const int p = min(c0 + c16, np - 1);
-            ia = p / nb;
-            ib = p - ia * nb;
+            if (ta == tb) {
+                // p = j (j + 1) / 2 + k with k <= j
+                int j = (int)((sqrtf(8.0f * p + 1.0f) - 1.0f) * 0.5f);
+                j -= j * (j + 1) / 2 > p;
+                j += (j + 1) * (j + 2) / 2 <= p;
+                ia = j;
+                ib = p - j * (j + 1) / 2;
+                wgt = ia == ib ? (acc)1 : (acc)2;
+            } else {
+                ia = p / nb;
+                ib = p - ia * nb;
+            }
         }
         sa = min(A.off[ta] + ia, A.nc - 1);   // (a type with sel 0 starts at nc)
         sb = min(A.off[tb] + ib, A.nc - 1);
@@ -627,9 +641,10 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
             accv Tacc[7];
             while (w.have) {
                 double x = 0.0, y = 0.0, z = 0.0;
-                acc th = 0;
+                acc th = 0, wt = 1;
                 if constexpr (E3) {
                     th = w.ra[0] * w.rb[0] + w.ra[1] * w.rb[1] + w.ra[2] * w.rb[2] + w.ra[3] * w.rb[3];
+                    wt = w.wgt;
                 } else {
                     x = w.px; y = w.py; z = w.pz;
                 }
@@ -652,7 +667,7 @@ __global__ void __launch_bounds__((EmbCfg<P, true, TAB>::NW * 64)) k_embed_fwd(E
                 if (valid) {
                     if constexpr (E3) {
                         s = (double)th;
-                        R[0] = s;
+                        R[0] = (double)(wt * th);   // the pair and its mirror image
                     } else {
                         const double r = sqrt(x * x + y * y + z * z);
                         const double ir = 1.0 / r;
@@ -903,10 +918,11 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
             while (w.have) {
                 double x = 0.0, y = 0.0, z = 0.0;
                 int jn = 0;
-                accv ra, rb;   // three-body: the pair's rows and slots
+                accv ra, rb;   // three-body: the pair's rows, slots and weight
                 int sa = 0, sb = 0;
+                acc wt = 1;
                 if constexpr (E3) {
-                    ra = w.ra; rb = w.rb; sa = w.sa; sb = w.sb;
+                    ra = w.ra; rb = w.rb; sa = w.sa; sb = w.sb; wt = w.wgt;
                 } else {
                     x = w.px; y = w.py; z = w.pz;
                     jn = w.pj;
@@ -1085,13 +1101,14 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                 // column sums over the lane groups (they hold different rows m): dR component ksel(g)
                 // in lane group g, gathered into group 0; sum_k H_k R_k as one value
                 const double ux = x * ir, uy = y * ir, uz = z * ir, sr = s * ir;
-                const acc Ra[4] = {(acc)s, (acc)(sr * x), (acc)(sr * y), (acc)(sr * z)};
+                const acc Ra[4] = {E3 ? (acc)(wt * (acc)s) : (acc)s, (acc)(sr * x), (acc)(sr * y), (acc)(sr * z)};
                 const acc dRg = sum_groups4(dR);
                 const acc hR = sum_groups(H[0] * Ra[0] + H[1] * Ra[1] + H[2] * Ra[2] + H[3] * Ra[3]);
                 if constexpr (E3) {
-                    // dE/dtheta (lane group 0 holds component 0 of dR), to every group; group g adds
-                    // component g of both rows' gradients
-                    const acc de = __shfl((acc)A.inv_nc * (dRg + hR), c16);
+                    // dE/dtheta of the row (weight w: the pair and its mirror image; lane group 0
+                    // holds component 0 of dR), to every group; group g adds component g of both
+                    // rows' gradients
+                    const acc de = __shfl((acc)A.inv_nc * (wt * dRg + hR), c16);
                     w.pin();
                     if (valid) {
                         const acc rag = g == 0 ? ra[0] : g == 1 ? ra[1] : g == 2 ? ra[2] : ra[3];
