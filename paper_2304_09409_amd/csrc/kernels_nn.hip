@@ -1256,7 +1256,7 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
 // exactly one lane's A fragment, and rows are padded by 16 B so the 16 rows a wave reads at once
 // fall in distinct banks. Global reads are 16-B pieces, issued into registers by load() one stage
 // ahead and written to LDS by store() after the MFMAs of the current stage.
-template <class P, int ROWS, int KC>
+template <class P, int ROWS, int KC, int NT = 256>
 struct FitStage {
     typedef typename P::wt wt;
     static constexpr int GB = 4 * sizeof(wt) * P::NPL;       // bytes per group in LDS
@@ -1265,15 +1265,15 @@ struct FitStage {
     static constexpr int EPP = 16 / sizeof(wt);               // elements per 16-B piece
     static constexpr int PPR = KC / EPP;                      // pieces per row and plane
     static constexpr int TOTAL = ROWS * PPR * P::NPL;
-    static constexpr int NP = (TOTAL + 255) / 256;
+    static constexpr int NP = (TOTAL + NT - 1) / NT;          // pieces per thread (NT threads)
     u32x4 r[NP];
 
     // Only the first nrows <= ROWS source rows are read; staged rows past them repeat the last one.
     __device__ __forceinline__ void load(const wt* src, int64_t ld, int64_t plane, int k0, int nrows = ROWS) {
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const int q = threadIdx.x + 256 * p;
-            if (TOTAL % 256 == 0 || q < TOTAL) {
+            const int q = threadIdx.x + NT * p;
+            if (TOTAL % NT == 0 || q < TOTAL) {
                 const int pl = q / (ROWS * PPR), rem = q - pl * ROWS * PPR;
                 const int row = rem / PPR, pc = rem - row * PPR;
                 const int rs = row < nrows ? row : nrows - 1;
@@ -1281,11 +1281,27 @@ struct FitStage {
             }
         }
     }
+    // Two row ranges in one stage: rows [0, ROWS/2) from the first n0 rows of src0 and rows
+    // [ROWS/2, ROWS) from the first n1 rows of src1 (n0, n1 >= 1; past them the last row repeats).
+    __device__ __forceinline__ void load2(const wt* src0, int n0, const wt* src1, int n1, int64_t ld, int k0) {
+        static_assert(P::NPL == 1, "one plane");
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int q = threadIdx.x + NT * p;
+            if (TOTAL % NT == 0 || q < TOTAL) {
+                const int row = q / PPR, pc = q - row * PPR;
+                const bool hi = row >= ROWS / 2;
+                const int lr = hi ? row - ROWS / 2 : row, n = hi ? n1 : n0;
+                const int rs = lr < n ? lr : n - 1;
+                r[p] = *reinterpret_cast<const u32x4*>((hi ? src1 : src0) + (int64_t)rs * ld + k0 + pc * EPP);
+            }
+        }
+    }
     __device__ __forceinline__ void store(char* dst) const {
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const int q = threadIdx.x + 256 * p;
-            if (TOTAL % 256 == 0 || q < TOTAL) {
+            const int q = threadIdx.x + NT * p;
+            if (TOTAL % NT == 0 || q < TOTAL) {
                 const int pl = q / (ROWS * PPR), rem = q - pl * ROWS * PPR;
                 const int row = rem / PPR, pc = rem - row * PPR;
                 char* rowp = dst + row * ROWB;
@@ -1338,8 +1354,12 @@ constexpr int F64_TP = 8;
 constexpr int FS_A1 = 0, FS_A2 = FW, FS_A3 = 2 * FW, FS_GA = 3 * FW, FS_GB = 4 * FW, FS_GH = 5 * FW, FS_ROW = 6 * FW;
 constexpr int RAD_K = N3P;   // padded width of a descriptor of M values
 
-template <class P, bool ENS, bool RAD>
-__global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
+// HALVES = 2: eight waves per block, two per atom tile; each layer's output tiles are split
+// between the two (the first ceil(n/2) tiles and the rest), and one LDS stage holds both halves'
+// weight rows. Every layer's input is read by both halves, so the scratch row is then shared between
+// two waves of the block (ordered by the barriers at the start of every product).
+template <class P, bool ENS, bool RAD, int HALVES>
+__global__ void __launch_bounds__(256 * HALVES) k_fit_dense(FitArgs A_)
 {
     const FitArgs A = ENS ? model_args(A_) : A_;
     typedef typename P::acc acc;
@@ -1347,11 +1367,15 @@ __global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
     typedef typename P::wt wt;
     typedef typename P::frag frag;
     typedef accv d4;   // four values of the element type (the lane's 4-row output or K group)
-    typedef FitStage<P, 16 * F64_TP, 16> SW;
+    // output tiles per pass: eight, or four in the two-half shape (two waves per SIMD: half the
+    // registers per wave)
+    constexpr int TP = HALVES == 2 ? 4 : F64_TP;
+    typedef FitStage<P, 16 * TP * HALVES, 16, 256 * HALVES> SW;
     __shared__ __attribute__((aligned(32))) char s_w[2][SW::BYTES];
     __shared__ acc s_p1[4][16][16][4];
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar registers)
+    const int aw = wave & 3, h = HALVES == 2 ? wave >> 2 : 0;           // atom tile, half
     const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     const int a0 = blockIdx.x * FIT_AF;
     const int a1 = min(a0 + FIT_AF, A.natoms);
@@ -1359,7 +1383,7 @@ __global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
     const int t_lo = A.itype[a0], t_hi = A.itype[a1 - 1];
     const acc* Tin = reinterpret_cast<const acc*>(A.T);
     acc* dTout = reinterpret_cast<acc*>(A.dT);
-    const int atom = a0 + 16 * wave + c16;
+    const int atom = a0 + 16 * aw + c16;
     const bool real = atom < A.natoms;
     const int arow = real ? atom : a0;
     const acc* Ta = Tin + (size_t)arow * E2 * 4;
@@ -1383,14 +1407,24 @@ __global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
         // memory read (32 B per lane) and make works on registers only; epi(t, out) receives
         // output tile t (rows 16t + orow(g, r)). Reads retire in issue order, so each chunk's
         // fetch is issued one chunk ahead and before the weight loads it would otherwise wait on.
+        // tiles of this wave: [tb, te) of ntiles (all of them, or its half)
+        auto tiles_of = [&](int ntiles, int& tb, int& te) {
+            const int hs = HALVES == 2 ? (ntiles + 1) / 2 : ntiles;
+            tb = h * hs;
+            te = min(ntiles, tb + hs);
+        };
         auto gemm = [&](int64_t mo, int K, int ntiles, auto&& fetch, auto&& make, auto&& epi) {
             const int nchunk = K / 16;
+            const int hs = HALVES == 2 ? (ntiles + 1) / 2 : ntiles;   // tiles of the first half
+            int tb, te;
+            tiles_of(ntiles, tb, te);
 #pragma unroll 1
-            for (int t0 = 0; t0 < ntiles; t0 += F64_TP) {
-                const int nt = min(F64_TP, ntiles - t0);
-                accv accs[F64_TP];
+            for (int t0 = 0; t0 < hs; t0 += TP) {
+                const int nt = min(TP, te - tb - t0);   // this wave's tiles in the pass (may be <= 0)
+                const int n0 = min(TP, hs - t0), n1 = max(1, min(TP, ntiles - hs - t0));
+                accv accs[TP];
 #pragma unroll
-                for (int t = 0; t < F64_TP; ++t) zero4(accs[t]);
+                for (int t = 0; t < TP; ++t) zero4(accs[t]);
                 // Weight chunks are fetched two ahead (two register stages in flight, alternated by
                 // unrolling the chunk loop twice) and staged through two LDS buffers: chunk c + 1
                 // goes to LDS after chunk c's products, into the buffer the previous barrier freed.
@@ -1398,23 +1432,29 @@ __global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
                 // the compiler's in-order wait counts stay exact instead of draining all reads.
                 SW st0, st1;
                 const wt* src = fm + mo + (int64_t)16 * t0 * K;
+                const wt* src1 = fm + mo + (int64_t)16 * (hs + t0) * K;
+                auto ld = [&](SW& st, int k0) {
+                    if constexpr (HALVES == 2) st.load2(src, 16 * n0, src1, 16 * n1, K, k0);
+                    else st.load(src, K, 0, k0, 16 * n0);
+                };
                 const int clast = nchunk - 1;
                 __syncthreads();
                 d4 x0 = fetch(0), x1 = {0, 0, 0, 0};
-                st0.load(src, K, 0, 0, 16 * nt);
+                ld(st0, 0);
                 st0.store(s_w[0]);
-                st1.load(src, K, 0, 16 * min(1, clast), 16 * nt);
+                ld(st1, 16 * min(1, clast));
                 __syncthreads();
                 // chunk c from LDS; `nxt` holds chunk c + 1 in flight, `fut` receives chunk c + 2;
                 // xc holds chunk c's fetch, xn receives chunk c + 1's
+                const int rb = 16 * TP * h;   // this half's first staged row
                 auto step = [&](int c, SW& nxt, SW& fut, const d4& xc, d4& xn) {
                     xn = fetch(min(c + 1, clast));
-                    fut.load(src, K, 0, 16 * min(c + 2, clast), 16 * nt);
+                    ld(fut, 16 * min(c + 2, clast));
                     const frag B = make(xc);
                     const char* buf = s_w[c & 1];
 #pragma unroll
-                    for (int t = 0; t < F64_TP; ++t)
-                        if (t < nt) P::mma(accs[t], fit_afrag<P, SW::ROWB>(buf, 16 * t + c16, g), B);
+                    for (int t = 0; t < TP; ++t)
+                        if (t < nt) P::mma(accs[t], fit_afrag<P, SW::ROWB>(buf, rb + 16 * t + c16, g), B);
                     nxt.store(s_w[(c + 1) & 1]);
                     __syncthreads();
                 };
@@ -1425,10 +1465,10 @@ __global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
                 }
                 if (nchunk & 1) step(clast, st1, st0, x0, x1);
 #pragma unroll
-                for (int t = 0; t < F64_TP; ++t)
+                for (int t = 0; t < TP; ++t)
                     if (t < nt) {
                         const acc o[4] = {accs[t][0], accs[t][1], accs[t][2], accs[t][3]};
-                        epi(t0 + t, o);
+                        epi(tb + t0 + t, o);
                     }
             }
         };
@@ -1439,9 +1479,11 @@ __global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
         // a = tanh(y + b) in place over the 15 tiles of a layer output (a loop, so that the
         // activation is inlined once rather than once per tile); side(t, a) forms the next
         // layer's input from it
+        int ab, ae;   // this wave's tiles of a 240-wide layer
+        tiles_of(15, ab, ae);
         auto activate = [&](int off, int boff, auto&& side) {
 #pragma unroll 1
-            for (int t = 0; t < 15; ++t) {
+            for (int t = ab; t < ae; ++t) {
                 const d4 y = rd4(off + 16 * t + 4 * g);
                 acc a[4];
 #pragma unroll
@@ -1495,7 +1537,8 @@ __global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
         gemm(FM_W3T, FW, 15, rdrow(FS_GH), asis, [&](int t, const acc* o) { wr4(FS_A3 + 16 * t + 4 * g, o); });
         activate(FS_A3, FV_B3, [](int, const acc*) {});
         // ---------------------------------------------------------- energy (Eq. 9) and ga3
-        {
+        if (HALVES == 2) __syncthreads();   // both halves' a3 in place
+        if (h == 0) {
             acc e = 0;
 #pragma unroll 1
             for (int t = 0; t < 15; ++t) {
@@ -1578,20 +1621,32 @@ __global__ void __launch_bounds__(256) k_fit_dense(FitArgs A_)
                  if (g == 0) {
                      if (m < 16) {
 #pragma unroll
-                         for (int k = 0; k < 4; ++k) s_p1[wave][c16][m][k] = part[k];
+                         for (int k = 0; k < 4; ++k) s_p1[aw][c16][m][k] = part[k];
                      } else if (mine) {
                          *reinterpret_cast<d4*>(dTout + ((size_t)atom * E2 + m) * 4) = d4{part[0], part[1], part[2], part[3]};
                      }
                  }
              });
         __syncthreads();
-        if (mine) {
+        // two halves: the second one's share of dT[n], n < 16, goes through LDS (the weight stages
+        // are free until the next product's first barrier)
+        acc* xq = reinterpret_cast<acc*>(&s_w[0][0]) + ((size_t)aw * 64 + lane) * 16;
+        if (HALVES == 2) {
+            if (h == 1)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) xq[4 * r + k] = q2[r][k];
+            __syncthreads();
+        }
+        if (h == 0 && mine) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int n = P::orow(g, r);
                 d4 o;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) o[k] = s_p1[wave][c16][n][k] + q2[r][k];
+                for (int k = 0; k < 4; ++k)
+                    o[k] = s_p1[aw][c16][n][k] + q2[r][k] + (HALVES == 2 ? xq[4 * r + k] : (acc)0);
                 *reinterpret_cast<d4*>(dTout + ((size_t)atom * E2 + n) * 4) = o;
             }
         }
@@ -1712,24 +1767,36 @@ void launch_e3_env(int precision, const EmbArgs& a, hipStream_t s)
 
 // The fitting net: FP64 and FP32 on the dense kernel, the BF16 paths on k_fitx; a descriptor of M
 // values (a.radial) always on the dense kernel (FP64, else FP32), whose first layer is then small.
-void launch_fit(int precision, const FitArgs& a, hipStream_t s)
+// Shape of the dense kernel: FP64 always in two halves (four 4-wave blocks run one wave per SIMD);
+// FP32 in two halves when the 64-atom blocks do not outnumber the CUs, else in the 4-wave shape,
+// whose blocks then share the CUs two at a time (measured: the 12,288-atom water box 0.424 -> 0.387
+// ms with halves, the 32,000-atom fcc box 0.730 -> 0.857 ms).
+template <class P, bool RAD, int HALVES>
+static void launch_dense_shape(const FitArgs& a, hipStream_t s)
 {
     const bool ens = a.nmodels > 1;
-    dim3 grid((a.natoms + FIT_AF - 1) / FIT_AF, ens ? a.nmodels : 1), block(256);
+    const dim3 grid((a.natoms + FIT_AF - 1) / FIT_AF, ens ? a.nmodels : 1), block(256 * HALVES);
+    if (ens) hipLaunchKernelGGL((k_fit_dense<P, true, RAD, HALVES>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_fit_dense<P, false, RAD, HALVES>), grid, block, 0, s, a);
+}
+
+template <class P, bool RAD>
+static void launch_dense(const FitArgs& a, hipStream_t s)
+{
+    const int64_t blocks = (int64_t)((a.natoms + FIT_AF - 1) / FIT_AF) * (a.nmodels > 1 ? a.nmodels : 1);
+    if (sizeof(typename P::acc) == 8 || blocks <= (a.ncu > 0 ? a.ncu : 256)) launch_dense_shape<P, RAD, 2>(a, s);
+    else launch_dense_shape<P, RAD, 1>(a, s);
+}
+
+void launch_fit(int precision, const FitArgs& a, hipStream_t s)
+{
     if (a.radial) {
-        if (precision == 0) {
-            if (ens) hipLaunchKernelGGL((k_fit_dense<PF64, true, true>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_fit_dense<PF64, false, true>), grid, block, 0, s, a);
-        } else {
-            if (ens) hipLaunchKernelGGL((k_fit_dense<PF32, true, true>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_fit_dense<PF32, false, true>), grid, block, 0, s, a);
-        }
+        if (precision == 0) launch_dense<PF64, true>(a, s);
+        else launch_dense<PF32, true>(a, s);
     } else if (precision == 0) {
-        if (ens) hipLaunchKernelGGL((k_fit_dense<PF64, true, false>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_fit_dense<PF64, false, false>), grid, block, 0, s, a);
+        launch_dense<PF64, false>(a, s);
     } else if (precision == 3) {
-        if (ens) hipLaunchKernelGGL((k_fit_dense<PF32, true, false>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_fit_dense<PF32, false, false>), grid, block, 0, s, a);
+        launch_dense<PF32, false>(a, s);
     } else {
         launch_fitx(precision == 1, a, s);
     }
