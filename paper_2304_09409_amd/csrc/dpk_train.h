@@ -55,6 +55,9 @@ void tr_colsum(int M, int N, const double* X1, double* o1, const double* X2, dou
 // with zd = sigma_m Zd (sigma optional, 1 if absent; Zd, Ydb optional: no tangent).
 void tr_adj_elem(int M, int N, const double* A, const double* Zd, const double* sigma, const double* Yb,
                  const double* Ydb, const double* wh, double* Zb, double* Zdb, double* H, hipStream_t s);
+// The same, with the column sums of zbar added into bsum and of h into hsum (h not stored).
+void tr_adj_sum(int M, int N, const double* A, const double* Zd, const double* sigma, const double* Yb,
+                const double* Ydb, const double* wh, double* Zb, double* Zdb, double* bsum, double* hsum, hipStream_t s);
 
 // Per-pair environment (pair p = (atom pa[p], slot ps[p])): R[p] = s (1, r/r), X0[p] = s, ones[p] = 1;
 // with vdir (training): the pair tangent rdot = vdir[j] - vdir[i] + CV r_ij, sigma[p] = ds/dt,

@@ -272,6 +272,50 @@ __global__ void __launch_bounds__(256) k_tr_adj_elem(int64_t total, int N, const
     }
 }
 
+// The same with the column sums of zbar and h added into bsum and hsum (the bias and w_hat
+// gradients): 64 columns x a range of rows per block, the four row groups reduced in LDS.
+__global__ void __launch_bounds__(256) k_tr_adj_sum(int M, int N, int rows_per, const double* A, const double* Zd,
+                                                    const double* sigma, const double* Yb, const double* Ydb,
+                                                    const double* wh, double* Zb, double* Zdb, double* bsum,
+                                                    double* hsum)
+{
+    __shared__ double s1[4][64], s2[4][64];
+    const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + c;
+    const int m0 = blockIdx.y * rows_per, m1 = min(M, m0 + rows_per);
+    double sb = 0.0, sh = 0.0;
+    if (n < N) {
+        const double w = wh[n];
+        for (int m = m0 + rg; m < m1; m += 4) {
+            const int64_t e = (int64_t)m * N + n;
+            const double a = A[e], gd = 1.0 - a * a, yb = Yb[e];
+            const double sg = sigma ? sigma[m] : 1.0;
+            const double zd = Zd ? sg * Zd[e] : 0.0, ydb = Ydb ? Ydb[e] : 0.0;
+            const double zb = w * gd * yb - 2.0 * w * a * gd * zd * ydb;
+            Zb[e] = zb;
+            if (Zdb) Zdb[e] = w * gd * ydb;
+            sb += zb;
+            sh += a * yb + gd * zd * ydb;
+        }
+    }
+    s1[rg][c] = sb;
+    s2[rg][c] = sh;
+    __syncthreads();
+    if (rg == 0 && n < N) {
+        atomicAdd(&bsum[n], s1[0][c] + s1[1][c] + s1[2][c] + s1[3][c]);
+        atomicAdd(&hsum[n], s2[0][c] + s2[1][c] + s2[2][c] + s2[3][c]);
+    }
+}
+
+void tr_adj_sum(int M, int N, const double* A, const double* Zd, const double* sigma, const double* Yb,
+                const double* Ydb, const double* wh, double* Zb, double* Zdb, double* bsum, double* hsum, hipStream_t s)
+{
+    if (M <= 0) return;
+    const int rows_per = 256;
+    const dim3 grid((N + 63) / 64, (M + rows_per - 1) / rows_per), block(256);
+    hipLaunchKernelGGL(k_tr_adj_sum, grid, block, 0, s, M, N, rows_per, A, Zd, sigma, Yb, Ydb, wh, Zb, Zdb, bsum, hsum);
+}
+
 void tr_adj_elem(int M, int N, const double* A, const double* Zd, const double* sigma, const double* Yb,
                  const double* Ydb, const double* wh, double* Zb, double* Zdb, double* H, hipStream_t s)
 {
@@ -346,36 +390,50 @@ void tr_env(const TrEnv& e, hipStream_t s)
 // ---------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_tr_contract(TrContract C)
 {
-    __shared__ double sT[E2][4], sTd[E2][4];
-    const int a = blockIdx.x;
+    // two atoms per block, 128 threads each: thread m < 100 accumulates T[m][0..3] (and Td) over the
+    // atom's pairs, reading row p of G at column m (consecutive threads, consecutive columns)
+    __shared__ double sT[2][E2][4], sTd[2][E2][4];
+    const int half = threadIdx.x >> 7, m = threadIdx.x & 127;
+    const int a = blockIdx.x * 2 + half;
     const bool tan = C.Td != nullptr;
-    for (int e = threadIdx.x; e < E2 * 4; e += 256) {
-        const int m = e >> 2, k = e & 3;
-        double t = 0.0, td = 0.0;
+    if (a < C.n && m < E2) {
+        double t[4] = {0, 0, 0, 0}, td[4] = {0, 0, 0, 0};
         for (int tj = 0; tj < C.nt; ++tj) {
             const int p0 = C.apo[(int64_t)a * C.nt + tj], cnt = C.nnei[(int64_t)a * C.nt + tj];
             for (int p = p0; p < p0 + cnt; ++p) {
-                const double g = C.G[(int64_t)p * E2 + m], r = C.R[4 * (int64_t)p + k];
-                t += g * r;
-                if (tan) td += C.sigma[p] * C.Gd[(int64_t)p * E2 + m] * r + g * C.Rd[4 * (int64_t)p + k];
+                const double g = C.G[(int64_t)p * E2 + m];
+                const double* r = C.R + 4 * (int64_t)p;
+                const double r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+                t[0] += g * r0; t[1] += g * r1; t[2] += g * r2; t[3] += g * r3;
+                if (tan) {
+                    const double gd = C.sigma[p] * C.Gd[(int64_t)p * E2 + m];
+                    const double* rd = C.Rd + 4 * (int64_t)p;
+                    td[0] += gd * r0 + g * rd[0];
+                    td[1] += gd * r1 + g * rd[1];
+                    td[2] += gd * r2 + g * rd[2];
+                    td[3] += gd * r3 + g * rd[3];
+                }
             }
         }
-        t *= C.inv_nc;
-        sT[m][k] = t;
-        C.T[((int64_t)a * E2 + m) * 4 + k] = t;
-        if (tan) {
-            td *= C.inv_nc;
-            sTd[m][k] = td;
-            C.Td[((int64_t)a * E2 + m) * 4 + k] = td;
+        for (int k = 0; k < 4; ++k) {
+            t[k] *= C.inv_nc;
+            sT[half][m][k] = t[k];
+            C.T[((int64_t)a * E2 + m) * 4 + k] = t[k];
+            if (tan) {
+                td[k] *= C.inv_nc;
+                sTd[half][m][k] = td[k];
+                C.Td[((int64_t)a * E2 + m) * 4 + k] = td[k];
+            }
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < DD; e += 256) {
-        const int m = e / AX, n = e - m * AX;
+    if (a >= C.n) return;
+    for (int e = m; e < DD; e += 128) {
+        const int mm = e / AX, nn = e - mm * AX;
         double d = 0.0, dd = 0.0;
         for (int k = 0; k < 4; ++k) {
-            d += sT[m][k] * sT[n][k];
-            if (tan) dd += sTd[m][k] * sT[n][k] + sT[m][k] * sTd[n][k];
+            d += sT[half][mm][k] * sT[half][nn][k];
+            if (tan) dd += sTd[half][mm][k] * sT[half][nn][k] + sT[half][mm][k] * sTd[half][nn][k];
         }
         C.D[(int64_t)a * DD + e] = d;
         if (tan) C.Dd[(int64_t)a * DD + e] = dd;
@@ -385,7 +443,7 @@ __global__ void __launch_bounds__(256) k_tr_contract(TrContract C)
 void tr_contract(const TrContract& c, hipStream_t s)
 {
     if (c.n <= 0) return;
-    hipLaunchKernelGGL(k_tr_contract, dim3(c.n), dim3(256), 0, s, c);
+    hipLaunchKernelGGL(k_tr_contract, dim3((c.n + 1) / 2), dim3(256), 0, s, c);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -145,10 +145,13 @@ void layer_bwd(dpk_trainer* t, const LayerOff& L, int M, const double* X, const 
                double* H, double* Xb, double* Xdb, bool wgrad, hipStream_t s)
 {
     const bool tan = Ydb != nullptr;
-    tr_adj_elem(M, L.nout, A, tan ? Zd : nullptr, sigma, Yb, Ydb, t->theta.p + L.wh, Zb, tan ? Zdb : nullptr, H, s);
     if (wgrad) {
+        // pre-activation adjoints with the bias and w_hat gradients, then the weight gradient
+        tr_adj_sum(M, L.nout, A, tan ? Zd : nullptr, sigma, Yb, Ydb, t->theta.p + L.wh, Zb, tan ? Zdb : nullptr,
+                   t->grad.p + L.b, t->grad.p + L.wh, s);
         tr_wgrad(M, L.nout, L.nin, X, Zb, tan ? Xd : nullptr, tan ? Zdb : nullptr, sigma, t->grad.p + L.W, s);
-        tr_colsum(M, L.nout, Zb, t->grad.p + L.b, H, t->grad.p + L.wh, s);
+    } else {
+        tr_adj_elem(M, L.nout, A, tan ? Zd : nullptr, sigma, Yb, Ydb, t->theta.p + L.wh, Zb, tan ? Zdb : nullptr, H, s);
     }
     if (Xb) {
         TrGemm g;
