@@ -19,7 +19,8 @@
 // Layout: the activations of every layer are materialised per row (rows = neighbour pairs grouped
 // by embedding net, or atoms grouped by type), and every layer is a row GEMM (tr_gemm) with a fused
 // epilogue; the weight gradients are GEMMs over the rows (tr_wgrad, split over rows with FP64
-// atomics). 64 x 64 output tiles, 16-deep K chunks staged in LDS, 4 x 4 outputs per thread.
+// atomics). 64 x 64 output tiles, 16-deep K chunks staged in LDS, four waves of 2 x 2 tiles of the
+// 16 x 16 x 4 FP64 matrix instruction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,21 +32,58 @@ namespace dpk {
 constexpr int TB = 64, TK = 16;
 
 // ---------------------------------------------------------------------------------------------
-// Row GEMM with layer epilogues
+// Row GEMM with layer epilogues, on v_mfma_f64_16x16x4f64. A block computes a 64 x 64 tile of C
+// with four waves of 32 x 32 (2 x 2 MFMA tiles); K runs in chunks of 16 staged in LDS. For one
+// instruction, lane l (group g = l / 16, column c = l % 16) supplies A[c][g] and B[g][c] of the
+// 16 x 16 x 4 step and receives D[g + 4r][c] in register r.
 // ---------------------------------------------------------------------------------------------
+typedef double d4v __attribute__((ext_vector_type(4)));
+constexpr int TAP = TK + 1;   // LDS row pitch of the A tiles (doubles): rows c = 0..15 fall in distinct banks
+
+__device__ __forceinline__ void tr_epilogue(const TrGemm& g, int m, int n, double c, double c2, bool dual)
+{
+    const int64_t o = (int64_t)m * g.N + n;
+    if (g.mode == TR_FWD) {
+        // skip source: the input row at n (N == K) or n mod K (N == 2K)
+        const int ks = g.N == g.K ? n : (g.N == 2 * g.K ? (n < g.K ? n : n - g.K) : -1);
+        const double a = tanh(c + g.bias[n]);
+        g.C[o] = a;
+        g.Y[o] = g.wh[n] * a + (ks >= 0 ? g.A[(int64_t)m * g.K + ks] : 0.0);
+        if (dual) {
+            g.Zd[o] = c2;
+            g.Yd[o] = g.wh[n] * (1.0 - a * a) * c2 + (ks >= 0 ? g.A2[(int64_t)m * g.K + ks] : 0.0);
+        }
+    } else if (g.mode == TR_BWD) {
+        double sk = 0.0, sk2 = 0.0;
+        if (g.NS == g.N) {
+            sk = g.S[(int64_t)m * g.NS + n];
+            if (dual) sk2 = g.S2[(int64_t)m * g.NS + n];
+        } else if (g.NS == 2 * g.N) {
+            sk = g.S[(int64_t)m * g.NS + n] + g.S[(int64_t)m * g.NS + n + g.N];
+            if (dual) sk2 = g.S2[(int64_t)m * g.NS + n] + g.S2[(int64_t)m * g.NS + n + g.N];
+        }
+        g.C[o] = c + sk;
+        if (dual) g.C2[o] = c2 + sk2;
+    } else {
+        g.C[o] = c;
+        if (dual) g.C2[o] = c2;
+    }
+}
+
 template <bool DUAL>
 __global__ void __launch_bounds__(256) k_tr_gemm(TrGemm g)
 {
-    __shared__ double sA[TK][TB + 1];
-    __shared__ double sA2[DUAL ? TK : 1][TB + 1];
+    __shared__ double sA[TB][TAP];
+    __shared__ double sA2[DUAL ? TB : 1][TAP];
     __shared__ double sB[TK][TB + 1];
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lg = lane >> 4, lc = lane & 15;
+    const int wr = wave >> 1, wc = wave & 1;
     const int m0 = blockIdx.y * TB, n0 = blockIdx.x * TB;
-    double acc[4][4], acc2[4][4];
+    d4v acc[2][2], acc2[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = acc2[i][j] = 0.0;
+        for (int j = 0; j < 2; ++j) acc[i][j] = acc2[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < g.K; k0 += TK) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -54,8 +92,8 @@ __global__ void __launch_bounds__(256) k_tr_gemm(TrGemm g)
             const int r = idx >> 4, kk = idx & 15;
             const int m = m0 + r, k = k0 + kk;
             const bool in = m < g.M && k < g.K;
-            sA[kk][r] = in ? g.A[(int64_t)m * g.K + k] : 0.0;
-            if (DUAL) sA2[kk][r] = in ? g.A2[(int64_t)m * g.K + k] : 0.0;
+            sA[r][kk] = in ? g.A[(int64_t)m * g.K + k] : 0.0;
+            if (DUAL) sA2[r][kk] = in ? g.A2[(int64_t)m * g.K + k] : 0.0;
             // B tile: 16 k x 64 n
             if (g.transB) {
                 const int c = idx >> 4, kb = idx & 15;
@@ -68,62 +106,34 @@ __global__ void __launch_bounds__(256) k_tr_gemm(TrGemm g)
             }
         }
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < TK; ++kk) {
-            double a[4], b[4], a2[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = sA[kk][ty + 16 * i];
-                if (DUAL) a2[i] = sA2[kk][ty + 16 * i];
-                b[i] = sB[kk][tx + 16 * i];
+        for (int ks = 0; ks < TK; ks += 4) {
+            double a[2], a2[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[i] = sA[wr * 32 + i * 16 + lc][ks + lg];
+                if (DUAL) a2[i] = sA2[wr * 32 + i * 16 + lc][ks + lg];
+                b[i] = sB[ks + lg][wc * 32 + i * 16 + lc];
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j] += a[i] * b[j];
-                    if (DUAL) acc2[i][j] += a2[i] * b[j];
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                    if (DUAL) acc2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i], b[j], acc2[i][j], 0, 0, 0);
                 }
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int m = m0 + ty + 16 * i;
-        if (m >= g.M) continue;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = n0 + tx + 16 * j;
-            if (n >= g.N) continue;
-            const int64_t o = (int64_t)m * g.N + n;
-            if (g.mode == TR_FWD) {
-                // skip source: the input row at n (N == K) or n mod K (N == 2K)
-                const int ks = g.N == g.K ? n : (g.N == 2 * g.K ? (n < g.K ? n : n - g.K) : -1);
-                const double a = tanh(acc[i][j] + g.bias[n]);
-                g.C[o] = a;
-                g.Y[o] = g.wh[n] * a + (ks >= 0 ? g.A[(int64_t)m * g.K + ks] : 0.0);
-                if (DUAL) {
-                    const double zd = acc2[i][j];
-                    g.Zd[o] = zd;
-                    g.Yd[o] = g.wh[n] * (1.0 - a * a) * zd + (ks >= 0 ? g.A2[(int64_t)m * g.K + ks] : 0.0);
-                }
-            } else if (g.mode == TR_BWD) {
-                double sk = 0.0, sk2 = 0.0;
-                if (g.NS == g.N) {
-                    sk = g.S[(int64_t)m * g.NS + n];
-                    if (DUAL) sk2 = g.S2[(int64_t)m * g.NS + n];
-                } else if (g.NS == 2 * g.N) {
-                    sk = g.S[(int64_t)m * g.NS + n] + g.S[(int64_t)m * g.NS + n + g.N];
-                    if (DUAL) sk2 = g.S2[(int64_t)m * g.NS + n] + g.S2[(int64_t)m * g.NS + n + g.N];
-                }
-                g.C[o] = acc[i][j] + sk;
-                if (DUAL) g.C2[o] = acc2[i][j] + sk2;
-            } else {
-                g.C[o] = acc[i][j];
-                if (DUAL) g.C2[o] = acc2[i][j];
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wr * 32 + i * 16 + lg + 4 * r, n = n0 + wc * 32 + j * 16 + lc;
+                if (m < g.M && n < g.N) tr_epilogue(g, m, n, acc[i][j][r], DUAL ? acc2[i][j][r] : 0.0, DUAL);
             }
-        }
-    }
 }
 
 void tr_gemm(const TrGemm& g, hipStream_t s)
@@ -135,7 +145,8 @@ void tr_gemm(const TrGemm& g, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------------------------
-// Weight gradient: Wbar[K][N] += A1^T B1 + A2^T B2 over the rows; blockIdx.z takes a row range.
+// Weight gradient: Wbar[K][N] += A1^T B1 + A2^T (scale2 B2) over the rows, on the FP64 MFMA with
+// the rows as the reduction index; blockIdx.z takes a row range (FP64 atomics into Wbar).
 // ---------------------------------------------------------------------------------------------
 template <bool DUAL>
 __global__ void __launch_bounds__(256) k_tr_wgrad(int M, int N, int K, int rows_per, const double* A1,
@@ -144,14 +155,15 @@ __global__ void __launch_bounds__(256) k_tr_wgrad(int M, int N, int K, int rows_
 {
     __shared__ double sA[TK][TB + 1], sB[TK][TB + 1];
     __shared__ double sA2[DUAL ? TK : 1][TB + 1], sB2[DUAL ? TK : 1][TB + 1];
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lg = lane >> 4, lc = lane & 15;
+    const int wr = wave >> 1, wc = wave & 1;
     const int k0 = blockIdx.y * TB, n0 = blockIdx.x * TB;
     const int r0 = blockIdx.z * rows_per, r1 = min(M, r0 + rows_per);
-    double acc[4][4];
+    d4v acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
     for (int m0 = r0; m0 < r1; m0 += TK) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -168,42 +180,37 @@ __global__ void __launch_bounds__(256) k_tr_wgrad(int M, int N, int K, int rows_
             }
         }
         __syncthreads();
-#pragma unroll 4
-        for (int mm = 0; mm < TK; ++mm) {
-            double a[4], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = sA[mm][ty + 16 * i];
-                b[i] = sB[mm][tx + 16 * i];
-            }
+        for (int ks = 0; ks < TK; ks += 4) {
+            double a[2], b[2], a2[2], b2[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-            if (DUAL) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    a[i] = sA2[mm][ty + 16 * i];
-                    b[i] = sB2[mm][tx + 16 * i];
+            for (int i = 0; i < 2; ++i) {
+                a[i] = sA[ks + lg][wr * 32 + i * 16 + lc];
+                b[i] = sB[ks + lg][wc * 32 + i * 16 + lc];
+                if (DUAL) {
+                    a2[i] = sA2[ks + lg][wr * 32 + i * 16 + lc];
+                    b2[i] = sB2[ks + lg][wc * 32 + i * 16 + lc];
                 }
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
             }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                    if (DUAL) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i], b2[j], acc[i][j], 0, 0, 0);
+                }
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int k = k0 + ty + 16 * i;
-        if (k >= K) continue;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = n0 + tx + 16 * j;
-            if (n < N) atomicAdd(&Wbar[(int64_t)k * N + n], acc[i][j]);
-        }
-    }
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = k0 + wr * 32 + i * 16 + lg + 4 * r, n = n0 + wc * 32 + j * 16 + lc;
+                if (k < K && n < N) atomicAdd(&Wbar[(int64_t)k * N + n], acc[i][j][r]);
+            }
 }
 
 void tr_wgrad(int M, int N, int K, const double* A1, const double* B1, const double* A2, const double* B2,
