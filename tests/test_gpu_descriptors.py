@@ -238,3 +238,24 @@ def test_se_e3_deviation_is_refused():
     with pytest.raises(dpk.DpkError) as e:
         dpk.Deviation([m, m], precision="fp64")
     assert e.value.code == dpk.DPK_E_UNIMPLEMENTED
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_se_e3_one_and_three_types(precision):
+    """se_e3 with one species (every pair in one type block: the k <= j walk throughout) on a
+    truncated fcc box, and with three species (nine nets, three same-type blocks) on a 3-type frame."""
+    from oracle import Oracle
+    from paper_2304_09409_amd import dpk
+    cases = [
+        (dict(synth.WATER_E3_MODEL, ntypes=1, sel=[40]), synth.fcc_box(4, 3.6, 2)),
+        (dict(synth.WATER_E3_MODEL, ntypes=3, sel=[20, 20, 14]), synth.serving_frame(400, 23, 3)),
+    ]
+    for spec, (c, t, b) in cases:
+        say(f"se_e3 {spec['ntypes']} types {precision} ({len(t)} atoms)")
+        p = synth.make_params(spec, 17, synth.WATER_E3_OUT_SCALE, synth.WATER_E3_FIT_IN)
+        ref = Oracle(spec, p).compute(c, t, b)
+        ctx = dpk.Context(dpk.Model(spec, p), precision=precision)
+        got = ctx.compute(c, t, b)
+        (check_fp64 if precision == "fp64" else check_mixed)(got, ref, len(t))
+        assert ctx.stats()["nbr_dropped"] == ref["ndrop"]
+        ctx.close()
