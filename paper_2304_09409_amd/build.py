@@ -25,6 +25,8 @@ SOURCES = {
     "kernels_geom.hip": ["-ffp-contract=off"],
     "kernels_nn.hip": [],
     "kernels_fit.hip": [],
+    # the table kernels keep their MFMA accumulators in VGPRs (no AGPR copies around the loops)
+    "kernels_tab.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "api.cpp": ["-ffp-contract=off"],
     "model_file.cpp": [],
     "kernels_train.hip": [],

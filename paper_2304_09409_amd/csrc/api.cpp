@@ -628,13 +628,29 @@ int upload_model(dpk_ctx* c)
     c->fmat_b = f64 ? fm.d.size() * 8 : dense ? fm.f.size() * 4 : fx.size() * 2;
     c->model_bytes = c->evec_b + c->fvec_b + c->emat_b + c->fmat_b;
     if (m->tabulated) {
+        // the per-interval layout, then the table as the row-major matrix C[6 l + j][m] and its
+        // transpose (the two-body descriptors' product kernels read whole 16-wide rows of both)
+        const int nint = m->tab_nint, kp = tab_kp(nint);
+        const size_t nets = (size_t)m->nets, prod = nets * kp * N3P;
+        std::vector<double> tab(m->table.size() + 2 * prod, 0.0);
+        std::copy(m->table.begin(), m->table.end(), tab.begin());
+        double* tk = tab.data() + m->table.size();
+        double* tm = tk + prod;
+        for (size_t net = 0; net < nets; ++net)
+            for (int l = 0; l < nint; ++l)
+                for (int o = 0; o < E2; ++o)
+                    for (int j = 0; j < 6; ++j) {
+                        const double v = m->table[((net * nint + l) * E2 + o) * 6 + j];
+                        tk[(net * kp + 6 * l + j) * N3P + o] = v;
+                        tm[(net * N3P + o) * kp + 6 * l + j] = v;
+                    }
         if (f64) {
-            if ((rc = upload(&c->table, m->table.data(), m->table.size()))) return rc;
+            if ((rc = upload(&c->table, tab.data(), tab.size()))) return rc;
         } else {
-            std::vector<float> tf(m->table.begin(), m->table.end());
+            std::vector<float> tf(tab.begin(), tab.end());
             if ((rc = upload(&c->table, tf.data(), tf.size()))) return rc;
         }
-        c->table_b = m->table.size() * c->acc_size;
+        c->table_b = tab.size() * c->acc_size;
         c->model_bytes += c->table_b;
         c->tab = true;
         c->tab_dx = m->tab_dx;

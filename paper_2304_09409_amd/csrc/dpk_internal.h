@@ -82,6 +82,16 @@ __host__ __device__ constexpr void emb_reg3(int f, int& g, int& u)
     u = 4 * (k - emb_kb(g)) + 2 * h2 + h3;
 }
 
+// The quintic table of the compressed embedding (Sec. II.A.6, eq. compress) is uploaded in three
+// layouts, one after the other in one buffer of the accumulation type:
+//   [nets][nint][100][6]        per interval and feature its six coefficients (three-body table);
+//   [nets][tab_kp][N3P]         row K = 6 l + j, column m: coefficient j of feature m on interval l;
+//   [nets][N3P][tab_kp]         the same transposed.
+// Coefficient j multiplies t^(5 - j), t = x - l dx. Rows past 6 nint and columns past 100 are zero;
+// tab_kp leaves at least 64 zero rows past the last interval (the product kernels read whole
+// groups of 16-row tiles there).
+__host__ __device__ constexpr int tab_kp(int nint) { return (6 * nint + 15) / 16 * 16 + 64; }
+
 constexpr int64_t EM_W2T = 0;                          // [64][32]
 constexpr int64_t EM_W3T = N2P * K2P;                  // [112][64]
 constexpr int64_t EM_SIZE = EM_W3T + N3P * N2P;
@@ -166,7 +176,7 @@ struct EmbArgs {
     // network (packed per policy) or table
     const void* evec;        // [nets][EVEC] of acc type
     const void* emat;        // [planes][nets][EM_SIZE] of weight type
-    const void* table;       // [nets][nint][100][6] of acc type
+    const void* table;       // the table's three layouts (tab_kp) of acc type
     double tab_dx; int tab_nint;
     void* T;                 // [N][100][4] of acc type (forward output)
     const void* dT;          // [N][100][4] (backward input)

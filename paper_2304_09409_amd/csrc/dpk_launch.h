@@ -66,6 +66,11 @@ int fit_atoms_per_block(int precision);
 void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s, bool e3 = false);
 void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s, bool e3 = false);
 void launch_e3_env(int precision, const EmbArgs& a, hipStream_t s);
+// Tabulated embedding of the two-body descriptors as products with the table (forward or
+// backward), its block count (one [E, virial] partial each) and its smallest block in atoms.
+void launch_tab(bool fwd, int precision, const EmbArgs& a, hipStream_t s);
+int tab_blocks(int64_t natoms, int ncu);
+int tab_atoms_per_block_min();
 void launch_fit(int precision, const FitArgs& a, hipStream_t s);
 // BF16 fitting kernel (split = three products); 16-atom tiles per block for a frame of natoms
 void launch_fitx(bool split, const FitArgs& a, hipStream_t s);

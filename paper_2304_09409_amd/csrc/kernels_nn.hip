@@ -28,13 +28,12 @@
 //     so each layer's output tiles are the next layer's B operand; the descriptor D = T T_<^T
 //     is formed on the fly in B-operand layout; the input gradient uses W as A.
 #include <hip/hip_runtime.h>
+#include "dpk_device.h"
 #include "dpk_internal.h"
 #include "dpk_launch.h"
 
 namespace dpk {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -266,13 +265,6 @@ __device__ __forceinline__ void outer4(f4& d, float a, float b)
     d = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, d, 0, 0, 0);
 }
 
-// Wave-scope ordering of LDS traffic between lanes of one wave.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Cross-lane sums over the four 16-lane groups of a wave on v_permlane32_swap (exchanges the
 // upper half of one register with the lower half of another: pairs groups g, g + 2) and
@@ -318,28 +310,6 @@ template <class T> __device__ __forceinline__ T sum_groups4(const T* p)
     return q0 + q1;
 }
 
-// Switching function of Sec. II.A.1 (eq. switch) and its derivative, FP64, from r, ir = 1/r and
-// inv_w = 1/(rc - rs) (no division here: the caller's 1/r is the only one per neighbour).
-__device__ __forceinline__ void switch_fn(double r, double ir, double rs, double rc, double inv_w, double& s,
-                                          double& ds)
-{
-    if (r < rs) {
-        s = ir;
-        ds = -ir * ir;
-    } else if (r < rc) {
-        // u = x^3 (-6 x^2 + 15 x - 10) + 1 as (1 - x)^3 (1 + 3 x + 6 x^2): no cancellation near
-        // r_c, so s >= 0 (a table counts negative inputs as out of range)
-        double x = (r - rs) * inv_w;
-        double y = 1.0 - x;
-        double u = y * y * y * (1.0 + x * (3.0 + 6.0 * x));
-        double du = -30.0 * x * x * y * y;
-        s = u * ir;
-        ds = du * ir * inv_w - u * ir * ir;
-    } else {
-        s = 0.0;
-        ds = 0.0;
-    }
-}
 
 // Row stride of the forward pass's neighbour-major layer-2 buffer (64 rows used): a multiple of 4
 // but not of 8, so the reads at (neighbour orow(g, r), row n) of the four lane groups fall in
@@ -843,14 +813,8 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
     // per neighbour column of a wave: [0, 3) the centre atom's force over its pairs, [3, 12) the
     // virial sum -g r^T over the wave's pairs (kept here rather than in every lane's registers)
     __shared__ __attribute__((aligned(16))) double s_pair[NW][16][12];
-    // table path: force scatter deferred by one chunk (per column -g of the last chunk's pair and
-    // the neighbour's caller index, -1: none; the centre force of an atom that ended, and its
-    // caller index); every path: the LDS atom table of the walk (its reads do not wait on the
-    // in-order vector memory counter, which also holds the force atomics)
-    // (the table path defers; the three-body path accumulates per slot instead)
-    constexpr bool DEFER = TAB && !E3;
-    __shared__ __attribute__((aligned(16))) double s_defer[DEFER ? NW : 1][16][4];
-    __shared__ __attribute__((aligned(16))) double s_defc[DEFER ? NW : 1][4];
+    // the LDS atom table of the walk (its reads do not wait on the in-order vector memory counter,
+    // which also holds the force atomics)
     __shared__ int s_wl[NW][2 * WL_MAX];
     // three-body: dE/dR_j of every slot of the wave's atom
     __shared__ __attribute__((aligned(16))) acc s_dRs[E3 ? NW : 1][E3 ? E3_MAXN : 1][4];
@@ -859,28 +823,8 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
     const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     for (int e = lane; e < N3P * 4; e += 64) s_dT[wave][e >> 2][e & 3] = 0;
     for (int e = lane; e < 16 * 12; e += 64) s_pair[wave][e / 12][e % 12] = 0.0;
-    if (DEFER && g == 0) s_defer[wave][c16][3] = -1.0;
-    if (DEFER && lane == 0) s_defc[wave][3] = -1.0;
     if constexpr (E3)
         for (int e = lane; e < E3_MAXN * 4; e += 64) s_dRs[wave][e >> 2][e & 3] = 0;
-    // the atomics deferred from the previous chunk (each lane issues what it stored itself)
-    auto issue_deferred = [&]() {
-        if (g == 0) {
-            const double* d = s_defer[wave][c16];
-            const int jd = (int)d[3];
-            if (jd >= 0) {
-                unsafeAtomicAdd(&A.F[3 * (size_t)jd], d[0]);
-                unsafeAtomicAdd(&A.F[3 * (size_t)jd + 1], d[1]);
-                unsafeAtomicAdd(&A.F[3 * (size_t)jd + 2], d[2]);
-                s_defer[wave][c16][3] = -1.0;
-            }
-        }
-        if (lane == 0 && s_defc[wave][3] >= 0.0) {
-            const int cd = (int)s_defc[wave][3];
-            for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&A.F[3 * (size_t)cd + k], s_defc[wave][k]);
-            s_defc[wave][3] = -1.0;
-        }
-    };
     const double inv_w = 1.0 / (A.rc - A.rs);
     const int a0 = blockIdx.x * APB;
     const int a1 = min(a0 + APB, A.natoms);
@@ -970,14 +914,6 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                         ir = 1.0 / r;
                         switch_fn(r, ir, A.rs, A.rc, inv_w, s, ds);
                     }
-                }
-                // table path: the previous chunk's force atomics are issued after this chunk's
-                // prefetches and dT staging, where no wait on the vector memory counter follows
-                // for a while (that counter is in order, so any wait would include them)
-                if constexpr (DEFER) {
-                    __builtin_amdgcn_sched_barrier(0);
-                    issue_deferred();
-                    __builtin_amdgcn_sched_barrier(0);
                 }
                 acc dR[4] = {0, 0, 0, 0}, H[4] = {0, 0, 0, 0};
                 if (TAB) {
@@ -1131,14 +1067,9 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                     const double q = d1 * ux + d2 * uy + d3 * uz;
                     const double rad = (d0 + dEds) * ds + q * (ds - sr);
                     const double gx = rad * ux + sr * d1, gy = rad * uy + sr * d2, gz = rad * uz + sr * d3;
-                    if constexpr (DEFER) {
-                        double* dfr = s_defer[wave][p];
-                        dfr[0] = -gx; dfr[1] = -gy; dfr[2] = -gz; dfr[3] = (double)jn;
-                    } else {
-                        unsafeAtomicAdd(&A.F[3 * (size_t)jn], -gx);
-                        unsafeAtomicAdd(&A.F[3 * (size_t)jn + 1], -gy);
-                        unsafeAtomicAdd(&A.F[3 * (size_t)jn + 2], -gz);
-                    }
+                    unsafeAtomicAdd(&A.F[3 * (size_t)jn], -gx);
+                    unsafeAtomicAdd(&A.F[3 * (size_t)jn + 1], -gy);
+                    unsafeAtomicAdd(&A.F[3 * (size_t)jn + 2], -gz);
                     double* pa = s_pair[wave][p];
                     pa[0] += gx; pa[1] += gy; pa[2] += gz;
                     pa[3] -= gx * x; pa[4] -= gx * y; pa[5] -= gx * z;
@@ -1158,20 +1089,17 @@ __global__ void __launch_bounds__((EmbCfg<P, false, TAB>::NW * 64)) k_embed_bwd(
                         v += __shfl_xor(v, 8);
                         if (lane == 0) {
                             if (k < 3) {
-                                if constexpr (DEFER) s_defc[wave][k] = v;
-                                else unsafeAtomicAdd(&A.F[3 * (size_t)cac + k], v);
+                                unsafeAtomicAdd(&A.F[3 * (size_t)cac + k], v);
                             } else {
                                 A.vir_atom[9 * (size_t)ca + k - 3] += v;
                             }
                         }
                     }
-                    if (DEFER && lane == 0) s_defc[wave][3] = (double)cac;
                     wave_sync();
                     if (g == 0)
                         for (int k = 0; k < nk; ++k) s_pair[wave][c16][k] = 0.0;
                 }
             }
-            if constexpr (DEFER) issue_deferred();   // the pass's last chunk
         }
     }
     if constexpr (E3) {
@@ -1682,6 +1610,7 @@ static int embed_bwd_blocks_p(int64_t natoms, int ncu, bool e3)
 
 int embed_bwd_blocks(int precision, bool table, int64_t natoms, int ncu, bool e3)
 {
+    if (table && !e3) return tab_blocks(natoms, ncu);
     if (precision == 0) return table ? embed_bwd_blocks_p<PF64, true>(natoms, ncu, e3) : embed_bwd_blocks_p<PF64, false>(natoms, ncu, e3);
     if (precision == 1) return table ? embed_bwd_blocks_p<PMIX, true>(natoms, ncu, e3) : embed_bwd_blocks_p<PMIX, false>(natoms, ncu, e3);
     if (precision == 3) return table ? embed_bwd_blocks_p<PF32, true>(natoms, ncu, e3) : embed_bwd_blocks_p<PF32, false>(natoms, ncu, e3);
@@ -1691,8 +1620,9 @@ int embed_bwd_blocks(int precision, bool table, int64_t natoms, int ncu, bool e3
 // at least one atom per wave: the smallest block (in atoms) over both paths bounds the count
 int64_t embed_bwd_max_blocks(int precision, int64_t natoms)
 {
-    const int nw = precision == 0 ? std::min(EmbCfg<PF64, false, false>::NW, EmbCfg<PF64, false, true>::NW)
-                                  : std::min(EmbCfg<PMIX, false, false>::NW, EmbCfg<PMIX, false, true>::NW);
+    const int nw = std::min(tab_atoms_per_block_min(),
+                            precision == 0 ? std::min(EmbCfg<PF64, false, false>::NW, EmbCfg<PF64, false, true>::NW)
+                                           : std::min(EmbCfg<PMIX, false, false>::NW, EmbCfg<PMIX, false, true>::NW));
     static_assert(EmbCfg<PBF16, false, false>::NW == EmbCfg<PMIX, false, false>::NW &&
                   EmbCfg<PBF16, false, true>::NW == EmbCfg<PMIX, false, true>::NW &&
                   EmbCfg<PF32, false, false>::NW == EmbCfg<PMIX, false, false>::NW &&
@@ -1707,7 +1637,8 @@ template __global__ void k_embed_bwd<PF64, false, false, true>(EmbArgs);
 template __global__ void k_embed_bwd<PF64, true, false, true>(EmbArgs);
 
 // e3: the three-body descriptor's pair passes (a single model; an ensemble of three-body models
-// is refused by the host).
+// is refused by the host). The table runs here only for the three-body descriptor (the two-body
+// descriptors' table has the product kernels of kernels_tab.hip).
 template <class P, bool FWD, bool TAB>
 static void launch_embed_shape(const EmbArgs& a0, bool e3, hipStream_t s)
 {
@@ -1719,12 +1650,16 @@ static void launch_embed_shape(const EmbArgs& a0, bool e3, hipStream_t s)
     const dim3 grid((a.natoms + apb - 1) / apb, ens ? a.nmodels : 1), block(Cfg::NW * 64);
     if constexpr (FWD) {
         if (e3) hipLaunchKernelGGL((k_embed_fwd<P, TAB, false, true>), grid, block, 0, s, a);
-        else if (ens) hipLaunchKernelGGL((k_embed_fwd<P, TAB, true, false>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_embed_fwd<P, TAB, false, false>), grid, block, 0, s, a);
+        else if constexpr (!TAB) {
+            if (ens) hipLaunchKernelGGL((k_embed_fwd<P, TAB, true, false>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_embed_fwd<P, TAB, false, false>), grid, block, 0, s, a);
+        }
     } else {
         if (e3) hipLaunchKernelGGL((k_embed_bwd<P, TAB, false, true>), grid, block, 0, s, a);
-        else if (ens) hipLaunchKernelGGL((k_embed_bwd<P, TAB, true, false>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_embed_bwd<P, TAB, false, false>), grid, block, 0, s, a);
+        else if constexpr (!TAB) {
+            if (ens) hipLaunchKernelGGL((k_embed_bwd<P, TAB, true, false>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_embed_bwd<P, TAB, false, false>), grid, block, 0, s, a);
+        }
     }
 }
 
@@ -1740,8 +1675,11 @@ static void launch_embed(bool fwd, bool table, const EmbArgs& a, bool e3, hipStr
     }
 }
 
+// The two-body descriptors' table runs on the matrix-product kernels of kernels_tab.hip; the
+// three-body table on the pair walk here.
 void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s, bool e3)
 {
+    if (table && !e3) return launch_tab(true, precision, a, s);
     if (precision == 0) launch_embed<PF64>(true, table, a, e3, s);
     else if (precision == 1) launch_embed<PMIX>(true, table, a, e3, s);
     else if (precision == 3) launch_embed<PF32>(true, table, a, e3, s);
@@ -1750,6 +1688,7 @@ void launch_embed_fwd(int precision, bool table, const EmbArgs& a, hipStream_t s
 
 void launch_embed_bwd(int precision, bool table, const EmbArgs& a, hipStream_t s, bool e3)
 {
+    if (table && !e3) return launch_tab(false, precision, a, s);
     if (precision == 0) launch_embed<PF64>(false, table, a, e3, s);
     else if (precision == 1) launch_embed<PMIX>(false, table, a, e3, s);
     else if (precision == 3) launch_embed<PF32>(false, table, a, e3, s);
