@@ -38,7 +38,8 @@ PEAK = {
 #   embedding net, per pair: 2 (25 + 25*50 + 50*100) = 12,550 flop forward; the input-gradient
 #     pass needs the same products again (12,550) on top of the contraction's;
 #   tabulated embedding, per pair: 100 features x 5 FMA for G (1,000 flop) and x 4 FMA for dG/ds
-#     (800 flop);
+#     (800 flop) (the kernels reach the same result with less arithmetic, as products of the table
+#     with per-interval moments; the fraction counts the method's work per second);
 #   contraction, per pair: T += G^T R 800 flop, dE/dR = G dT and dE/dG . R 1,600 flop;
 #   environment row and chain rule, per pair: about 50 flop (FP64);
 #   fitting, per atom: D = T T_<^T 12,800 + dE/dT 25,600 + 2 x 2 (1600*240 + 2*240^2 + 240)
@@ -107,7 +108,8 @@ def stage_rooflines(stage_ms: dict, precision: str, natoms: int, npairs: int, nc
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_water12288.txt")
 KERNEL_SOURCES = ("paper_2304_09409_amd/csrc/kernels_nn.hip", "paper_2304_09409_amd/csrc/kernels_geom.hip",
-                  "paper_2304_09409_amd/csrc/dpk_internal.h", "paper_2304_09409_amd/csrc/kernels_fit.hip")
+                  "paper_2304_09409_amd/csrc/dpk_internal.h", "paper_2304_09409_amd/csrc/kernels_fit.hip",
+                  "paper_2304_09409_amd/csrc/kernels_tab.hip", "paper_2304_09409_amd/csrc/dpk_device.h")
 
 
 def kernel_source_digest() -> str:
