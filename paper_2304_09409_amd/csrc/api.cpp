@@ -313,6 +313,13 @@ bool dense_fitting(const dpk_ctx* c)
     return c->precision == DPK_FP64 || c->precision == DPK_FP32 || c->model->desc.descriptor != DPK_SE_E2_A;
 }
 
+// Atom slots of the fitting grid for n atoms: the dense kernel's 64-atom blocks leave at most 63
+// padding slots; the BF16-path kernel tiles each species separately (at most 64 per species).
+int64_t fit_slots(int64_t n, bool dense)
+{
+    return (n + FIT_AF - 1) / FIT_AF * FIT_AF + FIT_AF * (dense ? 1 : MAXT + 1);
+}
+
 // Byte layout of the workspace for n atoms and ncell bins; if base != nullptr, assign views.
 size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
 {
@@ -348,10 +355,10 @@ size_t layout_ws(dpk_ctx* c, int64_t n, int64_t ncell, char* base)
     p = take(c->acc_size * n * E2 * 4); if (base) c->T = p;
     p = take(c->acc_size * n * E2 * 4); if (base) c->dT = p;
     // fitting scratch, for every atom slot of the fitting grid (padding lanes get their own rows):
-    // FP64 [slots][6][240]; BF16 paths [blocks][3][16][tiles][64][4] (XF_ACT floats per 16 slots),
-    // with at most 63 padding slots in either grid
-    const int64_t nfit = (n + FIT_AF - 1) / FIT_AF * FIT_AF + FIT_AF;
+    // FP64 [slots][6][240] with at most 63 padding slots; BF16 paths [blocks][3][16][tiles][64][4]
+    // (XF_ACT floats per 16 slots), species-aligned tiles: at most 64 padding slots per species
     const bool dense_fit = dense_fitting(c);
+    const int64_t nfit = fit_slots(n, dense_fit);
     p = take(dense_fit ? c->acc_size * nfit * 6 * FW : sizeof(float) * (nfit / 16) * XF_ACT);
     if (base) c->act = p;
     p = take(e3 ? c->acc_size * n * nc * 4 : 0); if (base) c->env = e3 ? p : nullptr;
@@ -1432,8 +1439,8 @@ int devi_buffers(dpk_devi* d, int64_t n)
 {
     if (n <= d->cap && d->buf) return DPK_OK;
     dpk_ctx* c = d->geo;
-    const int64_t nfit = (n + FIT_AF - 1) / FIT_AF * FIT_AF + FIT_AF;
     const bool dense_fit = dense_fitting(c);
+    const int64_t nfit = fit_slots(n, dense_fit);
     d->st_T = align256(c->acc_size * n * E2 * 4);
     d->st_act = align256(dense_fit ? c->acc_size * nfit * 6 * FW : sizeof(float) * (nfit / 16) * XF_ACT);
     d->st_vir = align256(sizeof(double) * 10 * embed_bwd_max_blocks(c->precision, n));

@@ -30,6 +30,9 @@ struct F8 {
 };
 
 constexpr int FX_G = 4;    // layer-1 K-chunks per D group
+#ifndef FITX_PD
+#define FITX_PD 4          // weight lookahead (K-chunks) of the 32-atom block shape
+#endif
 
 // FP32 hyperbolic tangent on the hardware exp2 and reciprocal: 1 - 2 / (2^(2x log2 e) + 1).
 __device__ __forceinline__ float fx_tanh(float x)
@@ -109,7 +112,7 @@ __device__ __forceinline__ float sum_groups4(const float* p)
 }
 __device__ __forceinline__ int ksel(int g) { return ((g & 1) << 1) | (g >> 1); }
 
-template <int NAT, bool SPLIT, int NW, bool ENS>
+template <int NAT, bool SPLIT, int NW, bool ENS, int PD>
 __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A_)
 {
     const FitArgs A = ENS ? model_args(A_) : A_;
@@ -119,6 +122,7 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A_)
     constexpr int NWA = NW / NAT;                      // waves sharing one atom tile's D fragments
     // the dD phase splits the waves into NW / 4 atom groups of NAT / (NW / 4) atom tiles each
     static_assert(NW % NAT == 0 && NW % 4 == 0 && NAT % (NW / 4) == 0, "wave layout");
+    static_assert(FX_G % PD == 0 && XF_NCH2 % PD == 0, "prefetch ring slots are compile-time");
     // B operands [K-chunk][atom tile] (layer 1: two groups of FX_G chunks); at the end the
     // per-wave dT partials (floats) of the D rows n < 16.
     __shared__ __attribute__((aligned(16))) __bf16 s_b[XF_NCH2 * NAT * FR];
@@ -131,10 +135,24 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A_)
     const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     const int nblk = gridDim.x, xcd = blockIdx.x & 7, per = nblk >> 3, rem = nblk & 7;
     const int blk = xcd * per + min(xcd, rem) + (blockIdx.x >> 3);
-    const int a0 = blk * NA;
-    if (a0 >= A.natoms) return;
-    const int a1 = min(a0 + NA, A.natoms);
-    const int t_lo = A.itype[a0], t_hi = A.itype[a1 - 1];
+    // tile blk of the species-aligned tiling: species t has ceil(count_t / NA) tiles of its own,
+    // so that no block runs the net twice for a boundary between species (the grid holds
+    // ceil(N / NA) + ntypes blocks, an upper bound; the surplus ones leave here)
+    int a0 = -1, ty = 0;
+    {
+        int tb = blk;
+        for (int t = 0; t < A.ntypes; ++t) {
+            const int lo = A.toff[t], nb = (A.toff[t + 1] - lo + NA - 1) / NA;
+            if (tb < nb) {
+                a0 = lo + tb * NA;
+                ty = t;
+                break;
+            }
+            tb -= nb;
+        }
+    }
+    if (a0 < 0) return;
+    const int t_lo = ty, t_hi = ty;
     const float* Tg = reinterpret_cast<const float*>(A.T);
     float* dTg = reinterpret_cast<float*>(A.dT);
     float* scr = reinterpret_cast<float*>(A.act) + (size_t)blk * NAT * XF_ACT;
@@ -165,30 +183,37 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A_)
 #pragma unroll
                 for (int a = 0; a < NAT; ++a) acc[i][a] = f4{0.f, 0.f, 0.f, 0.f};
         };
-        // First K-chunk weight fragments of the next 240-wide product, requested before the
-        // preceding epilogue and barrier so that their latency is hidden.
-        F8 Apf[TPW];
+        // Weight fragment of K-chunk c of the product at wb for the wave's tile i (a wave without a
+        // tile i reads its last valid tile again: every read is unconditional, since a read skipped
+        // by a branch makes the compiler wait for every read in flight).
+        auto wtile = [&](int i) { return min(wave + NW * i, 14); };
+        // The first PD K-chunks of the next 240-wide product, requested before the preceding
+        // epilogue and barrier so that their latency is hidden; each product step then requests
+        // the chunk PD ahead (a ring of PD register slots).
+        F8 Apf[PD][TPW];
         auto prefetch8 = [&](int wb) {
 #pragma unroll
-            for (int i = 0; i < TPW; ++i)
-                if (i < nown) Apf[i] = ld_wfrag<SPLIT>(wrs, lane16, wb + wave + NW * i);
+            for (int d = 0; d < PD; ++d)
+#pragma unroll
+                for (int i = 0; i < TPW; ++i) Apf[d][i] = ld_wfrag<SPLIT>(wrs, lane16, wb + d * 15 + wtile(i));
         };
         // acc[i][a] = sum over the 8 K-chunks of W(own tile i, c) B(c, a), B from s_b; Apf must
         // hold the first chunk of product wb (prefetch8)
         auto gemm8 = [&](int wb) {
             zero_acc();
-            F8 An[TPW];
+            F8 Rg[PD][TPW];
 #pragma unroll
-            for (int i = 0; i < TPW; ++i) An[i] = Apf[i];
+            for (int d = 0; d < PD; ++d)
+#pragma unroll
+                for (int i = 0; i < TPW; ++i) Rg[d][i] = Apf[d][i];
 #pragma unroll
             for (int c = 0; c < XF_NCH2; ++c) {
                 F8 Ac[TPW];
 #pragma unroll
-                for (int i = 0; i < TPW; ++i) Ac[i] = An[i];
-                if (c + 1 < XF_NCH2) {
+                for (int i = 0; i < TPW; ++i) Ac[i] = Rg[c % PD][i];
+                if (c + PD < XF_NCH2) {
 #pragma unroll
-                    for (int i = 0; i < TPW; ++i)
-                        if (i < nown) An[i] = ld_wfrag<SPLIT>(wrs, lane16, wb + (c + 1) * 15 + wave + NW * i);
+                    for (int i = 0; i < TPW; ++i) Rg[c % PD][i] = ld_wfrag<SPLIT>(wrs, lane16, wb + (c + PD) * 15 + wtile(i));
                 }
                 F8 B[NAT];
 #pragma unroll
@@ -248,9 +273,11 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A_)
         {
             zero_acc();
             const int wb = XF_W1F;
-            F8 An[TPW];
+            F8 R1[PD][TPW];
 #pragma unroll
-            for (int i = 0; i < TPW; ++i) An[i] = ld_wfrag<SPLIT>(wrs, lane16, wb + wave + NW * i);
+            for (int d = 0; d < PD; ++d)
+#pragma unroll
+                for (int i = 0; i < TPW; ++i) R1[d][i] = ld_wfrag<SPLIT>(wrs, lane16, wb + d * 15 + wtile(i));
             constexpr int NGRP = (XF_NCH1 + FX_G - 1) / FX_G;
             // One group of FX_G K-chunks. Reads retire in issue order, so the T rows of the D
             // fragment formed after a chunk's products are read before that chunk's weight
@@ -266,13 +293,13 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A_)
                     if (c < XF_NCH1) {
                         F8 Ac[TPW];
 #pragma unroll
-                        for (int i = 0; i < TPW; ++i) Ac[i] = An[i];
+                        for (int i = 0; i < TPW; ++i) Ac[i] = R1[cc % PD][i];
                         const int cn = c + FX_G;
                         f4 ta, tb;
                         trows(min(cn, XF_NCH1 - 1), ta, tb);
-                        const int c1 = min(c + 1, XF_NCH1 - 1);
+                        const int c1 = min(c + PD, XF_NCH1 - 1);
 #pragma unroll
-                        for (int i = 0; i < TPW; ++i) An[i] = ld_wfrag<SPLIT>(wrs, lane16, wb + c1 * 15 + wave + NW * i);
+                        for (int i = 0; i < TPW; ++i) R1[cc % PD][i] = ld_wfrag<SPLIT>(wrs, lane16, wb + c1 * 15 + wtile(i));
                         F8 B[NAT];
 #pragma unroll
                         for (int a = 0; a < NAT; ++a) B[a] = ld_frag<SPLIT>(sb(p * FX_G + cc, a), lane);
@@ -453,14 +480,26 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A_)
             auto wfrag = [&](int pass, int c, int j) {
                 return ld_wfrag<SPLIT>(wrs, lane16, wb + c * E2 + mw + 4 * (pass * MGD + j));
             };
-            F8 An[MGD];
+            // a ring of PD steps of weight fragments (a row tile past the last pass reads tile
+            // 0 of the pass again: unconditional reads)
+            constexpr int NSTEP = NPASS * XF_NCH2;
+            static_assert(NSTEP % PD == 0, "whole ring turns");
+            auto wstep = [&](int st, int j) {
+                const int pn = st / XF_NCH2, cn = st - pn * XF_NCH2;
+                return wfrag(pn, cn, j < min(MGD, NMT - pn * MGD) ? j : 0);
+            };
+            F8 RD[PD][MGD];
 #pragma unroll
-            for (int j = 0; j < MGD; ++j)
-                if (j < NMT) An[j] = wfrag(0, 0, j);
+            for (int d = 0; d < PD; ++d)
+#pragma unroll
+                for (int j = 0; j < MGD; ++j) RD[d][j] = wstep(d, j);
             f4 dd[MGD][NATD];
             f4 tmv[MGD][NATD];
 #pragma unroll 1
-            for (int step = 0; step < NPASS * XF_NCH2; ++step) {
+            for (int s0 = 0; s0 < NSTEP; s0 += PD)
+#pragma unroll
+            for (int dstep = 0; dstep < PD; ++dstep) {
+                const int step = s0 + dstep;
                 const int pass = step / XF_NCH2, c = step - pass * XF_NCH2;
                 const int nm = min(MGD, NMT - pass * MGD);
                 if (c == 0) {
@@ -476,13 +515,10 @@ __global__ void __launch_bounds__(64 * NW) k_fitx(FitArgs A_)
                 }
                 F8 Ac[MGD];
 #pragma unroll
-                for (int j = 0; j < MGD; ++j) Ac[j] = An[j];
-                if (step + 1 < NPASS * XF_NCH2) {
-                    const int pn = (step + 1) / XF_NCH2, cn = step + 1 - pn * XF_NCH2;
-                    const int nmn = min(MGD, NMT - pn * MGD);
+                for (int j = 0; j < MGD; ++j) Ac[j] = RD[dstep][j];
+                if (step + PD < NSTEP) {
 #pragma unroll
-                    for (int j = 0; j < MGD; ++j)
-                        if (j < nmn) An[j] = wfrag(pn, cn, j);
+                    for (int j = 0; j < MGD; ++j) RD[dstep][j] = wstep(step + PD, j);
                 }
                 F8 B[NATD];
 #pragma unroll
@@ -556,20 +592,31 @@ int fitx_tiles_per_block(int, int)
     return 4;
 }
 
+// Block shape: 64 atoms with a one-chunk weight lookahead when the frame fills the CUs; otherwise
+// 32 atoms per block (twice the blocks, so twice the CUs stream a frame's weights) and a ring of
+// FITX_PD chunks per wave, which the smaller accumulator set leaves registers for.
+template <int NAT, int PD>
+static void launch_fitx_shape(bool split, const FitArgs& a, hipStream_t s)
+{
+    constexpr int NW = 8;
+    const bool ens = a.nmodels > 1;
+    dim3 grid((a.natoms + 16 * NAT - 1) / (16 * NAT) + a.ntypes, ens ? a.nmodels : 1), block(64 * NW);
+    // ens: one launch for a model ensemble, blockIdx.y = model (a separate instantiation)
+    if (split) {
+        if (ens) hipLaunchKernelGGL((k_fitx<NAT, true, NW, true, PD>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_fitx<NAT, true, NW, false, PD>), grid, block, 0, s, a);
+    } else {
+        if (ens) hipLaunchKernelGGL((k_fitx<NAT, false, NW, true, PD>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_fitx<NAT, false, NW, false, PD>), grid, block, 0, s, a);
+    }
+}
+
 void launch_fitx(bool split, const FitArgs& a, hipStream_t s)
 {
     if (a.natoms <= 0) return;
-    constexpr int NAT = 4, NW = 8;
-    const bool ens = a.nmodels > 1;
-    dim3 grid((a.natoms + 16 * NAT - 1) / (16 * NAT), ens ? a.nmodels : 1), block(64 * NW);
-    // ens: one launch for a model ensemble, blockIdx.y = model (a separate instantiation)
-    if (split) {
-        if (ens) hipLaunchKernelGGL((k_fitx<NAT, true, NW, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_fitx<NAT, true, NW, false>), grid, block, 0, s, a);
-    } else {
-        if (ens) hipLaunchKernelGGL((k_fitx<NAT, false, NW, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_fitx<NAT, false, NW, false>), grid, block, 0, s, a);
-    }
+    const int64_t blocks64 = ((int64_t)a.natoms + 63) / 64 * (a.nmodels > 1 ? a.nmodels : 1);
+    if (blocks64 * 2 <= (a.ncu > 0 ? a.ncu : 256)) launch_fitx_shape<2, FITX_PD>(split, a, s);
+    else launch_fitx_shape<4, 1>(split, a, s);
 }
 
 }  // namespace dpk
