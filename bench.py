@@ -534,11 +534,11 @@ def main():
                                                                     max(1, args.warmup // 2), ("fp64", "mixed", "fp32"))
     training = None if args.no_train else training_bench(dpk, synth, max(2, args.steps // 4))
     # two operating points of the same server: the latency point (four slots, a budget of three
-    # of the largest frame's workspaces, which binds) and a throughput point (six slots, 24
-    # workspaces: batches of about seven frames)
+    # of the largest frame's workspaces, which binds) and a throughput point (four slots, 48
+    # workspaces: batches grow to the scheduler's 12,288-atom target)
     serving = None if args.no_serving else serving_bench(dpk, synth)
     if serving:
-        serving["throughput_point"] = serving_bench(dpk, synth, slots=6, budget_frames=24.0)
+        serving["throughput_point"] = serving_bench(dpk, synth, slots=4, budget_frames=48.0)
         for name, sv in (("serving", serving), ("serving (throughput point)", serving["throughput_point"])):
             print(f"# {name}: p50 {sv['p50_ms']:.3f} ms, p99 {sv['p99_ms']:.3f} ms at "
                   f"{sv['arrival_rate_req_per_s']:.0f} req/s; saturated {sv['saturated_atom_steps_per_s']:.4g} "

@@ -1773,7 +1773,7 @@ void release_ws(dpk_ctx* c)
 
 // A batch grows to at least BATCH_TARGET_ATOMS atoms when frames queue up; the pinned staging
 // reserved per slot holds such a batch plus one more frame of the largest batchable size.
-constexpr int64_t BATCH_TARGET_ATOMS = 4096;
+constexpr int64_t BATCH_TARGET_ATOMS = 12288;
 constexpr int64_t PIN_RESERVE_ATOMS = BATCH_TARGET_ATOMS + 8192;
 
 // Host-only context with the sizes of a slot's context, for workspace planning off the slots.
