@@ -317,9 +317,8 @@ typedef struct {
 
 /* Create an ensemble on `device` in `precision` (as dpk_ctx_create) from n_models models in
  * 1..DPK_MAX_MODELS, each packed and copied to the device (the models must outlive the ensemble).
- * DPK_E_INVALID_ARG for NULL pointers, a bad count, or models whose descriptions or tables differ
- * from model 0's; DPK_E_UNIMPLEMENTED for se_e3 models (the ensemble kernels cover the two-body
- * descriptors). */
+ * Every descriptor kind (se_e2_a, se_e2_r, se_e3), network or compressed. DPK_E_INVALID_ARG for
+ * NULL pointers, a bad count, or models whose descriptions or tables differ from model 0's. */
 int dpk_devi_create(const dpk_model *const *models, int n_models, int device, int precision,
                     dpk_devi **out);
 void dpk_devi_free(dpk_devi *d);

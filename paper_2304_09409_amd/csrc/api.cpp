@@ -1493,7 +1493,10 @@ void devi_enqueue(dpk_devi* d, int n, const GeomParams& gp, double nu, hipStream
     ea.natoms = n;
     ea.ntypes = nt;
     ea.nc = c->model->nc;
-    ea.type_one_side = c->model->desc.type_one_side;
+    // se_e3: pair nets indexed by the pair's types, N_c^-2, the environment rows staged once for
+    // every model (they depend on the geometry and the shared descriptor only)
+    const bool e3 = is_e3(c);
+    ea.type_one_side = e3 ? 0 : c->model->desc.type_one_side;
     ea.ncu = c->ncu;
     ea.apw = 1;
     for (int t = 0; t < nt; ++t) ea.off[t] = gp.off[t];
@@ -1503,7 +1506,8 @@ void devi_enqueue(dpk_devi* d, int n, const GeomParams& gp, double nu, hipStream
     ea.nl_r = c->nl_r;
     ea.rs = c->model->desc.rcut_smth;
     ea.rc = c->model->desc.rcut;
-    ea.inv_nc = 1.0 / c->model->nc;
+    ea.inv_nc = e3 ? 1.0 / ((double)c->model->nc * c->model->nc) : 1.0 / c->model->nc;
+    ea.env = c->env;
     ea.evec = d->evec;
     ea.emat = d->emat;
     ea.table = d->table;
@@ -1524,7 +1528,8 @@ void devi_enqueue(dpk_devi* d, int n, const GeomParams& gp, double nu, hipStream
     ea.ms_F = stF;
     ea.ms_Ei = stE;
     ea.ms_vir = d->st_vir;
-    launch_embed_fwd(c->precision, c->tab, ea, s);
+    if (e3) launch_e3_env(c->precision, ea, s);
+    launch_embed_fwd(c->precision, c->tab, ea, s, e3);
     FitArgs fa;
     std::memset(&fa, 0, sizeof(fa));
     fa.natoms = n;
@@ -1546,8 +1551,8 @@ void devi_enqueue(dpk_devi* d, int n, const GeomParams& gp, double nu, hipStream
     fa.ms_Ei = stE;
     fa.radial = c->model->desc.descriptor != DPK_SE_E2_A;
     launch_fit(c->precision, fa, s);
-    launch_embed_bwd(c->precision, c->tab, ea, s);
-    const int nb = embed_bwd_blocks(c->precision, c->tab, n, c->ncu);
+    launch_embed_bwd(c->precision, c->tab, ea, s, e3);
+    const int nb = embed_bwd_blocks(c->precision, c->tab, n, c->ncu, e3);
     for (int k = 0; k < nm; ++k)
         launch_finalize(nb, (const double*)((const char*)d->vir + k * d->st_vir), d->ev + 10 * k, d->ev + 10 * k + 1,
                         c->stats, s);
@@ -1572,8 +1577,6 @@ int dpk_devi_create(const dpk_model* const* models, int n_models, int device, in
             (models[k]->tabulated && (models[k]->tab_dx != models[0]->tab_dx || models[k]->tab_nint != models[0]->tab_nint)))
             return fail(DPK_E_INVALID_ARG, "model %d is compressed differently from model 0", k);
     }
-    if (models[0]->desc.descriptor == DPK_SE_E3)
-        return fail(DPK_E_UNIMPLEMENTED, "model deviation covers the two-body descriptors (se_e2_a, se_e2_r)");
     auto* d = new dpk_devi;
     d->nm = n_models;
     int rc = dpk_ctx_create(models[0], device, precision, 0, 0, &d->geo);

@@ -1635,9 +1635,10 @@ int fit_atoms_per_block(int) { return FIT_AF; }
 // for the FP64 network variant from its implicit instantiation alone.
 template __global__ void k_embed_bwd<PF64, false, false, true>(EmbArgs);
 template __global__ void k_embed_bwd<PF64, true, false, true>(EmbArgs);
+template __global__ void k_embed_bwd<PF64, false, true, true>(EmbArgs);
+template __global__ void k_embed_bwd<PF64, true, true, true>(EmbArgs);
 
-// e3: the three-body descriptor's pair passes (a single model; an ensemble of three-body models
-// is refused by the host). The table runs here only for the three-body descriptor (the two-body
+// e3: the three-body descriptor's pair passes (also for a model ensemble, blockIdx.y = model). The table runs here only for the three-body descriptor (the two-body
 // descriptors' table has the product kernels of kernels_tab.hip).
 template <class P, bool FWD, bool TAB>
 static void launch_embed_shape(const EmbArgs& a0, bool e3, hipStream_t s)
@@ -1649,13 +1650,15 @@ static void launch_embed_shape(const EmbArgs& a0, bool e3, hipStream_t s)
     const bool ens = a.nmodels > 1;
     const dim3 grid((a.natoms + apb - 1) / apb, ens ? a.nmodels : 1), block(Cfg::NW * 64);
     if constexpr (FWD) {
-        if (e3) hipLaunchKernelGGL((k_embed_fwd<P, TAB, false, true>), grid, block, 0, s, a);
+        if (e3 && ens) hipLaunchKernelGGL((k_embed_fwd<P, TAB, true, true>), grid, block, 0, s, a);
+        else if (e3) hipLaunchKernelGGL((k_embed_fwd<P, TAB, false, true>), grid, block, 0, s, a);
         else if constexpr (!TAB) {
             if (ens) hipLaunchKernelGGL((k_embed_fwd<P, TAB, true, false>), grid, block, 0, s, a);
             else hipLaunchKernelGGL((k_embed_fwd<P, TAB, false, false>), grid, block, 0, s, a);
         }
     } else {
-        if (e3) hipLaunchKernelGGL((k_embed_bwd<P, TAB, false, true>), grid, block, 0, s, a);
+        if (e3 && ens) hipLaunchKernelGGL((k_embed_bwd<P, TAB, true, true>), grid, block, 0, s, a);
+        else if (e3) hipLaunchKernelGGL((k_embed_bwd<P, TAB, false, true>), grid, block, 0, s, a);
         else if constexpr (!TAB) {
             if (ens) hipLaunchKernelGGL((k_embed_bwd<P, TAB, true, false>), grid, block, 0, s, a);
             else hipLaunchKernelGGL((k_embed_bwd<P, TAB, false, false>), grid, block, 0, s, a);

@@ -232,12 +232,27 @@ def test_se_e2_r_deviation(precision):
     dv.close()
 
 
-def test_se_e3_deviation_is_refused():
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_se_e3_deviation(precision):
+    """Model deviation (Sec. II.C) of an se_e3 ensemble (the pair walk on the ensemble axis): every
+    member's forces and eps_F against the oracle's members."""
+    from oracle import Oracle
+    from oracle.devi import ensemble
     from paper_2304_09409_amd import dpk
-    m = model_of("se_e3")
-    with pytest.raises(dpk.DpkError) as e:
-        dpk.Deviation([m, m], precision="fp64")
-    assert e.value.code == dpk.DPK_E_UNIMPLEMENTED
+    spec, params = SPECS["se_e3"]
+    ps = synth.ensemble_params(spec, params(), 3)
+    c, t, b = synth.serving_frame(700, 9, 2)
+    say(f"se_e3 devi {precision}")
+    ref = ensemble([Oracle(spec, p) for p in ps], c, t, b)
+    dv = dpk.Deviation([dpk.Model(spec, p) for p in ps], precision=precision)
+    got = dv.compute(c, t, b)
+    tol = 1e-10 if precision == "fp64" else 1e-3
+    df = np.abs(got["force"] - ref["force"]).max()
+    de = np.abs(got["eps_f"] - ref["eps_f"]).max()
+    print(f"  max|dF| {df:.3e}  max|d eps_F| {de:.3e}", flush=True)
+    assert df <= tol
+    assert de <= tol
+    dv.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
