@@ -53,9 +53,48 @@ template <> struct TabPol<double> {
 
 constexpr int TGA = 4;            // centre atoms per group (16 product columns)
 constexpr int TNW = 4;            // waves per block
-constexpr int TGPW_MAX = 4;       // groups per wave at most
+// groups per wave at most: one (blocks of 16 atoms) balanced the fcc box's 2,000 blocks best, in
+// both passes, also with the backward's force hash
+#ifndef TAB_GPW_MAX
+#define TAB_GPW_MAX 1
+#endif
+constexpr int TGPW_MAX = TAB_GPW_MAX;
 constexpr int TPS = 6 * 16 + 4;   // LDS stride of one interval's six moment rows (16-B aligned;
                                   // consecutive intervals start 36 banks apart)
+
+// Neighbour forces of a backward block are summed in LDS before they reach the force array: an
+// open-addressing hash on the neighbour's caller index (2^TAB_HLOG slots, linear probing over at
+// most TAB_PROBE slots; a neighbour that finds no slot adds to the force array directly). The atoms
+// of a block are consecutive, so where the caller's order is spatial (as an MD code keeps it) their
+// neighbour lists overlap and the block flushes each distinct neighbour once.
+#ifndef TAB_HLOG
+#define TAB_HLOG 10
+#endif
+#ifndef TAB_PROBE
+#define TAB_PROBE 4
+#endif
+constexpr int TH = TAB_HLOG > 0 ? 1 << TAB_HLOG : 1;
+
+__device__ __forceinline__ bool tab_hash_add(int* hk, double (*hf)[TH], int j, double fx, double fy, double fz)
+{
+    if (TAB_HLOG == 0) return false;
+    unsigned h = ((unsigned)j * 2654435761u) >> (32 - (TAB_HLOG > 0 ? TAB_HLOG : 1));
+#pragma unroll
+    for (int p = 0; p < TAB_PROBE; ++p) {
+        // a key once stored stays, so a plain read settles most lookups; an empty slot is claimed
+        // by compare-and-swap (which returns the key that won if another lane came first)
+        int old = __hip_atomic_load(&hk[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old == -1) old = atomicCAS(&hk[h], -1, j);
+        if (old == -1 || old == j) {
+            unsafeAtomicAdd(&hf[0][h], fx);
+            unsafeAtomicAdd(&hf[1][h], fy);
+            unsafeAtomicAdd(&hf[2][h], fz);
+            return true;
+        }
+        h = (h + 1) & (TH - 1);
+    }
+    return false;
+}
 
 // Geometry of one kept neighbour: r_ij, 1/r, s(r) and ds/dr (eq. switch), and the table interval
 // of s (clamped to the table; inputs past it use the end pieces extrapolated).
@@ -357,9 +396,18 @@ __global__ void __launch_bounds__(TNW * 64) k_tab_bwd(EmbArgs A_)
     static_assert(ROWS % 16 == 0, "whole 16-row tiles of W per window");
     __shared__ __attribute__((aligned(16))) T s_W[TNW][TGA][ROWS][4];
     __shared__ double s_vir[TNW][9];
+    __shared__ int s_hk[TH];
+    __shared__ double s_hf[3][TH];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
     const double inv_w = 1.0 / (A.rc - A.rs), inc = A.inv_nc;
+    if (TAB_HLOG > 0) {
+        for (int i = threadIdx.x; i < TH; i += TNW * 64) {
+            s_hk[i] = -1;
+            s_hf[0][i] = s_hf[1][i] = s_hf[2][i] = 0.0;
+        }
+        __syncthreads();
+    }
     const int nt = A.ntypes, kp = tab_kp(A.tab_nint);
     const bool tos = A.type_one_side;
     const int nets = tos ? nt : nt * nt;
@@ -493,9 +541,11 @@ __global__ void __launch_bounds__(TNW * 64) k_tab_bwd(EmbArgs A_)
                                 const double rad = (d0 + dEds) * o.ds + p * (o.ds - sr);
                                 const double gx = rad * ux + sr * d1, gy = rad * uy + sr * d2, gz = rad * uz + sr * d3;
                                 asm volatile("" ::"v"(px), "v"(py), "v"(pz), "v"(pj));
-                                unsafeAtomicAdd(&A.F[3 * (size_t)jn], -gx);
-                                unsafeAtomicAdd(&A.F[3 * (size_t)jn + 1], -gy);
-                                unsafeAtomicAdd(&A.F[3 * (size_t)jn + 2], -gz);
+                                if (!tab_hash_add(s_hk, s_hf, jn, -gx, -gy, -gz)) {
+                                    unsafeAtomicAdd(&A.F[3 * (size_t)jn], -gx);
+                                    unsafeAtomicAdd(&A.F[3 * (size_t)jn + 1], -gy);
+                                    unsafeAtomicAdd(&A.F[3 * (size_t)jn + 2], -gz);
+                                }
                                 fc[a][0] += gx;
                                 fc[a][1] += gy;
                                 fc[a][2] += gz;
@@ -540,6 +590,17 @@ __global__ void __launch_bounds__(TNW * 64) k_tab_bwd(EmbArgs A_)
         if (lane == 0) s_vir[wave][k] = v;
     }
     __syncthreads();
+    // the block's summed neighbour forces, once per distinct neighbour
+    if (TAB_HLOG > 0) {
+        for (int i = threadIdx.x; i < TH; i += TNW * 64) {
+            const int j = s_hk[i];
+            if (j >= 0) {
+                unsafeAtomicAdd(&A.F[3 * (size_t)j], s_hf[0][i]);
+                unsafeAtomicAdd(&A.F[3 * (size_t)j + 1], s_hf[1][i]);
+                unsafeAtomicAdd(&A.F[3 * (size_t)j + 2], s_hf[2][i]);
+            }
+        }
+    }
     double* part = A.vir_part + 10 * (size_t)blockIdx.x;
     if (threadIdx.x < 9) {
         double v = 0.0;
