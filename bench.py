@@ -139,12 +139,13 @@ def stored_traffic(stage: str, precision: str):
     return None
 
 
-def serving_bench(dpk, synth, n_sims=16, steps=16, slots=4, load=0.7, seed=2023, budget_frames=3.0):
+def serving_bench(dpk, synth, n_sims=16, steps=64, slots=4, load=0.7, seed=2023, budget_frames=3.0):
     """Requests from n_sims concurrent simulations (sizes log-uniform in [50, 3000], 2-type 1:2 or
     3-type 2:1:1 frames at 0.1 atoms/A^3; consecutive frames of a simulation are small random
-    displacements), round-robin over the simulations. First all requests at once (saturated
-    throughput X, median of three passes), then Poisson arrivals at load * X / mean size;
-    latency = completion - arrival.
+    displacements), round-robin over the simulations. After one untimed pass of all requests (the
+    server's steady state: every slot's workspace has grown to the batches it serves), all requests
+    at once (saturated throughput X, median of three passes), then Poisson arrivals at
+    load * X / mean size; latency = completion - arrival.
     HBM budget: the model plus budget_frames times the workspace of the largest frame (admission
     limits batch sizes to what that holds). Python's garbage collector is paused during the timed
     loops: its pauses (tens of ms with torch loaded) belong to this client, not to the server."""
@@ -166,8 +167,8 @@ def serving_bench(dpk, synth, n_sims=16, steps=16, slots=4, load=0.7, seed=2023,
     budget = int(model_bytes + budget_frames * big)
     total_atoms = sum(len(r[1]) for r in reqs)
     srv = dpk.Server(model, precision="mixed", nslots=slots, budget_bytes=budget)
-    # warm-up: one frame per simulation
-    for tk in [srv.submit(c, t, b, simulation=sid) for sid, (c, t, b) in enumerate(sims)]:
+    # warm-up: one pass of every request (a workspace that grows waits for the device)
+    for tk in [srv.submit(c, t, b, simulation=sid) for c, t, b, sid in reqs]:
         tk.result()
     gc.collect()
     gc.disable()

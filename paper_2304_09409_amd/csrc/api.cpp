@@ -11,6 +11,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -238,6 +239,52 @@ struct Planes {
     }
 };
 
+// The HBM of a server under a budget: one device allocation of the budget less the model, made
+// when the server is created, from which the slots' workspaces are carved (first fit over 256-B
+// granules, free neighbours merged). Only the scheduler thread carves and releases, so a slot's
+// workspace changes size without a device allocation or free (hipFree waits for the whole device,
+// every slot's work included).
+struct Arena {
+    char* base = nullptr;
+    int64_t size = 0;
+    std::map<int64_t, int64_t> holes;   // offset -> length: disjoint, never adjacent
+    void reset(char* b, int64_t n) {
+        base = b;
+        size = n;
+        holes.clear();
+        if (n > 0) holes[0] = n;
+    }
+    bool owns(const void* p) const { return base && (const char*)p >= base && (const char*)p < base + size; }
+    // offset of a carved range of at least `bytes`, or -1 if no hole holds it
+    int64_t carve(int64_t bytes) {
+        bytes = (bytes + 255) & ~(int64_t)255;
+        for (auto it = holes.begin(); it != holes.end(); ++it) {
+            if (it->second < bytes) continue;
+            const int64_t off = it->first, rest = it->second - bytes;
+            holes.erase(it);
+            if (rest > 0) holes[off + bytes] = rest;
+            return off;
+        }
+        return -1;
+    }
+    void give_back(int64_t off, int64_t bytes) {
+        bytes = (bytes + 255) & ~(int64_t)255;
+        auto next = holes.lower_bound(off);
+        if (next != holes.end() && off + bytes == next->first) {
+            bytes += next->second;
+            next = holes.erase(next);
+        }
+        if (next != holes.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += bytes;
+                return;
+            }
+        }
+        holes[off] = bytes;
+    }
+};
+
 }  // namespace
 
 struct dpk_ctx {
@@ -265,6 +312,7 @@ struct dpk_ctx {
     // workspace
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    Arena* arena = nullptr;              // server slot under a budget: the workspace is carved from it
     int64_t cap_atoms = 0;
     int64_t cap_cells = 0;
     bool cells_clear = false;            // cell_count is all zero (the multi-block preparation keeps it so)
@@ -282,6 +330,8 @@ struct dpk_ctx {
     FrameDesc* fd;                       // batched frames: [BATCH_MAX_FRAMES]
     GeomParams* gps;                     // batched frames: [BATCH_MAX_FRAMES]
     void* pin_desc = nullptr;            // pinned staging of fd and gps
+    hipEvent_t desc_copied = nullptr;    // recorded after the last copy out of pin_desc
+    bool desc_pending = false;
     void *T, *dT, *act;
     void* env;                           // three-body descriptor: environment rows [N][nc][4]
     DevStats* stats;
@@ -394,7 +444,17 @@ inline void prof_mark(std::vector<hipEvent_t>* ev, int k, hipStream_t s)
     if (ev) hipEventRecord((*ev)[k], s);
 }
 
-int ensure_ws(dpk_ctx* c, int64_t n, int64_t ncell)
+// The workspace's memory goes back where it came from: the server's arena, or the device.
+void free_ws_mem(dpk_ctx* c)
+{
+    if (c->arena && c->arena->owns(c->ws)) c->arena->give_back((char*)c->ws - c->arena->base, (int64_t)c->ws_bytes);
+    else hipFree(c->ws);
+    c->ws = nullptr;
+}
+
+// arena_only (a server slot's admission): carve from the arena or report DPK_E_BUDGET, without
+// falling back to a device allocation
+int ensure_ws(dpk_ctx* c, int64_t n, int64_t ncell, bool arena_only = false)
 {
     if (n <= c->cap_atoms && ncell <= c->cap_cells && c->ws) {
         if (c->views_scratch) {
@@ -413,11 +473,19 @@ int ensure_ws(dpk_ctx* c, int64_t n, int64_t ncell)
         // the old buffers may still be used by work queued on this context's streams
         if (c->last_stream) HIPCHK(hipStreamSynchronize(c->last_stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(hipFree(c->ws));
-        c->ws = nullptr;
+        free_ws_mem(c);
     }
     void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    const int64_t off = c->arena ? c->arena->carve((int64_t)bytes) : -1;
+    if (off >= 0) {
+        p = c->arena->base + off;
+    } else if (arena_only) {
+        c->ws_bytes = 0;
+        c->cap_atoms = c->cap_cells = 0;
+        return DPK_E_BUDGET;
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        // (a slot's admission carves its workspace from the arena beforehand; only a launch that
+        // needs more than was admitted comes here)
         hipGetLastError();
         return fail(DPK_E_OOM, "hipMalloc of %zu workspace bytes failed", bytes);
     }
@@ -846,6 +914,12 @@ int ensure_pin_desc(dpk_ctx* c)
         c->pin_desc = nullptr;
         return fail(DPK_E_OOM, "pinned staging of the batch descriptors failed");
     }
+    if (hipEventCreateWithFlags(&c->desc_copied, hipEventDisableTiming) != hipSuccess) {
+        hipHostFree(c->pin_desc);
+        c->pin_desc = nullptr;
+        c->desc_copied = nullptr;
+        return fail(DPK_E_DEVICE, "event for the batch descriptors' staging failed");
+    }
     return DPK_OK;
 }
 
@@ -861,14 +935,18 @@ int compute_batch(dpk_ctx* c, int nf, const BatchFrame* fr, const double* d_coor
     if ((rc = batch_plan(c, nf, fr, gps, fd, &n, &ncells, &ms, &mc, &outd))) return rc;
     if ((rc = ensure_ws(c, n, ncells))) return rc;
     if ((rc = ensure_pin_desc(c))) return rc;
-    // the previous use of the staging has completed: this context's last frame is done
-    if (c->last_stream) HIPCHK(hipStreamSynchronize(c->last_stream));
+    // the staging is rewritten once the previous batch's copies out of it have completed (an
+    // event on exactly those copies: a wait on the stream would also wait for the coordinates
+    // just queued on it)
+    if (c->desc_pending) HIPCHK(hipEventSynchronize(c->desc_copied));
     FrameDesc* pfd = (FrameDesc*)c->pin_desc;
     GeomParams* pgp = (GeomParams*)(pfd + BATCH_MAX_FRAMES);
     std::memcpy(pfd, fd, sizeof(FrameDesc) * nf);
     std::memcpy(pgp, gps, sizeof(GeomParams) * nf);
     HIPCHK(hipMemcpyAsync(c->fd, pfd, sizeof(FrameDesc) * nf, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(c->gps, pgp, sizeof(GeomParams) * nf, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(c->desc_copied, s));
+    c->desc_pending = true;
     const int nt = c->model->desc.ntypes;
     launch_batch_prep(nf, nt, d_coord, d_atype, c->gps, c->fd, c->tcount, c->toff, c->perm, c->inv_perm, c->itype,
                       c->frame_of, c->stats, c->pos, c->cell_of, c->cell_start, c->cand, c->F, c->vir_atom, s);
@@ -1030,9 +1108,10 @@ void dpk_ctx_free(dpk_ctx* c)
     if (c->owns_model) {
         hipFree(c->evec); hipFree(c->emat); hipFree(c->fvec); hipFree(c->fmat); hipFree(c->table);
     }
-    hipFree(c->ws);
+    if (c->ws) free_ws_mem(c);
     hipFree(c->ext_buf);
     hipHostFree(c->pin_desc);
+    if (c->desc_copied) hipEventDestroy(c->desc_copied);
     for (auto& set : c->prof_events)
         for (auto e : set) hipEventDestroy(e);
     if (c->stream) hipStreamDestroy(c->stream);
@@ -1767,8 +1846,7 @@ void release_ws(dpk_ctx* c)
     if (!c->ws) return;
     if (c->last_stream) hipStreamSynchronize(c->last_stream);
     hipStreamSynchronize(c->stream);
-    hipFree(c->ws);
-    c->ws = nullptr;
+    free_ws_mem(c);
     c->ws_bytes = 0;
     c->cap_atoms = 0;
     c->cap_cells = 0;
@@ -1832,6 +1910,7 @@ struct dpk_server {
     dpk_server_counters st{};
     int64_t model_bytes = 0;
     dpk_ctx plan;                      // host-only context for workspace sizing (never launched on)
+    Arena arena;                       // under a budget: the slots' workspaces
 };
 
 namespace {
@@ -2091,6 +2170,20 @@ void scheduler(dpk_server* s)
                     if (s->budget && grown > std::max((int64_t)sl.ctx->ws_bytes, need)) release_ws(sl.ctx);
                     else sl.expect = grown;
                 }
+                // under a budget the workspace is carved now (the slot is idle). The budget's
+                // arithmetic admitted it, but the arena's holes may be split: the idle slots'
+                // workspaces are released (their holes merge) and the carve tried once more. What
+                // still splits the arena then are busy slots, and the batch waits at the head of
+                // the queue for one of them to finish (with every slot idle the arena is one hole).
+                if (s->arena.base && ensure_ws(sl.ctx, batch_atoms, batch_cells, true) != DPK_OK) {
+                    for (int k = 0; k < ns; ++k)
+                        if (!busy[k] && k != slot) release_ws(s->slots[k].ctx);
+                    if (ensure_ws(sl.ctx, batch_atoms, batch_cells, true) != DPK_OK) {
+                        s->queue.insert(s->queue.begin(), batch.begin(), batch.end());
+                        s->st.budget_waits++;
+                        break;
+                    }
+                }
                 // reserve the slot; its workspace grows to the batch's during the launch
                 const int64_t sim = r->f.simulation;
                 if (sl.sim >= 0 && sl.sim == sim) s->st.slot_reuse++;
@@ -2235,6 +2328,18 @@ int dpk_server_create(const dpk_model* m, int device, int precision, int nslots,
         dpk_server_free(s);
         return fail(DPK_E_BUDGET, "model alone exceeds the server budget");
     }
+    if (s->budget) {
+        // whole 256-B granules, as the arena carves them
+        const int64_t bytes = (s->budget - s->model_bytes + 255) & ~(int64_t)255;
+        void* p = nullptr;
+        if (bytes > 0 && hipMalloc(&p, (size_t)bytes) != hipSuccess) {
+            hipGetLastError();
+            dpk_server_free(s);
+            return fail(DPK_E_OOM, "hipMalloc of the server's %lld workspace bytes failed", (long long)bytes);
+        }
+        s->arena.reset((char*)p, bytes);
+        for (auto& sl : s->slots) sl.ctx->arena = &s->arena;
+    }
     s->th = std::thread(scheduler, s);
     *out = s;
     return DPK_OK;
@@ -2342,6 +2447,7 @@ void dpk_server_free(dpk_server* s)
     // slots past the first share its model buffers: free them first
     for (size_t k = s->slots.size(); k-- > 0;)
         if (s->slots[k].ctx) dpk_ctx_free(s->slots[k].ctx);
+    if (s->arena.base) hipFree(s->arena.base);
     delete s;
 }
 
