@@ -49,12 +49,15 @@ CONTRACT_FWD, CONTRACT_BWD, ENV_PAIR = 800.0, 1600.0, 50.0
 FIT_ATOM = 2036160.0
 
 # FP32 vector work per pair of the BF16-path network kernels (activations, derivatives, the
-# contractions, the chain rule; tanh counted as 6 flop), a second view beside the matrix roofline:
-#   forward: layer 1 25 x (2 + 6 + 1) + layer 2 50 x (1 + 6 + 2) + layer 3 100 x (1 + 6 + 2 + 8)
-#            = 2,375 flop
-#   adjoint: layer 1 25 x (2 + 6 + 1 + 4) + layer 2 50 x (1 + 6 + 2 + 5)
-#            + layer 3 100 x (1 + 6 + 2 + 5 + 8 + 8) + chain rule ~50 = 4,075 flop
-VALU_FLOP_PER_PAIR = {"embed_fwd": 2375.0, "embed_bwd": 4075.0}
+# contractions, the chain rule), a second view beside the matrix roofline, in FMA-equivalent flop
+# (2 per issue slot). A tanh counts 10.5: calib/valu_rates.hip measures v_exp_f32 and v_rcp_f32 at
+# about 1.8 FMA issue slots each on this device, not overlapped with FMA issue, and the whole
+# tanh at 5.3 slots (profiles/valu_rates.md).
+#   forward: layer 1 25 x (2 + 10.5 + 1) + layer 2 50 x (1 + 10.5 + 2) + layer 3 100 x (1 + 10.5 + 2 + 8)
+#            = 3,162.5 flop
+#   adjoint: layer 1 25 x (2 + 10.5 + 1 + 4) + layer 2 50 x (1 + 10.5 + 2 + 5)
+#            + layer 3 100 x (1 + 10.5 + 2 + 5 + 8 + 8) + chain rule ~50 = 4,862.5 flop
+VALU_FLOP_PER_PAIR = {"embed_fwd": 3162.5, "embed_bwd": 4862.5}
 
 # End-to-end ceilings (atom-steps/s) of each workload and mode: the binding unit's time per
 # atom-step from the algorithmic work above.
@@ -227,7 +230,9 @@ def _serving_timed(srv, sims, reqs, rng, load, slots, budget, n_sims):
 
 def time_frame(dpk, torch, model, prec, c, t, b, steps, warmup, median_of=0):
     """Device-resident timing of one frame: warm-up, then `steps` evaluations back to back (mean
-    ms/step) with the stage profiler on; with median_of > 0 also that many single synchronised
+    ms/step; no events between the stages), then as many again with the stage profiler on (its
+    events between the stages cost a few microseconds each: the stage times and the kernel
+    rooflines come from this second loop); with median_of > 0 also that many single synchronised
     evaluations (median ms). Returns the result dict and the context (caller closes it)."""
     n = len(t)
     dev = torch.device("cuda:0")
@@ -241,12 +246,15 @@ def time_frame(dpk, torch, model, prec, c, t, b, steps, warmup, median_of=0):
         ctx.compute_device(coord, atype, b, energy, force, virial)
     ctx.check()
     torch.cuda.synchronize()
-    ctx.profile(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         ctx.compute_device(coord, atype, b, energy, force, virial)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ctx.profile(True)
+    for _ in range(steps):
+        ctx.compute_device(coord, atype, b, energy, force, virial)
+    torch.cuda.synchronize()
     stage_ms, nframes = ctx.profile_read()
     ctx.profile(False)
     ctx.check()

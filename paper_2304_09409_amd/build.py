@@ -53,6 +53,12 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    # the vector-ALU calibration program (a standalone executable; not part of the library)
+    probe = os.path.join(HERE, "calib", "valu_rates.hip")
+    cmd = [HIPCC] + COMMON + [probe, "-o", os.path.join(OUT, "valu_rates")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for calib/valu_rates.hip:\n{r.stderr}")
     if verbose:
         print("built", LIB)
     return LIB
