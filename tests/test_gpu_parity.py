@@ -273,6 +273,31 @@ def test_tabulated_fcc_32000(dpk, precision):
     ctx.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tabulated_fcc_32000_shuffled(dpk, precision):
+    """The same box with the caller's atoms in a random order: the table backward's per-block
+    force hash then finds few repeated neighbours, fills, and sends most pairs to the direct FP64
+    atomics. Every output against the oracle's (forces permuted with the atoms)."""
+    say(f"table {precision} fcc32000 shuffled")
+    spec, params = synth.FCC_MODEL, synth.fcc_params()
+    c, t, b = synth.fcc_32000()
+    if not _fcc32k:
+        o = oracle_of("fcc")
+        _fcc32k["ref"] = o.compute(c, t, b, table=o.table(0.01, 50), dx=0.01)
+        _fcc32k["model"] = dpk.Model(spec, params).tabulate(0.01, 0.5)
+    ref = dict(_fcc32k["ref"])
+    perm = np.random.default_rng(5).permutation(len(t))
+    ref["force"] = ref["force"][perm]
+    ctx = dpk.Context(_fcc32k["model"], precision=precision)
+    got = ctx.compute(c[perm], t[perm], b)
+    if precision == "fp64":
+        check_fp64(got, ref, len(t))
+    else:
+        check_mixed(got, ref, len(t))
+    assert ctx.stats()["table_out_of_range"] == 0
+    ctx.close()
+
+
 def test_context_keeps_the_model_it_was_created_with(dpk):
     """A context evaluates the model as it was when the context was created: tabulating the model
     afterwards (here a table that covers s < 0.1 only, so that its use shows in the out-of-range
