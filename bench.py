@@ -142,6 +142,9 @@ def stored_traffic(stage: str, precision: str):
     return None
 
 
+FIXED_RATES = (2000, 4000, 6000)   # requests/s
+
+
 def serving_bench(dpk, synth, n_sims=16, steps=64, slots=4, load=0.7, seed=2023, budget_frames=3.0):
     """Requests from n_sims concurrent simulations (sizes log-uniform in [50, 3000], 2-type 1:2 or
     3-type 2:1:1 frames at 0.1 atoms/A^3; consecutive frames of a simulation are small random
@@ -214,6 +217,26 @@ def _serving_timed(srv, sims, reqs, rng, load, slots, budget, n_sims):
         lat.append((done - due) * 1e-6)
         last = max(last, done)
     st = srv.stats()
+    # latency against fixed Poisson arrival rates (the saturated rate X above is measured with
+    # every request queued, i.e. the largest batches; Poisson arrivals batch less)
+    fixed = {}
+    for rate in FIXED_RATES:
+        arr = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
+        t_start = time.monotonic_ns() + 2_000_000
+        tks, dues = [], []
+        for (c, t, b, sid), a in zip(reqs, arr):
+            due = t_start + int(a * 1e9)
+            while time.monotonic_ns() < due:
+                pass
+            tks.append(srv.submit(c, t, b, simulation=sid))
+            dues.append(due)
+        lf = []
+        for tk, due in zip(tks, dues):
+            tk.result()
+            lf.append((int(srv.times(tk)[2]) - due) * 1e-6)
+        lf = np.array(lf)
+        fixed[str(rate)] = {"p50_ms": float(np.percentile(lf, 50)), "p90_ms": float(np.percentile(lf, 90)),
+                            "p99_ms": float(np.percentile(lf, 99))}
     srv.close()
     lat = np.array(lat)
     batch_sat = (s1["completed"] - s0["completed"]) / max(1, s1["launches"] - s0["launches"])
@@ -224,7 +247,7 @@ def _serving_timed(srv, sims, reqs, rng, load, slots, budget, n_sims):
             "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
             "throughput_atom_steps_per_s": total_atoms / ((last - start) * 1e-9),
             "peak_bytes": st["peak_bytes"], "budget_waits": st["budget_waits"],
-            "slot_reuse": st["slot_reuse"], "mean_batch_saturated": batch_sat,
+            "slot_reuse": st["slot_reuse"], "fixed_rate_latency": fixed, "mean_batch_saturated": batch_sat,
             "mean_batch_poisson": batch_poisson, "precision": "mixed"}
 
 
@@ -552,7 +575,9 @@ def main():
             print(f"# {name}: p50 {sv['p50_ms']:.3f} ms, p99 {sv['p99_ms']:.3f} ms at "
                   f"{sv['arrival_rate_req_per_s']:.0f} req/s; saturated {sv['saturated_atom_steps_per_s']:.4g} "
                   f"atom-steps/s; mean batch {sv['mean_batch_saturated']:.1f} (saturated), "
-                  f"{sv['mean_batch_poisson']:.1f} (Poisson), budget waits {sv['budget_waits']}",
+                  f"{sv['mean_batch_poisson']:.1f} (Poisson), budget waits {sv['budget_waits']}; fixed rates: "
+                  + ", ".join(f"{k} req/s p50 {v['p50_ms']:.3f} p99 {v['p99_ms']:.3f} ms"
+                              for k, v in sv["fixed_rate_latency"].items()),
                   file=sys.stderr, flush=True)
 
     cpu, errs = None, {}

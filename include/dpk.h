@@ -364,7 +364,7 @@ typedef struct {
 typedef struct {
     int64_t submitted, completed, failed;
     int64_t peak_bytes;        /* largest device footprint (model + slot workspaces) reached     */
-    int64_t budget_waits;      /* admissions delayed because the budget was full                  */
+    int64_t budget_waits;      /* frames whose admission waited for the budget (each counted once) */
     int64_t slot_reuse;        /* batches that ran on the slot of their simulation's previous frame */
     int64_t launches;          /* batches launched (frames completed / launches = mean batch size) */
 } dpk_server_counters;

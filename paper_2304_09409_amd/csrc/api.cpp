@@ -5,6 +5,7 @@
 //   types -> cell list -> neighbour list -> embedding + contraction (T) -> fitting (E_i, dE/dT)
 //   -> adjoint (F, virial) -> reductions.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <atomic>
@@ -24,6 +25,7 @@
 #include <vector>
 
 #include "../../include/dpk.h"
+#include "arena.h"
 #include "dpk_internal.h"
 #include "dpk_launch.h"
 #include "dpk_train.h"
@@ -236,52 +238,6 @@ struct Planes {
         const uint16_t hb = bf16_bits((float)v);
         h[i] = hb;
         if (precision == DPK_MIXED) l[i] = bf16_bits((float)(v - (double)bf16_float(hb)));
-    }
-};
-
-// The HBM of a server under a budget: one device allocation of the budget less the model, made
-// when the server is created, from which the slots' workspaces are carved (first fit over 256-B
-// granules, free neighbours merged). Only the scheduler thread carves and releases, so a slot's
-// workspace changes size without a device allocation or free (hipFree waits for the whole device,
-// every slot's work included).
-struct Arena {
-    char* base = nullptr;
-    int64_t size = 0;
-    std::map<int64_t, int64_t> holes;   // offset -> length: disjoint, never adjacent
-    void reset(char* b, int64_t n) {
-        base = b;
-        size = n;
-        holes.clear();
-        if (n > 0) holes[0] = n;
-    }
-    bool owns(const void* p) const { return base && (const char*)p >= base && (const char*)p < base + size; }
-    // offset of a carved range of at least `bytes`, or -1 if no hole holds it
-    int64_t carve(int64_t bytes) {
-        bytes = (bytes + 255) & ~(int64_t)255;
-        for (auto it = holes.begin(); it != holes.end(); ++it) {
-            if (it->second < bytes) continue;
-            const int64_t off = it->first, rest = it->second - bytes;
-            holes.erase(it);
-            if (rest > 0) holes[off + bytes] = rest;
-            return off;
-        }
-        return -1;
-    }
-    void give_back(int64_t off, int64_t bytes) {
-        bytes = (bytes + 255) & ~(int64_t)255;
-        auto next = holes.lower_bound(off);
-        if (next != holes.end() && off + bytes == next->first) {
-            bytes += next->second;
-            next = holes.erase(next);
-        }
-        if (next != holes.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                prev->second += bytes;
-                return;
-            }
-        }
-        holes[off] = bytes;
     }
 };
 
@@ -1822,6 +1778,7 @@ struct Request {
     int64_t out_off = 0;       // first double of its outputs in the slot's output staging
     bool solo = false;         // run alone (after its batch reported a data error)
     bool big_cap = false;      // largest candidate buffer (after overflowing the estimated one)
+    bool waited = false;       // counted once in budget_waits
     int state = 0;             // 0 queued, 1 running, 2 done
     int result = 0;
     std::string err;
@@ -1902,6 +1859,7 @@ struct dpk_server {
     std::vector<Slot> slots;
     std::mutex mu;
     std::condition_variable cv;
+    std::condition_variable wake;      // the scheduler's: a frame was queued, or the server stops
     std::deque<Request*> queue;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
     uint64_t next_ticket = 1;
@@ -2035,6 +1993,9 @@ int launch(Slot& sl, const std::vector<Request*>& batch)
 void scheduler(dpk_server* s)
 {
     hipSetDevice(s->device);
+    // short sleeps while a batch is in flight mean what they say (the default timer slack of
+    // 50 us would stretch each to about 70 us, on the path of every frame's completion)
+    prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
     const int ns = (int)s->slots.size();
     std::vector<int32_t> busy(ns);
     std::vector<int64_t> bytes(ns), sims(ns);
@@ -2143,7 +2104,10 @@ void scheduler(dpk_server* s)
                 if (plan == 0) {
                     bool any_idle = false;
                     for (int k = 0; k < ns; ++k) any_idle |= !busy[k];
-                    if (any_idle) s->st.budget_waits++;
+                    if (any_idle && !r->waited) {
+                        r->waited = true;
+                        s->st.budget_waits++;
+                    }
                     break;
                 }
                 std::vector<Request*> batch(s->queue.begin(), s->queue.begin() + take);
@@ -2180,7 +2144,10 @@ void scheduler(dpk_server* s)
                         if (!busy[k] && k != slot) release_ws(s->slots[k].ctx);
                     if (ensure_ws(sl.ctx, batch_atoms, batch_cells, true) != DPK_OK) {
                         s->queue.insert(s->queue.begin(), batch.begin(), batch.end());
-                        s->st.budget_waits++;
+                        if (!r->waited) {
+                            r->waited = true;
+                            s->st.budget_waits++;
+                        }
                         break;
                     }
                 }
@@ -2223,7 +2190,18 @@ void scheduler(dpk_server* s)
             s->st.peak_bytes = std::max(s->st.peak_bytes, resident_bytes(s));
             if (failed) s->cv.notify_all();
         }
-        if (fin.empty() && adm.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        if (fin.empty() && adm.empty()) {
+            bool inflight = false;
+            for (auto& sl : s->slots) inflight |= !sl.reqs.empty();   // this thread's own state
+            if (inflight) {
+                // a batch is on the device: poll its event again shortly
+                std::this_thread::sleep_for(std::chrono::microseconds(2));
+            } else {
+                // nothing on the device: sleep until a frame is queued (or the server stops)
+                std::unique_lock<std::mutex> lk(s->mu);
+                s->wake.wait_for(lk, std::chrono::milliseconds(1), [&] { return !s->queue.empty() || s->stop; });
+            }
+        }
     }
 }
 
@@ -2370,6 +2348,7 @@ int dpk_server_submit(dpk_server* s, const dpk_frame* f, uint64_t* ticket)
         s->cv.notify_all();
     } else {
         s->queue.push_back(r.get());
+        s->wake.notify_one();
     }
     s->reqs[r->ticket] = std::move(r);
     return DPK_OK;
@@ -2434,7 +2413,11 @@ void dpk_server_free(dpk_server* s)
 {
     if (!s) return;
     if (s->th.joinable()) {
-        s->stop = true;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stop = true;
+        }
+        s->wake.notify_one();
         s->th.join();
     }
     for (auto& sl : s->slots) {
