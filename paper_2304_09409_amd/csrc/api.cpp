@@ -695,8 +695,10 @@ int upload_model(dpk_ctx* c)
 // Embedding, fitting and the backward pass. F: force accumulator in caller order (zeroed by the
 // preparation). Single frame (single = true): per-block partials [E, virial] and E_i in caller
 // order (atom_energy, if not nullptr); batch: per-atom virials (vir_atom).
+// spatial: the candidate records hold exactly the n centres (no ghosts), so the tabulated
+// backward may take its atoms in their bin order
 void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* F, double* vir_atom, bool single,
-                 double* atom_energy, std::vector<hipEvent_t>* ev, hipStream_t s)
+                 double* atom_energy, std::vector<hipEvent_t>* ev, hipStream_t s, bool spatial = true)
 {
     const dpk_model* m = c->model;
     const int nt = m->desc.ntypes;
@@ -759,6 +761,13 @@ void run_network(dpk_ctx* c, int n, const GeomParams& gp, double* F, double* vir
     launch_fit(c->precision, fa, s);
 
     prof_mark(ev, DPK_STAGE_EMBED_BWD, s);
+    if (tab && !e3 && spatial) {
+        // the preparation's bin-sort scratch (cell_tmp) is free once the lists are built
+        // (its count goes to the statistics block, which the preparation cleared)
+        launch_spatial_order(n, c->cand, c->cell_of, c->cell_tmp, &c->stats->order_local, s);
+        ea.order = c->cell_tmp;
+        ea.order_cnt = &c->stats->order_local;
+    }
     launch_embed_bwd(c->precision, tab, ea, s, e3);
 }
 
@@ -1244,7 +1253,7 @@ int dpk_compute_ghost(dpk_ctx* c, int64_t nlocal, int64_t nghost, const double* 
                          c->nnei, c->stats, s);
         // descriptor, fitting and adjoint over the owned atoms: E_i of owned atoms only; forces land
         // on owned and ghost atoms alike (the ghosts' are the caller's to send back to their owners)
-        run_network(c, nl, gp, d_force, nullptr, true, atom_energy ? o + 10 + 3 * n : nullptr, nullptr, s);
+        run_network(c, nl, gp, d_force, nullptr, true, atom_energy ? o + 10 + 3 * n : nullptr, nullptr, s, nl == n);
         launch_finalize(embed_bwd_blocks(c->precision, c->tab, nl, c->ncu, is_e3(c)), c->vir_part, o, o + 1, c->stats, s);
         HIPCHK(hipGetLastError());
         c->last_stream = s;

@@ -130,7 +130,7 @@ struct DevStats {
     int max_cand;
     int err_type;       // atom type out of range
     int err_overflow;   // candidate buffer overflow
-    int pad;
+    int order_local;    // consecutive internal atoms that share a bin (tabulated backward's order)
 };
 
 // Neighbours dropped by sel are counted per atom into NL_DROP_SLOTS counters that follow the
@@ -190,6 +190,11 @@ struct EmbArgs {
     // and copied to atom_energy (caller order) if that is not nullptr
     const double* Ei;        // [N] internal order
     double* atom_energy;     // [N] caller order, or nullptr
+    // tabulated backward: the centres in bin order (internal index of the k-th) and the number of
+    // consecutive internal atoms that share a bin; where fewer than a quarter do (the caller's order
+    // is not spatial) the backward takes its groups in bin order. nullptr: internal order
+    const int* order;
+    const int* order_cnt;
     // Model ensemble (model deviation, one launch for all models): blockIdx.y selects model k,
     // whose parameters and per-model buffers start k times these byte strides past the pointers
     // above; the geometry (types, neighbour list, perm) and the statistics block are shared.

@@ -69,6 +69,9 @@ void launch_e3_env(int precision, const EmbArgs& a, hipStream_t s);
 // Tabulated embedding of the two-body descriptors as products with the table (forward or
 // backward), its block count (one [E, virial] partial each) and its smallest block in atoms.
 void launch_tab(bool fwd, int precision, const EmbArgs& a, hipStream_t s);
+// order[k] = internal index of candidate record k (records in bin order, one per atom; n records);
+// *cnt (zero on entry) += the number of internal atoms i < n - 1 in the bin of atom i + 1
+void launch_spatial_order(int n, const double4* cand, const int* cell_of, int* order, int* cnt, hipStream_t s);
 int tab_blocks(int64_t natoms, int ncu);
 int tab_atoms_per_block_min();
 void launch_fit(int precision, const FitArgs& a, hipStream_t s);

@@ -133,14 +133,18 @@ struct TabPass {
         return (span + nw - 1) / nw;
     }
 };
-__device__ __forceinline__ TabPass tab_pass(const EmbArgs& A, int a0, int na, int ti, int tj, bool all_types,
-                                            int lane, double inv_w)
+// The group's atom a: position a0 + a of the centres' order (bin order, or internal order).
+__device__ __forceinline__ int group_atom(const int* order, int a0, int a) { return order ? order[a0 + a] : a0 + a; }
+
+__device__ __forceinline__ TabPass tab_pass(const EmbArgs& A, const int* order, int a0, int na, int ti, int tj,
+                                            bool all_types, int lane, double inv_w)
 {
     int cnt = 0, li = 0;
     if (lane < 2 * TGA) {
         const int a = lane & (TGA - 1);
-        if (a < na && (all_types || A.itype[a0 + a] == ti)) cnt = A.nnei[(size_t)(a0 + a) * A.ntypes + tj];
-        if (cnt > 0) li = tab_geo(A, (size_t)(a0 + a) * A.nc + A.off[tj] + (lane < TGA ? 0 : cnt - 1), inv_w).li;
+        const int at = a < na ? group_atom(order, a0, a) : 0;
+        if (a < na && (all_types || A.itype[at] == ti)) cnt = A.nnei[(size_t)at * A.ntypes + tj];
+        if (cnt > 0) li = tab_geo(A, (size_t)at * A.nc + A.off[tj] + (lane < TGA ? 0 : cnt - 1), inv_w).li;
     }
     TabPass p;
     p.top = -1;
@@ -224,12 +228,12 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // Centre types of a group of consecutive internal atoms (one type except at a type boundary, or
 // where the atoms of a batch change frames).
-__device__ __forceinline__ void group_types(const EmbArgs& A, int a0, int na, int& tmin, int& tmax)
+__device__ __forceinline__ void group_types(const EmbArgs& A, const int* order, int a0, int na, int& tmin, int& tmax)
 {
-    tmin = A.itype[a0];
+    tmin = A.itype[group_atom(order, a0, 0)];
     tmax = tmin;
     for (int a = 1; a < na; ++a) {
-        const int t = A.itype[a0 + a];
+        const int t = A.itype[group_atom(order, a0, a)];
         tmin = min(tmin, t);
         tmax = max(tmax, t);
     }
@@ -268,11 +272,11 @@ __global__ void __launch_bounds__(TNW * 64) k_tab_fwd(EmbArgs A_)
 #pragma unroll
         for (int tm = 0; tm < 7; ++tm) acc[tm] = accv{0, 0, 0, 0};
         int tmin, tmax;
-        group_types(A, a0, na, tmin, tmax);
+        group_types(A, nullptr, a0, na, tmin, tmax);
         if (tos) tmax = tmin;   // the nets depend on the neighbour type only: one pass covers all
         for (int ti = tmin; ti <= tmax; ++ti)
             for (int tj = 0; tj < nt; ++tj) {
-                const TabPass ps = tab_pass(A, a0, na, ti, tj, tos, lane, inv_w);
+                const TabPass ps = tab_pass(A, nullptr, a0, na, ti, tj, tos, lane, inv_w);
                 if (!ps.any) continue;
                 const int net = tos ? tj : ti * nt + tj;
                 const T* tk = tabk + (size_t)net * kp * N3P;
@@ -393,6 +397,9 @@ __global__ void __launch_bounds__(TNW * 64) k_tab_bwd(EmbArgs A_)
     typedef TabPol<T> Pol;
     typedef typename Pol::accv accv;
     constexpr int WIN = Pol::WIN, ROWS = 6 * WIN, KC = 3;
+    // groups of atoms neighbouring in space (see the force hash): the internal order where it is
+    // spatial, else the bin order
+    const int* ord = (A.order && 4 * (int64_t)*A.order_cnt < (int64_t)A.natoms) ? A.order : nullptr;
     static_assert(ROWS % 16 == 0, "whole 16-row tiles of W per window");
     __shared__ __attribute__((aligned(16))) T s_W[TNW][TGA][ROWS][4];
     __shared__ double s_vir[TNW][9];
@@ -425,7 +432,7 @@ __global__ void __launch_bounds__(TNW * 64) k_tab_bwd(EmbArgs A_)
 #pragma unroll
         for (int a = 0; a < TGA; ++a) fc[a][0] = fc[a][1] = fc[a][2] = 0.0;
         int tmin, tmax;
-        group_types(A, a0, na, tmin, tmax);
+        group_types(A, ord, a0, na, tmin, tmax);
         if (tos) tmax = tmin;
         for (int ti = tmin; ti <= tmax; ++ti) {
             // dT^T as the A operand: lane (g, c) holds dT[atom c/4][feature 4 ms + g][component c%4]
@@ -433,13 +440,14 @@ __global__ void __launch_bounds__(TNW * 64) k_tab_bwd(EmbArgs A_)
             T adt[E2 / 4];
             {
                 const int ai = c >> 2;
-                const bool ok = ai < na && (tos || A.itype[a0 + ai] == ti);
-                const T* src = dTin + ((size_t)(a0 + (ok ? ai : 0)) * E2 + g) * 4 + (c & 3);
+                const int at = group_atom(ord, a0, ai < na ? ai : 0);
+                const bool ok = ai < na && (tos || A.itype[at] == ti);
+                const T* src = dTin + ((size_t)at * E2 + g) * 4 + (c & 3);
 #pragma unroll
                 for (int ms = 0; ms < E2 / 4; ++ms) adt[ms] = ok ? src[16 * ms] : (T)0;
             }
             for (int tj = 0; tj < nt; ++tj) {
-                const TabPass ps = tab_pass(A, a0, na, ti, tj, tos, lane, inv_w);
+                const TabPass ps = tab_pass(A, ord, a0, na, ti, tj, tos, lane, inv_w);
                 if (!ps.any) continue;
                 const int net = tos ? tj : ti * nt + tj;
                 const T* tmat = tabm + (size_t)net * N3P * kp;
@@ -492,7 +500,7 @@ __global__ void __launch_bounds__(TNW * 64) k_tab_bwd(EmbArgs A_)
                     for (int a = 0; a < TGA; ++a) {
                         const int n = ps.cnt[a];
                         if (n == 0) continue;
-                        const size_t row0 = (size_t)(a0 + a) * A.nc + A.off[tj];
+                        const size_t row0 = (size_t)group_atom(ord, a0, a) * A.nc + A.off[tj];
                         // r_ij and j of the chunk at the cursor; each chunk reads the next one's
                         // before its force atomics (reads and atomics retire in order, so a read
                         // issued after them would wait for them)
@@ -561,7 +569,7 @@ __global__ void __launch_bounds__(TNW * 64) k_tab_bwd(EmbArgs A_)
 #pragma unroll
                             for (int k = 0; k < 9; ++k) {
                                 const double v = wave_sum(vir[k]);
-                                if (lane == 0) A.vir_atom[9 * (size_t)(a0 + a) + k] += v;
+                                if (lane == 0) A.vir_atom[9 * (size_t)group_atom(ord, a0, a) + k] += v;
                                 vir[k] = 0.0;
                             }
                         }
@@ -578,7 +586,7 @@ __global__ void __launch_bounds__(TNW * 64) k_tab_bwd(EmbArgs A_)
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double v = wave_sum(fc[a][k]);
-                if (lane == 0) unsafeAtomicAdd(&A.F[3 * (size_t)A.perm[a0 + a] + k], v);
+                if (lane == 0) unsafeAtomicAdd(&A.F[3 * (size_t)A.perm[group_atom(ord, a0, a)] + k], v);
             }
         }
     }
@@ -640,6 +648,29 @@ int tab_blocks(int64_t natoms, int ncu)
 }
 
 int tab_atoms_per_block_min() { return TNW * TGA; }
+
+// The centres in bin order, from the candidate records (bin order, one per atom; the tag's low 30
+// bits are the internal index): groups of consecutive positions in this order are atoms in one or
+// two bins, whose neighbour lists overlap in the force hash. The caller's own order (kept within
+// each type by the internal order) is usually more compact still where it is spatial (a lattice, or
+// an MD code's periodic sort), so the backward keeps it unless fewer than a quarter of consecutive
+// internal atoms share a bin, the count this kernel makes (one atomic per wave into *cnt, which
+// starts the frame at zero).
+__global__ void __launch_bounds__(256) k_spatial_order(int n, const double4* cand, const int* cell_of, int* order,
+                                                       int* cnt)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k < n) order[k] = (int)(__double_as_longlong(cand[k].w) & ((1LL << 30) - 1));
+    const bool same = k + 1 < n && cell_of[k] == cell_of[k + 1];
+    const int w = __popcll(__ballot(same));
+    if ((threadIdx.x & 63) == 0 && w) atomicAdd(cnt, w);
+}
+
+void launch_spatial_order(int n, const double4* cand, const int* cell_of, int* order, int* cnt, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_spatial_order, dim3((n + 255) / 256), dim3(256), 0, s, n, cand, cell_of, order, cnt);
+}
 
 template <class T>
 static void launch_tab_p(bool fwd, const EmbArgs& a0, hipStream_t s)
