@@ -64,9 +64,10 @@ constexpr int TPS = 6 * 16 + 4;   // LDS stride of one interval's six moment row
 
 // Neighbour forces of a backward block are summed in LDS before they reach the force array: an
 // open-addressing hash on the neighbour's caller index (2^TAB_HLOG slots, linear probing over at
-// most TAB_PROBE slots; a neighbour that finds no slot adds to the force array directly). The atoms
-// of a block are consecutive, so where the caller's order is spatial (as an MD code keeps it) their
-// neighbour lists overlap and the block flushes each distinct neighbour once.
+// most TAB_PROBE slots; a neighbour that finds no slot adds to the force array directly). A block's
+// atoms are neighbours in space (consecutive internal atoms where the caller's order is spatial,
+// as an MD code keeps it; else consecutive in bin order, k_spatial_order), so their neighbour lists
+// overlap and the block flushes each distinct neighbour once.
 #ifndef TAB_HLOG
 #define TAB_HLOG 10
 #endif
@@ -226,8 +227,8 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Centre types of a group of consecutive internal atoms (one type except at a type boundary, or
-// where the atoms of a batch change frames).
+// Centre types of a group: of consecutive internal atoms, one type except at a type boundary or
+// where the atoms of a batch change frames; of atoms in bin order, any of them.
 __device__ __forceinline__ void group_types(const EmbArgs& A, const int* order, int a0, int na, int& tmin, int& tmax)
 {
     tmin = A.itype[group_atom(order, a0, 0)];
