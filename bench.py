@@ -406,6 +406,62 @@ def descriptor_bench(dpk, synth, torch, steps, warmup, precisions):
     return out
 
 
+def next_rows_bench(dpk, synth, reps=10):
+    """Model deviation (Sec. II.C) and one domain of a spatial decomposition with ghost atoms
+    (Sec. III.B.2), through their host-buffer entry points (synchronous, host-to-device and
+    device-to-host copies included, so the rates are lower bounds of device-resident ones); medians
+    of `reps` calls after one warm-up call, each beside the same model's single-frame host-buffer
+    time. Parity of both is tested (test_gpu_devi.py, test_gpu_ghost.py)."""
+    out = {}
+    med = lambda f: float(np.median([_wall_ms(f) for _ in range(reps)]))
+    # model deviation: four members (perturbed water parameters) on the 12,288-atom box
+    c, t, b = synth.water_12288()
+    n = len(t)
+    nm = 4
+    models = [dpk.Model(synth.WATER_MODEL, p) for p in synth.ensemble_params(synth.WATER_MODEL, synth.water_params(), nm)]
+    res = {"workload": f"water-like box, 12,288 atoms; {nm} se_e2_a water models (parameters x (1 + N(0, 0.02)))",
+           "atoms": n, "models": nm, "entry_point": "dpk_devi_compute (host buffers)"}
+    for prec in ("mixed", "fp64"):
+        dv = dpk.Deviation(models, precision=prec)
+        dv.compute(c, t, b)
+        ms = med(lambda: dv.compute(c, t, b))
+        dv.close()
+        ctx = dpk.Context(models[0], precision=prec)
+        ctx.compute(c, t, b)
+        one = med(lambda: ctx.compute(c, t, b))
+        ctx.close()
+        res[prec] = {"ms": ms, "model_atom_steps_per_s": nm * n / (ms * 1e-3), "single_model_ms": one,
+                     "vs_separate_models": ms / (nm * one)}
+        print(f"# model deviation ({nm} models) water12288 {prec}: {ms:.3f} ms per frame "
+              f"({res[prec]['model_atom_steps_per_s']:.4g} model-atom-steps/s; one model {one:.3f} ms, "
+              f"ensemble / {nm} separate evaluations {res[prec]['vs_separate_models']:.2f})",
+              file=sys.stderr, flush=True)
+    out["model_deviation"] = res
+    # one brick of eight of the 110,592-atom box, with the ghosts within r_c of it
+    c, t, b = synth.water_110592()
+    br = synth.ghost_bricks(c, t, b, (2, 2, 2), halo=synth.WATER_MODEL["rcut"])[0]
+    nl, ntot = int(br["nlocal"]), len(br["atype"])
+    model = dpk.Model(synth.WATER_MODEL, synth.water_params())
+    res = {"workload": "one of 2 x 2 x 2 bricks of the 110,592-atom water box (51.7 A cube), ghosts within "
+                       "r_c = 6 A", "owned": nl, "ghosts": ntot - nl, "entry_point": "dpk_compute_ghost (host buffers)"}
+    for prec in ("mixed", "fp64"):
+        ctx = dpk.Context(model, precision=prec)
+        ctx.compute_ghost(br["coord"], br["atype"], nl)
+        ms = med(lambda: ctx.compute_ghost(br["coord"], br["atype"], nl))
+        ctx.close()
+        res[prec] = {"ms": ms, "owned_atom_steps_per_s": nl / (ms * 1e-3)}
+        print(f"# ghost brick ({nl} owned + {ntot - nl} ghosts) {prec}: {ms:.3f} ms per frame "
+              f"({res[prec]['owned_atom_steps_per_s']:.4g} owned atom-steps/s)", file=sys.stderr, flush=True)
+    out["ghost_domain"] = res
+    return out
+
+
+def _wall_ms(f):
+    t0 = time.perf_counter()
+    f()
+    return (time.perf_counter() - t0) * 1e3
+
+
 # Training step (Sec. II.B) per frame, FP64: inference (embedding with its unit tangent 2 x 12,550
 # flop per pair, pair forces 1,600; fitting forward and input gradient 2 x 998,400 per atom), the
 # training pass (fitting forward with tangent 2 x 998,400, reverse of values and tangents
@@ -517,6 +573,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 110,592-atom water box")
     ap.add_argument("--no-descriptors", action="store_true", help="skip the se_e2_r / se_e3 section")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step section")
+    ap.add_argument("--no-next", action="store_true", help="skip the model-deviation and ghost-domain section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device-to-device (the reference for hardware byte counters)")
     args = ap.parse_args()
@@ -565,6 +622,7 @@ def main():
     descriptors = None if args.no_descriptors else descriptor_bench(dpk, synth, torch, max(1, args.steps // 2),
                                                                     max(1, args.warmup // 2), ("fp64", "mixed", "fp32"))
     training = None if args.no_train else training_bench(dpk, synth, max(2, args.steps // 4))
+    next_rows = None if args.no_next else next_rows_bench(dpk, synth)
     # two operating points of the same server: the latency point (four slots, a budget of three
     # of the largest frame's workspaces, which binds) and a throughput point (four slots, 48
     # workspaces: batches grow to the scheduler's 12,288-atom target)
@@ -640,6 +698,8 @@ def main():
         "tabulated": tabulated,
         "descriptors": descriptors,
         "training": training,
+        "model_deviation": None if next_rows is None else next_rows["model_deviation"],
+        "ghost_domain": None if next_rows is None else next_rows["ghost_domain"],
         "serving": serving,
     }
     line.update(others)
