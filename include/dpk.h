@@ -53,7 +53,9 @@ enum {
     DPK_E_BUDGET = -5,        /* the frame's device workspace exceeds the context's budget    */
     DPK_E_OOM = -6,           /* device allocation failed                                     */
     DPK_E_DEVICE = -7,        /* a HIP call failed                                            */
-    DPK_E_UNIMPLEMENTED = -8  /* combination not supported (e.g. table in FP64 with ntypes>4) */
+    DPK_E_UNIMPLEMENTED = -8, /* combination not supported (e.g. table in FP64 with ntypes>4) */
+    DPK_E_TIMEOUT = -9,       /* dpk_server_wait_for: the frame is not done yet               */
+    DPK_E_CANCELLED = -10     /* a served frame withdrawn by dpk_server_cancel before it ran  */
 };
 
 enum {
@@ -385,6 +387,14 @@ int dpk_server_submit(dpk_server *s, const dpk_frame *f, uint64_t *ticket);
 int dpk_server_poll(dpk_server *s, uint64_t ticket, int *done);
 /* Block until the frame finishes; returns its result code (error text via dpk_last_error). */
 int dpk_server_wait(dpk_server *s, uint64_t ticket);
+/* As dpk_server_wait for at most timeout_us microseconds (>= 0): DPK_E_TIMEOUT if the frame is
+ * still queued or running then (it stays in the server; wait, poll or cancel it later). For callers
+ * that keep a per-request deadline. */
+int dpk_server_wait_for(dpk_server *s, uint64_t ticket, int64_t timeout_us);
+/* Withdraw a frame that is still queued: it finishes at once with DPK_E_CANCELLED (its outputs
+ * untouched) and the server no longer reads its inputs. A frame already admitted to a slot runs to
+ * completion: DPK_E_INVALID_ARG (as for an unknown or finished ticket), the frame unaffected. */
+int dpk_server_cancel(dpk_server *s, uint64_t ticket);
 /* Forget a finished frame's record (its result code and times); the ticket is unknown afterwards.
  * DPK_E_INVALID_ARG if the frame is still queued or running. Records of finished frames are kept
  * until released (or until dpk_server_free). */

@@ -2386,6 +2386,38 @@ int dpk_server_wait(dpk_server* s, uint64_t ticket)
     return r->result;
 }
 
+int dpk_server_wait_for(dpk_server* s, uint64_t ticket, int64_t timeout_us)
+{
+    if (!s || timeout_us < 0) return fail(DPK_E_INVALID_ARG, "NULL server or negative timeout");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(DPK_E_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    Request* r = it->second.get();
+    if (!s->cv.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return r->state == 2; }))
+        return fail(DPK_E_TIMEOUT, "frame %llu not done within %lld us", (unsigned long long)ticket,
+                    (long long)timeout_us);
+    if (r->result) g_err = r->err;
+    return r->result;
+}
+
+int dpk_server_cancel(dpk_server* s, uint64_t ticket)
+{
+    if (!s) return fail(DPK_E_INVALID_ARG, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(DPK_E_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    Request* r = it->second.get();
+    // only a queued frame can be withdrawn (the scheduler admits under this lock, so a frame still
+    // in the queue here has not been handed to a slot)
+    auto q = std::find(s->queue.begin(), s->queue.end(), r);
+    if (r->state != 0 || q == s->queue.end())
+        return fail(DPK_E_INVALID_ARG, "frame %llu is running or done", (unsigned long long)ticket);
+    s->queue.erase(q);
+    publish(s, r, DPK_E_CANCELLED, "cancelled before it ran");
+    s->cv.notify_all();
+    return DPK_OK;
+}
+
 int dpk_server_times(dpk_server* s, uint64_t ticket, int64_t* times)
 {
     if (!s || !times) return fail(DPK_E_INVALID_ARG, "NULL argument");

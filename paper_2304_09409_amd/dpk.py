@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libdpk.so")
 
 DPK_OK, DPK_E_INVALID_ARG, DPK_E_TYPE_RANGE, DPK_E_BOX = 0, -1, -2, -3
 DPK_E_NBR_OVERFLOW, DPK_E_BUDGET, DPK_E_OOM, DPK_E_DEVICE, DPK_E_UNIMPLEMENTED = -4, -5, -6, -7, -8
+DPK_E_TIMEOUT, DPK_E_CANCELLED = -9, -10
 PRECISIONS = {"fp64": 0, "mixed": 1, "bf16": 2, "fp32": 3}
 MAX_TYPES = 8
 
@@ -490,6 +491,8 @@ def _server_sigs(L):
     L.dpk_server_submit.argtypes = [vp, C.POINTER(_Frame), C.POINTER(C.c_uint64)]
     L.dpk_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int)]
     L.dpk_server_wait.argtypes = [vp, C.c_uint64]
+    L.dpk_server_wait_for.argtypes = [vp, C.c_uint64, C.c_int64]
+    L.dpk_server_cancel.argtypes = [vp, C.c_uint64]
     L.dpk_server_times.argtypes = [vp, C.c_uint64, i64p]
     L.dpk_server_release.argtypes = [vp, C.c_uint64]
     L.dpk_server_stats.argtypes = [vp, C.POINTER(_Counters)]
@@ -525,9 +528,16 @@ class Ticket:
     def done(self) -> int:
         return self.server.poll(self)
 
-    def result(self) -> dict:
-        self.server.wait(self)
+    def result(self, timeout: float | None = None) -> dict:
+        """The frame's outputs; with a timeout (seconds) a frame not done by then raises DpkError
+        with DPK_E_TIMEOUT and stays in the server."""
+        self.server.wait(self, timeout)
         return self.out
+
+    def cancel(self) -> bool:
+        """Withdraw the frame if it is still queued (it then reports DPK_E_CANCELLED); False if it
+        was already admitted to a slot or has finished."""
+        return self.server.cancel(self)
 
     def __del__(self):
         srv = getattr(self, "server", None)
@@ -598,14 +608,26 @@ class Server:
             self._live.pop(ticket.id, None)
         return d
 
-    def wait(self, ticket: Ticket):
-        rc = lib().dpk_server_wait(self.handle, ticket.id)
+    def wait(self, ticket: Ticket, timeout: float | None = None):
+        if timeout is None:
+            rc = lib().dpk_server_wait(self.handle, ticket.id)
+        else:
+            rc = lib().dpk_server_wait_for(self.handle, ticket.id, max(0, int(timeout * 1e6)))
+            if rc == DPK_E_TIMEOUT:
+                _check(rc)   # still queued or running: its buffers stay with the server
         self._live.pop(ticket.id, None)
         _check(rc)
         o = ticket.out
         o["energy"] = float(o["energy_buf"][0])
         o["virial"] = o["virial_buf"].reshape(3, 3)
         return o
+
+    def cancel(self, ticket: Ticket) -> bool:
+        rc = lib().dpk_server_cancel(self.handle, ticket.id)
+        if rc == DPK_OK:
+            self._live.pop(ticket.id, None)   # the server no longer reads or writes its buffers
+            return True
+        return False
 
     def times(self, ticket: Ticket):
         t = np.zeros(3, dtype=np.int64)

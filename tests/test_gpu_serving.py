@@ -181,6 +181,44 @@ def test_dense_frame_through_autograd(dpk, model):
     assert e.value.code == dpk.DPK_E_TYPE_RANGE
 
 
+def test_cancel_and_timeout(dpk, model):
+    """Per-request control: two frames of 60,000 atoms (too large to batch) keep the single slot busy
+    for milliseconds while small frames queue behind them. A bounded wait on a queued frame reports
+    DPK_E_TIMEOUT and leaves it queued; a frame withdrawn while queued reports DPK_E_CANCELLED with
+    its outputs untouched; a finished frame cannot be withdrawn; every frame not withdrawn completes
+    with the result it has alone."""
+    say("serving: cancel and timeout")
+    blockers = [synth.serving_frame(60000, 51 + k, 3) for k in range(2)]
+    fr = _frames(12, 41)
+    srv = dpk.Server(model, precision="mixed", nslots=1)
+    tb = [srv.submit(*f) for f in blockers]
+    tks = [srv.submit(c, t, b) for c, t, b in fr]
+    with pytest.raises(dpk.DpkError) as e:
+        tks[-1].result(timeout=0.0)
+    assert e.value.code == dpk.DPK_E_TIMEOUT
+    tried = (4, 7, 10)
+    withdrawn = {k: tks[k].cancel() for k in tried}
+    print(f"  withdrawn {withdrawn}", flush=True)
+    assert any(withdrawn.values())
+    ctx = dpk.Context(model, precision="mixed")
+    for k, ((c, t, b), tk) in enumerate(zip(fr, tks)):
+        if withdrawn.get(k):
+            with pytest.raises(dpk.DpkError) as e:
+                tk.result()
+            assert e.value.code == dpk.DPK_E_CANCELLED
+            assert not np.any(tk.out["force"]) and tk.out["energy_buf"][0] == 0.0
+        else:
+            _compare(tk.result(), ctx.compute(c, t, b), len(t))
+    for t in tb:
+        t.result()
+    ctx.close()
+    assert not tks[0].cancel()   # finished
+    st = srv.stats()
+    nw = sum(withdrawn.values())
+    assert st["completed"] == 14 - nw and st["failed"] == nw
+    srv.close()
+
+
 def test_dropped_tickets(dpk, model):
     """Tickets dropped before their frames finish: the server keeps the frames' buffers until they
     are done, every frame completes, and the records of dropped tickets are released."""
