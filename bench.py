@@ -211,11 +211,15 @@ def _serving_timed(srv, sims, reqs, rng, load, slots, budget, n_sims):
         when.append(due)
     lat = []
     last = 0
-    for tk, due in zip(tickets, when):
+    records = []
+    for (c, t, b, sid), tk, due in zip(reqs, tickets, when):
         tk.result()
-        done = int(srv.times(tk)[2])
+        ts = srv.times(tk)
+        done = int(ts[2])
         lat.append((done - due) * 1e-6)
         last = max(last, done)
+        records.append({"simulation": int(sid), "atoms": int(len(t)), "arrival_ns": int(due), "submit_ns": int(ts[0]),
+                        "start_ns": int(ts[1]), "done_ns": done, "latency_ms": (done - due) * 1e-6})
     st = srv.stats()
     # latency against fixed Poisson arrival rates (the saturated rate X above is measured with
     # every request queued, i.e. the largest batches; Poisson arrivals batch less)
@@ -248,7 +252,7 @@ def _serving_timed(srv, sims, reqs, rng, load, slots, budget, n_sims):
             "throughput_atom_steps_per_s": total_atoms / ((last - start) * 1e-9),
             "peak_bytes": st["peak_bytes"], "budget_waits": st["budget_waits"],
             "slot_reuse": st["slot_reuse"], "fixed_rate_latency": fixed, "mean_batch_saturated": batch_sat,
-            "mean_batch_poisson": batch_poisson, "precision": "mixed"}
+            "mean_batch_poisson": batch_poisson, "precision": "mixed", "_records": records}
 
 
 def time_frame(dpk, torch, model, prec, c, t, b, steps, warmup, median_of=0):
@@ -574,6 +578,8 @@ def main():
     ap.add_argument("--no-descriptors", action="store_true", help="skip the se_e2_r / se_e3 section")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step section")
     ap.add_argument("--no-next", action="store_true", help="skip the model-deviation and ghost-domain section")
+    ap.add_argument("--requests-log", default=None,
+                    help="write one JSON record per served request of the Poisson phases to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device-to-device (the reference for hardware byte counters)")
     args = ap.parse_args()
@@ -629,6 +635,14 @@ def main():
     serving = None if args.no_serving else serving_bench(dpk, synth)
     if serving:
         serving["throughput_point"] = serving_bench(dpk, synth, slots=4, budget_frames=48.0)
+        # per-request records (arrival, submission, start on the device, completion): to a file if
+        # asked for, never into the JSON line
+        recs = [("latency", serving.pop("_records")), ("throughput", serving["throughput_point"].pop("_records"))]
+        if args.requests_log:
+            with open(args.requests_log, "w") as fh:
+                for point, rr in recs:
+                    for r in rr:
+                        fh.write(json.dumps(dict(point=point, **r)) + "\n")
         for name, sv in (("serving", serving), ("serving (throughput point)", serving["throughput_point"])):
             print(f"# {name}: p50 {sv['p50_ms']:.3f} ms, p99 {sv['p99_ms']:.3f} ms at "
                   f"{sv['arrival_rate_req_per_s']:.0f} req/s; saturated {sv['saturated_atom_steps_per_s']:.4g} "
