@@ -298,6 +298,39 @@ def test_tabulated_fcc_32000_shuffled(dpk, precision):
     ctx.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_run_to_run_determinism(dpk, precision):
+    """The same frame evaluated repeatedly (the same context twice, then a new context): energy and
+    per-atom energies are bitwise equal (fixed-order sums), forces and virial, summed by FP64
+    atomics in varying order, agree to rounding. The 12,288-atom water box (network) and the
+    32,000-atom fcc box with its atoms shuffled (table; groups in bin order, whose order within a
+    bin varies run to run)."""
+    cases = [("water12288", synth.WATER_MODEL, synth.water_params, None, synth.water_12288()),
+             ("fcc32000 shuffled, table", synth.FCC_MODEL, synth.fcc_params, (0.01, 0.5), None)]
+    for name, spec, params, tab, frame in cases:
+        say(f"determinism {precision} {name}")
+        model = dpk.Model(spec, params())
+        if tab:
+            model.tabulate(*tab)
+            c, t, b = synth.fcc_32000()
+            perm = np.random.default_rng(5).permutation(len(t))
+            frame = (c[perm], t[perm], b)
+        c, t, b = frame
+        ctx = dpk.Context(model, precision=precision)
+        outs = [ctx.compute(c, t, b, atom_energy=True) for _ in range(2)]
+        ctx.close()
+        ctx = dpk.Context(model, precision=precision)
+        outs.append(ctx.compute(c, t, b, atom_energy=True))
+        ctx.close()
+        a = outs[0]
+        for o in outs[1:]:
+            assert o["energy"] == a["energy"]
+            np.testing.assert_array_equal(o["atom_energy"], a["atom_energy"])
+            fs = np.abs(a["force"]).max()
+            assert np.abs(o["force"] - a["force"]).max() <= 1e-13 * max(1.0, fs)
+            assert np.abs(o["virial"] - a["virial"]).max() <= 1e-13 * max(1.0, np.abs(a["virial"]).max())
+
+
 def test_context_keeps_the_model_it_was_created_with(dpk):
     """A context evaluates the model as it was when the context was created: tabulating the model
     afterwards (here a table that covers s < 0.1 only, so that its use shows in the out-of-range
